@@ -1,0 +1,113 @@
+"""Oracle reaction kernel: exact special cases and invariants of the layered Green's function."""
+import numpy as np
+import pytest
+
+from oracle.medium import Medium
+from oracle.sommerfeld import reaction_pair
+from oracle import direct
+
+K = (0.8, 1.5, 2.0)
+D = (0.0, -1.2)
+ZS = {0: 0.35, 1: -0.55, 2: -1.7}
+
+
+def _full_g(med, l, lp, r, rp):
+    rho = np.hypot(r[0] - rp[0], r[1] - rp[1])
+    g = reaction_pair(med, l, lp, rho, r[2], rp[2])[0]
+    if l == lp:
+        R = np.linalg.norm(np.subtract(r, rp))
+        g += np.exp(1j * med.k[l] * R) / (4 * np.pi * R)
+    return g
+
+
+@pytest.mark.parametrize("l", [0, 1, 2])
+@pytest.mark.parametrize("lp", [0, 1, 2])
+def test_equal_k_is_free_space(l, lp):
+    """One wave number everywhere: G is exp(ikR)/(4 pi R) for every layer pair."""
+    med = Medium((1.5, 1.5, 1.5), D)
+    r = (0.1, -0.2, ZS[l] + 0.05)
+    rp = (-0.3, 0.25, ZS[lp])
+    R = np.linalg.norm(np.subtract(r, rp))
+    np.testing.assert_allclose(_full_g(med, l, lp, r, rp), np.exp(1.5j * R) / (4 * np.pi * R), rtol=1e-11)
+
+
+@pytest.mark.parametrize("l", [0, 1, 2])
+@pytest.mark.parametrize("lp", [0, 1, 2])
+def test_weighted_reciprocity(l, lp):
+    """The flux condition k du/dz continuous (Sec. 2.1) gives k_l G_{l,lp}(r, r') = k_lp G_{lp,l}(r', r)."""
+    med = Medium(K, D)
+    r = (0.1, -0.2, ZS[l] + 0.07)
+    rp = (-0.3, 0.25, ZS[lp] - 0.04)
+    a = med.k[l] * _full_g(med, l, lp, r, rp)
+    b = med.k[lp] * _full_g(med, lp, l, rp, r)
+    np.testing.assert_allclose(a, b, rtol=1e-11)
+
+
+@pytest.mark.parametrize("j", [0, 1])
+@pytest.mark.parametrize("lp", [0, 1, 2])
+def test_interface_conditions(j, lp):
+    """G continuous and k dG/dz continuous across interface d_j (Sec. 2.1)."""
+    med = Medium(K, D)
+    rp = (0.2, -0.1, ZS[lp] + 0.03)
+    x, y = -0.15, 0.3
+    h = 1e-3
+    up, lo = j, j + 1
+    zi = med.d[j]
+
+    def g(l, z):
+        return _full_g(med, l, lp, (x, y, z), rp)
+
+    # one-sided values and slopes (second-order one-sided differences)
+    va = g(up, zi + 1e-9)
+    vb = g(lo, zi - 1e-9)
+    sa = (-3 * g(up, zi) + 4 * g(up, zi + h) - g(up, zi + 2 * h)) / (2 * h)
+    sb = (3 * g(lo, zi) - 4 * g(lo, zi - h) + g(lo, zi - 2 * h)) / (2 * h)
+    np.testing.assert_allclose(va, vb, rtol=1e-7)
+    np.testing.assert_allclose(med.k[up] * sa, med.k[lo] * sb, rtol=2e-5)
+
+
+@pytest.mark.parametrize("l", [0, 1, 2])
+def test_helmholtz_residual(l):
+    """The reaction part solves the homogeneous Helmholtz equation in the target layer."""
+    med = Medium(K, D)
+    rp = (0.1, 0.05, ZS[1])
+    c = np.array([-0.2, 0.15, ZS[l] + 0.02])
+    h = 2e-2
+    lap = 0
+    val = reaction_pair(med, l, 1, np.hypot(*(c[:2] - rp[:2])), c[2], rp[2])[0]
+    for ax in range(3):
+        acc = 0
+        for m, w in [(-2, -1 / 12), (-1, 4 / 3), (0, -5 / 2), (1, 4 / 3), (2, -1 / 12)]:
+            p = c.copy()
+            p[ax] += m * h
+            acc += w * reaction_pair(med, l, 1, np.hypot(*(p[:2] - rp[:2])), p[2], rp[2])[0]
+        lap += acc / h**2
+    assert abs(lap + med.k[l] ** 2 * val) < 1e-6 * abs(med.k[l] ** 2 * val)
+
+
+def test_sum_integral_swap_matches_pairwise():
+    """The direct sum (sum over sources inside the integral) equals the sum of pairwise kernels."""
+    med = Medium(K, D)
+    rng = np.random.default_rng(7)
+    xyz = np.concatenate([rng.random((20, 3)) * [1, 1, 0.6] + [-.5, -.5, 0.2],
+                          rng.random((20, 3)) * [1, 1, 0.8] + [-.5, -.5, -1.0],
+                          rng.random((20, 3)) * [1, 1, 0.5] + [-.5, -.5, -2.0]])
+    q = rng.uniform(-1, 1, 60) + 1j * rng.uniform(-1, 1, 60)
+    tg = np.array([3, 25, 50])
+    got = direct.reaction_part(med, xyz, q, tg)
+    lay = med.layer_of(xyz[:, 2])
+    for i, t in enumerate(tg):
+        ref = 0
+        for lp in range(3):
+            s = lay == lp
+            rho = np.hypot(xyz[t, 0] - xyz[s, 0], xyz[t, 1] - xyz[s, 1])
+            ref += np.sum(q[s] * reaction_pair(med, lay[t], lp, rho, xyz[t, 2], xyz[s, 2]))
+        np.testing.assert_allclose(got[i], ref, rtol=1e-11)
+
+
+def test_free_part_excludes_self():
+    med = Medium(K, D)
+    xyz = np.array([[0, 0, -0.5], [0.3, 0, -0.5], [0, 0, 0.5]])
+    q = np.array([1.0, 2.0, 5.0]) + 0j
+    got = direct.free_part(med, xyz, q, np.array([0]))
+    np.testing.assert_allclose(got[0], 2.0 * np.exp(1.5j * 0.3) / (4 * np.pi * 0.3), rtol=1e-14)
