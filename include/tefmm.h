@@ -1,0 +1,180 @@
+/*
+ * tefmm.h -- C ABI of the MI355X Taylor-expansion FMM for the 3-D Helmholtz
+ * sum in horizontally layered media.
+ *
+ * Computes, for every particle i (sources = targets),
+ *
+ *   phi_i = sum_{j != i, same layer} q_j exp(i k_l R_ij) / (4 pi R_ij)
+ *         + sum_j q_j G^r_{l_i l_j}(r_i, r_j)                       (1)
+ *
+ * (Eq. totalinteraction, Sec. 3.2; the reaction part G^r is the Sommerfeld
+ * integral of Eq. greenfuncomponent / Eq. totaldensity, Sec. 2.1).  The free
+ * part excludes j = i, the reaction part includes it.  Results are returned
+ * in physical normalisation (the paper's kernels times i k_l / 4 pi) unless
+ * TEFMM_NORM_PAPER is requested.
+ *
+ * The layered medium follows Sec. 2.1: n_layers = L+1 layers, interfaces
+ * d_0 > d_1 > ... > d_{L-1}, wave number k_l in layer l, layer 0 on top;
+ * transmission conditions u and k du/dz continuous.
+ *
+ * Error behaviour: every function returns an int status (TEFMM_OK = 0, a
+ * negative TEFMM_ERR_* otherwise) and never throws across the ABI; a
+ * human-readable message for the last failure on a handle is available from
+ * tefmm_last_error().  A handle is not thread safe: one handle serves one
+ * host thread and one stream at a time.
+ *
+ * Memory: pointers marked "device" must be device memory of the current HIP
+ * device (e.g. torch tensors on cuda:0); the caller owns them.  The library
+ * owns its tree, expansions and tables (device memory it allocates itself,
+ * freed by tefmm_destroy).
+ */
+#ifndef TEFMM_H
+#define TEFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TEFMM_OK = 0,
+  TEFMM_ERR_INVALID_ARG = -1,
+  TEFMM_ERR_PARTICLE_ON_INTERFACE = -2,
+  TEFMM_ERR_UNSUPPORTED = -3,
+  TEFMM_ERR_HIP = -4,
+  TEFMM_ERR_DCIM_FIT = -5,
+  TEFMM_ERR_OOM = -6,
+  TEFMM_ERR_STATE = -7
+};
+
+enum { TEFMM_FP64 = 0, TEFMM_MIXED_FP32 = 1 };
+enum { TEFMM_NORM_PHYSICAL = 0, TEFMM_NORM_PAPER = 1 };
+
+typedef struct tefmm_ctx* tefmm_t;
+
+/* Layered medium of Sec. 2.1.  interfaces: n_layers-1 strictly decreasing
+ * heights; k: n_layers real wave numbers > 0, top to bottom. */
+typedef struct {
+  int n_layers;
+  const double* interfaces;
+  const double* k;
+} tefmm_medium;
+
+/* Method parameters.  p: Taylor order (|k| <= p, full truncation of the
+ * translation operators, Sec. 3.1).  depth: uniform octree depth per layer
+ * (0 = choose the smallest depth with mean occupancy <= max_leaf).
+ * DCIM parameters (Sec. 3.3): dcim_T1 and dcim_samples per level, relative
+ * singular-value cut dcim_svd_tol.  interface_eps: minimum distance of a
+ * particle from an interface (the Sommerfeld integrals diverge on them). */
+typedef struct {
+  int p;
+  int depth;
+  int max_leaf;
+  int precision;      /* TEFMM_FP64 or TEFMM_MIXED_FP32 */
+  int normalization;  /* TEFMM_NORM_PHYSICAL or TEFMM_NORM_PAPER */
+  double dcim_T1;
+  int dcim_samples;
+  double dcim_svd_tol;
+  double interface_eps;
+  int n_rhs_max;
+} tefmm_options;
+
+/* Timings (ms, measured with HIP events on the evaluate stream) and counters. */
+typedef struct {
+  double t_setup_tree_ms, t_setup_tables_ms, t_setup_dcim_ms;
+  double t_p2m_ms, t_m2m_ms, t_m2l_ms, t_l2l_ms, t_l2p_ms, t_p2p_ms, t_total_ms;
+  int64_t m2l_pairs, p2p_pairs;
+  int n_images[8];       /* DCIM image counts of the fitted families */
+  double dcim_fit_err[8]; /* max relative misfit on the sampling paths */
+  int depth[4];          /* tree depth per layer (0 if no particles) */
+  int n_families;
+} tefmm_stats;
+
+/* Fill an options struct with the defaults (p = 8, depth auto, max_leaf 64,
+ * FP64, physical normalisation, T1 = 10, 101 samples, tol 1e-12,
+ * interface_eps 1e-9, n_rhs_max 64). */
+void tefmm_default_options(tefmm_options* opt);
+
+/* Create a handle for a medium (host FP64 work only: validation).
+ * Returns TEFMM_ERR_INVALID_ARG for non-decreasing interfaces, k <= 0,
+ * p outside [1, 12] or more than 4 layers.  Pure host call. */
+int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefmm_options* opt);
+
+/* Set the particle geometry.  xyz_soa: 3*n doubles, x[0..n) then y then z,
+ * device memory (on_device = 1) or host memory (on_device = 0).  Builds the
+ * per-layer octrees on the GPU, fits the discrete complex images
+ * (Sec. 3.3, two-level GPOF) on the host and generates the derivative
+ * tables on the GPU.  stream: hipStream_t (NULL = default stream).  Fails
+ * with TEFMM_ERR_PARTICLE_ON_INTERFACE if a particle lies within
+ * interface_eps of an interface, TEFMM_ERR_UNSUPPORTED for particles in more
+ * than one layer when the cross-layer path is not available. */
+int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz_soa, int on_device, void* stream);
+
+/* Evaluate (1) for n_rhs charge vectors.  q: device, complex128 interleaved
+ * (re, im), column-major n x n_rhs (vector r starts at q + 2*n*r).
+ * phi: device, same layout, written (not accumulated), in the caller's
+ * particle order.  Stream ordered on `stream`; returns after enqueueing
+ * (call hipStreamSynchronize to wait). */
+int tefmm_evaluate(tefmm_t h, const double* q, int n_rhs, double* phi, void* stream);
+
+/* Statistics of the last set_particles / evaluate (timings need the stream
+ * to have completed; this call synchronises it). */
+int tefmm_get_stats(tefmm_t h, tefmm_stats* st);
+
+const char* tefmm_last_error(tefmm_t h);
+void tefmm_destroy(tefmm_t h);
+
+/* ----------------------------------------------------------------------
+ * Introspection entry points (host FP64 or single kernels), used to check
+ * individual steps against the oracle.
+ * ---------------------------------------------------------------------- */
+
+/* Reaction densities sigma^{ab}_{m,lp}(k_rho) of Eq. updownspectraldoamin
+ * for a source in layer lp at n complex points krho (interleaved).  out:
+ * host, complex interleaved, 4*(L+1)*n entries ordered
+ * [m][ab][point] with ab = uu, ud, du, dd (absent entries are zero).
+ * Up-going waves are referenced at a layer's lower interface, down-going
+ * waves at its upper interface.  Pure host call. */
+int tefmm_densities(const tefmm_medium* medium, int lp, int n, const double* krho, double* out);
+
+/* Discrete complex images of the same-layer reaction families of layer l
+ * (Sec. 3.3, Eq. compleximageapp, two-level GPOF): family 0 = Sigma-up
+ * (sigma^{uu}, exponent z + z' - 2 d_l), 1 = Sigma-down (sigma^{dd},
+ * exponent 2 d_{l-1} - z - z'), 2 = Delta (sigma^{ud} = sigma^{du},
+ * exponents D +- (z - z')).  z_lo, z_hi: range of particle heights in the
+ * layer (sets the decay shift z_min of the paper).  On return *m holds the
+ * image count; amp/depth (host, complex interleaved, capacity cap) the
+ * amplitudes A_j and complex depths of the kernel representation
+ *   K(rho, Z) = sum_j A_j exp(i k R_j) / (4 pi R_j),  R_j = sqrt(rho^2 + (Z - depth_j)^2)
+ * where Z is the family's exponent.  *fit_err gets the largest relative
+ * misfit on the sampling paths.  Pure host call. */
+int tefmm_dcim_family(const tefmm_medium* medium, const tefmm_options* opt, int l, int family,
+                      double z_lo, double z_hi, int cap, int* m, double* amp, double* depth,
+                      double* fit_err);
+
+/* Scaled Taylor coefficients h^{|g|} D^g f / g! of f = exp(i k R)/R at n
+ * points (x, y, zeta) with complex zeta (device arrays x, y: n doubles;
+ * zeta: 2n doubles interleaved), orders |g| <= order, on the GPU with the
+ * derivative recurrence.  out: device, n * C(order+3,3) complex
+ * interleaved, graded order (|g| ascending, then g1 descending, then g2
+ * descending).  Single kernel, synchronous. */
+int tefmm_taylor_coefficients(int n, const double* x, const double* y, const double* zeta,
+                              double k, double h, int order, double* out);
+
+/* Multipole moments of the last evaluate (rhs 0) for layer group g at tree
+ * level l: host copy, n_box * C(p+3,3) complex interleaved, boxes in
+ * grid order (ix * n + iy) * n + iz, moments normalised by the box size. */
+int tefmm_get_moments(tefmm_t h, int g, int level, double* out, int64_t cap);
+
+/* Geometry of layer group g: *layer, *depth, centre/side of the root cube. */
+int tefmm_get_tree(tefmm_t h, int g, int* layer, int* depth, double* centre3, double* side);
+
+/* MFMA lane-layout self test: multiplies fixed 16x4 by 4x16 matrices in FP64
+ * and FP32 on the GPU and returns 0 when the results match the host. */
+int tefmm_selftest_mfma(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TEFMM_H */

@@ -1,0 +1,238 @@
+"""Python binding of libtefmm.so (argument marshalling only).
+
+Every step of the evaluation runs in the library's HIP kernels; PyTorch is
+used for device memory and streams.  Importing this module does not load the
+library; the first call does, and raises if libtefmm.so is missing (run
+``python -m paper_1902_05875_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtefmm.so")
+
+TEFMM_FP64, TEFMM_MIXED_FP32 = 0, 1
+TEFMM_NORM_PHYSICAL, TEFMM_NORM_PAPER = 0, 1
+ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "PARTICLE_ON_INTERFACE", -3: "UNSUPPORTED", -4: "HIP",
+          -5: "DCIM_FIT", -6: "OOM", -7: "STATE"}
+
+EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefmm_evaluate",
+           "tefmm_get_stats", "tefmm_last_error", "tefmm_destroy", "tefmm_densities",
+           "tefmm_dcim_family", "tefmm_taylor_coefficients", "tefmm_get_moments", "tefmm_get_tree",
+           "tefmm_selftest_mfma"]
+
+
+class TefmmError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"tefmm error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class MediumC(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int), ("interfaces", ctypes.POINTER(ctypes.c_double)),
+                ("k", ctypes.POINTER(ctypes.c_double))]
+
+
+class OptionsC(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("depth", ctypes.c_int), ("max_leaf", ctypes.c_int),
+                ("precision", ctypes.c_int), ("normalization", ctypes.c_int), ("dcim_T1", ctypes.c_double),
+                ("dcim_samples", ctypes.c_int), ("dcim_svd_tol", ctypes.c_double),
+                ("interface_eps", ctypes.c_double), ("n_rhs_max", ctypes.c_int)]
+
+
+class StatsC(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ["t_setup_tree_ms", "t_setup_tables_ms", "t_setup_dcim_ms", "t_p2m_ms", "t_m2m_ms", "t_m2l_ms",
+                 "t_l2l_ms", "t_l2p_ms", "t_p2p_ms", "t_total_ms"]] + [
+        ("m2l_pairs", ctypes.c_int64), ("p2p_pairs", ctypes.c_int64), ("n_images", ctypes.c_int * 8),
+        ("dcim_fit_err", ctypes.c_double * 8), ("depth", ctypes.c_int * 4), ("n_families", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtefmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1902_05875_amd.build")
+        # torch must own the process's HIP runtime (libamdhip64.so.7): loading it first makes the
+        # library bind to the same runtime, so torch's streams and allocations are valid here
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        L.tefmm_default_options.argtypes = [ctypes.POINTER(OptionsC)]
+        L.tefmm_default_options.restype = None
+        L.tefmm_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(MediumC), ctypes.POINTER(OptionsC)]
+        L.tefmm_set_particles.argtypes = [vp, i64, vp, i32, vp]
+        L.tefmm_evaluate.argtypes = [vp, vp, i32, vp, vp]
+        L.tefmm_get_stats.argtypes = [vp, ctypes.POINTER(StatsC)]
+        L.tefmm_last_error.argtypes = [vp]
+        L.tefmm_last_error.restype = ctypes.c_char_p
+        L.tefmm_destroy.argtypes = [vp]
+        L.tefmm_destroy.restype = None
+        L.tefmm_densities.argtypes = [ctypes.POINTER(MediumC), i32, i32, vp, vp]
+        L.tefmm_dcim_family.argtypes = [ctypes.POINTER(MediumC), ctypes.POINTER(OptionsC), i32, i32, dbl, dbl,
+                                        i32, ctypes.POINTER(i32), vp, vp, ctypes.POINTER(dbl)]
+        L.tefmm_taylor_coefficients.argtypes = [i32, vp, vp, vp, dbl, dbl, i32, vp]
+        L.tefmm_get_moments.argtypes = [vp, i32, i32, vp, i64]
+        L.tefmm_get_tree.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, ctypes.POINTER(dbl)]
+        L.tefmm_selftest_mfma.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _medium(k, d):
+    ka = (ctypes.c_double * len(k))(*[float(x) for x in k])
+    da = (ctypes.c_double * max(1, len(d)))(*[float(x) for x in d])
+    m = MediumC(len(k), da, ka)
+    m._keep = (ka, da)
+    return m
+
+
+def default_options(**kw) -> OptionsC:
+    o = OptionsC()
+    lib().tefmm_default_options(ctypes.byref(o))
+    for name, v in kw.items():
+        if name == "precision" and isinstance(v, str):
+            v = {"fp64": TEFMM_FP64, "fp32": TEFMM_MIXED_FP32, "mixed": TEFMM_MIXED_FP32}[v]
+        if name == "normalization" and isinstance(v, str):
+            v = {"physical": TEFMM_NORM_PHYSICAL, "paper": TEFMM_NORM_PAPER}[v]
+        setattr(o, name, v)
+    return o
+
+
+def _check(rc, h=None):
+    if rc != 0:
+        msg = lib().tefmm_last_error(h).decode() if h else ""
+        raise TefmmError(rc, msg)
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class TEFMM:
+    """Handle of one medium + options.  set_particles(xyz) then evaluate(q)."""
+
+    def __init__(self, k, d, **options):
+        self.k, self.d = tuple(k), tuple(d)
+        self._med = _medium(self.k, self.d)
+        self.opt = default_options(**options)
+        h = ctypes.c_void_p()
+        _check(lib().tefmm_create(ctypes.byref(h), ctypes.byref(self._med), ctypes.byref(self.opt)))
+        self.h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tefmm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_particles(self, xyz, stream=None):
+        """xyz: torch float64 tensor (N, 3) on the GPU (copied to SoA) or numpy (N, 3)."""
+        import torch
+        if isinstance(xyz, np.ndarray):
+            soa = torch.from_numpy(np.ascontiguousarray(np.asarray(xyz, np.float64).T)).cuda()
+        else:
+            soa = xyz.to(torch.float64).t().contiguous()
+        self._xyz = soa
+        self.n = soa.shape[1]
+        _check(lib().tefmm_set_particles(self.h, self.n, ctypes.c_void_p(soa.data_ptr()), 1, _stream_ptr(stream)),
+               self.h)
+
+    def evaluate(self, q, out=None, stream=None):
+        """q: torch complex128 on the GPU, shape (N,) or (R, N).  Returns phi, same shape."""
+        import torch
+        q = q.to(torch.complex128)
+        squeeze = q.dim() == 1
+        q2 = q.reshape(1, -1) if squeeze else q
+        q2 = q2.contiguous()
+        R = q2.shape[0]
+        if q2.shape[1] != self.n:
+            raise ValueError("charge vector length does not match the particles")
+        if out is None:
+            out = torch.empty_like(q2)
+        _check(lib().tefmm_evaluate(self.h, ctypes.c_void_p(q2.data_ptr()), R, ctypes.c_void_p(out.data_ptr()),
+                                    _stream_ptr(stream)), self.h)
+        return out.reshape(-1) if squeeze else out
+
+    def stats(self) -> dict:
+        s = StatsC()
+        _check(lib().tefmm_get_stats(self.h, ctypes.byref(s)), self.h)
+        d = {f[0]: getattr(s, f[0]) for f in StatsC._fields_}
+        d["n_images"] = list(s.n_images)[: s.n_families]
+        d["dcim_fit_err"] = list(s.dcim_fit_err)[: s.n_families]
+        d["depth"] = list(s.depth)
+        return d
+
+    def tree(self, g=0):
+        layer, depth, side = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        c = np.zeros(3)
+        _check(lib().tefmm_get_tree(self.h, g, ctypes.byref(layer), ctypes.byref(depth),
+                                    c.ctypes.data_as(ctypes.c_void_p), ctypes.byref(side)), self.h)
+        return {"layer": layer.value, "depth": depth.value, "centre": c, "side": side.value}
+
+    def moments(self, g, level):
+        nb = 8 ** level
+        nC = (self.opt.p + 1) * (self.opt.p + 2) * (self.opt.p + 3) // 6
+        out = np.zeros(nb * nC, np.complex128)
+        _check(lib().tefmm_get_moments(self.h, g, level, out.ctypes.data_as(ctypes.c_void_p), 2 * nb * nC), self.h)
+        return out.reshape(nb, nC)
+
+
+def densities(k, d, lp, krho):
+    """sigma^{ab}_{m,lp}(krho): array [m][ab][point], ab = uu, ud, du, dd (host FP64)."""
+    krho = np.ascontiguousarray(np.asarray(krho, np.complex128).ravel())
+    med = _medium(k, d)
+    out = np.zeros(len(k) * 4 * len(krho), np.complex128)
+    _check(lib().tefmm_densities(ctypes.byref(med), lp, len(krho), krho.ctypes.data_as(ctypes.c_void_p),
+                                 out.ctypes.data_as(ctypes.c_void_p)))
+    return out.reshape(len(k), 4, len(krho))
+
+
+def dcim_family(k, d, layer, family, z_lo, z_hi, **options):
+    """Complex images (A_j, depth_j) of a same-layer reaction family (host FP64)."""
+    med = _medium(k, d)
+    opt = default_options(**options)
+    cap = 256
+    amp = np.zeros(cap, np.complex128)
+    dep = np.zeros(cap, np.complex128)
+    m = ctypes.c_int()
+    fe = ctypes.c_double()
+    _check(lib().tefmm_dcim_family(ctypes.byref(med), ctypes.byref(opt), layer, family, float(z_lo), float(z_hi),
+                                   cap, ctypes.byref(m), amp.ctypes.data_as(ctypes.c_void_p),
+                                   dep.ctypes.data_as(ctypes.c_void_p), ctypes.byref(fe)))
+    return amp[: m.value].copy(), dep[: m.value].copy(), fe.value
+
+
+def taylor_coefficients(x, y, zeta, k, h, order):
+    """GPU recurrence: h^{|g|} D^g f / g! ... returned as a_g/h in box units (see tefmm.h)."""
+    import torch
+    x = torch.as_tensor(np.asarray(x, np.float64)).cuda()
+    y = torch.as_tensor(np.asarray(y, np.float64)).cuda()
+    z = torch.as_tensor(np.asarray(zeta, np.complex128)).cuda()
+    zr = torch.view_as_real(z).contiguous()
+    nT = (order + 1) * (order + 2) * (order + 3) // 6
+    out = torch.empty(len(x), nT, dtype=torch.complex128, device="cuda")
+    _check(lib().tefmm_taylor_coefficients(len(x), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                           ctypes.c_void_p(zr.data_ptr()), float(k), float(h), order,
+                                           ctypes.c_void_p(out.data_ptr())))
+    return out.cpu().numpy()
+
+
+def selftest_mfma() -> int:
+    return lib().tefmm_selftest_mfma()

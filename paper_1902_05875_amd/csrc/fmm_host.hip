@@ -1,0 +1,780 @@
+// Host orchestration and the C ABI of the layered-media TE-FMM.
+//
+// set_particles: per-layer uniform octrees (GPU radix sort by leaf), complex
+// image fits of the same-layer reaction families (host FP64), derivative
+// tables for every translation key (GPU FP64).  evaluate: P2M, M2M, M2L
+// (free + Delta family and Sigma family, MFMA), L2L, L2P, P2P, scale and
+// un-permute, all stream ordered on the caller's stream (Algorithm 1 for the
+// reaction components, fused with the free-space FMM of Algorithm 2 for the
+// same layer).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <hipcub/hipcub.hpp>
+#include <string>
+#include <vector>
+
+#include "../../include/tefmm.h"
+#include "fmm_kernels.hpp"
+#include "host_math.hpp"
+#include "kernels.hpp"
+
+namespace tefmm {
+bool medium_from_desc(const tefmm_medium* m, MediumDesc& out, std::string& err);
+}
+
+using namespace tefmm;
+
+namespace {
+
+const double PI = 3.14159265358979323846;
+
+struct Group {
+  int layer = 0, depth = 2;
+  double lo[3] = {0, 0, 0}, side = 1;
+  int64_t start = 0, count = 0, leaf_base = 0;
+  double zlo = 0, zhi = 0;
+  std::vector<cplx> famA[3], famZ[3];
+  double fam_err[3] = {0, 0, 0};
+  bool has[3] = {false, false, false};
+  std::vector<double2*> alpha, beta;  // by level
+  std::vector<double2*> Tfd, TS;
+  std::vector<float2*> Tfd32, TS32;
+  std::vector<int64_t> nbox;          // boxes at level
+};
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct tefmm_ctx {
+  MediumDesc med;
+  tefmm_options opt;
+  std::string err;
+  int nC = 0, nT = 0, nKB = 0, nRB = 0, nCs = 0;
+  // constant tables
+  int* d_mi = nullptr;
+  short* d_nbr = nullptr;
+  unsigned char* d_g3 = nullptr;
+  double *d_fact = nullptr, *d_scale = nullptr, *d_invfact = nullptr;
+  // geometry
+  int64_t n = 0;
+  double* d_xs = nullptr;   // sorted SoA
+  int* d_perm = nullptr;
+  int* d_leaf_start = nullptr;
+  int* d_leaf_count = nullptr;
+  int64_t total_leaves = 0;
+  std::vector<Group> groups;
+  // evaluate buffers
+  double2 *d_q = nullptr, *d_phi = nullptr;
+  int nrhs_alloc = 0;
+  bool ready = false;
+  // stats
+  tefmm_stats st;
+  std::vector<hipEvent_t> ev;
+  int64_t p2p_pairs = 0, m2l_pairs = 0;
+};
+
+static int fail(tefmm_t h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+#define HIPCHK(h, x)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess)                                                          \
+      return fail(h, TEFMM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static void free_geometry(tefmm_t h) {
+  dfree(h->d_xs);
+  dfree(h->d_perm);
+  dfree(h->d_leaf_start);
+  dfree(h->d_leaf_count);
+  for (auto& g : h->groups) {
+    for (auto& p : g.alpha) dfree(p);
+    for (auto& p : g.beta) dfree(p);
+    for (auto& p : g.Tfd) dfree(p);
+    for (auto& p : g.TS) dfree(p);
+    for (auto& p : g.Tfd32) dfree(p);
+    for (auto& p : g.TS32) dfree(p);
+  }
+  h->groups.clear();
+  dfree(h->d_q);
+  dfree(h->d_phi);
+  h->nrhs_alloc = 0;
+  h->ready = false;
+}
+
+static int build_constant_tables(tefmm_t h) {
+  const int p = h->opt.p;
+  h->nC = mi_count(p);
+  h->nT = mi_count(2 * p);
+  h->nKB = (h->nC + 3) / 4;
+  h->nRB = (h->nC + 15) / 16;
+  int cs = 4 * h->nKB;
+  while (cs % 16 != 1) ++cs;
+  h->nCs = cs;
+  const int nT = h->nT, nC = h->nC;
+  std::vector<int> mi(nT);
+  std::vector<short> nbr(6 * nT, -1);
+  std::vector<unsigned char> g3(nT);
+  std::vector<double> fact(nT), scale(nC), invfact(nC);
+  auto f = [](int n) {
+    double r = 1;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+  };
+  for (int m = 0; m <= 2 * p; ++m)
+    for (int a = m; a >= 0; --a)
+      for (int b = m - a; b >= 0; --b) {
+        const int c = m - a - b, i = mi_index(a, b, c);
+        mi[i] = a | (b << 8) | (c << 16);
+        g3[i] = (unsigned char)c;
+        fact[i] = f(a) * f(b) * f(c);
+        if (a >= 1) nbr[6 * i + 0] = (short)mi_index(a - 1, b, c);
+        if (b >= 1) nbr[6 * i + 1] = (short)mi_index(a, b - 1, c);
+        if (c >= 1) nbr[6 * i + 2] = (short)mi_index(a, b, c - 1);
+        if (a >= 2) nbr[6 * i + 3] = (short)mi_index(a - 2, b, c);
+        if (b >= 2) nbr[6 * i + 4] = (short)mi_index(a, b - 2, c);
+        if (c >= 2) nbr[6 * i + 5] = (short)mi_index(a, b, c - 2);
+        if (m <= p) {
+          scale[i] = ((m & 1) ? -1.0 : 1.0) / fact[i];
+          invfact[i] = 1.0 / fact[i];
+        }
+      }
+  HIPCHK(h, hipMalloc(&h->d_mi, sizeof(int) * nT));
+  HIPCHK(h, hipMalloc(&h->d_nbr, sizeof(short) * 6 * nT));
+  HIPCHK(h, hipMalloc(&h->d_g3, nT));
+  HIPCHK(h, hipMalloc(&h->d_fact, sizeof(double) * nT));
+  HIPCHK(h, hipMalloc(&h->d_scale, sizeof(double) * nC));
+  HIPCHK(h, hipMalloc(&h->d_invfact, sizeof(double) * nC));
+  HIPCHK(h, hipMemcpy(h->d_mi, mi.data(), sizeof(int) * nT, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_nbr, nbr.data(), sizeof(short) * 6 * nT, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_g3, g3.data(), nT, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_fact, fact.data(), sizeof(double) * nT, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_scale, scale.data(), sizeof(double) * nC, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_invfact, invfact.data(), sizeof(double) * nC, hipMemcpyHostToDevice));
+  upload_binomials();
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefmm_options* opt) {
+  if (!out) return TEFMM_ERR_INVALID_ARG;
+  *out = nullptr;
+  tefmm_ctx* h = new tefmm_ctx();
+  std::string err;
+  if (!medium_from_desc(medium, h->med, err)) {
+    delete h;
+    return TEFMM_ERR_INVALID_ARG;
+  }
+  if (opt)
+    h->opt = *opt;
+  else
+    tefmm_default_options(&h->opt);
+  const tefmm_options& o = h->opt;
+  if (o.p < 1 || o.p > 10 || o.depth < 0 || o.depth > 7 || o.max_leaf < 1 ||
+      (o.precision != TEFMM_FP64 && o.precision != TEFMM_MIXED_FP32) ||
+      (o.normalization != TEFMM_NORM_PHYSICAL && o.normalization != TEFMM_NORM_PAPER) || o.dcim_samples < 8 ||
+      !(o.dcim_T1 > 0) || !(o.dcim_svd_tol > 0) || !(o.interface_eps >= 0) || o.n_rhs_max < 1) {
+    delete h;
+    return TEFMM_ERR_INVALID_ARG;
+  }
+  std::memset(&h->st, 0, sizeof(h->st));
+  int rc = build_constant_tables(h);
+  if (rc != TEFMM_OK) {
+    tefmm_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return TEFMM_OK;
+}
+
+extern "C" void tefmm_destroy(tefmm_t h) {
+  if (!h) return;
+  free_geometry(h);
+  dfree(h->d_mi);
+  dfree(h->d_nbr);
+  dfree(h->d_g3);
+  dfree(h->d_fact);
+  dfree(h->d_scale);
+  dfree(h->d_invfact);
+  for (auto& e : h->ev) (void)hipEventDestroy(e);
+  delete h;
+}
+
+extern "C" const char* tefmm_last_error(tefmm_t h) { return h ? h->err.c_str() : "null handle"; }
+
+// ---------------------------------------------------------------------------
+// Derivative tables of one group (all levels).
+// ---------------------------------------------------------------------------
+static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
+  const MediumDesc& med = h->med;
+  const int l_ = g.layer;
+  const double D = (l_ > 0 && l_ < med.L) ? med.thickness(l_) : 0.0;
+  const double k = med.k[l_];
+  g.Tfd.assign(g.depth + 1, nullptr);
+  g.TS.assign(g.depth + 1, nullptr);
+  g.Tfd32.assign(g.depth + 1, nullptr);
+  g.TS32.assign(g.depth + 1, nullptr);
+  const bool has_sigma = g.has[0] || g.has[1];
+  for (int lev = 2; lev <= g.depth; ++lev) {
+    const int nb = 1 << lev;
+    const double hb = g.side / nb;
+    const bool leaf = lev == g.depth;
+    for (int which = 0; which < 2; ++which) {
+      if (which == 1 && !has_sigma) continue;
+      std::vector<TableTerm> terms;
+      std::vector<int> start;
+      std::vector<double> hk;
+      int nkeys;
+      auto push = [&](double x, double y, cplx zeta, cplx coef, int flip, bool image) {
+        // an image term is valid only for Re(zeta) > 0; keys failing this join
+        // boxes outside the layer (empty, zero moments) and are left out
+        if (image && zeta.real() <= 1e-9) return;
+        TableTerm t;
+        t.x = x, t.y = y, t.zr = zeta.real(), t.zi = zeta.imag(), t.cr = coef.real(), t.ci = coef.imag();
+        t.flip = flip, t.pad = 0;
+        terms.push_back(t);
+      };
+      if (which == 0) {
+        nkeys = 343;
+        for (int dx = -3; dx <= 3; ++dx)
+          for (int dy = -3; dy <= 3; ++dy)
+            for (int dz = -3; dz <= 3; ++dz) {
+              start.push_back((int)terms.size());
+              hk.push_back(hb);
+              const bool nearb = std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) <= 1;
+              // the key (dx, dy, dz) is the source offset; the kernel is evaluated at the
+              // centre displacement target - source = -(dx, dy, dz) h
+              if (!nearb) push(-dx, -dy, cplx(-dz, 0), cplx(1, 0), 0, false);
+              if (g.has[2] && (!nearb || leaf)) {
+                // w = z_t - z_s = -dz h enters as D + w (flip 0) and D - w (flip 1)
+                for (size_t j = 0; j < g.famA[2].size(); ++j) {
+                  const cplx A = g.famA[2][j], Z = g.famZ[2][j];
+                  push(-dx, -dy, (D - dz * hb - Z) / hb, A, 0, true);
+                  push(-dx, -dy, (D + dz * hb - Z) / hb, A, 1, true);
+                }
+              }
+            }
+      } else {
+        nkeys = 49 * (2 * nb - 1);
+        for (int dx = -3; dx <= 3; ++dx)
+          for (int dy = -3; dy <= 3; ++dy)
+            for (int m = 0; m <= 2 * nb - 2; ++m) {
+              start.push_back((int)terms.size());
+              hk.push_back(hb);
+              const double S = 2 * g.lo[2] + (m + 1) * hb;
+              if (g.has[0])
+                for (size_t j = 0; j < g.famA[0].size(); ++j)
+                  push(-dx, -dy, (S - 2 * med.d[l_] - g.famZ[0][j]) / hb, g.famA[0][j], 0, true);
+              if (g.has[1])
+                for (size_t j = 0; j < g.famA[1].size(); ++j)
+                  push(-dx, -dy, (2 * med.d[l_ - 1] - S - g.famZ[1][j]) / hb, g.famA[1][j], 1, true);
+            }
+      }
+      start.push_back((int)terms.size());
+      TableTerm* d_terms = nullptr;
+      int* d_start = nullptr;
+      double* d_h = nullptr;
+      double2* d_out = nullptr;
+      HIPCHK(h, hipMalloc(&d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
+      HIPCHK(h, hipMalloc(&d_start, sizeof(int) * start.size()));
+      HIPCHK(h, hipMalloc(&d_h, sizeof(double) * hk.size()));
+      HIPCHK(h, hipMalloc(&d_out, sizeof(double2) * (size_t)nkeys * h->nT));
+      if (!terms.empty())
+        HIPCHK(h, hipMemcpyAsync(d_terms, terms.data(), sizeof(TableTerm) * terms.size(), hipMemcpyHostToDevice, s));
+      HIPCHK(h, hipMemcpyAsync(d_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, s));
+      HIPCHK(h, hipMemcpyAsync(d_h, hk.data(), sizeof(double) * hk.size(), hipMemcpyHostToDevice, s));
+      TableGenArgs ta;
+      ta.terms = d_terms, ta.term_start = d_start, ta.h = d_h, ta.k = k, ta.order = 2 * h->opt.p, ta.nT = h->nT;
+      ta.nbr = h->d_nbr, ta.g3 = h->d_g3, ta.fact = h->d_fact, ta.out = d_out;
+      const size_t lds = 2 * sizeof(double2) * h->nT;
+      HIPCHK(h, hipFuncSetAttribute((const void*)k_table_gen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL(k_table_gen, dim3(nkeys), dim3(64), lds, s, ta);
+      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, hipStreamSynchronize(s));
+      dfree(d_terms);
+      dfree(d_start);
+      dfree(d_h);
+      if (which == 0)
+        g.Tfd[lev] = d_out;
+      else
+        g.TS[lev] = d_out;
+      if (h->opt.precision == TEFMM_MIXED_FP32) {
+        const size_t cnt = (size_t)nkeys * h->nT;
+        std::vector<double2> hd(cnt);
+        std::vector<float2> hf(cnt);
+        HIPCHK(h, hipMemcpy(hd.data(), d_out, sizeof(double2) * cnt, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < cnt; ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
+        float2* d32 = nullptr;
+        HIPCHK(h, hipMalloc(&d32, sizeof(float2) * cnt));
+        HIPCHK(h, hipMemcpy(d32, hf.data(), sizeof(float2) * cnt, hipMemcpyHostToDevice));
+        if (which == 0)
+          g.Tfd32[lev] = d32;
+        else
+          g.TS32[lev] = d32;
+      }
+    }
+  }
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int on_device, void* stream) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  if (n < 1 || !xyz) return fail(h, TEFMM_ERR_INVALID_ARG, "need n >= 1 particles");
+  if (n > (int64_t)2000000000) return fail(h, TEFMM_ERR_INVALID_ARG, "too many particles");
+  hipStream_t s = (hipStream_t)stream;
+  free_geometry(h);
+  const MediumDesc& med = h->med;
+  const int L = med.L;
+  hipEvent_t e0, e1, e2;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  HIPCHK(h, hipEventCreate(&e2));
+  HIPCHK(h, hipEventRecord(e0, s));
+  double* d_in = nullptr;
+  const double* src = xyz;
+  if (!on_device) {
+    HIPCHK(h, hipMalloc(&d_in, sizeof(double) * 3 * n));
+    HIPCHK(h, hipMemcpyAsync(d_in, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    src = d_in;
+  }
+  double* d_if = nullptr;
+  HIPCHK(h, hipMalloc(&d_if, sizeof(double) * std::max(L, 1)));
+  if (L) HIPCHK(h, hipMemcpyAsync(d_if, med.d.data(), sizeof(double) * L, hipMemcpyHostToDevice, s));
+  // layer statistics
+  const int nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  double* d_part = nullptr;
+  int* d_bad = nullptr;
+  HIPCHK(h, hipMalloc(&d_part, sizeof(double) * nblk * 4 * 7));
+  HIPCHK(h, hipMalloc(&d_bad, sizeof(int)));
+  HIPCHK(h, hipMemsetAsync(d_bad, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_layer_stats, dim3(nblk), dim3(256), 0, s, src, n, L, d_if, h->opt.interface_eps, d_part, d_bad);
+  HIPCHK(h, hipGetLastError());
+  std::vector<double> part((size_t)nblk * 28);
+  int bad = 0;
+  HIPCHK(h, hipMemcpyAsync(part.data(), d_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  dfree(d_part);
+  dfree(d_bad);
+  if (bad & 2) {
+    dfree(d_in), dfree(d_if);
+    return fail(h, TEFMM_ERR_INVALID_ARG, "non-finite particle coordinate");
+  }
+  if (bad & 1) {
+    dfree(d_in), dfree(d_if);
+    return fail(h, TEFMM_ERR_PARTICLE_ON_INTERFACE, "a particle lies within interface_eps of an interface");
+  }
+  double mn[4][3], mx[4][3];
+  int64_t cnt[4] = {0, 0, 0, 0};
+  for (int l = 0; l < 4; ++l)
+    for (int c = 0; c < 3; ++c) mn[l][c] = 1e300, mx[l][c] = -1e300;
+  for (int b = 0; b < nblk; ++b)
+    for (int l = 0; l < 4; ++l) {
+      const double* o = &part[((size_t)b * 4 + l) * 7];
+      for (int c = 0; c < 3; ++c) mn[l][c] = std::min(mn[l][c], o[c]), mx[l][c] = std::max(mx[l][c], o[3 + c]);
+      cnt[l] += (int64_t)o[6];
+    }
+  int ngroups = 0;
+  for (int l = 0; l <= L; ++l) ngroups += cnt[l] > 0;
+  if (ngroups > 1) {
+    dfree(d_in), dfree(d_if);
+    return fail(h, TEFMM_ERR_UNSUPPORTED, "particles in more than one layer: cross-layer components not built");
+  }
+  TreeGeom geo;
+  std::memset(&geo, 0, sizeof(geo));
+  for (int l = 0; l < 4; ++l) geo.group_of_layer[l] = 0;
+  int64_t leaf_off = 0, pos = 0;
+  for (int l = 0; l <= L; ++l) {
+    if (!cnt[l]) continue;
+    Group g;
+    g.layer = l;
+    g.count = cnt[l];
+    g.start = pos;
+    pos += cnt[l];
+    double side = 0;
+    for (int c = 0; c < 3; ++c) side = std::max(side, mx[l][c] - mn[l][c]);
+    side = side * (1 + 1e-9) + 1e-12;
+    for (int c = 0; c < 3; ++c) g.lo[c] = 0.5 * (mn[l][c] + mx[l][c]) - 0.5 * side;
+    g.side = side;
+    int depth = h->opt.depth;
+    if (depth == 0) {
+      depth = 2;
+      while (depth < 7 && (double)cnt[l] / std::pow(8.0, depth) > h->opt.max_leaf) ++depth;
+    }
+    g.depth = std::max(2, std::min(7, depth));
+    g.leaf_base = leaf_off;
+    leaf_off += (int64_t)1 << (3 * g.depth);
+    g.zlo = mn[l][2], g.zhi = mx[l][2];
+    const int gi = (int)h->groups.size();
+    geo.group_of_layer[l] = gi;
+    geo.depth[gi] = g.depth;
+    for (int c = 0; c < 3; ++c) geo.lo[gi][c] = g.lo[c];
+    geo.side[gi] = g.side;
+    geo.leaf_offset[gi] = g.leaf_base;
+    h->groups.push_back(g);
+  }
+  h->total_leaves = leaf_off;
+  h->n = n;
+  // sort particles by leaf
+  unsigned *d_keys = nullptr, *d_keys2 = nullptr;
+  int* d_perm_in = nullptr;
+  HIPCHK(h, hipMalloc(&d_keys, sizeof(unsigned) * n));
+  HIPCHK(h, hipMalloc(&d_keys2, sizeof(unsigned) * n));
+  HIPCHK(h, hipMalloc(&d_perm_in, sizeof(int) * n));
+  HIPCHK(h, hipMalloc(&h->d_perm, sizeof(int) * n));
+  const int nb256 = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_leaf_keys, dim3(nb256), dim3(256), 0, s, src, n, L, d_if, geo, d_keys, d_perm_in);
+  HIPCHK(h, hipGetLastError());
+  int end_bit = 1;
+  while (((int64_t)1 << end_bit) < leaf_off) ++end_bit;
+  size_t tmp_bytes = 0;
+  HIPCHK(h, hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, d_keys, d_keys2, d_perm_in, h->d_perm, (int)n, 0,
+                                               end_bit, s));
+  void* d_tmp = nullptr;
+  HIPCHK(h, hipMalloc(&d_tmp, std::max<size_t>(tmp_bytes, 16)));
+  HIPCHK(h, hipcub::DeviceRadixSort::SortPairs(d_tmp, tmp_bytes, d_keys, d_keys2, d_perm_in, h->d_perm, (int)n, 0,
+                                               end_bit, s));
+  dfree(d_tmp);
+  HIPCHK(h, hipMalloc(&h->d_leaf_count, sizeof(int) * leaf_off));
+  HIPCHK(h, hipMalloc(&h->d_leaf_start, sizeof(int) * leaf_off));
+  HIPCHK(h, hipMemsetAsync(h->d_leaf_count, 0, sizeof(int) * leaf_off, s));
+  hipLaunchKernelGGL(k_count_keys, dim3(nb256), dim3(256), 0, s, d_keys2, n, h->d_leaf_count);
+  HIPCHK(h, hipGetLastError());
+  tmp_bytes = 0;
+  HIPCHK(h, hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, h->d_leaf_count, h->d_leaf_start, (int)leaf_off, s));
+  HIPCHK(h, hipMalloc(&d_tmp, std::max<size_t>(tmp_bytes, 16)));
+  HIPCHK(h, hipcub::DeviceScan::ExclusiveSum(d_tmp, tmp_bytes, h->d_leaf_count, h->d_leaf_start, (int)leaf_off, s));
+  HIPCHK(h, hipMalloc(&h->d_xs, sizeof(double) * 3 * n));
+  hipLaunchKernelGGL(k_gather_pos, dim3(nb256), dim3(256), 0, s, src, h->d_perm, n, h->d_xs);
+  HIPCHK(h, hipGetLastError());
+  std::vector<int> lc(leaf_off);
+  HIPCHK(h, hipMemcpyAsync(lc.data(), h->d_leaf_count, sizeof(int) * leaf_off, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  dfree(d_tmp);
+  dfree(d_keys);
+  dfree(d_keys2);
+  dfree(d_perm_in);
+  dfree(d_in);
+  dfree(d_if);
+  HIPCHK(h, hipEventRecord(e1, s));
+  // interaction counts (statistics)
+  h->p2p_pairs = 0;
+  h->m2l_pairs = 0;
+  for (auto& g : h->groups) {
+    const int nb = 1 << g.depth;
+    for (int ix = 0; ix < nb; ++ix)
+      for (int iy = 0; iy < nb; ++iy)
+        for (int iz = 0; iz < nb; ++iz) {
+          int64_t c = lc[g.leaf_base + ((int64_t)ix * nb + iy) * nb + iz], nbsum = 0;
+          for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dz = -1; dz <= 1; ++dz) {
+                int jx = ix + dx, jy = iy + dy, jz = iz + dz;
+                if (jx < 0 || jy < 0 || jz < 0 || jx >= nb || jy >= nb || jz >= nb) continue;
+                nbsum += lc[g.leaf_base + ((int64_t)jx * nb + jy) * nb + jz];
+              }
+          h->p2p_pairs += c * nbsum - c;
+        }
+    for (int lev = 2; lev <= g.depth; ++lev) {
+      const int nb2 = 1 << lev;
+      auto cnt1 = [&](int i, int d) {
+        int j = i + d;
+        return j >= 0 && j < nb2;
+      };
+      for (int ix = 0; ix < nb2; ++ix)
+        for (int dx = -2 - (ix & 1); dx <= 3 - (ix & 1); ++dx) {
+          if (!cnt1(ix, dx)) continue;
+          for (int iy = 0; iy < nb2; ++iy)
+            for (int dy = -2 - (iy & 1); dy <= 3 - (iy & 1); ++dy) {
+              if (!cnt1(iy, dy)) continue;
+              for (int iz = 0; iz < nb2; ++iz)
+                for (int dz = -2 - (iz & 1); dz <= 3 - (iz & 1); ++dz) {
+                  if (!cnt1(iz, dz)) continue;
+                  if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+                  h->m2l_pairs++;
+                }
+            }
+        }
+    }
+  }
+  // complex images (host FP64)
+  for (auto& g : h->groups) {
+    const int l = g.layer;
+    const double hleaf = g.side / (1 << g.depth);
+    double zlo = std::min(g.zlo, g.lo[2] + 0.5 * hleaf), zhi = std::max(g.zhi, g.lo[2] + g.side - 0.5 * hleaf);
+    const double top = med.top(l), bot = med.bottom(l);
+    zlo = std::max(zlo, bot + 1e-6);
+    zhi = std::min(zhi, top - 1e-6);
+    for (int fam = 0; fam < 3; ++fam) {
+      std::string err;
+      if (!same_layer_family(med, l, fam, zlo, zhi, h->opt.dcim_T1, h->opt.dcim_samples, h->opt.dcim_svd_tol,
+                             g.famA[fam], g.famZ[fam], g.fam_err[fam], err))
+        return fail(h, TEFMM_ERR_DCIM_FIT, "complex-image fit failed: " + err);
+      g.has[fam] = !g.famA[fam].empty();
+    }
+  }
+  // derivative tables
+  for (auto& g : h->groups) {
+    int rc = build_tables(h, g, s);
+    if (rc != TEFMM_OK) return rc;
+  }
+  HIPCHK(h, hipEventRecord(e2, s));
+  HIPCHK(h, hipEventSynchronize(e2));
+  float ms1 = 0, ms2 = 0;
+  (void)hipEventElapsedTime(&ms1, e0, e1);
+  (void)hipEventElapsedTime(&ms2, e1, e2);
+  std::memset(&h->st, 0, sizeof(h->st));
+  h->st.t_setup_tree_ms = ms1;
+  h->st.t_setup_tables_ms = ms2;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  int fi = 0;
+  for (size_t gi = 0; gi < h->groups.size() && gi < 4; ++gi) {
+    auto& g = h->groups[gi];
+    h->st.depth[gi] = g.depth;
+    for (int fam = 0; fam < 3 && fi < 8; ++fam)
+      if (g.has[fam]) {
+        h->st.n_images[fi] = (int)g.famA[fam].size();
+        h->st.dcim_fit_err[fi] = g.fam_err[fam];
+        ++fi;
+      }
+  }
+  h->st.n_families = fi;
+  h->st.p2p_pairs = h->p2p_pairs;
+  h->st.m2l_pairs = h->m2l_pairs;
+  h->ready = true;
+  return TEFMM_OK;
+}
+
+static int ensure_rhs(tefmm_t h, int nrhs) {
+  if (nrhs <= h->nrhs_alloc) return TEFMM_OK;
+  dfree(h->d_q);
+  dfree(h->d_phi);
+  for (auto& g : h->groups) {
+    for (auto& p : g.alpha) dfree(p);
+    for (auto& p : g.beta) dfree(p);
+  }
+  HIPCHK(h, hipMalloc(&h->d_q, sizeof(double2) * h->n * nrhs));
+  HIPCHK(h, hipMalloc(&h->d_phi, sizeof(double2) * h->n * nrhs));
+  for (auto& g : h->groups) {
+    g.alpha.assign(g.depth + 1, nullptr);
+    g.beta.assign(g.depth + 1, nullptr);
+    g.nbox.assign(g.depth + 1, 0);
+    for (int lev = 2; lev <= g.depth; ++lev) {
+      const int64_t nbx = (int64_t)1 << (3 * lev);
+      g.nbox[lev] = nbx;
+      HIPCHK(h, hipMalloc(&g.alpha[lev], sizeof(double2) * nbx * h->nC * nrhs));
+      HIPCHK(h, hipMalloc(&g.beta[lev], sizeof(double2) * nbx * h->nC * nrhs));
+    }
+  }
+  h->nrhs_alloc = nrhs;
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, void* stream) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  if (!h->ready) return fail(h, TEFMM_ERR_STATE, "set_particles has not succeeded");
+  if (!q || !phi || nrhs < 1 || nrhs > h->opt.n_rhs_max) return fail(h, TEFMM_ERR_INVALID_ARG, "bad q/phi/n_rhs");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_rhs(h, nrhs);
+  if (rc != TEFMM_OK) return rc;
+  if (h->ev.empty()) {
+    h->ev.resize(8);
+    for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
+  }
+  const int64_t n = h->n;
+  const bool fp32 = h->opt.precision == TEFMM_MIXED_FP32;
+  HIPCHK(h, hipEventRecord(h->ev[0], s));
+  hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, (const double2*)q,
+                     h->d_perm, n, h->d_q);
+  HIPCHK(h, hipGetLastError());
+  for (auto& g : h->groups) {
+    const int H = g.depth, p = h->opt.p;
+    PassArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.p = p, pa.nC = h->nC, pa.k = h->med.k[g.layer], pa.n = n, pa.xs = h->d_xs, pa.q = h->d_q, pa.phi = h->d_phi;
+    pa.leaf_start = h->d_leaf_start, pa.leaf_count = h->d_leaf_count, pa.leaf_base = g.leaf_base, pa.mi = h->d_mi;
+    for (int c = 0; c < 3; ++c) pa.lo[c] = g.lo[c];
+    // P2M at the leaves
+    {
+      PassArgs a = pa;
+      a.nbox_dim = 1 << H, a.h = g.side / (1 << H), a.alpha = g.alpha[H], a.rhs_stride = g.nbox[H] * h->nC;
+      const size_t lds = sizeof(double) * 64 * 3 * (p + 1) + sizeof(double2) * 64;
+      hipLaunchKernelGGL(k_p2m, dim3((unsigned)g.nbox[H], nrhs), dim3(64), lds, s, a);
+      HIPCHK(h, hipGetLastError());
+    }
+    HIPCHK(h, hipEventRecord(h->ev[1], s));
+    for (int lev = H - 1; lev >= 2; --lev) {
+      PassArgs a = pa;
+      a.nbox_dim = 1 << lev, a.alpha = g.alpha[lev], a.rhs_stride = g.nbox[lev] * h->nC;
+      a.alpha_child = g.alpha[lev + 1], a.rhs_stride_child = g.nbox[lev + 1] * h->nC;
+      const size_t lds = sizeof(double2) * 8 * h->nC;
+      HIPCHK(h, hipFuncSetAttribute((const void*)k_m2m, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL(k_m2m, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), lds, s, a);
+      HIPCHK(h, hipGetLastError());
+    }
+    HIPCHK(h, hipEventRecord(h->ev[2], s));
+    for (int lev = 2; lev <= H; ++lev) {
+      M2LArgs m;
+      std::memset(&m, 0, sizeof(m));
+      const int nb = 1 << lev;
+      m.n = nb, m.nC = h->nC, m.nCs = h->nCs, m.nKB = h->nKB, m.nRB = h->nRB, m.leaf = lev == H;
+      m.tiles_x = ((nb / 2) + 3) / 4;
+      m.ntiles = nb * 4 * m.tiles_x * m.tiles_x;
+      m.alpha = g.alpha[lev], m.beta = g.beta[lev], m.rhs_stride = g.nbox[lev] * h->nC;
+      m.Tfd = g.Tfd[lev], m.TS = g.TS[lev], m.Tfd32 = g.Tfd32[lev], m.TS32 = g.TS32[lev], m.nT = h->nT;
+      m.near_fd = g.has[2], m.near_s = g.has[0] || g.has[1];
+      m.mi = h->d_mi, m.scale = h->d_scale, m.invfact = h->d_invfact;
+      HIPCHK(h, launch_m2l(m, nrhs, fp32, s));
+    }
+    HIPCHK(h, hipEventRecord(h->ev[3], s));
+    for (int lev = 3; lev <= H; ++lev) {
+      PassArgs a = pa;
+      a.nbox_dim = 1 << lev, a.beta = g.beta[lev], a.rhs_stride = g.nbox[lev] * h->nC;
+      a.beta_parent = g.beta[lev - 1], a.rhs_stride_parent = g.nbox[lev - 1] * h->nC;
+      hipLaunchKernelGGL(k_l2l, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, a);
+      HIPCHK(h, hipGetLastError());
+    }
+    HIPCHK(h, hipEventRecord(h->ev[4], s));
+    {
+      PassArgs a = pa;
+      a.nbox_dim = 1 << H, a.h = g.side / (1 << H), a.beta = g.beta[H], a.rhs_stride = g.nbox[H] * h->nC;
+      const size_t lds = sizeof(double2) * h->nC + sizeof(double) * 64 * 3 * (p + 1) + sizeof(int) * h->nC;
+      hipLaunchKernelGGL(k_l2p, dim3((unsigned)g.nbox[H], nrhs), dim3(64), lds, s, a);
+      HIPCHK(h, hipGetLastError());
+    }
+    HIPCHK(h, hipEventRecord(h->ev[5], s));
+    {
+      PassArgs a = pa;
+      a.nbox_dim = 1 << H;
+      if (fp32)
+        hipLaunchKernelGGL(k_p2p<float>, dim3((unsigned)g.nbox[H], nrhs), dim3(64), 0, s, a);
+      else
+        hipLaunchKernelGGL(k_p2p<double>, dim3((unsigned)g.nbox[H], nrhs), dim3(64), 0, s, a);
+      HIPCHK(h, hipGetLastError());
+    }
+    HIPCHK(h, hipEventRecord(h->ev[6], s));
+    {
+      double sr = 1.0 / (4 * PI), si = 0.0;
+      if (h->opt.normalization == TEFMM_NORM_PAPER) {  // divide by i k
+        const double kk = h->med.k[g.layer];
+        sr = 0.0, si = -1.0 / kk;
+      }
+      hipLaunchKernelGGL(k_finalize, dim3((unsigned)((g.count + 255) / 256), nrhs), dim3(256), 0, s, h->d_phi,
+                         h->d_perm, g.start, g.count, n, sr, si, (double2*)phi);
+      HIPCHK(h, hipGetLastError());
+    }
+  }
+  HIPCHK(h, hipEventRecord(h->ev[7], s));
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_get_stats(tefmm_t h, tefmm_stats* st) {
+  if (!h || !st) return TEFMM_ERR_INVALID_ARG;
+  if (h->ev.size() == 8) {
+    HIPCHK(h, hipEventSynchronize(h->ev[7]));
+    float t[8] = {0};
+    for (int i = 1; i < 8; ++i) (void)hipEventElapsedTime(&t[i], h->ev[i - 1], h->ev[i]);
+    h->st.t_p2m_ms = t[1] + 0;  // includes the charge gather
+    h->st.t_m2m_ms = t[2];
+    h->st.t_m2l_ms = t[3];
+    h->st.t_l2l_ms = t[4];
+    h->st.t_l2p_ms = t[5];
+    h->st.t_p2p_ms = t[6];
+    float tot = 0;
+    (void)hipEventElapsedTime(&tot, h->ev[0], h->ev[7]);
+    h->st.t_total_ms = tot;
+  }
+  *st = h->st;
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_get_moments(tefmm_t h, int gi, int level, double* out, int64_t cap) {
+  if (!h || !h->ready || gi < 0 || gi >= (int)h->groups.size()) return TEFMM_ERR_INVALID_ARG;
+  Group& g = h->groups[gi];
+  if (level < 2 || level > g.depth || g.alpha.empty() || !g.alpha[level]) return TEFMM_ERR_STATE;
+  const int64_t cnt = g.nbox[level] * h->nC;
+  if (cap < cnt * 2) return TEFMM_ERR_INVALID_ARG;
+  HIPCHK(h, hipDeviceSynchronize());
+  HIPCHK(h, hipMemcpy(out, g.alpha[level], sizeof(double2) * cnt, hipMemcpyDeviceToHost));
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_get_tree(tefmm_t h, int gi, int* layer, int* depth, double* centre3, double* side) {
+  if (!h || !h->ready || gi < 0 || gi >= (int)h->groups.size()) return TEFMM_ERR_INVALID_ARG;
+  Group& g = h->groups[gi];
+  if (layer) *layer = g.layer;
+  if (depth) *depth = g.depth;
+  if (centre3)
+    for (int c = 0; c < 3; ++c) centre3[c] = g.lo[c] + 0.5 * g.side;
+  if (side) *side = g.side;
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_taylor_coefficients(int n, const double* x, const double* y, const double* zeta, double k,
+                                         double hsc, int order, double* out) {
+  if (n < 0 || order < 0 || order > 20 || !(hsc > 0)) return TEFMM_ERR_INVALID_ARG;
+  if (n == 0) return TEFMM_OK;
+  const int nT = mi_count(order);
+  std::vector<short> nbr(6 * nT, -1);
+  for (int m = 0; m <= order; ++m)
+    for (int a = m; a >= 0; --a)
+      for (int b = m - a; b >= 0; --b) {
+        const int c = m - a - b, i = mi_index(a, b, c);
+        if (a >= 1) nbr[6 * i + 0] = (short)mi_index(a - 1, b, c);
+        if (b >= 1) nbr[6 * i + 1] = (short)mi_index(a, b - 1, c);
+        if (c >= 1) nbr[6 * i + 2] = (short)mi_index(a, b, c - 1);
+        if (a >= 2) nbr[6 * i + 3] = (short)mi_index(a - 2, b, c);
+        if (b >= 2) nbr[6 * i + 4] = (short)mi_index(a, b - 2, c);
+        if (c >= 2) nbr[6 * i + 5] = (short)mi_index(a, b, c - 2);
+      }
+  short* d_nbr = nullptr;
+  if (hipMalloc(&d_nbr, sizeof(short) * 6 * nT) != hipSuccess) return TEFMM_ERR_HIP;
+  if (hipMemcpy(d_nbr, nbr.data(), sizeof(short) * 6 * nT, hipMemcpyHostToDevice) != hipSuccess) {
+    dfree(d_nbr);
+    return TEFMM_ERR_HIP;
+  }
+  const size_t lds = 2 * sizeof(double2) * nT;
+  (void)hipFuncSetAttribute((const void*)k_taylor_points, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_taylor_points, dim3(n), dim3(64), lds, 0, x, y, zeta, k, hsc, order, nT, d_nbr,
+                     (double2*)out);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  dfree(d_nbr);
+  return e == hipSuccess ? TEFMM_OK : TEFMM_ERR_HIP;
+}
+
+extern "C" int tefmm_selftest_mfma(void) {
+  double* d64 = nullptr;
+  float* d32 = nullptr;
+  if (hipMalloc(&d64, 256 * sizeof(double)) != hipSuccess) return TEFMM_ERR_HIP;
+  if (hipMalloc(&d32, 256 * sizeof(float)) != hipSuccess) return TEFMM_ERR_HIP;
+  hipLaunchKernelGGL(k_selftest_mfma, dim3(1), dim3(64), 0, 0, d64, d32);
+  double h64[256];
+  float h32[256];
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(h64, d64, sizeof(h64), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(h32, d32, sizeof(h32), hipMemcpyDeviceToHost);
+  dfree(d64);
+  dfree(d32);
+  if (e != hipSuccess) return TEFMM_ERR_HIP;
+  int bad = 0;
+  for (int m = 0; m < 16; ++m)
+    for (int nn = 0; nn < 16; ++nn) {
+      double ref = 0;
+      for (int kk = 0; kk < 4; ++kk) ref += (1.0 + m + 0.25 * kk) * (2.0 - 0.5 * kk + 0.125 * nn);
+      if (std::abs(h64[m * 16 + nn] - ref) > 1e-12 * std::abs(ref)) bad |= 1;
+      if (std::abs(h32[m * 16 + nn] - ref) > 1e-5 * std::abs(ref)) bad |= 2;
+    }
+  return bad;
+}

@@ -1,0 +1,535 @@
+// HIP kernels of the layered-media Taylor-expansion FMM (gfx950).
+//
+// Notation (Sec. 3.1, Sec. 3.2): a box of side h at centre c carries scaled
+// multipole moments  alpha^_k = sum_j q_j ((r_j - c)/h)^k  and scaled local
+// coefficients beta^_k (the Taylor coefficients of the far field in
+// (r - c)/h).  Multi-indices are stored in the graded order of mi_index().
+#include <hip/hip_runtime.h>
+
+#include "fmm_kernels.hpp"
+#include "kernels.hpp"
+
+namespace tefmm {
+
+__constant__ double c_binom[24][24];
+
+void upload_binomials() {
+  double b[24][24] = {};
+  for (int n = 0; n < 24; ++n) {
+    b[n][0] = 1.0;
+    for (int k = 1; k <= n; ++k) b[n][k] = b[n - 1][k - 1] + (k <= n - 1 ? b[n - 1][k] : 0.0);
+  }
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_binom), b, sizeof(b));
+}
+
+// ---------------------------------------------------------------------------
+// Derivative tables (Sec. 3.3, Eq. derivativeapp with the recurrence of
+// Eq. recurrsion in corrected form).  For f = exp(i k R)/R and
+// psi = exp(i k R), with a_g = D^g f / g!, b_g = D^g psi / g! at a point x
+// (third coordinate possibly complex) and n = |g| >= 1:
+//   n b_g = i k ( sum_i x_i a_{g-e_i} + sum_i a_{g-2e_i} )
+//   n R^2 a_g = i k ( sum_i x_i b_{g-e_i} + sum_i b_{g-2e_i} )
+//               - (2n-1) sum_i x_i a_{g-e_i} - (n-1) sum_i a_{g-2e_i}
+// which follows from  R^2 d_i f + x_i f = i k x_i psi  and  d_i psi = i k x_i f
+// by comparing Taylor coefficients.  Coordinates are in box units (x / h) and
+// k is replaced by k h; the table entry is  G_g = h^{|g|} D^g F = g! a_g / h
+// summed over the key's terms  F = sum coef * f(x, y, zeta)  (zeta -> -zeta
+// direction flips contribute (-1)^{g3}).
+// One 64-lane wave per key.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
+  extern __shared__ double2 lds_tab[];
+  double2* sa = lds_tab;
+  double2* sb = lds_tab + a.nT;
+  const int key = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int t0 = a.term_start[key], t1 = a.term_start[key + 1];
+  constexpr int MAXJ = 28;
+  dc acc[MAXJ];
+#pragma unroll
+  for (int j = 0; j < MAXJ; ++j) acc[j] = {0.0, 0.0};
+  const double kh = a.k * a.h[key];
+  for (int t = t0; t < t1; ++t) {
+    const TableTerm tm = a.terms[t];
+    const dc x1 = {tm.x, 0.0}, x2 = {tm.y, 0.0}, x3 = {tm.zr, tm.zi};
+    const dc R2 = {tm.x * tm.x + tm.y * tm.y + tm.zr * tm.zr - tm.zi * tm.zi, 2.0 * tm.zr * tm.zi};
+    const dc R = csqrt_pr(R2);
+    const dc e = cexp_i(R, kh);
+    const dc invR2 = cdiv({1.0, 0.0}, R2);
+    if (lane == 0) {
+      sa[0] = make_double2(cdiv(e, R).x, cdiv(e, R).y);
+      sb[0] = make_double2(e.x, e.y);
+    }
+    __syncthreads();
+    for (int n = 1; n <= a.order; ++n) {
+      const int off = (n * (n + 1) * (n + 2)) / 6, cnt = ((n + 1) * (n + 2)) / 2;
+      for (int i = lane; i < cnt; i += 64) {
+        const int g = off + i;
+        const short* nb = a.nbr + 6 * g;
+        dc s1a = {0, 0}, s2a = {0, 0}, s1b = {0, 0}, s2b = {0, 0};
+        const dc xs[3] = {x1, x2, x3};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          int i1 = nb[d], i2 = nb[3 + d];
+          if (i1 >= 0) {
+            dc av = {sa[i1].x, sa[i1].y}, bv = {sb[i1].x, sb[i1].y};
+            s1a = cadd(s1a, cmul(xs[d], av));
+            s1b = cadd(s1b, cmul(xs[d], bv));
+          }
+          if (i2 >= 0) {
+            s2a = cadd(s2a, {sa[i2].x, sa[i2].y});
+            s2b = cadd(s2b, {sb[i2].x, sb[i2].y});
+          }
+        }
+        const dc ik = {0.0, kh};
+        dc bn = cscale(cmul(ik, cadd(s1a, s2a)), 1.0 / n);
+        dc num = csub(csub(cmul(ik, cadd(s1b, s2b)), cscale(s1a, 2.0 * n - 1.0)), cscale(s2a, n - 1.0));
+        dc an = cscale(cmul(num, invR2), 1.0 / n);
+        sa[g] = make_double2(an.x, an.y);
+        sb[g] = make_double2(bn.x, bn.y);
+      }
+      __syncthreads();
+    }
+    const dc cf = {tm.cr, tm.ci};
+#pragma unroll
+    for (int j = 0; j < MAXJ; ++j) {
+      const int g = lane + 64 * j;
+      if (g < a.nT) {
+        dc v = cmul(cf, {sa[g].x, sa[g].y});
+        if (tm.flip && (a.g3[g] & 1)) v = {-v.x, -v.y};
+        acc[j] = cadd(acc[j], v);
+      }
+    }
+    __syncthreads();
+  }
+  const double invh = 1.0 / a.h[key];
+#pragma unroll
+  for (int j = 0; j < MAXJ; ++j) {
+    const int g = lane + 64 * j;
+    if (g < a.nT) {
+      const double s = a.fact[g] * invh;
+      a.out[(size_t)key * a.nT + g] = make_double2(acc[j].x * s, acc[j].y * s);
+    }
+  }
+}
+
+// Scaled Taylor coefficients at arbitrary points (introspection): same
+// recurrence, one wave per point, output a_g * (order-independent) 1/h.
+__global__ __launch_bounds__(64) void k_taylor_points(const double* px, const double* py,
+                                                      const double* pz, double k, double h, int order,
+                                                      int nT, const short* nbr, double2* out) {
+  extern __shared__ double2 lds_tp[];
+  double2* sa = lds_tp;
+  double2* sb = lds_tp + nT;
+  const int p = blockIdx.x, lane = threadIdx.x;
+  const double kh = k * h;
+  const dc x1 = {px[p] / h, 0}, x2 = {py[p] / h, 0}, x3 = {pz[2 * p] / h, pz[2 * p + 1] / h};
+  const dc R2 = cadd(cadd(cmul(x1, x1), cmul(x2, x2)), cmul(x3, x3));
+  const dc R = csqrt_pr(R2);
+  const dc e = cexp_i(R, kh);
+  const dc invR2 = cdiv({1.0, 0.0}, R2);
+  if (lane == 0) {
+    dc f = cdiv(e, R);
+    sa[0] = make_double2(f.x, f.y);
+    sb[0] = make_double2(e.x, e.y);
+  }
+  __syncthreads();
+  for (int n = 1; n <= order; ++n) {
+    const int off = (n * (n + 1) * (n + 2)) / 6, cnt = ((n + 1) * (n + 2)) / 2;
+    for (int i = lane; i < cnt; i += 64) {
+      const int g = off + i;
+      const short* nb = nbr + 6 * g;
+      dc s1a = {0, 0}, s2a = {0, 0}, s1b = {0, 0}, s2b = {0, 0};
+      const dc xs[3] = {x1, x2, x3};
+      for (int d = 0; d < 3; ++d) {
+        int i1 = nb[d], i2 = nb[3 + d];
+        if (i1 >= 0) {
+          s1a = cadd(s1a, cmul(xs[d], {sa[i1].x, sa[i1].y}));
+          s1b = cadd(s1b, cmul(xs[d], {sb[i1].x, sb[i1].y}));
+        }
+        if (i2 >= 0) {
+          s2a = cadd(s2a, {sa[i2].x, sa[i2].y});
+          s2b = cadd(s2b, {sb[i2].x, sb[i2].y});
+        }
+      }
+      const dc ik = {0.0, kh};
+      dc bn = cscale(cmul(ik, cadd(s1a, s2a)), 1.0 / n);
+      dc num = csub(csub(cmul(ik, cadd(s1b, s2b)), cscale(s1a, 2.0 * n - 1.0)), cscale(s2a, n - 1.0));
+      dc an = cscale(cmul(num, invR2), 1.0 / n);
+      sa[g] = make_double2(an.x, an.y);
+      sb[g] = make_double2(bn.x, bn.y);
+    }
+    __syncthreads();
+  }
+  for (int g = lane; g < nT; g += 64) out[(size_t)p * nT + g] = make_double2(sa[g].x / h, sa[g].y / h);
+}
+
+// ---------------------------------------------------------------------------
+// MFMA lane layout self test (16x16x4, FP64 and FP32).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_selftest_mfma(double* out64, float* out32) {
+  const int l = threadIdx.x;
+  const int m = l & 15, kk = l >> 4;
+  double a = 1.0 + m + 0.25 * kk, b = 2.0 - 0.5 * kk + 0.125 * m;
+  d4 acc = {0, 0, 0, 0};
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  f4 accf = {0, 0, 0, 0};
+  accf = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, accf, 0, 0, 0);
+  // operands: lane l holds A[l & 15][l >> 4] and B[l >> 4][l & 15]; results differ by precision
+  for (int i = 0; i < 4; ++i) {
+    const int col = l & 15;
+    out64[((l >> 4) + 4 * i) * 16 + col] = acc[i];
+    out32[(4 * (l >> 4) + i) * 16 + col] = accf[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tree construction.
+// ---------------------------------------------------------------------------
+__global__ void k_layer_stats(const double* xyz, int64_t n, int nif, const double* ifz, double eps,
+                              double* part, int* bad) {
+  // per block: for up to 4 layers, min/max of x, y, z and counts
+  __shared__ double smin[4][3][256], smax[4][3][256];
+  __shared__ int scnt[4][256];
+  const int tid = threadIdx.x;
+  for (int l = 0; l < 4; ++l) {
+    for (int c = 0; c < 3; ++c) smin[l][c][tid] = 1e300, smax[l][c][tid] = -1e300;
+    scnt[l][tid] = 0;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + tid; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+    int l = 0;
+    for (int j = 0; j < nif; ++j) {
+      l += (z < ifz[j]);
+      if (fabs(z - ifz[j]) < eps) atomicOr(bad, 1);
+    }
+    if (!(x == x) || !(y == y) || !(z == z)) atomicOr(bad, 2);
+    double v[3] = {x, y, z};
+    for (int c = 0; c < 3; ++c) {
+      smin[l][c][tid] = fmin(smin[l][c][tid], v[c]);
+      smax[l][c][tid] = fmax(smax[l][c][tid], v[c]);
+    }
+    scnt[l][tid] += 1;
+  }
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s)
+      for (int l = 0; l < 4; ++l) {
+        for (int c = 0; c < 3; ++c) {
+          smin[l][c][tid] = fmin(smin[l][c][tid], smin[l][c][tid + s]);
+          smax[l][c][tid] = fmax(smax[l][c][tid], smax[l][c][tid + s]);
+        }
+        scnt[l][tid] += scnt[l][tid + s];
+      }
+    __syncthreads();
+  }
+  if (tid == 0)
+    for (int l = 0; l < 4; ++l) {
+      double* o = part + ((size_t)blockIdx.x * 4 + l) * 7;
+      for (int c = 0; c < 3; ++c) o[c] = smin[l][c][0], o[3 + c] = smax[l][c][0];
+      o[6] = (double)scnt[l][0];
+    }
+}
+
+__global__ void k_leaf_keys(const double* xyz, int64_t n, int nif, const double* ifz, TreeGeom geo,
+                            unsigned* keys, int* perm) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+  int l = 0;
+  for (int j = 0; j < nif; ++j) l += (z < ifz[j]);
+  const int g = geo.group_of_layer[l];
+  const int nb = 1 << geo.depth[g];
+  const double inv = nb / geo.side[g];
+  int ix = (int)floor((x - geo.lo[g][0]) * inv);
+  int iy = (int)floor((y - geo.lo[g][1]) * inv);
+  int iz = (int)floor((z - geo.lo[g][2]) * inv);
+  ix = min(max(ix, 0), nb - 1);
+  iy = min(max(iy, 0), nb - 1);
+  iz = min(max(iz, 0), nb - 1);
+  keys[i] = (unsigned)(geo.leaf_offset[g] + ((int64_t)ix * nb + iy) * nb + iz);
+  perm[i] = (int)i;
+}
+
+__global__ void k_count_keys(const unsigned* keys, int64_t n, int* count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&count[keys[i]], 1);
+}
+
+__global__ void k_gather_pos(const double* xyz, const int* perm, int64_t n, double* xs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int j = perm[i];
+  xs[i] = xyz[j];
+  xs[n + i] = xyz[n + j];
+  xs[2 * n + i] = xyz[2 * n + j];
+}
+
+// ---------------------------------------------------------------------------
+// Charges in, potentials out.
+// ---------------------------------------------------------------------------
+__global__ void k_gather_q(const double2* q, const int* perm, int64_t n, double2* qs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int r = blockIdx.y;
+  if (i < n) qs[(int64_t)r * n + i] = q[(int64_t)r * n + perm[i]];
+}
+
+__global__ void k_finalize(const double2* phi_s, const int* perm, int64_t start, int64_t cnt, int64_t n,
+                           double sr, double si, double2* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int r = blockIdx.y;
+  if (i >= cnt) return;
+  i += start;
+  double2 v = phi_s[(int64_t)r * n + i];
+  out[(int64_t)r * n + perm[i]] = make_double2(v.x * sr - v.y * si, v.x * si + v.y * sr);
+}
+
+// ---------------------------------------------------------------------------
+// P2M (Sec. 3.1, Eq. taylorexpfarxcfree): alpha^_k = sum_j q_j u_j^k,
+// u_j = (r_j - c)/h, one 64-lane block per leaf.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_p2m(PassArgs a) {
+  extern __shared__ double lds_p2m[];
+  const int P1 = a.p + 1;
+  double* pw = lds_p2m;                              // [64][3][P1]
+  double2* sq = (double2*)(lds_p2m + 64 * 3 * P1);   // [64]
+  const int leaf = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int nb = a.nbox_dim;
+  const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
+  const double h = a.h;
+  const double cx = a.lo[0] + (ix + 0.5) * h, cy = a.lo[1] + (iy + 0.5) * h, cz = a.lo[2] + (iz + 0.5) * h;
+  const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
+  const double2* q = a.q + (int64_t)r * a.n;
+  constexpr int MAXK = 5;
+  dc acc[MAXK];
+#pragma unroll
+  for (int j = 0; j < MAXK; ++j) acc[j] = {0, 0};
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const int m = min(64, cnt - c0);
+    if (tid < m) {
+      const int64_t i = start + c0 + tid;
+      const double u[3] = {(a.xs[i] - cx) / h, (a.xs[a.n + i] - cy) / h, (a.xs[2 * a.n + i] - cz) / h};
+      for (int d = 0; d < 3; ++d) {
+        double v = 1.0;
+        for (int e = 0; e < P1; ++e) pw[(tid * 3 + d) * P1 + e] = v, v *= u[d];
+      }
+      sq[tid] = q[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < MAXK; ++j) {
+      const int k = tid + 64 * j;
+      if (k < a.nC) {
+        const int pk = a.mi[k];
+        const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
+        dc s = acc[j];
+        for (int t = 0; t < m; ++t) {
+          const double w = pw[(t * 3 + 0) * P1 + k1] * pw[(t * 3 + 1) * P1 + k2] * pw[(t * 3 + 2) * P1 + k3];
+          s.x += sq[t].x * w;
+          s.y += sq[t].y * w;
+        }
+        acc[j] = s;
+      }
+    }
+    __syncthreads();
+  }
+  double2* out = a.alpha + (int64_t)r * a.rhs_stride + (int64_t)leaf * a.nC;
+#pragma unroll
+  for (int j = 0; j < MAXK; ++j) {
+    const int k = tid + 64 * j;
+    if (k < a.nC) out[k] = make_double2(acc[j].x, acc[j].y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// M2M (Sec. 3.1, Eq. TETartoTETar): parent moments from the 8 children.
+// In parent units the child offset is delta = (c - 1/2)/2 per coordinate and
+//   alpha^P_k = sum_{k' <= k} prod_i C(k_i, k'_i) delta_i^{k_i - k'_i} 2^{-|k'|} alpha^C_{k'}.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_m2m(PassArgs a) {
+  extern __shared__ double2 lds_m2m[];  // [8][nC]
+  const int pb = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int np = a.nbox_dim;  // parent grid size
+  const int nc = 2 * np;
+  const int ix = pb / (np * np), iy = (pb / np) % np, iz = pb % np;
+  const double2* ch = a.alpha_child + (int64_t)r * a.rhs_stride_child;
+  for (int e = tid; e < 8 * a.nC; e += 64) {
+    const int c = e / a.nC, k = e % a.nC;
+    const int cx = (c >> 2) & 1, cy = (c >> 1) & 1, cz = c & 1;
+    const int cb = ((2 * ix + cx) * nc + (2 * iy + cy)) * nc + (2 * iz + cz);
+    lds_m2m[e] = ch[(int64_t)cb * a.nC + k];
+  }
+  __syncthreads();
+  double2* out = a.alpha + (int64_t)r * a.rhs_stride + (int64_t)pb * a.nC;
+  for (int k = tid; k < a.nC; k += 64) {
+    const int pk = a.mi[k];
+    const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
+    dc s = {0, 0};
+    for (int c = 0; c < 8; ++c) {
+      const double dx = ((c >> 2) & 1) ? 0.25 : -0.25, dy = ((c >> 1) & 1) ? 0.25 : -0.25,
+                   dz = (c & 1) ? 0.25 : -0.25;
+      for (int a1 = 0; a1 <= k1; ++a1) {
+        const double f1 = c_binom[k1][a1] * pow(dx, (double)(k1 - a1));
+        for (int a2 = 0; a2 <= k2; ++a2) {
+          const double f2 = f1 * c_binom[k2][a2] * pow(dy, (double)(k2 - a2));
+          for (int a3 = 0; a3 <= k3; ++a3) {
+            const double f = f2 * c_binom[k3][a3] * pow(dz, (double)(k3 - a3)) * ldexp(1.0, -(a1 + a2 + a3));
+            const double2 v = lds_m2m[c * a.nC + mi_index(a1, a2, a3)];
+            s.x += f * v.x;
+            s.y += f * v.y;
+          }
+        }
+      }
+    }
+    out[k] = make_double2(s.x, s.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L2L (Sec. 3.1, Eq. freeletole): child locals from the parent.  In parent
+// units the child centre is at delta = (c - 1/2)/2 and
+//   beta^C_k += 2^{-|k|} sum_{k' >= k} prod_i C(k'_i, k_i) delta_i^{k'_i - k_i} beta^P_{k'}.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_l2l(PassArgs a) {
+  extern __shared__ double2 lds_l2l[];
+  const int cb = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int nc = a.nbox_dim, np = nc / 2;
+  const int ix = cb / (nc * nc), iy = (cb / nc) % nc, iz = cb % nc;
+  const int pb = ((ix >> 1) * np + (iy >> 1)) * np + (iz >> 1);
+  const double2* par = a.beta_parent + (int64_t)r * a.rhs_stride_parent + (int64_t)pb * a.nC;
+  for (int k = tid; k < a.nC; k += 64) lds_l2l[k] = par[k];
+  __syncthreads();
+  const double dx = (ix & 1) ? 0.25 : -0.25, dy = (iy & 1) ? 0.25 : -0.25, dz = (iz & 1) ? 0.25 : -0.25;
+  double2* out = a.beta + (int64_t)r * a.rhs_stride + (int64_t)cb * a.nC;
+  for (int k = tid; k < a.nC; k += 64) {
+    const int pk = a.mi[k];
+    const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
+    dc s = {0, 0};
+    for (int b1 = k1; b1 <= a.p; ++b1) {
+      const double f1 = c_binom[b1][k1] * pow(dx, (double)(b1 - k1));
+      for (int b2 = k2; b1 + b2 <= a.p; ++b2) {
+        const double f2 = f1 * c_binom[b2][k2] * pow(dy, (double)(b2 - k2));
+        for (int b3 = k3; b1 + b2 + b3 <= a.p; ++b3) {
+          const double f = f2 * c_binom[b3][k3] * pow(dz, (double)(b3 - k3));
+          const double2 v = lds_l2l[mi_index(b1, b2, b3)];
+          s.x += f * v.x;
+          s.y += f * v.y;
+        }
+      }
+    }
+    const double sc = ldexp(1.0, -(k1 + k2 + k3));
+    double2 o = out[k];
+    out[k] = make_double2(o.x + sc * s.x, o.y + sc * s.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L2P (Sec. 3.1, Eq. taylorexplocxclfree): phi_i = sum_k beta^_k u_i^k.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_l2p(PassArgs a) {
+  extern __shared__ double lds_l2p[];
+  const int P1 = a.p + 1;
+  double2* sb = (double2*)lds_l2p;              // [nC]
+  double* pw = lds_l2p + 2 * a.nC;               // [64][3][P1]
+  int* smi = (int*)(pw + 64 * 3 * P1);           // [nC]
+  const int leaf = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int nb = a.nbox_dim;
+  const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
+  const double h = a.h;
+  const double cx = a.lo[0] + (ix + 0.5) * h, cy = a.lo[1] + (iy + 0.5) * h, cz = a.lo[2] + (iz + 0.5) * h;
+  const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
+  const double2* bt = a.beta + (int64_t)r * a.rhs_stride + (int64_t)leaf * a.nC;
+  for (int k = tid; k < a.nC; k += 64) sb[k] = bt[k], smi[k] = a.mi[k];
+  __syncthreads();
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    if (c0 + tid < cnt) {
+      const int64_t i = start + c0 + tid;
+      const double u[3] = {(a.xs[i] - cx) / h, (a.xs[a.n + i] - cy) / h, (a.xs[2 * a.n + i] - cz) / h};
+      for (int d = 0; d < 3; ++d) {
+        double v = 1.0;
+        for (int e = 0; e < P1; ++e) pw[(tid * 3 + d) * P1 + e] = v, v *= u[d];
+      }
+      dc s = {0, 0};
+      for (int k = 0; k < a.nC; ++k) {
+        const int pk = smi[k];
+        const double w = pw[(tid * 3 + 0) * P1 + (pk & 255)] * pw[(tid * 3 + 1) * P1 + ((pk >> 8) & 255)] *
+                         pw[(tid * 3 + 2) * P1 + (pk >> 16)];
+        s.x += sb[k].x * w;
+        s.y += sb[k].y * w;
+      }
+      a.phi[(int64_t)r * a.n + i] = make_double2(s.x, s.y);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P2P, free space (Eq. totalinteraction, free part): for every target in a
+// leaf, sum over the 27 neighbour leaves (itself included, j = i excluded) of
+// q_j exp(i k r)/r.  One 64-lane block per target leaf; source chunks staged
+// in LDS.  Adds into phi.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2p(PassArgs a) {
+  __shared__ T sx[64], sy[64], sz[64], sqr[64], sqi[64];
+  __shared__ int sidx[64];
+  const int leaf = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int nb = a.nbox_dim;
+  const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
+  const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
+  const double2* q = a.q + (int64_t)r * a.n;
+  const T k = (T)a.k;
+  for (int c0 = 0; c0 < cnt; c0 += 64) {
+    const bool act = c0 + tid < cnt;
+    const int64_t i = start + c0 + tid;
+    const double txd = act ? a.xs[i] : 0.0, tyd = act ? a.xs[a.n + i] : 0.0, tzd = act ? a.xs[2 * a.n + i] : 0.0;
+    T accr = 0, acci = 0;
+    for (int nbh = 0; nbh < 27; ++nbh) {
+      const int jx = ix + nbh / 9 - 1, jy = iy + (nbh / 3) % 3 - 1, jz = iz + nbh % 3 - 1;
+      if (jx < 0 || jy < 0 || jz < 0 || jx >= nb || jy >= nb || jz >= nb) continue;
+      const int sl = (jx * nb + jy) * nb + jz;
+      const int ss = a.leaf_start[a.leaf_base + sl], sc = a.leaf_count[a.leaf_base + sl];
+      for (int s0 = 0; s0 < sc; s0 += 64) {
+        const int m = min(64, sc - s0);
+        __syncthreads();
+        if (tid < m) {
+          const int64_t j = ss + s0 + tid;
+          // source coordinates relative to the target leaf's corner keep FP32 differences exact-ish
+          sx[tid] = (T)(a.xs[j] - a.lo[0]);
+          sy[tid] = (T)(a.xs[a.n + j] - a.lo[1]);
+          sz[tid] = (T)(a.xs[2 * a.n + j] - a.lo[2]);
+          sqr[tid] = (T)q[j].x;
+          sqi[tid] = (T)q[j].y;
+          sidx[tid] = (int)j;
+        }
+        __syncthreads();
+        if (act) {
+          const T tx = (T)(txd - a.lo[0]), ty = (T)(tyd - a.lo[1]), tz = (T)(tzd - a.lo[2]);
+          for (int t = 0; t < m; ++t) {
+            const T dx = tx - sx[t], dy = ty - sy[t], dz = tz - sz[t];
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            if (sidx[t] == (int)i) continue;
+            const T rr = sqrt(r2);
+            const T inv = (T)1 / rr;
+            T sn, cs;
+            sincos_t(k * rr, &sn, &cs);
+            const T er = cs * inv, ei = sn * inv;
+            accr += sqr[t] * er - sqi[t] * ei;
+            acci += sqr[t] * ei + sqi[t] * er;
+          }
+        }
+      }
+    }
+    if (act) {
+      double2 o = a.phi[(int64_t)r * a.n + i];
+      a.phi[(int64_t)r * a.n + i] = make_double2(o.x + (double)accr, o.y + (double)acci);
+    }
+  }
+}
+
+template __global__ void k_p2p<double>(PassArgs);
+template __global__ void k_p2p<float>(PassArgs);
+
+}  // namespace tefmm

@@ -1,0 +1,104 @@
+// Kernel argument blocks and launch declarations of the TE-FMM kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tefmm {
+
+// One term of a derivative-table key: coef * f(x, y, zeta) in box units,
+// f = exp(i kh R)/R; flip = 1 when the key's variable enters zeta with a minus sign.
+struct TableTerm {
+  double x, y, zr, zi, cr, ci;
+  int flip, pad;
+};
+
+struct TableGenArgs {
+  const TableTerm* terms;
+  const int* term_start;  // [nkeys+1]
+  const double* h;        // [nkeys] box size of each key
+  double k;
+  int order, nT;
+  const short* nbr;       // [nT][6]: g - e_x, g - e_y, g - e_z, g - 2e_x, g - 2e_y, g - 2e_z (-1 if none)
+  const unsigned char* g3;  // [nT] third component of g
+  const double* fact;     // [nT] g!
+  double2* out;           // [nkeys][nT]
+};
+
+struct TreeGeom {
+  int group_of_layer[4];
+  int depth[4];
+  double lo[4][3];
+  double side[4];
+  int64_t leaf_offset[4];
+};
+
+// Arguments shared by the per-box passes (P2M, M2M, L2L, L2P, P2P).
+struct PassArgs {
+  int p, nC;
+  int nbox_dim;        // boxes per dimension at this level
+  double h;            // box size at this level
+  double lo[3];        // root-cube corner
+  double k;            // wave number of the group's layer
+  int64_t n;           // total particles (sorted arrays' length)
+  const double* xs;    // sorted positions SoA [3][n]
+  const double2* q;    // sorted charges [rhs][n]
+  double2* phi;        // sorted potentials [rhs][n]
+  const int* leaf_start;
+  const int* leaf_count;
+  int64_t leaf_base;   // offset of this group's leaves in leaf_start/count
+  const int* mi;       // packed multi-indices k1 | k2<<8 | k3<<16, graded order
+  double2* alpha;      // this level [rhs][box][nC]
+  double2* beta;
+  int64_t rhs_stride;  // per-rhs stride of alpha/beta at this level (elements)
+  const double2* alpha_child;
+  int64_t rhs_stride_child;
+  const double2* beta_parent;
+  int64_t rhs_stride_parent;
+};
+
+struct M2LArgs {
+  int n;                 // boxes per dimension
+  int nC, nCs, nKB, nRB;  // coefficients, LDS row stride, K blocks of 4, row blocks of 16
+  int leaf;              // leaf level: neighbour offsets take part
+  int tiles_x, ntiles;
+  const double2* alpha;  // [rhs][box][nC]
+  double2* beta;
+  int64_t rhs_stride;
+  const double2* Tfd;    // [343][nT] free + Delta (|d|>=2) and Delta-only (|d|<=1) or null
+  const double2* TS;     // [49 (2n-1)][nT] Sigma family or null
+  const float2* Tfd32;   // FP32 copies (mixed precision)
+  const float2* TS32;
+  int nT;
+  int near_fd, near_s;
+  const int* mi;
+  const double* scale;   // (-1)^{|k|}/k!
+  const double* invfact; // 1/k!
+};
+
+void upload_binomials();
+
+__global__ void k_table_gen(TableGenArgs a);
+__global__ void k_taylor_points(const double* px, const double* py, const double* pz, double k, double h,
+                                int order, int nT, const short* nbr, double2* out);
+__global__ void k_selftest_mfma(double* out64, float* out32);
+__global__ void k_layer_stats(const double* xyz, int64_t n, int nif, const double* ifz, double eps,
+                              double* part, int* bad);
+__global__ void k_leaf_keys(const double* xyz, int64_t n, int nif, const double* ifz, TreeGeom geo,
+                            unsigned* keys, int* perm);
+__global__ void k_count_keys(const unsigned* keys, int64_t n, int* count);
+__global__ void k_gather_pos(const double* xyz, const int* perm, int64_t n, double* xs);
+__global__ void k_gather_q(const double2* q, const int* perm, int64_t n, double2* qs);
+__global__ void k_finalize(const double2* phi_s, const int* perm, int64_t start, int64_t cnt, int64_t n,
+                           double sr, double si, double2* out);
+__global__ void k_p2m(PassArgs a);
+__global__ void k_m2m(PassArgs a);
+__global__ void k_l2l(PassArgs a);
+__global__ void k_l2p(PassArgs a);
+template <typename T>
+__global__ void k_p2p(PassArgs a);
+
+// M2L launcher (picks the row-block instantiation for nRB).
+hipError_t launch_m2l(const M2LArgs& a, int nrhs, bool fp32, hipStream_t s);
+
+}  // namespace tefmm

@@ -1,0 +1,76 @@
+"""Write the oracle's expected potentials for the parity tests.
+
+Calls only oracle/ (and the seeded input generators).  Usage:
+    python tests/golden/make_expected.py [case ...]
+Cases: c1 (N=1000, all targets), c2s (N=200,000, 64 sampled targets),
+c4s (N=1,000,000, 16 sampled targets), n20k (N=20,000, 128 sampled targets).
+Output: tests/golden/expected_<case>.txt with columns  index  re  im.
+"""
+from __future__ import annotations
+
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle.medium import Medium  # noqa: E402
+from oracle import direct  # noqa: E402
+from paper_1902_05875_amd import inputs  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def case_spec(name):
+    """(workload name, N, targets) of a parity case."""
+    if name == "c1":
+        xyz, q = inputs.workload("c1")
+        return xyz, q, np.arange(xyz.shape[0])
+    if name == "c2s":
+        xyz, q = inputs.workload("c2")
+        return xyz, q, inputs.sample_targets(xyz, 48, 16, seed=102)
+    if name == "c4s":
+        xyz, q = inputs.workload("c4")
+        return xyz, q, inputs.sample_targets(xyz, 12, 4, seed=104)
+    if name == "n20k":
+        xyz, q = inputs.workload("c2", n=20_000)
+        return xyz, q, inputs.sample_targets(xyz, 96, 32, seed=120)
+    raise ValueError(name)
+
+
+_G = {}
+
+
+def _work(chunk):
+    med = Medium(inputs.MEDIUM_K, inputs.MEDIUM_D)
+    xyz, q = _G["xyz"], _G["q"]
+    return direct.potential(med, xyz, q, chunk)
+
+
+def _init(name):
+    xyz, q, _ = case_spec(name)
+    _G["xyz"], _G["q"] = xyz, q
+
+
+def run(name, procs=None):
+    xyz, q, targets = case_spec(name)
+    procs = procs or min(8, os.cpu_count() or 1)
+    chunks = np.array_split(targets, max(1, min(len(targets), procs * 4)))
+    t0 = time.time()
+    with mp.get_context("fork").Pool(procs, initializer=_init, initargs=(name,)) as pool:
+        parts = pool.map(_work, chunks)
+    phi = np.concatenate(parts)
+    out = os.path.join(HERE, f"expected_{name}.txt")
+    np.savetxt(out, np.column_stack([targets, phi.real, phi.imag]), fmt=["%d", "%.17e", "%.17e"],
+               header=f"oracle direct sum (oracle/direct.py), case {name}, N={xyz.shape[0]}; "
+                      f"columns: target index, Re phi, Im phi (physical normalisation)")
+    print(f"{name}: {len(targets)} targets in {time.time() - t0:.1f} s -> {out}", flush=True)
+
+
+if __name__ == "__main__":
+    for c in (sys.argv[1:] or ["c1", "n20k", "c2s", "c4s"]):
+        run(c)

@@ -1,0 +1,121 @@
+"""libtefmm.so on the CPU: exported symbols and the host-side FP64 steps
+(densities, complex-image fits) against the oracle."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = os.path.join(ROOT, "tests", "golden", "table_3_1_3_2.txt")
+
+
+def _api():
+    from paper_1902_05875_amd import api
+    api.lib()
+    return api
+
+
+def test_exports_every_declared_symbol():
+    api = _api()
+    hdr = open(os.path.join(ROOT, "include", "tefmm.h")).read()
+    declared = set(re.findall(r"\b(tefmm_[a-z_0-9]+)\s*\(", hdr))
+    assert declared == set(api.EXPORTS)
+    for name in declared:
+        assert hasattr(api.lib(), name), name
+
+
+def test_densities_match_oracle():
+    from oracle.medium import Medium, densities
+    api = _api()
+    k, d = (0.8, 1.5, 2.0), (0.0, -1.2)
+    kr = np.array([0.3, 1.2 + 0.1j, 2.5 - 0.5j, 4.0 - 1.0j, 9.0])
+    for lp in range(3):
+        got = api.densities(k, d, lp, kr)
+        ref = densities(Medium(k, d), lp, kr)
+        for (m, a, b), v in ref.items():
+            ab = {"uu": 0, "ud": 1, "du": 2, "dd": 3}[a + b]
+            np.testing.assert_allclose(got[m, ab], v, rtol=1e-13, atol=1e-15)
+
+
+def test_invalid_medium_rejected():
+    api = _api()
+    with pytest.raises(api.TefmmError):
+        api.densities((0.8, 1.5, 2.0), (0.0, 0.5), 0, [0.5])
+    with pytest.raises(api.TefmmError):
+        api.densities((0.8, -1.5), (0.0,), 0, [0.5])
+
+
+def _family_kernel(A, Z, k, rho, Zv):
+    zeta = Zv - Z
+    R = np.sqrt(rho ** 2 + zeta ** 2 + 0j)
+    R = np.where(R.real < 0, -R, R)
+    return np.sum(A * np.exp(1j * k * R) / (4 * np.pi * R))
+
+
+@pytest.mark.parametrize("family", [0, 1, 2])
+def test_dcim_family_vs_quadrature(family):
+    """Complex images of each same-layer family reproduce the Sommerfeld integral of its
+    density (Sec. 3.3) at random points of the particle range to 1e-7 relative."""
+    from oracle import sommerfeld as S
+    from oracle.medium import Medium, densities, kz
+    api = _api()
+    k, d = (0.8, 1.5, 2.0), (0.0, -1.2)
+    zlo, zhi = -1.1, -0.1
+    A, Z, fe = api.dcim_family(k, d, 1, family, zlo, zhi)
+    assert 5 <= len(A) <= 60
+    med = Medium(k, d)
+    rng = np.random.default_rng(11)
+    key = {0: (1, "u", "u"), 1: (1, "d", "d"), 2: (1, "u", "d")}[family]
+    for _ in range(8):
+        z, zp = rng.uniform(zlo, zhi, 2)
+        rho = rng.uniform(0, 1.4)
+        Zv = {0: z + zp - 2 * d[1], 1: 2 * d[0] - z - zp, 2: 1.2 + (z - zp)}[family]
+        nodes, w, _ = S.contour(2.0, S.tail_length(Zv, 0, 2.0))
+        sig = densities(med, 1, nodes)[key]
+        k1 = kz(1.5, nodes)
+        ref = 1j / (4 * np.pi) * np.sum(w * nodes * S.bessel_j(0, nodes * rho) / k1 * sig * np.exp(1j * k1 * Zv))
+        got = _family_kernel(A, Z, 1.5, rho, Zv)
+        assert abs(got - ref) <= 1e-7 * abs(ref), (rho, z, zp, got, ref)
+
+
+def test_dcim_reproduces_table_3_columns():
+    """Sec. 3.3, Tables 3.1/3.2: the library's images (Sigma-up + Delta '+' part = u^up_11),
+    differentiated exactly, agree with the printed quadrature values at least as well as the
+    printed DCIM values do (within a factor 20 of the printed DCIM error, or 1e-8 relative)."""
+    from oracle.taylor import coefficients
+    api = _api()
+    k, d = (0.8, 1.5, 2.0), (0.0, -2.0)
+    k1, D = 1.5, 2.0
+    rows = np.loadtxt(GOLD)
+    pairs = {1: ((0.5, 1.0, -0.5), (0.3, 1.3, -0.5)), 2: ((0.6, 0.3, -1.2), (0.5, 1.0, -0.5))}
+    # the paper fits with z_min = -1.5 (Fig. 3.2); the particle range here is [-1.5, -0.5]
+    Au, Zu, _ = api.dcim_family(k, d, 1, 0, -1.5, -0.5)
+    Ad, Zd, _ = api.dcim_family(k, d, 1, 2, -1.5, -0.5)
+    for row in rows:
+        p, k3, k3p, s = map(int, row[:4])
+        quad = row[4] + 1j * row[5]
+        dcim_paper = row[6] + 1j * row[7]
+        r, rp = pairs[p]
+        dx, dy = r[0] - rp[0], r[1] - rp[1]
+        n = s + k3 + k3p
+        tot = 0
+        # Sigma-up: zeta = (z + z') - 2 d_1 - depth, d/dz = d/dz' = d/dzeta
+        # Delta '+': zeta = D + (z - z') - depth, d/dz = d/dzeta, d/dz' = -d/dzeta
+        for A, Z, Zfun, sgn in ((Au, Zu, r[2] + rp[2] - 2 * d[1], 1), (Ad, Zd, D + r[2] - rp[2], -1)):
+            for Aj, Zj in zip(A, Z):
+                c = coefficients(dx, dy, Zfun - Zj, k1, n)
+                # (dx + i dy)^s d_zeta^(k3+k3') of f, divided by s! k3! k3'!
+                acc = 0
+                for m in range(s + 1):
+                    a, b = s - m, m
+                    acc += math.comb(s, m) * (1j) ** m * c[a, b, k3 + k3p] * (
+                        math.factorial(a) * math.factorial(b) * math.factorial(k3 + k3p))
+                acc *= sgn ** k3p / (math.factorial(s) * math.factorial(k3) * math.factorial(k3p))
+                tot += Aj * acc
+        # G = sum_j A_j f(R_j) / (4 pi) physically; the paper's u = G / (i k_1 / 4 pi)
+        got = tot / (1j * k1)
+        err = abs(got - quad)
+        bound = max(20 * abs(dcim_paper - quad), 1e-8 * abs(quad))
+        assert err <= bound, (row[:4], got, quad, err, abs(dcim_paper - quad))
