@@ -96,9 +96,11 @@ typedef struct {
  * interface_eps 1e-9, n_rhs_max 64). */
 void tefmm_default_options(tefmm_options* opt);
 
-/* Create a handle for a medium (host FP64 work only: validation).
+/* Create a handle for a medium: validates the medium and options and uploads
+ * the small index tables of order p to the current HIP device.
  * Returns TEFMM_ERR_INVALID_ARG for non-decreasing interfaces, k <= 0,
- * p outside [1, 12] or more than 4 layers.  Pure host call. */
+ * p outside [1, 16] or more than 4 layers, TEFMM_ERR_HIP if the device
+ * tables cannot be allocated. */
 int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefmm_options* opt);
 
 /* Set the particle geometry.  xyz_soa: 3*n doubles, x[0..n) then y then z,

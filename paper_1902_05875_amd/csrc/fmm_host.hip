@@ -39,7 +39,8 @@ struct Group {
   std::vector<cplx> famA[3], famZ[3];
   double fam_err[3] = {0, 0, 0};
   bool has[3] = {false, false, false};
-  std::vector<double2*> alpha, beta;  // by level
+  std::vector<double2*> alpha, beta;  // by level, full Taylor sets [rhs][box][nC]
+  std::vector<double2*> ared, bred;   // by level, Helmholtz-reduced sets [rhs][box][nR]
   std::vector<double2*> Tfd, TS;
   std::vector<float2*> Tfd32, TS32;
   std::vector<int64_t> nbox;          // boxes at level
@@ -57,10 +58,12 @@ struct tefmm_ctx {
   MediumDesc med;
   tefmm_options opt;
   std::string err;
-  int nC = 0, nT = 0, nKB = 0, nRB = 0, nCs = 0;
+  int nC = 0, nR = 0, nG = 0, nKB = 0, nRB = 0, nRs = 0;
   // constant tables
-  int* d_mi = nullptr;
-  short* d_nbr = nullptr;
+  int* d_mi = nullptr;      // [nC] graded multi-indices (packed)
+  int* d_rmi = nullptr;     // [nR] reduced multi-indices (packed)
+  int* d_rfull = nullptr;   // [nR] graded index of each reduced entry
+  short* d_nbr = nullptr;   // [nG][6] compact-table recurrence neighbours
   unsigned char* d_g3 = nullptr;
   double *d_fact = nullptr, *d_scale = nullptr, *d_invfact = nullptr;
   // geometry
@@ -100,6 +103,8 @@ static void free_geometry(tefmm_t h) {
   for (auto& g : h->groups) {
     for (auto& p : g.alpha) dfree(p);
     for (auto& p : g.beta) dfree(p);
+    for (auto& p : g.ared) dfree(p);
+    for (auto& p : g.bred) dfree(p);
     for (auto& p : g.Tfd) dfree(p);
     for (auto& p : g.TS) dfree(p);
     for (auto& p : g.Tfd32) dfree(p);
@@ -115,50 +120,71 @@ static void free_geometry(tefmm_t h) {
 static int build_constant_tables(tefmm_t h) {
   const int p = h->opt.p;
   h->nC = mi_count(p);
-  h->nT = mi_count(2 * p);
-  h->nKB = (h->nC + 3) / 4;
-  h->nRB = (h->nC + 15) / 16;
-  int cs = 4 * h->nKB;
-  while (cs % 16 != 1) ++cs;
-  h->nCs = cs;
-  const int nT = h->nT, nC = h->nC;
-  std::vector<int> mi(nT);
-  std::vector<short> nbr(6 * nT, -1);
-  std::vector<unsigned char> g3(nT);
-  std::vector<double> fact(nT), scale(nC), invfact(nC);
+  h->nR = (p + 1) * (p + 1);
+  h->nG = g_count(2 * p);
+  h->nKB = (h->nR + 3) / 4;
+  h->nRB = (h->nR + 15) / 16;
+  int rs = 4 * h->nKB;
+  while (rs % 16 != 1) ++rs;
+  h->nRs = rs;
+  const int nC = h->nC, nR = h->nR, nG = h->nG;
   auto f = [](int n) {
     double r = 1;
     for (int i = 2; i <= n; ++i) r *= i;
     return r;
   };
-  for (int m = 0; m <= 2 * p; ++m)
+  std::vector<int> mi(nC), rmi, rfull;
+  std::vector<double> scale(nC), invfact(nC);
+  for (int m = 0; m <= p; ++m)
     for (int a = m; a >= 0; --a)
       for (int b = m - a; b >= 0; --b) {
         const int c = m - a - b, i = mi_index(a, b, c);
         mi[i] = a | (b << 8) | (c << 16);
-        g3[i] = (unsigned char)c;
-        fact[i] = f(a) * f(b) * f(c);
-        if (a >= 1) nbr[6 * i + 0] = (short)mi_index(a - 1, b, c);
-        if (b >= 1) nbr[6 * i + 1] = (short)mi_index(a, b - 1, c);
-        if (c >= 1) nbr[6 * i + 2] = (short)mi_index(a, b, c - 1);
-        if (a >= 2) nbr[6 * i + 3] = (short)mi_index(a - 2, b, c);
-        if (b >= 2) nbr[6 * i + 4] = (short)mi_index(a, b - 2, c);
-        if (c >= 2) nbr[6 * i + 5] = (short)mi_index(a, b, c - 2);
-        if (m <= p) {
-          scale[i] = ((m & 1) ? -1.0 : 1.0) / fact[i];
-          invfact[i] = 1.0 / fact[i];
-        }
+        const double fa = f(a) * f(b) * f(c);
+        scale[i] = ((m & 1) ? -1.0 : 1.0) / fa;
+        invfact[i] = 1.0 / fa;
       }
-  HIPCHK(h, hipMalloc(&h->d_mi, sizeof(int) * nT));
-  HIPCHK(h, hipMalloc(&h->d_nbr, sizeof(short) * 6 * nT));
-  HIPCHK(h, hipMalloc(&h->d_g3, nT));
-  HIPCHK(h, hipMalloc(&h->d_fact, sizeof(double) * nT));
+  for (int k1 = 0; k1 <= std::min(1, p); ++k1)
+    for (int t = 0; t <= p - k1; ++t)
+      for (int k3 = 0; k3 <= t; ++k3) {
+        const int k2 = t - k3;
+        rmi.push_back(k1 | (k2 << 8) | (k3 << 16));
+        rfull.push_back(mi_index(k1, k2, k3));
+      }
+  if ((int)rmi.size() != nR) return fail(h, TEFMM_ERR_STATE, "reduced index set size");
+  std::vector<short> nbr(6 * nG, -1);
+  std::vector<unsigned char> g3(nG);
+  std::vector<double> fact(nG);
+  int cnt = 0;
+  for (int n = 0; n <= 2 * p; ++n)
+    for (int g1 = 0; g1 <= std::min(2, n); ++g1)
+      for (int c = 0; c <= n - g1; ++c) {
+        const int b = n - g1 - c, i = g_index(g1, b, c);
+        if (i != cnt++) return fail(h, TEFMM_ERR_STATE, "compact table order");
+        g3[i] = (unsigned char)c;
+        fact[i] = f(g1) * f(b) * f(c);
+        if (g1 >= 1) nbr[6 * i + 0] = (short)g_index(g1 - 1, b, c);
+        if (b >= 1) nbr[6 * i + 1] = (short)g_index(g1, b - 1, c);
+        if (c >= 1) nbr[6 * i + 2] = (short)g_index(g1, b, c - 1);
+        if (g1 >= 2) nbr[6 * i + 3] = (short)g_index(g1 - 2, b, c);
+        if (b >= 2) nbr[6 * i + 4] = (short)g_index(g1, b - 2, c);
+        if (c >= 2) nbr[6 * i + 5] = (short)g_index(g1, b, c - 2);
+      }
+  if (cnt != nG) return fail(h, TEFMM_ERR_STATE, "compact table size");
+  HIPCHK(h, hipMalloc(&h->d_mi, sizeof(int) * nC));
+  HIPCHK(h, hipMalloc(&h->d_rmi, sizeof(int) * nR));
+  HIPCHK(h, hipMalloc(&h->d_rfull, sizeof(int) * nR));
+  HIPCHK(h, hipMalloc(&h->d_nbr, sizeof(short) * 6 * nG));
+  HIPCHK(h, hipMalloc(&h->d_g3, nG));
+  HIPCHK(h, hipMalloc(&h->d_fact, sizeof(double) * nG));
   HIPCHK(h, hipMalloc(&h->d_scale, sizeof(double) * nC));
   HIPCHK(h, hipMalloc(&h->d_invfact, sizeof(double) * nC));
-  HIPCHK(h, hipMemcpy(h->d_mi, mi.data(), sizeof(int) * nT, hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->d_nbr, nbr.data(), sizeof(short) * 6 * nT, hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->d_g3, g3.data(), nT, hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->d_fact, fact.data(), sizeof(double) * nT, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_mi, mi.data(), sizeof(int) * nC, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_rmi, rmi.data(), sizeof(int) * nR, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_rfull, rfull.data(), sizeof(int) * nR, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_nbr, nbr.data(), sizeof(short) * 6 * nG, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_g3, g3.data(), nG, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->d_fact, fact.data(), sizeof(double) * nG, hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->d_scale, scale.data(), sizeof(double) * nC, hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->d_invfact, invfact.data(), sizeof(double) * nC, hipMemcpyHostToDevice));
   upload_binomials();
@@ -179,7 +205,7 @@ extern "C" int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefm
   else
     tefmm_default_options(&h->opt);
   const tefmm_options& o = h->opt;
-  if (o.p < 1 || o.p > 10 || o.depth < 0 || o.depth > 7 || o.max_leaf < 1 ||
+  if (o.p < 1 || o.p > 16 || o.depth < 0 || o.depth > 7 || o.max_leaf < 1 ||
       (o.precision != TEFMM_FP64 && o.precision != TEFMM_MIXED_FP32) ||
       (o.normalization != TEFMM_NORM_PHYSICAL && o.normalization != TEFMM_NORM_PAPER) || o.dcim_samples < 8 ||
       !(o.dcim_T1 > 0) || !(o.dcim_svd_tol > 0) || !(o.interface_eps >= 0) || o.n_rhs_max < 1) {
@@ -200,6 +226,8 @@ extern "C" void tefmm_destroy(tefmm_t h) {
   if (!h) return;
   free_geometry(h);
   dfree(h->d_mi);
+  dfree(h->d_rmi);
+  dfree(h->d_rfull);
   dfree(h->d_nbr);
   dfree(h->d_g3);
   dfree(h->d_fact);
@@ -287,15 +315,15 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
       HIPCHK(h, hipMalloc(&d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
       HIPCHK(h, hipMalloc(&d_start, sizeof(int) * start.size()));
       HIPCHK(h, hipMalloc(&d_h, sizeof(double) * hk.size()));
-      HIPCHK(h, hipMalloc(&d_out, sizeof(double2) * (size_t)nkeys * h->nT));
+      HIPCHK(h, hipMalloc(&d_out, sizeof(double2) * (size_t)nkeys * h->nG));
       if (!terms.empty())
         HIPCHK(h, hipMemcpyAsync(d_terms, terms.data(), sizeof(TableTerm) * terms.size(), hipMemcpyHostToDevice, s));
       HIPCHK(h, hipMemcpyAsync(d_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, s));
       HIPCHK(h, hipMemcpyAsync(d_h, hk.data(), sizeof(double) * hk.size(), hipMemcpyHostToDevice, s));
       TableGenArgs ta;
-      ta.terms = d_terms, ta.term_start = d_start, ta.h = d_h, ta.k = k, ta.order = 2 * h->opt.p, ta.nT = h->nT;
+      ta.terms = d_terms, ta.term_start = d_start, ta.h = d_h, ta.k = k, ta.order = 2 * h->opt.p, ta.nG = h->nG;
       ta.nbr = h->d_nbr, ta.g3 = h->d_g3, ta.fact = h->d_fact, ta.out = d_out;
-      const size_t lds = 2 * sizeof(double2) * h->nT;
+      const size_t lds = 2 * sizeof(double2) * h->nG;
       HIPCHK(h, hipFuncSetAttribute((const void*)k_table_gen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
       hipLaunchKernelGGL(k_table_gen, dim3(nkeys), dim3(64), lds, s, ta);
       HIPCHK(h, hipGetLastError());
@@ -308,7 +336,7 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
       else
         g.TS[lev] = d_out;
       if (h->opt.precision == TEFMM_MIXED_FP32) {
-        const size_t cnt = (size_t)nkeys * h->nT;
+        const size_t cnt = (size_t)nkeys * h->nG;
         std::vector<double2> hd(cnt);
         std::vector<float2> hf(cnt);
         HIPCHK(h, hipMemcpy(hd.data(), d_out, sizeof(double2) * cnt, hipMemcpyDeviceToHost));
@@ -563,18 +591,24 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
   for (auto& g : h->groups) {
     for (auto& p : g.alpha) dfree(p);
     for (auto& p : g.beta) dfree(p);
+    for (auto& p : g.ared) dfree(p);
+    for (auto& p : g.bred) dfree(p);
   }
   HIPCHK(h, hipMalloc(&h->d_q, sizeof(double2) * h->n * nrhs));
   HIPCHK(h, hipMalloc(&h->d_phi, sizeof(double2) * h->n * nrhs));
   for (auto& g : h->groups) {
     g.alpha.assign(g.depth + 1, nullptr);
     g.beta.assign(g.depth + 1, nullptr);
+    g.ared.assign(g.depth + 1, nullptr);
+    g.bred.assign(g.depth + 1, nullptr);
     g.nbox.assign(g.depth + 1, 0);
     for (int lev = 2; lev <= g.depth; ++lev) {
       const int64_t nbx = (int64_t)1 << (3 * lev);
       g.nbox[lev] = nbx;
       HIPCHK(h, hipMalloc(&g.alpha[lev], sizeof(double2) * nbx * h->nC * nrhs));
       HIPCHK(h, hipMalloc(&g.beta[lev], sizeof(double2) * nbx * h->nC * nrhs));
+      HIPCHK(h, hipMalloc(&g.ared[lev], sizeof(double2) * nbx * h->nR * nrhs));
+      HIPCHK(h, hipMalloc(&g.bred[lev], sizeof(double2) * nbx * h->nR * nrhs));
     }
   }
   h->nrhs_alloc = nrhs;
@@ -623,27 +657,46 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
       hipLaunchKernelGGL(k_m2m, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), lds, s, a);
       HIPCHK(h, hipGetLastError());
     }
+    // Helmholtz-reduced moments per level
+    for (int lev = 2; lev <= H; ++lev) {
+      ReduceArgs ra;
+      const double hl = g.side / (1 << lev), kh = h->med.k[g.layer] * hl;
+      ra.p = p, ra.nC = h->nC, ra.nR = h->nR, ra.kh2 = kh * kh, ra.mi = h->d_mi, ra.rfull = h->d_rfull;
+      ra.scale = h->d_scale, ra.invfact = h->d_invfact, ra.in = g.alpha[lev], ra.out = g.ared[lev];
+      ra.in_stride = g.nbox[lev] * h->nC, ra.out_stride = g.nbox[lev] * h->nR;
+      hipLaunchKernelGGL(k_reduce, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, ra);
+      HIPCHK(h, hipGetLastError());
+    }
     HIPCHK(h, hipEventRecord(h->ev[2], s));
     for (int lev = 2; lev <= H; ++lev) {
       M2LArgs m;
       std::memset(&m, 0, sizeof(m));
       const int nb = 1 << lev;
-      m.n = nb, m.nC = h->nC, m.nCs = h->nCs, m.nKB = h->nKB, m.nRB = h->nRB, m.leaf = lev == H;
+      m.n = nb, m.nR = h->nR, m.nRs = h->nRs, m.nKB = h->nKB, m.nRB = h->nRB, m.leaf = lev == H;
       m.tiles_x = ((nb / 2) + 3) / 4;
       m.ntiles = nb * 4 * m.tiles_x * m.tiles_x;
-      m.alpha = g.alpha[lev], m.beta = g.beta[lev], m.rhs_stride = g.nbox[lev] * h->nC;
-      m.Tfd = g.Tfd[lev], m.TS = g.TS[lev], m.Tfd32 = g.Tfd32[lev], m.TS32 = g.TS32[lev], m.nT = h->nT;
+      m.a = g.ared[lev], m.b = g.bred[lev], m.rhs_stride = g.nbox[lev] * h->nR;
+      m.Tfd = g.Tfd[lev], m.TS = g.TS[lev], m.Tfd32 = g.Tfd32[lev], m.TS32 = g.TS32[lev], m.nG = h->nG;
       m.near_fd = g.has[2], m.near_s = g.has[0] || g.has[1];
-      m.mi = h->d_mi, m.scale = h->d_scale, m.invfact = h->d_invfact;
+      m.rmi = h->d_rmi;
       HIPCHK(h, launch_m2l(m, nrhs, fp32, s));
     }
     HIPCHK(h, hipEventRecord(h->ev[3], s));
-    for (int lev = 3; lev <= H; ++lev) {
-      PassArgs a = pa;
-      a.nbox_dim = 1 << lev, a.beta = g.beta[lev], a.rhs_stride = g.nbox[lev] * h->nC;
-      a.beta_parent = g.beta[lev - 1], a.rhs_stride_parent = g.nbox[lev - 1] * h->nC;
-      hipLaunchKernelGGL(k_l2l, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, a);
+    for (int lev = 2; lev <= H; ++lev) {
+      ReduceArgs ra;
+      const double hl = g.side / (1 << lev), kh = h->med.k[g.layer] * hl;
+      ra.p = p, ra.nC = h->nC, ra.nR = h->nR, ra.kh2 = kh * kh, ra.mi = h->d_mi, ra.rfull = h->d_rfull;
+      ra.scale = h->d_scale, ra.invfact = h->d_invfact, ra.in = g.bred[lev], ra.out = g.beta[lev];
+      ra.in_stride = g.nbox[lev] * h->nR, ra.out_stride = g.nbox[lev] * h->nC;
+      hipLaunchKernelGGL(k_expand, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, ra);
       HIPCHK(h, hipGetLastError());
+      if (lev >= 3) {
+        PassArgs a = pa;
+        a.nbox_dim = 1 << lev, a.beta = g.beta[lev], a.rhs_stride = g.nbox[lev] * h->nC;
+        a.beta_parent = g.beta[lev - 1], a.rhs_stride_parent = g.nbox[lev - 1] * h->nC;
+        hipLaunchKernelGGL(k_l2l, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, a);
+        HIPCHK(h, hipGetLastError());
+      }
     }
     HIPCHK(h, hipEventRecord(h->ev[4], s));
     {

@@ -38,13 +38,15 @@ void upload_binomials() {
 // One 64-lane wave per key.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
+  // Only entries with g1 <= 2 are generated (compact order of g_index); the
+  // recurrence for such g needs g - e_i and g - 2 e_i, which stay in that set.
   extern __shared__ double2 lds_tab[];
   double2* sa = lds_tab;
-  double2* sb = lds_tab + a.nT;
+  double2* sb = lds_tab + a.nG;
   const int key = blockIdx.x;
   const int lane = threadIdx.x;
   const int t0 = a.term_start[key], t1 = a.term_start[key + 1];
-  constexpr int MAXJ = 28;
+  constexpr int MAXJ = 25;  // nG <= 1600 (order <= 32)
   dc acc[MAXJ];
 #pragma unroll
   for (int j = 0; j < MAXJ; ++j) acc[j] = {0.0, 0.0};
@@ -57,12 +59,13 @@ __global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
     const dc e = cexp_i(R, kh);
     const dc invR2 = cdiv({1.0, 0.0}, R2);
     if (lane == 0) {
-      sa[0] = make_double2(cdiv(e, R).x, cdiv(e, R).y);
+      const dc f = cdiv(e, R);
+      sa[0] = make_double2(f.x, f.y);
       sb[0] = make_double2(e.x, e.y);
     }
     __syncthreads();
     for (int n = 1; n <= a.order; ++n) {
-      const int off = (n * (n + 1) * (n + 2)) / 6, cnt = ((n + 1) * (n + 2)) / 2;
+      const int off = g_offset(n), cnt = g_offset(n + 1) - off;
       for (int i = lane; i < cnt; i += 64) {
         const int g = off + i;
         const short* nb = a.nbr + 6 * g;
@@ -70,9 +73,9 @@ __global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
         const dc xs[3] = {x1, x2, x3};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          int i1 = nb[d], i2 = nb[3 + d];
+          const int i1 = nb[d], i2 = nb[3 + d];
           if (i1 >= 0) {
-            dc av = {sa[i1].x, sa[i1].y}, bv = {sb[i1].x, sb[i1].y};
+            const dc av = {sa[i1].x, sa[i1].y}, bv = {sb[i1].x, sb[i1].y};
             s1a = cadd(s1a, cmul(xs[d], av));
             s1b = cadd(s1b, cmul(xs[d], bv));
           }
@@ -82,9 +85,9 @@ __global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
           }
         }
         const dc ik = {0.0, kh};
-        dc bn = cscale(cmul(ik, cadd(s1a, s2a)), 1.0 / n);
-        dc num = csub(csub(cmul(ik, cadd(s1b, s2b)), cscale(s1a, 2.0 * n - 1.0)), cscale(s2a, n - 1.0));
-        dc an = cscale(cmul(num, invR2), 1.0 / n);
+        const dc bn = cscale(cmul(ik, cadd(s1a, s2a)), 1.0 / n);
+        const dc num = csub(csub(cmul(ik, cadd(s1b, s2b)), cscale(s1a, 2.0 * n - 1.0)), cscale(s2a, n - 1.0));
+        const dc an = cscale(cmul(num, invR2), 1.0 / n);
         sa[g] = make_double2(an.x, an.y);
         sb[g] = make_double2(bn.x, bn.y);
       }
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
 #pragma unroll
     for (int j = 0; j < MAXJ; ++j) {
       const int g = lane + 64 * j;
-      if (g < a.nT) {
+      if (g < a.nG) {
         dc v = cmul(cf, {sa[g].x, sa[g].y});
         if (tm.flip && (a.g3[g] & 1)) v = {-v.x, -v.y};
         acc[j] = cadd(acc[j], v);
@@ -106,9 +109,9 @@ __global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
 #pragma unroll
   for (int j = 0; j < MAXJ; ++j) {
     const int g = lane + 64 * j;
-    if (g < a.nT) {
-      const double s = a.fact[g] * invh;
-      a.out[(size_t)key * a.nT + g] = make_double2(acc[j].x * s, acc[j].y * s);
+    if (g < a.nG) {
+      const double sc = a.fact[g] * invh;
+      a.out[(size_t)key * a.nG + g] = make_double2(acc[j].x * sc, acc[j].y * sc);
     }
   }
 }
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(64) void k_p2m(PassArgs a) {
   const double cx = a.lo[0] + (ix + 0.5) * h, cy = a.lo[1] + (iy + 0.5) * h, cz = a.lo[2] + (iz + 0.5) * h;
   const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
   const double2* q = a.q + (int64_t)r * a.n;
-  constexpr int MAXK = 5;
+  constexpr int MAXK = 16;  // nC <= 1024 (p <= 16)
   dc acc[MAXK];
 #pragma unroll
   for (int j = 0; j < MAXK; ++j) acc[j] = {0, 0};
@@ -338,6 +341,86 @@ __global__ __launch_bounds__(64) void k_p2m(PassArgs a) {
   for (int j = 0; j < MAXK; ++j) {
     const int k = tid + 64 * j;
     if (k < a.nC) out[k] = make_double2(acc[j].x, acc[j].y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Helmholtz reduction.  Every table satisfies the Helmholtz equation in the
+// displacement: G_{g+2e1} = -G_{g+2e2} - G_{g+2e3} - (kh)^2 G_g.  In the M2L sum
+// b_k = sum_{k'} G_{k+k'} a_{k'} the terms with k'1 >= 2 can therefore be moved
+// onto k' - 2e1 + 2e2, k' - 2e1 + 2e3 and k' - 2e1 (same or lower order), which
+// leaves moments with k'1 <= 1 only; likewise only b_k with k1 <= 1 need to be
+// computed and the rest follow from the same identity.  Both steps are exact.
+// k_reduce: a_k = (-1)^{|k|} alpha^_k / k!, folded down to k1 <= 1.
+// One 64-lane block per box.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
+  extern __shared__ double2 lds_red[];  // [nC]
+  const int box = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const double2* in = a.in + (int64_t)r * a.in_stride + (int64_t)box * a.nC;
+  for (int k = tid; k < a.nC; k += 64) {
+    const double s = a.scale[k];
+    const double2 v = in[k];
+    lds_red[k] = make_double2(v.x * s, v.y * s);
+  }
+  __syncthreads();
+  // gather form, targets at level k1 = t1 receive from level t1 + 2 (already final)
+  for (int t1 = a.p - 2; t1 >= 0; --t1) {
+    const int m = a.p - t1;  // k2 + k3 <= m
+    const int cnt = ((m + 1) * (m + 2)) / 2;
+    for (int e = tid; e < cnt; e += 64) {
+      // enumerate (k2, k3) with k2 + k3 <= m
+      int tt = 0;
+      while ((tt + 1) * (tt + 2) / 2 <= e) ++tt;
+      const int k3 = e - tt * (tt + 1) / 2, k2 = tt - k3;
+      double2 acc = lds_red[mi_index(t1, k2, k3)];
+      if (k2 >= 2) {
+        const double2 v = lds_red[mi_index(t1 + 2, k2 - 2, k3)];
+        acc.x -= v.x, acc.y -= v.y;
+      }
+      if (k3 >= 2) {
+        const double2 v = lds_red[mi_index(t1 + 2, k2, k3 - 2)];
+        acc.x -= v.x, acc.y -= v.y;
+      }
+      if (t1 + 2 + k2 + k3 <= a.p) {
+        const double2 v = lds_red[mi_index(t1 + 2, k2, k3)];
+        acc.x -= a.kh2 * v.x, acc.y -= a.kh2 * v.y;
+      }
+      lds_red[mi_index(t1, k2, k3)] = acc;
+    }
+    __syncthreads();
+  }
+  double2* out = a.out + (int64_t)r * a.out_stride + (int64_t)box * a.nR;
+  for (int i = tid; i < a.nR; i += 64) out[i] = lds_red[a.rfull[i]];
+}
+
+// k_expand: b (k1 <= 1) -> all |k| <= p by b_k = -b_{k-2e1+2e2} - b_{k-2e1+2e3}
+// - (kh)^2 b_{k-2e1}, then beta^_k = b_k / k!.  Overwrites beta^.
+__global__ __launch_bounds__(64) void k_expand(ReduceArgs a) {
+  extern __shared__ double2 lds_exp[];  // [nC]
+  const int box = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const double2* in = a.in + (int64_t)r * a.in_stride + (int64_t)box * a.nR;
+  for (int i = tid; i < a.nR; i += 64) lds_exp[a.rfull[i]] = in[i];
+  __syncthreads();
+  for (int k1 = 2; k1 <= a.p; ++k1) {
+    const int m = a.p - k1;
+    const int cnt = ((m + 1) * (m + 2)) / 2;
+    for (int e = tid; e < cnt; e += 64) {
+      int tt = 0;
+      while ((tt + 1) * (tt + 2) / 2 <= e) ++tt;
+      const int k3 = e - tt * (tt + 1) / 2, k2 = tt - k3;
+      const double2 u = lds_exp[mi_index(k1 - 2, k2 + 2, k3)];
+      const double2 v = lds_exp[mi_index(k1 - 2, k2, k3 + 2)];
+      const double2 w = lds_exp[mi_index(k1 - 2, k2, k3)];
+      lds_exp[mi_index(k1, k2, k3)] = make_double2(-u.x - v.x - a.kh2 * w.x, -u.y - v.y - a.kh2 * w.y);
+    }
+    __syncthreads();
+  }
+  double2* out = a.out + (int64_t)r * a.out_stride + (int64_t)box * a.nC;
+  for (int k = tid; k < a.nC; k += 64) {
+    const double f = a.invfact[k];
+    const double2 v = lds_exp[k];
+    out[k] = make_double2(v.x * f, v.y * f);
   }
 }
 

@@ -18,11 +18,11 @@ struct TableGenArgs {
   const int* term_start;  // [nkeys+1]
   const double* h;        // [nkeys] box size of each key
   double k;
-  int order, nT;
-  const short* nbr;       // [nT][6]: g - e_x, g - e_y, g - e_z, g - 2e_x, g - 2e_y, g - 2e_z (-1 if none)
-  const unsigned char* g3;  // [nT] third component of g
-  const double* fact;     // [nT] g!
-  double2* out;           // [nkeys][nT]
+  int order, nG;          // orders 0..order, nG = g_count(order) compact entries (g1 <= 2)
+  const short* nbr;       // [nG][6]: g - e_x, g - e_y, g - e_z, g - 2e_x, g - 2e_y, g - 2e_z (-1 if none)
+  const unsigned char* g3;  // [nG] third component of g
+  const double* fact;     // [nG] g!
+  double2* out;           // [nkeys][nG]
 };
 
 struct TreeGeom {
@@ -57,23 +57,35 @@ struct PassArgs {
   int64_t rhs_stride_parent;
 };
 
+// Per-box change of representation between the full Taylor coefficients (C(p+3,3),
+// graded order) and the Helmholtz-reduced set (k1 <= 1, (p+1)^2 entries).
+struct ReduceArgs {
+  int p, nC, nR;
+  double kh2;            // (k h)^2 at this level
+  const int* mi;         // [nC] packed graded multi-indices
+  const int* rfull;      // [nR] graded index of each reduced entry
+  const double* scale;   // [nC] (-1)^{|k|}/k!  (reduce)
+  const double* invfact; // [nC] 1/k!          (expand)
+  const double2* in;     // reduce: alpha^ [rhs][box][nC];  expand: b [rhs][box][nR]
+  double2* out;          // reduce: a [rhs][box][nR];      expand: beta^ [rhs][box][nC]
+  int64_t in_stride, out_stride;  // per-rhs strides (elements)
+};
+
 struct M2LArgs {
   int n;                 // boxes per dimension
-  int nC, nCs, nKB, nRB;  // coefficients, LDS row stride, K blocks of 4, row blocks of 16
+  int nR, nRs, nKB, nRB; // reduced coefficients, LDS row stride, K blocks of 4, row blocks of 16
   int leaf;              // leaf level: neighbour offsets take part
   int tiles_x, ntiles;
-  const double2* alpha;  // [rhs][box][nC]
-  double2* beta;
+  const double2* a;      // reduced scaled moments [rhs][box][nR]
+  double2* b;            // reduced locals [rhs][box][nR]
   int64_t rhs_stride;
-  const double2* Tfd;    // [343][nT] free + Delta (|d|>=2) and Delta-only (|d|<=1) or null
-  const double2* TS;     // [49 (2n-1)][nT] Sigma family or null
+  const double2* Tfd;    // [343][nG] free + Delta (|d|>=2) and Delta-only (|d|<=1) or null
+  const double2* TS;     // [49 (2n-1)][nG] Sigma family or null
   const float2* Tfd32;   // FP32 copies (mixed precision)
   const float2* TS32;
-  int nT;
+  int nG;
   int near_fd, near_s;
-  const int* mi;
-  const double* scale;   // (-1)^{|k|}/k!
-  const double* invfact; // 1/k!
+  const int* rmi;        // [nR] packed reduced multi-indices
 };
 
 void upload_binomials();
@@ -92,6 +104,8 @@ __global__ void k_gather_q(const double2* q, const int* perm, int64_t n, double2
 __global__ void k_finalize(const double2* phi_s, const int* perm, int64_t start, int64_t cnt, int64_t n,
                            double sr, double si, double2* out);
 __global__ void k_p2m(PassArgs a);
+__global__ void k_reduce(ReduceArgs a);
+__global__ void k_expand(ReduceArgs a);
 __global__ void k_m2m(PassArgs a);
 __global__ void k_l2l(PassArgs a);
 __global__ void k_l2p(PassArgs a);

@@ -7,6 +7,9 @@
 //     beta^_k = b_k / k!,
 // with s = (-1)^{k3'} for the Sigma family (whose kernel depends on z + z',
 // so that source derivatives in z enter with a plus sign) and s = 1 otherwise.
+// Both a and b are used in the Helmholtz-reduced form (k1 <= 1, (p+1)^2
+// entries; see k_reduce / k_expand), so the operator is (p+1)^2 x (p+1)^2 and
+// only table entries with g1 <= 2 are read.
 //
 // Work decomposition: a workgroup owns a tile of 16 target boxes that share
 // z index and the parity of x and y (so all 16 have the same 6x6x6 window of
@@ -52,9 +55,8 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   typedef typename Ty::acc AC;
   extern __shared__ double lds_m2l[];
   T2* sG = (T2*)lds_m2l;
-  T2* sA = sG + a.nT;
-  int* sMi = (int*)(sA + 16 * a.nCs);
-  double* sScale = (double*)(sMi + 4 * a.nKB + 4);
+  T2* sA = sG + a.nG;
+  int* sMi = (int*)(sA + 16 * a.nRs);
 
   // XCD-aware tile order: consecutive tiles (same z slab) stay on one XCD.
   const int per = (a.ntiles + 7) / 8;
@@ -76,20 +78,19 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     if (ix < N && iy < N) tmask |= 1u << n;
   }
 
-  const double2* alpha = a.alpha + (int64_t)r * a.rhs_stride;
-  for (int e = tid; e < 16 * a.nCs; e += 256) {
+  const double2* alpha = a.a + (int64_t)r * a.rhs_stride;
+  for (int e = tid; e < 16 * a.nRs; e += 256) {
     sA[e].x = 0;
     sA[e].y = 0;
   }
-  for (int e = tid; e < 4 * a.nKB; e += 256) sMi[e] = e < a.nC ? a.mi[e] : -1;
-  for (int e = tid; e < a.nC; e += 256) sScale[e] = a.scale[e];
+  for (int e = tid; e < 4 * a.nKB; e += 256) sMi[e] = e < a.nR ? a.rmi[e] : -1;
 
   const int col = lane & 15, krow = lane >> 4;
   int rowmi[RB];
 #pragma unroll
   for (int j = 0; j < RB; ++j) {
     const int rb = w + 4 * j, k = 16 * rb + col;
-    rowmi[j] = (rb < a.nRB && k < a.nC) ? a.mi[k] : -1;
+    rowmi[j] = (rb < a.nRB && k < a.nR) ? a.rmi[k] : -1;
   }
   AC accR[RB], accI[RB];
 #pragma unroll
@@ -121,27 +122,26 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
           const int key = pass ? ((dx + 3) * 7 + (dy + 3)) * (2 * N - 1) + (2 * iz + dz)
                                : ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
           __syncthreads();
-          const T2* g = table + (int64_t)key * a.nT;
-          for (int e = tid; e < a.nT; e += 256) sG[e] = g[e];
-          for (int e = tid; e < 16 * a.nC; e += 256) {
-            const int n = e / a.nC, kk = e - n * a.nC;
+          const T2* g = table + (int64_t)key * a.nG;
+          for (int e = tid; e < a.nG; e += 256) sG[e] = g[e];
+          for (int e = tid; e < 16 * a.nR; e += 256) {
+            const int n = e / a.nR, kk = e - n * a.nR;
             T2 v;
             v.x = 0;
             v.y = 0;
             if ((smask >> n) & 1) {
               const int ix = px + 2 * (4 * X0 + (n & 3)) + dx, iy = py + 2 * (4 * Y0 + (n >> 2)) + dy;
               const int64_t sb = ((int64_t)ix * N + iy) * N + (iz + dz);
-              double s = sScale[kk];
-              if (mirror && ((sMi[kk] >> 16) & 1)) s = -s;
-              const double2 av = alpha[sb * a.nC + kk];
+              const double s = (mirror && ((sMi[kk] >> 16) & 1)) ? -1.0 : 1.0;
+              const double2 av = alpha[sb * a.nR + kk];
               v = Ty::cvt(make_double2(av.x * s, av.y * s));
             }
-            sA[n * a.nCs + kk] = v;
+            sA[n * a.nRs + kk] = v;
           }
           __syncthreads();
           for (int kb = 0; kb < a.nKB; ++kb) {
             const int kp = 4 * kb + krow;
-            const T2 bv = sA[col * a.nCs + kp];
+            const T2 bv = sA[col * a.nRs + kp];
             const int mp = sMi[kp];
 #pragma unroll
             for (int j = 0; j < RB; ++j) {
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
                 gv.y = 0;
                 if (rowmi[j] >= 0 && mp >= 0) {
                   const int gg = rowmi[j] + mp;
-                  gv = sG[mi_index(gg & 255, (gg >> 8) & 255, gg >> 16)];
+                  gv = sG[g_index(gg & 255, (gg >> 8) & 255, gg >> 16)];
                 }
                 accR[j] = Ty::mfma(gv.x, bv.x, accR[j]);
                 accR[j] = Ty::mfma(-gv.y, bv.y, accR[j]);
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     }
   }
   // epilogue: result rows per the precision's MFMA layout, columns = targets
-  double2* beta = a.beta + (int64_t)r * a.rhs_stride;
+  double2* beta = a.b + (int64_t)r * a.rhs_stride;
 #pragma unroll
   for (int j = 0; j < RB; ++j) {
     const int rb = w + 4 * j;
@@ -177,10 +177,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int k = 16 * rb + Ty::row(krow, i);
-      if (k < a.nC) {
-        const double f = a.invfact[k];
-        beta[tb * a.nC + k] = make_double2((double)accR[j][i] * f, (double)accI[j][i] * f);
-      }
+      if (k < a.nR) beta[tb * a.nR + k] = make_double2((double)accR[j][i], (double)accI[j][i]);
     }
   }
 }
@@ -188,8 +185,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
 template <typename T>
 static hipError_t launch_t(const M2LArgs& a, int nrhs, hipStream_t s) {
   typedef typename M2LTypes<T>::T2 T2;
-  size_t lds = (size_t)a.nT * sizeof(T2) + (size_t)16 * a.nCs * sizeof(T2) + (4 * (size_t)a.nKB + 4) * sizeof(int) +
-               (size_t)a.nC * sizeof(double);
+  size_t lds = (size_t)a.nG * sizeof(T2) + (size_t)16 * a.nRs * sizeof(T2) + (4 * (size_t)a.nKB + 4) * sizeof(int);
   const int RB = (a.nRB + 3) / 4;
   dim3 grid(8 * ((a.ntiles + 7) / 8), nrhs), block(256);
   void (*fn)(M2LArgs) = nullptr;

@@ -53,3 +53,16 @@ __host__ __device__ __forceinline__ int mi_index(int a, int b, int c) {
 __host__ __device__ __forceinline__ int mi_count(int n) { return ((n + 1) * (n + 2) * (n + 3)) / 6; }
 
 }  // namespace tefmm
+
+namespace tefmm {
+// Compact derivative-table layout: only g with g1 <= 2 are kept (the Helmholtz
+// equation gives every other entry from these), ordered by |g| = n, then g1,
+// then g3:  idx = off(n) + [g1>=1](n+1) + [g1>=2] n + g3,  off(0) = 0,
+// off(n) = 1 + 3 n (n-1) / 2.  Count up to order N: off(N+1) = 1 + 3 N (N+1)/2.
+__host__ __device__ __forceinline__ int g_offset(int n) { return n == 0 ? 0 : 1 + (3 * n * (n - 1)) / 2; }
+__host__ __device__ __forceinline__ int g_index(int g1, int g2, int g3) {
+  const int n = g1 + g2 + g3;
+  return g_offset(n) + (g1 >= 1 ? n + 1 : 0) + (g1 >= 2 ? n : 0) + g3;
+}
+__host__ __device__ __forceinline__ int g_count(int N) { return g_offset(N + 1); }
+}  // namespace tefmm
