@@ -89,6 +89,10 @@ typedef struct {
   double dcim_fit_err[8]; /* max relative misfit on the sampling paths */
   int depth[4];          /* tree depth per layer (0 if no particles) */
   int n_families;
+  double m2l_flops;      /* algorithmic M2L flops of the last evaluate: 8 (p+1)^4 per
+                            (target box, source box, family) contraction, times n_rhs */
+  int m2l_launches;      /* M2L kernel launches of the last evaluate */
+  int n_rhs;             /* charge vectors of the last evaluate */
 } tefmm_stats;
 
 /* Fill an options struct with the defaults (p = 8, depth auto, max_leaf 64,

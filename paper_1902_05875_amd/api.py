@@ -49,7 +49,8 @@ class StatsC(ctypes.Structure):
                 ["t_setup_tree_ms", "t_setup_tables_ms", "t_setup_dcim_ms", "t_p2m_ms", "t_m2m_ms", "t_m2l_ms",
                  "t_l2l_ms", "t_l2p_ms", "t_p2p_ms", "t_total_ms"]] + [
         ("m2l_pairs", ctypes.c_int64), ("p2p_pairs", ctypes.c_int64), ("n_images", ctypes.c_int * 8),
-        ("dcim_fit_err", ctypes.c_double * 8), ("depth", ctypes.c_int * 4), ("n_families", ctypes.c_int)]
+        ("dcim_fit_err", ctypes.c_double * 8), ("depth", ctypes.c_int * 4), ("n_families", ctypes.c_int),
+        ("m2l_flops", ctypes.c_double), ("m2l_launches", ctypes.c_int), ("n_rhs", ctypes.c_int)]
 
 
 _lib = None

@@ -44,6 +44,7 @@ struct Group {
   std::vector<double2*> Tfd, TS;
   std::vector<float2*> Tfd32, TS32;
   std::vector<int64_t> nbox;          // boxes at level
+  std::vector<int64_t> far_pairs, near_pairs;  // per level from 2: interaction-list / neighbour pairs
 };
 
 template <class T>
@@ -63,6 +64,7 @@ struct tefmm_ctx {
   int* d_mi = nullptr;      // [nC] graded multi-indices (packed)
   int* d_rmi = nullptr;     // [nR] reduced multi-indices (packed)
   int* d_rfull = nullptr;   // [nR] graded index of each reduced entry
+  int* d_gpad = nullptr;    // [nG] padded LDS position of each compact table entry
   short* d_nbr = nullptr;   // [nG][6] compact-table recurrence neighbours
   unsigned char* d_g3 = nullptr;
   double *d_fact = nullptr, *d_scale = nullptr, *d_invfact = nullptr;
@@ -153,6 +155,7 @@ static int build_constant_tables(tefmm_t h) {
       }
   if ((int)rmi.size() != nR) return fail(h, TEFMM_ERR_STATE, "reduced index set size");
   std::vector<short> nbr(6 * nG, -1);
+  std::vector<int> gpad(nG);
   std::vector<unsigned char> g3(nG);
   std::vector<double> fact(nG);
   int cnt = 0;
@@ -162,6 +165,7 @@ static int build_constant_tables(tefmm_t h) {
         const int b = n - g1 - c, i = g_index(g1, b, c);
         if (i != cnt++) return fail(h, TEFMM_ERR_STATE, "compact table order");
         g3[i] = (unsigned char)c;
+        gpad[i] = (g1 * (2 * p + 1) + (b + c)) * (2 * p + 1) + c;
         fact[i] = f(g1) * f(b) * f(c);
         if (g1 >= 1) nbr[6 * i + 0] = (short)g_index(g1 - 1, b, c);
         if (b >= 1) nbr[6 * i + 1] = (short)g_index(g1, b - 1, c);
@@ -175,6 +179,8 @@ static int build_constant_tables(tefmm_t h) {
   HIPCHK(h, hipMalloc(&h->d_rmi, sizeof(int) * nR));
   HIPCHK(h, hipMalloc(&h->d_rfull, sizeof(int) * nR));
   HIPCHK(h, hipMalloc(&h->d_nbr, sizeof(short) * 6 * nG));
+  HIPCHK(h, hipMalloc(&h->d_gpad, sizeof(int) * nG));
+  HIPCHK(h, hipMemcpy(h->d_gpad, gpad.data(), sizeof(int) * nG, hipMemcpyHostToDevice));
   HIPCHK(h, hipMalloc(&h->d_g3, nG));
   HIPCHK(h, hipMalloc(&h->d_fact, sizeof(double) * nG));
   HIPCHK(h, hipMalloc(&h->d_scale, sizeof(double) * nC));
@@ -228,6 +234,7 @@ extern "C" void tefmm_destroy(tefmm_t h) {
   dfree(h->d_mi);
   dfree(h->d_rmi);
   dfree(h->d_rfull);
+  dfree(h->d_gpad);
   dfree(h->d_nbr);
   dfree(h->d_g3);
   dfree(h->d_fact);
@@ -514,24 +521,27 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
         }
     for (int lev = 2; lev <= g.depth; ++lev) {
       const int nb2 = 1 << lev;
-      auto cnt1 = [&](int i, int d) {
-        int j = i + d;
-        return j >= 0 && j < nb2;
-      };
+      // valid (target, source) pairs for one parity class window, split into far and near
+      int64_t far1 = 0, near1 = 0;
       for (int ix = 0; ix < nb2; ++ix)
         for (int dx = -2 - (ix & 1); dx <= 3 - (ix & 1); ++dx) {
-          if (!cnt1(ix, dx)) continue;
+          if (ix + dx < 0 || ix + dx >= nb2) continue;
           for (int iy = 0; iy < nb2; ++iy)
             for (int dy = -2 - (iy & 1); dy <= 3 - (iy & 1); ++dy) {
-              if (!cnt1(iy, dy)) continue;
+              if (iy + dy < 0 || iy + dy >= nb2) continue;
               for (int iz = 0; iz < nb2; ++iz)
                 for (int dz = -2 - (iz & 1); dz <= 3 - (iz & 1); ++dz) {
-                  if (!cnt1(iz, dz)) continue;
-                  if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
-                  h->m2l_pairs++;
+                  if (iz + dz < 0 || iz + dz >= nb2) continue;
+                  if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1)
+                    ++near1;
+                  else
+                    ++far1;
                 }
             }
         }
+      g.far_pairs.push_back(far1);
+      g.near_pairs.push_back(near1);
+      h->m2l_pairs += far1;
     }
   }
   // complex images (host FP64)
@@ -628,6 +638,8 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
   }
   const int64_t n = h->n;
   const bool fp32 = h->opt.precision == TEFMM_MIXED_FP32;
+  double m2l_flops = 0;
+  int m2l_launches = 0;
   HIPCHK(h, hipEventRecord(h->ev[0], s));
   hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, (const double2*)q,
                      h->d_perm, n, h->d_q);
@@ -652,7 +664,7 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
       PassArgs a = pa;
       a.nbox_dim = 1 << lev, a.alpha = g.alpha[lev], a.rhs_stride = g.nbox[lev] * h->nC;
       a.alpha_child = g.alpha[lev + 1], a.rhs_stride_child = g.nbox[lev + 1] * h->nC;
-      const size_t lds = sizeof(double2) * 8 * h->nC;
+      const size_t lds = (3 * sizeof(double2) + sizeof(int)) * h->nC;
       HIPCHK(h, hipFuncSetAttribute((const void*)k_m2m, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
       hipLaunchKernelGGL(k_m2m, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), lds, s, a);
       HIPCHK(h, hipGetLastError());
@@ -668,20 +680,33 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
       HIPCHK(h, hipGetLastError());
     }
     HIPCHK(h, hipEventRecord(h->ev[2], s));
-    for (int lev = 2; lev <= H; ++lev) {
+    {
       M2LArgs m;
       std::memset(&m, 0, sizeof(m));
-      const int nb = 1 << lev;
-      m.n = nb, m.nR = h->nR, m.nRs = h->nRs, m.nKB = h->nKB, m.nRB = h->nRB, m.leaf = lev == H;
-      m.tiles_x = ((nb / 2) + 3) / 4;
-      m.ntiles = nb * 4 * m.tiles_x * m.tiles_x;
-      m.a = g.ared[lev], m.b = g.bred[lev], m.rhs_stride = g.nbox[lev] * h->nR;
-      m.Tfd = g.Tfd[lev], m.TS = g.TS[lev], m.Tfd32 = g.Tfd32[lev], m.TS32 = g.TS32[lev], m.nG = h->nG;
-      m.near_fd = g.has[2], m.near_s = g.has[0] || g.has[1];
-      m.rmi = h->d_rmi;
+      m.nR = h->nR, m.nRs = h->nRs, m.nKB = h->nKB, m.nRB = h->nRB, m.nG = h->nG, m.p = p, m.P2 = 2 * p + 1;
+      m.rmi = h->d_rmi, m.gpad = h->d_gpad;
+      m.nlev = H - 1;
+      for (int lev = 2; lev <= H; ++lev) {
+        M2LLevel& L = m.lev[lev - 2];
+        L.n = 1 << lev, L.leaf = lev == H;
+        L.near_fd = g.has[2], L.near_s = g.has[0] || g.has[1];
+        L.a = g.ared[lev], L.b = g.bred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
+        L.Tfd = g.Tfd[lev], L.TS = g.TS[lev], L.Tfd32 = g.Tfd32[lev], L.TS32 = g.TS32[lev];
+      }
       HIPCHK(h, launch_m2l(m, nrhs, fp32, s));
     }
     HIPCHK(h, hipEventRecord(h->ev[3], s));
+    {
+      const double per = 8.0 * (double)h->nR * (double)h->nR;
+      for (int lev = 2; lev <= H; ++lev) {
+        const int64_t far = g.far_pairs[lev - 2], nr = g.near_pairs[lev - 2];
+        const bool sig = g.has[0] || g.has[1];
+        double pairs = (double)far + (sig ? (double)far : 0.0);
+        if (lev == H) pairs += (g.has[2] ? (double)nr : 0.0) + (sig ? (double)nr : 0.0);
+        m2l_flops += per * pairs * nrhs;
+      }
+      ++m2l_launches;
+    }
     for (int lev = 2; lev <= H; ++lev) {
       ReduceArgs ra;
       const double hl = g.side / (1 << lev), kh = h->med.k[g.layer] * hl;
@@ -694,7 +719,8 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
         PassArgs a = pa;
         a.nbox_dim = 1 << lev, a.beta = g.beta[lev], a.rhs_stride = g.nbox[lev] * h->nC;
         a.beta_parent = g.beta[lev - 1], a.rhs_stride_parent = g.nbox[lev - 1] * h->nC;
-        hipLaunchKernelGGL(k_l2l, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, a);
+        hipLaunchKernelGGL(k_l2l, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), (2 * sizeof(double2) + sizeof(int)) * h->nC,
+                           s, a);
         HIPCHK(h, hipGetLastError());
       }
     }
@@ -729,6 +755,9 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
     }
   }
   HIPCHK(h, hipEventRecord(h->ev[7], s));
+  h->st.m2l_flops = m2l_flops;
+  h->st.m2l_launches = m2l_launches;
+  h->st.n_rhs = nrhs;
   return TEFMM_OK;
 }
 

@@ -425,84 +425,115 @@ __global__ __launch_bounds__(64) void k_expand(ReduceArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// M2M (Sec. 3.1, Eq. TETartoTETar): parent moments from the 8 children.
-// In parent units the child offset is delta = (c - 1/2)/2 per coordinate and
-//   alpha^P_k = sum_{k' <= k} prod_i C(k_i, k'_i) delta_i^{k_i - k'_i} 2^{-|k'|} alpha^C_{k'}.
+// M2M (Sec. 3.1, Eq. TETartoTETar) and L2L (Eq. freeletole).  Both shifts are
+// products of one-dimensional binomial shifts, applied here as three passes
+// (x, then y, then z) over the coefficient set |k| <= p; every intermediate
+// that the final result needs also has total order <= p, so the passes are
+// exact.  Child centre relative to the parent, in parent units:
+// delta_i = (c_i - 1/2)/2 = +-1/4.
+//   M2M: alpha^P_k = sum_{k' <= k} prod_i C(k_i, k'_i) delta_i^{k_i-k'_i} 2^{-k'_i} alpha^C_{k'}
+//   L2L: beta^C_k = sum_{k' >= k} prod_i C(k'_i, k_i) delta_i^{k'_i-k_i} 2^{-k_i} beta^P_{k'}
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double quarter_pow(int neg, int e) {
+  // (+-1/4)^e
+  const double v = ldexp(1.0, -2 * e);
+  return (neg && (e & 1)) ? -v : v;
+}
+
+// One pass along axis `ax` of the upward shift: dst[k] = sum_{j <= k_ax} C(k_ax, j)
+// delta^{k_ax - j} 2^{-j} src[k with k_ax -> j]
+__device__ __forceinline__ void m2m_pass(const double2* src, double2* dst, const int* mi, int nC, int ax,
+                                         int neg, int tid) {
+  for (int k = tid; k < nC; k += 64) {
+    const int pk = mi[k];
+    int c[3] = {pk & 255, (pk >> 8) & 255, pk >> 16};
+    const int ka = c[ax];
+    double sx = 0, sy = 0;
+    for (int j = 0; j <= ka; ++j) {
+      c[ax] = j;
+      const double f = c_binom[ka][j] * quarter_pow(neg, ka - j) * ldexp(1.0, -j);
+      const double2 v = src[mi_index(c[0], c[1], c[2])];
+      sx += f * v.x;
+      sy += f * v.y;
+    }
+    dst[k] = make_double2(sx, sy);
+  }
+}
+
 __global__ __launch_bounds__(64) void k_m2m(PassArgs a) {
-  extern __shared__ double2 lds_m2m[];  // [8][nC]
+  extern __shared__ double2 lds_m2m[];  // buf0, buf1, acc: 3 x nC
+  double2* b0 = lds_m2m;
+  double2* b1 = b0 + a.nC;
+  double2* acc = b1 + a.nC;
+  int* smi = (int*)(acc + a.nC);
   const int pb = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
   const int np = a.nbox_dim;  // parent grid size
   const int nc = 2 * np;
   const int ix = pb / (np * np), iy = (pb / np) % np, iz = pb % np;
   const double2* ch = a.alpha_child + (int64_t)r * a.rhs_stride_child;
-  for (int e = tid; e < 8 * a.nC; e += 64) {
-    const int c = e / a.nC, k = e % a.nC;
+  for (int k = tid; k < a.nC; k += 64) acc[k] = make_double2(0.0, 0.0), smi[k] = a.mi[k];
+  for (int c = 0; c < 8; ++c) {
     const int cx = (c >> 2) & 1, cy = (c >> 1) & 1, cz = c & 1;
-    const int cb = ((2 * ix + cx) * nc + (2 * iy + cy)) * nc + (2 * iz + cz);
-    lds_m2m[e] = ch[(int64_t)cb * a.nC + k];
+    const int64_t cb = ((int64_t)(2 * ix + cx) * nc + (2 * iy + cy)) * nc + (2 * iz + cz);
+    __syncthreads();
+    for (int k = tid; k < a.nC; k += 64) b0[k] = ch[cb * a.nC + k];
+    __syncthreads();
+    m2m_pass(b0, b1, smi, a.nC, 0, !cx, tid);
+    __syncthreads();
+    m2m_pass(b1, b0, smi, a.nC, 1, !cy, tid);
+    __syncthreads();
+    m2m_pass(b0, b1, smi, a.nC, 2, !cz, tid);
+    __syncthreads();
+    for (int k = tid; k < a.nC; k += 64) acc[k] = make_double2(acc[k].x + b1[k].x, acc[k].y + b1[k].y);
   }
-  __syncthreads();
   double2* out = a.alpha + (int64_t)r * a.rhs_stride + (int64_t)pb * a.nC;
-  for (int k = tid; k < a.nC; k += 64) {
-    const int pk = a.mi[k];
-    const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
-    dc s = {0, 0};
-    for (int c = 0; c < 8; ++c) {
-      const double dx = ((c >> 2) & 1) ? 0.25 : -0.25, dy = ((c >> 1) & 1) ? 0.25 : -0.25,
-                   dz = (c & 1) ? 0.25 : -0.25;
-      for (int a1 = 0; a1 <= k1; ++a1) {
-        const double f1 = c_binom[k1][a1] * pow(dx, (double)(k1 - a1));
-        for (int a2 = 0; a2 <= k2; ++a2) {
-          const double f2 = f1 * c_binom[k2][a2] * pow(dy, (double)(k2 - a2));
-          for (int a3 = 0; a3 <= k3; ++a3) {
-            const double f = f2 * c_binom[k3][a3] * pow(dz, (double)(k3 - a3)) * ldexp(1.0, -(a1 + a2 + a3));
-            const double2 v = lds_m2m[c * a.nC + mi_index(a1, a2, a3)];
-            s.x += f * v.x;
-            s.y += f * v.y;
-          }
-        }
-      }
+  for (int k = tid; k < a.nC; k += 64) out[k] = acc[k];
+}
+
+// One pass of the downward shift: dst[k] = 2^{-k_ax} sum_{j >= k_ax} C(j, k_ax) delta^{j - k_ax}
+// src[k with k_ax -> j], j up to p minus the other two components.
+__device__ __forceinline__ void l2l_pass(const double2* src, double2* dst, const int* mi, int nC, int p, int ax,
+                                         int neg, int tid) {
+  for (int k = tid; k < nC; k += 64) {
+    const int pk = mi[k];
+    int c[3] = {pk & 255, (pk >> 8) & 255, pk >> 16};
+    const int ka = c[ax];
+    const int top = p - (c[0] + c[1] + c[2] - ka);
+    double sx = 0, sy = 0;
+    for (int j = ka; j <= top; ++j) {
+      c[ax] = j;
+      const double f = c_binom[j][ka] * quarter_pow(neg, j - ka);
+      const double2 v = src[mi_index(c[0], c[1], c[2])];
+      sx += f * v.x;
+      sy += f * v.y;
     }
-    out[k] = make_double2(s.x, s.y);
+    const double s = ldexp(1.0, -ka);
+    dst[k] = make_double2(s * sx, s * sy);
   }
 }
 
-// ---------------------------------------------------------------------------
-// L2L (Sec. 3.1, Eq. freeletole): child locals from the parent.  In parent
-// units the child centre is at delta = (c - 1/2)/2 and
-//   beta^C_k += 2^{-|k|} sum_{k' >= k} prod_i C(k'_i, k_i) delta_i^{k'_i - k_i} beta^P_{k'}.
-// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_l2l(PassArgs a) {
-  extern __shared__ double2 lds_l2l[];
+  extern __shared__ double2 lds_l2l[];  // b0, b1: 2 x nC
+  double2* b0 = lds_l2l;
+  double2* b1 = b0 + a.nC;
+  int* smi = (int*)(b1 + a.nC);
   const int cb = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
   const int nc = a.nbox_dim, np = nc / 2;
   const int ix = cb / (nc * nc), iy = (cb / nc) % nc, iz = cb % nc;
-  const int pb = ((ix >> 1) * np + (iy >> 1)) * np + (iz >> 1);
-  const double2* par = a.beta_parent + (int64_t)r * a.rhs_stride_parent + (int64_t)pb * a.nC;
-  for (int k = tid; k < a.nC; k += 64) lds_l2l[k] = par[k];
+  const int64_t pb = ((int64_t)(ix >> 1) * np + (iy >> 1)) * np + (iz >> 1);
+  const double2* par = a.beta_parent + (int64_t)r * a.rhs_stride_parent + pb * a.nC;
+  for (int k = tid; k < a.nC; k += 64) b0[k] = par[k], smi[k] = a.mi[k];
   __syncthreads();
-  const double dx = (ix & 1) ? 0.25 : -0.25, dy = (iy & 1) ? 0.25 : -0.25, dz = (iz & 1) ? 0.25 : -0.25;
+  l2l_pass(b0, b1, smi, a.nC, a.p, 0, !(ix & 1), tid);
+  __syncthreads();
+  l2l_pass(b1, b0, smi, a.nC, a.p, 1, !(iy & 1), tid);
+  __syncthreads();
+  l2l_pass(b0, b1, smi, a.nC, a.p, 2, !(iz & 1), tid);
+  __syncthreads();
   double2* out = a.beta + (int64_t)r * a.rhs_stride + (int64_t)cb * a.nC;
   for (int k = tid; k < a.nC; k += 64) {
-    const int pk = a.mi[k];
-    const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
-    dc s = {0, 0};
-    for (int b1 = k1; b1 <= a.p; ++b1) {
-      const double f1 = c_binom[b1][k1] * pow(dx, (double)(b1 - k1));
-      for (int b2 = k2; b1 + b2 <= a.p; ++b2) {
-        const double f2 = f1 * c_binom[b2][k2] * pow(dy, (double)(b2 - k2));
-        for (int b3 = k3; b1 + b2 + b3 <= a.p; ++b3) {
-          const double f = f2 * c_binom[b3][k3] * pow(dz, (double)(b3 - k3));
-          const double2 v = lds_l2l[mi_index(b1, b2, b3)];
-          s.x += f * v.x;
-          s.y += f * v.y;
-        }
-      }
-    }
-    const double sc = ldexp(1.0, -(k1 + k2 + k3));
-    double2 o = out[k];
-    out[k] = make_double2(o.x + sc * s.x, o.y + sc * s.y);
+    const double2 o = out[k];
+    out[k] = make_double2(o.x + b1[k].x, o.y + b1[k].y);
   }
 }
 

@@ -71,11 +71,12 @@ struct ReduceArgs {
   int64_t in_stride, out_stride;  // per-rhs strides (elements)
 };
 
-struct M2LArgs {
+// One tree level of the M2L launch.
+struct M2LLevel {
   int n;                 // boxes per dimension
-  int nR, nRs, nKB, nRB; // reduced coefficients, LDS row stride, K blocks of 4, row blocks of 16
   int leaf;              // leaf level: neighbour offsets take part
-  int tiles_x, ntiles;
+  int tiles_x, tiles_y, ntiles;
+  int near_fd, near_s;
   const double2* a;      // reduced scaled moments [rhs][box][nR]
   double2* b;            // reduced locals [rhs][box][nR]
   int64_t rhs_stride;
@@ -83,9 +84,18 @@ struct M2LArgs {
   const double2* TS;     // [49 (2n-1)][nG] Sigma family or null
   const float2* Tfd32;   // FP32 copies (mixed precision)
   const float2* TS32;
-  int nG;
-  int near_fd, near_s;
+};
+
+constexpr int M2L_MAX_LEVELS = 8;
+
+struct M2LArgs {
+  int nR, nRs, nKB, nRB; // reduced coefficients, LDS row stride, K blocks of 4, row blocks of 16
+  int nG, p, P2;         // compact table size, order, 2p + 1
+  int nlev;              // levels in this launch; the last one is the widest
+  int tile_start[M2L_MAX_LEVELS + 1];
+  M2LLevel lev[M2L_MAX_LEVELS];
   const int* rmi;        // [nR] packed reduced multi-indices
+  const int* gpad;       // [nG] position of each compact table entry in the padded LDS layout
 };
 
 void upload_binomials();

@@ -32,7 +32,8 @@ struct M2LTypes<double> {
   typedef double2 T2;
   typedef d4 acc;
   __device__ static acc mfma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  __device__ static const T2* table(const M2LArgs& a, int pass) { return pass ? a.TS : a.Tfd; }
+  __device__ static const T2* tableF(const M2LLevel& L) { return L.Tfd; }
+  __device__ static const T2* tableS(const M2LLevel& L) { return L.TS; }
   __device__ static T2 cvt(double2 v) { return v; }
   // FP64 16x16x4 result: register i of lane l holds row (l >> 4) + 4 i, column l & 15
   __device__ static int row(int lane_hi, int i) { return lane_hi + 4 * i; }
@@ -42,68 +43,111 @@ struct M2LTypes<float> {
   typedef float2 T2;
   typedef f4 acc;
   __device__ static acc mfma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  __device__ static const T2* table(const M2LArgs& a, int pass) { return pass ? a.TS32 : a.Tfd32; }
+  __device__ static const T2* tableF(const M2LLevel& L) { return L.Tfd32; }
+  __device__ static const T2* tableS(const M2LLevel& L) { return L.TS32; }
   __device__ static T2 cvt(double2 v) { return make_float2((float)v.x, (float)v.y); }
   // FP32 16x16x4 result: register i of lane l holds row 4 (l >> 4) + i, column l & 15
   __device__ static int row(int lane_hi, int i) { return 4 * lane_hi + i; }
 };
 
-template <typename T, int RB>
+// LDS layout of a key's table: G_{k+k'} sits at ((g1 P2 + m) P2 + g3) with
+// g1 = k1 + k1', m = (k2 + k3) + (k2' + k3'), g3 = k3 + k3', P2 = 2p + 1, so
+// the address splits into a row part and a column part:
+//   row(k) = (k1 P2 + k2 + k3) P2 + k3,  col(k') = (k1' P2 + k2' + k3') P2 + k3'.
+
+template <typename T, int TW, int NCB>
 __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   typedef M2LTypes<T> Ty;
   typedef typename Ty::T2 T2;
   typedef typename Ty::acc AC;
+  constexpr int NT = 16 * NCB;  // target boxes per workgroup
   extern __shared__ double lds_m2l[];
+  const int P2 = a.P2;
+  const int padG = 3 * P2 * P2;
   T2* sG = (T2*)lds_m2l;
-  T2* sA = sG + a.nG;
-  int* sMi = (int*)(sA + 16 * a.nRs);
+  T2* sA = sG + padG;
+  int* sCol = (int*)(sA + NT * a.nRs);     // [4 nKB]: column offset | k3' parity << 20 | valid << 21
 
-  // XCD-aware tile order: consecutive tiles (same z slab) stay on one XCD.
-  const int per = (a.ntiles + 7) / 8;
-  const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (tile >= a.ntiles) return;
+  // Block -> (level, tile).  The coarse levels come first and keep the hardware's
+  // round-robin over the XCDs; tiles of the last (widest) level are remapped so
+  // that consecutive tiles (same z slab) stay on one XCD.
+  int li = 0, tile = 0;
+  const int widest = a.nlev - 1;
+  if ((int)blockIdx.x < a.tile_start[widest]) {
+    while ((int)blockIdx.x >= a.tile_start[li + 1]) ++li;
+    tile = blockIdx.x - a.tile_start[li];
+  } else {
+    li = widest;
+    const int b = blockIdx.x - a.tile_start[widest];
+    const int nt = a.lev[li].ntiles;
+    const int per = (nt + 7) / 8;
+    tile = (b % 8) * per + b / 8;
+    if (tile >= nt) return;
+  }
+  const M2LLevel& L = a.lev[li];
   const int r = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int t = tile;
-  const int X0 = t % a.tiles_x;
-  t /= a.tiles_x;
-  const int Y0 = t % a.tiles_x;
-  t /= a.tiles_x;
+  const int X0 = t % L.tiles_x;
+  t /= L.tiles_x;
+  const int Y0 = t % L.tiles_y;
+  t /= L.tiles_y;
   const int px = t & 1, py = (t >> 1) & 1, iz = t >> 2;
-  const int N = a.n, pz = iz & 1;
-  // target n (0..15): ix = px + 2(4 X0 + (n & 3)), iy = py + 2(4 Y0 + (n >> 2))
+  const int N = L.n, pz = iz & 1;
+  // target n: ix = px + 2 (4 X0 + (n & 3)), iy = py + 2 (4 NCB Y0 + (n >> 2))
   unsigned tmask = 0;
-  for (int n = 0; n < 16; ++n) {
-    const int ix = px + 2 * (4 * X0 + (n & 3)), iy = py + 2 * (4 * Y0 + (n >> 2));
+  for (int n = 0; n < NT; ++n) {
+    const int ix = px + 2 * (4 * X0 + (n & 3)), iy = py + 2 * (4 * NCB * Y0 + (n >> 2));
     if (ix < N && iy < N) tmask |= 1u << n;
   }
 
-  const double2* alpha = a.a + (int64_t)r * a.rhs_stride;
-  for (int e = tid; e < 16 * a.nRs; e += 256) {
+  const double2* alpha = L.a + (int64_t)r * L.rhs_stride;
+  for (int e = tid; e < NT * a.nRs; e += 256) {
     sA[e].x = 0;
     sA[e].y = 0;
   }
-  for (int e = tid; e < 4 * a.nKB; e += 256) sMi[e] = e < a.nR ? a.rmi[e] : -1;
-
-  const int col = lane & 15, krow = lane >> 4;
-  int rowmi[RB];
-#pragma unroll
-  for (int j = 0; j < RB; ++j) {
-    const int rb = w + 4 * j, k = 16 * rb + col;
-    rowmi[j] = (rb < a.nRB && k < a.nR) ? a.rmi[k] : -1;
+  for (int e = tid; e < padG; e += 256) {
+    sG[e].x = 0;
+    sG[e].y = 0;
   }
-  AC accR[RB], accI[RB];
+  for (int e = tid; e < 4 * a.nKB; e += 256) {
+    int v = 0;
+    if (e < a.nR) {
+      const int pk = a.rmi[e];
+      const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
+      v = ((k1 * P2 + k2 + k3) * P2 + k3) | ((k3 & 1) << 20) | (1 << 21);
+    }
+    sCol[e] = v;
+  }
+
+  // this wave's (row block, column block) tiles, round robin over the 4 waves
+  const int col = lane & 15, krow = lane >> 4;
+  const int ntile = a.nRB * NCB;
+  int rowo[TW], tcb[TW];
 #pragma unroll
-  for (int j = 0; j < RB; ++j) {
+  for (int j = 0; j < TW; ++j) {
+    const int id = w + 4 * j;
+    const int rb = id % a.nRB, cb = id / a.nRB;
+    const int k = 16 * rb + col;
+    rowo[j] = -1, tcb[j] = cb;
+    if (id < ntile && k < a.nR) {
+      const int pk = a.rmi[k];
+      const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
+      rowo[j] = (k1 * P2 + k2 + k3) * P2 + k3;
+    }
+  }
+  AC accR[TW], accI[TW];
+#pragma unroll
+  for (int j = 0; j < TW; ++j) {
     accR[j] = AC{0, 0, 0, 0};
     accI[j] = AC{0, 0, 0, 0};
   }
 
   for (int pass = 0; pass < 2; ++pass) {
-    const T2* table = Ty::table(a, pass);
+    const T2* table = pass ? (const T2*)Ty::tableS(L) : (const T2*)Ty::tableF(L);
     if (!table) continue;
     const bool mirror = pass == 1;
-    const bool near_ok = pass ? a.near_s : a.near_fd;
+    const bool near_ok = pass ? L.near_s : L.near_fd;
     for (int oz = 0; oz < 6; ++oz) {
       const int dz = oz - 2 - pz;
       if (iz + dz < 0 || iz + dz >= N) continue;
@@ -112,10 +156,10 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
         for (int ox = 0; ox < 6; ++ox) {
           const int dx = ox - 2 - px;
           const bool nearb = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
-          if (nearb && !(a.leaf && near_ok)) continue;
+          if (nearb && !(L.leaf && near_ok)) continue;
           unsigned smask = 0;
-          for (int n = 0; n < 16; ++n) {
-            const int ix = px + 2 * (4 * X0 + (n & 3)) + dx, iy = py + 2 * (4 * Y0 + (n >> 2)) + dy;
+          for (int n = 0; n < NT; ++n) {
+            const int ix = px + 2 * (4 * X0 + (n & 3)) + dx, iy = py + 2 * (4 * NCB * Y0 + (n >> 2)) + dy;
             if (((tmask >> n) & 1) && ix >= 0 && iy >= 0 && ix < N && iy < N) smask |= 1u << n;
           }
           if (!smask) continue;
@@ -123,16 +167,16 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
                                : ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
           __syncthreads();
           const T2* g = table + (int64_t)key * a.nG;
-          for (int e = tid; e < a.nG; e += 256) sG[e] = g[e];
-          for (int e = tid; e < 16 * a.nR; e += 256) {
+          for (int e = tid; e < a.nG; e += 256) sG[a.gpad[e]] = g[e];
+          for (int e = tid; e < NT * a.nR; e += 256) {
             const int n = e / a.nR, kk = e - n * a.nR;
             T2 v;
             v.x = 0;
             v.y = 0;
             if ((smask >> n) & 1) {
-              const int ix = px + 2 * (4 * X0 + (n & 3)) + dx, iy = py + 2 * (4 * Y0 + (n >> 2)) + dy;
+              const int ix = px + 2 * (4 * X0 + (n & 3)) + dx, iy = py + 2 * (4 * NCB * Y0 + (n >> 2)) + dy;
               const int64_t sb = ((int64_t)ix * N + iy) * N + (iz + dz);
-              const double s = (mirror && ((sMi[kk] >> 16) & 1)) ? -1.0 : 1.0;
+              const double s = (mirror && ((sCol[kk] >> 20) & 1)) ? -1.0 : 1.0;
               const double2 av = alpha[sb * a.nR + kk];
               v = Ty::cvt(make_double2(av.x * s, av.y * s));
             }
@@ -141,38 +185,48 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
           __syncthreads();
           for (int kb = 0; kb < a.nKB; ++kb) {
             const int kp = 4 * kb + krow;
-            const T2 bv = sA[col * a.nRs + kp];
-            const int mp = sMi[kp];
+            const int ci = sCol[kp];
+            const bool cvalid = (ci >> 21) & 1;
+            const int co = ci & 0xFFFFF;
+            const T2 bv0 = sA[col * a.nRs + kp];
+            const T2 bv1 = NCB == 2 ? sA[(16 + col) * a.nRs + kp] : bv0;
+            T2 gv[TW];
 #pragma unroll
-            for (int j = 0; j < RB; ++j) {
-              if (w + 4 * j < a.nRB) {
-                T2 gv;
-                gv.x = 0;
-                gv.y = 0;
-                if (rowmi[j] >= 0 && mp >= 0) {
-                  const int gg = rowmi[j] + mp;
-                  gv = sG[g_index(gg & 255, (gg >> 8) & 255, gg >> 16)];
-                }
-                accR[j] = Ty::mfma(gv.x, bv.x, accR[j]);
-                accR[j] = Ty::mfma(-gv.y, bv.y, accR[j]);
-                accI[j] = Ty::mfma(gv.x, bv.y, accI[j]);
-                accI[j] = Ty::mfma(gv.y, bv.x, accI[j]);
-              }
+            for (int j = 0; j < TW; ++j) {
+              gv[j].x = 0;
+              gv[j].y = 0;
+              if (rowo[j] >= 0 && cvalid) gv[j] = sG[rowo[j] + co];
             }
+            // independent MFMAs between the two updates of each accumulator
+#pragma unroll
+            for (int j = 0; j < TW; ++j)
+              if (w + 4 * j < ntile) {
+                const T2 b = tcb[j] ? bv1 : bv0;
+                accR[j] = Ty::mfma(gv[j].x, b.x, accR[j]);
+                accI[j] = Ty::mfma(gv[j].x, b.y, accI[j]);
+              }
+#pragma unroll
+            for (int j = 0; j < TW; ++j)
+              if (w + 4 * j < ntile) {
+                const T2 b = tcb[j] ? bv1 : bv0;
+                accR[j] = Ty::mfma(-gv[j].y, b.y, accR[j]);
+                accI[j] = Ty::mfma(gv[j].y, b.x, accI[j]);
+              }
           }
         }
       }
     }
   }
   // epilogue: result rows per the precision's MFMA layout, columns = targets
-  double2* beta = a.b + (int64_t)r * a.rhs_stride;
+  double2* beta = L.b + (int64_t)r * L.rhs_stride;
 #pragma unroll
-  for (int j = 0; j < RB; ++j) {
-    const int rb = w + 4 * j;
-    if (rb >= a.nRB) continue;
-    const int n = col;
+  for (int j = 0; j < TW; ++j) {
+    const int id = w + 4 * j;
+    if (id >= ntile) continue;
+    const int rb = id % a.nRB, cb = id / a.nRB;
+    const int n = 16 * cb + col;
     if (!((tmask >> n) & 1)) continue;
-    const int ix = px + 2 * (4 * X0 + (n & 3)), iy = py + 2 * (4 * Y0 + (n >> 2));
+    const int ix = px + 2 * (4 * X0 + (n & 3)), iy = py + 2 * (4 * NCB * Y0 + (n >> 2));
     const int64_t tb = ((int64_t)ix * N + iy) * N + iz;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -182,19 +236,36 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   }
 }
 
-template <typename T>
-static hipError_t launch_t(const M2LArgs& a, int nrhs, hipStream_t s) {
+template <typename T, int NCB>
+static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
   typedef typename M2LTypes<T>::T2 T2;
-  size_t lds = (size_t)a.nG * sizeof(T2) + (size_t)16 * a.nRs * sizeof(T2) + (4 * (size_t)a.nKB + 4) * sizeof(int);
-  const int RB = (a.nRB + 3) / 4;
-  dim3 grid(8 * ((a.ntiles + 7) / 8), nrhs), block(256);
+  M2LArgs a = a0;
+  int total = 0;
+  for (int i = 0; i < a.nlev; ++i) {
+    M2LLevel& L = a.lev[i];
+    L.tiles_x = ((L.n / 2) + 3) / 4;
+    L.tiles_y = ((L.n / 2) + 4 * NCB - 1) / (4 * NCB);
+    L.ntiles = L.n * 4 * L.tiles_x * L.tiles_y;
+    a.tile_start[i] = total;
+    total += (i == a.nlev - 1) ? 8 * ((L.ntiles + 7) / 8) : L.ntiles;
+  }
+  a.tile_start[a.nlev] = total;
+  const size_t lds = (size_t)3 * a.P2 * a.P2 * sizeof(T2) + (size_t)16 * NCB * a.nRs * sizeof(T2) +
+                     4 * (size_t)a.nKB * sizeof(int);
+  const int TW = (a.nRB * NCB + 3) / 4;
+  dim3 grid(total, nrhs), block(256);
   void (*fn)(M2LArgs) = nullptr;
-  switch (RB) {
-    case 1: fn = k_m2l<T, 1>; break;
-    case 2: fn = k_m2l<T, 2>; break;
-    case 3: fn = k_m2l<T, 3>; break;
-    case 4: fn = k_m2l<T, 4>; break;
-    case 5: fn = k_m2l<T, 5>; break;
+  switch (TW) {
+    case 1: fn = k_m2l<T, 1, NCB>; break;
+    case 2: fn = k_m2l<T, 2, NCB>; break;
+    case 3: fn = k_m2l<T, 3, NCB>; break;
+    case 4: fn = k_m2l<T, 4, NCB>; break;
+    case 5: fn = k_m2l<T, 5, NCB>; break;
+    case 6: fn = k_m2l<T, 6, NCB>; break;
+    case 7: fn = k_m2l<T, 7, NCB>; break;
+    case 8: fn = k_m2l<T, 8, NCB>; break;
+    case 9: fn = k_m2l<T, 9, NCB>; break;
+    case 10: fn = k_m2l<T, 10, NCB>; break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -203,7 +274,19 @@ static hipError_t launch_t(const M2LArgs& a, int nrhs, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T>
+static hipError_t launch_t(const M2LArgs& a, int nrhs, hipStream_t s) {
+  typedef typename M2LTypes<T>::T2 T2;
+  // 32 targets per workgroup when the widest level is wide enough and two
+  // workgroups still fit in the LDS of a CU; 16 otherwise.
+  const size_t lds2 = (size_t)3 * a.P2 * a.P2 * sizeof(T2) + (size_t)32 * a.nRs * sizeof(T2);
+  const int tw2 = (a.nRB * 2 + 3) / 4;
+  if (a.lev[a.nlev - 1].n >= 16 && lds2 <= 78 * 1024 && tw2 <= 10) return launch_t2<T, 2>(a, nrhs, s);
+  return launch_t2<T, 1>(a, nrhs, s);
+}
+
 hipError_t launch_m2l(const M2LArgs& a, int nrhs, bool fp32, hipStream_t s) {
+  if (a.nlev < 1 || a.nlev > M2L_MAX_LEVELS) return hipErrorInvalidValue;
   return fp32 ? launch_t<float>(a, nrhs, s) : launch_t<double>(a, nrhs, s);
 }
 
