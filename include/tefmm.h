@@ -124,6 +124,24 @@ int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz_soa, int on_devi
  * (call hipStreamSynchronize to wait). */
 int tefmm_evaluate(tefmm_t h, const double* q, int n_rhs, double* phi, void* stream);
 
+/* Batched evaluation of n_geom handles, each with its own geometry, charges
+ * q[g] (n_rhs[g] vectors, layout as in tefmm_evaluate) and output phi[g].
+ * The handles' evaluation sequences are captured once into a HIP graph, one
+ * stream branch per geometry so that independent geometries run concurrently,
+ * and the graph is replayed by later calls with the same handles, pointers and
+ * n_rhs (a changed list, or a handle whose geometry or buffers changed since,
+ * triggers a new capture).  The graph reads q[g] at replay time.  The graph is
+ * owned by hs[0].  Returns after enqueueing on `stream`.  All handles must be
+ * distinct and ready; per-phase timings are not recorded for batched calls. */
+int tefmm_evaluate_batch(tefmm_t* hs, int n_geom, const double* const* q, const int* n_rhs,
+                         double* const* phi, void* stream);
+
+/* Autotuner: times the evaluation of the handle's own geometry (unit charges)
+ * for tree depths d-1, d, d+1 (d the current depth, clamped to [2, 7]) and for
+ * 16 or 32 target boxes per M2L workgroup, then rebuilds the handle with the
+ * fastest choice.  *depth_out / *ncb_out (may be NULL) receive it.  Synchronous. */
+int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_out);
+
 /* Statistics of the last set_particles / evaluate (timings need the stream
  * to have completed; this call synchronises it). */
 int tefmm_get_stats(tefmm_t h, tefmm_stats* st);

@@ -23,7 +23,7 @@ ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "PARTICLE_ON_INTERFACE", -3: "UNSUPPOR
 EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefmm_evaluate",
            "tefmm_get_stats", "tefmm_last_error", "tefmm_destroy", "tefmm_densities",
            "tefmm_dcim_family", "tefmm_taylor_coefficients", "tefmm_get_moments", "tefmm_get_tree",
-           "tefmm_selftest_mfma"]
+           "tefmm_selftest_mfma", "tefmm_evaluate_batch", "tefmm_autotune"]
 
 
 class TefmmError(RuntimeError):
@@ -84,6 +84,9 @@ def lib():
         L.tefmm_get_moments.argtypes = [vp, i32, i32, vp, i64]
         L.tefmm_get_tree.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, ctypes.POINTER(dbl)]
         L.tefmm_selftest_mfma.argtypes = []
+        L.tefmm_evaluate_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                           ctypes.POINTER(vp), vp]
+        L.tefmm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         _lib = L
     return _lib
 
@@ -171,6 +174,12 @@ class TEFMM:
                                     _stream_ptr(stream)), self.h)
         return out.reshape(-1) if squeeze else out
 
+    def autotune(self, stream=None):
+        """Pick tree depth and M2L tile width by timing; returns (depth, targets per workgroup / 16)."""
+        d, c = ctypes.c_int(), ctypes.c_int()
+        _check(lib().tefmm_autotune(self.h, _stream_ptr(stream), ctypes.byref(d), ctypes.byref(c)), self.h)
+        return d.value, c.value
+
     def stats(self) -> dict:
         s = StatsC()
         _check(lib().tefmm_get_stats(self.h, ctypes.byref(s)), self.h)
@@ -193,6 +202,30 @@ class TEFMM:
         out = np.zeros(nb * nC, np.complex128)
         _check(lib().tefmm_get_moments(self.h, g, level, out.ctypes.data_as(ctypes.c_void_p), 2 * nb * nC), self.h)
         return out.reshape(nb, nC)
+
+
+def evaluate_batch(handles, qs, outs=None, stream=None):
+    """Evaluate several TEFMM handles in one graph launch.  qs: list of torch complex128 tensors
+    (N_g,) or (R_g, N_g) on the GPU.  Returns the list of outputs (same shapes)."""
+    import torch
+    n = len(handles)
+    qs2, outs2, shapes = [], [], []
+    for i, (f, q) in enumerate(zip(handles, qs)):
+        q = q.to(torch.complex128)
+        shapes.append(q.shape)
+        q2 = (q.reshape(1, -1) if q.dim() == 1 else q).contiguous()
+        if q2.shape[1] != f.n:
+            raise ValueError(f"geometry {i}: charge length does not match")
+        qs2.append(q2)
+        outs2.append(torch.empty_like(q2) if outs is None else outs[i].reshape(q2.shape))
+    H = (ctypes.c_void_p * n)(*[f.h.value for f in handles])
+    Q = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs2])
+    P = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs2])
+    R = (ctypes.c_int * n)(*[q.shape[0] for q in qs2])
+    _check(lib().tefmm_evaluate_batch(H, n, Q, R, P, _stream_ptr(stream)), handles[0].h)
+    # keep the inputs alive until the caller synchronises (the graph reads them)
+    evaluate_batch._keep = (qs2, outs2)
+    return [o.reshape(s) for o, s in zip(outs2, shapes)]
 
 
 def densities(k, d, lp, krho):

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <hipcub/hipcub.hpp>
@@ -84,7 +85,27 @@ struct tefmm_ctx {
   tefmm_stats st;
   std::vector<hipEvent_t> ev;
   int64_t p2p_pairs = 0, m2l_pairs = 0;
+  // copy of the caller's positions (SoA), kept for re-building the tree (autotuner)
+  double* d_xyz_user = nullptr;
+  int m2l_ncb = 0;  // M2L tile width override (0 = automatic)
+  uint64_t gen = 0; // changes whenever device buffers are (re)allocated
+  // graph of the last batched evaluation
+  struct Batch {
+    std::vector<tefmm_ctx*> hs;
+    std::vector<uint64_t> gens;
+    std::vector<const double*> q;
+    std::vector<double*> phi;
+    std::vector<int> nrhs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t origin = nullptr;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;
+  } batch;
 };
+
+static void batch_destroy(tefmm_ctx::Batch& b);
+static std::atomic<uint64_t> g_generation{1};
 
 static int fail(tefmm_t h, int code, const std::string& msg) {
   if (h) h->err = msg;
@@ -241,6 +262,8 @@ extern "C" void tefmm_destroy(tefmm_t h) {
   dfree(h->d_scale);
   dfree(h->d_invfact);
   for (auto& e : h->ev) (void)hipEventDestroy(e);
+  batch_destroy(h->batch);
+  dfree(h->d_xyz_user);
   delete h;
 }
 
@@ -380,6 +403,11 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     HIPCHK(h, hipMalloc(&d_in, sizeof(double) * 3 * n));
     HIPCHK(h, hipMemcpyAsync(d_in, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
     src = d_in;
+  }
+  if (src != h->d_xyz_user) {
+    dfree(h->d_xyz_user);
+    HIPCHK(h, hipMalloc(&h->d_xyz_user, sizeof(double) * 3 * n));
+    HIPCHK(h, hipMemcpyAsync(h->d_xyz_user, src, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
   }
   double* d_if = nullptr;
   HIPCHK(h, hipMalloc(&d_if, sizeof(double) * std::max(L, 1)));
@@ -591,6 +619,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   h->st.p2p_pairs = h->p2p_pairs;
   h->st.m2l_pairs = h->m2l_pairs;
   h->ready = true;
+  h->gen = g_generation++;
   return TEFMM_OK;
 }
 
@@ -622,25 +651,33 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
     }
   }
   h->nrhs_alloc = nrhs;
+  h->gen = g_generation++;
   return TEFMM_OK;
 }
 
-extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, void* stream) {
+static int check_eval_args(tefmm_t h, const double* q, int nrhs, double* phi) {
   if (!h) return TEFMM_ERR_INVALID_ARG;
   if (!h->ready) return fail(h, TEFMM_ERR_STATE, "set_particles has not succeeded");
   if (!q || !phi || nrhs < 1 || nrhs > h->opt.n_rhs_max) return fail(h, TEFMM_ERR_INVALID_ARG, "bad q/phi/n_rhs");
-  hipStream_t s = (hipStream_t)stream;
-  int rc = ensure_rhs(h, nrhs);
-  if (rc != TEFMM_OK) return rc;
-  if (h->ev.empty()) {
+  return TEFMM_OK;
+}
+
+// Enqueue one evaluation on stream s (buffers must already be sized for nrhs).
+// With timed = false no events are recorded (graph capture).
+static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, hipStream_t s, bool timed) {
+  if (timed && h->ev.empty()) {
     h->ev.resize(8);
     for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
   }
+#define EVREC(i)                                   \
+  do {                                             \
+    if (timed) HIPCHK(h, hipEventRecord(h->ev[i], s)); \
+  } while (0)
   const int64_t n = h->n;
   const bool fp32 = h->opt.precision == TEFMM_MIXED_FP32;
   double m2l_flops = 0;
   int m2l_launches = 0;
-  HIPCHK(h, hipEventRecord(h->ev[0], s));
+  EVREC(0);
   hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, (const double2*)q,
                      h->d_perm, n, h->d_q);
   HIPCHK(h, hipGetLastError());
@@ -659,7 +696,7 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
       hipLaunchKernelGGL(k_p2m, dim3((unsigned)g.nbox[H], nrhs), dim3(64), lds, s, a);
       HIPCHK(h, hipGetLastError());
     }
-    HIPCHK(h, hipEventRecord(h->ev[1], s));
+    EVREC(1);
     for (int lev = H - 1; lev >= 2; --lev) {
       PassArgs a = pa;
       a.nbox_dim = 1 << lev, a.alpha = g.alpha[lev], a.rhs_stride = g.nbox[lev] * h->nC;
@@ -679,7 +716,7 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
       hipLaunchKernelGGL(k_reduce, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, ra);
       HIPCHK(h, hipGetLastError());
     }
-    HIPCHK(h, hipEventRecord(h->ev[2], s));
+    EVREC(2);
     {
       M2LArgs m;
       std::memset(&m, 0, sizeof(m));
@@ -693,9 +730,10 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
         L.a = g.ared[lev], L.b = g.bred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
         L.Tfd = g.Tfd[lev], L.TS = g.TS[lev], L.Tfd32 = g.Tfd32[lev], L.TS32 = g.TS32[lev];
       }
+      m.ncb = h->m2l_ncb;
       HIPCHK(h, launch_m2l(m, nrhs, fp32, s));
     }
-    HIPCHK(h, hipEventRecord(h->ev[3], s));
+    EVREC(3);
     {
       const double per = 8.0 * (double)h->nR * (double)h->nR;
       for (int lev = 2; lev <= H; ++lev) {
@@ -724,7 +762,7 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
         HIPCHK(h, hipGetLastError());
       }
     }
-    HIPCHK(h, hipEventRecord(h->ev[4], s));
+    EVREC(4);
     {
       PassArgs a = pa;
       a.nbox_dim = 1 << H, a.h = g.side / (1 << H), a.beta = g.beta[H], a.rhs_stride = g.nbox[H] * h->nC;
@@ -732,7 +770,7 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
       hipLaunchKernelGGL(k_l2p, dim3((unsigned)g.nbox[H], nrhs), dim3(64), lds, s, a);
       HIPCHK(h, hipGetLastError());
     }
-    HIPCHK(h, hipEventRecord(h->ev[5], s));
+    EVREC(5);
     {
       PassArgs a = pa;
       a.nbox_dim = 1 << H;
@@ -742,7 +780,7 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
         hipLaunchKernelGGL(k_p2p<double>, dim3((unsigned)g.nbox[H], nrhs), dim3(64), 0, s, a);
       HIPCHK(h, hipGetLastError());
     }
-    HIPCHK(h, hipEventRecord(h->ev[6], s));
+    EVREC(6);
     {
       double sr = 1.0 / (4 * PI), si = 0.0;
       if (h->opt.normalization == TEFMM_NORM_PAPER) {  // divide by i k
@@ -754,11 +792,156 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
       HIPCHK(h, hipGetLastError());
     }
   }
-  HIPCHK(h, hipEventRecord(h->ev[7], s));
+  EVREC(7);
+#undef EVREC
   h->st.m2l_flops = m2l_flops;
   h->st.m2l_launches = m2l_launches;
   h->st.n_rhs = nrhs;
   return TEFMM_OK;
+}
+
+extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, void* stream) {
+  int rc = check_eval_args(h, q, nrhs, phi);
+  if (rc != TEFMM_OK) return rc;
+  rc = ensure_rhs(h, nrhs);
+  if (rc != TEFMM_OK) return rc;
+  return enqueue_evaluate(h, q, nrhs, phi, (hipStream_t)stream, true);
+}
+
+static void batch_clear(tefmm_ctx::Batch& b) {
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.graph) (void)hipGraphDestroy(b.graph);
+  b.exec = nullptr, b.graph = nullptr;
+  b.hs.clear(), b.gens.clear(), b.q.clear(), b.phi.clear(), b.nrhs.clear();
+}
+
+static void batch_destroy(tefmm_ctx::Batch& b) {
+  batch_clear(b);
+  for (auto& e : b.ev) (void)hipEventDestroy(e);
+  for (auto& st : b.side) (void)hipStreamDestroy(st);
+  if (b.origin) (void)hipStreamDestroy(b.origin);
+  b.ev.clear(), b.side.clear(), b.origin = nullptr;
+}
+
+// Batched evaluation (E2): the geometries' evaluation sequences are captured once
+// into a HIP graph, each on its own stream branch so that independent geometries
+// run concurrently, and the graph is replayed while the argument lists match.
+extern "C" int tefmm_evaluate_batch(tefmm_t* hs, int n_geom, const double* const* q, const int* nrhs,
+                                    double* const* phi, void* stream) {
+  if (!hs || n_geom < 1 || !q || !nrhs || !phi || !hs[0]) return TEFMM_ERR_INVALID_ARG;
+  tefmm_t h0 = hs[0];
+  for (int g = 0; g < n_geom; ++g) {
+    if (!hs[g]) return fail(h0, TEFMM_ERR_INVALID_ARG, "null handle in batch");
+    for (int g2 = 0; g2 < g; ++g2)
+      if (hs[g2] == hs[g]) return fail(h0, TEFMM_ERR_INVALID_ARG, "a handle appears twice in the batch");
+    int rc = check_eval_args(hs[g], q[g], nrhs[g], phi[g]);
+    if (rc != TEFMM_OK) return fail(h0, rc, "geometry " + std::to_string(g) + ": " + hs[g]->err);
+    rc = ensure_rhs(hs[g], nrhs[g]);
+    if (rc != TEFMM_OK) return fail(h0, rc, "geometry " + std::to_string(g) + ": " + hs[g]->err);
+  }
+  tefmm_ctx::Batch& b = h0->batch;
+  bool same = b.exec && (int)b.hs.size() == n_geom;
+  for (int g = 0; same && g < n_geom; ++g)
+    same = b.hs[g] == hs[g] && b.gens[g] == hs[g]->gen && b.q[g] == q[g] && b.phi[g] == phi[g] &&
+           b.nrhs[g] == nrhs[g];
+  if (!same) {
+    batch_clear(b);
+    if (!b.origin) HIPCHK(h0, hipStreamCreateWithFlags(&b.origin, hipStreamNonBlocking));
+    while ((int)b.side.size() < n_geom) {
+      hipStream_t st;
+      HIPCHK(h0, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      b.side.push_back(st);
+    }
+    while ((int)b.ev.size() < n_geom + 1) {
+      hipEvent_t e;
+      HIPCHK(h0, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b.ev.push_back(e);
+    }
+    HIPCHK(h0, hipStreamBeginCapture(b.origin, hipStreamCaptureModeThreadLocal));
+    int rc = TEFMM_OK;
+    hipError_t e = hipEventRecord(b.ev[n_geom], b.origin);
+    for (int g = 0; g < n_geom && rc == TEFMM_OK && e == hipSuccess; ++g) {
+      e = hipStreamWaitEvent(b.side[g], b.ev[n_geom], 0);
+      if (e != hipSuccess) break;
+      rc = enqueue_evaluate(hs[g], q[g], nrhs[g], phi[g], b.side[g], false);
+      if (rc != TEFMM_OK) break;
+      e = hipEventRecord(b.ev[g], b.side[g]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b.origin, b.ev[g], 0);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b.origin, &graph);
+    if (rc != TEFMM_OK || e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc != TEFMM_OK) return fail(h0, rc, "capture: " + std::string(h0->err));
+      return fail(h0, TEFMM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b.graph = graph;
+    HIPCHK(h0, hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+    b.hs.assign(hs, hs + n_geom);
+    b.gens.clear();
+    for (int g = 0; g < n_geom; ++g) b.gens.push_back(hs[g]->gen);
+    b.q.assign(q, q + n_geom);
+    b.phi.assign(phi, phi + n_geom);
+    b.nrhs.assign(nrhs, nrhs + n_geom);
+  }
+  HIPCHK(h0, hipGraphLaunch(b.exec, (hipStream_t)stream));
+  return TEFMM_OK;
+}
+
+__global__ static void k_fill_ones(double2* q, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) q[i] = make_double2(1.0, 0.0);
+}
+
+// Autotuner (E2): times the evaluation for tree depths d-1, d, d+1 and both M2L
+// tile widths on the handle's own geometry and keeps the fastest.
+extern "C" int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_out) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  if (!h->ready || !h->d_xyz_user) return fail(h, TEFMM_ERR_STATE, "set_particles has not succeeded");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = h->n;
+  const int d0 = h->groups[0].depth;
+  const int depth_opt = h->opt.depth;
+  double2 *q1 = nullptr, *phi1 = nullptr;
+  HIPCHK(h, hipMalloc(&q1, sizeof(double2) * n));
+  HIPCHK(h, hipMalloc(&phi1, sizeof(double2) * n));
+  hipLaunchKernelGGL(k_fill_ones, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, q1, n);
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  float best = 1e30f;
+  int bd = d0, bn = 0, rc = TEFMM_OK;
+  for (int cand = std::max(2, d0 - 1); cand <= std::min(7, d0 + 1) && rc == TEFMM_OK; ++cand) {
+    h->opt.depth = cand;
+    rc = tefmm_set_particles(h, n, h->d_xyz_user, 1, stream);
+    if (rc == TEFMM_OK) rc = ensure_rhs(h, 1);
+    for (int ncb = 1; ncb <= 2 && rc == TEFMM_OK; ++ncb) {
+      h->m2l_ncb = ncb;
+      rc = enqueue_evaluate(h, (const double*)q1, 1, (double*)phi1, s, false);
+      if (rc != TEFMM_OK) break;
+      (void)hipEventRecord(e0, s);
+      for (int it = 0; it < 2 && rc == TEFMM_OK; ++it) rc = enqueue_evaluate(h, (const double*)q1, 1, (double*)phi1, s, false);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rc == TEFMM_OK && ms < best) best = ms, bd = cand, bn = ncb;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  dfree(q1);
+  dfree(phi1);
+  if (rc != TEFMM_OK) {
+    h->opt.depth = depth_opt;
+    return rc;
+  }
+  h->opt.depth = bd;
+  rc = tefmm_set_particles(h, n, h->d_xyz_user, 1, stream);
+  h->m2l_ncb = bn;
+  if (depth_out) *depth_out = bd;
+  if (ncb_out) *ncb_out = bn;
+  return rc;
 }
 
 extern "C" int tefmm_get_stats(tefmm_t h, tefmm_stats* st) {

@@ -92,6 +92,7 @@ struct M2LArgs {
   int nR, nRs, nKB, nRB; // reduced coefficients, LDS row stride, K blocks of 4, row blocks of 16
   int nG, p, P2;         // compact table size, order, 2p + 1
   int nlev;              // levels in this launch; the last one is the widest
+  int ncb;               // targets per workgroup / 16: 1 or 2, 0 = automatic
   int tile_start[M2L_MAX_LEVELS + 1];
   M2LLevel lev[M2L_MAX_LEVELS];
   const int* rmi;        // [nR] packed reduced multi-indices

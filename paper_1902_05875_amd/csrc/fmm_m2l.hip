@@ -281,6 +281,9 @@ static hipError_t launch_t(const M2LArgs& a, int nrhs, hipStream_t s) {
   // workgroups still fit in the LDS of a CU; 16 otherwise.
   const size_t lds2 = (size_t)3 * a.P2 * a.P2 * sizeof(T2) + (size_t)32 * a.nRs * sizeof(T2);
   const int tw2 = (a.nRB * 2 + 3) / 4;
+  const bool fit2 = lds2 <= 150 * 1024 && tw2 <= 10;
+  if (a.ncb == 2 && fit2) return launch_t2<T, 2>(a, nrhs, s);
+  if (a.ncb == 1) return launch_t2<T, 1>(a, nrhs, s);
   if (a.lev[a.nlev - 1].n >= 16 && lds2 <= 78 * 1024 && tw2 <= 10) return launch_t2<T, 2>(a, nrhs, s);
   return launch_t2<T, 1>(a, nrhs, s);
 }
