@@ -65,8 +65,12 @@ typedef struct {
  * translation operators, Sec. 3.1).  depth: uniform octree depth per layer
  * (0 = choose the smallest depth with mean occupancy <= max_leaf).
  * DCIM parameters (Sec. 3.3): dcim_T1 and dcim_samples per level, relative
- * singular-value cut dcim_svd_tol.  interface_eps: minimum distance of a
- * particle from an interface (the Sommerfeld integrals diverge on them). */
+ * singular-value cut dcim_svd_tol; dcim_T1_cross is the length of the second
+ * sampling path for the cross-layer fits (their spectral functions have
+ * branch points of the other layers near the path, and a longer second path
+ * moves the misfit away from the spatial range used).  interface_eps: minimum
+ * distance of a particle from an interface (the Sommerfeld integrals diverge
+ * on them). */
 typedef struct {
   int p;
   int depth;
@@ -78,6 +82,7 @@ typedef struct {
   double dcim_svd_tol;
   double interface_eps;
   int n_rhs_max;
+  double dcim_T1_cross;
 } tefmm_options;
 
 /* Timings (ms, measured with HIP events on the evaluate stream) and counters. */
@@ -93,11 +98,17 @@ typedef struct {
                             (target box, source box, family) contraction, times n_rhs */
   int m2l_launches;      /* M2L kernel launches of the last evaluate */
   int n_rhs;             /* charge vectors of the last evaluate */
+  int64_t cross_pairs;   /* cross-layer (target box, source box) translations per charge vector */
+  int64_t cross_pairs_forced; /* of those, leaf pairs that fail the acceptance test sqrt(3) h <= 0.6 D
+                                 (translated anyway: less accurate; zero with the automatic depth
+                                 unless the depth limit 7 is reached) */
+  int n_cross_fits;      /* cross-layer complex-image fits of the geometry */
+  double cross_fit_err;  /* their largest relative misfit on the sampling paths */
 } tefmm_stats;
 
 /* Fill an options struct with the defaults (p = 8, depth auto, max_leaf 64,
  * FP64, physical normalisation, T1 = 10, 101 samples, tol 1e-12,
- * interface_eps 1e-9, n_rhs_max 64). */
+ * interface_eps 1e-9, n_rhs_max 64, T1 = 30 for the cross-layer fits). */
 void tefmm_default_options(tefmm_options* opt);
 
 /* Create a handle for a medium: validates the medium and options and uploads
@@ -113,8 +124,11 @@ int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefmm_options* 
  * (Sec. 3.3, two-level GPOF) on the host and generates the derivative
  * tables on the GPU.  stream: hipStream_t (NULL = default stream).  Fails
  * with TEFMM_ERR_PARTICLE_ON_INTERFACE if a particle lies within
- * interface_eps of an interface, TEFMM_ERR_UNSUPPORTED for particles in more
- * than one layer when the cross-layer path is not available. */
+ * interface_eps of an interface.  With particles in several layers all layer
+ * trees share one x-y box grid, one box side and one depth (the common grid of
+ * the cross-layer translations, Algorithm 2); each cube is placed inside its
+ * layer when the layer is thick enough, and TEFMM_ERR_UNSUPPORTED is returned
+ * when a box holding particles would have its centre outside its layer. */
 int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz_soa, int on_device, void* stream);
 
 /* Evaluate (1) for n_rhs charge vectors.  q: device, complex128 interleaved
@@ -176,6 +190,18 @@ int tefmm_densities(const tefmm_medium* medium, int lp, int n, const double* krh
 int tefmm_dcim_family(const tefmm_medium* medium, const tefmm_options* opt, int l, int family,
                       double z_lo, double z_hi, int cap, int* m, double* amp, double* depth,
                       double* fit_err);
+
+/* Cross-layer complex images (Sec. 3.3: one fit per source height and z'
+ * derivative order): target layer l, source layer lp != l, target-side wave
+ * a (0 = up-going, 1 = down-going), source height zs, derivative order k3p;
+ * z_lo, z_hi: the target particles' height range.  The kernel
+ *   d^{k3p}/dz'^{k3p} G^{(a)}_{l,lp}(r, r') / k3p!  at z' = zs
+ * equals sum_j A_j exp(i k_l R_j) / (4 pi R_j), R_j = sqrt(rho^2 + (Z - depth_j)^2),
+ * Z = z - d_l (a = 0) or d_{l-1} - z (a = 1).  Output as for tefmm_dcim_family.
+ * Pure host call. */
+int tefmm_dcim_cross(const tefmm_medium* medium, const tefmm_options* opt, int l, int lp, int a, double zs,
+                     int k3p, double z_lo, double z_hi, int cap, int* m, double* amp, double* depth,
+                     double* fit_err);
 
 /* Scaled Taylor coefficients h^{|g|} D^g f / g! of f = exp(i k R)/R at n
  * points (x, y, zeta) with complex zeta (device arrays x, y: n doubles;

@@ -23,7 +23,7 @@ ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "PARTICLE_ON_INTERFACE", -3: "UNSUPPOR
 EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefmm_evaluate",
            "tefmm_get_stats", "tefmm_last_error", "tefmm_destroy", "tefmm_densities",
            "tefmm_dcim_family", "tefmm_taylor_coefficients", "tefmm_get_moments", "tefmm_get_tree",
-           "tefmm_selftest_mfma", "tefmm_evaluate_batch", "tefmm_autotune"]
+           "tefmm_selftest_mfma", "tefmm_evaluate_batch", "tefmm_autotune", "tefmm_dcim_cross"]
 
 
 class TefmmError(RuntimeError):
@@ -41,7 +41,7 @@ class OptionsC(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("depth", ctypes.c_int), ("max_leaf", ctypes.c_int),
                 ("precision", ctypes.c_int), ("normalization", ctypes.c_int), ("dcim_T1", ctypes.c_double),
                 ("dcim_samples", ctypes.c_int), ("dcim_svd_tol", ctypes.c_double),
-                ("interface_eps", ctypes.c_double), ("n_rhs_max", ctypes.c_int)]
+                ("interface_eps", ctypes.c_double), ("n_rhs_max", ctypes.c_int), ("dcim_T1_cross", ctypes.c_double)]
 
 
 class StatsC(ctypes.Structure):
@@ -50,7 +50,9 @@ class StatsC(ctypes.Structure):
                  "t_l2l_ms", "t_l2p_ms", "t_p2p_ms", "t_total_ms"]] + [
         ("m2l_pairs", ctypes.c_int64), ("p2p_pairs", ctypes.c_int64), ("n_images", ctypes.c_int * 8),
         ("dcim_fit_err", ctypes.c_double * 8), ("depth", ctypes.c_int * 4), ("n_families", ctypes.c_int),
-        ("m2l_flops", ctypes.c_double), ("m2l_launches", ctypes.c_int), ("n_rhs", ctypes.c_int)]
+        ("m2l_flops", ctypes.c_double), ("m2l_launches", ctypes.c_int), ("n_rhs", ctypes.c_int),
+        ("cross_pairs", ctypes.c_int64), ("cross_pairs_forced", ctypes.c_int64), ("n_cross_fits", ctypes.c_int),
+        ("cross_fit_err", ctypes.c_double)]
 
 
 _lib = None
@@ -87,6 +89,8 @@ def lib():
         L.tefmm_evaluate_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i32),
                                            ctypes.POINTER(vp), vp]
         L.tefmm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.tefmm_dcim_cross.argtypes = [ctypes.POINTER(MediumC), ctypes.POINTER(OptionsC), i32, i32, i32, dbl, i32,
+                                       dbl, dbl, i32, ctypes.POINTER(i32), vp, vp, ctypes.POINTER(dbl)]
         _lib = L
     return _lib
 
@@ -250,6 +254,22 @@ def dcim_family(k, d, layer, family, z_lo, z_hi, **options):
     _check(lib().tefmm_dcim_family(ctypes.byref(med), ctypes.byref(opt), layer, family, float(z_lo), float(z_hi),
                                    cap, ctypes.byref(m), amp.ctypes.data_as(ctypes.c_void_p),
                                    dep.ctypes.data_as(ctypes.c_void_p), ctypes.byref(fe)))
+    return amp[: m.value].copy(), dep[: m.value].copy(), fe.value
+
+
+def dcim_cross(k, d, layer, src_layer, wave, zs, k3p, z_lo, z_hi, **options):
+    """Cross-layer complex images (A_j, depth_j) for one source height and z' derivative order."""
+    med = _medium(k, d)
+    opt = default_options(**options)
+    cap = 256
+    amp = np.zeros(cap, np.complex128)
+    dep = np.zeros(cap, np.complex128)
+    m = ctypes.c_int()
+    fe = ctypes.c_double()
+    _check(lib().tefmm_dcim_cross(ctypes.byref(med), ctypes.byref(opt), layer, src_layer, wave, float(zs), k3p,
+                                  float(z_lo), float(z_hi), cap, ctypes.byref(m),
+                                  amp.ctypes.data_as(ctypes.c_void_p), dep.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(fe)))
     return amp[: m.value].copy(), dep[: m.value].copy(), fe.value
 
 

@@ -43,6 +43,7 @@ extern "C" void tefmm_default_options(tefmm_options* o) {
   o->dcim_svd_tol = 1e-12;
   o->interface_eps = 1e-9;
   o->n_rhs_max = 64;
+  o->dcim_T1_cross = 30.0;
 }
 
 extern "C" int tefmm_densities(const tefmm_medium* medium, int lp, int n, const double* krho,
@@ -81,6 +82,34 @@ extern "C" int tefmm_dcim_family(const tefmm_medium* medium, const tefmm_options
   double fe = 0;
   if (!tefmm::same_layer_family(med, l, family, z_lo, z_hi, o.dcim_T1, o.dcim_samples,
                                 o.dcim_svd_tol, A, Z, fe, err))
+    return TEFMM_ERR_DCIM_FIT;
+  *m = (int)A.size();
+  if (fit_err) *fit_err = fe;
+  if ((int)A.size() > cap) return TEFMM_ERR_INVALID_ARG;
+  for (size_t i = 0; i < A.size(); ++i) {
+    amp[2 * i] = A[i].real(), amp[2 * i + 1] = A[i].imag();
+    depth[2 * i] = Z[i].real(), depth[2 * i + 1] = Z[i].imag();
+  }
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_dcim_cross(const tefmm_medium* medium, const tefmm_options* opt, int l, int lp, int a,
+                                double zs, int k3p, double z_lo, double z_hi, int cap, int* m, double* amp,
+                                double* depth, double* fit_err) {
+  tefmm::MediumDesc med;
+  std::string err;
+  if (!tefmm::medium_from_desc(medium, med, err)) return TEFMM_ERR_INVALID_ARG;
+  tefmm_options o;
+  if (opt)
+    o = *opt;
+  else
+    tefmm_default_options(&o);
+  if (l < 0 || l > med.L || lp < 0 || lp > med.L || l == lp || a < 0 || a > 1 || k3p < 0 || k3p > 32 || !m)
+    return TEFMM_ERR_INVALID_ARG;
+  std::vector<cplx> A, Z;
+  double fe = 0;
+  if (!tefmm::cross_layer_fit(med, l, lp, a, zs, k3p, z_lo, z_hi, o.dcim_T1_cross, o.dcim_samples, o.dcim_svd_tol, A, Z,
+                              fe, err))
     return TEFMM_ERR_DCIM_FIT;
   *m = (int)A.size();
   if (fit_err) *fit_err = fe;

@@ -10,11 +10,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
 #include <hipcub/hipcub.hpp>
+#include <map>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/tefmm.h"
@@ -46,6 +50,19 @@ struct Group {
   std::vector<float2*> Tfd32, TS32;
   std::vector<int64_t> nbox;          // boxes at level
   std::vector<int64_t> far_pairs, near_pairs;  // per level from 2: interaction-list / neighbour pairs
+  double fit_zlo = 0, fit_zhi = 0;              // height range of the complex-image fits
+  // cross-layer (this group as target): z-reduced moments/locals and per-level lists and tables
+  std::vector<double2*> azred, bzred;
+  std::vector<int*> xlist_start;
+  std::vector<CrossEntry*> xlist;
+  std::vector<int> xkeys;                       // keys per level
+  std::vector<double2*> XT0, XT1;
+  std::vector<float2*> XT032, XT132;
+  double cross_flops_per_rhs = 0;
+  int64_t cross_pairs = 0, cross_forced = 0;  // forced: leaf pairs translated below the acceptance test
+  int n_cross_fits = 0;
+  double cross_fit_err = 0;
+  bool has_cross = false;
 };
 
 template <class T>
@@ -66,6 +83,10 @@ struct tefmm_ctx {
   int* d_rmi = nullptr;     // [nR] reduced multi-indices (packed)
   int* d_rfull = nullptr;   // [nR] graded index of each reduced entry
   int* d_gpad = nullptr;    // [nG] padded LDS position of each compact table entry
+  int* d_rzmi = nullptr;    // [nR] z-reduced multi-indices (packed)
+  int* d_rzfull = nullptr;  // [nR] graded index of each z-reduced entry
+  int* d_gpadz = nullptr;   // [nG] padded LDS position for the cross tables (-1: unused)
+  unsigned char* d_g1 = nullptr;
   short* d_nbr = nullptr;   // [nG][6] compact-table recurrence neighbours
   unsigned char* d_g3 = nullptr;
   double *d_fact = nullptr, *d_scale = nullptr, *d_invfact = nullptr;
@@ -128,6 +149,14 @@ static void free_geometry(tefmm_t h) {
     for (auto& p : g.beta) dfree(p);
     for (auto& p : g.ared) dfree(p);
     for (auto& p : g.bred) dfree(p);
+    for (auto& p : g.azred) dfree(p);
+    for (auto& p : g.bzred) dfree(p);
+    for (auto& p : g.xlist_start) dfree(p);
+    for (auto& p : g.xlist) dfree(p);
+    for (auto& p : g.XT0) dfree(p);
+    for (auto& p : g.XT1) dfree(p);
+    for (auto& p : g.XT032) dfree(p);
+    for (auto& p : g.XT132) dfree(p);
     for (auto& p : g.Tfd) dfree(p);
     for (auto& p : g.TS) dfree(p);
     for (auto& p : g.Tfd32) dfree(p);
@@ -175,9 +204,18 @@ static int build_constant_tables(tefmm_t h) {
         rfull.push_back(mi_index(k1, k2, k3));
       }
   if ((int)rmi.size() != nR) return fail(h, TEFMM_ERR_STATE, "reduced index set size");
+  std::vector<int> rzmi, rzfull;
+  for (int k3 = 0; k3 <= std::min(1, p); ++k3)
+    for (int t = 0; t <= p - k3; ++t)
+      for (int k1 = t; k1 >= 0; --k1) {
+        const int k2 = t - k1;
+        rzmi.push_back(k1 | (k2 << 8) | (k3 << 16));
+        rzfull.push_back(mi_index(k1, k2, k3));
+      }
+  if ((int)rzmi.size() != nR) return fail(h, TEFMM_ERR_STATE, "z-reduced index set size");
   std::vector<short> nbr(6 * nG, -1);
-  std::vector<int> gpad(nG);
-  std::vector<unsigned char> g3(nG);
+  std::vector<int> gpad(nG), gpadz(nG, -1);
+  std::vector<unsigned char> g3(nG), g1v(nG);
   std::vector<double> fact(nG);
   int cnt = 0;
   for (int n = 0; n <= 2 * p; ++n)
@@ -187,6 +225,8 @@ static int build_constant_tables(tefmm_t h) {
         if (i != cnt++) return fail(h, TEFMM_ERR_STATE, "compact table order");
         g3[i] = (unsigned char)c;
         gpad[i] = (g1 * (2 * p + 1) + (b + c)) * (2 * p + 1) + c;
+        g1v[i] = (unsigned char)g1;
+        if (g1 <= 1) gpadz[i] = (g1 * (2 * p + 1) + (b + c)) * (2 * p + 1) + c;
         fact[i] = f(g1) * f(b) * f(c);
         if (g1 >= 1) nbr[6 * i + 0] = (short)g_index(g1 - 1, b, c);
         if (b >= 1) nbr[6 * i + 1] = (short)g_index(g1, b - 1, c);
@@ -201,6 +241,14 @@ static int build_constant_tables(tefmm_t h) {
   HIPCHK(h, hipMalloc(&h->d_rfull, sizeof(int) * nR));
   HIPCHK(h, hipMalloc(&h->d_nbr, sizeof(short) * 6 * nG));
   HIPCHK(h, hipMalloc(&h->d_gpad, sizeof(int) * nG));
+  HIPCHK(h, hipMalloc(&h->d_gpadz, sizeof(int) * nG));
+  HIPCHK(h, hipMemcpy(h->d_gpadz, gpadz.data(), sizeof(int) * nG, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMalloc(&h->d_g1, nG));
+  HIPCHK(h, hipMemcpy(h->d_g1, g1v.data(), nG, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMalloc(&h->d_rzmi, sizeof(int) * nR));
+  HIPCHK(h, hipMemcpy(h->d_rzmi, rzmi.data(), sizeof(int) * nR, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMalloc(&h->d_rzfull, sizeof(int) * nR));
+  HIPCHK(h, hipMemcpy(h->d_rzfull, rzfull.data(), sizeof(int) * nR, hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->d_gpad, gpad.data(), sizeof(int) * nG, hipMemcpyHostToDevice));
   HIPCHK(h, hipMalloc(&h->d_g3, nG));
   HIPCHK(h, hipMalloc(&h->d_fact, sizeof(double) * nG));
@@ -235,7 +283,7 @@ extern "C" int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefm
   if (o.p < 1 || o.p > 16 || o.depth < 0 || o.depth > 7 || o.max_leaf < 1 ||
       (o.precision != TEFMM_FP64 && o.precision != TEFMM_MIXED_FP32) ||
       (o.normalization != TEFMM_NORM_PHYSICAL && o.normalization != TEFMM_NORM_PAPER) || o.dcim_samples < 8 ||
-      !(o.dcim_T1 > 0) || !(o.dcim_svd_tol > 0) || !(o.interface_eps >= 0) || o.n_rhs_max < 1) {
+      !(o.dcim_T1 > 0) || !(o.dcim_T1_cross > 0) || !(o.dcim_svd_tol > 0) || !(o.interface_eps >= 0) || o.n_rhs_max < 1) {
     delete h;
     return TEFMM_ERR_INVALID_ARG;
   }
@@ -256,6 +304,10 @@ extern "C" void tefmm_destroy(tefmm_t h) {
   dfree(h->d_rmi);
   dfree(h->d_rfull);
   dfree(h->d_gpad);
+  dfree(h->d_gpadz);
+  dfree(h->d_g1);
+  dfree(h->d_rzmi);
+  dfree(h->d_rzfull);
   dfree(h->d_nbr);
   dfree(h->d_g3);
   dfree(h->d_fact);
@@ -352,7 +404,7 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
       HIPCHK(h, hipMemcpyAsync(d_h, hk.data(), sizeof(double) * hk.size(), hipMemcpyHostToDevice, s));
       TableGenArgs ta;
       ta.terms = d_terms, ta.term_start = d_start, ta.h = d_h, ta.k = k, ta.order = 2 * h->opt.p, ta.nG = h->nG;
-      ta.nbr = h->d_nbr, ta.g3 = h->d_g3, ta.fact = h->d_fact, ta.out = d_out;
+      ta.nbr = h->d_nbr, ta.g3 = h->d_g3, ta.g1 = h->d_g1, ta.swap13 = 0, ta.fact = h->d_fact, ta.out = d_out;
       const size_t lds = 2 * sizeof(double2) * h->nG;
       HIPCHK(h, hipFuncSetAttribute((const void*)k_table_gen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
       hipLaunchKernelGGL(k_table_gen, dim3(nkeys), dim3(64), lds, s, ta);
@@ -378,6 +430,249 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
           g.Tfd32[lev] = d32;
         else
           g.TS32[lev] = d32;
+      }
+    }
+  }
+  return TEFMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Cross-layer interaction lists, complex images and tables of target group gt.
+// A pair of boxes (target in gt, source in another group) at level l is
+// translated at l if it passes the acceptance test sqrt(3) h <= theta |c_t - c_s|
+// and its parent pair failed it (or l = 2), or if l is the leaf level.  The
+// test is monotone under refinement for theta <= 1, so every leaf pair is
+// translated exactly once.  Lists depend only on the target's x/y parity and
+// z index (common x-y grid), keys on (source group, dx, dy, iz_t, iz_s).
+// ---------------------------------------------------------------------------
+static const double CROSS_THETA = 0.6;
+
+static int build_cross(tefmm_t h, int gt, hipStream_t s) {
+  Group& G = h->groups[gt];
+  const MediumDesc& med = h->med;
+  const int H = G.depth, p = h->opt.p;
+  const int lt = G.layer;
+  const int ng = (int)h->groups.size();
+  G.xlist_start.assign(H + 1, nullptr);
+  G.xlist.assign(H + 1, nullptr);
+  G.xkeys.assign(H + 1, 0);
+  G.XT0.assign(H + 1, nullptr), G.XT1.assign(H + 1, nullptr);
+  G.XT032.assign(H + 1, nullptr), G.XT132.assign(H + 1, nullptr);
+  G.cross_flops_per_rhs = 0;
+  G.cross_pairs = 0, G.cross_forced = 0, G.n_cross_fits = 0, G.cross_fit_err = 0;
+  G.has_cross = ng > 1;
+  if (!G.has_cross) return TEFMM_OK;
+  std::vector<int> waves;
+  if (lt < med.L) waves.push_back(0);
+  if (lt > 0) waves.push_back(1);
+  const double sq3 = std::sqrt(3.0);
+  auto mac = [&](int sg, int l, int dx, int dy, int izt, int izs) {
+    const double hh = G.side / (1 << l);
+    const double zt = G.lo[2] + (izt + 0.5) * hh, zs = h->groups[sg].lo[2] + (izs + 0.5) * hh;
+    const double D = std::sqrt((dx * hh) * (dx * hh) + (dy * hh) * (dy * hh) + (zt - zs) * (zt - zs));
+    return sq3 * hh <= CROSS_THETA * D;
+  };
+  auto nvalid = [](int d, int par, int n) {
+    int c = 0;
+    for (int i = par; i < n; i += 2)
+      if (i + d >= 0 && i + d < n) ++c;
+    return c;
+  };
+  struct KeyRec {
+    int sg, dx, dy, izt, izs;
+  };
+  std::vector<std::vector<KeyRec>> keys(H + 1);
+  std::vector<std::vector<std::vector<CrossEntry>>> lists(H + 1);
+  // fits needed: (sg, level, izs)
+  std::map<std::tuple<int, int, int>, int> fitmap;
+  for (int lev = 2; lev <= H; ++lev) {
+    const int n = 1 << lev;
+    lists[lev].assign(4 * n, {});
+    std::map<std::tuple<int, int, int, int, int>, int> kmap;
+    for (int sg = 0; sg < ng; ++sg) {
+      if (sg == gt) continue;
+      for (int izt = 0; izt < n; ++izt)
+        for (int pc = 0; pc < 4; ++pc) {
+          const int px = pc & 1, py = pc >> 1;
+          std::vector<std::array<int, 3>> cand;
+          if (lev == 2) {
+            for (int dx = -(n - 1); dx <= n - 1; ++dx)
+              for (int dy = -(n - 1); dy <= n - 1; ++dy)
+                for (int izs = 0; izs < n; ++izs) cand.push_back({dx, dy, izs});
+          } else {
+            const int W = 3;
+            for (int Pdx = -W; Pdx <= W; ++Pdx)
+              for (int Pdy = -W; Pdy <= W; ++Pdy)
+                for (int Pz = 0; Pz < n / 2; ++Pz) {
+                  if (mac(sg, lev - 1, Pdx, Pdy, izt >> 1, Pz)) continue;
+                  for (int c = 0; c < 8; ++c)
+                    cand.push_back({2 * Pdx + ((c >> 2) & 1) - px, 2 * Pdy + ((c >> 1) & 1) - py, 2 * Pz + (c & 1)});
+                }
+          }
+          for (auto& cd : cand) {
+            const int dx = cd[0], dy = cd[1], izs = cd[2];
+            const bool pass = mac(sg, lev, dx, dy, izt, izs);
+            if (!(pass || lev == H)) continue;
+            const int vx = nvalid(dx, px, n), vy = nvalid(dy, py, n);
+            if (!vx || !vy) continue;
+            auto kt = std::make_tuple(sg, dx, dy, izt, izs);
+            auto it = kmap.find(kt);
+            int key;
+            if (it == kmap.end()) {
+              key = (int)keys[lev].size();
+              kmap[kt] = key;
+              keys[lev].push_back({sg, dx, dy, izt, izs});
+              fitmap.emplace(std::make_tuple(sg, lev, izs), 0);
+            } else {
+              key = it->second;
+            }
+            lists[lev][4 * izt + pc].push_back({sg, dx, dy, izs, key});
+            G.cross_flops_per_rhs += 8.0 * h->nR * h->nR * vx * vy;
+            G.cross_pairs += (int64_t)vx * vy;
+            if (!pass) G.cross_forced += (int64_t)vx * vy;
+          }
+        }
+    }
+  }
+  // complex images: (sg, level, izs) x k3' in {0, 1} x target waves, fitted in parallel
+  struct Job {
+    int sg, lev, izs, k3, a;
+    std::vector<cplx> A, Z;
+    double fe = 0;
+    bool ok = true;
+    std::string err;
+  };
+  std::vector<Job> jobs;
+  for (auto& kv : fitmap) {
+    int idx = (int)jobs.size();
+    kv.second = idx;
+    for (int k3 = 0; k3 < 2; ++k3)
+      for (int a : waves) {
+        Job j;
+        j.sg = std::get<0>(kv.first), j.lev = std::get<1>(kv.first), j.izs = std::get<2>(kv.first);
+        j.k3 = k3, j.a = a;
+        jobs.push_back(j);
+      }
+  }
+  {
+    const int nthr = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    std::atomic<int> next{0};
+    for (int t = 0; t < nthr; ++t)
+      th.emplace_back([&]() {
+        for (;;) {
+          const int i = next++;
+          if (i >= (int)jobs.size()) break;
+          Job& j = jobs[i];
+          const Group& S = h->groups[j.sg];
+          const double hh = G.side / (1 << j.lev);
+          const double zs = S.lo[2] + (j.izs + 0.5) * hh;
+          j.ok = cross_layer_fit(med, lt, S.layer, j.a, zs, j.k3, G.fit_zlo, G.fit_zhi, h->opt.dcim_T1_cross,
+                                 h->opt.dcim_samples, h->opt.dcim_svd_tol, j.A, j.Z, j.fe, j.err);
+        }
+      });
+    for (auto& t : th) t.join();
+  }
+  for (auto& j : jobs)
+    if (!j.ok) return fail(h, TEFMM_ERR_DCIM_FIT, "cross-layer complex-image fit failed: " + j.err);
+  G.n_cross_fits = (int)jobs.size();
+  G.cross_fit_err = 0;
+  for (auto& j : jobs) G.cross_fit_err = std::max(G.cross_fit_err, j.fe);
+  // the images represent the kernel only for heights inside the layers; a box that
+  // may hold particles must have its centre there (target and source side)
+  for (int lev = 2; lev <= H; ++lev)
+    for (const KeyRec& kr : keys[lev]) {
+      const double hb = G.side / (1 << lev);
+      const Group& S = h->groups[kr.sg];
+      const double zt = G.lo[2] + (kr.izt + 0.5) * hb, zs = S.lo[2] + (kr.izs + 0.5) * hb;
+      const bool t_occ = zt - 0.5 * hb < G.zhi && zt + 0.5 * hb > G.zlo;
+      const bool s_occ = zs - 0.5 * hb < S.zhi && zs + 0.5 * hb > S.zlo;
+      if ((t_occ && (zt <= med.bottom(lt) || zt >= med.top(lt))) ||
+          (s_occ && (zs <= med.bottom(S.layer) || zs >= med.top(S.layer))))
+        return fail(h, TEFMM_ERR_UNSUPPORTED,
+                    "cross-layer geometry: a box holding particles has its centre outside its layer "
+                    "(layer thinner than the common box side)");
+    }
+  // tables per level and k3'
+  for (int lev = 2; lev <= H; ++lev) {
+    const int n = 1 << lev;
+    const double hb = G.side / n;
+    const int nkeys = (int)keys[lev].size();
+    G.xkeys[lev] = nkeys;
+    std::vector<int> starts(4 * n + 1, 0);
+    std::vector<CrossEntry> flat;
+    for (int c = 0; c < 4 * n; ++c) {
+      starts[c] = (int)flat.size();
+      flat.insert(flat.end(), lists[lev][c].begin(), lists[lev][c].end());
+    }
+    starts[4 * n] = (int)flat.size();
+    HIPCHK(h, hipMalloc(&G.xlist_start[lev], sizeof(int) * (4 * n + 1)));
+    HIPCHK(h, hipMemcpy(G.xlist_start[lev], starts.data(), sizeof(int) * (4 * n + 1), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMalloc(&G.xlist[lev], sizeof(CrossEntry) * std::max<size_t>(1, flat.size())));
+    if (!flat.empty())
+      HIPCHK(h, hipMemcpy(G.xlist[lev], flat.data(), sizeof(CrossEntry) * flat.size(), hipMemcpyHostToDevice));
+    for (int k3 = 0; k3 < 2; ++k3) {
+      std::vector<TableTerm> terms;
+      std::vector<int> start;
+      std::vector<double> hk;
+      for (const KeyRec& kr : keys[lev]) {
+        start.push_back((int)terms.size());
+        hk.push_back(hb);
+        const double zt = G.lo[2] + (kr.izt + 0.5) * hb;
+        const int fi = fitmap.at(std::make_tuple(kr.sg, lev, kr.izs));
+        for (int wi = 0; wi < (int)waves.size(); ++wi) {
+          const int a = waves[wi];
+          const Job& j = jobs[fi + k3 * (int)waves.size() + wi];
+          const double Za = a == 0 ? zt - med.d[lt] : med.d[lt - 1] - zt;
+          const cplx sc = k3 ? cplx(-hb, 0) : cplx(1, 0);
+          for (size_t q = 0; q < j.A.size(); ++q) {
+            const cplx zeta = (Za - j.Z[q]) / hb;
+            if (zeta.real() <= 1e-9) continue;
+            TableTerm t;
+            t.x = -kr.dx, t.y = -kr.dy, t.zr = zeta.real(), t.zi = zeta.imag();
+            const cplx cf = j.A[q] * sc;
+            t.cr = cf.real(), t.ci = cf.imag(), t.flip = a == 1, t.pad = 0;
+            terms.push_back(t);
+          }
+        }
+      }
+      start.push_back((int)terms.size());
+      double2* d_out = nullptr;
+      HIPCHK(h, hipMalloc(&d_out, sizeof(double2) * std::max<size_t>(1, (size_t)nkeys * h->nG)));
+      if (nkeys > 0) {
+        TableTerm* d_terms = nullptr;
+        int* d_start = nullptr;
+        double* d_h = nullptr;
+        HIPCHK(h, hipMalloc(&d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
+        HIPCHK(h, hipMalloc(&d_start, sizeof(int) * start.size()));
+        HIPCHK(h, hipMalloc(&d_h, sizeof(double) * hk.size()));
+        if (!terms.empty())
+          HIPCHK(h, hipMemcpyAsync(d_terms, terms.data(), sizeof(TableTerm) * terms.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipMemcpyAsync(d_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipMemcpyAsync(d_h, hk.data(), sizeof(double) * hk.size(), hipMemcpyHostToDevice, s));
+        TableGenArgs ta;
+        ta.terms = d_terms, ta.term_start = d_start, ta.h = d_h, ta.k = med.k[lt], ta.order = 2 * p, ta.nG = h->nG;
+        ta.nbr = h->d_nbr, ta.g3 = h->d_g3, ta.g1 = h->d_g1, ta.swap13 = 1, ta.fact = h->d_fact, ta.out = d_out;
+        const size_t lds = 2 * sizeof(double2) * h->nG;
+        HIPCHK(h, hipFuncSetAttribute((const void*)k_table_gen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_table_gen, dim3(nkeys), dim3(64), lds, s, ta);
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipStreamSynchronize(s));
+        dfree(d_terms);
+        dfree(d_start);
+        dfree(d_h);
+      }
+      (k3 ? G.XT1[lev] : G.XT0[lev]) = d_out;
+      if (h->opt.precision == TEFMM_MIXED_FP32) {
+        const size_t cnt = (size_t)nkeys * h->nG;
+        std::vector<double2> hd(std::max<size_t>(cnt, 1));
+        std::vector<float2> hf(std::max<size_t>(cnt, 1));
+        if (cnt) HIPCHK(h, hipMemcpy(hd.data(), d_out, sizeof(double2) * cnt, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < cnt; ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
+        float2* d32 = nullptr;
+        HIPCHK(h, hipMalloc(&d32, sizeof(float2) * std::max<size_t>(cnt, 1)));
+        if (cnt) HIPCHK(h, hipMemcpy(d32, hf.data(), sizeof(float2) * cnt, hipMemcpyHostToDevice));
+        (k3 ? G.XT132[lev] : G.XT032[lev]) = d32;
       }
     }
   }
@@ -448,9 +743,50 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     }
   int ngroups = 0;
   for (int l = 0; l <= L; ++l) ngroups += cnt[l] > 0;
-  if (ngroups > 1) {
-    dfree(d_in), dfree(d_if);
-    return fail(h, TEFMM_ERR_UNSUPPORTED, "particles in more than one layer: cross-layer components not built");
+  // Several layers: one common x-y box grid (so that cross-layer offsets are whole
+  // boxes), one common cube side and one depth; each layer's cube is centred on
+  // its particles in z.
+  double cx0 = 1e300, cx1 = -1e300, cy0 = 1e300, cy1 = -1e300, zext = 0;
+  int depth_common = 2;
+  for (int l = 0; l <= L; ++l) {
+    if (!cnt[l]) continue;
+    cx0 = std::min(cx0, mn[l][0]), cx1 = std::max(cx1, mx[l][0]);
+    cy0 = std::min(cy0, mn[l][1]), cy1 = std::max(cy1, mx[l][1]);
+    zext = std::max(zext, mx[l][2] - mn[l][2]);
+    int dl = 2;
+    while (dl < 7 && (double)cnt[l] / std::pow(8.0, dl) > h->opt.max_leaf) ++dl;
+    depth_common = std::max(depth_common, dl);
+  }
+  const double side_common = std::max(std::max(cx1 - cx0, cy1 - cy0), zext) * (1 + 1e-9) + 1e-12;
+  // z origin of each layer's cube: centred on the layer's particles, then moved
+  // (keeping them inside) so that the cube stays within the layer when the layer
+  // is thick enough
+  double lo_z[4] = {0, 0, 0, 0};
+  for (int l = 0; l <= L; ++l) {
+    if (!cnt[l]) continue;
+    double z0 = 0.5 * (mn[l][2] + mx[l][2]) - 0.5 * side_common;
+    const double a0 = std::max(mx[l][2] - side_common, med.bottom(l)), a1 = std::min(mn[l][2], med.top(l) - side_common);
+    if (a0 <= a1) z0 = std::min(std::max(z0, a0), a1);
+    lo_z[l] = z0;
+  }
+  // Automatic depth with several layers: deep enough that the closest occupied
+  // leaf slabs of two layers pass the cross-layer acceptance test (so no
+  // cross-layer pair is translated below it), up to the depth limit.
+  if (ngroups > 1 && h->opt.depth == 0) {
+    auto slab_gap_ok = [&](int dep) {
+      const double hb = side_common / (1 << dep);
+      for (int a = 0; a <= L; ++a)
+        for (int b = a + 1; b <= L; ++b) {
+          if (!cnt[a] || !cnt[b]) continue;
+          // occupied slab centres of a and b closest to each other
+          const int ia0 = (int)std::floor((mn[a][2] - lo_z[a]) / hb), ib1 = (int)std::floor((mx[b][2] - lo_z[b]) / hb);
+          const double za = lo_z[a] + (std::max(ia0, 0) + 0.5) * hb;
+          const double zb = lo_z[b] + (std::min(ib1, (1 << dep) - 1) + 0.5) * hb;
+          if (std::sqrt(3.0) * hb > CROSS_THETA * std::fabs(za - zb)) return false;
+        }
+      return true;
+    };
+    while (depth_common < 7 && !slab_gap_ok(depth_common)) ++depth_common;
   }
   TreeGeom geo;
   std::memset(&geo, 0, sizeof(geo));
@@ -467,11 +803,18 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     for (int c = 0; c < 3; ++c) side = std::max(side, mx[l][c] - mn[l][c]);
     side = side * (1 + 1e-9) + 1e-12;
     for (int c = 0; c < 3; ++c) g.lo[c] = 0.5 * (mn[l][c] + mx[l][c]) - 0.5 * side;
+    if (ngroups > 1) {
+      side = side_common;
+      g.lo[0] = 0.5 * (cx0 + cx1) - 0.5 * side;
+      g.lo[1] = 0.5 * (cy0 + cy1) - 0.5 * side;
+      g.lo[2] = lo_z[l];
+    }
     g.side = side;
     int depth = h->opt.depth;
     if (depth == 0) {
       depth = 2;
       while (depth < 7 && (double)cnt[l] / std::pow(8.0, depth) > h->opt.max_leaf) ++depth;
+      if (ngroups > 1) depth = depth_common;
     }
     g.depth = std::max(2, std::min(7, depth));
     g.leaf_base = leaf_off;
@@ -580,6 +923,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     const double top = med.top(l), bot = med.bottom(l);
     zlo = std::max(zlo, bot + 1e-6);
     zhi = std::min(zhi, top - 1e-6);
+    g.fit_zlo = zlo, g.fit_zhi = zhi;
     for (int fam = 0; fam < 3; ++fam) {
       std::string err;
       if (!same_layer_family(med, l, fam, zlo, zhi, h->opt.dcim_T1, h->opt.dcim_samples, h->opt.dcim_svd_tol,
@@ -591,6 +935,10 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   // derivative tables
   for (auto& g : h->groups) {
     int rc = build_tables(h, g, s);
+    if (rc != TEFMM_OK) return rc;
+  }
+  for (int gi = 0; gi < (int)h->groups.size(); ++gi) {
+    int rc = build_cross(h, gi, s);
     if (rc != TEFMM_OK) return rc;
   }
   HIPCHK(h, hipEventRecord(e2, s));
@@ -616,6 +964,12 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
       }
   }
   h->st.n_families = fi;
+  for (auto& g : h->groups) {
+    h->st.cross_pairs += g.cross_pairs;
+    h->st.cross_pairs_forced += g.cross_forced;
+    h->st.n_cross_fits += g.n_cross_fits;
+    h->st.cross_fit_err = std::max(h->st.cross_fit_err, g.cross_fit_err);
+  }
   h->st.p2p_pairs = h->p2p_pairs;
   h->st.m2l_pairs = h->m2l_pairs;
   h->ready = true;
@@ -632,6 +986,8 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
     for (auto& p : g.beta) dfree(p);
     for (auto& p : g.ared) dfree(p);
     for (auto& p : g.bred) dfree(p);
+    for (auto& p : g.azred) dfree(p);
+    for (auto& p : g.bzred) dfree(p);
   }
   HIPCHK(h, hipMalloc(&h->d_q, sizeof(double2) * h->n * nrhs));
   HIPCHK(h, hipMalloc(&h->d_phi, sizeof(double2) * h->n * nrhs));
@@ -640,6 +996,8 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
     g.beta.assign(g.depth + 1, nullptr);
     g.ared.assign(g.depth + 1, nullptr);
     g.bred.assign(g.depth + 1, nullptr);
+    g.azred.assign(g.depth + 1, nullptr);
+    g.bzred.assign(g.depth + 1, nullptr);
     g.nbox.assign(g.depth + 1, 0);
     for (int lev = 2; lev <= g.depth; ++lev) {
       const int64_t nbx = (int64_t)1 << (3 * lev);
@@ -648,6 +1006,10 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
       HIPCHK(h, hipMalloc(&g.beta[lev], sizeof(double2) * nbx * h->nC * nrhs));
       HIPCHK(h, hipMalloc(&g.ared[lev], sizeof(double2) * nbx * h->nR * nrhs));
       HIPCHK(h, hipMalloc(&g.bred[lev], sizeof(double2) * nbx * h->nR * nrhs));
+      if (h->groups.size() > 1) {
+        HIPCHK(h, hipMalloc(&g.azred[lev], sizeof(double2) * nbx * h->nR * nrhs));
+        HIPCHK(h, hipMalloc(&g.bzred[lev], sizeof(double2) * nbx * h->nR * nrhs));
+      }
     }
   }
   h->nrhs_alloc = nrhs;
@@ -674,31 +1036,46 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     if (timed) HIPCHK(h, hipEventRecord(h->ev[i], s)); \
   } while (0)
   const int64_t n = h->n;
+  const int p = h->opt.p;
   const bool fp32 = h->opt.precision == TEFMM_MIXED_FP32;
+  const bool cross = h->groups.size() > 1;
   double m2l_flops = 0;
   int m2l_launches = 0;
-  EVREC(0);
-  hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, (const double2*)q,
-                     h->d_perm, n, h->d_q);
-  HIPCHK(h, hipGetLastError());
-  for (auto& g : h->groups) {
-    const int H = g.depth, p = h->opt.p;
+  auto pass_args = [&](const Group& g) {
     PassArgs pa;
     std::memset(&pa, 0, sizeof(pa));
     pa.p = p, pa.nC = h->nC, pa.k = h->med.k[g.layer], pa.n = n, pa.xs = h->d_xs, pa.q = h->d_q, pa.phi = h->d_phi;
     pa.leaf_start = h->d_leaf_start, pa.leaf_count = h->d_leaf_count, pa.leaf_base = g.leaf_base, pa.mi = h->d_mi;
     for (int c = 0; c < 3; ++c) pa.lo[c] = g.lo[c];
-    // P2M at the leaves
-    {
-      PassArgs a = pa;
-      a.nbox_dim = 1 << H, a.h = g.side / (1 << H), a.alpha = g.alpha[H], a.rhs_stride = g.nbox[H] * h->nC;
-      const size_t lds = sizeof(double) * 64 * 3 * (p + 1) + sizeof(double2) * 64;
-      hipLaunchKernelGGL(k_p2m, dim3((unsigned)g.nbox[H], nrhs), dim3(64), lds, s, a);
-      HIPCHK(h, hipGetLastError());
-    }
-    EVREC(1);
+    return pa;
+  };
+  auto reduce_args = [&](const Group& g, int lev, bool z) {
+    ReduceArgs ra;
+    const double hl = g.side / (1 << lev), kh = h->med.k[g.layer] * hl;
+    ra.p = p, ra.nC = h->nC, ra.nR = h->nR, ra.kh2 = kh * kh, ra.mi = h->d_mi, ra.rfull = z ? h->d_rzfull : h->d_rfull;
+    ra.scale = h->d_scale, ra.invfact = h->d_invfact;
+    return ra;
+  };
+  EVREC(0);
+  hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, (const double2*)q,
+                     h->d_perm, n, h->d_q);
+  HIPCHK(h, hipGetLastError());
+  // P2M at the leaves (Sec. 3.1)
+  for (auto& g : h->groups) {
+    const int H = g.depth;
+    PassArgs a = pass_args(g);
+    a.nbox_dim = 1 << H, a.h = g.side / (1 << H), a.alpha = g.alpha[H], a.rhs_stride = g.nbox[H] * h->nC;
+    const size_t lds = sizeof(double) * 64 * 3 * (p + 1) + sizeof(double2) * 64;
+    hipLaunchKernelGGL(k_p2m, dim3((unsigned)g.nbox[H], nrhs), dim3(64), lds, s, a);
+    HIPCHK(h, hipGetLastError());
+  }
+  EVREC(1);
+  // M2M, then the reduced moments of every level (x-reduced for the same-layer
+  // translations, z-reduced for the cross-layer ones)
+  for (auto& g : h->groups) {
+    const int H = g.depth;
     for (int lev = H - 1; lev >= 2; --lev) {
-      PassArgs a = pa;
+      PassArgs a = pass_args(g);
       a.nbox_dim = 1 << lev, a.alpha = g.alpha[lev], a.rhs_stride = g.nbox[lev] * h->nC;
       a.alpha_child = g.alpha[lev + 1], a.rhs_stride_child = g.nbox[lev + 1] * h->nC;
       const size_t lds = (3 * sizeof(double2) + sizeof(int)) * h->nC;
@@ -706,55 +1083,90 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       hipLaunchKernelGGL(k_m2m, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), lds, s, a);
       HIPCHK(h, hipGetLastError());
     }
-    // Helmholtz-reduced moments per level
     for (int lev = 2; lev <= H; ++lev) {
-      ReduceArgs ra;
-      const double hl = g.side / (1 << lev), kh = h->med.k[g.layer] * hl;
-      ra.p = p, ra.nC = h->nC, ra.nR = h->nR, ra.kh2 = kh * kh, ra.mi = h->d_mi, ra.rfull = h->d_rfull;
-      ra.scale = h->d_scale, ra.invfact = h->d_invfact, ra.in = g.alpha[lev], ra.out = g.ared[lev];
+      ReduceArgs ra = reduce_args(g, lev, false);
+      ra.in = g.alpha[lev], ra.out = g.ared[lev];
       ra.in_stride = g.nbox[lev] * h->nC, ra.out_stride = g.nbox[lev] * h->nR;
       hipLaunchKernelGGL(k_reduce, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, ra);
       HIPCHK(h, hipGetLastError());
-    }
-    EVREC(2);
-    {
-      M2LArgs m;
-      std::memset(&m, 0, sizeof(m));
-      m.nR = h->nR, m.nRs = h->nRs, m.nKB = h->nKB, m.nRB = h->nRB, m.nG = h->nG, m.p = p, m.P2 = 2 * p + 1;
-      m.rmi = h->d_rmi, m.gpad = h->d_gpad;
-      m.nlev = H - 1;
-      for (int lev = 2; lev <= H; ++lev) {
-        M2LLevel& L = m.lev[lev - 2];
-        L.n = 1 << lev, L.leaf = lev == H;
-        L.near_fd = g.has[2], L.near_s = g.has[0] || g.has[1];
-        L.a = g.ared[lev], L.b = g.bred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
-        L.Tfd = g.Tfd[lev], L.TS = g.TS[lev], L.Tfd32 = g.Tfd32[lev], L.TS32 = g.TS32[lev];
+      if (cross) {
+        ReduceArgs rz = reduce_args(g, lev, true);
+        rz.in = g.alpha[lev], rz.out = g.azred[lev];
+        rz.in_stride = g.nbox[lev] * h->nC, rz.out_stride = g.nbox[lev] * h->nR;
+        hipLaunchKernelGGL(k_reduce_z, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, rz);
+        HIPCHK(h, hipGetLastError());
       }
-      m.ncb = h->m2l_ncb;
-      HIPCHK(h, launch_m2l(m, nrhs, fp32, s));
     }
-    EVREC(3);
-    {
-      const double per = 8.0 * (double)h->nR * (double)h->nR;
+  }
+  EVREC(2);
+  // M2L: same-layer families, then cross-layer components (Algorithm 2)
+  for (auto& g : h->groups) {
+    const int H = g.depth;
+    M2LArgs m;
+    std::memset(&m, 0, sizeof(m));
+    m.nR = h->nR, m.nRs = h->nRs, m.nKB = h->nKB, m.nRB = h->nRB, m.nG = h->nG, m.p = p, m.P2 = 2 * p + 1;
+    m.rmi = h->d_rmi, m.gpad = h->d_gpad;
+    m.nlev = H - 1;
+    for (int lev = 2; lev <= H; ++lev) {
+      M2LLevel& L = m.lev[lev - 2];
+      L.n = 1 << lev, L.leaf = lev == H;
+      L.near_fd = g.has[2], L.near_s = g.has[0] || g.has[1];
+      L.a = g.ared[lev], L.b = g.bred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
+      L.Tfd = g.Tfd[lev], L.TS = g.TS[lev], L.Tfd32 = g.Tfd32[lev], L.TS32 = g.TS32[lev];
+    }
+    m.ncb = h->m2l_ncb;
+    HIPCHK(h, launch_m2l(m, nrhs, fp32, s));
+    const double per = 8.0 * (double)h->nR * (double)h->nR;
+    for (int lev = 2; lev <= H; ++lev) {
+      const int64_t far = g.far_pairs[lev - 2], nr = g.near_pairs[lev - 2];
+      const bool sig = g.has[0] || g.has[1];
+      double pairs = (double)far + (sig ? (double)far : 0.0);
+      if (lev == H) pairs += (g.has[2] ? (double)nr : 0.0) + (sig ? (double)nr : 0.0);
+      m2l_flops += per * pairs * nrhs;
+    }
+    ++m2l_launches;
+    if (g.has_cross) {
+      M2LCrossArgs c;
+      std::memset(&c, 0, sizeof(c));
+      c.nR = h->nR, c.nRs = h->nRs, c.nKB = h->nKB, c.nRB = h->nRB, c.nG = h->nG, c.p = p, c.P2 = 2 * p + 1;
+      c.rzmi = h->d_rzmi, c.gpadz = h->d_gpadz;
+      c.nlev = H - 1;
       for (int lev = 2; lev <= H; ++lev) {
-        const int64_t far = g.far_pairs[lev - 2], nr = g.near_pairs[lev - 2];
-        const bool sig = g.has[0] || g.has[1];
-        double pairs = (double)far + (sig ? (double)far : 0.0);
-        if (lev == H) pairs += (g.has[2] ? (double)nr : 0.0) + (sig ? (double)nr : 0.0);
-        m2l_flops += per * pairs * nrhs;
+        M2LCrossLevel& L = c.lev[lev - 2];
+        L.n = 1 << lev;
+        L.list_start = g.xlist_start[lev], L.list = g.xlist[lev];
+        L.b = g.bzred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
+        L.T[0] = g.XT0[lev], L.T[1] = g.XT1[lev], L.T32[0] = g.XT032[lev], L.T32[1] = g.XT132[lev];
+        for (size_t sg = 0; sg < h->groups.size() && sg < 4; ++sg) {
+          L.asrc[sg] = h->groups[sg].azred[lev];
+          L.src_stride[sg] = h->groups[sg].nbox[lev] * h->nR;
+        }
       }
+      HIPCHK(h, launch_m2l_cross(c, nrhs, fp32, s));
+      m2l_flops += g.cross_flops_per_rhs * nrhs;
       ++m2l_launches;
     }
+  }
+  EVREC(3);
+  // locals: expansion of the reduced sets, cross-layer part added, then L2L
+  for (auto& g : h->groups) {
+    const int H = g.depth;
     for (int lev = 2; lev <= H; ++lev) {
-      ReduceArgs ra;
-      const double hl = g.side / (1 << lev), kh = h->med.k[g.layer] * hl;
-      ra.p = p, ra.nC = h->nC, ra.nR = h->nR, ra.kh2 = kh * kh, ra.mi = h->d_mi, ra.rfull = h->d_rfull;
-      ra.scale = h->d_scale, ra.invfact = h->d_invfact, ra.in = g.bred[lev], ra.out = g.beta[lev];
+      ReduceArgs ra = reduce_args(g, lev, false);
+      ra.in = g.bred[lev], ra.out = g.beta[lev];
       ra.in_stride = g.nbox[lev] * h->nR, ra.out_stride = g.nbox[lev] * h->nC;
       hipLaunchKernelGGL(k_expand, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, ra);
       HIPCHK(h, hipGetLastError());
+      if (g.has_cross) {
+        ReduceArgs rz = reduce_args(g, lev, true);
+        rz.in = g.bzred[lev], rz.out = g.beta[lev];
+        rz.in_stride = g.nbox[lev] * h->nR, rz.out_stride = g.nbox[lev] * h->nC;
+        hipLaunchKernelGGL(k_expand_z_add, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s,
+                           rz);
+        HIPCHK(h, hipGetLastError());
+      }
       if (lev >= 3) {
-        PassArgs a = pa;
+        PassArgs a = pass_args(g);
         a.nbox_dim = 1 << lev, a.beta = g.beta[lev], a.rhs_stride = g.nbox[lev] * h->nC;
         a.beta_parent = g.beta[lev - 1], a.rhs_stride_parent = g.nbox[lev - 1] * h->nC;
         hipLaunchKernelGGL(k_l2l, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), (2 * sizeof(double2) + sizeof(int)) * h->nC,
@@ -762,35 +1174,36 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
         HIPCHK(h, hipGetLastError());
       }
     }
-    EVREC(4);
-    {
-      PassArgs a = pa;
-      a.nbox_dim = 1 << H, a.h = g.side / (1 << H), a.beta = g.beta[H], a.rhs_stride = g.nbox[H] * h->nC;
-      const size_t lds = sizeof(double2) * h->nC + sizeof(double) * 64 * 3 * (p + 1) + sizeof(int) * h->nC;
-      hipLaunchKernelGGL(k_l2p, dim3((unsigned)g.nbox[H], nrhs), dim3(64), lds, s, a);
-      HIPCHK(h, hipGetLastError());
+  }
+  EVREC(4);
+  for (auto& g : h->groups) {
+    const int H = g.depth;
+    PassArgs a = pass_args(g);
+    a.nbox_dim = 1 << H, a.h = g.side / (1 << H), a.beta = g.beta[H], a.rhs_stride = g.nbox[H] * h->nC;
+    const size_t lds = sizeof(double2) * h->nC + sizeof(double) * 64 * 3 * (p + 1) + sizeof(int) * h->nC;
+    hipLaunchKernelGGL(k_l2p, dim3((unsigned)g.nbox[H], nrhs), dim3(64), lds, s, a);
+    HIPCHK(h, hipGetLastError());
+  }
+  EVREC(5);
+  for (auto& g : h->groups) {
+    PassArgs a = pass_args(g);
+    a.nbox_dim = 1 << g.depth;
+    if (fp32)
+      hipLaunchKernelGGL(k_p2p<float>, dim3((unsigned)g.nbox[g.depth], nrhs), dim3(64), 0, s, a);
+    else
+      hipLaunchKernelGGL(k_p2p<double>, dim3((unsigned)g.nbox[g.depth], nrhs), dim3(64), 0, s, a);
+    HIPCHK(h, hipGetLastError());
+  }
+  EVREC(6);
+  for (auto& g : h->groups) {
+    double sr = 1.0 / (4 * PI), si = 0.0;
+    if (h->opt.normalization == TEFMM_NORM_PAPER) {  // divide by i k of the target layer
+      const double kk = h->med.k[g.layer];
+      sr = 0.0, si = -1.0 / kk;
     }
-    EVREC(5);
-    {
-      PassArgs a = pa;
-      a.nbox_dim = 1 << H;
-      if (fp32)
-        hipLaunchKernelGGL(k_p2p<float>, dim3((unsigned)g.nbox[H], nrhs), dim3(64), 0, s, a);
-      else
-        hipLaunchKernelGGL(k_p2p<double>, dim3((unsigned)g.nbox[H], nrhs), dim3(64), 0, s, a);
-      HIPCHK(h, hipGetLastError());
-    }
-    EVREC(6);
-    {
-      double sr = 1.0 / (4 * PI), si = 0.0;
-      if (h->opt.normalization == TEFMM_NORM_PAPER) {  // divide by i k
-        const double kk = h->med.k[g.layer];
-        sr = 0.0, si = -1.0 / kk;
-      }
-      hipLaunchKernelGGL(k_finalize, dim3((unsigned)((g.count + 255) / 256), nrhs), dim3(256), 0, s, h->d_phi,
-                         h->d_perm, g.start, g.count, n, sr, si, (double2*)phi);
-      HIPCHK(h, hipGetLastError());
-    }
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((g.count + 255) / 256), nrhs), dim3(256), 0, s, h->d_phi,
+                       h->d_perm, g.start, g.count, n, sr, si, (double2*)phi);
+    HIPCHK(h, hipGetLastError());
   }
   EVREC(7);
 #undef EVREC

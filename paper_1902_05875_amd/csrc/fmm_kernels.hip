@@ -53,8 +53,11 @@ __global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
   const double kh = a.k * a.h[key];
   for (int t = t0; t < t1; ++t) {
     const TableTerm tm = a.terms[t];
-    const dc x1 = {tm.x, 0.0}, x2 = {tm.y, 0.0}, x3 = {tm.zr, tm.zi};
-    const dc R2 = {tm.x * tm.x + tm.y * tm.y + tm.zr * tm.zr - tm.zi * tm.zi, 2.0 * tm.zr * tm.zi};
+    // swap13: the table is generated in the frame (zeta, y, x), i.e. restricted
+    // to small orders in z instead of x (cross-layer translations)
+    const dc xr = {tm.x, 0.0}, zc = {tm.zr, tm.zi};
+    const dc x1 = a.swap13 ? zc : xr, x2 = {tm.y, 0.0}, x3 = a.swap13 ? xr : zc;
+    const dc R2 = cadd(cadd(cmul(x1, x1), cmul(x2, x2)), cmul(x3, x3));
     const dc R = csqrt_pr(R2);
     const dc e = cexp_i(R, kh);
     const dc invR2 = cdiv({1.0, 0.0}, R2);
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
       const int g = lane + 64 * j;
       if (g < a.nG) {
         dc v = cmul(cf, {sa[g].x, sa[g].y});
-        if (tm.flip && (a.g3[g] & 1)) v = {-v.x, -v.y};
+        if (tm.flip && ((a.swap13 ? a.g1[g] : a.g3[g]) & 1)) v = {-v.x, -v.y};
         acc[j] = cadd(acc[j], v);
       }
     }
@@ -392,6 +395,83 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
   }
   double2* out = a.out + (int64_t)r * a.out_stride + (int64_t)box * a.nR;
   for (int i = tid; i < a.nR; i += 64) out[i] = lds_red[a.rfull[i]];
+}
+
+// Index of the multi-index whose component along `ax` is t and whose other two
+// components (in increasing axis order) are u, v.
+__device__ __forceinline__ int mi_axis(int ax, int t, int u, int v) {
+  return ax == 0 ? mi_index(t, u, v) : (ax == 1 ? mi_index(u, t, v) : mi_index(u, v, t));
+}
+
+// The same reduction along z (moments with k3 <= 1), used by the cross-layer
+// translation: a_k = (-1)^{|k|} alpha^_k / k!, folded with
+// G_{g+2e3} = -G_{g+2e1} - G_{g+2e2} - (kh)^2 G_g.
+__global__ __launch_bounds__(64) void k_reduce_z(ReduceArgs a) {
+  extern __shared__ double2 lds_rz[];  // [nC]
+  const int box = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const double2* in = a.in + (int64_t)r * a.in_stride + (int64_t)box * a.nC;
+  for (int k = tid; k < a.nC; k += 64) {
+    const double s = a.scale[k];
+    const double2 v = in[k];
+    lds_rz[k] = make_double2(v.x * s, v.y * s);
+  }
+  __syncthreads();
+  for (int t3 = a.p - 2; t3 >= 0; --t3) {
+    const int m = a.p - t3;
+    const int cnt = ((m + 1) * (m + 2)) / 2;
+    for (int e = tid; e < cnt; e += 64) {
+      int tt = 0;
+      while ((tt + 1) * (tt + 2) / 2 <= e) ++tt;
+      const int k2 = e - tt * (tt + 1) / 2, k1 = tt - k2;
+      double2 acc = lds_rz[mi_axis(2, t3, k1, k2)];
+      if (k1 >= 2) {
+        const double2 v = lds_rz[mi_axis(2, t3 + 2, k1 - 2, k2)];
+        acc.x -= v.x, acc.y -= v.y;
+      }
+      if (k2 >= 2) {
+        const double2 v = lds_rz[mi_axis(2, t3 + 2, k1, k2 - 2)];
+        acc.x -= v.x, acc.y -= v.y;
+      }
+      if (t3 + 2 + k1 + k2 <= a.p) {
+        const double2 v = lds_rz[mi_axis(2, t3 + 2, k1, k2)];
+        acc.x -= a.kh2 * v.x, acc.y -= a.kh2 * v.y;
+      }
+      lds_rz[mi_axis(2, t3, k1, k2)] = acc;
+    }
+    __syncthreads();
+  }
+  double2* out = a.out + (int64_t)r * a.out_stride + (int64_t)box * a.nR;
+  for (int i = tid; i < a.nR; i += 64) out[i] = lds_rz[a.rfull[i]];
+}
+
+// z-direction expansion of cross-layer locals (k3 <= 1 -> all |k| <= p), then
+// beta^_k += b_k / k!  (adds to the locals already written).
+__global__ __launch_bounds__(64) void k_expand_z_add(ReduceArgs a) {
+  extern __shared__ double2 lds_ez[];  // [nC]
+  const int box = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const double2* in = a.in + (int64_t)r * a.in_stride + (int64_t)box * a.nR;
+  for (int i = tid; i < a.nR; i += 64) lds_ez[a.rfull[i]] = in[i];
+  __syncthreads();
+  for (int k3 = 2; k3 <= a.p; ++k3) {
+    const int m = a.p - k3;
+    const int cnt = ((m + 1) * (m + 2)) / 2;
+    for (int e = tid; e < cnt; e += 64) {
+      int tt = 0;
+      while ((tt + 1) * (tt + 2) / 2 <= e) ++tt;
+      const int k2 = e - tt * (tt + 1) / 2, k1 = tt - k2;
+      const double2 u = lds_ez[mi_axis(2, k3 - 2, k1 + 2, k2)];
+      const double2 v = lds_ez[mi_axis(2, k3 - 2, k1, k2 + 2)];
+      const double2 w = lds_ez[mi_axis(2, k3 - 2, k1, k2)];
+      lds_ez[mi_axis(2, k3, k1, k2)] = make_double2(-u.x - v.x - a.kh2 * w.x, -u.y - v.y - a.kh2 * w.y);
+    }
+    __syncthreads();
+  }
+  double2* out = a.out + (int64_t)r * a.out_stride + (int64_t)box * a.nC;
+  for (int k = tid; k < a.nC; k += 64) {
+    const double f = a.invfact[k];
+    const double2 v = lds_ez[k], o = out[k];
+    out[k] = make_double2(o.x + v.x * f, o.y + v.y * f);
+  }
 }
 
 // k_expand: b (k1 <= 1) -> all |k| <= p by b_k = -b_{k-2e1+2e2} - b_{k-2e1+2e3}

@@ -21,6 +21,8 @@ struct TableGenArgs {
   int order, nG;          // orders 0..order, nG = g_count(order) compact entries (g1 <= 2)
   const short* nbr;       // [nG][6]: g - e_x, g - e_y, g - e_z, g - 2e_x, g - 2e_y, g - 2e_z (-1 if none)
   const unsigned char* g3;  // [nG] third component of g
+  const unsigned char* g1;  // [nG] first component of g
+  int swap13;             // generate in the (zeta, y, x) frame (flip follows g1 then)
   const double* fact;     // [nG] g!
   double2* out;           // [nkeys][nG]
 };
@@ -99,6 +101,36 @@ struct M2LArgs {
   const int* gpad;       // [nG] position of each compact table entry in the padded LDS layout
 };
 
+// Cross-layer translation (target layer group vs source layer groups), list driven.
+struct CrossEntry {
+  int src;          // source group index
+  int dx, dy, izs;  // source box offset (x, y) and absolute z index in the source grid
+  int key;          // table key
+};
+
+struct M2LCrossLevel {
+  int n, tiles_x, tiles_y, ntiles;
+  const int* list_start;   // [4 n + 1]: entries of (parity class px + 2 py, iz_t) at 4 iz_t + pc
+  const CrossEntry* list;
+  double2* b;              // z-reduced locals of the target group [rhs][box][nR]
+  int64_t rhs_stride;
+  const double2* T[2];     // tables per k3' in {0, 1}: [nkeys][nG] (swapped frame)
+  const float2* T32[2];
+  const double2* asrc[4];  // z-reduced moments of each source group at this level
+  int64_t src_stride[4];
+};
+
+struct M2LCrossArgs {
+  int nR, nRs, nKB, nRB, nG, p, P2;
+  int nlev;
+  int tile_start[M2L_MAX_LEVELS + 1];
+  M2LCrossLevel lev[M2L_MAX_LEVELS];
+  const int* rzmi;         // [nR] z-reduced multi-indices (packed)
+  const int* gpadz;        // [nG] padded LDS position of each swapped-frame entry, -1 if unused
+};
+
+hipError_t launch_m2l_cross(const M2LCrossArgs& a, int nrhs, bool fp32, hipStream_t s);
+
 void upload_binomials();
 
 __global__ void k_table_gen(TableGenArgs a);
@@ -117,6 +149,8 @@ __global__ void k_finalize(const double2* phi_s, const int* perm, int64_t start,
 __global__ void k_p2m(PassArgs a);
 __global__ void k_reduce(ReduceArgs a);
 __global__ void k_expand(ReduceArgs a);
+__global__ void k_reduce_z(ReduceArgs a);
+__global__ void k_expand_z_add(ReduceArgs a);
 __global__ void k_m2m(PassArgs a);
 __global__ void k_l2l(PassArgs a);
 __global__ void k_l2p(PassArgs a);

@@ -288,6 +288,223 @@ static hipError_t launch_t(const M2LArgs& a, int nrhs, hipStream_t s) {
   return launch_t2<T, 1>(a, nrhs, s);
 }
 
+// ---------------------------------------------------------------------------
+// Cross-layer M2L (Algorithm 2, components with target and source in different
+// layers).  Moments and locals are used in the z-reduced form (k3 <= 1) so that
+// only the z' derivative orders 0 and 1 of the kernel are needed; for those the
+// source height enters through per-height complex images (Sec. 3.3).  The table
+// of key (dx, dy, iz_t, iz_s) and order k3' holds
+//   (-1)^{k3'} h^{k3'} h^{|g|} D^g [d^{k3'}_{z'} G / k3'!]
+// in the frame (z, y, x) (entries with small z order), so that
+//   b_k = sum_{k'} T^{(k3')}_{(k1+k1', k2+k2', k3)} a_{k'}
+// with a the z-reduced scaled moments of the source box.  The target tile is
+// a 4 x 4 NCB patch of boxes at one z index and one parity class; its list of
+// (source group, dx, dy, iz_s, key) entries is built on the host from the
+// acceptance test and is the same for every tile of the class.
+// ---------------------------------------------------------------------------
+template <typename T, int TW, int NCB>
+__global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
+  typedef M2LTypes<T> Ty;
+  typedef typename Ty::T2 T2;
+  typedef typename Ty::acc AC;
+  constexpr int NT = 16 * NCB;
+  extern __shared__ double lds_x[];
+  const int P2 = a.P2;
+  const int sub = 2 * P2 * P2;  // one k3' table: planes k3 = 0, 1
+  T2* sG = (T2*)lds_x;          // [2 sub]
+  T2* sA = sG + 2 * sub;        // [NT nRs]
+  int* sCol = (int*)(sA + NT * a.nRs);
+
+  int li = 0, tile = 0;
+  const int widest = a.nlev - 1;
+  if ((int)blockIdx.x < a.tile_start[widest]) {
+    while ((int)blockIdx.x >= a.tile_start[li + 1]) ++li;
+    tile = blockIdx.x - a.tile_start[li];
+  } else {
+    li = widest;
+    const int b = blockIdx.x - a.tile_start[widest];
+    const int nt = a.lev[li].ntiles;
+    const int per = (nt + 7) / 8;
+    tile = (b % 8) * per + b / 8;
+    if (tile >= nt) return;
+  }
+  const M2LCrossLevel& L = a.lev[li];
+  const int r = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int t = tile;
+  const int X0 = t % L.tiles_x;
+  t /= L.tiles_x;
+  const int Y0 = t % L.tiles_y;
+  t /= L.tiles_y;
+  const int px = t & 1, py = (t >> 1) & 1, iz = t >> 2;
+  const int N = L.n;
+  unsigned tmask = 0;
+  for (int n = 0; n < NT; ++n) {
+    const int ix = px + 2 * (4 * X0 + (n & 3)), iy = py + 2 * (4 * NCB * Y0 + (n >> 2));
+    if (ix < N && iy < N) tmask |= 1u << n;
+  }
+  for (int e = tid; e < NT * a.nRs; e += 256) {
+    sA[e].x = 0;
+    sA[e].y = 0;
+  }
+  for (int e = tid; e < 2 * sub; e += 256) {
+    sG[e].x = 0;
+    sG[e].y = 0;
+  }
+  for (int e = tid; e < 4 * a.nKB; e += 256) {
+    int v = 0;
+    if (e < a.nR) {
+      const int pk = a.rzmi[e];
+      const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
+      v = (k3 * sub + (k1 + k2) * P2 + k1) | (1 << 24);
+    }
+    sCol[e] = v;
+  }
+  const int col = lane & 15, krow = lane >> 4;
+  const int ntile = a.nRB * NCB;
+  int rowo[TW], tcb[TW];
+#pragma unroll
+  for (int j = 0; j < TW; ++j) {
+    const int id = w + 4 * j;
+    const int rb = id % a.nRB, cb = id / a.nRB;
+    const int k = 16 * rb + col;
+    rowo[j] = -1, tcb[j] = cb;
+    if (id < ntile && k < a.nR) {
+      const int pk = a.rzmi[k];
+      const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
+      rowo[j] = (k3 * P2 + k1 + k2) * P2 + k1;
+    }
+  }
+  AC accR[TW], accI[TW];
+#pragma unroll
+  for (int j = 0; j < TW; ++j) {
+    accR[j] = AC{0, 0, 0, 0};
+    accI[j] = AC{0, 0, 0, 0};
+  }
+  const int cls = 4 * iz + px + 2 * py;
+  const int e0 = L.list_start[cls], e1 = L.list_start[cls + 1];
+  for (int ei = e0; ei < e1; ++ei) {
+    const CrossEntry ce = L.list[ei];
+    unsigned smask = 0;
+    for (int n = 0; n < NT; ++n) {
+      const int ix = px + 2 * (4 * X0 + (n & 3)) + ce.dx, iy = py + 2 * (4 * NCB * Y0 + (n >> 2)) + ce.dy;
+      if (((tmask >> n) & 1) && ix >= 0 && iy >= 0 && ix < N && iy < N) smask |= 1u << n;
+    }
+    if (!smask) continue;
+    const double2* asrc = ce.src == 0 ? L.asrc[0] : ce.src == 1 ? L.asrc[1] : ce.src == 2 ? L.asrc[2] : L.asrc[3];
+    const int64_t sst = ce.src == 0 ? L.src_stride[0]
+                        : ce.src == 1 ? L.src_stride[1]
+                        : ce.src == 2 ? L.src_stride[2]
+                                      : L.src_stride[3];
+    const double2* alpha = asrc + (int64_t)r * sst;
+    __syncthreads();
+    for (int kk3 = 0; kk3 < 2; ++kk3) {
+      const T2* g = (const T2*)(sizeof(T) == 8 ? (const void*)L.T[kk3] : (const void*)L.T32[kk3]) +
+                    (int64_t)ce.key * a.nG;
+      for (int e = tid; e < a.nG; e += 256) {
+        const int pos = a.gpadz[e];
+        if (pos >= 0) sG[kk3 * sub + pos] = g[e];
+      }
+    }
+    for (int e = tid; e < NT * a.nR; e += 256) {
+      const int n = e / a.nR, kk = e - n * a.nR;
+      T2 v;
+      v.x = 0;
+      v.y = 0;
+      if ((smask >> n) & 1) {
+        const int ix = px + 2 * (4 * X0 + (n & 3)) + ce.dx, iy = py + 2 * (4 * NCB * Y0 + (n >> 2)) + ce.dy;
+        const int64_t sb = ((int64_t)ix * N + iy) * N + ce.izs;
+        v = Ty::cvt(alpha[sb * a.nR + kk]);
+      }
+      sA[n * a.nRs + kk] = v;
+    }
+    __syncthreads();
+    for (int kb = 0; kb < a.nKB; ++kb) {
+      const int kp = 4 * kb + krow;
+      const int ci = sCol[kp];
+      const bool cvalid = (ci >> 24) & 1;
+      const int co = ci & 0xFFFFFF;
+      const T2 bv0 = sA[col * a.nRs + kp];
+      const T2 bv1 = NCB == 2 ? sA[(16 + col) * a.nRs + kp] : bv0;
+      T2 gv[TW];
+#pragma unroll
+      for (int j = 0; j < TW; ++j) {
+        gv[j].x = 0;
+        gv[j].y = 0;
+        if (rowo[j] >= 0 && cvalid) gv[j] = sG[rowo[j] + co];
+      }
+#pragma unroll
+      for (int j = 0; j < TW; ++j)
+        if (w + 4 * j < ntile) {
+          const T2 b = tcb[j] ? bv1 : bv0;
+          accR[j] = Ty::mfma(gv[j].x, b.x, accR[j]);
+          accI[j] = Ty::mfma(gv[j].x, b.y, accI[j]);
+        }
+#pragma unroll
+      for (int j = 0; j < TW; ++j)
+        if (w + 4 * j < ntile) {
+          const T2 b = tcb[j] ? bv1 : bv0;
+          accR[j] = Ty::mfma(-gv[j].y, b.y, accR[j]);
+          accI[j] = Ty::mfma(gv[j].y, b.x, accI[j]);
+        }
+    }
+  }
+  double2* beta = L.b + (int64_t)r * L.rhs_stride;
+#pragma unroll
+  for (int j = 0; j < TW; ++j) {
+    const int id = w + 4 * j;
+    if (id >= ntile) continue;
+    const int rb = id % a.nRB, cb = id / a.nRB;
+    const int n = 16 * cb + col;
+    if (!((tmask >> n) & 1)) continue;
+    const int ix = px + 2 * (4 * X0 + (n & 3)), iy = py + 2 * (4 * NCB * Y0 + (n >> 2));
+    const int64_t tb = ((int64_t)ix * N + iy) * N + iz;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 16 * rb + Ty::row(krow, i);
+      if (k < a.nR) beta[tb * a.nR + k] = make_double2((double)accR[j][i], (double)accI[j][i]);
+    }
+  }
+}
+
+template <typename T, int NCB>
+static hipError_t launch_cross_t2(const M2LCrossArgs& a0, int nrhs, hipStream_t s) {
+  typedef typename M2LTypes<T>::T2 T2;
+  M2LCrossArgs a = a0;
+  int total = 0;
+  for (int i = 0; i < a.nlev; ++i) {
+    M2LCrossLevel& L = a.lev[i];
+    L.tiles_x = ((L.n / 2) + 3) / 4;
+    L.tiles_y = ((L.n / 2) + 4 * NCB - 1) / (4 * NCB);
+    L.ntiles = L.n * 4 * L.tiles_x * L.tiles_y;
+    a.tile_start[i] = total;
+    total += (i == a.nlev - 1) ? 8 * ((L.ntiles + 7) / 8) : L.ntiles;
+  }
+  a.tile_start[a.nlev] = total;
+  const size_t lds = (size_t)4 * a.P2 * a.P2 * sizeof(T2) + (size_t)16 * NCB * a.nRs * sizeof(T2) +
+                     4 * (size_t)a.nKB * sizeof(int);
+  const int TW = (a.nRB * NCB + 3) / 4;
+  dim3 grid(total, nrhs), block(256);
+  void (*fn)(M2LCrossArgs) = nullptr;
+  switch (TW) {
+    case 1: fn = k_m2l_cross<T, 1, NCB>; break;
+    case 2: fn = k_m2l_cross<T, 2, NCB>; break;
+    case 3: fn = k_m2l_cross<T, 3, NCB>; break;
+    case 4: fn = k_m2l_cross<T, 4, NCB>; break;
+    case 5: fn = k_m2l_cross<T, 5, NCB>; break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_m2l_cross(const M2LCrossArgs& a, int nrhs, bool fp32, hipStream_t s) {
+  if (a.nlev < 1 || a.nlev > M2L_MAX_LEVELS) return hipErrorInvalidValue;
+  return fp32 ? launch_cross_t2<float, 1>(a, nrhs, s) : launch_cross_t2<double, 1>(a, nrhs, s);
+}
+
 hipError_t launch_m2l(const M2LArgs& a, int nrhs, bool fp32, hipStream_t s) {
   if (a.nlev < 1 || a.nlev > M2L_MAX_LEVELS) return hipErrorInvalidValue;
   return fp32 ? launch_t<float>(a, nrhs, s) : launch_t<double>(a, nrhs, s);

@@ -306,6 +306,23 @@ static bool eigenvalues(CMat H, std::vector<cplx>& ev) {
   return true;
 }
 
+bool residues_ls(const std::vector<cplx>& y, const std::vector<cplx>& w, std::vector<cplx>& r, std::string& err) {
+  const int N = (int)y.size(), M = (int)w.size();
+  r.assign(M, cplx(0, 0));
+  if (M == 0) return true;
+  CMat Vd(N, M), rhs(N, 1), res;
+  for (int n = 0; n < N; ++n) {
+    rhs(n, 0) = y[n];
+    for (int i = 0; i < M; ++i) Vd(n, i) = std::pow(w[i], (double)n);
+  }
+  if (!householder_lstsq(Vd, rhs, res)) {
+    err = "pencil: singular Vandermonde";
+    return false;
+  }
+  for (int i = 0; i < M; ++i) r[i] = res(i, 0);
+  return true;
+}
+
 bool pencil_fit(const std::vector<cplx>& y, double svd_tol, int max_terms, PencilFit& out,
                 std::string& err) {
   const int N = (int)y.size();
@@ -371,8 +388,36 @@ bool two_level_dcim(F theta, double k, double T0, double T1, int samples, double
     y1[n] = theta(kz1[n]);
     ymax = std::max(ymax, std::abs(y1[n]));
   }
+  const double dt2 = T0 / (samples - 1);
+  std::vector<cplx> y2(samples), kz2(samples), full2(samples);
+  for (int n = 0; n < samples; ++n) {
+    const double t = n * dt2;
+    kz2[n] = k * cplx(1.0 - t / T0, t);
+    full2[n] = theta(kz2[n]);
+    ymax = std::max(ymax, std::abs(full2[n]));
+  }
+  // a spectral function that vanishes to rounding (e.g. a wave that a uniform
+  // medium does not produce) has no images
+  if (!(ymax > 1e-13)) {
+    out.fit_err = 0.0;
+    return true;
+  }
   PencilFit f1;
   if (!pencil_fit(y1, svd_tol, samples / 2, f1, err)) return false;
+  // An image is usable only if its depth has Re Z < 0 (then Re(zeta) > 0 wherever
+  // the kernel is evaluated, as the Sommerfeld identity requires); other poles are
+  // dropped and the residues re-solved on the same samples.
+  auto keep_valid = [&](PencilFit& f, const std::vector<cplx>& y, auto zmap) {
+    std::vector<cplx> w;
+    for (size_t i = 0; i < f.w.size(); ++i) {
+      const cplx Z = zmap(f.w[i]);
+      if (std::isfinite(Z.real()) && std::isfinite(Z.imag()) && Z.real() < -1e-12) w.push_back(f.w[i]);
+    }
+    if (w.size() == f.w.size()) return true;
+    f.w = w;
+    return residues_ls(y, f.w, f.r, err);
+  };
+  if (!keep_valid(f1, y1, [&](cplx w) { return std::log(w) / (k * dt1); })) return false;
   for (size_t i = 0; i < f1.w.size(); ++i) {
     cplx Z = std::log(f1.w[i]) / (k * dt1);
     out.Z.push_back(Z);
@@ -380,13 +425,7 @@ bool two_level_dcim(F theta, double k, double T0, double T1, int samples, double
   }
   const size_t n1 = out.A.size();
   // level 2: k_z = k (1 - t/T0 + i t), 0 <= t <= T0, after removing level 1
-  const double dt2 = T0 / (samples - 1);
-  std::vector<cplx> y2(samples), kz2(samples), full2(samples);
   for (int n = 0; n < samples; ++n) {
-    double t = n * dt2;
-    kz2[n] = k * cplx(1.0 - t / T0, t);
-    full2[n] = theta(kz2[n]);
-    ymax = std::max(ymax, std::abs(full2[n]));
     cplx s(0, 0);
     for (size_t i = 0; i < n1; ++i) s += out.A[i] * std::exp(-I * kz2[n] * out.Z[i]);
     y2[n] = full2[n] - s;
@@ -394,6 +433,7 @@ bool two_level_dcim(F theta, double k, double T0, double T1, int samples, double
   PencilFit f2;
   if (!pencil_fit(y2, svd_tol, samples / 2, f2, err)) return false;
   const cplx g = -I * k * cplx(-1.0 / T0, 1.0) * dt2;  // w = exp(g Z)
+  if (!keep_valid(f2, y2, [&](cplx w) { return std::log(w) / g; })) return false;
   for (size_t i = 0; i < f2.w.size(); ++i) {
     cplx Z = std::log(f2.w[i]) / g;
     out.Z.push_back(Z);
@@ -451,6 +491,43 @@ bool same_layer_family(const MediumDesc& med, int l, int family, double z_lo, do
     cplx krho = std::sqrt(cplx(kl * kl, 0) - kzl * kzl);
     reaction_densities(med, l, krho, sig);
     return sig[l * 4 + ab] * std::exp(I * kzl * zmin);
+  };
+  ImageSet im;
+  if (!two_level_dcim(theta, kl, T0, T1, samples, svd_tol, im, err)) return false;
+  fit_err = im.fit_err;
+  for (size_t i = 0; i < im.A.size(); ++i) {
+    amp.push_back(im.A[i]);
+    depth.push_back(zmin + im.Z[i]);
+  }
+  return true;
+}
+
+bool cross_layer_fit(const MediumDesc& med, int l, int lp, int a, double zs, int k3p, double z_lo, double z_hi,
+                     double T1, int samples, double svd_tol, std::vector<cplx>& amp, std::vector<cplx>& depth,
+                     double& fit_err, std::string& err) {
+  amp.clear(), depth.clear();
+  fit_err = 0.0;
+  const int L = med.L;
+  if (l == lp || (a == 0 && l >= L) || (a == 1 && l == 0)) return true;
+  double zmin = a == 0 ? z_lo - med.d[l] : med.d[l - 1] - z_hi;
+  zmin = std::max(zmin, 0.0);
+  const double kl = med.k[l];
+  double kmax = 0;
+  for (double kk : med.k) kmax = std::max(kmax, kk);
+  const double T0 = std::sqrt(((kmax + 0.8) / kl) * ((kmax + 0.8) / kl) - 1.0);
+  const cplx I(0, 1);
+  double kf = 1.0;
+  for (int i = 2; i <= k3p; ++i) kf *= i;
+  std::vector<cplx> sig;
+  auto theta = [&](cplx kzl) {
+    const cplx krho = std::sqrt(cplx(kl * kl, 0) - kzl * kzl);
+    reaction_densities(med, lp, krho, sig);
+    const cplx kzp = vertical_wavenumber(med.k[lp], krho);
+    cplx s(0, 0);
+    const int ai = a == 0 ? 0 : 2;  // uu/ud or du/dd
+    if (lp < L) s += sig[l * 4 + ai + 0] * std::pow(I * kzp, (double)k3p) * std::exp(I * kzp * (zs - med.d[lp]));
+    if (lp > 0) s += sig[l * 4 + ai + 1] * std::pow(-I * kzp, (double)k3p) * std::exp(I * kzp * (med.d[lp - 1] - zs));
+    return s / kf * std::exp(I * kzl * zmin);
   };
   ImageSet im;
   if (!two_level_dcim(theta, kl, T0, T1, samples, svd_tol, im, err)) return false;

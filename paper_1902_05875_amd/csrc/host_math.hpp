@@ -38,6 +38,8 @@ struct PencilFit {
 };
 bool pencil_fit(const std::vector<cplx>& y, double svd_tol, int max_terms, PencilFit& out,
                 std::string& err);
+// Least-squares residues r for fixed poles w:  y_n ~ sum_i r_i w_i^n.
+bool residues_ls(const std::vector<cplx>& y, const std::vector<cplx>& w, std::vector<cplx>& r, std::string& err);
 
 // Complex images of a spectral function  Theta(k_z) ~ sum_j A_j exp(-i k_z Z_j)
 // (Eq. compleximageapp) by the paper's two-level sampling (paths C_ap1, C_ap2).
@@ -55,5 +57,15 @@ bool two_level_dcim(F theta, double k, double T0, double T1, int samples, double
 bool same_layer_family(const MediumDesc& med, int l, int family, double z_lo, double z_hi,
                        double T1, int samples, double svd_tol, std::vector<cplx>& amp,
                        std::vector<cplx>& depth, double& fit_err, std::string& err);
+
+// Cross-layer complex images (Sec. 3.3, the paper's per source height and per
+// z' derivative fits): target layer l, source layer lp != l, target-side wave
+// a (0 = up-going, needs l < L; 1 = down-going, needs l > 0), source height zs,
+// z' derivative order k3p.  The kernel  d^{k3p}/dz'^{k3p} G^{(a)}_{l,lp}(r, r') / k3p!
+// at z' = zs is  sum_j A_j e^{i k_l R_j} / (4 pi R_j),
+// R_j = sqrt(rho^2 + (Z_a(z) - depth_j)^2),  Z_up(z) = z - d_l,  Z_dn(z) = d_{l-1} - z.
+bool cross_layer_fit(const MediumDesc& med, int l, int lp, int a, double zs, int k3p, double z_lo, double z_hi,
+                     double T1, int samples, double svd_tol, std::vector<cplx>& amp, std::vector<cplx>& depth,
+                     double& fit_err, std::string& err);
 
 }  // namespace tefmm

@@ -3,7 +3,8 @@
 Calls only oracle/ (and the seeded input generators).  Usage:
     python tests/golden/make_expected.py [case ...]
 Cases: c1 (N=1000, all targets), c2s (N=200,000, 64 sampled targets),
-c4s (N=1,000,000, 16 sampled targets), n20k (N=20,000, 128 sampled targets).
+c4s (N=1,000,000, 16 sampled targets), n20k (N=20,000, 128 sampled targets),
+c3small (three layers, N=3000, 300 targets), c3s (three layers, N=1,000,000, 6 targets per layer).
 Output: tests/golden/expected_<case>.txt with columns  index  re  im.
 """
 from __future__ import annotations
@@ -40,6 +41,17 @@ def case_spec(name):
     if name == "c4s":
         xyz, q = inputs.workload("c4")
         return xyz, q, inputs.sample_targets(xyz, 12, 4, seed=104)
+    if name == "c3small":
+        xyz, q = inputs.workload("c3", n=3000)
+        rng = np.random.default_rng(130)
+        return xyz, q, np.sort(rng.choice(3000, size=300, replace=False))
+    if name == "c3s":
+        xyz, q = inputs.workload("c3")
+        med_d = np.asarray(inputs.MEDIUM_D)
+        lay = np.sum(xyz[:, 2:3] < med_d[None, :], axis=1)
+        rng = np.random.default_rng(103)
+        tg = np.concatenate([rng.choice(np.nonzero(lay == l)[0], size=6, replace=False) for l in range(3)])
+        return xyz, q, np.sort(tg)
     if name == "n20k":
         xyz, q = inputs.workload("c2", n=20_000)
         return xyz, q, inputs.sample_targets(xyz, 96, 32, seed=120)
