@@ -30,12 +30,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "target evals/sec at N=1M, rel err≤1e-4: surrogate+FP32 vs plain FP64 FMM"
 PEAK = {"fp64": 78.6, "fp32": 157.3}  # TFLOP/s, dense MFMA, MI355X published
+SHAPES = {"c1": "uniform unit cube centred (0,0,-0.6)", "c2": "uniform unit cube centred (0,0,-0.6)",
+          "c4": "uniform unit cube centred (0,0,-0.6)", "c5": "uniform unit cube centred (0,0,-0.6)",
+          "c3": "split over three unit cubes centred (0,0,0.6), (0,0,-0.6), (0,0,-1.8), one per layer"}
 
 
 def _sampled_error(workload, phi):
     """Relative 2-norm error on the targets whose oracle values are stored (if any)."""
     import numpy as np
-    name = {"c4": "c4s", "c2": "c2s", "c1": "c1"}.get(workload)
+    name = {"c4": "c4s", "c2": "c2s", "c1": "c1", "c3": "c3s"}.get(workload)
     path = os.path.join(ROOT, "tests", "golden", f"expected_{name}.txt") if name else None
     if not path or not os.path.exists(path):
         return None, 0
@@ -146,7 +149,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c4", help="c4: N=1M mid-layer cube (default); c2: N=200k")
+    ap.add_argument("--workload", default="c4",
+                    help="c4: N=1M mid-layer cube (default); c2: N=200k; c3: N=1M over three layers")
     ap.add_argument("--n", type=int, default=None, help="override N (same recipe)")
     ap.add_argument("--p64", type=int, default=12, help="Taylor order of the plain FP64 mode")
     ap.add_argument("--p32", type=int, default=8, help="Taylor order of the mixed FP32 mode")
@@ -191,7 +195,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if head["precision"] == "fp32" else "f64", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: N={N} uniform unit cube centred (0,0,-0.6), 3 layers "
+        "config": {"workload": f"{args.workload}: N={N} {SHAPES.get(args.workload, '')}, 3 layers "
                                f"(d=0,-1.2; k=0.8,1.5,2.0), {qm.shape[0]} complex charge vector(s)",
                    "p": head["p"], "precision": head["precision"], "max_leaf": args.max_leaf,
                    "depth": head["depth"], "parallelism": "single GPU"},

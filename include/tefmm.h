@@ -48,6 +48,11 @@ enum {
   TEFMM_ERR_STATE = -7
 };
 
+/* Precision.  TEFMM_FP64: every step in FP64.  TEFMM_MIXED_FP32: the M2L
+ * contractions (FP32 MFMA, FP32 accumulation within one launch) and the P2P
+ * sums run in FP32, with pairs closer than 5% of the leaf side redone in FP64;
+ * complex-image fits, table generation, P2M/M2M/L2L/L2P and the final
+ * accumulation of the potential stay FP64. */
 enum { TEFMM_FP64 = 0, TEFMM_MIXED_FP32 = 1 };
 enum { TEFMM_NORM_PHYSICAL = 0, TEFMM_NORM_PAPER = 1 };
 

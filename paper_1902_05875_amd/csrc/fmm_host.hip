@@ -1187,7 +1187,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
   EVREC(5);
   for (auto& g : h->groups) {
     PassArgs a = pass_args(g);
-    a.nbox_dim = 1 << g.depth;
+    a.nbox_dim = 1 << g.depth, a.h = g.side / (1 << g.depth);
     if (fp32)
       hipLaunchKernelGGL(k_p2p<float>, dim3((unsigned)g.nbox[g.depth], nrhs), dim3(64), 0, s, a);
     else

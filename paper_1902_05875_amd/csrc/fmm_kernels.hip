@@ -675,11 +675,14 @@ __global__ __launch_bounds__(64) void k_p2p(PassArgs a) {
   const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
   const double2* q = a.q + (int64_t)r * a.n;
   const T k = (T)a.k;
+  // pairs closer than 5% of the leaf side are evaluated in FP64 in the FP32 path
+  const T rns2 = (T)(0.0025 * a.h * a.h);
   for (int c0 = 0; c0 < cnt; c0 += 64) {
     const bool act = c0 + tid < cnt;
     const int64_t i = start + c0 + tid;
     const double txd = act ? a.xs[i] : 0.0, tyd = act ? a.xs[a.n + i] : 0.0, tzd = act ? a.xs[2 * a.n + i] : 0.0;
     T accr = 0, acci = 0;
+    double nsr = 0.0, nsi = 0.0;  // near-singular pairs (FP32 path only)
     for (int nbh = 0; nbh < 27; ++nbh) {
       const int jx = ix + nbh / 9 - 1, jy = iy + (nbh / 3) % 3 - 1, jz = iz + nbh % 3 - 1;
       if (jx < 0 || jy < 0 || jz < 0 || jx >= nb || jy >= nb || jz >= nb) continue;
@@ -705,6 +708,18 @@ __global__ __launch_bounds__(64) void k_p2p(PassArgs a) {
             const T dx = tx - sx[t], dy = ty - sy[t], dz = tz - sz[t];
             const T r2 = dx * dx + dy * dy + dz * dz;
             if (sidx[t] == (int)i) continue;
+            if (sizeof(T) == 4 && r2 < rns2) {
+              // near-singular pair: the FP32 difference has lost digits, redo it in FP64
+              const int64_t j = sidx[t];
+              const double ex = txd - a.xs[j], ey = tyd - a.xs[a.n + j], ez = tzd - a.xs[2 * a.n + j];
+              const double rd = sqrt(ex * ex + ey * ey + ez * ez);
+              double sn, cs;
+              sincos(a.k * rd, &sn, &cs);
+              const double er = cs / rd, ei = sn / rd;
+              nsr += q[j].x * er - q[j].y * ei;
+              nsi += q[j].x * ei + q[j].y * er;
+              continue;
+            }
             const T rr = sqrt(r2);
             const T inv = (T)1 / rr;
             T sn, cs;
@@ -718,7 +733,7 @@ __global__ __launch_bounds__(64) void k_p2p(PassArgs a) {
     }
     if (act) {
       double2 o = a.phi[(int64_t)r * a.n + i];
-      a.phi[(int64_t)r * a.n + i] = make_double2(o.x + (double)accr, o.y + (double)acci);
+      a.phi[(int64_t)r * a.n + i] = make_double2(o.x + (double)accr + nsr, o.y + (double)acci + nsi);
     }
   }
 }

@@ -89,6 +89,21 @@ def workload(name: str, n: int | None = None, n_rhs: int | None = None):
     raise ValueError(name)
 
 
+def with_close_pairs(xyz, q, n_pairs, dist, seed):
+    """Append n_pairs particles, each at distance `dist` (random direction) from a
+    randomly chosen existing particle, with fresh U[-1,1] complex charges.  Returns
+    (xyz, q, partners): partners[i] = (existing index, new index)."""
+    rng = np.random.default_rng(seed)
+    n = xyz.shape[0]
+    base = rng.choice(n, size=n_pairs, replace=False)
+    v = rng.normal(size=(n_pairs, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    new = xyz[base] + dist * v
+    qn = charges(rng, n_pairs)
+    pairs = np.column_stack([base, n + np.arange(n_pairs)])
+    return np.concatenate([xyz, new]), np.concatenate([q, qn]), pairs
+
+
 def c5_geometries(count=16, seed=50):
     """The 16 independent geometries of the batched workload: sizes log-uniform in
     [1e4, 3e5]; even entries are unit cubes, odd ones Example-2 domains with

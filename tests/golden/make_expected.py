@@ -4,7 +4,8 @@ Calls only oracle/ (and the seeded input generators).  Usage:
     python tests/golden/make_expected.py [case ...]
 Cases: c1 (N=1000, all targets), c2s (N=200,000, 64 sampled targets),
 c4s (N=1,000,000, 16 sampled targets), n20k (N=20,000, 128 sampled targets),
-c3small (three layers, N=3000, 300 targets), c3s (three layers, N=1,000,000, 6 targets per layer).
+c3small (three layers, N=3000, 300 targets), c3s (three layers, N=1,000,000, 6 targets per layer),
+c1ns (c1 plus 24 particles at distance 1e-6 from existing ones; the 48 particles of those pairs).
 Output: tests/golden/expected_<case>.txt with columns  index  re  im.
 """
 from __future__ import annotations
@@ -52,6 +53,10 @@ def case_spec(name):
         rng = np.random.default_rng(103)
         tg = np.concatenate([rng.choice(np.nonzero(lay == l)[0], size=6, replace=False) for l in range(3)])
         return xyz, q, np.sort(tg)
+    if name == "c1ns":
+        xyz, q = inputs.workload("c1")
+        xyz, q, pairs = inputs.with_close_pairs(xyz, q, 24, 1e-6, seed=140)
+        return xyz, q, np.sort(pairs.ravel())
     if name == "n20k":
         xyz, q = inputs.workload("c2", n=20_000)
         return xyz, q, inputs.sample_targets(xyz, 96, 32, seed=120)

@@ -144,3 +144,18 @@ def test_errors_reported():
         f.evaluate(torch.zeros(3, dtype=torch.complex128, device="cuda"))
     assert e.value.code in (-7, -1)
     f.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_near_singular_pairs(precision):
+    """C1 plus 24 particles 1e-6 from existing ones: the close pairs dominate the
+    potential of their 48 particles.  In the FP32 path their coordinate
+    differences would keep ~2 digits; they are redone in FP64 (E1)."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c1")
+    xyz, q, _ = inputs.with_close_pairs(xyz, q, 24, 1e-6, seed=140)
+    idx, ref = _expected("c1ns")
+    phi, st = _run(xyz, q, p=8, depth=2, precision=precision)
+    e = _err(phi[idx], ref)
+    print(f"near-singular pairs {precision}: rel err {e:.3e}")
+    assert e < 1e-6
