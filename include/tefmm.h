@@ -229,6 +229,47 @@ int tefmm_get_tree(tefmm_t h, int g, int* layer, int* depth, double* centre3, do
  * and FP32 on the GPU and returns 0 when the results match the host. */
 int tefmm_selftest_mfma(void);
 
+/* ------------------------------------------------------------------------
+ * Surrogate network (an extension beyond the paper: a learned replacement for
+ * the reaction derivative tables, trained from the method's own complex-image
+ * tables).  A fully connected tanh network
+ *   a_0 = x,  a_{l+1} = tanh(W_l a_l + b_l)  (l < n_hidden, width units),
+ *   y = W_out a_{n_hidden} + b_out,
+ * trained on the mean-squared loss L = mean over samples and outputs of
+ * (y - t)^2 with Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ * Matrix products use BF16 operands with FP32 accumulation on the matrix
+ * cores; the first layer and its gradient are FP32; weights, gradients and
+ * moments are FP32.  Parameter vector (float): W_0, b_0, W_1, b_1, ...,
+ * W_out, b_out, matrices row-major with W[j][i] the weight from input i to
+ * unit j.  Data arrays are device memory, row-major, one row per sample.
+ * Calls are stream ordered on `stream` unless stated; one handle serves one
+ * stream at a time.
+ * ------------------------------------------------------------------------ */
+typedef struct tefmm_mlp* tefmm_mlp_t;
+
+/* Create a network (n_in <= 4, width <= 4096, 1 <= n_hidden <= 16) with
+ * Glorot-uniform weights from `seed` and zero biases. */
+int tefmm_mlp_create(tefmm_mlp_t* out, int n_in, int width, int n_hidden, int n_out, uint64_t seed);
+void tefmm_mlp_destroy(tefmm_mlp_t m);
+int64_t tefmm_mlp_num_params(tefmm_mlp_t m);
+const char* tefmm_mlp_last_error(tefmm_mlp_t m);
+/* Host parameter vectors (num_params floats); set also clears the Adam state. */
+int tefmm_mlp_set_params(tefmm_mlp_t m, const float* theta_host);
+int tefmm_mlp_get_params(tefmm_mlp_t m, float* theta_host);
+/* y[n x n_out] = network(x[n x n_in]) (device arrays). */
+int tefmm_mlp_forward(tefmm_mlp_t m, const float* x, int64_t n, float* y, void* stream);
+/* Loss of (x, t) (device, n rows) and its gradient: *loss and grad_host
+ * (num_params floats) on the host, either may be NULL.  Synchronous. */
+int tefmm_mlp_loss_grad(tefmm_mlp_t m, const float* x, const float* t, int64_t n, double* loss, float* grad_host,
+                        void* stream);
+/* One Adam step with the gradient of the last tefmm_mlp_loss_grad.  Synchronous. */
+int tefmm_mlp_adam_step(tefmm_mlp_t m, float lr, void* stream);
+/* Minibatch Adam over (x, t) (device, n rows): `epochs` passes in a shuffled
+ * order (seeded), batches of `batch` rows.  epoch_loss (host, epochs
+ * doubles, may be NULL) gets each epoch's mean batch loss.  Synchronous. */
+int tefmm_mlp_train(tefmm_mlp_t m, const float* x, const float* t, int64_t n, int epochs, int batch, float lr,
+                    uint64_t seed, double* epoch_loss, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

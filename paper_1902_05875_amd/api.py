@@ -23,7 +23,10 @@ ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "PARTICLE_ON_INTERFACE", -3: "UNSUPPOR
 EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefmm_evaluate",
            "tefmm_get_stats", "tefmm_last_error", "tefmm_destroy", "tefmm_densities",
            "tefmm_dcim_family", "tefmm_taylor_coefficients", "tefmm_get_moments", "tefmm_get_tree",
-           "tefmm_selftest_mfma", "tefmm_evaluate_batch", "tefmm_autotune", "tefmm_dcim_cross"]
+           "tefmm_selftest_mfma", "tefmm_evaluate_batch", "tefmm_autotune", "tefmm_dcim_cross",
+           "tefmm_mlp_create", "tefmm_mlp_destroy", "tefmm_mlp_num_params", "tefmm_mlp_last_error",
+           "tefmm_mlp_set_params", "tefmm_mlp_get_params", "tefmm_mlp_forward", "tefmm_mlp_loss_grad",
+           "tefmm_mlp_adam_step", "tefmm_mlp_train"]
 
 
 class TefmmError(RuntimeError):
@@ -91,6 +94,19 @@ def lib():
         L.tefmm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.tefmm_dcim_cross.argtypes = [ctypes.POINTER(MediumC), ctypes.POINTER(OptionsC), i32, i32, i32, dbl, i32,
                                        dbl, dbl, i32, ctypes.POINTER(i32), vp, vp, ctypes.POINTER(dbl)]
+        L.tefmm_mlp_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, ctypes.c_uint64]
+        L.tefmm_mlp_destroy.argtypes = [vp]
+        L.tefmm_mlp_destroy.restype = None
+        L.tefmm_mlp_num_params.argtypes = [vp]
+        L.tefmm_mlp_num_params.restype = i64
+        L.tefmm_mlp_last_error.argtypes = [vp]
+        L.tefmm_mlp_last_error.restype = ctypes.c_char_p
+        L.tefmm_mlp_set_params.argtypes = [vp, vp]
+        L.tefmm_mlp_get_params.argtypes = [vp, vp]
+        L.tefmm_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.tefmm_mlp_loss_grad.argtypes = [vp, vp, vp, i64, ctypes.POINTER(dbl), vp, vp]
+        L.tefmm_mlp_adam_step.argtypes = [vp, ctypes.c_float, vp]
+        L.tefmm_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float, ctypes.c_uint64, vp, vp]
         _lib = L
     return _lib
 
@@ -290,3 +306,73 @@ def taylor_coefficients(x, y, zeta, k, h, order):
 
 def selftest_mfma() -> int:
     return lib().tefmm_selftest_mfma()
+
+
+class MLP:
+    """The surrogate network through the C ABI (device tensors in, device tensors out)."""
+
+    def __init__(self, n_in, width, n_hidden, n_out, seed=0):
+        self.h = ctypes.c_void_p()
+        rc = lib().tefmm_mlp_create(ctypes.byref(self.h), n_in, width, n_hidden, n_out, seed)
+        if rc != 0:
+            raise TefmmError(rc, "mlp_create")
+        self.dims = (n_in, width, n_hidden, n_out)
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise TefmmError(rc, lib().tefmm_mlp_last_error(self.h).decode())
+
+    @property
+    def num_params(self):
+        return int(lib().tefmm_mlp_num_params(self.h))
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, np.float32)
+        assert th.size == self.num_params
+        self._chk(lib().tefmm_mlp_set_params(self.h, th.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self):
+        th = np.empty(self.num_params, np.float32)
+        self._chk(lib().tefmm_mlp_get_params(self.h, th.ctypes.data_as(ctypes.c_void_p)))
+        return th
+
+    def forward(self, x, stream=None):
+        import torch
+        x = x.contiguous().float()
+        y = torch.empty(x.shape[0], self.dims[3], dtype=torch.float32, device=x.device)
+        self._chk(lib().tefmm_mlp_forward(self.h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                          ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)))
+        return y
+
+    def loss_grad(self, x, t, stream=None):
+        x = x.contiguous().float()
+        t = t.contiguous().float()
+        g = np.empty(self.num_params, np.float32)
+        L = ctypes.c_double()
+        self._chk(lib().tefmm_mlp_loss_grad(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                            x.shape[0], ctypes.byref(L), g.ctypes.data_as(ctypes.c_void_p),
+                                            _stream_ptr(stream)))
+        return L.value, g
+
+    def adam_step(self, lr, stream=None):
+        self._chk(lib().tefmm_mlp_adam_step(self.h, float(lr), _stream_ptr(stream)))
+
+    def train(self, x, t, epochs, batch, lr, seed=0, stream=None):
+        x = x.contiguous().float()
+        t = t.contiguous().float()
+        losses = np.zeros(max(1, epochs))
+        self._chk(lib().tefmm_mlp_train(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                        x.shape[0], epochs, batch, float(lr), seed,
+                                        losses.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+        return losses[:epochs]
+
+    def close(self):
+        if self.h:
+            lib().tefmm_mlp_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
