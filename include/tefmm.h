@@ -109,6 +109,8 @@ typedef struct {
                                  unless the depth limit 7 is reached) */
   int n_cross_fits;      /* cross-layer complex-image fits of the geometry */
   double cross_fit_err;  /* their largest relative misfit on the sampling paths */
+  int64_t sigma_keys;    /* rows of the Sigma-family tables of the geometry */
+  int64_t surrogate_keys; /* of those, rows produced by the attached surrogate network */
 } tefmm_stats;
 
 /* Fill an options struct with the defaults (p = 8, depth auto, max_leaf 64,
@@ -269,6 +271,72 @@ int tefmm_mlp_adam_step(tefmm_mlp_t m, float lr, void* stream);
  * doubles, may be NULL) gets each epoch's mean batch loss.  Synchronous. */
 int tefmm_mlp_train(tefmm_mlp_t m, const float* x, const float* t, int64_t n, int epochs, int batch, float lr,
                     uint64_t seed, double* epoch_loss, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Surrogate for the Sigma-family derivative tables of one layer (the
+ * reaction component whose kernel depends on z + z', Sec. 3.2; an extension
+ * beyond the paper).  The network maps a table key position (x, y, S = z + z')
+ * inside a training box to the compact table entries, scaled by the envelope
+ * of a source at the nearer mirror distance,
+ *   W_g = D^g K(x, y, S) R_e^{|g|+1} / |g|!,  R_e = sqrt(x^2 + y^2 + Z_m^2),
+ *   Z_m = min(S - 2 d_l, 2 d_{l-1} - S),
+ * each output also divided by its RMS over the training set.  Training data
+ * are the method's own complex-image tables at n_train uniform points of the
+ * box; training is minibatch Adam on the GPU (tefmm_mlp kernels).  A
+ * validation map over cells_xy x cells_xy x cells_s cells of the box keeps a
+ * cell when the largest |W_network - W_images| over n_valid fresh points in
+ * it is <= budget.  Attached to a handle, the surrogate produces the Sigma
+ * table rows whose keys fall in kept cells; every other row (outside the box,
+ * rejected cells, other layers) comes from the complex images as before.
+ * ------------------------------------------------------------------------ */
+typedef struct tefmm_surrogate* tefmm_surrogate_t;
+
+typedef struct {
+  int layer;           /* layer whose Sigma tables are learned */
+  double x_max;        /* |x|, |y| <= x_max in the box */
+  double s_lo, s_hi;   /* z + z' range of the box (inside the layer) */
+  int n_train;         /* training points */
+  int epochs, batch;
+  float lr;
+  int width, n_hidden; /* network shape (3 -> width x n_hidden -> 2 nG) */
+  int cells_xy, cells_s, n_valid;
+  double budget;       /* largest accepted error of W in a cell */
+  uint64_t seed;
+} tefmm_surrogate_options;
+
+typedef struct {
+  int status;
+  double t_data_s, t_train_s, t_valid_s;  /* host wall time of the three phases */
+  double final_loss;                      /* mean loss of the last epoch (normalised outputs) */
+  double max_cell_err;                    /* largest cell error of W */
+  int cells_ok, cells_total;
+  int n_out;
+  int64_t n_params;
+} tefmm_surrogate_report;
+
+/* Defaults for `layer` of `medium`: x_max 0.75, S range the layer's z + z'
+ * range less 0.15 at each interface (2 units beyond the interface in a
+ * half-space), n_train 131072, 60 epochs of 1024, lr 2e-3, width 128,
+ * 4 hidden layers, 6 x 6 x 12 cells with 16 points, budget 3e-3. */
+void tefmm_surrogate_default_options(const tefmm_medium* medium, int layer, tefmm_surrogate_options* o);
+/* Fit the images of the box, generate the training and validation tables,
+ * train, build the validation map.  opt gives p and the image parameters
+ * (NULL: defaults).  epoch_loss (host, `epochs` doubles) may be NULL.
+ * Synchronous on `stream`; fails with TEFMM_ERR_UNSUPPORTED if the layer has
+ * no Sigma family, TEFMM_ERR_INVALID_ARG if the box leaves the layer. */
+int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium* medium, const tefmm_options* opt,
+                          const tefmm_surrogate_options* so, tefmm_surrogate_report* rep, double* epoch_loss,
+                          void* stream);
+void tefmm_surrogate_destroy(tefmm_surrogate_t s);
+/* ok[i] = 1 if the point (x, y, S) = xys[3i..3i+2] lies in a kept cell. */
+int tefmm_surrogate_cell_ok(tefmm_surrogate_t s, int n, const double* xys, int* ok);
+/* Largest validation error of W in each cell (cells_xy^2 cells_s doubles,
+ * cell (i, j, m) of x, y, S at (i cells_xy + j) cells_s + m). */
+int tefmm_surrogate_cell_errors(tefmm_surrogate_t s, double* err);
+/* Attach (or with NULL detach) a surrogate; it is used by the following
+ * tefmm_set_particles calls and must outlive them.  Rejects a surrogate of
+ * another order p or medium. */
+int tefmm_set_surrogate(tefmm_t h, tefmm_surrogate_t s);
 
 #ifdef __cplusplus
 }

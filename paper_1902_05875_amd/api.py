@@ -26,7 +26,8 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_selftest_mfma", "tefmm_evaluate_batch", "tefmm_autotune", "tefmm_dcim_cross",
            "tefmm_mlp_create", "tefmm_mlp_destroy", "tefmm_mlp_num_params", "tefmm_mlp_last_error",
            "tefmm_mlp_set_params", "tefmm_mlp_get_params", "tefmm_mlp_forward", "tefmm_mlp_loss_grad",
-           "tefmm_mlp_adam_step", "tefmm_mlp_train"]
+           "tefmm_mlp_adam_step", "tefmm_mlp_train", "tefmm_surrogate_default_options", "tefmm_surrogate_train",
+           "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors"]
 
 
 class TefmmError(RuntimeError):
@@ -55,7 +56,22 @@ class StatsC(ctypes.Structure):
         ("dcim_fit_err", ctypes.c_double * 8), ("depth", ctypes.c_int * 4), ("n_families", ctypes.c_int),
         ("m2l_flops", ctypes.c_double), ("m2l_launches", ctypes.c_int), ("n_rhs", ctypes.c_int),
         ("cross_pairs", ctypes.c_int64), ("cross_pairs_forced", ctypes.c_int64), ("n_cross_fits", ctypes.c_int),
-        ("cross_fit_err", ctypes.c_double)]
+        ("cross_fit_err", ctypes.c_double), ("sigma_keys", ctypes.c_int64), ("surrogate_keys", ctypes.c_int64)]
+
+
+class SurOptionsC(ctypes.Structure):
+    _fields_ = [("layer", ctypes.c_int), ("x_max", ctypes.c_double), ("s_lo", ctypes.c_double),
+                ("s_hi", ctypes.c_double), ("n_train", ctypes.c_int), ("epochs", ctypes.c_int),
+                ("batch", ctypes.c_int), ("lr", ctypes.c_float), ("width", ctypes.c_int), ("n_hidden", ctypes.c_int),
+                ("cells_xy", ctypes.c_int), ("cells_s", ctypes.c_int), ("n_valid", ctypes.c_int),
+                ("budget", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class SurReportC(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("t_data_s", ctypes.c_double), ("t_train_s", ctypes.c_double),
+                ("t_valid_s", ctypes.c_double), ("final_loss", ctypes.c_double), ("max_cell_err", ctypes.c_double),
+                ("cells_ok", ctypes.c_int), ("cells_total", ctypes.c_int), ("n_out", ctypes.c_int),
+                ("n_params", ctypes.c_int64)]
 
 
 _lib = None
@@ -107,6 +123,15 @@ def lib():
         L.tefmm_mlp_loss_grad.argtypes = [vp, vp, vp, i64, ctypes.POINTER(dbl), vp, vp]
         L.tefmm_mlp_adam_step.argtypes = [vp, ctypes.c_float, vp]
         L.tefmm_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float, ctypes.c_uint64, vp, vp]
+        L.tefmm_surrogate_default_options.argtypes = [ctypes.POINTER(MediumC), i32, ctypes.POINTER(SurOptionsC)]
+        L.tefmm_surrogate_default_options.restype = None
+        L.tefmm_surrogate_train.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(MediumC), ctypes.POINTER(OptionsC),
+                                            ctypes.POINTER(SurOptionsC), ctypes.POINTER(SurReportC), vp, vp]
+        L.tefmm_surrogate_destroy.argtypes = [vp]
+        L.tefmm_surrogate_destroy.restype = None
+        L.tefmm_surrogate_cell_ok.argtypes = [vp, i32, vp, vp]
+        L.tefmm_set_surrogate.argtypes = [vp, vp]
+        L.tefmm_surrogate_cell_errors.argtypes = [vp, vp]
         _lib = L
     return _lib
 
@@ -165,6 +190,11 @@ class TEFMM:
             self.close()
         except Exception:
             pass
+
+    def set_surrogate(self, sur):
+        """Attach a trained Surrogate (or None); used by the following set_particles calls."""
+        self._sur = sur
+        _check(lib().tefmm_set_surrogate(self.h, sur.h if sur is not None else None), self.h)
 
     def set_particles(self, xyz, stream=None):
         """xyz: torch float64 tensor (N, 3) on the GPU (copied to SoA) or numpy (N, 3)."""
@@ -369,6 +399,54 @@ class MLP:
     def close(self):
         if self.h:
             lib().tefmm_mlp_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Surrogate:
+    """Trained surrogate for the Sigma tables of one layer (tefmm_surrogate_train)."""
+
+    def __init__(self, k, d, layer, p=8, stream=None, **overrides):
+        med = _medium(k, d)
+        so = SurOptionsC()
+        lib().tefmm_surrogate_default_options(ctypes.byref(med), layer, ctypes.byref(so))
+        for name, v in overrides.items():
+            setattr(so, name, v)
+        opt = default_options(p=p)
+        self.h = ctypes.c_void_p()
+        rep = SurReportC()
+        losses = np.zeros(max(1, so.epochs))
+        rc = lib().tefmm_surrogate_train(ctypes.byref(self.h), ctypes.byref(med), ctypes.byref(opt), ctypes.byref(so),
+                                         ctypes.byref(rep), losses.ctypes.data_as(ctypes.c_void_p),
+                                         _stream_ptr(stream))
+        if rc != 0:
+            raise TefmmError(rc, "surrogate_train")
+        self.options = {f[0]: getattr(so, f[0]) for f in SurOptionsC._fields_}
+        self.report = {f[0]: getattr(rep, f[0]) for f in SurReportC._fields_}
+        self.losses = losses[: so.epochs]
+        self.p = p
+
+    def cell_ok(self, xys):
+        xys = np.ascontiguousarray(xys, np.float64).reshape(-1, 3)
+        ok = np.zeros(xys.shape[0], np.int32)
+        _check(lib().tefmm_surrogate_cell_ok(self.h, xys.shape[0], xys.ctypes.data_as(ctypes.c_void_p),
+                                             ok.ctypes.data_as(ctypes.c_void_p)))
+        return ok.astype(bool)
+
+    def cell_errors(self):
+        o = self.options
+        e = np.zeros(o["cells_xy"] * o["cells_xy"] * o["cells_s"])
+        _check(lib().tefmm_surrogate_cell_errors(self.h, e.ctypes.data_as(ctypes.c_void_p)))
+        return e.reshape(o["cells_xy"], o["cells_xy"], o["cells_s"])
+
+    def close(self):
+        if self.h:
+            lib().tefmm_surrogate_destroy(self.h)
             self.h = ctypes.c_void_p()
 
     def __del__(self):

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <hipcub/hipcub.hpp>
@@ -25,6 +26,7 @@
 #include "fmm_kernels.hpp"
 #include "host_math.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 
 namespace tefmm {
 bool medium_from_desc(const tefmm_medium* m, MediumDesc& out, std::string& err);
@@ -106,9 +108,11 @@ struct tefmm_ctx {
   tefmm_stats st;
   std::vector<hipEvent_t> ev;
   int64_t p2p_pairs = 0, m2l_pairs = 0;
+  int64_t sigma_keys = 0, sur_keys = 0;  // Sigma table rows of the geometry / answered by the surrogate
   // copy of the caller's positions (SoA), kept for re-building the tree (autotuner)
   double* d_xyz_user = nullptr;
   int m2l_ncb = 0;  // M2L tile width override (0 = automatic)
+  tefmm_surrogate* sur = nullptr;  // surrogate for the Sigma tables (borrowed)
   uint64_t gen = 0; // changes whenever device buffers are (re)allocated
   // graph of the last batched evaluation
   struct Batch {
@@ -321,6 +325,15 @@ extern "C" void tefmm_destroy(tefmm_t h) {
 
 extern "C" const char* tefmm_last_error(tefmm_t h) { return h ? h->err.c_str() : "null handle"; }
 
+struct SigmaKeys {
+  std::vector<int> key;                // table row
+  std::vector<double> X, Y, S, Re;     // key geometry and envelope distance
+};
+static int surrogate_tables(tefmm_t h, const SigmaKeys& sk, double hb, double2* d_out, hipStream_t s);
+static bool surrogate_accepts(const tefmm_surrogate* su, double X, double Y, double S);
+static bool surrogate_applies(const tefmm_surrogate* su, int layer, bool up, bool dn);
+static double sigma_envelope(const MediumDesc& med, int l, bool up, bool dn, double X, double Y, double S);
+
 // ---------------------------------------------------------------------------
 // Derivative tables of one group (all levels).
 // ---------------------------------------------------------------------------
@@ -343,6 +356,7 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
       std::vector<TableTerm> terms;
       std::vector<int> start;
       std::vector<double> hk;
+      SigmaKeys sk;
       int nkeys;
       auto push = [&](double x, double y, cplx zeta, cplx coef, int flip, bool image) {
         // an image term is valid only for Re(zeta) > 0; keys failing this join
@@ -375,12 +389,20 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
             }
       } else {
         nkeys = 49 * (2 * nb - 1);
+        const bool use_sur = h->sur && surrogate_applies(h->sur, l_, g.has[0], g.has[1]);
         for (int dx = -3; dx <= 3; ++dx)
           for (int dy = -3; dy <= 3; ++dy)
             for (int m = 0; m <= 2 * nb - 2; ++m) {
               start.push_back((int)terms.size());
               hk.push_back(hb);
               const double S = 2 * g.lo[2] + (m + 1) * hb;
+              if (use_sur && surrogate_accepts(h->sur, -dx * hb, -dy * hb, S)) {
+                // answered by the network after the image tables are generated
+                sk.key.push_back((int)start.size() - 1);
+                sk.X.push_back(-dx * hb), sk.Y.push_back(-dy * hb), sk.S.push_back(S);
+                sk.Re.push_back(sigma_envelope(med, l_, g.has[0], g.has[1], -dx * hb, -dy * hb, S));
+                continue;
+              }
               if (g.has[0])
                 for (size_t j = 0; j < g.famA[0].size(); ++j)
                   push(-dx, -dy, (S - 2 * med.d[l_] - g.famZ[0][j]) / hb, g.famA[0][j], 0, true);
@@ -413,6 +435,15 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
       dfree(d_terms);
       dfree(d_start);
       dfree(d_h);
+      if (!sk.key.empty()) {
+        int rc = surrogate_tables(h, sk, hb, d_out, s);
+        if (rc != TEFMM_OK) {
+          dfree(d_out);
+          return rc;
+        }
+        h->sur_keys += (int64_t)sk.key.size();
+      }
+      if (which == 1) h->sigma_keys += nkeys;
       if (which == 0)
         g.Tfd[lev] = d_out;
       else
@@ -933,6 +964,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     }
   }
   // derivative tables
+  h->sigma_keys = 0, h->sur_keys = 0;
   for (auto& g : h->groups) {
     int rc = build_tables(h, g, s);
     if (rc != TEFMM_OK) return rc;
@@ -964,6 +996,8 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
       }
   }
   h->st.n_families = fi;
+  h->st.sigma_keys = h->sigma_keys;
+  h->st.surrogate_keys = h->sur_keys;
   for (auto& g : h->groups) {
     h->st.cross_pairs += g.cross_pairs;
     h->st.cross_pairs_forced += g.cross_forced;
@@ -1455,4 +1489,402 @@ extern "C" int tefmm_selftest_mfma(void) {
       if (std::abs(h32[m * 16 + nn] - ref) > 1e-5 * std::abs(ref)) bad |= 2;
     }
   return bad;
+}
+
+// ---------------------------------------------------------------------------
+// Surrogate for the Sigma-family tables of one layer.  The network maps a key
+// position (x, y, S = z + z') to the compact table entries scaled by the
+// envelope of a source at the nearer mirror distance,
+//   W_g = D^g K_Sigma(x, y, S) R_e^{|g|+1} / |g|!,
+//   R_e = sqrt(x^2 + y^2 + Z_m^2),  Z_m = min(S - 2 d_l, 2 d_{l-1} - S),
+// each output further divided by its RMS over the training set.  It is trained
+// on tables generated from the complex images (the method itself), and a
+// validation map over cells of the (x, y, S) box keeps a cell only if the
+// largest error of W found there is within the budget; keys outside the box
+// or in rejected cells use the image tables.
+// ---------------------------------------------------------------------------
+struct tefmm_surrogate {
+  tefmm_t ref = nullptr;  // medium and order-p constant tables
+  int layer = 0, p = 0, nG = 0;
+  tefmm_surrogate_options o;
+  std::vector<cplx> A[2], Z[2];  // Sigma-up and Sigma-down images of the training box
+  bool has[2] = {false, false};
+  tefmm::Mlp net;
+  std::vector<float> sigma;
+  float* d_sigma = nullptr;
+  unsigned char* d_gord = nullptr;
+  std::vector<unsigned char> cell_ok;
+  std::vector<double> cell_err;
+  std::string err;
+  ~tefmm_surrogate() {
+    if (d_sigma) (void)hipFree(d_sigma);
+    if (d_gord) (void)hipFree(d_gord);
+    if (ref) tefmm_destroy(ref);
+  }
+};
+
+static double sigma_envelope(const MediumDesc& med, int l, bool up, bool dn, double X, double Y, double S) {
+  double zm = 1e300;
+  if (up) zm = std::min(zm, S - 2 * med.d[l]);
+  if (dn) zm = std::min(zm, 2 * med.d[l - 1] - S);
+  return std::sqrt(X * X + Y * Y + zm * zm);
+}
+
+static int sur_cell(const tefmm_surrogate* su, double X, double Y, double S) {
+  const tefmm_surrogate_options& o = su->o;
+  const double u = (X + o.x_max) / (2 * o.x_max), v = (Y + o.x_max) / (2 * o.x_max), w = (S - o.s_lo) / (o.s_hi - o.s_lo);
+  if (!(u >= 0 && u <= 1 && v >= 0 && v <= 1 && w >= 0 && w <= 1)) return -1;
+  const int cu = std::min(o.cells_xy - 1, (int)(u * o.cells_xy)), cv = std::min(o.cells_xy - 1, (int)(v * o.cells_xy));
+  const int cw = std::min(o.cells_s - 1, (int)(w * o.cells_s));
+  return (cu * o.cells_xy + cv) * o.cells_s + cw;
+}
+
+static bool surrogate_applies(const tefmm_surrogate* su, int layer, bool up, bool dn) {
+  return su->layer == layer && su->has[0] == up && su->has[1] == dn;
+}
+
+static bool surrogate_accepts(const tefmm_surrogate* su, double X, double Y, double S) {
+  const int c = sur_cell(su, X, Y, S);
+  return c >= 0 && su->cell_ok[c];
+}
+
+// Image tables (h = 1: entries D^g K_Sigma) at points (X, Y, S), generated like
+// the method's own Sigma tables; d_out: [n][nG].
+static int sur_image_tables(tefmm_surrogate* su, const std::vector<double>& X, const std::vector<double>& Y,
+                            const std::vector<double>& S, double2* d_out, hipStream_t s) {
+  tefmm_t h = su->ref;
+  const MediumDesc& med = h->med;
+  const int l = su->layer, n = (int)X.size();
+  const int chunk = 16384;
+  for (int c0 = 0; c0 < n; c0 += chunk) {
+    const int cnt = std::min(chunk, n - c0);
+    std::vector<TableTerm> terms;
+    std::vector<int> start;
+    std::vector<double> hk(cnt, 1.0);
+    for (int i = c0; i < c0 + cnt; ++i) {
+      start.push_back((int)terms.size());
+      for (int f = 0; f < 2; ++f)
+        for (size_t j = 0; j < su->A[f].size(); ++j) {
+          const cplx zeta = f == 0 ? S[i] - 2 * med.d[l] - su->Z[f][j] : 2 * med.d[l - 1] - S[i] - su->Z[f][j];
+          if (zeta.real() <= 1e-9) continue;
+          TableTerm t;
+          t.x = X[i], t.y = Y[i], t.zr = zeta.real(), t.zi = zeta.imag();
+          t.cr = su->A[f][j].real(), t.ci = su->A[f][j].imag(), t.flip = f, t.pad = 0;
+          terms.push_back(t);
+        }
+    }
+    start.push_back((int)terms.size());
+    TableTerm* d_terms = nullptr;
+    int* d_start = nullptr;
+    double* d_h = nullptr;
+    HIPCHK(h, hipMalloc(&d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
+    HIPCHK(h, hipMalloc(&d_start, sizeof(int) * start.size()));
+    HIPCHK(h, hipMalloc(&d_h, sizeof(double) * cnt));
+    if (!terms.empty())
+      HIPCHK(h, hipMemcpyAsync(d_terms, terms.data(), sizeof(TableTerm) * terms.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_h, hk.data(), sizeof(double) * cnt, hipMemcpyHostToDevice, s));
+    TableGenArgs ta;
+    ta.terms = d_terms, ta.term_start = d_start, ta.h = d_h, ta.k = med.k[l], ta.order = 2 * su->p, ta.nG = su->nG;
+    ta.nbr = h->d_nbr, ta.g3 = h->d_g3, ta.g1 = h->d_g1, ta.swap13 = 0, ta.fact = h->d_fact;
+    ta.out = d_out + (size_t)c0 * su->nG;
+    const size_t lds = 2 * sizeof(double2) * su->nG;
+    HIPCHK(h, hipFuncSetAttribute((const void*)k_table_gen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_table_gen, dim3(cnt), dim3(64), lds, s, ta);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    dfree(d_terms);
+    dfree(d_start);
+    dfree(d_h);
+  }
+  return TEFMM_OK;
+}
+
+static void sur_inputs(const tefmm_surrogate* su, const std::vector<double>& X, const std::vector<double>& Y,
+                       const std::vector<double>& S, std::vector<float>& u) {
+  const tefmm_surrogate_options& o = su->o;
+  u.resize(3 * X.size());
+  for (size_t i = 0; i < X.size(); ++i) {
+    u[3 * i] = (float)(X[i] / o.x_max);
+    u[3 * i + 1] = (float)(Y[i] / o.x_max);
+    u[3 * i + 2] = (float)((2 * S[i] - o.s_lo - o.s_hi) / (o.s_hi - o.s_lo));
+  }
+}
+
+// rows sk.key of d_out from the network (level box size hb)
+static int surrogate_tables(tefmm_t h, const SigmaKeys& sk, double hb, double2* d_out, hipStream_t s) {
+  tefmm_surrogate* su = h->sur;
+  const int nk = (int)sk.key.size(), nG = h->nG;
+  std::vector<float> u;
+  sur_inputs(su, sk.X, sk.Y, sk.S, u);
+  float *d_u = nullptr, *d_y = nullptr;
+  int* d_key = nullptr;
+  double* d_re = nullptr;
+  HIPCHK(h, hipMalloc(&d_u, sizeof(float) * u.size()));
+  HIPCHK(h, hipMalloc(&d_y, sizeof(float) * (size_t)nk * 2 * nG));
+  HIPCHK(h, hipMalloc(&d_key, sizeof(int) * nk));
+  HIPCHK(h, hipMalloc(&d_re, sizeof(double) * nk));
+  HIPCHK(h, hipMemcpyAsync(d_u, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(d_key, sk.key.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(d_re, sk.Re.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
+  HIPCHK(h, su->net.reserve(std::min(nk, 65536)));
+  for (int r0 = 0; r0 < nk; r0 += (int)su->net.cap) {
+    const int cnt = std::min<int>((int)su->net.cap, nk - r0);
+    HIPCHK(h, su->net.forward(d_u + 3 * (size_t)r0, cnt, d_y + (size_t)r0 * 2 * nG, s));
+  }
+  hipLaunchKernelGGL(k_sur_assemble, dim3(nk), dim3(128), 0, s, d_y, d_key, d_re, nk, nG, hb, su->d_sigma,
+                     su->d_gord, d_out);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(s));
+  dfree(d_u);
+  dfree(d_y);
+  dfree(d_key);
+  dfree(d_re);
+  return TEFMM_OK;
+}
+
+extern "C" void tefmm_surrogate_default_options(const tefmm_medium* medium, int layer, tefmm_surrogate_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->layer = layer;
+  o->x_max = 0.75;
+  o->s_lo = -1.0, o->s_hi = 1.0;
+  MediumDesc med;
+  std::string err;
+  if (medium && medium_from_desc(medium, med, err) && layer >= 0 && layer <= med.L) {
+    const double margin = 0.15;
+    const double top = layer == 0 ? (med.L ? med.d[0] + 2.0 : 2.0) : med.d[layer - 1];
+    const double bot = layer == med.L ? (med.L ? med.d[med.L - 1] - 2.0 : -2.0) : med.d[layer];
+    o->s_lo = 2 * bot + margin, o->s_hi = 2 * top - margin;
+  }
+  o->n_train = 131072;
+  o->epochs = 60;
+  o->batch = 1024;
+  o->lr = 2e-3f;
+  o->width = 128;
+  o->n_hidden = 4;
+  o->cells_xy = 6;
+  o->cells_s = 12;
+  o->n_valid = 16;
+  o->budget = 3e-3;
+  o->seed = 1234;
+}
+
+#define SURCHK(x)                                                \
+  do {                                                           \
+    int rc_ = (x);                                               \
+    if (rc_ != TEFMM_OK) {                                       \
+      if (rep) rep->status = rc_;                                \
+      std::string m_ = su->ref ? su->ref->err : std::string(""); \
+      delete su;                                                 \
+      (void)m_;                                                  \
+      return rc_;                                                \
+    }                                                            \
+  } while (0)
+#define SURHIP(x) SURCHK(((x) == hipSuccess) ? TEFMM_OK : TEFMM_ERR_HIP)
+
+extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium* medium, const tefmm_options* opt,
+                                     const tefmm_surrogate_options* so, tefmm_surrogate_report* rep,
+                                     double* epoch_loss, void* stream) {
+  if (!out || !medium || !so) return TEFMM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (rep) std::memset(rep, 0, sizeof(*rep));
+  const tefmm_surrogate_options& o = *so;
+  if (!(o.x_max > 0) || !(o.s_hi > o.s_lo) || o.n_train < 64 || o.epochs < 0 || o.batch < 1 || !(o.lr > 0) ||
+      o.width < 16 || o.n_hidden < 1 || o.cells_xy < 1 || o.cells_s < 1 || o.n_valid < 1 || !(o.budget > 0))
+    return TEFMM_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  tefmm_surrogate* su = new tefmm_surrogate();
+  su->o = o;
+  su->layer = o.layer;
+  SURCHK(tefmm_create(&su->ref, medium, opt));
+  tefmm_t h = su->ref;
+  const MediumDesc& med = h->med;
+  const int l = o.layer;
+  if (l < 0 || l > med.L) SURCHK(TEFMM_ERR_INVALID_ARG);
+  su->p = h->opt.p, su->nG = h->nG;
+  const int nG = su->nG;
+  // the training box must lie in the layer (S = z + z' of two points of the layer)
+  const double top = med.top(l), bot = med.bottom(l);
+  if (!(o.s_lo > 2 * bot) || !(o.s_hi < 2 * top)) SURCHK(TEFMM_ERR_INVALID_ARG);
+  auto t0 = std::chrono::steady_clock::now();
+  // complex images of the box (Sec. 3.3), as the method's own tables use them
+  for (int f = 0; f < 2; ++f) {
+    double fe = 0;
+    std::string err;
+    if (!same_layer_family(med, l, f, 0.5 * o.s_lo, 0.5 * o.s_hi, h->opt.dcim_T1, h->opt.dcim_samples,
+                           h->opt.dcim_svd_tol, su->A[f], su->Z[f], fe, err))
+      SURCHK(TEFMM_ERR_DCIM_FIT);
+    su->has[f] = !su->A[f].empty();
+  }
+  if (!su->has[0] && !su->has[1]) SURCHK(TEFMM_ERR_UNSUPPORTED);  // no Sigma family in this layer
+  std::vector<unsigned char> gord(nG);
+  for (int n = 0; n <= 2 * su->p; ++n)
+    for (int i = g_offset(n); i < g_offset(n + 1); ++i) gord[i] = (unsigned char)n;
+  SURHIP(hipMalloc(&su->d_gord, nG));
+  SURHIP(hipMemcpy(su->d_gord, gord.data(), nG, hipMemcpyHostToDevice));
+  // samples: uniform in the box
+  uint64_t st = o.seed;
+  auto unif = [&]() {
+    st += 0x9e3779b97f4a7c15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  };
+  auto targets = [&](const std::vector<double>& X, const std::vector<double>& Y, const std::vector<double>& S,
+                     double2* d_W, double* d_sumsq) -> int {
+    const int n = (int)X.size();
+    double2* d_raw = nullptr;
+    double* d_re = nullptr;
+    HIPCHK(h, hipMalloc(&d_raw, sizeof(double2) * (size_t)n * nG));
+    HIPCHK(h, hipMalloc(&d_re, sizeof(double) * n));
+    int rc = sur_image_tables(su, X, Y, S, d_raw, s);
+    if (rc != TEFMM_OK) return rc;
+    std::vector<double> re(n);
+    for (int i = 0; i < n; ++i) re[i] = sigma_envelope(med, l, su->has[0], su->has[1], X[i], Y[i], S[i]);
+    HIPCHK(h, hipMemcpyAsync(d_re, re.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sur_normalize, dim3(n), dim3(128), 0, s, d_raw, d_re, n, nG, su->d_gord, d_W, d_sumsq);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    dfree(d_raw);
+    dfree(d_re);
+    return TEFMM_OK;
+  };
+  const int n = o.n_train;
+  std::vector<double> X(n), Y(n), S(n);
+  for (int i = 0; i < n; ++i) {
+    X[i] = (2 * unif() - 1) * o.x_max;
+    Y[i] = (2 * unif() - 1) * o.x_max;
+    S[i] = o.s_lo + unif() * (o.s_hi - o.s_lo);
+  }
+  double2* d_W = nullptr;
+  double* d_sumsq = nullptr;
+  float *d_T = nullptr, *d_X = nullptr;
+  SURHIP(hipMalloc(&d_W, sizeof(double2) * (size_t)n * nG));
+  SURHIP(hipMalloc(&d_sumsq, sizeof(double) * nG));
+  SURHIP(hipMemset(d_sumsq, 0, sizeof(double) * nG));
+  SURCHK(targets(X, Y, S, d_W, d_sumsq));
+  std::vector<double> sumsq(nG);
+  SURHIP(hipMemcpy(sumsq.data(), d_sumsq, sizeof(double) * nG, hipMemcpyDeviceToHost));
+  su->sigma.resize(nG);
+  for (int g = 0; g < nG; ++g) su->sigma[g] = (float)std::max(std::sqrt(sumsq[g] / n), 1e-30);
+  SURHIP(hipMalloc(&su->d_sigma, sizeof(float) * nG));
+  SURHIP(hipMemcpy(su->d_sigma, su->sigma.data(), sizeof(float) * nG, hipMemcpyHostToDevice));
+  SURHIP(hipMalloc(&d_T, sizeof(float) * (size_t)n * 2 * nG));
+  hipLaunchKernelGGL(k_sur_targets, dim3((unsigned)(((size_t)n * nG + 255) / 256)), dim3(256), 0, s, d_W, n, nG,
+                     su->d_sigma, d_T);
+  SURHIP(hipGetLastError());
+  std::vector<float> u;
+  sur_inputs(su, X, Y, S, u);
+  SURHIP(hipMalloc(&d_X, sizeof(float) * u.size()));
+  SURHIP(hipMemcpyAsync(d_X, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice, s));
+  SURHIP(hipStreamSynchronize(s));
+  dfree(d_W);
+  dfree(d_sumsq);
+  auto t1 = std::chrono::steady_clock::now();
+  // training on the matrix cores
+  SURHIP(su->net.init(3, o.width, o.n_hidden, 2 * nG, o.seed ^ 0x5bd1e995ull));
+  std::vector<double> losses;
+  SURHIP(su->net.train(d_X, d_T, n, o.epochs, o.batch, o.lr, o.seed + 17, losses, s));
+  if (epoch_loss)
+    for (size_t i = 0; i < losses.size(); ++i) epoch_loss[i] = losses[i];
+  dfree(d_X);
+  dfree(d_T);
+  auto t2 = std::chrono::steady_clock::now();
+  // validation map: n_valid fresh points per cell
+  const int ncell = o.cells_xy * o.cells_xy * o.cells_s, nv = ncell * o.n_valid;
+  std::vector<double> vX(nv), vY(nv), vS(nv);
+  for (int c = 0; c < ncell; ++c) {
+    const int cu = c / (o.cells_xy * o.cells_s), cv = (c / o.cells_s) % o.cells_xy, cw = c % o.cells_s;
+    for (int j = 0; j < o.n_valid; ++j) {
+      const int i = c * o.n_valid + j;
+      vX[i] = (-1 + 2 * (cu + unif()) / o.cells_xy) * o.x_max;
+      vY[i] = (-1 + 2 * (cv + unif()) / o.cells_xy) * o.x_max;
+      vS[i] = o.s_lo + (cw + unif()) / o.cells_s * (o.s_hi - o.s_lo);
+    }
+  }
+  double2* d_vW = nullptr;
+  float *d_vu = nullptr, *d_vy = nullptr;
+  SURHIP(hipMalloc(&d_vW, sizeof(double2) * (size_t)nv * nG));
+  SURCHK(targets(vX, vY, vS, d_vW, nullptr));
+  std::vector<float> vu;
+  sur_inputs(su, vX, vY, vS, vu);
+  SURHIP(hipMalloc(&d_vu, sizeof(float) * vu.size()));
+  SURHIP(hipMalloc(&d_vy, sizeof(float) * (size_t)nv * 2 * nG));
+  SURHIP(hipMemcpy(d_vu, vu.data(), sizeof(float) * vu.size(), hipMemcpyHostToDevice));
+  SURHIP(su->net.reserve(std::min(nv, 65536)));
+  for (int r0 = 0; r0 < nv; r0 += (int)su->net.cap) {
+    const int cnt = std::min<int>((int)su->net.cap, nv - r0);
+    SURHIP(su->net.forward(d_vu + 3 * (size_t)r0, cnt, d_vy + (size_t)r0 * 2 * nG, s));
+  }
+  std::vector<double2> vW((size_t)nv * nG);
+  std::vector<float> vy((size_t)nv * 2 * nG);
+  SURHIP(hipMemcpyAsync(vW.data(), d_vW, sizeof(double2) * vW.size(), hipMemcpyDeviceToHost, s));
+  SURHIP(hipMemcpyAsync(vy.data(), d_vy, sizeof(float) * vy.size(), hipMemcpyDeviceToHost, s));
+  SURHIP(hipStreamSynchronize(s));
+  dfree(d_vW);
+  dfree(d_vu);
+  dfree(d_vy);
+  su->cell_ok.assign(ncell, 0);
+  su->cell_err.assign(ncell, 0.0);
+  double emax = 0;
+  int ok = 0;
+  for (int c = 0; c < ncell; ++c) {
+    double e = 0;
+    for (int j = 0; j < o.n_valid; ++j) {
+      const size_t i = (size_t)c * o.n_valid + j;
+      for (int g = 0; g < nG; ++g) {
+        const double pr = vy[(i * nG + g) * 2] * su->sigma[g], pi = vy[(i * nG + g) * 2 + 1] * su->sigma[g];
+        e = std::max(e, std::hypot(pr - vW[i * nG + g].x, pi - vW[i * nG + g].y));
+      }
+    }
+    su->cell_err[c] = e;
+    su->cell_ok[c] = e <= o.budget;
+    ok += su->cell_ok[c];
+    emax = std::max(emax, e);
+  }
+  auto t3 = std::chrono::steady_clock::now();
+  if (rep) {
+    rep->t_data_s = std::chrono::duration<double>(t1 - t0).count();
+    rep->t_train_s = std::chrono::duration<double>(t2 - t1).count();
+    rep->t_valid_s = std::chrono::duration<double>(t3 - t2).count();
+    rep->final_loss = losses.empty() ? 0.0 : losses.back();
+    rep->max_cell_err = emax;
+    rep->cells_ok = ok;
+    rep->cells_total = ncell;
+    rep->n_out = 2 * nG;
+    rep->n_params = su->net.P;
+    rep->status = TEFMM_OK;
+  }
+  *out = su;
+  return TEFMM_OK;
+}
+#undef SURCHK
+#undef SURHIP
+
+extern "C" void tefmm_surrogate_destroy(tefmm_surrogate_t su) { delete su; }
+
+extern "C" int tefmm_surrogate_cell_ok(tefmm_surrogate_t su, int n, const double* xys, int* ok) {
+  if (!su || n < 0 || (n > 0 && (!xys || !ok))) return TEFMM_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) ok[i] = surrogate_accepts(su, xys[3 * i], xys[3 * i + 1], xys[3 * i + 2]) ? 1 : 0;
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_surrogate_cell_errors(tefmm_surrogate_t su, double* err) {
+  if (!su || !err) return TEFMM_ERR_INVALID_ARG;
+  for (size_t c = 0; c < su->cell_err.size(); ++c) err[c] = su->cell_err[c];
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_set_surrogate(tefmm_t h, tefmm_surrogate_t su) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  if (su) {
+    if (su->p != h->opt.p) return fail(h, TEFMM_ERR_INVALID_ARG, "surrogate trained for another order p");
+    const MediumDesc& a = su->ref->med;
+    if (a.k != h->med.k || a.d != h->med.d) return fail(h, TEFMM_ERR_INVALID_ARG, "surrogate trained for another medium");
+  }
+  h->sur = su;
+  return TEFMM_OK;
 }

@@ -738,6 +738,52 @@ __global__ __launch_bounds__(64) void k_p2p(PassArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Surrogate tables.  Entry g of a reaction table at (x, y, S) is scaled by the
+// Cauchy-type envelope of a source at distance R_e (the distance to the nearer
+// mirror point):  W_g = D^g K R_e^{|g|+1} / |g|!.
+// ---------------------------------------------------------------------------
+__global__ void k_sur_normalize(const double2* raw, const double* Re, int n, int nG, const unsigned char* gord,
+                                double2* W, double* sumsq) {
+  const int key = blockIdx.x;
+  if (key >= n) return;
+  const double r = Re[key];
+  for (int g = threadIdx.x; g < nG; g += blockDim.x) {
+    const int o = gord[g];
+    double f = r;
+    for (int i = 1; i <= o; ++i) f *= r / i;
+    const double2 v = raw[(size_t)key * nG + g];
+    const double2 w = make_double2(v.x * f, v.y * f);
+    W[(size_t)key * nG + g] = w;
+    if (sumsq) atomicAdd(&sumsq[g], w.x * w.x + w.y * w.y);
+  }
+}
+
+// network targets: (Re W_g / sigma_g, Im W_g / sigma_g) per entry
+__global__ void k_sur_targets(const double2* W, int n, int nG, const float* sigma, float* T) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * nG) return;
+  const int g = (int)(e % nG);
+  const double2 w = W[e];
+  T[2 * e] = (float)(w.x / sigma[g]);
+  T[2 * e + 1] = (float)(w.y / sigma[g]);
+}
+
+// table rows of the keys answered by the network: h^{|g|} D^g K = sigma_g y_g |g|! h^{|g|} / R_e^{|g|+1}
+__global__ void k_sur_assemble(const float* y, const int* key_of, const double* Re, int nk, int nG, double h,
+                               const float* sigma, const unsigned char* gord, double2* table) {
+  const int i = blockIdx.x;
+  if (i >= nk) return;
+  const double r = Re[i];
+  for (int g = threadIdx.x; g < nG; g += blockDim.x) {
+    const int o = gord[g];
+    double f = 1.0 / r;
+    for (int j = 1; j <= o; ++j) f *= j * h / r;
+    const double s = sigma[g] * f;
+    table[(size_t)key_of[i] * nG + g] = make_double2(y[(size_t)i * 2 * nG + 2 * g] * s, y[(size_t)i * 2 * nG + 2 * g + 1] * s);
+  }
+}
+
 template __global__ void k_p2p<double>(PassArgs);
 template __global__ void k_p2p<float>(PassArgs);
 

@@ -134,6 +134,11 @@ hipError_t launch_m2l_cross(const M2LCrossArgs& a, int nrhs, bool fp32, hipStrea
 void upload_binomials();
 
 __global__ void k_table_gen(TableGenArgs a);
+__global__ void k_sur_normalize(const double2* raw, const double* Re, int n, int nG, const unsigned char* gord,
+                                double2* W, double* sumsq);
+__global__ void k_sur_targets(const double2* W, int n, int nG, const float* sigma, float* T);
+__global__ void k_sur_assemble(const float* y, const int* key_of, const double* Re, int nk, int nG, double h,
+                               const float* sigma, const unsigned char* gord, double2* table);
 __global__ void k_taylor_points(const double* px, const double* py, const double* pz, double k, double h,
                                 int order, int nT, const short* nbr, double2* out);
 __global__ void k_selftest_mfma(double* out64, float* out32);

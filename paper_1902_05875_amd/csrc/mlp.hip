@@ -374,7 +374,9 @@ hipError_t Mlp::train(const float* X, const float* T, int64_t n, int epochs, int
       hipLaunchKernelGGL(k_mlp_gather, dim3(nblk(cnt * n_out)), dim3(256), 0, s, T, d_perm + b0, cnt, n_out, tb);
       if ((e = hipGetLastError()) != hipSuccess) break;
       if ((e = loss_grad(xb, tb, cnt, s)) != hipSuccess) break;
-      e = adam(lr, s);
+      // cosine decay of the step size over the run, down to 2% of lr
+      const double prog = (double)ep / std::max(1, epochs);
+      e = adam((float)(lr * (0.02 + 0.98 * 0.5 * (1.0 + std::cos(3.14159265358979 * prog)))), s);
     }
     if (e != hipSuccess) break;
     double L = 0;
