@@ -11,8 +11,10 @@ Default workload: N = 1,000,000 particles uniform in the unit cube centred at
 (0, 0, -0.6) inside the three-layer medium (interfaces 0 and -1.2, k = 0.8,
 1.5, 2.0), one complex charge vector; seeded synthetic data.  Two modes are
 timed: the plain FP64 FMM (p = 12, relative error <= 1e-6) and the mixed
-FP32 FMM (complex FP32 M2L and P2P, FP64 tables and accumulation); `value` is
-the mode named by --headline.
+FP32 FMM (complex FP32 M2L and P2P, FP64 tables and accumulation) with the
+Sigma-table surrogate attached (its validated cells answer table rows, the
+rest fall back to the complex images); `value` is the mode named by
+--headline.
 
 Prints one JSON line.
 """
@@ -49,11 +51,20 @@ def _sampled_error(workload, phi):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), len(idx)
 
 
-def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload):
+def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload, surrogate=False, autotune=True):
     import torch
     from paper_1902_05875_amd import api, inputs
     f = api.TEFMM(inputs.MEDIUM_K, inputs.MEDIUM_D, p=p, precision=precision, max_leaf=max_leaf,
                   n_rhs_max=max(64, q.shape[0]))
+    sur_info = None
+    if surrogate:
+        # trained once per medium and layer (untimed, like the rest of the setup), then attached
+        t0 = time.perf_counter()
+        sur = api.Surrogate(inputs.MEDIUM_K, inputs.MEDIUM_D, 1, p=p)
+        sur_info = {"train_wall_s": round(time.perf_counter() - t0, 3), **{k: sur.report[k] for k in (
+            "t_data_s", "t_train_s", "final_loss", "max_cell_err", "cells_ok", "cells_total", "n_params")},
+            "budget": sur.options["budget"], "n_train": sur.options["n_train"], "epochs": sur.options["epochs"]}
+        f.set_surrogate(sur)
     stream = torch.cuda.current_stream()
     xt = torch.from_numpy(xyz).cuda()
     qt = torch.from_numpy(q).cuda()
@@ -62,6 +73,13 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload):
     f.set_particles(xt)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    tuned = None
+    if autotune:
+        # depth (occupancy vs far-field work) and M2L tile width, chosen by timing (untimed setup)
+        t0 = time.perf_counter()
+        tuned = f.autotune()
+        torch.cuda.synchronize()
+        tuned = {"depth": tuned[0], "m2l_tile": tuned[1], "autotune_s": round(time.perf_counter() - t0, 3)}
     out = torch.empty_like(qt)
     for _ in range(warmup):
         f.evaluate(qt, out=out)
@@ -90,7 +108,9 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload):
         "phases_ms": {k[2:-3]: round(v, 4) for k, v in phases.items()},
         "m2l_flops": st["m2l_flops"], "m2l_launches": st["m2l_launches"], "depth": st["depth"][0],
         "images": st["n_images"], "p2p_pairs": st["p2p_pairs"],
-        "rel_err_sampled": err, "n_checked": nchk,
+        "rel_err_sampled": err, "n_checked": nchk, "t_setup_tables_ms": st["t_setup_tables_ms"],
+        "sigma_keys": st["sigma_keys"], "surrogate_keys": st["surrogate_keys"], "surrogate": sur_info,
+        "cross_pairs": st["cross_pairs"], "autotune": tuned,
     }
     f.close()
     del xt, qt, out
@@ -159,6 +179,10 @@ def main():
     ap.add_argument("--headline", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--modes", default="fp64,fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="FP32 mode without the Sigma-table surrogate")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the occupancy-based depth and tile width")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one device copy of this many MiB (calibrates HBM counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition "
@@ -168,6 +192,12 @@ def main():
     import torch
     from paper_1902_05875_amd import inputs
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     xyz, q = inputs.workload(args.workload, n=args.n, n_rhs=args.n_rhs)
     qm = q.reshape(1, -1) if q.ndim == 1 else np.ascontiguousarray(q.T)
     N = xyz.shape[0]
@@ -175,7 +205,9 @@ def main():
     for m in args.modes.split(","):
         p = args.p64 if m == "fp64" else args.p32
         print(f"[bench] mode {m} p={p} N={N} n_rhs={qm.shape[0]}", file=sys.stderr, flush=True)
-        modes[m] = run_mode(xyz, qm, p, m, args.max_leaf, args.steps, args.warmup, args.workload)
+        modes[m] = run_mode(xyz, qm, p, m, args.max_leaf, args.steps, args.warmup, args.workload,
+                            surrogate=(m == "fp32" and not args.no_surrogate and args.workload != "c3"),
+                            autotune=not args.no_autotune)
         print(f"[bench] {m}: {modes[m]['ms_per_step']:.2f} ms/step, err {modes[m]['rel_err_sampled']}",
               file=sys.stderr, flush=True)
     head = modes[args.headline] if args.headline in modes else next(iter(modes.values()))
@@ -198,7 +230,8 @@ def main():
         "config": {"workload": f"{args.workload}: N={N} {SHAPES.get(args.workload, '')}, 3 layers "
                                f"(d=0,-1.2; k=0.8,1.5,2.0), {qm.shape[0]} complex charge vector(s)",
                    "p": head["p"], "precision": head["precision"], "max_leaf": args.max_leaf,
-                   "depth": head["depth"], "parallelism": "single GPU"},
+                   "depth": head["depth"], "m2l_tile": (head["autotune"] or {}).get("m2l_tile"),
+                   "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "modes": modes,
     }
     print(json.dumps(line))

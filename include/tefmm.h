@@ -88,6 +88,7 @@ typedef struct {
   double interface_eps;
   int n_rhs_max;
   double dcim_T1_cross;
+  int m2l_tile;       /* M2L targets per workgroup / 16: 1 or 2 (0 = automatic; tefmm_autotune measures) */
 } tefmm_options;
 
 /* Timings (ms, measured with HIP events on the evaluate stream) and counters. */

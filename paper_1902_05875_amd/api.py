@@ -45,7 +45,8 @@ class OptionsC(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("depth", ctypes.c_int), ("max_leaf", ctypes.c_int),
                 ("precision", ctypes.c_int), ("normalization", ctypes.c_int), ("dcim_T1", ctypes.c_double),
                 ("dcim_samples", ctypes.c_int), ("dcim_svd_tol", ctypes.c_double),
-                ("interface_eps", ctypes.c_double), ("n_rhs_max", ctypes.c_int), ("dcim_T1_cross", ctypes.c_double)]
+                ("interface_eps", ctypes.c_double), ("n_rhs_max", ctypes.c_int), ("dcim_T1_cross", ctypes.c_double),
+                ("m2l_tile", ctypes.c_int)]
 
 
 class StatsC(ctypes.Structure):

@@ -287,7 +287,7 @@ extern "C" int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefm
   if (o.p < 1 || o.p > 16 || o.depth < 0 || o.depth > 7 || o.max_leaf < 1 ||
       (o.precision != TEFMM_FP64 && o.precision != TEFMM_MIXED_FP32) ||
       (o.normalization != TEFMM_NORM_PHYSICAL && o.normalization != TEFMM_NORM_PAPER) || o.dcim_samples < 8 ||
-      !(o.dcim_T1 > 0) || !(o.dcim_T1_cross > 0) || !(o.dcim_svd_tol > 0) || !(o.interface_eps >= 0) || o.n_rhs_max < 1) {
+      !(o.dcim_T1 > 0) || !(o.dcim_T1_cross > 0) || !(o.dcim_svd_tol > 0) || o.m2l_tile < 0 || o.m2l_tile > 2 || !(o.interface_eps >= 0) || o.n_rhs_max < 1) {
     delete h;
     return TEFMM_ERR_INVALID_ARG;
   }
@@ -1148,7 +1148,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       L.a = g.ared[lev], L.b = g.bred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
       L.Tfd = g.Tfd[lev], L.TS = g.TS[lev], L.Tfd32 = g.Tfd32[lev], L.TS32 = g.TS32[lev];
     }
-    m.ncb = h->m2l_ncb;
+    m.ncb = h->m2l_ncb ? h->m2l_ncb : h->opt.m2l_tile;
     HIPCHK(h, launch_m2l(m, nrhs, fp32, s));
     const double per = 8.0 * (double)h->nR * (double)h->nR;
     for (int lev = 2; lev <= H; ++lev) {
@@ -1222,10 +1222,16 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
   for (auto& g : h->groups) {
     PassArgs a = pass_args(g);
     a.nbox_dim = 1 << g.depth, a.h = g.side / (1 << g.depth);
-    if (fp32)
-      hipLaunchKernelGGL(k_p2p<float>, dim3((unsigned)g.nbox[g.depth], nrhs), dim3(64), 0, s, a);
+    const bool wide = g.count > 96 * g.nbox[g.depth];  // mean leaf occupancy above 96
+    const dim3 grid((unsigned)g.nbox[g.depth], nrhs);
+    if (fp32 && wide)
+      hipLaunchKernelGGL((k_p2p<float, 256>), grid, dim3(256), 0, s, a);
+    else if (fp32)
+      hipLaunchKernelGGL((k_p2p<float, 64>), grid, dim3(64), 0, s, a);
+    else if (wide)
+      hipLaunchKernelGGL((k_p2p<double, 256>), grid, dim3(256), 0, s, a);
     else
-      hipLaunchKernelGGL(k_p2p<double>, dim3((unsigned)g.nbox[g.depth], nrhs), dim3(64), 0, s, a);
+      hipLaunchKernelGGL((k_p2p<double, 64>), grid, dim3(64), 0, s, a);
     HIPCHK(h, hipGetLastError());
   }
   EVREC(6);

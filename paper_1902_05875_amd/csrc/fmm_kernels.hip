@@ -659,16 +659,70 @@ __global__ __launch_bounds__(64) void k_l2p(PassArgs a) {
 // ---------------------------------------------------------------------------
 // P2P, free space (Eq. totalinteraction, free part): for every target in a
 // leaf, sum over the 27 neighbour leaves (itself included, j = i excluded) of
-// q_j exp(i k r)/r.  One 64-lane block per target leaf; source chunks staged
-// in LDS.  Adds into phi.
+// q_j exp(i k r)/r.  One block of BS lanes (64 or 256, by mean leaf occupancy)
+// per target leaf.  Leaves are stored in
+// (x, y, z) order, so the three z-neighbours of one (x, y) column are one
+// contiguous particle range: nine ranges per leaf, staged through LDS in
+// chunks of 256.  Adds into phi.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincosf(x, s, c); }
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_p2p(PassArgs a) {
-  __shared__ T sx[64], sy[64], sz[64], sqr[64], sqi[64];
-  __shared__ int sidx[64];
+// sin and cos of 0 <= x < 1e4 in FP64: x = q pi/2 + y with pi/2 split in two
+// parts (Cody and Waite), |y| <= pi/4, then the Taylor series of sin y (to
+// y^17) and cos y (to y^18), whose first omitted terms are below 1e-19.
+__device__ __forceinline__ void sincos_f64(double x, double* s, double* c) {
+  const double q = rint(x * 0.63661977236758134308);
+  double y = fma(-q, 1.5707963267948965580e+00, x);
+  y = fma(-q, 6.1232339957367658e-17, y);
+  const double y2 = y * y;
+  double ps = 2.8114572543455207632e-15;          //  1/17!
+  ps = fma(ps, y2, -7.6471637318198164759e-13);   // -1/15!
+  ps = fma(ps, y2, 1.6059043836821614599e-10);    //  1/13!
+  ps = fma(ps, y2, -2.5052108385441718775e-08);   // -1/11!
+  ps = fma(ps, y2, 2.7557319223985890653e-06);    //  1/9!
+  ps = fma(ps, y2, -1.9841269841269841270e-04);   // -1/7!
+  ps = fma(ps, y2, 8.3333333333333333333e-03);    //  1/5!
+  ps = fma(ps, y2, -1.6666666666666666667e-01);   // -1/3!
+  const double sy = fma(y * y2, ps, y);
+  double pc = 1.5619206968586225796e-16;          //  1/18!
+  pc = fma(pc, y2, -4.7794773323873852974e-14);   // -1/16!
+  pc = fma(pc, y2, 1.1470745597729724714e-11);    //  1/14!
+  pc = fma(pc, y2, -2.0876756987868098979e-09);   // -1/12!
+  pc = fma(pc, y2, 2.7557319223985890653e-07);    //  1/10!
+  pc = fma(pc, y2, -2.4801587301587301587e-05);   // -1/8!
+  pc = fma(pc, y2, 1.3888888888888888889e-03);    //  1/6!
+  pc = fma(pc, y2, -4.1666666666666666667e-02);   // -1/4!
+  pc = fma(pc, y2, 0.5);
+  const double cy = fma(-y2, pc, 1.0);
+  const int qi = ((int)q) & 3;
+  const double s0 = (qi & 1) ? cy : sy, c0 = (qi & 1) ? sy : cy;
+  *s = (qi & 2) ? -s0 : s0;
+  *c = ((qi + 1) & 2) ? -c0 : c0;
+}
+
+// 1/sqrt(r2) in FP64: FP32 estimate refined by two Newton steps (error squared each step).
+__device__ __forceinline__ double rsqrt_f64(double r2) {
+  double y = (double)rsqrtf((float)r2);
+  y = y * fma(-0.5 * r2, y * y, 1.5);
+  return y * fma(-0.5 * r2, y * y, 1.5);
+}
+
+__device__ __forceinline__ void pair_kernel(double r2, double k, double* er, double* ei) {
+  const double ri = rsqrt_f64(r2);
+  double sn, cs;
+  sincos_f64(k * (r2 * ri), &sn, &cs);
+  *er = cs * ri, *ei = sn * ri;
+}
+__device__ __forceinline__ void pair_kernel(float r2, float k, float* er, float* ei) {
+  const float ri = rsqrtf(r2);
+  float sn, cs;
+  __sincosf(k * (r2 * ri), &sn, &cs);
+  *er = cs * ri, *ei = sn * ri;
+}
+
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
+  __shared__ T sx[BS], sy[BS], sz[BS], sqr[BS], sqi[BS];
+  __shared__ int sidx[BS];
   const int leaf = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
   const int nb = a.nbox_dim;
   const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
@@ -677,23 +731,25 @@ __global__ __launch_bounds__(64) void k_p2p(PassArgs a) {
   const T k = (T)a.k;
   // pairs closer than 5% of the leaf side are evaluated in FP64 in the FP32 path
   const T rns2 = (T)(0.0025 * a.h * a.h);
-  for (int c0 = 0; c0 < cnt; c0 += 64) {
+  const int z0 = max(iz - 1, 0), z1 = min(iz + 1, nb - 1);
+  for (int c0 = 0; c0 < cnt; c0 += BS) {
     const bool act = c0 + tid < cnt;
     const int64_t i = start + c0 + tid;
     const double txd = act ? a.xs[i] : 0.0, tyd = act ? a.xs[a.n + i] : 0.0, tzd = act ? a.xs[2 * a.n + i] : 0.0;
+    // coordinates relative to the root corner keep FP32 differences accurate
+    const T tx = (T)(txd - a.lo[0]), ty = (T)(tyd - a.lo[1]), tz = (T)(tzd - a.lo[2]);
     T accr = 0, acci = 0;
     double nsr = 0.0, nsi = 0.0;  // near-singular pairs (FP32 path only)
-    for (int nbh = 0; nbh < 27; ++nbh) {
-      const int jx = ix + nbh / 9 - 1, jy = iy + (nbh / 3) % 3 - 1, jz = iz + nbh % 3 - 1;
-      if (jx < 0 || jy < 0 || jz < 0 || jx >= nb || jy >= nb || jz >= nb) continue;
-      const int sl = (jx * nb + jy) * nb + jz;
-      const int ss = a.leaf_start[a.leaf_base + sl], sc = a.leaf_count[a.leaf_base + sl];
-      for (int s0 = 0; s0 < sc; s0 += 64) {
-        const int m = min(64, sc - s0);
+    for (int col = 0; col < 9; ++col) {
+      const int jx = ix + col / 3 - 1, jy = iy + col % 3 - 1;
+      if (jx < 0 || jy < 0 || jx >= nb || jy >= nb) continue;
+      const int64_t kl = a.leaf_base + ((int64_t)jx * nb + jy) * nb;
+      const int ss = a.leaf_start[kl + z0], se = a.leaf_start[kl + z1] + a.leaf_count[kl + z1];
+      for (int s0 = ss; s0 < se; s0 += BS) {
+        const int m = min(BS, se - s0);
         __syncthreads();
         if (tid < m) {
-          const int64_t j = ss + s0 + tid;
-          // source coordinates relative to the target leaf's corner keep FP32 differences exact-ish
+          const int64_t j = s0 + tid;
           sx[tid] = (T)(a.xs[j] - a.lo[0]);
           sy[tid] = (T)(a.xs[a.n + j] - a.lo[1]);
           sz[tid] = (T)(a.xs[2 * a.n + j] - a.lo[2]);
@@ -703,28 +759,24 @@ __global__ __launch_bounds__(64) void k_p2p(PassArgs a) {
         }
         __syncthreads();
         if (act) {
-          const T tx = (T)(txd - a.lo[0]), ty = (T)(tyd - a.lo[1]), tz = (T)(tzd - a.lo[2]);
           for (int t = 0; t < m; ++t) {
             const T dx = tx - sx[t], dy = ty - sy[t], dz = tz - sz[t];
             const T r2 = dx * dx + dy * dy + dz * dz;
-            if (sidx[t] == (int)i) continue;
+            // the target itself has r2 = 0 (same coordinates, same arithmetic)
+            if (sizeof(T) == 8 && !(r2 > 0)) continue;
             if (sizeof(T) == 4 && r2 < rns2) {
               // near-singular pair: the FP32 difference has lost digits, redo it in FP64
               const int64_t j = sidx[t];
+              if (j == i) continue;
               const double ex = txd - a.xs[j], ey = tyd - a.xs[a.n + j], ez = tzd - a.xs[2 * a.n + j];
-              const double rd = sqrt(ex * ex + ey * ey + ez * ez);
-              double sn, cs;
-              sincos(a.k * rd, &sn, &cs);
-              const double er = cs / rd, ei = sn / rd;
+              double er, ei;
+              pair_kernel(ex * ex + ey * ey + ez * ez, a.k, &er, &ei);
               nsr += q[j].x * er - q[j].y * ei;
               nsi += q[j].x * ei + q[j].y * er;
               continue;
             }
-            const T rr = sqrt(r2);
-            const T inv = (T)1 / rr;
-            T sn, cs;
-            sincos_t(k * rr, &sn, &cs);
-            const T er = cs * inv, ei = sn * inv;
+            T er, ei;
+            pair_kernel(r2, k, &er, &ei);
             accr += sqr[t] * er - sqi[t] * ei;
             acci += sqr[t] * ei + sqi[t] * er;
           }
@@ -737,6 +789,11 @@ __global__ __launch_bounds__(64) void k_p2p(PassArgs a) {
     }
   }
 }
+
+template __global__ void k_p2p<double, 64>(PassArgs);
+template __global__ void k_p2p<float, 64>(PassArgs);
+template __global__ void k_p2p<double, 256>(PassArgs);
+template __global__ void k_p2p<float, 256>(PassArgs);
 
 // ---------------------------------------------------------------------------
 // Surrogate tables.  Entry g of a reaction table at (x, y, S) is scaled by the
@@ -783,8 +840,5 @@ __global__ void k_sur_assemble(const float* y, const int* key_of, const double* 
     table[(size_t)key_of[i] * nG + g] = make_double2(y[(size_t)i * 2 * nG + 2 * g] * s, y[(size_t)i * 2 * nG + 2 * g + 1] * s);
   }
 }
-
-template __global__ void k_p2p<double>(PassArgs);
-template __global__ void k_p2p<float>(PassArgs);
 
 }  // namespace tefmm

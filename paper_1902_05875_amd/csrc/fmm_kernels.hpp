@@ -159,7 +159,7 @@ __global__ void k_expand_z_add(ReduceArgs a);
 __global__ void k_m2m(PassArgs a);
 __global__ void k_l2l(PassArgs a);
 __global__ void k_l2p(PassArgs a);
-template <typename T>
+template <typename T, int BS>
 __global__ void k_p2p(PassArgs a);
 
 // M2L launcher (picks the row-block instantiation for nRB).

@@ -55,6 +55,24 @@ struct M2LTypes<float> {
 // the address splits into a row part and a column part:
 //   row(k) = (k1 P2 + k2 + k3) P2 + k3,  col(k') = (k1' P2 + k2' + k3') P2 + k3'.
 
+// Valid-target bit mask of a tile for a source offset (dx, dy): target n sits
+// at x index px + 2 (4 X0 + (n & 3)), y index py + 2 (4 NCB Y0 + (n >> 2)).
+template <int NCB>
+__device__ __forceinline__ unsigned tile_mask(int N, int px, int py, int X0, int Y0, int dx, int dy) {
+  unsigned xm = 0, m = 0;
+#pragma unroll
+  for (int xi = 0; xi < 4; ++xi) {
+    const int ix = px + 2 * (4 * X0 + xi);
+    xm |= (ix < N && ix + dx >= 0 && ix + dx < N) ? (1u << xi) : 0u;
+  }
+#pragma unroll
+  for (int yi = 0; yi < 4 * NCB; ++yi) {
+    const int iy = py + 2 * (4 * NCB * Y0 + yi);
+    m |= (iy < N && iy + dy >= 0 && iy + dy < N) ? (xm << (4 * yi)) : 0u;
+  }
+  return m;
+}
+
 template <typename T, int TW, int NCB>
 __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   typedef M2LTypes<T> Ty;
@@ -143,6 +161,16 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     accI[j] = AC{0, 0, 0, 0};
   }
 
+  // staging constants: thread's first element, the per-step advance, and the
+  // moment address of target n at offset (0, 0, 0):
+  //   ((ix N + iy) N + iz) nR with ix = px + 2 (4 X0 + (n & 3)), iy = py + 2 (4 NCB Y0 + (n >> 2))
+  const int n0 = tid / a.nR, kk0 = tid - n0 * a.nR;
+  const int step_q = 256 / a.nR, step_r = 256 - step_q * a.nR;
+  int tbase[4];
+#pragma unroll
+  for (int xi = 0; xi < 4; ++xi)
+    tbase[xi] = (((px + 2 * (4 * X0 + xi)) * N + (py + 8 * NCB * Y0)) * N + iz) * a.nR;
+  const int tbase_y = 2 * N * a.nR;
   for (int pass = 0; pass < 2; ++pass) {
     const T2* table = pass ? (const T2*)Ty::tableS(L) : (const T2*)Ty::tableF(L);
     if (!table) continue;
@@ -157,30 +185,31 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
           const int dx = ox - 2 - px;
           const bool nearb = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
           if (nearb && !(L.leaf && near_ok)) continue;
-          unsigned smask = 0;
-          for (int n = 0; n < NT; ++n) {
-            const int ix = px + 2 * (4 * X0 + (n & 3)) + dx, iy = py + 2 * (4 * NCB * Y0 + (n >> 2)) + dy;
-            if (((tmask >> n) & 1) && ix >= 0 && iy >= 0 && ix < N && iy < N) smask |= 1u << n;
-          }
+          const unsigned smask = tile_mask<NCB>(N, px, py, X0, Y0, dx, dy);
           if (!smask) continue;
           const int key = pass ? ((dx + 3) * 7 + (dy + 3)) * (2 * N - 1) + (2 * iz + dz)
                                : ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
           __syncthreads();
           const T2* g = table + (int64_t)key * a.nG;
           for (int e = tid; e < a.nG; e += 256) sG[a.gpad[e]] = g[e];
-          for (int e = tid; e < NT * a.nR; e += 256) {
-            const int n = e / a.nR, kk = e - n * a.nR;
-            T2 v;
-            v.x = 0;
-            v.y = 0;
-            if ((smask >> n) & 1) {
-              const int ix = px + 2 * (4 * X0 + (n & 3)) + dx, iy = py + 2 * (4 * NCB * Y0 + (n >> 2)) + dy;
-              const int64_t sb = ((int64_t)ix * N + iy) * N + (iz + dz);
-              const double s = (mirror && ((sCol[kk] >> 20) & 1)) ? -1.0 : 1.0;
-              const double2 av = alpha[sb * a.nR + kk];
-              v = Ty::cvt(make_double2(av.x * s, av.y * s));
+          // element e = tid + 256 i of the NT x nR moment block: target n, index kk
+          // (advanced by 256 = q nR + rem per step, without a division per element)
+          {
+            int n = n0, kk = kk0;
+            const int delta = ((dx * N + dy) * N + dz) * a.nR;
+            for (int e = tid; e < NT * a.nR; e += 256) {
+              T2 v;
+              v.x = 0;
+              v.y = 0;
+              if ((smask >> n) & 1) {
+                const double s = (mirror && ((sCol[kk] >> 20) & 1)) ? -1.0 : 1.0;
+                const double2 av = alpha[tbase[n & 3] + tbase_y * (n >> 2) + kk + delta];
+                v = Ty::cvt(make_double2(av.x * s, av.y * s));
+              }
+              sA[n * a.nRs + kk] = v;
+              n += step_q, kk += step_r;
+              if (kk >= a.nR) kk -= a.nR, ++n;
             }
-            sA[n * a.nRs + kk] = v;
           }
           __syncthreads();
           for (int kb = 0; kb < a.nKB; ++kb) {
