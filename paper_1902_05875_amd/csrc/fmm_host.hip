@@ -1011,6 +1011,10 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   return TEFMM_OK;
 }
 
+// Offset splits of the same-layer M2L: shallow trees have few tiles (304 work-
+// groups at depth 4), so each tile's offsets are shared by several workgroups.
+static int m2l_split(int depth) { return depth <= 4 ? 4 : (depth == 5 ? 2 : 1); }
+
 static int ensure_rhs(tefmm_t h, int nrhs) {
   if (nrhs <= h->nrhs_alloc) return TEFMM_OK;
   dfree(h->d_q);
@@ -1039,7 +1043,7 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
       HIPCHK(h, hipMalloc(&g.alpha[lev], sizeof(double2) * nbx * h->nC * nrhs));
       HIPCHK(h, hipMalloc(&g.beta[lev], sizeof(double2) * nbx * h->nC * nrhs));
       HIPCHK(h, hipMalloc(&g.ared[lev], sizeof(double2) * nbx * h->nR * nrhs));
-      HIPCHK(h, hipMalloc(&g.bred[lev], sizeof(double2) * nbx * h->nR * nrhs));
+      HIPCHK(h, hipMalloc(&g.bred[lev], sizeof(double2) * nbx * h->nR * nrhs * m2l_split(g.depth)));
       if (h->groups.size() > 1) {
         HIPCHK(h, hipMalloc(&g.azred[lev], sizeof(double2) * nbx * h->nR * nrhs));
         HIPCHK(h, hipMalloc(&g.bzred[lev], sizeof(double2) * nbx * h->nR * nrhs));
@@ -1088,6 +1092,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     const double hl = g.side / (1 << lev), kh = h->med.k[g.layer] * hl;
     ra.p = p, ra.nC = h->nC, ra.nR = h->nR, ra.kh2 = kh * kh, ra.mi = h->d_mi, ra.rfull = z ? h->d_rzfull : h->d_rfull;
     ra.scale = h->d_scale, ra.invfact = h->d_invfact;
+    ra.nsplit = 1, ra.split_stride = 0;
     return ra;
   };
   EVREC(0);
@@ -1146,9 +1151,11 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       L.n = 1 << lev, L.leaf = lev == H;
       L.near_fd = g.has[2], L.near_s = g.has[0] || g.has[1];
       L.a = g.ared[lev], L.b = g.bred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
+      L.split_stride = g.nbox[lev] * h->nR * h->nrhs_alloc;
       L.Tfd = g.Tfd[lev], L.TS = g.TS[lev], L.Tfd32 = g.Tfd32[lev], L.TS32 = g.TS32[lev];
     }
     m.ncb = h->m2l_ncb ? h->m2l_ncb : h->opt.m2l_tile;
+    m.nsplit = m2l_split(H);
     HIPCHK(h, launch_m2l(m, nrhs, fp32, s));
     const double per = 8.0 * (double)h->nR * (double)h->nR;
     for (int lev = 2; lev <= H; ++lev) {
@@ -1189,6 +1196,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       ReduceArgs ra = reduce_args(g, lev, false);
       ra.in = g.bred[lev], ra.out = g.beta[lev];
       ra.in_stride = g.nbox[lev] * h->nR, ra.out_stride = g.nbox[lev] * h->nC;
+      ra.nsplit = m2l_split(H), ra.split_stride = g.nbox[lev] * h->nR * h->nrhs_alloc;
       hipLaunchKernelGGL(k_expand, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, ra);
       HIPCHK(h, hipGetLastError());
       if (g.has_cross) {

@@ -474,13 +474,21 @@ __global__ __launch_bounds__(64) void k_expand_z_add(ReduceArgs a) {
   }
 }
 
-// k_expand: b (k1 <= 1) -> all |k| <= p by b_k = -b_{k-2e1+2e2} - b_{k-2e1+2e3}
-// - (kh)^2 b_{k-2e1}, then beta^_k = b_k / k!.  Overwrites beta^.
+// k_expand: b (k1 <= 1; the sum of nsplit partial sets) -> all |k| <= p by
+// b_k = -b_{k-2e1+2e2} - b_{k-2e1+2e3} - (kh)^2 b_{k-2e1}, then beta^_k = b_k / k!.
+// Overwrites beta^.
 __global__ __launch_bounds__(64) void k_expand(ReduceArgs a) {
   extern __shared__ double2 lds_exp[];  // [nC]
   const int box = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
   const double2* in = a.in + (int64_t)r * a.in_stride + (int64_t)box * a.nR;
-  for (int i = tid; i < a.nR; i += 64) lds_exp[a.rfull[i]] = in[i];
+  for (int i = tid; i < a.nR; i += 64) {
+    double2 v = in[i];
+    for (int sp = 1; sp < a.nsplit; ++sp) {  // partial sets of a split M2L, fixed order
+      const double2 u = in[(int64_t)sp * a.split_stride + i];
+      v.x += u.x, v.y += u.y;
+    }
+    lds_exp[a.rfull[i]] = v;
+  }
   __syncthreads();
   for (int k1 = 2; k1 <= a.p; ++k1) {
     const int m = a.p - k1;

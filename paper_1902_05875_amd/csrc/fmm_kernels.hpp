@@ -71,6 +71,8 @@ struct ReduceArgs {
   const double2* in;     // reduce: alpha^ [rhs][box][nC];  expand: b [rhs][box][nR]
   double2* out;          // reduce: a [rhs][box][nR];      expand: beta^ [rhs][box][nC]
   int64_t in_stride, out_stride;  // per-rhs strides (elements)
+  int nsplit;            // expand: partial sets of b to sum (1 if unsplit)
+  int64_t split_stride;  // elements between partial sets
 };
 
 // One tree level of the M2L launch.
@@ -86,6 +88,7 @@ struct M2LLevel {
   const double2* TS;     // [49 (2n-1)][nG] Sigma family or null
   const float2* Tfd32;   // FP32 copies (mixed precision)
   const float2* TS32;
+  int64_t split_stride;  // elements between the partial outputs of the offset splits
 };
 
 constexpr int M2L_MAX_LEVELS = 8;
@@ -95,6 +98,8 @@ struct M2LArgs {
   int nG, p, P2;         // compact table size, order, 2p + 1
   int nlev;              // levels in this launch; the last one is the widest
   int ncb;               // targets per workgroup / 16: 1 or 2, 0 = automatic
+  int nsplit;            // the offsets of a tile are split over nsplit workgroups (blockIdx.z),
+                         // each writing its own partial locals (summed in fixed order by k_expand)
   int tile_start[M2L_MAX_LEVELS + 1];
   M2LLevel lev[M2L_MAX_LEVELS];
   const int* rmi;        // [nR] packed reduced multi-indices

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     if (tile >= nt) return;
   }
   const M2LLevel& L = a.lev[li];
-  const int r = blockIdx.y;
+  const int r = blockIdx.y, split = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int t = tile;
   const int X0 = t % L.tiles_x;
@@ -112,6 +112,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   t /= L.tiles_y;
   const int px = t & 1, py = (t >> 1) & 1, iz = t >> 2;
   const int N = L.n, pz = iz & 1;
+  int ocount = 0;  // offsets with work so far; this workgroup takes those with ocount % nsplit == split
   // target n: ix = px + 2 (4 X0 + (n & 3)), iy = py + 2 (4 NCB Y0 + (n >> 2))
   unsigned tmask = 0;
   for (int n = 0; n < NT; ++n) {
@@ -187,6 +188,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
           if (nearb && !(L.leaf && near_ok)) continue;
           const unsigned smask = tile_mask<NCB>(N, px, py, X0, Y0, dx, dy);
           if (!smask) continue;
+          if ((ocount++) % a.nsplit != split) continue;
           const int key = pass ? ((dx + 3) * 7 + (dy + 3)) * (2 * N - 1) + (2 * iz + dz)
                                : ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
           __syncthreads();
@@ -247,7 +249,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     }
   }
   // epilogue: result rows per the precision's MFMA layout, columns = targets
-  double2* beta = L.b + (int64_t)r * L.rhs_stride;
+  double2* beta = L.b + (int64_t)split * L.split_stride + (int64_t)r * L.rhs_stride;
 #pragma unroll
   for (int j = 0; j < TW; ++j) {
     const int id = w + 4 * j;
@@ -282,7 +284,8 @@ static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
   const size_t lds = (size_t)3 * a.P2 * a.P2 * sizeof(T2) + (size_t)16 * NCB * a.nRs * sizeof(T2) +
                      4 * (size_t)a.nKB * sizeof(int);
   const int TW = (a.nRB * NCB + 3) / 4;
-  dim3 grid(total, nrhs), block(256);
+  if (a.nsplit < 1) a.nsplit = 1;
+  dim3 grid(total, nrhs, a.nsplit), block(256);
   void (*fn)(M2LArgs) = nullptr;
   switch (TW) {
     case 1: fn = k_m2l<T, 1, NCB>; break;
