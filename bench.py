@@ -31,7 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "target evals/sec at N=1M, rel err≤1e-4: surrogate+FP32 vs plain FP64 FMM"
-PEAK = {"fp64": 78.6, "fp32": 157.3}  # TFLOP/s, dense MFMA, MI355X published
+PEAK = {"fp64": 78.6, "fp32": 157.3}  # TFLOP/s, MI355X published: dense MFMA, and the vector ALUs alike
+# algorithmic flops of one P2P pair: distance (3 sub, 3 mul, 2 add), 1/r and r (2),
+# k r (1), sin and cos (2), exp(ikr)/r (2), complex multiply-add into the sum (8)
+P2P_FLOPS_PER_PAIR = 23
 SHAPES = {"c1": "uniform unit cube centred (0,0,-0.6)", "c2": "uniform unit cube centred (0,0,-0.6)",
           "c4": "uniform unit cube centred (0,0,-0.6)", "c5": "uniform unit cube centred (0,0,-0.6)",
           "c3": "split over three unit cubes centred (0,0,0.6), (0,0,-0.6), (0,0,-1.8), one per layer"}
@@ -85,21 +88,18 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload, surrogate=
         f.evaluate(qt, out=out)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f.reset_timers()  # phase times below average over exactly the timed evaluations
     ev0.record(stream)
     for _ in range(steps):
         f.evaluate(qt, out=out)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / steps
-    # phase breakdown (library HIP events on the same stream), outside the timed region
-    phases = {k: 0.0 for k in ("t_p2m_ms", "t_m2m_ms", "t_m2l_ms", "t_l2l_ms", "t_l2p_ms", "t_p2p_ms", "t_total_ms")}
-    nprof = max(1, min(3, steps))
-    st = None
-    for _ in range(nprof):
-        f.evaluate(qt, out=out)
-        st = f.stats()
-        for k in phases:
-            phases[k] += st[k] / nprof
+    # per-phase kernel times: library HIP events on the evaluate stream, recorded inside
+    # every timed evaluation and averaged over them
+    st = f.stats()
+    assert st["timed_evaluations"] == min(steps, 64)
+    phases = {k: st[k] for k in ("t_p2m_ms", "t_m2m_ms", "t_m2l_ms", "t_l2l_ms", "t_l2p_ms", "t_p2p_ms", "t_total_ms")}
     phi = out[0].cpu().numpy() if out.dim() == 2 else out.cpu().numpy()
     err, nchk = _sampled_error(workload, phi)
     res = {
@@ -107,15 +107,60 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload, surrogate=
         "evals_per_s": q.shape[0] * q.shape[1] / (ms / 1e3) if q.ndim == 2 else xyz.shape[0] / (ms / 1e3),
         "phases_ms": {k[2:-3]: round(v, 4) for k, v in phases.items()},
         "m2l_flops": st["m2l_flops"], "m2l_launches": st["m2l_launches"], "depth": st["depth"][0],
+        "p2p_flops": P2P_FLOPS_PER_PAIR * st["p2p_pairs"] * q.shape[0], "n_groups": sum(1 for d in st["depth"] if d),
         "images": st["n_images"], "p2p_pairs": st["p2p_pairs"],
         "rel_err_sampled": err, "n_checked": nchk, "t_setup_tables_ms": st["t_setup_tables_ms"],
         "sigma_keys": st["sigma_keys"], "surrogate_keys": st["surrogate_keys"], "surrogate": sur_info,
-        "cross_pairs": st["cross_pairs"], "autotune": tuned,
+        "cross_pairs": st["cross_pairs"], "autotune": tuned, "workload": workload,
     }
     f.close()
     del xt, qt, out
     torch.cuda.empty_cache()
     return res
+
+
+def _traffic(kernel, src, workload, launches):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE runs, each scaled by the same counter on a copy of known size), if the
+    kernel's source is unchanged since the counters were taken; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1902_05875_amd", "csrc", src), "rb").read()).hexdigest()
+    if vals.get("source_sha256") != sha:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
+def roofline(head):
+    """Roofline of the dominant kernel (the larger of the P2P and M2L phases) and of the other."""
+    prec = "fp32" if head["precision"] == "fp32" else "fp64"
+    ph = head["phases_ms"]
+    n_launch = max(1, head["n_groups"])
+    p2p = {"bound": "alu", "achieved": head["p2p_flops"] / (ph["p2p"] / 1e3) / 1e12 if ph["p2p"] > 0 else 0.0,
+           "peak": PEAK[prec], "unit": "TFLOP/s",
+           "kernel": f"k_p2p<{'float' if prec == 'fp32' else 'double'}> (vector ALU), {n_launch} launch(es)/step, "
+                     f"avg {ph['p2p'] / n_launch:.3f} ms; {P2P_FLOPS_PER_PAIR} flop per pair x "
+                     f"{head['p2p_pairs']} pairs"}
+    m2l = {"bound": "mfma", "achieved": head["m2l_flops"] / (ph["m2l"] / 1e3) / 1e12 if ph["m2l"] > 0 else 0.0,
+           "peak": PEAK[prec], "unit": "TFLOP/s",
+           "kernel": f"k_m2l ({prec.upper()} MFMA 16x16x4), {head['m2l_launches']} launch(es)/step, "
+                     f"avg {ph['m2l'] / max(1, head['m2l_launches']):.3f} ms; 8 (p+1)^4 flop per box pair"}
+    wl = head["workload"]
+    tp = _traffic("k_p2p", "fmm_kernels.hip", wl, n_launch)
+    tm = _traffic("k_m2l", "fmm_m2l.hip", wl, head["m2l_launches"])
+    p2p["traffic"] = tp
+    m2l["traffic"] = tm
+    for r in (p2p, m2l):
+        r["achieved"] = round(r["achieved"], 3)
+        r["frac"] = round(r["achieved"] / r["peak"], 4)
+    return (p2p, m2l) if ph["p2p"] >= ph["m2l"] else (m2l, p2p)
 
 
 def cpu_baseline(xyz, q):
@@ -211,13 +256,7 @@ def main():
         print(f"[bench] {m}: {modes[m]['ms_per_step']:.2f} ms/step, err {modes[m]['rel_err_sampled']}",
               file=sys.stderr, flush=True)
     head = modes[args.headline] if args.headline in modes else next(iter(modes.values()))
-    m2l_ms = head["phases_ms"]["m2l"]
-    achieved = head["m2l_flops"] / (m2l_ms / 1e3) / 1e12 if m2l_ms > 0 else 0.0
-    peak = PEAK["fp32" if head["precision"] == "fp32" else "fp64"]
-    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": f"k_m2l ({'FP32' if head['precision'] == 'fp32' else 'FP64'} MFMA 16x16x4), "
-                      f"{head['m2l_launches']} launches/step, avg {m2l_ms / max(1, head['m2l_launches']):.3f} ms"}
+    roof, roof_other = roofline(head)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -232,7 +271,7 @@ def main():
                    "p": head["p"], "precision": head["precision"], "max_leaf": args.max_leaf,
                    "depth": head["depth"], "m2l_tile": (head["autotune"] or {}).get("m2l_tile"),
                    "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu, "modes": modes,
+        "roofline": roof, "roofline_other": roof_other, "cpu_baseline": cpu, "modes": modes,
     }
     print(json.dumps(line))
 

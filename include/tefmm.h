@@ -91,7 +91,9 @@ typedef struct {
   int m2l_tile;       /* M2L targets per workgroup / 16: 1 or 2 (0 = automatic; tefmm_autotune measures) */
 } tefmm_options;
 
-/* Timings (ms, measured with HIP events on the evaluate stream) and counters. */
+/* Timings (ms, measured with HIP events on the evaluate stream; the phase
+ * times are averages over the evaluations since the last tefmm_reset_timers,
+ * at most the last 64) and counters. */
 typedef struct {
   double t_setup_tree_ms, t_setup_tables_ms, t_setup_dcim_ms;
   double t_p2m_ms, t_m2m_ms, t_m2l_ms, t_l2l_ms, t_l2p_ms, t_p2p_ms, t_total_ms;
@@ -112,6 +114,7 @@ typedef struct {
   double cross_fit_err;  /* their largest relative misfit on the sampling paths */
   int64_t sigma_keys;    /* rows of the Sigma-family tables of the geometry */
   int64_t surrogate_keys; /* of those, rows produced by the attached surrogate network */
+  int timed_evaluations; /* evaluations the phase times t_p2m_ms .. t_total_ms average over */
 } tefmm_stats;
 
 /* Fill an options struct with the defaults (p = 8, depth auto, max_leaf 64,
@@ -167,6 +170,8 @@ int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_out);
 /* Statistics of the last set_particles / evaluate (timings need the stream
  * to have completed; this call synchronises it). */
 int tefmm_get_stats(tefmm_t h, tefmm_stats* st);
+/* Start a new averaging window for the phase times of tefmm_get_stats. */
+int tefmm_reset_timers(tefmm_t h);
 
 const char* tefmm_last_error(tefmm_t h);
 void tefmm_destroy(tefmm_t h);

@@ -27,7 +27,8 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_mlp_create", "tefmm_mlp_destroy", "tefmm_mlp_num_params", "tefmm_mlp_last_error",
            "tefmm_mlp_set_params", "tefmm_mlp_get_params", "tefmm_mlp_forward", "tefmm_mlp_loss_grad",
            "tefmm_mlp_adam_step", "tefmm_mlp_train", "tefmm_surrogate_default_options", "tefmm_surrogate_train",
-           "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors"]
+           "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
+           "tefmm_reset_timers"]
 
 
 class TefmmError(RuntimeError):
@@ -57,7 +58,8 @@ class StatsC(ctypes.Structure):
         ("dcim_fit_err", ctypes.c_double * 8), ("depth", ctypes.c_int * 4), ("n_families", ctypes.c_int),
         ("m2l_flops", ctypes.c_double), ("m2l_launches", ctypes.c_int), ("n_rhs", ctypes.c_int),
         ("cross_pairs", ctypes.c_int64), ("cross_pairs_forced", ctypes.c_int64), ("n_cross_fits", ctypes.c_int),
-        ("cross_fit_err", ctypes.c_double), ("sigma_keys", ctypes.c_int64), ("surrogate_keys", ctypes.c_int64)]
+        ("cross_fit_err", ctypes.c_double), ("sigma_keys", ctypes.c_int64), ("surrogate_keys", ctypes.c_int64),
+        ("timed_evaluations", ctypes.c_int)]
 
 
 class SurOptionsC(ctypes.Structure):
@@ -133,6 +135,7 @@ def lib():
         L.tefmm_surrogate_cell_ok.argtypes = [vp, i32, vp, vp]
         L.tefmm_set_surrogate.argtypes = [vp, vp]
         L.tefmm_surrogate_cell_errors.argtypes = [vp, vp]
+        L.tefmm_reset_timers.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -230,6 +233,10 @@ class TEFMM:
         d, c = ctypes.c_int(), ctypes.c_int()
         _check(lib().tefmm_autotune(self.h, _stream_ptr(stream), ctypes.byref(d), ctypes.byref(c)), self.h)
         return d.value, c.value
+
+    def reset_timers(self):
+        """Start a new averaging window for the phase times reported by stats()."""
+        _check(lib().tefmm_reset_timers(self.h), self.h)
 
     def stats(self) -> dict:
         s = StatsC()

@@ -106,7 +106,8 @@ struct tefmm_ctx {
   bool ready = false;
   // stats
   tefmm_stats st;
-  std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t> ev;  // EV_RING sets of 8 phase events
+  int ev_next = 0, ev_count = 0;
   int64_t p2p_pairs = 0, m2l_pairs = 0;
   int64_t sigma_keys = 0, sur_keys = 0;  // Sigma table rows of the geometry / answered by the surrogate
   // copy of the caller's positions (SoA), kept for re-building the tree (autotuner)
@@ -125,11 +126,13 @@ struct tefmm_ctx {
     hipGraphExec_t exec = nullptr;
     hipStream_t origin = nullptr;
     std::vector<hipStream_t> side;
-    std::vector<hipEvent_t> ev;
+    std::vector<hipEvent_t> ev;  // EV_RING sets of 8 phase events
+  int ev_next = 0, ev_count = 0;
   } batch;
 };
 
 static void batch_destroy(tefmm_ctx::Batch& b);
+static constexpr int EV_RING = 64;  // evaluations whose phase times are kept
 static std::atomic<uint64_t> g_generation{1};
 
 static int fail(tefmm_t h, int code, const std::string& msg) {
@@ -1066,12 +1069,18 @@ static int check_eval_args(tefmm_t h, const double* q, int nrhs, double* phi) {
 // With timed = false no events are recorded (graph capture).
 static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, hipStream_t s, bool timed) {
   if (timed && h->ev.empty()) {
-    h->ev.resize(8);
+    h->ev.resize(8 * EV_RING);
     for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
   }
-#define EVREC(i)                                   \
-  do {                                             \
-    if (timed) HIPCHK(h, hipEventRecord(h->ev[i], s)); \
+  // phase events of this evaluation: set ev_next of the ring
+  const int evset = h->ev_next;
+  if (timed) {
+    h->ev_next = (h->ev_next + 1) % EV_RING;
+    h->ev_count = std::min(h->ev_count + 1, EV_RING);
+  }
+#define EVREC(i)                                                 \
+  do {                                                           \
+    if (timed) HIPCHK(h, hipEventRecord(h->ev[8 * evset + (i)], s)); \
   } while (0)
   const int64_t n = h->n;
   const int p = h->opt.p;
@@ -1407,21 +1416,39 @@ extern "C" int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_
 
 extern "C" int tefmm_get_stats(tefmm_t h, tefmm_stats* st) {
   if (!h || !st) return TEFMM_ERR_INVALID_ARG;
-  if (h->ev.size() == 8) {
-    HIPCHK(h, hipEventSynchronize(h->ev[7]));
-    float t[8] = {0};
-    for (int i = 1; i < 8; ++i) (void)hipEventElapsedTime(&t[i], h->ev[i - 1], h->ev[i]);
-    h->st.t_p2m_ms = t[1] + 0;  // includes the charge gather
-    h->st.t_m2m_ms = t[2];
-    h->st.t_m2l_ms = t[3];
-    h->st.t_l2l_ms = t[4];
-    h->st.t_l2p_ms = t[5];
-    h->st.t_p2p_ms = t[6];
-    float tot = 0;
-    (void)hipEventElapsedTime(&tot, h->ev[0], h->ev[7]);
-    h->st.t_total_ms = tot;
+  if (!h->ev.empty() && h->ev_count > 0) {
+    // average over the evaluations recorded since the last timer reset (at most EV_RING)
+    double t[8] = {0}, tot = 0;
+    for (int c = 0; c < h->ev_count; ++c) {
+      const int set = ((h->ev_next - 1 - c) % EV_RING + EV_RING) % EV_RING;
+      hipEvent_t* e = &h->ev[8 * set];
+      HIPCHK(h, hipEventSynchronize(e[7]));
+      for (int i = 1; i < 8; ++i) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e[i - 1], e[i]);
+        t[i] += ms;
+      }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e[0], e[7]);
+      tot += ms;
+    }
+    const double inv = 1.0 / h->ev_count;
+    h->st.t_p2m_ms = t[1] * inv;  // includes the charge gather
+    h->st.t_m2m_ms = t[2] * inv;
+    h->st.t_m2l_ms = t[3] * inv;
+    h->st.t_l2l_ms = t[4] * inv;
+    h->st.t_l2p_ms = t[5] * inv;
+    h->st.t_p2p_ms = t[6] * inv;
+    h->st.t_total_ms = tot * inv;
+    h->st.timed_evaluations = h->ev_count;
   }
   *st = h->st;
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_reset_timers(tefmm_t h) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  h->ev_count = 0;
   return TEFMM_OK;
 }
 
