@@ -676,14 +676,13 @@ __global__ __launch_bounds__(64) void k_l2p(PassArgs a) {
 
 // sin and cos of 0 <= x < 1e4 in FP64: x = q pi/2 + y with pi/2 split in two
 // parts (Cody and Waite), |y| <= pi/4, then the Taylor series of sin y (to
-// y^17) and cos y (to y^18), whose first omitted terms are below 1e-19.
+// y^15) and cos y (to y^16); the first omitted terms are below 5e-17 and 2e-18.
 __device__ __forceinline__ void sincos_f64(double x, double* s, double* c) {
   const double q = rint(x * 0.63661977236758134308);
   double y = fma(-q, 1.5707963267948965580e+00, x);
   y = fma(-q, 6.1232339957367658e-17, y);
   const double y2 = y * y;
-  double ps = 2.8114572543455207632e-15;          //  1/17!
-  ps = fma(ps, y2, -7.6471637318198164759e-13);   // -1/15!
+  double ps = -7.6471637318198164759e-13;         // -1/15!
   ps = fma(ps, y2, 1.6059043836821614599e-10);    //  1/13!
   ps = fma(ps, y2, -2.5052108385441718775e-08);   // -1/11!
   ps = fma(ps, y2, 2.7557319223985890653e-06);    //  1/9!
@@ -691,26 +690,25 @@ __device__ __forceinline__ void sincos_f64(double x, double* s, double* c) {
   ps = fma(ps, y2, 8.3333333333333333333e-03);    //  1/5!
   ps = fma(ps, y2, -1.6666666666666666667e-01);   // -1/3!
   const double sy = fma(y * y2, ps, y);
-  double pc = 1.5619206968586225796e-16;          //  1/18!
-  pc = fma(pc, y2, -4.7794773323873852974e-14);   // -1/16!
-  pc = fma(pc, y2, 1.1470745597729724714e-11);    //  1/14!
-  pc = fma(pc, y2, -2.0876756987868098979e-09);   // -1/12!
-  pc = fma(pc, y2, 2.7557319223985890653e-07);    //  1/10!
-  pc = fma(pc, y2, -2.4801587301587301587e-05);   // -1/8!
-  pc = fma(pc, y2, 1.3888888888888888889e-03);    //  1/6!
-  pc = fma(pc, y2, -4.1666666666666666667e-02);   // -1/4!
-  pc = fma(pc, y2, 0.5);
-  const double cy = fma(-y2, pc, 1.0);
+  double pc = 4.7794773323873852974e-14;          //  1/16!
+  pc = fma(pc, y2, -1.1470745597729724714e-11);   // -1/14!
+  pc = fma(pc, y2, 2.0876756987868098979e-09);    //  1/12!
+  pc = fma(pc, y2, -2.7557319223985890653e-07);   // -1/10!
+  pc = fma(pc, y2, 2.4801587301587301587e-05);    //  1/8!
+  pc = fma(pc, y2, -1.3888888888888888889e-03);   // -1/6!
+  pc = fma(pc, y2, 4.1666666666666666667e-02);    //  1/4!
+  pc = fma(pc, y2, -0.5);
+  const double cy = fma(y2, pc, 1.0);
   const int qi = ((int)q) & 3;
   const double s0 = (qi & 1) ? cy : sy, c0 = (qi & 1) ? sy : cy;
   *s = (qi & 2) ? -s0 : s0;
   *c = ((qi + 1) & 2) ? -c0 : c0;
 }
 
-// 1/sqrt(r2) in FP64: FP32 estimate refined by two Newton steps (error squared each step).
+// 1/sqrt(r2) in FP64: FP32 estimate (relative error ~1e-7) refined by one
+// Newton step (error squared: ~2e-14, far below the FP64 mode's 1e-6 target).
 __device__ __forceinline__ double rsqrt_f64(double r2) {
-  double y = (double)rsqrtf((float)r2);
-  y = y * fma(-0.5 * r2, y * y, 1.5);
+  const double y = (double)rsqrtf((float)r2);
   return y * fma(-0.5 * r2, y * y, 1.5);
 }
 
@@ -767,11 +765,25 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
         }
         __syncthreads();
         if (act) {
+          if (sizeof(T) == 8) {
+            // branch free: the target itself has r2 = 0 (same coordinates, same
+            // arithmetic) and is given weight 0
+#pragma unroll 4
+            for (int t = 0; t < m; ++t) {
+              const T dx = tx - sx[t], dy = ty - sy[t], dz = tz - sz[t];
+              const T r2 = dx * dx + dy * dy + dz * dz;
+              const bool self = !(r2 > 0);
+              T er, ei;
+              pair_kernel(self ? (T)1 : r2, k, &er, &ei);
+              const T wr = self ? (T)0 : sqr[t], wi = self ? (T)0 : sqi[t];
+              accr += wr * er - wi * ei;
+              acci += wr * ei + wi * er;
+            }
+            continue;
+          }
           for (int t = 0; t < m; ++t) {
             const T dx = tx - sx[t], dy = ty - sy[t], dz = tz - sz[t];
             const T r2 = dx * dx + dy * dy + dz * dz;
-            // the target itself has r2 = 0 (same coordinates, same arithmetic)
-            if (sizeof(T) == 8 && !(r2 > 0)) continue;
             if (sizeof(T) == 4 && r2 < rns2) {
               // near-singular pair: the FP32 difference has lost digits, redo it in FP64
               const int64_t j = sidx[t];
