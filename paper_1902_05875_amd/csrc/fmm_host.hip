@@ -1017,6 +1017,9 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
 // Offset splits of the same-layer M2L: shallow trees have few tiles (304 work-
 // groups at depth 4), so each tile's offsets are shared by several workgroups.
 static int m2l_split(int depth) { return depth <= 4 ? 4 : (depth == 5 ? 2 : 1); }
+// The cross-layer lists of the coarse levels hold up to 2 x 196 entries per tile
+// on few tiles; their entries are split over this many workgroups.
+static constexpr int CROSS_SPLIT = 8;
 
 static int ensure_rhs(tefmm_t h, int nrhs) {
   if (nrhs <= h->nrhs_alloc) return TEFMM_OK;
@@ -1049,7 +1052,7 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
       HIPCHK(h, hipMalloc(&g.bred[lev], sizeof(double2) * nbx * h->nR * nrhs * m2l_split(g.depth)));
       if (h->groups.size() > 1) {
         HIPCHK(h, hipMalloc(&g.azred[lev], sizeof(double2) * nbx * h->nR * nrhs));
-        HIPCHK(h, hipMalloc(&g.bzred[lev], sizeof(double2) * nbx * h->nR * nrhs));
+        HIPCHK(h, hipMalloc(&g.bzred[lev], sizeof(double2) * nbx * h->nR * nrhs * CROSS_SPLIT));
       }
     }
   }
@@ -1181,11 +1184,13 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       c.nR = h->nR, c.nRs = h->nRs, c.nKB = h->nKB, c.nRB = h->nRB, c.nG = h->nG, c.p = p, c.P2 = 2 * p + 1;
       c.rzmi = h->d_rzmi, c.gpadz = h->d_gpadz;
       c.nlev = H - 1;
+      c.nsplit = CROSS_SPLIT;
       for (int lev = 2; lev <= H; ++lev) {
         M2LCrossLevel& L = c.lev[lev - 2];
         L.n = 1 << lev;
         L.list_start = g.xlist_start[lev], L.list = g.xlist[lev];
         L.b = g.bzred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
+        L.split_stride = g.nbox[lev] * h->nR * h->nrhs_alloc;
         L.T[0] = g.XT0[lev], L.T[1] = g.XT1[lev], L.T32[0] = g.XT032[lev], L.T32[1] = g.XT132[lev];
         for (size_t sg = 0; sg < h->groups.size() && sg < 4; ++sg) {
           L.asrc[sg] = h->groups[sg].azred[lev];
@@ -1212,6 +1217,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
         ReduceArgs rz = reduce_args(g, lev, true);
         rz.in = g.bzred[lev], rz.out = g.beta[lev];
         rz.in_stride = g.nbox[lev] * h->nR, rz.out_stride = g.nbox[lev] * h->nC;
+        rz.nsplit = CROSS_SPLIT, rz.split_stride = g.nbox[lev] * h->nR * h->nrhs_alloc;
         hipLaunchKernelGGL(k_expand_z_add, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s,
                            rz);
         HIPCHK(h, hipGetLastError());

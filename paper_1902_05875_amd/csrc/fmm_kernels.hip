@@ -450,7 +450,14 @@ __global__ __launch_bounds__(64) void k_expand_z_add(ReduceArgs a) {
   extern __shared__ double2 lds_ez[];  // [nC]
   const int box = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
   const double2* in = a.in + (int64_t)r * a.in_stride + (int64_t)box * a.nR;
-  for (int i = tid; i < a.nR; i += 64) lds_ez[a.rfull[i]] = in[i];
+  for (int i = tid; i < a.nR; i += 64) {
+    double2 v = in[i];
+    for (int sp = 1; sp < a.nsplit; ++sp) {  // partial sets of a split translation, fixed order
+      const double2 u = in[(int64_t)sp * a.split_stride + i];
+      v.x += u.x, v.y += u.y;
+    }
+    lds_ez[a.rfull[i]] = v;
+  }
   __syncthreads();
   for (int k3 = 2; k3 <= a.p; ++k3) {
     const int m = a.p - k3;

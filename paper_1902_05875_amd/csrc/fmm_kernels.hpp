@@ -123,11 +123,13 @@ struct M2LCrossLevel {
   const float2* T32[2];
   const double2* asrc[4];  // z-reduced moments of each source group at this level
   int64_t src_stride[4];
+  int64_t split_stride;    // elements between the partial outputs of the list splits
 };
 
 struct M2LCrossArgs {
   int nR, nRs, nKB, nRB, nG, p, P2;
   int nlev;
+  int nsplit;              // list entries of a tile split over nsplit workgroups (blockIdx.z)
   int tile_start[M2L_MAX_LEVELS + 1];
   M2LCrossLevel lev[M2L_MAX_LEVELS];
   const int* rzmi;         // [nR] z-reduced multi-indices (packed)

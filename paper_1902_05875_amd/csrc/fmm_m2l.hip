@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
     if (tile >= nt) return;
   }
   const M2LCrossLevel& L = a.lev[li];
-  const int r = blockIdx.y;
+  const int r = blockIdx.y, split = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int t = tile;
   const int X0 = t % L.tiles_x;
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
   }
   const int cls = 4 * iz + px + 2 * py;
   const int e0 = L.list_start[cls], e1 = L.list_start[cls + 1];
-  for (int ei = e0; ei < e1; ++ei) {
+  for (int ei = e0 + split; ei < e1; ei += a.nsplit) {
     const CrossEntry ce = L.list[ei];
     unsigned smask = 0;
     for (int n = 0; n < NT; ++n) {
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
         }
     }
   }
-  double2* beta = L.b + (int64_t)r * L.rhs_stride;
+  double2* beta = L.b + (int64_t)split * L.split_stride + (int64_t)r * L.rhs_stride;
 #pragma unroll
   for (int j = 0; j < TW; ++j) {
     const int id = w + 4 * j;
@@ -516,7 +516,8 @@ static hipError_t launch_cross_t2(const M2LCrossArgs& a0, int nrhs, hipStream_t 
   const size_t lds = (size_t)4 * a.P2 * a.P2 * sizeof(T2) + (size_t)16 * NCB * a.nRs * sizeof(T2) +
                      4 * (size_t)a.nKB * sizeof(int);
   const int TW = (a.nRB * NCB + 3) / 4;
-  dim3 grid(total, nrhs), block(256);
+  if (a.nsplit < 1) a.nsplit = 1;
+  dim3 grid(total, nrhs, a.nsplit), block(256);
   void (*fn)(M2LCrossArgs) = nullptr;
   switch (TW) {
     case 1: fn = k_m2l_cross<T, 1, NCB>; break;

@@ -69,3 +69,21 @@ def test_c3small(p, precision, tol):
           f"cross pairs {st['cross_pairs']} fits {st['n_cross_fits']} fit err {st['cross_fit_err']:.1e}")
     assert st["cross_pairs_forced"] == 0
     assert e < tol
+
+
+@pytest.mark.parametrize("p,precision,tol", [(12, "fp64", 1e-6), (10, "fp32", 1e-4)])
+def test_c3_full_size_sampled(p, precision, tol):
+    """C3 at full size: N = 1,000,000 over three layer cubes, 6 sampled targets per layer
+    against the oracle (the configuration the three-layer bench line runs)."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c3")
+    a = np.loadtxt(os.path.join(GOLD, "expected_c3s.txt"))
+    idx, ref = a[:, 0].astype(int), a[:, 1] + 1j * a[:, 2]
+    phi, st = _run(K3, xyz, q, p=p, precision=precision)
+    e = _err(phi[idx], ref)
+    lay = _layers(xyz[idx])
+    per = [_err(phi[idx][lay == l], ref[lay == l]) for l in range(3)]
+    print(f"c3 N=1M p={p} {precision}: rel err {e:.3e} per layer {per} depth {st['depth']} "
+          f"cross pairs {st['cross_pairs']} fits {st['n_cross_fits']}")
+    assert st["cross_pairs_forced"] == 0
+    assert e < tol
