@@ -725,11 +725,13 @@ __device__ __forceinline__ void pair_kernel(double r2, double k, double* er, dou
   sincos_f64(k * (r2 * ri), &sn, &cs);
   *er = cs * ri, *ei = sn * ri;
 }
-__device__ __forceinline__ void pair_kernel(float r2, float k, float* er, float* ei) {
+// FP32 pair on coordinates pre-scaled by k / (2 pi): r2 is (k r / 2 pi)^2, the
+// hardware sine and cosine take revolutions, and the common factor k / (2 pi)
+// of 1/r is applied once to the sum.
+__device__ __forceinline__ void pair_kernel(float r2, float, float* er, float* ei) {
   const float ri = rsqrtf(r2);
-  float sn, cs;
-  __sincosf(k * (r2 * ri), &sn, &cs);
-  *er = cs * ri, *ei = sn * ri;
+  const float rv = r2 * ri;
+  *er = __builtin_amdgcn_cosf(rv) * ri, *ei = __builtin_amdgcn_sinf(rv) * ri;
 }
 
 template <typename T, int BS>
@@ -742,15 +744,17 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
   const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
   const double2* q = a.q + (int64_t)r * a.n;
   const T k = (T)a.k;
+  // FP32: coordinates in units of 2 pi / k (see pair_kernel); FP64: physical
+  const double kap = sizeof(T) == 4 ? a.k / 6.283185307179586477 : 1.0;
   // pairs closer than 5% of the leaf side are evaluated in FP64 in the FP32 path
-  const T rns2 = (T)(0.0025 * a.h * a.h);
+  const T rns2 = (T)(0.0025 * a.h * a.h * kap * kap);
   const int z0 = max(iz - 1, 0), z1 = min(iz + 1, nb - 1);
   for (int c0 = 0; c0 < cnt; c0 += BS) {
     const bool act = c0 + tid < cnt;
     const int64_t i = start + c0 + tid;
     const double txd = act ? a.xs[i] : 0.0, tyd = act ? a.xs[a.n + i] : 0.0, tzd = act ? a.xs[2 * a.n + i] : 0.0;
     // coordinates relative to the root corner keep FP32 differences accurate
-    const T tx = (T)(txd - a.lo[0]), ty = (T)(tyd - a.lo[1]), tz = (T)(tzd - a.lo[2]);
+    const T tx = (T)((txd - a.lo[0]) * kap), ty = (T)((tyd - a.lo[1]) * kap), tz = (T)((tzd - a.lo[2]) * kap);
     T accr = 0, acci = 0;
     double nsr = 0.0, nsi = 0.0;  // near-singular pairs (FP32 path only)
     for (int col = 0; col < 9; ++col) {
@@ -763,9 +767,9 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
         __syncthreads();
         if (tid < m) {
           const int64_t j = s0 + tid;
-          sx[tid] = (T)(a.xs[j] - a.lo[0]);
-          sy[tid] = (T)(a.xs[a.n + j] - a.lo[1]);
-          sz[tid] = (T)(a.xs[2 * a.n + j] - a.lo[2]);
+          sx[tid] = (T)((a.xs[j] - a.lo[0]) * kap);
+          sy[tid] = (T)((a.xs[a.n + j] - a.lo[1]) * kap);
+          sz[tid] = (T)((a.xs[2 * a.n + j] - a.lo[2]) * kap);
           sqr[tid] = (T)q[j].x;
           sqi[tid] = (T)q[j].y;
           sidx[tid] = (int)j;
@@ -812,7 +816,7 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
     }
     if (act) {
       double2 o = a.phi[(int64_t)r * a.n + i];
-      a.phi[(int64_t)r * a.n + i] = make_double2(o.x + (double)accr + nsr, o.y + (double)acci + nsi);
+      a.phi[(int64_t)r * a.n + i] = make_double2(o.x + (double)accr * kap + nsr, o.y + (double)acci * kap + nsi);
     }
   }
 }

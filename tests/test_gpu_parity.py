@@ -159,3 +159,18 @@ def test_near_singular_pairs(precision):
     e = _err(phi[idx], ref)
     print(f"near-singular pairs {precision}: rel err {e:.3e}")
     assert e < 1e-6
+
+
+@pytest.mark.parametrize("p,precision,depth,tol", [(13, "fp64", 4, 1e-6), (8, "fp32", 4, 1e-4), (8, "fp32", 5, 1e-4)])
+def test_c4_full_size_sampled(p, precision, depth, tol):
+    """The bench workload at full size: N = 1,000,000 in the middle-layer cube, 16 sampled
+    targets (12 uniform + 4 nearest an interface) against the oracle, at the depth the
+    autotuner picks (4) and the occupancy default (5).  At this size p = 12 gives 1.1e-6
+    (both depths), so the FP64 operating point is p = 13."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c4")
+    idx, ref = _expected("c4s")
+    phi, st = _run(xyz, q, p=p, precision=precision, depth=depth)
+    e = _err(phi[idx], ref)
+    print(f"C4 N=1M p={p} {precision} depth {depth}: rel err {e:.3e}")
+    assert e < tol
