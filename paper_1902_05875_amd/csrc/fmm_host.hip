@@ -101,7 +101,10 @@ struct tefmm_ctx {
   int64_t total_leaves = 0;
   std::vector<Group> groups;
   // evaluate buffers
-  double2 *d_q = nullptr, *d_phi = nullptr;
+  double2 *d_q = nullptr, *d_phi = nullptr, *d_phi_near = nullptr;
+  // the near field runs on a second stream beside the far field (fork/join by events)
+  hipStream_t s2 = nullptr;
+  hipEvent_t e_fork = nullptr, e_join = nullptr;
   int nrhs_alloc = 0;
   bool ready = false;
   // stats
@@ -172,6 +175,7 @@ static void free_geometry(tefmm_t h) {
   h->groups.clear();
   dfree(h->d_q);
   dfree(h->d_phi);
+  dfree(h->d_phi_near);
   h->nrhs_alloc = 0;
   h->ready = false;
 }
@@ -321,6 +325,9 @@ extern "C" void tefmm_destroy(tefmm_t h) {
   dfree(h->d_scale);
   dfree(h->d_invfact);
   for (auto& e : h->ev) (void)hipEventDestroy(e);
+  if (h->e_fork) (void)hipEventDestroy(h->e_fork);
+  if (h->e_join) (void)hipEventDestroy(h->e_join);
+  if (h->s2) (void)hipStreamDestroy(h->s2);
   batch_destroy(h->batch);
   dfree(h->d_xyz_user);
   delete h;
@@ -1025,6 +1032,7 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
   if (nrhs <= h->nrhs_alloc) return TEFMM_OK;
   dfree(h->d_q);
   dfree(h->d_phi);
+  dfree(h->d_phi_near);
   for (auto& g : h->groups) {
     for (auto& p : g.alpha) dfree(p);
     for (auto& p : g.beta) dfree(p);
@@ -1035,6 +1043,7 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
   }
   HIPCHK(h, hipMalloc(&h->d_q, sizeof(double2) * h->n * nrhs));
   HIPCHK(h, hipMalloc(&h->d_phi, sizeof(double2) * h->n * nrhs));
+  HIPCHK(h, hipMalloc(&h->d_phi_near, sizeof(double2) * h->n * nrhs));
   for (auto& g : h->groups) {
     g.alpha.assign(g.depth + 1, nullptr);
     g.beta.assign(g.depth + 1, nullptr);
@@ -1072,8 +1081,13 @@ static int check_eval_args(tefmm_t h, const double* q, int nrhs, double* phi) {
 // With timed = false no events are recorded (graph capture).
 static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, hipStream_t s, bool timed) {
   if (timed && h->ev.empty()) {
-    h->ev.resize(8 * EV_RING);
+    h->ev.resize(9 * EV_RING);
     for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
+  }
+  if (!h->s2) {
+    HIPCHK(h, hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
+    HIPCHK(h, hipEventCreateWithFlags(&h->e_fork, hipEventDisableTiming));
+    HIPCHK(h, hipEventCreateWithFlags(&h->e_join, hipEventDisableTiming));
   }
   // phase events of this evaluation: set ev_next of the ring
   const int evset = h->ev_next;
@@ -1083,7 +1097,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
   }
 #define EVREC(i)                                                 \
   do {                                                           \
-    if (timed) HIPCHK(h, hipEventRecord(h->ev[8 * evset + (i)], s)); \
+    if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + (i)], s)); \
   } while (0)
   const int64_t n = h->n;
   const int p = h->opt.p;
@@ -1111,6 +1125,37 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
   hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, (const double2*)q,
                      h->d_perm, n, h->d_q);
   HIPCHK(h, hipGetLastError());
+  // near field (P2P, Eq. totalinteraction free part) on the second stream: it reads only
+  // particles and charges and writes its own sum, so it overlaps the far field.  Under
+  // graph capture (the batch, whose geometries are already concurrent branches) it
+  // stays on the captured stream.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIPCHK(h, hipStreamIsCapturing(s, &cap));
+  const bool fork = cap == hipStreamCaptureStatusNone;
+  hipStream_t sn = fork ? h->s2 : s;
+  if (fork) {
+    HIPCHK(h, hipEventRecord(h->e_fork, s));
+    HIPCHK(h, hipStreamWaitEvent(h->s2, h->e_fork, 0));
+  }
+  if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + 8], sn));
+  for (auto& g : h->groups) {
+    PassArgs a = pass_args(g);
+    a.phi = h->d_phi_near;
+    a.nbox_dim = 1 << g.depth, a.h = g.side / (1 << g.depth);
+    const bool wide = g.count > 96 * g.nbox[g.depth];  // mean leaf occupancy above 96
+    const dim3 grid((unsigned)g.nbox[g.depth], nrhs);
+    if (fp32 && wide)
+      hipLaunchKernelGGL((k_p2p<float, 256>), grid, dim3(256), 0, sn, a);
+    else if (fp32)
+      hipLaunchKernelGGL((k_p2p<float, 64>), grid, dim3(64), 0, sn, a);
+    else if (wide)
+      hipLaunchKernelGGL((k_p2p<double, 256>), grid, dim3(256), 0, sn, a);
+    else
+      hipLaunchKernelGGL((k_p2p<double, 64>), grid, dim3(64), 0, sn, a);
+    HIPCHK(h, hipGetLastError());
+  }
+  if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + 6], sn));
+  if (fork) HIPCHK(h, hipEventRecord(h->e_join, h->s2));
   // P2M at the leaves (Sec. 3.1)
   for (auto& g : h->groups) {
     const int H = g.depth;
@@ -1242,22 +1287,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     HIPCHK(h, hipGetLastError());
   }
   EVREC(5);
-  for (auto& g : h->groups) {
-    PassArgs a = pass_args(g);
-    a.nbox_dim = 1 << g.depth, a.h = g.side / (1 << g.depth);
-    const bool wide = g.count > 96 * g.nbox[g.depth];  // mean leaf occupancy above 96
-    const dim3 grid((unsigned)g.nbox[g.depth], nrhs);
-    if (fp32 && wide)
-      hipLaunchKernelGGL((k_p2p<float, 256>), grid, dim3(256), 0, s, a);
-    else if (fp32)
-      hipLaunchKernelGGL((k_p2p<float, 64>), grid, dim3(64), 0, s, a);
-    else if (wide)
-      hipLaunchKernelGGL((k_p2p<double, 256>), grid, dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_p2p<double, 64>), grid, dim3(64), 0, s, a);
-    HIPCHK(h, hipGetLastError());
-  }
-  EVREC(6);
+  if (fork) HIPCHK(h, hipStreamWaitEvent(s, h->e_join, 0));
   for (auto& g : h->groups) {
     double sr = 1.0 / (4 * PI), si = 0.0;
     if (h->opt.normalization == TEFMM_NORM_PAPER) {  // divide by i k of the target layer
@@ -1265,7 +1295,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       sr = 0.0, si = -1.0 / kk;
     }
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)((g.count + 255) / 256), nrhs), dim3(256), 0, s, h->d_phi,
-                       h->d_perm, g.start, g.count, n, sr, si, (double2*)phi);
+                       h->d_phi_near, h->d_perm, g.start, g.count, n, sr, si, (double2*)phi);
     HIPCHK(h, hipGetLastError());
   }
   EVREC(7);
@@ -1427,13 +1457,18 @@ extern "C" int tefmm_get_stats(tefmm_t h, tefmm_stats* st) {
     double t[8] = {0}, tot = 0;
     for (int c = 0; c < h->ev_count; ++c) {
       const int set = ((h->ev_next - 1 - c) % EV_RING + EV_RING) % EV_RING;
-      hipEvent_t* e = &h->ev[8 * set];
+      hipEvent_t* e = &h->ev[9 * set];
       HIPCHK(h, hipEventSynchronize(e[7]));
-      for (int i = 1; i < 8; ++i) {
+      // far-field phases on the caller's stream: 0 start, 1..5 after P2M, M2M, M2L,
+      // L2L, L2P; near field on the second stream: 8 start, 6 end; 7 after finalize
+      for (int i = 1; i < 6; ++i) {
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e[i - 1], e[i]);
         t[i] += ms;
       }
+      float mp = 0;
+      (void)hipEventElapsedTime(&mp, e[8], e[6]);
+      t[6] += mp;
       float ms = 0;
       (void)hipEventElapsedTime(&ms, e[0], e[7]);
       tot += ms;

@@ -280,13 +280,14 @@ __global__ void k_gather_q(const double2* q, const int* perm, int64_t n, double2
   if (i < n) qs[(int64_t)r * n + i] = q[(int64_t)r * n + perm[i]];
 }
 
-__global__ void k_finalize(const double2* phi_s, const int* perm, int64_t start, int64_t cnt, int64_t n,
-                           double sr, double si, double2* out) {
+__global__ void k_finalize(const double2* phi_s, const double2* phi_near, const int* perm, int64_t start, int64_t cnt,
+                           int64_t n, double sr, double si, double2* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int r = blockIdx.y;
   if (i >= cnt) return;
   i += start;
-  double2 v = phi_s[(int64_t)r * n + i];
+  const double2 f = phi_s[(int64_t)r * n + i], c = phi_near[(int64_t)r * n + i];
+  const double2 v = make_double2(f.x + c.x, f.y + c.y);
   out[(int64_t)r * n + perm[i]] = make_double2(v.x * sr - v.y * si, v.x * si + v.y * sr);
 }
 
@@ -677,8 +678,8 @@ __global__ __launch_bounds__(64) void k_l2p(PassArgs a) {
 // q_j exp(i k r)/r.  One block of BS lanes (64 or 256, by mean leaf occupancy)
 // per target leaf.  Leaves are stored in
 // (x, y, z) order, so the three z-neighbours of one (x, y) column are one
-// contiguous particle range: nine ranges per leaf, staged through LDS in
-// chunks of 256.  Adds into phi.
+// contiguous particle range: nine ranges per leaf, staged through LDS.
+// Writes the near-field sum (its own buffer: it runs beside the far field).
 // ---------------------------------------------------------------------------
 
 // sin and cos of 0 <= x < 1e4 in FP64: x = q pi/2 + y with pi/2 split in two
@@ -814,10 +815,7 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
         }
       }
     }
-    if (act) {
-      double2 o = a.phi[(int64_t)r * a.n + i];
-      a.phi[(int64_t)r * a.n + i] = make_double2(o.x + (double)accr * kap + nsr, o.y + (double)acci * kap + nsi);
-    }
+    if (act) a.phi[(int64_t)r * a.n + i] = make_double2((double)accr * kap + nsr, (double)acci * kap + nsi);
   }
 }
 

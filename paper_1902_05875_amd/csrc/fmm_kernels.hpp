@@ -156,8 +156,8 @@ __global__ void k_leaf_keys(const double* xyz, int64_t n, int nif, const double*
 __global__ void k_count_keys(const unsigned* keys, int64_t n, int* count);
 __global__ void k_gather_pos(const double* xyz, const int* perm, int64_t n, double* xs);
 __global__ void k_gather_q(const double2* q, const int* perm, int64_t n, double2* qs);
-__global__ void k_finalize(const double2* phi_s, const int* perm, int64_t start, int64_t cnt, int64_t n,
-                           double sr, double si, double2* out);
+__global__ void k_finalize(const double2* phi_s, const double2* phi_near, const int* perm, int64_t start, int64_t cnt,
+                           int64_t n, double sr, double si, double2* out);
 __global__ void k_p2m(PassArgs a);
 __global__ void k_reduce(ReduceArgs a);
 __global__ void k_expand(ReduceArgs a);
