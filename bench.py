@@ -119,12 +119,12 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload, surrogate=
     return res
 
 
-def _traffic(kernel, src, workload, launches):
+def _traffic(kernel, prec, src, workload):
     """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE runs, each scaled by the same counter on a copy of known size), if the
     kernel's source is unchanged since the counters were taken; else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{prec}_{workload}.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -153,8 +153,8 @@ def roofline(head):
            "kernel": f"k_m2l ({prec.upper()} MFMA 16x16x4), {head['m2l_launches']} launch(es)/step, "
                      f"avg {ph['m2l'] / max(1, head['m2l_launches']):.3f} ms; 8 (p+1)^4 flop per box pair"}
     wl = head["workload"]
-    tp = _traffic("k_p2p", "fmm_kernels.hip", wl, n_launch)
-    tm = _traffic("k_m2l", "fmm_m2l.hip", wl, head["m2l_launches"])
+    tp = _traffic("k_p2p", prec, "fmm_kernels.hip", wl)
+    tm = _traffic("k_m2l", prec, "fmm_m2l.hip", wl)
     p2p["traffic"] = tp
     m2l["traffic"] = tm
     for r in (p2p, m2l):
