@@ -1143,15 +1143,16 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     a.phi = h->d_phi_near;
     a.nbox_dim = 1 << g.depth, a.h = g.side / (1 << g.depth);
     const bool wide = g.count > 96 * g.nbox[g.depth];  // mean leaf occupancy above 96
-    const dim3 grid((unsigned)g.nbox[g.depth], nrhs);
-    if (fp32 && wide)
-      hipLaunchKernelGGL((k_p2p<float, 256>), grid, dim3(256), 0, sn, a);
-    else if (fp32)
-      hipLaunchKernelGGL((k_p2p<float, 64>), grid, dim3(64), 0, sn, a);
-    else if (wide)
-      hipLaunchKernelGGL((k_p2p<double, 256>), grid, dim3(256), 0, sn, a);
+    // several charge vectors share each pair kernel, 8 per block
+    const bool multi = nrhs > 1;
+    const dim3 grid((unsigned)g.nbox[g.depth], multi ? (nrhs + 7) / 8 : 1);
+    void (*fn)(PassArgs, int) = nullptr;
+    if (fp32)
+      fn = wide ? (multi ? k_p2p<float, 256, 8> : k_p2p<float, 256, 1>) : (multi ? k_p2p<float, 64, 8> : k_p2p<float, 64, 1>);
     else
-      hipLaunchKernelGGL((k_p2p<double, 64>), grid, dim3(64), 0, sn, a);
+      fn = wide ? (multi ? k_p2p<double, 256, 8> : k_p2p<double, 256, 1>)
+                : (multi ? k_p2p<double, 64, 8> : k_p2p<double, 64, 1>);
+    hipLaunchKernelGGL(fn, grid, dim3(wide ? 256 : 64), 0, sn, a, nrhs);
     HIPCHK(h, hipGetLastError());
   }
   if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + 6], sn));

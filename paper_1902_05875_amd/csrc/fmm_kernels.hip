@@ -735,15 +735,16 @@ __device__ __forceinline__ void pair_kernel(float r2, float, float* er, float* e
   *er = __builtin_amdgcn_cosf(rv) * ri, *ei = __builtin_amdgcn_sinf(rv) * ri;
 }
 
-template <typename T, int BS>
-__global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
-  __shared__ T sx[BS], sy[BS], sz[BS], sqr[BS], sqi[BS];
+// RB charge vectors per block (blockIdx.y = group of RB): the pair kernel is
+// computed once and applied to all of them, in the same order as for one vector.
+template <typename T, int BS, int RB>
+__global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
+  __shared__ T sx[BS], sy[BS], sz[BS], sq[BS][2 * RB];
   __shared__ int sidx[BS];
-  const int leaf = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int leaf = blockIdx.x, r0 = blockIdx.y * RB, tid = threadIdx.x;
   const int nb = a.nbox_dim;
   const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
   const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
-  const double2* q = a.q + (int64_t)r * a.n;
   const T k = (T)a.k;
   // FP32: coordinates in units of 2 pi / k (see pair_kernel); FP64: physical
   const double kap = sizeof(T) == 4 ? a.k / 6.283185307179586477 : 1.0;
@@ -756,8 +757,10 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
     const double txd = act ? a.xs[i] : 0.0, tyd = act ? a.xs[a.n + i] : 0.0, tzd = act ? a.xs[2 * a.n + i] : 0.0;
     // coordinates relative to the root corner keep FP32 differences accurate
     const T tx = (T)((txd - a.lo[0]) * kap), ty = (T)((tyd - a.lo[1]) * kap), tz = (T)((tzd - a.lo[2]) * kap);
-    T accr = 0, acci = 0;
-    double nsr = 0.0, nsi = 0.0;  // near-singular pairs (FP32 path only)
+    T accr[RB], acci[RB];
+    double nsr[RB], nsi[RB];  // near-singular pairs (FP32 path only)
+#pragma unroll
+    for (int b = 0; b < RB; ++b) accr[b] = 0, acci[b] = 0, nsr[b] = 0.0, nsi[b] = 0.0;
     for (int col = 0; col < 9; ++col) {
       const int jx = ix + col / 3 - 1, jy = iy + col % 3 - 1;
       if (jx < 0 || jy < 0 || jx >= nb || jy >= nb) continue;
@@ -771,8 +774,12 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
           sx[tid] = (T)((a.xs[j] - a.lo[0]) * kap);
           sy[tid] = (T)((a.xs[a.n + j] - a.lo[1]) * kap);
           sz[tid] = (T)((a.xs[2 * a.n + j] - a.lo[2]) * kap);
-          sqr[tid] = (T)q[j].x;
-          sqi[tid] = (T)q[j].y;
+#pragma unroll
+          for (int b = 0; b < RB; ++b) {
+            const double2 qv = r0 + b < nrhs ? a.q[(int64_t)(r0 + b) * a.n + j] : make_double2(0.0, 0.0);
+            sq[tid][2 * b] = (T)qv.x;
+            sq[tid][2 * b + 1] = (T)qv.y;
+          }
           sidx[tid] = (int)j;
         }
         __syncthreads();
@@ -787,9 +794,12 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
               const bool self = !(r2 > 0);
               T er, ei;
               pair_kernel(self ? (T)1 : r2, k, &er, &ei);
-              const T wr = self ? (T)0 : sqr[t], wi = self ? (T)0 : sqi[t];
-              accr += wr * er - wi * ei;
-              acci += wr * ei + wi * er;
+#pragma unroll
+              for (int b = 0; b < RB; ++b) {
+                const T wr = self ? (T)0 : sq[t][2 * b], wi = self ? (T)0 : sq[t][2 * b + 1];
+                accr[b] += wr * er - wi * ei;
+                acci[b] += wr * ei + wi * er;
+              }
             }
             continue;
           }
@@ -803,26 +813,43 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a) {
               const double ex = txd - a.xs[j], ey = tyd - a.xs[a.n + j], ez = tzd - a.xs[2 * a.n + j];
               double er, ei;
               pair_kernel(ex * ex + ey * ey + ez * ez, a.k, &er, &ei);
-              nsr += q[j].x * er - q[j].y * ei;
-              nsi += q[j].x * ei + q[j].y * er;
+#pragma unroll
+              for (int b = 0; b < RB; ++b)
+                if (r0 + b < nrhs) {
+                  const double2 qv = a.q[(int64_t)(r0 + b) * a.n + j];
+                  nsr[b] += qv.x * er - qv.y * ei;
+                  nsi[b] += qv.x * ei + qv.y * er;
+                }
               continue;
             }
             T er, ei;
             pair_kernel(r2, k, &er, &ei);
-            accr += sqr[t] * er - sqi[t] * ei;
-            acci += sqr[t] * ei + sqi[t] * er;
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+              accr[b] += sq[t][2 * b] * er - sq[t][2 * b + 1] * ei;
+              acci[b] += sq[t][2 * b] * ei + sq[t][2 * b + 1] * er;
+            }
           }
         }
       }
     }
-    if (act) a.phi[(int64_t)r * a.n + i] = make_double2((double)accr * kap + nsr, (double)acci * kap + nsi);
+    if (act)
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+        if (r0 + b < nrhs)
+          a.phi[(int64_t)(r0 + b) * a.n + i] =
+              make_double2((double)accr[b] * kap + nsr[b], (double)acci[b] * kap + nsi[b]);
   }
 }
 
-template __global__ void k_p2p<double, 64>(PassArgs);
-template __global__ void k_p2p<float, 64>(PassArgs);
-template __global__ void k_p2p<double, 256>(PassArgs);
-template __global__ void k_p2p<float, 256>(PassArgs);
+template __global__ void k_p2p<double, 64, 1>(PassArgs, int);
+template __global__ void k_p2p<float, 64, 1>(PassArgs, int);
+template __global__ void k_p2p<double, 256, 1>(PassArgs, int);
+template __global__ void k_p2p<float, 256, 1>(PassArgs, int);
+template __global__ void k_p2p<double, 64, 8>(PassArgs, int);
+template __global__ void k_p2p<float, 64, 8>(PassArgs, int);
+template __global__ void k_p2p<double, 256, 8>(PassArgs, int);
+template __global__ void k_p2p<float, 256, 8>(PassArgs, int);
 
 // ---------------------------------------------------------------------------
 // Surrogate tables.  Entry g of a reaction table at (x, y, S) is scaled by the

@@ -166,8 +166,8 @@ __global__ void k_expand_z_add(ReduceArgs a);
 __global__ void k_m2m(PassArgs a);
 __global__ void k_l2l(PassArgs a);
 __global__ void k_l2p(PassArgs a);
-template <typename T, int BS>
-__global__ void k_p2p(PassArgs a);
+template <typename T, int BS, int RB>
+__global__ void k_p2p(PassArgs a, int nrhs);
 
 // M2L launcher (picks the row-block instantiation for nRB).
 hipError_t launch_m2l(const M2LArgs& a, int nrhs, bool fp32, hipStream_t s);
