@@ -105,6 +105,9 @@ struct tefmm_ctx {
   // the near field runs on a second stream beside the far field (fork/join by events)
   hipStream_t s2 = nullptr;
   hipEvent_t e_fork = nullptr, e_join = nullptr;
+  // with several layer groups their M2L launches run on streams of their own
+  hipStream_t sg[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t e_gfork = nullptr, e_gjoin[4] = {nullptr, nullptr, nullptr, nullptr};
   int nrhs_alloc = 0;
   bool ready = false;
   // stats
@@ -328,6 +331,11 @@ extern "C" void tefmm_destroy(tefmm_t h) {
   if (h->e_fork) (void)hipEventDestroy(h->e_fork);
   if (h->e_join) (void)hipEventDestroy(h->e_join);
   if (h->s2) (void)hipStreamDestroy(h->s2);
+  if (h->e_gfork) (void)hipEventDestroy(h->e_gfork);
+  for (int i = 0; i < 4; ++i) {
+    if (h->e_gjoin[i]) (void)hipEventDestroy(h->e_gjoin[i]);
+    if (h->sg[i]) (void)hipStreamDestroy(h->sg[i]);
+  }
   batch_destroy(h->batch);
   dfree(h->d_xyz_user);
   delete h;
@@ -1088,6 +1096,11 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     HIPCHK(h, hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
     HIPCHK(h, hipEventCreateWithFlags(&h->e_fork, hipEventDisableTiming));
     HIPCHK(h, hipEventCreateWithFlags(&h->e_join, hipEventDisableTiming));
+    HIPCHK(h, hipEventCreateWithFlags(&h->e_gfork, hipEventDisableTiming));
+    for (int i = 1; i < 4; ++i) {
+      HIPCHK(h, hipStreamCreateWithFlags(&h->sg[i], hipStreamNonBlocking));
+      HIPCHK(h, hipEventCreateWithFlags(&h->e_gjoin[i], hipEventDisableTiming));
+    }
   }
   // phase events of this evaluation: set ev_next of the ring
   const int evset = h->ev_next;
@@ -1196,8 +1209,18 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     }
   }
   EVREC(2);
-  // M2L: same-layer families, then cross-layer components (Algorithm 2)
-  for (auto& g : h->groups) {
+  // M2L: same-layer families, then cross-layer components (Algorithm 2).  The groups'
+  // launches are independent (each writes only its own locals): with several groups
+  // and no graph capture, group gi > 0 runs on stream sg[gi], joined before the locals.
+  const int ngr = (int)h->groups.size();
+  const bool gfork = fork && ngr > 1;
+  if (gfork) {
+    HIPCHK(h, hipEventRecord(h->e_gfork, s));
+    for (int gi = 1; gi < ngr; ++gi) HIPCHK(h, hipStreamWaitEvent(h->sg[gi], h->e_gfork, 0));
+  }
+  for (int gi = 0; gi < ngr; ++gi) {
+    Group& g = h->groups[gi];
+    const hipStream_t sm = (gfork && gi > 0) ? h->sg[gi] : s;
     const int H = g.depth;
     M2LArgs m;
     std::memset(&m, 0, sizeof(m));
@@ -1214,7 +1237,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     }
     m.ncb = h->m2l_ncb ? h->m2l_ncb : h->opt.m2l_tile;
     m.nsplit = m2l_split(H);
-    HIPCHK(h, launch_m2l(m, nrhs, fp32, s));
+    HIPCHK(h, launch_m2l(m, nrhs, fp32, sm));
     const double per = 8.0 * (double)h->nR * (double)h->nR;
     for (int lev = 2; lev <= H; ++lev) {
       const int64_t far = g.far_pairs[lev - 2], nr = g.near_pairs[lev - 2];
@@ -1243,11 +1266,14 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
           L.src_stride[sg] = h->groups[sg].nbox[lev] * h->nR;
         }
       }
-      HIPCHK(h, launch_m2l_cross(c, nrhs, fp32, s));
+      HIPCHK(h, launch_m2l_cross(c, nrhs, fp32, sm));
       m2l_flops += g.cross_flops_per_rhs * nrhs;
       ++m2l_launches;
     }
+    if (gfork && gi > 0) HIPCHK(h, hipEventRecord(h->e_gjoin[gi], sm));
   }
+  if (gfork)
+    for (int gi = 1; gi < ngr; ++gi) HIPCHK(h, hipStreamWaitEvent(s, h->e_gjoin[gi], 0));
   EVREC(3);
   // locals: expansion of the reduced sets, cross-layer part added, then L2L
   for (auto& g : h->groups) {
