@@ -716,8 +716,31 @@ __device__ __forceinline__ void sincos_f64(double x, double* s, double* c) {
 // 1/sqrt(r2) in FP64: FP32 estimate (relative error ~1e-7) refined by one
 // Newton step (error squared: ~2e-14, far below the FP64 mode's 1e-6 target).
 __device__ __forceinline__ double rsqrt_f64(double r2) {
-  const double y = (double)rsqrtf((float)r2);
+  // the hardware estimate directly (pair distances are far above the FP32 denormal range)
+  const double y = (double)__builtin_amdgcn_rsqf((float)r2);
   return y * fma(-0.5 * r2, y * y, 1.5);
+}
+
+// The same sine and cosine for 0 <= x <= pi/4 (no reduction needed).
+__device__ __forceinline__ void sincos_f64_small(double y, double* s, double* c) {
+  const double y2 = y * y;
+  double ps = -7.6471637318198164759e-13;
+  ps = fma(ps, y2, 1.6059043836821614599e-10);
+  ps = fma(ps, y2, -2.5052108385441718775e-08);
+  ps = fma(ps, y2, 2.7557319223985890653e-06);
+  ps = fma(ps, y2, -1.9841269841269841270e-04);
+  ps = fma(ps, y2, 8.3333333333333333333e-03);
+  ps = fma(ps, y2, -1.6666666666666666667e-01);
+  *s = fma(y * y2, ps, y);
+  double pc = 4.7794773323873852974e-14;
+  pc = fma(pc, y2, -1.1470745597729724714e-11);
+  pc = fma(pc, y2, 2.0876756987868098979e-09);
+  pc = fma(pc, y2, -2.7557319223985890653e-07);
+  pc = fma(pc, y2, 2.4801587301587301587e-05);
+  pc = fma(pc, y2, -1.3888888888888888889e-03);
+  pc = fma(pc, y2, 4.1666666666666666667e-02);
+  pc = fma(pc, y2, -0.5);
+  *c = fma(y2, pc, 1.0);
 }
 
 __device__ __forceinline__ void pair_kernel(double r2, double k, double* er, double* ei) {
@@ -730,9 +753,34 @@ __device__ __forceinline__ void pair_kernel(double r2, double k, double* er, dou
 // hardware sine and cosine take revolutions, and the common factor k / (2 pi)
 // of 1/r is applied once to the sum.
 __device__ __forceinline__ void pair_kernel(float r2, float, float* er, float* ei) {
-  const float ri = rsqrtf(r2);
+  const float ri = __builtin_amdgcn_rsqf(r2);
   const float rv = r2 * ri;
   *er = __builtin_amdgcn_cosf(rv) * ri, *ei = __builtin_amdgcn_sinf(rv) * ri;
+}
+
+// FP64 pair loop over m staged sources (see k_p2p).
+template <int RB, bool SMALL, bool SELF, typename T>
+__device__ __forceinline__ void p2p_f64_rows(int m, T tx, T ty, T tz, const T* sx, const T* sy, const T* sz,
+                                             const T (*sq)[2 * RB], double k, T* accr, T* acci) {
+#pragma unroll 4
+  for (int t = 0; t < m; ++t) {
+    const double dx = tx - sx[t], dy = ty - sy[t], dz = tz - sz[t];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const bool self = SELF && !(r2 > 0);
+    const double ri = rsqrt_f64(self ? 1.0 : r2);
+    double sn, cs;
+    if (SMALL)
+      sincos_f64_small(k * (r2 * ri), &sn, &cs);
+    else
+      sincos_f64(k * (r2 * ri), &sn, &cs);
+    const double er = cs * ri, ei = sn * ri;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const double wr = self ? 0.0 : (double)sq[t][2 * b], wi = self ? 0.0 : (double)sq[t][2 * b + 1];
+      accr[b] += wr * er - wi * ei;
+      acci[b] += wr * ei + wi * er;
+    }
+  }
 }
 
 // RB charge vectors per block (blockIdx.y = group of RB): the pair kernel is
@@ -751,6 +799,8 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
   // pairs closer than 5% of the leaf side are evaluated in FP64 in the FP32 path
   const T rns2 = (T)(0.0025 * a.h * a.h * kap * kap);
   const int z0 = max(iz - 1, 0), z1 = min(iz + 1, nb - 1);
+  // largest k r in the 3 x 3 x 3 leaf block: the corners of a 2 x 2 x 2 span, sqrt(3) 2 h
+  const bool small = a.k * 3.4641016151377546 * a.h <= 0.78539816339744831;
   for (int c0 = 0; c0 < cnt; c0 += BS) {
     const bool act = c0 + tid < cnt;
     const int64_t i = start + c0 + tid;
@@ -785,21 +835,20 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
         __syncthreads();
         if (act) {
           if (sizeof(T) == 8) {
-            // branch free: the target itself has r2 = 0 (same coordinates, same
-            // arithmetic) and is given weight 0
-#pragma unroll 4
-            for (int t = 0; t < m; ++t) {
-              const T dx = tx - sx[t], dy = ty - sy[t], dz = tz - sz[t];
-              const T r2 = dx * dx + dy * dy + dz * dz;
-              const bool self = !(r2 > 0);
-              T er, ei;
-              pair_kernel(self ? (T)1 : r2, k, &er, &ei);
-#pragma unroll
-              for (int b = 0; b < RB; ++b) {
-                const T wr = self ? (T)0 : sq[t][2 * b], wi = self ? (T)0 : sq[t][2 * b + 1];
-                accr[b] += wr * er - wi * ei;
-                acci[b] += wr * ei + wi * er;
-              }
+            // Only the centre column holds the target itself; there the pair with
+            // r2 = 0 (same coordinates, same arithmetic) gets weight 0, branch free.
+            // When k r stays below pi/4 for every pair of the leaf's neighbourhood the
+            // sine and cosine need no argument reduction.
+            if (col == 4) {
+              if (small)
+                p2p_f64_rows<RB, true, true>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
+              else
+                p2p_f64_rows<RB, false, true>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
+            } else {
+              if (small)
+                p2p_f64_rows<RB, true, false>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
+              else
+                p2p_f64_rows<RB, false, false>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
             }
             continue;
           }
