@@ -100,6 +100,7 @@ struct M2LArgs {
   int ncb;               // targets per workgroup / 16: 1 or 2, 0 = automatic
   int nsplit;            // the offsets of a tile are split over nsplit workgroups (blockIdx.z),
                          // each writing its own partial locals (summed in fixed order by k_expand)
+  int kph, kpb, nRsP;    // source moments staged in kph phases of kpb blocks of 4 (LDS row stride nRsP)
   int tile_start[M2L_MAX_LEVELS + 1];
   M2LLevel lev[M2L_MAX_LEVELS];
   const int* rmi;        // [nR] packed reduced multi-indices

@@ -20,6 +20,8 @@
 // gathered from the compact table in LDS.  Four waves split the row blocks.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "fmm_kernels.hpp"
 #include "kernels.hpp"
 
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   const int padG = 3 * P2 * P2;
   T2* sG = (T2*)lds_m2l;
   T2* sA = sG + padG;
-  int* sCol = (int*)(sA + NT * a.nRs);     // [4 nKB]: column offset | k3' parity << 20 | valid << 21
+  int* sCol = (int*)(sA + NT * a.nRsP);    // [4 nKB]: column offset | k3' parity << 20 | valid << 21
 
   // Block -> (level, tile).  The coarse levels come first and keep the hardware's
   // round-robin over the XCDs; tiles of the last (widest) level are remapped so
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   }
 
   const double2* alpha = L.a + (int64_t)r * L.rhs_stride;
-  for (int e = tid; e < NT * a.nRs; e += 256) {
+  for (int e = tid; e < NT * a.nRsP; e += 256) {
     sA[e].x = 0;
     sA[e].y = 0;
   }
@@ -165,8 +167,10 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   // staging constants: thread's first element, the per-step advance, and the
   // moment address of target n at offset (0, 0, 0):
   //   ((ix N + iy) N + iz) nR with ix = px + 2 (4 X0 + (n & 3)), iy = py + 2 (4 NCB Y0 + (n >> 2))
-  const int n0 = tid / a.nR, kk0 = tid - n0 * a.nR;
-  const int step_q = 256 / a.nR, step_r = 256 - step_q * a.nR;
+  // the moments of a phase: k' in [4 kpb ph, 4 kpb (ph + 1)), element e = (n, k' - base)
+  const int Lp = 4 * a.kpb;
+  const int n0 = tid / Lp, kk0 = tid - n0 * Lp;
+  const int step_q = 256 / Lp, step_r = 256 - step_q * Lp;
   int tbase[4];
 #pragma unroll
   for (int xi = 0; xi < 4; ++xi)
@@ -191,58 +195,65 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
           if ((ocount++) % a.nsplit != split) continue;
           const int key = pass ? ((dx + 3) * 7 + (dy + 3)) * (2 * N - 1) + (2 * iz + dz)
                                : ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
-          __syncthreads();
-          const T2* g = table + (int64_t)key * a.nG;
-          for (int e = tid; e < a.nG; e += 256) sG[a.gpad[e]] = g[e];
-          // element e = tid + 256 i of the NT x nR moment block: target n, index kk
-          // (advanced by 256 = q nR + rem per step, without a division per element)
-          {
-            int n = n0, kk = kk0;
-            const int delta = ((dx * N + dy) * N + dz) * a.nR;
-            for (int e = tid; e < NT * a.nR; e += 256) {
-              T2 v;
-              v.x = 0;
-              v.y = 0;
-              if ((smask >> n) & 1) {
-                const double s = (mirror && ((sCol[kk] >> 20) & 1)) ? -1.0 : 1.0;
-                const double2 av = alpha[tbase[n & 3] + tbase_y * (n >> 2) + kk + delta];
-                v = Ty::cvt(make_double2(av.x * s, av.y * s));
-              }
-              sA[n * a.nRs + kk] = v;
-              n += step_q, kk += step_r;
-              if (kk >= a.nR) kk -= a.nR, ++n;
+          const int delta = ((dx * N + dy) * N + dz) * a.nR;
+          for (int ph = 0; ph < a.kph; ++ph) {
+            const int kbase = Lp * ph;
+            __syncthreads();
+            if (ph == 0) {
+              const T2* g = table + (int64_t)key * a.nG;
+              for (int e = tid; e < a.nG; e += 256) sG[a.gpad[e]] = g[e];
             }
-          }
-          __syncthreads();
-          for (int kb = 0; kb < a.nKB; ++kb) {
-            const int kp = 4 * kb + krow;
-            const int ci = sCol[kp];
-            const bool cvalid = (ci >> 21) & 1;
-            const int co = ci & 0xFFFFF;
-            const T2 bv0 = sA[col * a.nRs + kp];
-            const T2 bv1 = NCB == 2 ? sA[(16 + col) * a.nRs + kp] : bv0;
-            T2 gv[TW];
-#pragma unroll
-            for (int j = 0; j < TW; ++j) {
-              gv[j].x = 0;
-              gv[j].y = 0;
-              if (rowo[j] >= 0 && cvalid) gv[j] = sG[rowo[j] + co];
+            // element e = tid + 256 i of the NT x Lp moment block: target n, index kk
+            // (advanced by 256 = q Lp + rem per step, without a division per element)
+            {
+              int n = n0, kl = kk0;
+              for (int e = tid; e < NT * Lp; e += 256) {
+                const int kk = kbase + kl;
+                T2 v;
+                v.x = 0;
+                v.y = 0;
+                if (kk < a.nR && ((smask >> n) & 1)) {
+                  const double s = (mirror && ((sCol[kk] >> 20) & 1)) ? -1.0 : 1.0;
+                  const double2 av = alpha[tbase[n & 3] + tbase_y * (n >> 2) + kk + delta];
+                  v = Ty::cvt(make_double2(av.x * s, av.y * s));
+                }
+                sA[n * a.nRsP + kl] = v;
+                n += step_q, kl += step_r;
+                if (kl >= Lp) kl -= Lp, ++n;
+              }
             }
-            // independent MFMAs between the two updates of each accumulator
+            __syncthreads();
+            const int kb1 = min(a.nKB, a.kpb * (ph + 1));
+            for (int kb = a.kpb * ph; kb < kb1; ++kb) {
+              const int kp = 4 * kb + krow;
+              const int ci = sCol[kp];
+              const bool cvalid = (ci >> 21) & 1;
+              const int co = ci & 0xFFFFF;
+              const T2 bv0 = sA[col * a.nRsP + kp - kbase];
+              const T2 bv1 = NCB == 2 ? sA[(16 + col) * a.nRsP + kp - kbase] : bv0;
+              T2 gv[TW];
 #pragma unroll
-            for (int j = 0; j < TW; ++j)
-              if (w + 4 * j < ntile) {
-                const T2 b = tcb[j] ? bv1 : bv0;
-                accR[j] = Ty::mfma(gv[j].x, b.x, accR[j]);
-                accI[j] = Ty::mfma(gv[j].x, b.y, accI[j]);
+              for (int j = 0; j < TW; ++j) {
+                gv[j].x = 0;
+                gv[j].y = 0;
+                if (rowo[j] >= 0 && cvalid) gv[j] = sG[rowo[j] + co];
               }
+              // independent MFMAs between the two updates of each accumulator
 #pragma unroll
-            for (int j = 0; j < TW; ++j)
-              if (w + 4 * j < ntile) {
-                const T2 b = tcb[j] ? bv1 : bv0;
-                accR[j] = Ty::mfma(-gv[j].y, b.y, accR[j]);
-                accI[j] = Ty::mfma(gv[j].y, b.x, accI[j]);
-              }
+              for (int j = 0; j < TW; ++j)
+                if (w + 4 * j < ntile) {
+                  const T2 b = tcb[j] ? bv1 : bv0;
+                  accR[j] = Ty::mfma(gv[j].x, b.x, accR[j]);
+                  accI[j] = Ty::mfma(gv[j].x, b.y, accI[j]);
+                }
+#pragma unroll
+              for (int j = 0; j < TW; ++j)
+                if (w + 4 * j < ntile) {
+                  const T2 b = tcb[j] ? bv1 : bv0;
+                  accR[j] = Ty::mfma(-gv[j].y, b.y, accR[j]);
+                  accI[j] = Ty::mfma(gv[j].y, b.x, accI[j]);
+                }
+            }
           }
         }
       }
@@ -281,8 +292,18 @@ static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
     total += (i == a.nlev - 1) ? 8 * ((L.ntiles + 7) / 8) : L.ntiles;
   }
   a.tile_start[a.nlev] = total;
-  const size_t lds = (size_t)3 * a.P2 * a.P2 * sizeof(T2) + (size_t)16 * NCB * a.nRs * sizeof(T2) +
-                     4 * (size_t)a.nKB * sizeof(int);
+  // stage the source moments in two phases when that lets two workgroups share a CU
+  auto lds_of = [&](int kph) {
+    const int kpb = (a.nKB + kph - 1) / kph;
+    int rs = 4 * kpb;
+    while (rs % 16 != 1) ++rs;
+    return std::make_pair((size_t)3 * a.P2 * a.P2 * sizeof(T2) + (size_t)16 * NCB * rs * sizeof(T2) +
+                              4 * (size_t)a.nKB * sizeof(int), rs);
+  };
+  a.kph = (lds_of(1).first > 80 * 1024 && lds_of(2).first <= 80 * 1024) ? 2 : 1;
+  a.kpb = (a.nKB + a.kph - 1) / a.kph;
+  const size_t lds = lds_of(a.kph).first;
+  a.nRsP = lds_of(a.kph).second;
   const int TW = (a.nRB * NCB + 3) / 4;
   if (a.nsplit < 1) a.nsplit = 1;
   dim3 grid(total, nrhs, a.nsplit), block(256);
