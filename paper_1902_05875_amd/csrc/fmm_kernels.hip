@@ -783,21 +783,95 @@ __device__ __forceinline__ void p2p_f64_rows(int m, T tx, T ty, T tz, const T* s
   }
 }
 
+// FP32 pair loop over m staged sources (see k_p2p). Every pair is evaluated in
+// FP32 with its squared distance raised to at least rns2, so the pair with
+// itself and near-singular pairs (closer than 5% of the leaf side, where the
+// FP32 difference has lost digits) give a finite, known term. Sources are taken
+// four at a time and one wave-wide test per four decides whether any lane met
+// such a pair; only then (rare) the known FP32 term is taken back in FP64 and
+// the pair redone in FP64 from the stored coordinates (the pair with itself: 0).
+template <int RB>
+__device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz, const float4* s4,
+                                             const float (*sq)[2 * RB], const int* sidx, float rns2, float ecr,
+                                             float eci, double kap, const PassArgs& a, int64_t i, double txd,
+                                             double tyd, double tzd, int r0, int nrhs, float* accr, float* acci,
+                                             double* nsr, double* nsi) {
+  auto fixup = [&](int t, float r2) {
+    if (!(r2 < rns2)) return;
+    const int64_t j = sidx[t];
+    double er = 0.0, ei = 0.0;
+    if (j != i) {
+      const double ex = txd - a.xs[j], ey = tyd - a.xs[a.n + j], ez = tzd - a.xs[2 * a.n + j];
+      pair_kernel(ex * ex + ey * ey + ez * ez, a.k, &er, &ei);
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+      if (r0 + b < nrhs) {
+        const double2 qv = a.q[(int64_t)(r0 + b) * a.n + j];
+        const double qr = sq[t][2 * b], qi = sq[t][2 * b + 1];
+        nsr[b] += qv.x * er - qv.y * ei - kap * (qr * ecr - qi * eci);
+        nsi[b] += qv.x * ei + qv.y * er - kap * (qr * eci + qi * ecr);
+      }
+  };
+  auto pair = [&](int t, float r2) {
+    // max of two non-negative floats as the max of their bit patterns (no canonicalising)
+    float er, ei;
+    pair_kernel(__int_as_float(max(__float_as_int(r2), __float_as_int(rns2))), 0.0f, &er, &ei);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const float qr = sq[t][2 * b], qi = sq[t][2 * b + 1];
+      accr[b] = fmaf(qr, er, fmaf(-qi, ei, accr[b]));
+      acci[b] = fmaf(qr, ei, fmaf(qi, er, acci[b]));
+    }
+  };
+  m = __builtin_amdgcn_readfirstlane(m);
+  int t = 0;
+  for (; t + 4 <= m; t += 4) {
+    float r2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float4 s = s4[t + u];
+      const float dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
+      r2[u] = dx * dx + dy * dy + dz * dz;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pair(t + u, r2[u]);
+    const float mn = fminf(fminf(r2[0], r2[1]), fminf(r2[2], r2[3]));
+    if (__any(mn < rns2)) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) fixup(t + u, r2[u]);
+    }
+  }
+  for (; t < m; ++t) {
+    const float4 s = s4[t];
+    const float dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    pair(t, r2);
+    fixup(t, r2);
+  }
+}
+
 // RB charge vectors per block (blockIdx.y = group of RB): the pair kernel is
 // computed once and applied to all of them, in the same order as for one vector.
 template <typename T, int BS, int RB>
 __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
-  __shared__ T sx[BS], sy[BS], sz[BS], sq[BS][2 * RB];
+  constexpr bool F32 = sizeof(T) == 4;
+  // FP64 sources as three coordinate arrays; FP32 sources as (x, y, z, unused)
+  __shared__ T sx[F32 ? 1 : BS], sy[F32 ? 1 : BS], sz[F32 ? 1 : BS];
+  __shared__ float4 s4[F32 ? BS : 1];
+  __shared__ T sq[BS][2 * RB];
   __shared__ int sidx[BS];
   const int leaf = blockIdx.x, r0 = blockIdx.y * RB, tid = threadIdx.x;
   const int nb = a.nbox_dim;
   const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
   const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
-  const T k = (T)a.k;
   // FP32: coordinates in units of 2 pi / k (see pair_kernel); FP64: physical
-  const double kap = sizeof(T) == 4 ? a.k / 6.283185307179586477 : 1.0;
+  const double kap = F32 ? a.k / 6.283185307179586477 : 1.0;
   // pairs closer than 5% of the leaf side are evaluated in FP64 in the FP32 path
-  const T rns2 = (T)(0.0025 * a.h * a.h * kap * kap);
+  const float rns2 = (float)(0.0025 * a.h * a.h * kap * kap);
+  // the FP32 pair term at squared distance rns2, as every lane computes it
+  float ecr = 0.0f, eci = 0.0f;
+  if (F32) pair_kernel(rns2, 0.0f, &ecr, &eci);
   const int z0 = max(iz - 1, 0), z1 = min(iz + 1, nb - 1);
   // largest k r in the 3 x 3 x 3 leaf block: the corners of a 2 x 2 x 2 span, sqrt(3) 2 h
   const bool small = a.k * 3.4641016151377546 * a.h <= 0.78539816339744831;
@@ -821,9 +895,12 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
         __syncthreads();
         if (tid < m) {
           const int64_t j = s0 + tid;
-          sx[tid] = (T)((a.xs[j] - a.lo[0]) * kap);
-          sy[tid] = (T)((a.xs[a.n + j] - a.lo[1]) * kap);
-          sz[tid] = (T)((a.xs[2 * a.n + j] - a.lo[2]) * kap);
+          const T x = (T)((a.xs[j] - a.lo[0]) * kap), y = (T)((a.xs[a.n + j] - a.lo[1]) * kap),
+                  z = (T)((a.xs[2 * a.n + j] - a.lo[2]) * kap);
+          if constexpr (F32)
+            s4[tid] = make_float4(x, y, z, 0.0f);
+          else
+            sx[tid] = x, sy[tid] = y, sz[tid] = z;
 #pragma unroll
           for (int b = 0; b < RB; ++b) {
             const double2 qv = r0 + b < nrhs ? a.q[(int64_t)(r0 + b) * a.n + j] : make_double2(0.0, 0.0);
@@ -833,51 +910,25 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
           sidx[tid] = (int)j;
         }
         __syncthreads();
-        if (act) {
-          if (sizeof(T) == 8) {
-            // Only the centre column holds the target itself; there the pair with
-            // r2 = 0 (same coordinates, same arithmetic) gets weight 0, branch free.
-            // When k r stays below pi/4 for every pair of the leaf's neighbourhood the
-            // sine and cosine need no argument reduction.
-            if (col == 4) {
-              if (small)
-                p2p_f64_rows<RB, true, true>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
-              else
-                p2p_f64_rows<RB, false, true>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
-            } else {
-              if (small)
-                p2p_f64_rows<RB, true, false>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
-              else
-                p2p_f64_rows<RB, false, false>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
-            }
-            continue;
-          }
-          for (int t = 0; t < m; ++t) {
-            const T dx = tx - sx[t], dy = ty - sy[t], dz = tz - sz[t];
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            if (sizeof(T) == 4 && r2 < rns2) {
-              // near-singular pair: the FP32 difference has lost digits, redo it in FP64
-              const int64_t j = sidx[t];
-              if (j == i) continue;
-              const double ex = txd - a.xs[j], ey = tyd - a.xs[a.n + j], ez = tzd - a.xs[2 * a.n + j];
-              double er, ei;
-              pair_kernel(ex * ex + ey * ey + ez * ez, a.k, &er, &ei);
-#pragma unroll
-              for (int b = 0; b < RB; ++b)
-                if (r0 + b < nrhs) {
-                  const double2 qv = a.q[(int64_t)(r0 + b) * a.n + j];
-                  nsr[b] += qv.x * er - qv.y * ei;
-                  nsi[b] += qv.x * ei + qv.y * er;
-                }
-              continue;
-            }
-            T er, ei;
-            pair_kernel(r2, k, &er, &ei);
-#pragma unroll
-            for (int b = 0; b < RB; ++b) {
-              accr[b] += sq[t][2 * b] * er - sq[t][2 * b + 1] * ei;
-              acci[b] += sq[t][2 * b] * ei + sq[t][2 * b + 1] * er;
-            }
+        if (!act) continue;
+        if constexpr (F32) {
+          p2p_f32_rows<RB>(m, tx, ty, tz, s4, sq, sidx, rns2, ecr, eci, kap, a, i, txd, tyd, tzd, r0, nrhs, accr,
+                           acci, nsr, nsi);
+        } else {
+          // Only the centre column holds the target itself; there the pair with
+          // r2 = 0 (same coordinates, same arithmetic) gets weight 0, branch free.
+          // When k r stays below pi/4 for every pair of the leaf's neighbourhood the
+          // sine and cosine need no argument reduction.
+          if (col == 4) {
+            if (small)
+              p2p_f64_rows<RB, true, true>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
+            else
+              p2p_f64_rows<RB, false, true>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
+          } else {
+            if (small)
+              p2p_f64_rows<RB, true, false>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
+            else
+              p2p_f64_rows<RB, false, false>(m, tx, ty, tz, sx, sy, sz, sq, a.k, accr, acci);
           }
         }
       }
