@@ -35,6 +35,10 @@ PEAK = {"fp64": 78.6, "fp32": 157.3}  # TFLOP/s, MI355X published: dense MFMA, a
 # algorithmic flops of one P2P pair: distance (3 sub, 3 mul, 2 add), 1/r and r (2),
 # k r (1), sin and cos (2), exp(ikr)/r (2), complex multiply-add into the sum (8)
 P2P_FLOPS_PER_PAIR = 23
+# FP32 with one charge vector: the pairs of particles in different leaves are evaluated
+# once and applied both ways: distance 8, 1/r and r 2, k r 1, sin and cos 2, e^{ikr}/r 2,
+# two complex multiply-adds 16
+P2P_FLOPS_PER_SYM_PAIR = 31
 SHAPES = {"c1": "uniform unit cube centred (0,0,-0.6)", "c2": "uniform unit cube centred (0,0,-0.6)",
           "c4": "uniform unit cube centred (0,0,-0.6)", "c5": "uniform unit cube centred (0,0,-0.6)",
           "c3": "split over three unit cubes centred (0,0,0.6), (0,0,-0.6), (0,0,-1.8), one per layer"}
@@ -107,8 +111,9 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload, surrogate=
         "evals_per_s": q.shape[0] * q.shape[1] / (ms / 1e3) if q.ndim == 2 else xyz.shape[0] / (ms / 1e3),
         "phases_ms": {k[2:-3]: round(v, 4) for k, v in phases.items()},
         "m2l_flops": st["m2l_flops"], "m2l_launches": st["m2l_launches"], "depth": st["depth"][0],
-        "p2p_flops": P2P_FLOPS_PER_PAIR * st["p2p_pairs"] * q.shape[0], "n_groups": sum(1 for d in st["depth"] if d),
-        "images": st["n_images"], "p2p_pairs": st["p2p_pairs"],
+        "p2p_flops": _p2p_flops(st, precision, q), "p2p_sym": _p2p_sym(precision, q),
+        "n_groups": sum(1 for d in st["depth"] if d),
+        "images": st["n_images"], "p2p_pairs": st["p2p_pairs"], "p2p_pairs_same_leaf": st["p2p_pairs_same_leaf"],
         "rel_err_sampled": err, "n_checked": nchk, "t_setup_tables_ms": st["t_setup_tables_ms"],
         "sigma_keys": st["sigma_keys"], "surrogate_keys": st["surrogate_keys"], "surrogate": sur_info,
         "cross_pairs": st["cross_pairs"], "autotune": tuned, "workload": workload,
@@ -117,6 +122,19 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload, surrogate=
     del xt, qt, out
     torch.cuda.empty_cache()
     return res
+
+
+def _p2p_sym(precision, q):
+    """Whether the near field ran the kernel that evaluates each cross-leaf pair once."""
+    return precision == "fp32" and (q.ndim == 1 or q.shape[0] == 1)
+
+
+def _p2p_flops(st, precision, q):
+    """Algorithmic near-field flops of one evaluation (per charge vector: pairs times flops)."""
+    pairs, same = st["p2p_pairs"], st["p2p_pairs_same_leaf"]
+    if _p2p_sym(precision, q):
+        return P2P_FLOPS_PER_SYM_PAIR * (pairs - same) // 2 + P2P_FLOPS_PER_PAIR * same
+    return P2P_FLOPS_PER_PAIR * pairs * (1 if q.ndim == 1 else q.shape[0])
 
 
 def _traffic(kernel, prec, src, workload):
@@ -143,17 +161,22 @@ def roofline(head):
     prec = "fp32" if head["precision"] == "fp32" else "fp64"
     ph = head["phases_ms"]
     n_launch = max(1, head["n_groups"])
+    if head.get("p2p_sym"):
+        same = head["p2p_pairs_same_leaf"]
+        what = (f"k_p2p_sym<float> + k_p2p_sym_gather (vector ALU), {n_launch} launch(es)/step, avg "
+                f"{ph['p2p'] / n_launch:.3f} ms; {P2P_FLOPS_PER_SYM_PAIR} flop x {(head['p2p_pairs'] - same) // 2} "
+                f"cross-leaf pairs (each once) + {P2P_FLOPS_PER_PAIR} flop x {same} same-leaf ordered pairs")
+    else:
+        what = (f"k_p2p<{'float' if prec == 'fp32' else 'double'}> (vector ALU), {n_launch} launch(es)/step, "
+                f"avg {ph['p2p'] / n_launch:.3f} ms; {P2P_FLOPS_PER_PAIR} flop per pair x {head['p2p_pairs']} pairs")
     p2p = {"bound": "alu", "achieved": head["p2p_flops"] / (ph["p2p"] / 1e3) / 1e12 if ph["p2p"] > 0 else 0.0,
-           "peak": PEAK[prec], "unit": "TFLOP/s",
-           "kernel": f"k_p2p<{'float' if prec == 'fp32' else 'double'}> (vector ALU), {n_launch} launch(es)/step, "
-                     f"avg {ph['p2p'] / n_launch:.3f} ms; {P2P_FLOPS_PER_PAIR} flop per pair x "
-                     f"{head['p2p_pairs']} pairs"}
+           "peak": PEAK[prec], "unit": "TFLOP/s", "kernel": what}
     m2l = {"bound": "mfma", "achieved": head["m2l_flops"] / (ph["m2l"] / 1e3) / 1e12 if ph["m2l"] > 0 else 0.0,
            "peak": PEAK[prec], "unit": "TFLOP/s",
            "kernel": f"k_m2l ({prec.upper()} MFMA 16x16x4), {head['m2l_launches']} launch(es)/step, "
                      f"avg {ph['m2l'] / max(1, head['m2l_launches']):.3f} ms; 8 (p+1)^4 flop per box pair"}
     wl = head["workload"]
-    tp = _traffic("k_p2p", prec, "fmm_kernels.hip", wl)
+    tp = _traffic("k_p2p_sym" if head.get("p2p_sym") else "k_p2p", prec, "fmm_kernels.hip", wl)
     tm = _traffic("k_m2l", prec, "fmm_m2l.hip", wl)
     p2p["traffic"] = tp
     m2l["traffic"] = tm

@@ -89,6 +89,11 @@ typedef struct {
   int n_rhs_max;
   double dcim_T1_cross;
   int m2l_tile;       /* M2L targets per workgroup / 16: 1 or 2 (0 = automatic; tefmm_autotune measures) */
+  int p2p_targets;    /* near field, TEFMM_MIXED_FP32 with one charge vector: each pair of particles
+                         in different leaves is evaluated once and its kernel value applied in both
+                         directions, with 1, 2 or 4 targets per GPU lane (0 = 2 above a mean
+                         leaf occupancy of 96, else 1); -1 = every ordered pair evaluated on its
+                         own (the FP64 and several-vector kernel) */
 } tefmm_options;
 
 /* Timings (ms, measured with HIP events; averages over the evaluations since
@@ -118,6 +123,7 @@ typedef struct {
   int64_t sigma_keys;    /* rows of the Sigma-family tables of the geometry */
   int64_t surrogate_keys; /* of those, rows produced by the attached surrogate network */
   int timed_evaluations; /* evaluations the phase times t_p2m_ms .. t_total_ms average over */
+  int64_t p2p_pairs_same_leaf; /* of p2p_pairs, the ordered pairs inside one leaf */
 } tefmm_stats;
 
 /* Fill an options struct with the defaults (p = 8, depth auto, max_leaf 64,

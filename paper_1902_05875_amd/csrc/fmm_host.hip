@@ -102,6 +102,8 @@ struct tefmm_ctx {
   std::vector<Group> groups;
   // evaluate buffers
   double2 *d_q = nullptr, *d_phi = nullptr, *d_phi_near = nullptr;
+  // source-side sums of the symmetric FP32 near field: [13 slots][n]
+  float2* d_part = nullptr;
   // the near field runs on a second stream beside the far field (fork/join by events)
   hipStream_t s2 = nullptr;
   hipEvent_t e_fork = nullptr, e_join = nullptr;
@@ -114,7 +116,7 @@ struct tefmm_ctx {
   tefmm_stats st;
   std::vector<hipEvent_t> ev;  // EV_RING sets of 8 phase events
   int ev_next = 0, ev_count = 0;
-  int64_t p2p_pairs = 0, m2l_pairs = 0;
+  int64_t p2p_pairs = 0, m2l_pairs = 0, p2p_same = 0;
   int64_t sigma_keys = 0, sur_keys = 0;  // Sigma table rows of the geometry / answered by the surrogate
   // copy of the caller's positions (SoA), kept for re-building the tree (autotuner)
   double* d_xyz_user = nullptr;
@@ -179,6 +181,7 @@ static void free_geometry(tefmm_t h) {
   dfree(h->d_q);
   dfree(h->d_phi);
   dfree(h->d_phi_near);
+  dfree(h->d_part);
   h->nrhs_alloc = 0;
   h->ready = false;
 }
@@ -297,7 +300,10 @@ extern "C" int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefm
   if (o.p < 1 || o.p > 16 || o.depth < 0 || o.depth > 7 || o.max_leaf < 1 ||
       (o.precision != TEFMM_FP64 && o.precision != TEFMM_MIXED_FP32) ||
       (o.normalization != TEFMM_NORM_PHYSICAL && o.normalization != TEFMM_NORM_PAPER) || o.dcim_samples < 8 ||
-      !(o.dcim_T1 > 0) || !(o.dcim_T1_cross > 0) || !(o.dcim_svd_tol > 0) || o.m2l_tile < 0 || o.m2l_tile > 2 || !(o.interface_eps >= 0) || o.n_rhs_max < 1) {
+      !(o.dcim_T1 > 0) || !(o.dcim_T1_cross > 0) || !(o.dcim_svd_tol > 0) || o.m2l_tile < 0 || o.m2l_tile > 2 ||
+      !(o.interface_eps >= 0) || o.n_rhs_max < 1 ||
+      !(o.p2p_targets == -1 || o.p2p_targets == 0 || o.p2p_targets == 1 || o.p2p_targets == 2 ||
+        o.p2p_targets == 4)) {
     delete h;
     return TEFMM_ERR_INVALID_ARG;
   }
@@ -923,6 +929,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   HIPCHK(h, hipEventRecord(e1, s));
   // interaction counts (statistics)
   h->p2p_pairs = 0;
+  h->p2p_same = 0;
   h->m2l_pairs = 0;
   for (auto& g : h->groups) {
     const int nb = 1 << g.depth;
@@ -938,6 +945,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
                 nbsum += lc[g.leaf_base + ((int64_t)jx * nb + jy) * nb + jz];
               }
           h->p2p_pairs += c * nbsum - c;
+          h->p2p_same += c * c - c;
         }
     for (int lev = 2; lev <= g.depth; ++lev) {
       const int nb2 = 1 << lev;
@@ -1023,6 +1031,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     h->st.cross_fit_err = std::max(h->st.cross_fit_err, g.cross_fit_err);
   }
   h->st.p2p_pairs = h->p2p_pairs;
+  h->st.p2p_pairs_same_leaf = h->p2p_same;
   h->st.m2l_pairs = h->m2l_pairs;
   h->ready = true;
   h->gen = g_generation++;
@@ -1052,6 +1061,9 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
   HIPCHK(h, hipMalloc(&h->d_q, sizeof(double2) * h->n * nrhs));
   HIPCHK(h, hipMalloc(&h->d_phi, sizeof(double2) * h->n * nrhs));
   HIPCHK(h, hipMalloc(&h->d_phi_near, sizeof(double2) * h->n * nrhs));
+  dfree(h->d_part);
+  if (h->opt.precision == TEFMM_MIXED_FP32 && h->opt.p2p_targets >= 0)
+    HIPCHK(h, hipMalloc(&h->d_part, sizeof(float2) * 13 * h->n));
   for (auto& g : h->groups) {
     g.alpha.assign(g.depth + 1, nullptr);
     g.beta.assign(g.depth + 1, nullptr);
@@ -1158,6 +1170,21 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     const bool wide = g.count > 96 * g.nbox[g.depth];  // mean leaf occupancy above 96
     // several charge vectors share each pair kernel, 8 per block
     const bool multi = nrhs > 1;
+    if (fp32 && !multi && h->d_part) {
+      // each pair of particles in different leaves once (k_p2p_sym); targets per
+      // lane unless set: 2 above a mean leaf occupancy of 96 (4 holds more
+      // registers than it saves work), else 1
+      int tpl = h->opt.p2p_targets;
+      if (tpl == 0) tpl = wide ? 2 : 1;
+      void (*fs)(PassArgs, int, float2*) =
+          tpl == 1 ? k_p2p_sym<1, 4> : tpl == 2 ? k_p2p_sym<2, 4> : k_p2p_sym<4, 4>;
+      hipLaunchKernelGGL(fs, dim3((unsigned)g.nbox[g.depth], 1), dim3(256), 0, sn, a, 1, h->d_part);
+      HIPCHK(h, hipGetLastError());
+      hipLaunchKernelGGL(k_p2p_sym_gather, dim3((unsigned)g.nbox[g.depth], 1), dim3(128), 0, sn, a, 1,
+                         (const float2*)h->d_part);
+      HIPCHK(h, hipGetLastError());
+      continue;
+    }
     const dim3 grid((unsigned)g.nbox[g.depth], multi ? (nrhs + 7) / 8 : 1);
     void (*fn)(PassArgs, int) = nullptr;
     if (fp32)

@@ -942,6 +942,358 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Near field with each pair of particles in different leaves evaluated once
+// (FP32, one charge vector).  The free-space kernel e^{ikr}/r is symmetric in
+// its two points, so the pair (i, j) adds q_j G to phi_i and q_i G to phi_j.
+// Of the 26 neighbour leaves of a leaf A only the forward half is visited: the
+// columns (dx, dy) = (0, 1), (1, -1), (1, 0), (1, 1) with dz = -1, 0, 1 (slots
+// 3 c + dz + 1, c the column) and the leaf (0, 0, 1) (slot 12); A's own leaf is
+// done in full.  The workgroup of A adds the q_j G terms to its targets in
+// registers; the q_i G terms for a source j of a forward neighbour B are
+// summed over A's targets (per wave, a transposing butterfly over the 64
+// lanes, sixteen sources at a time; then over the waves in LDS, in a fixed
+// order) and written to part[slot][j].  k_p2p_sym_gather then adds to each
+// particle of B the slots of its existing, non-empty backward neighbours, in
+// slot order: the result is deterministic.
+// Near-singular pairs (closer than 5% of the leaf side) get G from FP64
+// coordinates, rounded to FP32; the pair with itself gets 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fwd_column(int c, int* dx, int* dy) {
+  *dx = c == 0 ? 0 : 1;
+  *dy = c == 0 ? 1 : c - 2;
+}
+
+// Squared distance of an FP32 near-field pair as used for its value, one
+// rounding order wherever it is formed.  SYM (sources in other leaves): plus
+// eps2, a 1e-8 fraction of the near-singular threshold, which only keeps two
+// particles that coincide in FP32 finite.  Otherwise (the leaf itself, which
+// holds the pair of each particle with itself): raised to at least rns2, so that
+// this pair's stand-in value is small.
+template <bool SYM>
+__device__ __forceinline__ float sym_r2(float tx, float ty, float tz, const float4& sp, float eps2, float rns2) {
+  const float dx = tx - sp.x, dy = ty - sp.y, dz = tz - sp.z;
+  if (SYM) return fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
+  // max of two non-negative floats as the max of their bit patterns
+  return __int_as_float(max(__float_as_int(fmaf(dz, dz, fmaf(dy, dy, dx * dx))), __float_as_int(rns2)));
+}
+
+// Eight staged sources [t, t + 8) against this lane's T targets.  SYM: also the
+// eight source-side sums over the wave's 64 T targets, written to
+// psw[2 (t + u) + c] (c = 0 real, 1 imaginary part).  Every pair is applied
+// with the FP32 value at the squared distance from sym_r2.  Pairs closer than
+// the threshold rns2 (rare: the pair of a particle with itself, or two
+// particles closer than 5% of the leaf side, whose FP32 coordinate differences
+// have lost digits) are marked in nl (a bit mask per step and lane) and, after
+// the eight sources, taken one by one: the value used is replaced by the one
+// from FP64 differences (0 for the pair with itself), its source-side part
+// added to dps[2 (t + u) + c].
+template <int T, bool SYM>
+__device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T], const float (&ty)[T],
+                                         const float (&tz)[T], const float (&qri)[T], const float (&qii)[T],
+                                         const bool (&act)[T], const float4* s4, const float* sqi,
+                                         const int* sidx, float rns2, float eps2, double kap2,
+                                         const PassArgs& a, float (&accr)[T], float (&acci)[T], float* psw,
+                                         float* dps, int* nl) {
+  const int lane = threadIdx.x & 63;
+  // a vector value, not an array: the butterfly's selects stay selects of values
+  typedef float f16v __attribute__((ext_vector_type(16)));
+  f16v c;
+  int steps = 0;  // steps with marked pairs
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {  // two sources at a time
+    float r2[2][T];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const float4 sp = s4[t + 2 * v + u];
+      const float qr = sp.w, qi = sqi[t + 2 * v + u];
+      float cr = 0.0f, ci = 0.0f;
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        // SYM: r2 as used; otherwise the clamped value (the test below needs the
+        // plain one, and the clamp only ever raises it to the threshold itself)
+        r2[u][k] = SYM ? sym_r2<true>(tx[k], ty[k], tz[k], sp, eps2, rns2) : 0.0f;
+        float used = r2[u][k];
+        if (!SYM) {
+          const float dx = tx[k] - sp.x, dy = ty[k] - sp.y, dz = tz[k] - sp.z;
+          r2[u][k] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          used = __int_as_float(max(__float_as_int(r2[u][k]), __float_as_int(rns2)));
+        }
+        float er, ei;
+        pair_kernel(used, 0.0f, &er, &ei);
+        accr[k] = fmaf(qr, er, fmaf(-qi, ei, accr[k]));
+        acci[k] = fmaf(qr, ei, fmaf(qi, er, acci[k]));
+        if (SYM) {
+          cr = fmaf(qri[k], er, fmaf(-qii[k], ei, cr));
+          ci = fmaf(qri[k], ei, fmaf(qii[k], er, ci));
+        }
+      }
+      if (SYM) {
+        // pin the source-side sums to this step (left to itself the compiler
+        // sinks them to the butterfly and keeps every pair value alive)
+        asm volatile("" : "+v"(cr), "+v"(ci));
+        c[2 * (2 * v + u)] = cr, c[2 * (2 * v + u) + 1] = ci;
+      }
+    }
+    float mn = r2[0][0];
+#pragma unroll
+    for (int k = 0; k < T; ++k) mn = fminf(mn, fminf(r2[0][k], r2[1][k]));
+    if (__any(mn < rns2)) {
+      unsigned m = 0;  // bit u T + k: pair (source 2 v + u, target slot k)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int k = 0; k < T; ++k) m |= (act[k] && r2[u][k] < rns2) ? 1u << (u * T + k) : 0u;
+      nl[64 * v + lane] = (int)m;
+      steps |= 1 << v;
+    }
+    // one step at a time: interleaving the steps would only raise register pressure
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (SYM) {
+    // transposing butterfly over the 16 values: after the stage with mask m a
+    // lane holds the half of its values selected by (lane & m), summed with the
+    // partner's same half.  Masks 32 and 16 by the lane-swap instructions (value
+    // k to the low half of the lanes, k + H to the high half), masks 8 and 4 by
+    // a select and a shuffle; then lane l holds value (l >> 2) summed over 16
+    // lanes, and two plain steps (masks 2, 1) complete the sum over 64 lanes.
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[k]), __float_as_uint(c[k + 8]), false, false);
+      c[k] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(c[k]), __float_as_uint(c[k + 4]), false, false);
+      c[k] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+    }
+#pragma unroll
+    for (int st = 2; st < 4; ++st) {
+      const int m = 32 >> st, H = 8 >> st;
+      const bool hi = (lane & m) != 0;
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        const float send = hi ? c[k] : c[k + H];
+        const float keep = hi ? c[k + H] : c[k];
+        c[k] = keep + __shfl_xor(send, m);
+      }
+    }
+    float tot = c[0] + __shfl_xor(c[0], 2);
+    tot += __shfl_xor(tot, 1);
+    if (!(lane & 3)) psw[2 * t + (lane >> 2)] = tot;
+  }
+  // the marked pairs, step by step, lane by lane, pair by pair (a fixed order)
+  for (int v = 0; v < 4; ++v) {
+    if (!((steps >> v) & 1)) continue;
+    const unsigned mine = (unsigned)nl[64 * v + lane];
+    unsigned long long bal = __ballot(mine != 0);
+    while (bal) {
+      const int l = __builtin_ctzll(bal);
+      bal &= bal - 1;
+      if (lane != l) continue;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+          if (!((mine >> (u * T + k)) & 1)) continue;
+          const int uu = 2 * v + u;
+          const int64_t j = sidx[t + uu], i = tbase + 64 * k;
+          // the digits lost are those of the coordinate differences: those in FP64,
+          // the rest of the pair in FP32 as above
+          float er = 0.0f, ei = 0.0f;
+          if (j >= 0 && j != i) {
+            const double ex = a.xs[i] - a.xs[j], ey = a.xs[a.n + i] - a.xs[a.n + j],
+                         ez = a.xs[2 * a.n + i] - a.xs[2 * a.n + j];
+            pair_kernel((float)((ex * ex + ey * ey + ez * ez) * kap2), 0.0f, &er, &ei);
+          }
+          float ur, ui;  // the value used above
+          pair_kernel(sym_r2<SYM>(tx[k], ty[k], tz[k], s4[t + uu], eps2, rns2), 0.0f, &ur, &ui);
+          const float der = er - ur, dei = ei - ui;
+          const float qr = s4[t + uu].w, qi = sqi[t + uu];
+          accr[k] = fmaf(qr, der, fmaf(-qi, dei, accr[k]));
+          acci[k] = fmaf(qr, dei, fmaf(qi, der, acci[k]));
+          if (SYM) {
+            dps[2 * (t + uu)] += fmaf(qri[k], der, -qii[k] * dei);
+            dps[2 * (t + uu) + 1] += fmaf(qri[k], dei, qii[k] * der);
+          }
+        }
+    }
+  }
+}
+
+// Within a wave, data written to LDS by some lanes and read by others: the
+// wave's LDS operations complete in order, so only the compiler must keep them
+// in order.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One workgroup per leaf A, T targets per lane: the 64 T targets of a pass are
+// the same for the NW waves, which share out the staged source chunks (SC
+// sources; chunk c of the pass, counted over the ranges, goes to wave c mod NW).
+// Each wave stages, evaluates and writes its chunks' source-side sums on its
+// own; at the end of the pass the waves' target sums are added in wave order.
+template <int T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float2* part) {
+  constexpr int SC = 128, TP = 64 * T;  // sources per chunk, targets per pass
+  __shared__ float4 s4[NW][SC];  // scaled x, y, z and the real part of the charge
+  __shared__ float sqi[NW][SC];
+  __shared__ int sidx[NW][SC];
+  __shared__ float psw[NW][2 * SC];
+  __shared__ float dps[NW][2 * SC];  // near-singular corrections of the source-side sums
+  __shared__ int nl[NW][4 * 64];     // near-pair masks of the current eight sources, per step and lane
+  __shared__ float2 tacc[NW > 1 ? NW : 1][NW > 1 ? TP : 1];
+  const int leaf = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int nb = a.nbox_dim;
+  const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
+  const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
+  // coordinates in units of 2 pi / k (see pair_kernel)
+  const double kap = a.k / 6.283185307179586477;
+  const float rns2 = (float)(0.0025 * a.h * a.h * kap * kap);
+  const float eps2 = 1e-8f * rns2;
+  const double2* q = a.q + (int64_t)r * a.n;
+  for (int c0 = 0; c0 < cnt; c0 += TP) {
+    float tx[T], ty[T], tz[T], qri[T], qii[T], accr[T], acci[T];
+    bool act[T];
+    const int tbase = start + c0 + lane;  // target index of slot k: tbase + 64 k
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const int c = c0 + 64 * k + lane;
+      act[k] = c < cnt;
+      const int64_t i = start + (act[k] ? c : 0);
+      tx[k] = (float)((a.xs[i] - a.lo[0]) * kap);
+      ty[k] = (float)((a.xs[a.n + i] - a.lo[1]) * kap);
+      tz[k] = (float)((a.xs[2 * a.n + i] - a.lo[2]) * kap);
+      const double2 qv = act[k] ? q[i] : make_double2(0.0, 0.0);
+      qri[k] = (float)qv.x, qii[k] = (float)qv.y;
+      accr[k] = 0.0f, acci[k] = 0.0f;
+    }
+    int chunk = 0;
+    // ranges: 0 = the leaf itself, 1..4 = forward columns, 5 = the leaf above
+    for (int rg = 0; rg < 6; ++rg) {
+      int ss, se, z1 = iz;
+      int64_t kl = 0;
+      if (rg == 0) {
+        ss = start, se = start + cnt;
+      } else if (rg == 5) {
+        if (iz + 1 >= nb) continue;
+        kl = a.leaf_base + ((int64_t)ix * nb + iy) * nb;
+        ss = a.leaf_start[kl + iz + 1], se = ss + a.leaf_count[kl + iz + 1];
+      } else {
+        int dx, dy;
+        fwd_column(rg - 1, &dx, &dy);
+        const int jx = ix + dx, jy = iy + dy;
+        if (jx >= nb || jy < 0 || jy >= nb) continue;
+        kl = a.leaf_base + ((int64_t)jx * nb + jy) * nb;
+        const int z0 = max(iz - 1, 0);
+        z1 = min(iz + 1, nb - 1);
+        ss = a.leaf_start[kl + z0], se = a.leaf_start[kl + z1] + a.leaf_count[kl + z1];
+      }
+      for (int s0 = ss; s0 < se; s0 += SC, ++chunk) {
+        if (chunk % NW != w) continue;
+        const int m = min(SC, se - s0), m8 = (m + 7) & ~7;
+        wave_lds_sync();
+        for (int e = lane; e < m8; e += 64) {
+          // eight-aligned tail: copies of the first source with charge 0 and no index
+          const int64_t j = s0 + (e < m ? e : 0);
+          const double2 qj = q[j];
+          s4[w][e] = make_float4((float)((a.xs[j] - a.lo[0]) * kap), (float)((a.xs[a.n + j] - a.lo[1]) * kap),
+                                 (float)((a.xs[2 * a.n + j] - a.lo[2]) * kap), e < m ? (float)qj.x : 0.0f);
+          sqi[w][e] = e < m ? (float)qj.y : 0.0f;
+          sidx[w][e] = e < m ? (int)j : -1;
+          dps[w][2 * e] = 0.0f, dps[w][2 * e + 1] = 0.0f;
+        }
+        wave_lds_sync();
+        const int mu = __builtin_amdgcn_readfirstlane(m8);
+        if (rg == 0) {
+          for (int t = 0; t < mu; t += 8)
+            p2p_sym8<T, false>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap,
+                               a, accr, acci, psw[w], dps[w], nl[w]);
+          continue;
+        }
+        for (int t = 0; t < mu; t += 8)
+          p2p_sym8<T, true>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap, a,
+                            accr, acci, psw[w], dps[w], nl[w]);
+        wave_lds_sync();
+        for (int e = lane; e < m; e += 64) {
+          const int64_t j = s0 + e;
+          const float pr = psw[w][2 * e] + dps[w][2 * e], pi = psw[w][2 * e + 1] + dps[w][2 * e + 1];
+          int slot = 12;
+          if (rg < 5) {
+            const int zj = (z1 > iz && j >= a.leaf_start[kl + iz + 1]) ? iz + 1
+                           : (j >= a.leaf_start[kl + iz])               ? iz
+                                                                         : iz - 1;
+            slot = 3 * (rg - 1) + (zj - iz + 1);
+          }
+          float2* dst = part + ((int64_t)slot * nrhs + r) * a.n + j;
+          if (c0 == 0)
+            *dst = make_float2(pr, pi);
+          else
+            *dst = make_float2(dst->x + pr, dst->y + pi);
+        }
+      }
+    }
+    if (NW > 1) {
+      // the waves' target sums, added in wave order
+#pragma unroll
+      for (int k = 0; k < T; ++k) tacc[w][64 * k + lane] = make_float2(accr[k], acci[k]);
+      __syncthreads();
+      if (w == 0) {
+#pragma unroll
+        for (int k = 0; k < T; ++k) {
+          accr[k] = tacc[0][64 * k + lane].x, acci[k] = tacc[0][64 * k + lane].y;
+          for (int ww = 1; ww < NW; ++ww) accr[k] += tacc[ww][64 * k + lane].x, acci[k] += tacc[ww][64 * k + lane].y;
+        }
+      }
+      __syncthreads();
+    }
+    if (w == 0)
+#pragma unroll
+      for (int k = 0; k < T; ++k)
+        if (act[k])
+          a.phi[(int64_t)r * a.n + tbase + 64 * k] = make_double2((double)accr[k] * kap, (double)acci[k] * kap);
+  }
+}
+
+// Adds to each particle of leaf B the source-side sums that its backward
+// neighbours A = B - o (o in the forward half, A inside the grid and not empty)
+// left in part, in slot order (see k_p2p_sym).
+__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, const float2* part) {
+  const int leaf = blockIdx.x, r = blockIdx.y;
+  const int nb = a.nbox_dim;
+  const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
+  const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
+  if (cnt == 0) return;
+  unsigned have = 0;
+  for (int slot = 0; slot < 13; ++slot) {
+    int dx = 0, dy = 0, dz = 1;
+    if (slot < 12) fwd_column(slot / 3, &dx, &dy), dz = slot % 3 - 1;
+    const int ax = ix - dx, ay = iy - dy, az = iz - dz;
+    if (ax < 0 || ay < 0 || az < 0 || ax >= nb || ay >= nb || az >= nb) continue;
+    if (a.leaf_count[a.leaf_base + ((int64_t)ax * nb + ay) * nb + az] > 0) have |= 1u << slot;
+  }
+  const double kap = a.k / 6.283185307179586477;
+  for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+    const int64_t j = start + c;
+    float sr = 0.0f, si = 0.0f;
+    for (int slot = 0; slot < 13; ++slot)
+      if ((have >> slot) & 1) {
+        const float2 v = part[((int64_t)slot * nrhs + r) * a.n + j];
+        sr += v.x, si += v.y;
+      }
+    double2* o = a.phi + (int64_t)r * a.n + j;
+    *o = make_double2(o->x + (double)sr * kap, o->y + (double)si * kap);
+  }
+}
+
+template __global__ void k_p2p_sym<1, 1>(PassArgs, int, float2*);
+template __global__ void k_p2p_sym<2, 1>(PassArgs, int, float2*);
+template __global__ void k_p2p_sym<4, 1>(PassArgs, int, float2*);
+template __global__ void k_p2p_sym<1, 4>(PassArgs, int, float2*);
+template __global__ void k_p2p_sym<2, 4>(PassArgs, int, float2*);
+template __global__ void k_p2p_sym<4, 4>(PassArgs, int, float2*);
+
 template __global__ void k_p2p<double, 64, 1>(PassArgs, int);
 template __global__ void k_p2p<float, 64, 1>(PassArgs, int);
 template __global__ void k_p2p<double, 256, 1>(PassArgs, int);

@@ -169,6 +169,9 @@ __global__ void k_l2l(PassArgs a);
 __global__ void k_l2p(PassArgs a);
 template <typename T, int BS, int RB>
 __global__ void k_p2p(PassArgs a, int nrhs);
+template <int T, int NW>
+__global__ void k_p2p_sym(PassArgs a, int nrhs, float2* part);
+__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, const float2* part);
 
 // M2L launcher (picks the row-block instantiation for nRB).
 hipError_t launch_m2l(const M2LArgs& a, int nrhs, bool fp32, hipStream_t s);
