@@ -48,6 +48,7 @@ struct Group {
   bool has[3] = {false, false, false};
   std::vector<double2*> alpha, beta;  // by level, full Taylor sets [rhs][box][nC]
   std::vector<double2*> ared, bred;   // by level, Helmholtz-reduced sets [rhs][box][nR]
+  std::vector<float2*> ared32;        // reduced moments in FP32 (mixed precision; ared unused then)
   std::vector<double2*> Tfd, TS;
   std::vector<float2*> Tfd32, TS32;
   std::vector<int64_t> nbox;          // boxes at level
@@ -163,6 +164,7 @@ static void free_geometry(tefmm_t h) {
     for (auto& p : g.alpha) dfree(p);
     for (auto& p : g.beta) dfree(p);
     for (auto& p : g.ared) dfree(p);
+    for (auto& p : g.ared32) dfree(p);
     for (auto& p : g.bred) dfree(p);
     for (auto& p : g.azred) dfree(p);
     for (auto& p : g.bzred) dfree(p);
@@ -1054,6 +1056,7 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
     for (auto& p : g.alpha) dfree(p);
     for (auto& p : g.beta) dfree(p);
     for (auto& p : g.ared) dfree(p);
+    for (auto& p : g.ared32) dfree(p);
     for (auto& p : g.bred) dfree(p);
     for (auto& p : g.azred) dfree(p);
     for (auto& p : g.bzred) dfree(p);
@@ -1068,6 +1071,7 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
     g.alpha.assign(g.depth + 1, nullptr);
     g.beta.assign(g.depth + 1, nullptr);
     g.ared.assign(g.depth + 1, nullptr);
+    g.ared32.assign(g.depth + 1, nullptr);
     g.bred.assign(g.depth + 1, nullptr);
     g.azred.assign(g.depth + 1, nullptr);
     g.bzred.assign(g.depth + 1, nullptr);
@@ -1077,7 +1081,10 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
       g.nbox[lev] = nbx;
       HIPCHK(h, hipMalloc(&g.alpha[lev], sizeof(double2) * nbx * h->nC * nrhs));
       HIPCHK(h, hipMalloc(&g.beta[lev], sizeof(double2) * nbx * h->nC * nrhs));
-      HIPCHK(h, hipMalloc(&g.ared[lev], sizeof(double2) * nbx * h->nR * nrhs));
+      if (h->opt.precision == TEFMM_MIXED_FP32)
+        HIPCHK(h, hipMalloc(&g.ared32[lev], sizeof(float2) * nbx * h->nR * nrhs));
+      else
+        HIPCHK(h, hipMalloc(&g.ared[lev], sizeof(double2) * nbx * h->nR * nrhs));
       HIPCHK(h, hipMalloc(&g.bred[lev], sizeof(double2) * nbx * h->nR * nrhs * m2l_split(g.depth)));
       if (h->groups.size() > 1) {
         HIPCHK(h, hipMalloc(&g.azred[lev], sizeof(double2) * nbx * h->nR * nrhs));
@@ -1143,7 +1150,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     const double hl = g.side / (1 << lev), kh = h->med.k[g.layer] * hl;
     ra.p = p, ra.nC = h->nC, ra.nR = h->nR, ra.kh2 = kh * kh, ra.mi = h->d_mi, ra.rfull = z ? h->d_rzfull : h->d_rfull;
     ra.scale = h->d_scale, ra.invfact = h->d_invfact;
-    ra.nsplit = 1, ra.split_stride = 0;
+    ra.nsplit = 1, ra.split_stride = 0, ra.out32 = nullptr;
     return ra;
   };
   EVREC(0);
@@ -1222,7 +1229,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     }
     for (int lev = 2; lev <= H; ++lev) {
       ReduceArgs ra = reduce_args(g, lev, false);
-      ra.in = g.alpha[lev], ra.out = g.ared[lev];
+      ra.in = g.alpha[lev], ra.out = g.ared[lev], ra.out32 = g.ared32[lev];
       ra.in_stride = g.nbox[lev] * h->nC, ra.out_stride = g.nbox[lev] * h->nR;
       hipLaunchKernelGGL(k_reduce, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), sizeof(double2) * h->nC, s, ra);
       HIPCHK(h, hipGetLastError());
@@ -1258,12 +1265,14 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       M2LLevel& L = m.lev[lev - 2];
       L.n = 1 << lev, L.leaf = lev == H;
       L.near_fd = g.has[2], L.near_s = g.has[0] || g.has[1];
-      L.a = g.ared[lev], L.b = g.bred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
+      L.a = g.ared[lev], L.a32 = g.ared32[lev], L.b = g.bred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
       L.split_stride = g.nbox[lev] * h->nR * h->nrhs_alloc;
       L.Tfd = g.Tfd[lev], L.TS = g.TS[lev], L.Tfd32 = g.Tfd32[lev], L.TS32 = g.TS32[lev];
     }
     m.ncb = h->m2l_ncb ? h->m2l_ncb : h->opt.m2l_tile;
     m.nsplit = m2l_split(H);
+    // the pipelined FP32 kernel holds more registers: faster alone, slower beside the near field
+    m.pipe = fork ? 0 : 1;
     HIPCHK(h, launch_m2l(m, nrhs, fp32, sm));
     const double per = 8.0 * (double)h->nR * (double)h->nR;
     for (int lev = 2; lev <= H; ++lev) {

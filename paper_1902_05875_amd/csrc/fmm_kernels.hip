@@ -394,6 +394,14 @@ __global__ __launch_bounds__(64) void k_reduce(ReduceArgs a) {
     }
     __syncthreads();
   }
+  if (a.out32) {
+    float2* out = a.out32 + (int64_t)r * a.out_stride + (int64_t)box * a.nR;
+    for (int i = tid; i < a.nR; i += 64) {
+      const double2 v = lds_red[a.rfull[i]];
+      out[i] = make_float2((float)v.x, (float)v.y);
+    }
+    return;
+  }
   double2* out = a.out + (int64_t)r * a.out_stride + (int64_t)box * a.nR;
   for (int i = tid; i < a.nR; i += 64) out[i] = lds_red[a.rfull[i]];
 }
@@ -1144,115 +1152,118 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float
   __shared__ float dps[NW][2 * SC];  // near-singular corrections of the source-side sums
   __shared__ int nl[NW][4 * 64];     // near-pair masks of the current eight sources, per step and lane
   __shared__ float2 tacc[NW > 1 ? NW : 1][NW > 1 ? TP : 1];
-  const int leaf = blockIdx.x, r = blockIdx.y, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int r = blockIdx.y, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int nb = a.nbox_dim;
-  const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
-  const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
   // coordinates in units of 2 pi / k (see pair_kernel)
   const double kap = a.k / 6.283185307179586477;
   const float rns2 = (float)(0.0025 * a.h * a.h * kap * kap);
   const float eps2 = 1e-8f * rns2;
   const double2* q = a.q + (int64_t)r * a.n;
-  for (int c0 = 0; c0 < cnt; c0 += TP) {
-    float tx[T], ty[T], tz[T], qri[T], qii[T], accr[T], acci[T];
-    bool act[T];
-    const int tbase = start + c0 + lane;  // target index of slot k: tbase + 64 k
+  // leaves blockIdx.x, blockIdx.x + gridDim.x, ...
+  for (int leaf = blockIdx.x; leaf < nb * nb * nb; leaf += gridDim.x) {
+    const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
+    const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
+    for (int c0 = 0; c0 < cnt; c0 += TP) {
+      float tx[T], ty[T], tz[T], qri[T], qii[T], accr[T], acci[T];
+      bool act[T];
+      const int tbase = start + c0 + lane;  // target index of slot k: tbase + 64 k
 #pragma unroll
-    for (int k = 0; k < T; ++k) {
-      const int c = c0 + 64 * k + lane;
-      act[k] = c < cnt;
-      const int64_t i = start + (act[k] ? c : 0);
-      tx[k] = (float)((a.xs[i] - a.lo[0]) * kap);
-      ty[k] = (float)((a.xs[a.n + i] - a.lo[1]) * kap);
-      tz[k] = (float)((a.xs[2 * a.n + i] - a.lo[2]) * kap);
-      const double2 qv = act[k] ? q[i] : make_double2(0.0, 0.0);
-      qri[k] = (float)qv.x, qii[k] = (float)qv.y;
-      accr[k] = 0.0f, acci[k] = 0.0f;
-    }
-    int chunk = 0;
-    // ranges: 0 = the leaf itself, 1..4 = forward columns, 5 = the leaf above
-    for (int rg = 0; rg < 6; ++rg) {
-      int ss, se, z1 = iz;
-      int64_t kl = 0;
-      if (rg == 0) {
-        ss = start, se = start + cnt;
-      } else if (rg == 5) {
-        if (iz + 1 >= nb) continue;
-        kl = a.leaf_base + ((int64_t)ix * nb + iy) * nb;
-        ss = a.leaf_start[kl + iz + 1], se = ss + a.leaf_count[kl + iz + 1];
-      } else {
-        int dx, dy;
-        fwd_column(rg - 1, &dx, &dy);
-        const int jx = ix + dx, jy = iy + dy;
-        if (jx >= nb || jy < 0 || jy >= nb) continue;
-        kl = a.leaf_base + ((int64_t)jx * nb + jy) * nb;
-        const int z0 = max(iz - 1, 0);
-        z1 = min(iz + 1, nb - 1);
-        ss = a.leaf_start[kl + z0], se = a.leaf_start[kl + z1] + a.leaf_count[kl + z1];
+      for (int k = 0; k < T; ++k) {
+        const int c = c0 + 64 * k + lane;
+        act[k] = c < cnt;
+        const int64_t i = start + (act[k] ? c : 0);
+        tx[k] = (float)((a.xs[i] - a.lo[0]) * kap);
+        ty[k] = (float)((a.xs[a.n + i] - a.lo[1]) * kap);
+        tz[k] = (float)((a.xs[2 * a.n + i] - a.lo[2]) * kap);
+        const double2 qv = act[k] ? q[i] : make_double2(0.0, 0.0);
+        qri[k] = (float)qv.x, qii[k] = (float)qv.y;
+        accr[k] = 0.0f, acci[k] = 0.0f;
       }
-      for (int s0 = ss; s0 < se; s0 += SC, ++chunk) {
-        if (chunk % NW != w) continue;
-        const int m = min(SC, se - s0), m8 = (m + 7) & ~7;
-        wave_lds_sync();
-        for (int e = lane; e < m8; e += 64) {
-          // eight-aligned tail: copies of the first source with charge 0 and no index
-          const int64_t j = s0 + (e < m ? e : 0);
-          const double2 qj = q[j];
-          s4[w][e] = make_float4((float)((a.xs[j] - a.lo[0]) * kap), (float)((a.xs[a.n + j] - a.lo[1]) * kap),
-                                 (float)((a.xs[2 * a.n + j] - a.lo[2]) * kap), e < m ? (float)qj.x : 0.0f);
-          sqi[w][e] = e < m ? (float)qj.y : 0.0f;
-          sidx[w][e] = e < m ? (int)j : -1;
-          dps[w][2 * e] = 0.0f, dps[w][2 * e + 1] = 0.0f;
-        }
-        wave_lds_sync();
-        const int mu = __builtin_amdgcn_readfirstlane(m8);
+      int chunk = 0;
+      // ranges: 0 = the leaf itself, 1..4 = forward columns, 5 = the leaf above
+      for (int rg = 0; rg < 6; ++rg) {
+        int ss, se, z1 = iz;
+        int64_t kl = 0;
         if (rg == 0) {
-          for (int t = 0; t < mu; t += 8)
-            p2p_sym8<T, false>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap,
-                               a, accr, acci, psw[w], dps[w], nl[w]);
-          continue;
+          ss = start, se = start + cnt;
+        } else if (rg == 5) {
+          if (iz + 1 >= nb) continue;
+          kl = a.leaf_base + ((int64_t)ix * nb + iy) * nb;
+          ss = a.leaf_start[kl + iz + 1], se = ss + a.leaf_count[kl + iz + 1];
+        } else {
+          int dx, dy;
+          fwd_column(rg - 1, &dx, &dy);
+          const int jx = ix + dx, jy = iy + dy;
+          if (jx >= nb || jy < 0 || jy >= nb) continue;
+          kl = a.leaf_base + ((int64_t)jx * nb + jy) * nb;
+          const int z0 = max(iz - 1, 0);
+          z1 = min(iz + 1, nb - 1);
+          ss = a.leaf_start[kl + z0], se = a.leaf_start[kl + z1] + a.leaf_count[kl + z1];
         }
-        for (int t = 0; t < mu; t += 8)
-          p2p_sym8<T, true>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap, a,
-                            accr, acci, psw[w], dps[w], nl[w]);
-        wave_lds_sync();
-        for (int e = lane; e < m; e += 64) {
-          const int64_t j = s0 + e;
-          const float pr = psw[w][2 * e] + dps[w][2 * e], pi = psw[w][2 * e + 1] + dps[w][2 * e + 1];
-          int slot = 12;
-          if (rg < 5) {
-            const int zj = (z1 > iz && j >= a.leaf_start[kl + iz + 1]) ? iz + 1
-                           : (j >= a.leaf_start[kl + iz])               ? iz
-                                                                         : iz - 1;
-            slot = 3 * (rg - 1) + (zj - iz + 1);
+        for (int s0 = ss; s0 < se; s0 += SC, ++chunk) {
+          if (chunk % NW != w) continue;
+          const int m = min(SC, se - s0), m8 = (m + 7) & ~7;
+          wave_lds_sync();
+          for (int e = lane; e < m8; e += 64) {
+            // eight-aligned tail: copies of the first source with charge 0 and no index
+            const int64_t j = s0 + (e < m ? e : 0);
+            const double2 qj = q[j];
+            s4[w][e] = make_float4((float)((a.xs[j] - a.lo[0]) * kap), (float)((a.xs[a.n + j] - a.lo[1]) * kap),
+                                   (float)((a.xs[2 * a.n + j] - a.lo[2]) * kap), e < m ? (float)qj.x : 0.0f);
+            sqi[w][e] = e < m ? (float)qj.y : 0.0f;
+            sidx[w][e] = e < m ? (int)j : -1;
+            dps[w][2 * e] = 0.0f, dps[w][2 * e + 1] = 0.0f;
           }
-          float2* dst = part + ((int64_t)slot * nrhs + r) * a.n + j;
-          if (c0 == 0)
-            *dst = make_float2(pr, pi);
-          else
-            *dst = make_float2(dst->x + pr, dst->y + pi);
+          wave_lds_sync();
+          const int mu = __builtin_amdgcn_readfirstlane(m8);
+          if (rg == 0) {
+            for (int t = 0; t < mu; t += 8)
+              p2p_sym8<T, false>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap,
+                                 a, accr, acci, psw[w], dps[w], nl[w]);
+            continue;
+          }
+          for (int t = 0; t < mu; t += 8)
+            p2p_sym8<T, true>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap, a,
+                              accr, acci, psw[w], dps[w], nl[w]);
+          wave_lds_sync();
+          for (int e = lane; e < m; e += 64) {
+            const int64_t j = s0 + e;
+            const float pr = psw[w][2 * e] + dps[w][2 * e], pi = psw[w][2 * e + 1] + dps[w][2 * e + 1];
+            int slot = 12;
+            if (rg < 5) {
+              const int zj = (z1 > iz && j >= a.leaf_start[kl + iz + 1]) ? iz + 1
+                             : (j >= a.leaf_start[kl + iz])               ? iz
+                                                                           : iz - 1;
+              slot = 3 * (rg - 1) + (zj - iz + 1);
+            }
+            float2* dst = part + ((int64_t)slot * nrhs + r) * a.n + j;
+            if (c0 == 0)
+              *dst = make_float2(pr, pi);
+            else
+              *dst = make_float2(dst->x + pr, dst->y + pi);
+          }
         }
       }
-    }
-    if (NW > 1) {
-      // the waves' target sums, added in wave order
+      if (NW > 1) {
+        // the waves' target sums, added in wave order
 #pragma unroll
-      for (int k = 0; k < T; ++k) tacc[w][64 * k + lane] = make_float2(accr[k], acci[k]);
-      __syncthreads();
-      if (w == 0) {
+        for (int k = 0; k < T; ++k) tacc[w][64 * k + lane] = make_float2(accr[k], acci[k]);
+        __syncthreads();
+        if (w == 0) {
 #pragma unroll
-        for (int k = 0; k < T; ++k) {
-          accr[k] = tacc[0][64 * k + lane].x, acci[k] = tacc[0][64 * k + lane].y;
-          for (int ww = 1; ww < NW; ++ww) accr[k] += tacc[ww][64 * k + lane].x, acci[k] += tacc[ww][64 * k + lane].y;
+          for (int k = 0; k < T; ++k) {
+            accr[k] = tacc[0][64 * k + lane].x, acci[k] = tacc[0][64 * k + lane].y;
+            for (int ww = 1; ww < NW; ++ww) accr[k] += tacc[ww][64 * k + lane].x, acci[k] += tacc[ww][64 * k + lane].y;
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
-    }
-    if (w == 0)
+      if (w == 0)
 #pragma unroll
-      for (int k = 0; k < T; ++k)
-        if (act[k])
-          a.phi[(int64_t)r * a.n + tbase + 64 * k] = make_double2((double)accr[k] * kap, (double)acci[k] * kap);
+        for (int k = 0; k < T; ++k)
+          if (act[k])
+            a.phi[(int64_t)r * a.n + tbase + 64 * k] = make_double2((double)accr[k] * kap, (double)acci[k] * kap);
+    }
   }
 }
 

@@ -70,6 +70,7 @@ struct ReduceArgs {
   const double* invfact; // [nC] 1/k!          (expand)
   const double2* in;     // reduce: alpha^ [rhs][box][nC];  expand: b [rhs][box][nR]
   double2* out;          // reduce: a [rhs][box][nR];      expand: beta^ [rhs][box][nC]
+  float2* out32;         // reduce: if set, a in FP32 here instead of out (mixed precision)
   int64_t in_stride, out_stride;  // per-rhs strides (elements)
   int nsplit;            // expand: partial sets of b to sum (1 if unsplit)
   int64_t split_stride;  // elements between partial sets
@@ -82,6 +83,7 @@ struct M2LLevel {
   int tiles_x, tiles_y, ntiles;
   int near_fd, near_s;
   const double2* a;      // reduced scaled moments [rhs][box][nR]
+  const float2* a32;     // the same in FP32 (mixed precision)
   double2* b;            // reduced locals [rhs][box][nR]
   int64_t rhs_stride;
   const double2* Tfd;    // [343][nG] free + Delta (|d|>=2) and Delta-only (|d|<=1) or null
@@ -101,6 +103,8 @@ struct M2LArgs {
   int nsplit;            // the offsets of a tile are split over nsplit workgroups (blockIdx.z),
                          // each writing its own partial locals (summed in fixed order by k_expand)
   int kph, kpb, nRsP;    // source moments staged in kph phases of kpb blocks of 4 (LDS row stride nRsP)
+  int pipe;              // FP32: the kernel that stages the next offset during the current one may be
+                         // used (faster alone; the near field running beside it favours the other)
   int tile_start[M2L_MAX_LEVELS + 1];
   M2LLevel lev[M2L_MAX_LEVELS];
   const int* rmi;        // [nR] packed reduced multi-indices
