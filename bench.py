@@ -297,7 +297,9 @@ def main():
                          "c5: the batched workload (its own JSON line)")
     ap.add_argument("--n", type=int, default=None, help="override N (same recipe)")
     ap.add_argument("--p64", type=int, default=13, help="Taylor order of the plain FP64 mode")
-    ap.add_argument("--p32", type=int, default=8, help="Taylor order of the mixed FP32 mode")
+    ap.add_argument("--p32", type=int, default=7,
+                    help="Taylor order of the mixed FP32 mode (the smallest meeting 1e-4 at N = 1M: "
+                         "relative 2-norm error 3.7e-5 over all targets against FP64 p = 13)")
     ap.add_argument("--max-leaf", type=int, default=64)
     ap.add_argument("--n-rhs", type=int, default=1)
     ap.add_argument("--headline", choices=["fp32", "fp64"], default="fp32")

@@ -161,7 +161,8 @@ def test_near_singular_pairs(precision):
     assert e < 1e-6
 
 
-@pytest.mark.parametrize("p,precision,depth,tol", [(13, "fp64", 4, 1e-6), (8, "fp32", 4, 1e-4), (8, "fp32", 5, 1e-4)])
+@pytest.mark.parametrize("p,precision,depth,tol", [(13, "fp64", 4, 1e-6), (8, "fp32", 4, 1e-4), (8, "fp32", 5, 1e-4),
+                                                    (7, "fp32", 4, 1e-4)])
 def test_c4_full_size_sampled(p, precision, depth, tol):
     """The bench workload at full size: N = 1,000,000 in the middle-layer cube, 16 sampled
     targets (12 uniform + 4 nearest an interface) against the oracle, at the depth the
