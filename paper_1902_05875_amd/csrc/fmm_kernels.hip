@@ -1036,12 +1036,14 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
           ci = fmaf(qri[k], ei, fmaf(qii[k], er, ci));
         }
       }
+      // pin the sums to this source (left to itself the compiler sinks the
+      // accumulations towards their use and keeps every pair value alive)
       if (SYM) {
-        // pin the source-side sums to this step (left to itself the compiler
-        // sinks them to the butterfly and keeps every pair value alive)
         asm volatile("" : "+v"(cr), "+v"(ci));
         c[2 * (2 * v + u)] = cr, c[2 * (2 * v + u) + 1] = ci;
       }
+#pragma unroll
+      for (int k = 0; k < T; ++k) asm volatile("" : "+v"(accr[k]), "+v"(acci[k]));
     }
     float mn = r2[0][0];
 #pragma unroll
