@@ -787,6 +787,10 @@ __device__ __forceinline__ void p2p_f64_rows(int m, T tx, T ty, T tz, const T* s
       const double wr = self ? 0.0 : (double)sq[t][2 * b], wi = self ? 0.0 : (double)sq[t][2 * b + 1];
       accr[b] += wr * er - wi * ei;
       acci[b] += wr * ei + wi * er;
+      // several vectors: keep the sums with this source (else the compiler defers them and
+      // holds every pair value: 256 registers and spills at 8 vectors).  One vector: left
+      // alone, its 122 registers leave room for the far field running beside it.
+      if (RB > 1) asm volatile("" : "+v"(accr[b]), "+v"(acci[b]));
     }
   }
 }
@@ -830,6 +834,8 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
       const float qr = sq[t][2 * b], qi = sq[t][2 * b + 1];
       accr[b] = fmaf(qr, er, fmaf(-qi, ei, accr[b]));
       acci[b] = fmaf(qr, ei, fmaf(qi, er, acci[b]));
+      // keep the sums with this source (else the compiler defers them and holds every pair value)
+      asm volatile("" : "+v"(accr[b]), "+v"(acci[b]));
     }
   };
   m = __builtin_amdgcn_readfirstlane(m);
