@@ -75,7 +75,8 @@ __device__ __forceinline__ unsigned tile_mask(int N, int px, int py, int X0, int
   return m;
 }
 
-template <typename T, int TW, int NCB>
+// EX: every wave has TW tiles (4 TW row-block x column-block tiles in all), no test
+template <typename T, int TW, int NCB, bool EX>
 __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   typedef M2LTypes<T> Ty;
   typedef typename Ty::T2 T2;
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   const int P2 = a.P2;
   const int padG = 3 * P2 * P2;
   T2* sG = (T2*)lds_m2l;
-  T2* sA = sG + padG;
+  T2* sA = sG + padG + 1;  // sG[padG]: a zero read by lanes with no table entry
   int* sCol = (int*)(sA + NT * a.nRsP);    // [4 nKB]: column offset | k3' parity << 20 | valid << 21
 
   // Block -> (level, tile).  The coarse levels come first and keep the hardware's
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   }
   const M2LLevel& L = a.lev[li];
   const int r = blockIdx.y, split = blockIdx.z;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
   int t = tile;
   const int X0 = t % L.tiles_x;
   t /= L.tiles_x;
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     sA[e].x = 0;
     sA[e].y = 0;
   }
-  for (int e = tid; e < padG; e += 256) {
+  for (int e = tid; e <= padG; e += 256) {
     sG[e].x = 0;
     sG[e].y = 0;
   }
@@ -160,6 +161,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     }
   }
   AC accR[TW], accI[TW];
+  const bool last_ok = w + 4 * (TW - 1) < ntile;  // wave-uniform
 #pragma unroll
   for (int j = 0; j < TW; ++j) {
     accR[j] = AC{0, 0, 0, 0};
@@ -231,36 +233,44 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
               }
             }
             __syncthreads();
-            const int kb1 = min(a.nKB, a.kpb * (ph + 1));
-            for (int kb = a.kpb * ph; kb < kb1; ++kb) {
+            const int kb0 = a.kpb * ph, kb1 = min(a.nKB, a.kpb * (ph + 1));
+            // operands of block kb: B from the staged moments, A gathered from the table
+            // (sG[padG] = 0 where the lane has no entry); those of kb + 1 are loaded while
+            // the MFMAs of kb run
+            auto load = [&](int kb, T2& b0, T2& b1, T2 (&g)[TW]) {
               const int kp = 4 * kb + krow;
               const int ci = sCol[kp];
               const bool cvalid = (ci >> 21) & 1;
               const int co = ci & 0xFFFFF;
-              const T2 bv0 = sA[col * a.nRsP + kp - kbase];
-              const T2 bv1 = NCB == 2 ? sA[(16 + col) * a.nRsP + kp - kbase] : bv0;
-              T2 gv[TW];
+              b0 = sA[col * a.nRsP + kp - kbase];
+              b1 = NCB == 2 ? sA[(16 + col) * a.nRsP + kp - kbase] : b0;
 #pragma unroll
-              for (int j = 0; j < TW; ++j) {
-                gv[j].x = 0;
-                gv[j].y = 0;
-                if (rowo[j] >= 0 && cvalid) gv[j] = sG[rowo[j] + co];
-              }
-              // independent MFMAs between the two updates of each accumulator
+              for (int j = 0; j < TW; ++j) g[j] = sG[(rowo[j] >= 0 && cvalid) ? rowo[j] + co : padG];
+            };
+            T2 bv0, bv1, gv[TW];
+            if (kb0 < kb1) load(kb0, bv0, bv1, gv);
+            for (int kb = kb0; kb < kb1; ++kb) {
+              T2 nb0, nb1, ngv[TW];
+              if (kb + 1 < kb1) load(kb + 1, nb0, nb1, ngv);
+              // independent MFMAs between the two updates of each accumulator; only the
+              // wave's last tile can be missing (ntile > 4 (TW - 1)), a uniform test
 #pragma unroll
               for (int j = 0; j < TW; ++j)
-                if (w + 4 * j < ntile) {
+                if (EX || j < TW - 1 || last_ok) {
                   const T2 b = tcb[j] ? bv1 : bv0;
                   accR[j] = Ty::mfma(gv[j].x, b.x, accR[j]);
                   accI[j] = Ty::mfma(gv[j].x, b.y, accI[j]);
                 }
 #pragma unroll
               for (int j = 0; j < TW; ++j)
-                if (w + 4 * j < ntile) {
+                if (EX || j < TW - 1 || last_ok) {
                   const T2 b = tcb[j] ? bv1 : bv0;
                   accR[j] = Ty::mfma(-gv[j].y, b.y, accR[j]);
                   accI[j] = Ty::mfma(gv[j].y, b.x, accI[j]);
                 }
+              bv0 = nb0, bv1 = nb1;
+#pragma unroll
+              for (int j = 0; j < TW; ++j) gv[j] = ngv[j];
             }
           }
         }
@@ -292,7 +302,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
 // are loaded into registers (at most PG table entries and PM moments per thread)
 // while offset o is contracted, and written to LDS after it.  One staging phase
 // (all source moments at once).
-template <int TW, int NCB, int PG, int PM>
+template <int TW, int NCB, int PG, int PM, bool EX>
 __global__ __launch_bounds__(256) void k_m2l_pipe(M2LArgs a) {
   typedef float2 T2;
   typedef f4 AC;
@@ -301,7 +311,7 @@ __global__ __launch_bounds__(256) void k_m2l_pipe(M2LArgs a) {
   const int P2 = a.P2;
   const int padG = 3 * P2 * P2;
   T2* sG = (T2*)lds_m2l;
-  T2* sA = sG + padG;
+  T2* sA = sG + padG + 1;  // sG[padG]: a zero read by lanes with no table entry
   int* sCol = (int*)(sA + NT * a.nRsP);
   int* sOff = sCol + 4 * a.nKB;  // [2 * 216]: pass | (dx + 3) << 1 | (dy + 3) << 4 | (dz + 3) << 7
   __shared__ int sNoff;
@@ -321,7 +331,7 @@ __global__ __launch_bounds__(256) void k_m2l_pipe(M2LArgs a) {
   }
   const M2LLevel& L = a.lev[li];
   const int r = blockIdx.y, split = blockIdx.z;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
   int t = tile;
   const int X0 = t % L.tiles_x;
   t /= L.tiles_x;
@@ -336,7 +346,7 @@ __global__ __launch_bounds__(256) void k_m2l_pipe(M2LArgs a) {
   }
   const float2* alpha = L.a32 + (int64_t)r * L.rhs_stride;
   for (int e = tid; e < NT * a.nRsP; e += 256) sA[e] = make_float2(0.0f, 0.0f);
-  for (int e = tid; e < padG; e += 256) sG[e] = make_float2(0.0f, 0.0f);
+  for (int e = tid; e <= padG; e += 256) sG[e] = make_float2(0.0f, 0.0f);
   for (int e = tid; e < 4 * a.nKB; e += 256) {
     int v = 0;
     if (e < a.nR) {
@@ -389,6 +399,7 @@ __global__ __launch_bounds__(256) void k_m2l_pipe(M2LArgs a) {
     }
   }
   AC accR[TW], accI[TW];
+  const bool last_ok = w + 4 * (TW - 1) < ntile;  // wave-uniform
 #pragma unroll
   for (int j = 0; j < TW; ++j) {
     accR[j] = AC{0, 0, 0, 0};
@@ -452,33 +463,38 @@ __global__ __launch_bounds__(256) void k_m2l_pipe(M2LArgs a) {
       if (mslot[i] >= 0) sA[(mslot[i] >> 16) * a.nRsP + (mslot[i] & 0xFFFF)] = mreg[i];
     __syncthreads();
     if (o + 1 < noff) fetch(o + 1);
-    for (int kb = 0; kb < a.nKB; ++kb) {
+    auto load = [&](int kb, T2& b0, T2& b1, T2 (&g)[TW]) {
       const int kp = 4 * kb + krow;
       const int ci = sCol[kp];
       const bool cvalid = (ci >> 21) & 1;
       const int co = ci & 0xFFFFF;
-      const T2 bv0 = sA[col * a.nRsP + kp];
-      const T2 bv1 = NCB == 2 ? sA[(16 + col) * a.nRsP + kp] : bv0;
-      T2 gv[TW];
+      b0 = sA[col * a.nRsP + kp];
+      b1 = NCB == 2 ? sA[(16 + col) * a.nRsP + kp] : b0;
 #pragma unroll
-      for (int j = 0; j < TW; ++j) {
-        gv[j] = make_float2(0.0f, 0.0f);
-        if (rowo[j] >= 0 && cvalid) gv[j] = sG[rowo[j] + co];
-      }
+      for (int j = 0; j < TW; ++j) g[j] = sG[(rowo[j] >= 0 && cvalid) ? rowo[j] + co : padG];
+    };
+    T2 bv0, bv1, gv[TW];
+    load(0, bv0, bv1, gv);
+    for (int kb = 0; kb < a.nKB; ++kb) {
+      T2 nb0, nb1, ngv[TW];
+      if (kb + 1 < a.nKB) load(kb + 1, nb0, nb1, ngv);
 #pragma unroll
       for (int j = 0; j < TW; ++j)
-        if (w + 4 * j < ntile) {
+        if (EX || j < TW - 1 || last_ok) {
           const T2 b = tcb[j] ? bv1 : bv0;
           accR[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[j].x, b.x, accR[j], 0, 0, 0);
           accI[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[j].x, b.y, accI[j], 0, 0, 0);
         }
 #pragma unroll
       for (int j = 0; j < TW; ++j)
-        if (w + 4 * j < ntile) {
+        if (EX || j < TW - 1 || last_ok) {
           const T2 b = tcb[j] ? bv1 : bv0;
           accR[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-gv[j].y, b.y, accR[j], 0, 0, 0);
           accI[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[j].y, b.x, accI[j], 0, 0, 0);
         }
+      bv0 = nb0, bv1 = nb1;
+#pragma unroll
+      for (int j = 0; j < TW; ++j) gv[j] = ngv[j];
     }
   }
   double2* beta = L.b + (int64_t)split * L.split_stride + (int64_t)r * L.rhs_stride;
@@ -518,7 +534,7 @@ static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
     const int kpb = (a.nKB + kph - 1) / kph;
     int rs = 4 * kpb;
     while (rs % 16 != 1) ++rs;
-    return std::make_pair((size_t)3 * a.P2 * a.P2 * sizeof(T2) + (size_t)16 * NCB * rs * sizeof(T2) +
+    return std::make_pair(((size_t)3 * a.P2 * a.P2 + 1) * sizeof(T2) + (size_t)16 * NCB * rs * sizeof(T2) +
                               4 * (size_t)a.nKB * sizeof(int), rs);
   };
   a.kph = (lds_of(1).first > 80 * 1024 && lds_of(2).first <= 80 * 1024) ? 2 : 1;
@@ -526,6 +542,7 @@ static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
   const size_t lds = lds_of(a.kph).first;
   a.nRsP = lds_of(a.kph).second;
   const int TW = (a.nRB * NCB + 3) / 4;
+  const bool ex = 4 * TW == a.nRB * NCB;
   if (a.nsplit < 1) a.nsplit = 1;
   dim3 grid(total, nrhs, a.nsplit), block(256);
   void (*fn)(M2LArgs) = nullptr;
@@ -535,12 +552,16 @@ static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
     const int need_g = (a.nG + 255) / 256, need_m = (16 * NCB * 4 * a.nKB + 255) / 256;
     const int cfg = (need_g <= 4 && need_m <= 12) ? 0 : (need_g <= 8 && need_m <= 16) ? 1 : -1;
     if (cfg >= 0) {
-      void (*fp[2][6])(M2LArgs) = {
-          {k_m2l_pipe<1, NCB, 4, 12>, k_m2l_pipe<2, NCB, 4, 12>, k_m2l_pipe<3, NCB, 4, 12>,
-           k_m2l_pipe<4, NCB, 4, 12>, k_m2l_pipe<5, NCB, 4, 12>, k_m2l_pipe<6, NCB, 4, 12>},
-          {k_m2l_pipe<1, NCB, 8, 16>, k_m2l_pipe<2, NCB, 8, 16>, k_m2l_pipe<3, NCB, 8, 16>,
-           k_m2l_pipe<4, NCB, 8, 16>, k_m2l_pipe<5, NCB, 8, 16>, k_m2l_pipe<6, NCB, 8, 16>}};
-      fn = fp[cfg][TW - 1];
+      void (*fp[2][2][6])(M2LArgs) = {
+          {{k_m2l_pipe<1, NCB, 4, 12, false>, k_m2l_pipe<2, NCB, 4, 12, false>, k_m2l_pipe<3, NCB, 4, 12, false>,
+            k_m2l_pipe<4, NCB, 4, 12, false>, k_m2l_pipe<5, NCB, 4, 12, false>, k_m2l_pipe<6, NCB, 4, 12, false>},
+           {k_m2l_pipe<1, NCB, 8, 16, false>, k_m2l_pipe<2, NCB, 8, 16, false>, k_m2l_pipe<3, NCB, 8, 16, false>,
+            k_m2l_pipe<4, NCB, 8, 16, false>, k_m2l_pipe<5, NCB, 8, 16, false>, k_m2l_pipe<6, NCB, 8, 16, false>}},
+          {{k_m2l_pipe<1, NCB, 4, 12, true>, k_m2l_pipe<2, NCB, 4, 12, true>, k_m2l_pipe<3, NCB, 4, 12, true>,
+            k_m2l_pipe<4, NCB, 4, 12, true>, k_m2l_pipe<5, NCB, 4, 12, true>, k_m2l_pipe<6, NCB, 4, 12, true>},
+           {k_m2l_pipe<1, NCB, 8, 16, true>, k_m2l_pipe<2, NCB, 8, 16, true>, k_m2l_pipe<3, NCB, 8, 16, true>,
+            k_m2l_pipe<4, NCB, 8, 16, true>, k_m2l_pipe<5, NCB, 8, 16, true>, k_m2l_pipe<6, NCB, 8, 16, true>}}};
+      fn = fp[ex ? 1 : 0][cfg][TW - 1];
       const size_t lds_p = lds + sizeof(int) * 2 * 216;
       hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_p);
       if (e != hipSuccess) return e;
@@ -549,16 +570,16 @@ static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
     }
   }
   switch (TW) {
-    case 1: fn = k_m2l<T, 1, NCB>; break;
-    case 2: fn = k_m2l<T, 2, NCB>; break;
-    case 3: fn = k_m2l<T, 3, NCB>; break;
-    case 4: fn = k_m2l<T, 4, NCB>; break;
-    case 5: fn = k_m2l<T, 5, NCB>; break;
-    case 6: fn = k_m2l<T, 6, NCB>; break;
-    case 7: fn = k_m2l<T, 7, NCB>; break;
-    case 8: fn = k_m2l<T, 8, NCB>; break;
-    case 9: fn = k_m2l<T, 9, NCB>; break;
-    case 10: fn = k_m2l<T, 10, NCB>; break;
+    case 1: fn = ex ? k_m2l<T, 1, NCB, true> : k_m2l<T, 1, NCB, false>; break;
+    case 2: fn = ex ? k_m2l<T, 2, NCB, true> : k_m2l<T, 2, NCB, false>; break;
+    case 3: fn = ex ? k_m2l<T, 3, NCB, true> : k_m2l<T, 3, NCB, false>; break;
+    case 4: fn = ex ? k_m2l<T, 4, NCB, true> : k_m2l<T, 4, NCB, false>; break;
+    case 5: fn = ex ? k_m2l<T, 5, NCB, true> : k_m2l<T, 5, NCB, false>; break;
+    case 6: fn = ex ? k_m2l<T, 6, NCB, true> : k_m2l<T, 6, NCB, false>; break;
+    case 7: fn = ex ? k_m2l<T, 7, NCB, true> : k_m2l<T, 7, NCB, false>; break;
+    case 8: fn = ex ? k_m2l<T, 8, NCB, true> : k_m2l<T, 8, NCB, false>; break;
+    case 9: fn = ex ? k_m2l<T, 9, NCB, true> : k_m2l<T, 9, NCB, false>; break;
+    case 10: fn = ex ? k_m2l<T, 10, NCB, true> : k_m2l<T, 10, NCB, false>; break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -572,7 +593,7 @@ static hipError_t launch_t(const M2LArgs& a, int nrhs, hipStream_t s) {
   typedef typename M2LTypes<T>::T2 T2;
   // 32 targets per workgroup when the widest level is wide enough and two
   // workgroups still fit in the LDS of a CU; 16 otherwise.
-  const size_t lds2 = (size_t)3 * a.P2 * a.P2 * sizeof(T2) + (size_t)32 * a.nRs * sizeof(T2);
+  const size_t lds2 = ((size_t)3 * a.P2 * a.P2 + 1) * sizeof(T2) + (size_t)32 * a.nRs * sizeof(T2);
   const int tw2 = (a.nRB * 2 + 3) / 4;
   const bool fit2 = lds2 <= 150 * 1024 && tw2 <= 10;
   if (a.ncb == 2 && fit2) return launch_t2<T, 2>(a, nrhs, s);
@@ -623,7 +644,7 @@ __global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
   }
   const M2LCrossLevel& L = a.lev[li];
   const int r = blockIdx.y, split = blockIdx.z;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
   int t = tile;
   const int X0 = t % L.tiles_x;
   t /= L.tiles_x;
@@ -777,6 +798,7 @@ static hipError_t launch_cross_t2(const M2LCrossArgs& a0, int nrhs, hipStream_t 
   const size_t lds = (size_t)4 * a.P2 * a.P2 * sizeof(T2) + (size_t)16 * NCB * a.nRs * sizeof(T2) +
                      4 * (size_t)a.nKB * sizeof(int);
   const int TW = (a.nRB * NCB + 3) / 4;
+  const bool ex = 4 * TW == a.nRB * NCB;
   if (a.nsplit < 1) a.nsplit = 1;
   dim3 grid(total, nrhs, a.nsplit), block(256);
   void (*fn)(M2LCrossArgs) = nullptr;
