@@ -6,6 +6,8 @@
 // (r - c)/h).  Multi-indices are stored in the graded order of mi_index().
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fmm_kernels.hpp"
 #include "kernels.hpp"
 
@@ -1171,12 +1173,14 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float
   for (int leaf = blockIdx.x; leaf < nb * nb * nb; leaf += gridDim.x) {
     const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
     const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
-    for (int c0 = 0; c0 < cnt; c0 += TP) {
-      float tx[T], ty[T], tz[T], qri[T], qii[T], accr[T], acci[T];
-      bool act[T];
+    // one pass over the neighbourhood for 64 TT targets from c0 on
+    auto pass = [&](auto tt, int c0) {
+      constexpr int TT = decltype(tt)::value;
+      float tx[TT], ty[TT], tz[TT], qri[TT], qii[TT], accr[TT], acci[TT];
+      bool act[TT];
       const int tbase = start + c0 + lane;  // target index of slot k: tbase + 64 k
 #pragma unroll
-      for (int k = 0; k < T; ++k) {
+      for (int k = 0; k < TT; ++k) {
         const int c = c0 + 64 * k + lane;
         act[k] = c < cnt;
         const int64_t i = start + (act[k] ? c : 0);
@@ -1226,12 +1230,12 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float
           const int mu = __builtin_amdgcn_readfirstlane(m8);
           if (rg == 0) {
             for (int t = 0; t < mu; t += 8)
-              p2p_sym8<T, false>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap,
+              p2p_sym8<TT, false>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap,
                                  a, accr, acci, psw[w], dps[w], nl[w]);
             continue;
           }
           for (int t = 0; t < mu; t += 8)
-            p2p_sym8<T, true>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap, a,
+            p2p_sym8<TT, true>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap, a,
                               accr, acci, psw[w], dps[w], nl[w]);
           wave_lds_sync();
           for (int e = lane; e < m; e += 64) {
@@ -1255,11 +1259,11 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float
       if (NW > 1) {
         // the waves' target sums, added in wave order
 #pragma unroll
-        for (int k = 0; k < T; ++k) tacc[w][64 * k + lane] = make_float2(accr[k], acci[k]);
+        for (int k = 0; k < TT; ++k) tacc[w][64 * k + lane] = make_float2(accr[k], acci[k]);
         __syncthreads();
         if (w == 0) {
 #pragma unroll
-          for (int k = 0; k < T; ++k) {
+          for (int k = 0; k < TT; ++k) {
             accr[k] = tacc[0][64 * k + lane].x, acci[k] = tacc[0][64 * k + lane].y;
             for (int ww = 1; ww < NW; ++ww) accr[k] += tacc[ww][64 * k + lane].x, acci[k] += tacc[ww][64 * k + lane].y;
           }
@@ -1268,9 +1272,16 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float
       }
       if (w == 0)
 #pragma unroll
-        for (int k = 0; k < T; ++k)
+        for (int k = 0; k < TT; ++k)
           if (act[k])
             a.phi[(int64_t)r * a.n + tbase + 64 * k] = make_double2((double)accr[k] * kap, (double)acci[k] * kap);
+    };
+    // passes of 64 T targets; a last one of at most 64 with one target per lane
+    for (int c0 = 0; c0 < cnt; c0 += TP) {
+      if (T > 1 && cnt - c0 <= 64)
+        pass(std::integral_constant<int, 1>(), c0);
+      else
+        pass(std::integral_constant<int, T>(), c0);
     }
   }
 }
