@@ -1345,7 +1345,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     const int H = g.depth;
     PassArgs a = pass_args(g);
     a.nbox_dim = 1 << H, a.h = g.side / (1 << H), a.beta = g.beta[H], a.rhs_stride = g.nbox[H] * h->nC;
-    const size_t lds = sizeof(double2) * h->nC + sizeof(double) * 64 * 3 * (p + 1) + sizeof(int) * h->nC;
+    const size_t lds = sizeof(double2) * h->nC;
     hipLaunchKernelGGL(k_l2p, dim3((unsigned)g.nbox[H], nrhs), dim3(64), lds, s, a);
     HIPCHK(h, hipGetLastError());
   }

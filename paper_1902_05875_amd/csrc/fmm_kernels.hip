@@ -647,38 +647,48 @@ __global__ __launch_bounds__(64) void k_l2l(PassArgs a) {
 // L2P (Sec. 3.1, Eq. taylorexplocxclfree): phi_i = sum_k beta^_k u_i^k.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_l2p(PassArgs a) {
+  // the leaf's local coefficients in nested order (k1, then k2, then k3 ascending), so
+  // that each particle walks them with running products of its scaled offsets
   extern __shared__ double lds_l2p[];
-  const int P1 = a.p + 1;
-  double2* sb = (double2*)lds_l2p;              // [nC]
-  double* pw = lds_l2p + 2 * a.nC;               // [64][3][P1]
-  int* smi = (int*)(pw + 64 * 3 * P1);           // [nC]
+  double2* sb = (double2*)lds_l2p;  // [nC]
+  const int p = a.p;
   const int leaf = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
   const int nb = a.nbox_dim;
   const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
   const double h = a.h;
   const double cx = a.lo[0] + (ix + 0.5) * h, cy = a.lo[1] + (iy + 0.5) * h, cz = a.lo[2] + (iz + 0.5) * h;
   const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
+  if (cnt == 0) return;
   const double2* bt = a.beta + (int64_t)r * a.rhs_stride + (int64_t)leaf * a.nC;
-  for (int k = tid; k < a.nC; k += 64) sb[k] = bt[k], smi[k] = a.mi[k];
+  for (int k = tid; k < a.nC; k += 64) {
+    const int pk = a.mi[k];
+    const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
+    int pos = 0;  // tuples before (k1, k2, k3) in nested order
+    for (int t = 0; t < k1; ++t) pos += ((p - t + 1) * (p - t + 2)) / 2;
+    for (int t = 0; t < k2; ++t) pos += p - k1 - t + 1;
+    sb[pos + k3] = bt[k];
+  }
   __syncthreads();
   for (int c0 = 0; c0 < cnt; c0 += 64) {
-    if (c0 + tid < cnt) {
-      const int64_t i = start + c0 + tid;
-      const double u[3] = {(a.xs[i] - cx) / h, (a.xs[a.n + i] - cy) / h, (a.xs[2 * a.n + i] - cz) / h};
-      for (int d = 0; d < 3; ++d) {
-        double v = 1.0;
-        for (int e = 0; e < P1; ++e) pw[(tid * 3 + d) * P1 + e] = v, v *= u[d];
+    if (c0 + tid >= cnt) break;
+    const int64_t i = start + c0 + tid;
+    const double ux = (a.xs[i] - cx) / h, uy = (a.xs[a.n + i] - cy) / h, uz = (a.xs[2 * a.n + i] - cz) / h;
+    double sx = 0.0, sy = 0.0, wx = 1.0;
+    int e = 0;
+    for (int k1 = 0; k1 <= p; ++k1) {
+      double wxy = wx;
+      for (int k2 = 0; k2 <= p - k1; ++k2) {
+        double w = wxy;
+        for (int k3 = 0; k3 <= p - k1 - k2; ++k3, ++e) {
+          sx = fma(sb[e].x, w, sx);
+          sy = fma(sb[e].y, w, sy);
+          w *= uz;
+        }
+        wxy *= uy;
       }
-      dc s = {0, 0};
-      for (int k = 0; k < a.nC; ++k) {
-        const int pk = smi[k];
-        const double w = pw[(tid * 3 + 0) * P1 + (pk & 255)] * pw[(tid * 3 + 1) * P1 + ((pk >> 8) & 255)] *
-                         pw[(tid * 3 + 2) * P1 + (pk >> 16)];
-        s.x += sb[k].x * w;
-        s.y += sb[k].y * w;
-      }
-      a.phi[(int64_t)r * a.n + i] = make_double2(s.x, s.y);
+      wx *= ux;
     }
+    a.phi[(int64_t)r * a.n + i] = make_double2(sx, sy);
   }
 }
 
