@@ -35,8 +35,8 @@ PEAK = {"fp64": 78.6, "fp32": 157.3}  # TFLOP/s, MI355X published: dense MFMA, a
 # algorithmic flops of one P2P pair: distance (3 sub, 3 mul, 2 add), 1/r and r (2),
 # k r (1), sin and cos (2), exp(ikr)/r (2), complex multiply-add into the sum (8)
 P2P_FLOPS_PER_PAIR = 23
-# FP32 with one charge vector: the pairs of particles in different leaves are evaluated
-# once and applied both ways: distance 8, 1/r and r 2, k r 1, sin and cos 2, e^{ikr}/r 2,
+# one charge vector: the pairs of particles in different leaves are evaluated once and
+# applied both ways: distance 8, 1/r and r 2, k r 1, sin and cos 2, e^{ikr}/r 2,
 # two complex multiply-adds 16
 P2P_FLOPS_PER_SYM_PAIR = 31
 SHAPES = {"c1": "uniform unit cube centred (0,0,-0.6)", "c2": "uniform unit cube centred (0,0,-0.6)",
@@ -125,8 +125,9 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload, surrogate=
 
 
 def _p2p_sym(precision, q):
-    """Whether the near field ran the kernel that evaluates each cross-leaf pair once."""
-    return precision == "fp32" and (q.ndim == 1 or q.shape[0] == 1)
+    """Whether the near field ran the kernel that evaluates each cross-leaf pair once
+    (the default with one charge vector, in both precisions)."""
+    return q.ndim == 1 or q.shape[0] == 1
 
 
 def _p2p_flops(st, precision, q):
@@ -163,7 +164,7 @@ def roofline(head):
     n_launch = max(1, head["n_groups"])
     if head.get("p2p_sym"):
         same = head["p2p_pairs_same_leaf"]
-        what = (f"k_p2p_sym<float> + k_p2p_sym_gather (vector ALU), {n_launch} launch(es)/step, avg "
+        what = (f"k_p2p_sym<{'float' if prec == 'fp32' else 'double'}> + k_p2p_sym_gather (vector ALU), {n_launch} launch(es)/step, avg "
                 f"{ph['p2p'] / n_launch:.3f} ms; {P2P_FLOPS_PER_SYM_PAIR} flop x {(head['p2p_pairs'] - same) // 2} "
                 f"cross-leaf pairs (each once) + {P2P_FLOPS_PER_PAIR} flop x {same} same-leaf ordered pairs")
     else:

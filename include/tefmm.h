@@ -89,11 +89,12 @@ typedef struct {
   int n_rhs_max;
   double dcim_T1_cross;
   int m2l_tile;       /* M2L targets per workgroup / 16: 1 or 2 (0 = automatic; tefmm_autotune measures) */
-  int p2p_targets;    /* near field, TEFMM_MIXED_FP32 with one charge vector: each pair of particles
-                         in different leaves is evaluated once and its kernel value applied in both
-                         directions, with 1, 2 or 4 targets per GPU lane (0 = 2 above a mean
-                         leaf occupancy of 96, else 1); -1 = every ordered pair evaluated on its
-                         own (the FP64 and several-vector kernel) */
+  int p2p_targets;    /* near field with one charge vector: 1, 2 or 4 = each pair of particles in
+                         different leaves is evaluated once and its kernel value applied in both
+                         directions, with that many targets per GPU lane (FP64: 1 or 2, 4 is
+                         rejected); 0 = that kernel with 2 targets per lane above a mean leaf
+                         occupancy of 96, else 1; -1 = every ordered pair evaluated on its own
+                         (also the kernel for several charge vectors) */
 } tefmm_options;
 
 /* Timings (ms, measured with HIP events; averages over the evaluations since

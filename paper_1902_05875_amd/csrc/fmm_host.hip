@@ -103,8 +103,8 @@ struct tefmm_ctx {
   std::vector<Group> groups;
   // evaluate buffers
   double2 *d_q = nullptr, *d_phi = nullptr, *d_phi_near = nullptr;
-  // source-side sums of the symmetric FP32 near field: [13 slots][n]
-  float2* d_part = nullptr;
+  // source-side sums of the symmetric near field: [13 slots][n] float2 (FP32) or double2 (FP64)
+  void* d_part = nullptr;
   // the near field runs on a second stream beside the far field (fork/join by events)
   hipStream_t s2 = nullptr;
   hipEvent_t e_fork = nullptr, e_join = nullptr;
@@ -187,6 +187,9 @@ static void free_geometry(tefmm_t h) {
   h->nrhs_alloc = 0;
   h->ready = false;
 }
+
+// Whether the near field with one charge vector takes the symmetric kernel.
+static bool sym_near(const tefmm_options& o) { return o.p2p_targets >= 0; }
 
 static int build_constant_tables(tefmm_t h) {
   const int p = h->opt.p;
@@ -305,7 +308,8 @@ extern "C" int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefm
       !(o.dcim_T1 > 0) || !(o.dcim_T1_cross > 0) || !(o.dcim_svd_tol > 0) || o.m2l_tile < 0 || o.m2l_tile > 2 ||
       !(o.interface_eps >= 0) || o.n_rhs_max < 1 ||
       !(o.p2p_targets == -1 || o.p2p_targets == 0 || o.p2p_targets == 1 || o.p2p_targets == 2 ||
-        o.p2p_targets == 4)) {
+        o.p2p_targets == 4) ||
+      (o.precision == TEFMM_FP64 && o.p2p_targets == 4)) {
     delete h;
     return TEFMM_ERR_INVALID_ARG;
   }
@@ -1065,8 +1069,8 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
   HIPCHK(h, hipMalloc(&h->d_phi, sizeof(double2) * h->n * nrhs));
   HIPCHK(h, hipMalloc(&h->d_phi_near, sizeof(double2) * h->n * nrhs));
   dfree(h->d_part);
-  if (h->opt.precision == TEFMM_MIXED_FP32 && h->opt.p2p_targets >= 0)
-    HIPCHK(h, hipMalloc(&h->d_part, sizeof(float2) * 13 * h->n));
+  if (sym_near(h->opt))
+    HIPCHK(h, hipMalloc(&h->d_part, (h->opt.precision == TEFMM_FP64 ? sizeof(double2) : sizeof(float2)) * 13 * h->n));
   for (auto& g : h->groups) {
     g.alpha.assign(g.depth + 1, nullptr);
     g.beta.assign(g.depth + 1, nullptr);
@@ -1177,18 +1181,25 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     const bool wide = g.count > 96 * g.nbox[g.depth];  // mean leaf occupancy above 96
     // several charge vectors share each pair kernel, 8 per block
     const bool multi = nrhs > 1;
-    if (fp32 && !multi && h->d_part) {
+    if (!multi && h->d_part) {
       // each pair of particles in different leaves once (k_p2p_sym); targets per
       // lane unless set: 2 above a mean leaf occupancy of 96 (4 holds more
       // registers than it saves work), else 1
       int tpl = h->opt.p2p_targets;
       if (tpl == 0) tpl = wide ? 2 : 1;
-      void (*fs)(PassArgs, int, float2*) =
-          tpl == 1 ? k_p2p_sym<1, 4> : tpl == 2 ? k_p2p_sym<2, 4> : k_p2p_sym<4, 4>;
-      hipLaunchKernelGGL(fs, dim3((unsigned)g.nbox[g.depth], 1), dim3(256), 0, sn, a, 1, h->d_part);
-      HIPCHK(h, hipGetLastError());
-      hipLaunchKernelGGL(k_p2p_sym_gather, dim3((unsigned)g.nbox[g.depth], 1), dim3(128), 0, sn, a, 1,
-                         (const float2*)h->d_part);
+      const dim3 grid((unsigned)g.nbox[g.depth], 1);
+      if (fp32) {
+        void (*fs)(PassArgs, int, float2*) =
+            tpl == 1 ? k_p2p_sym<float, 1, 4> : tpl == 2 ? k_p2p_sym<float, 2, 4> : k_p2p_sym<float, 4, 4>;
+        hipLaunchKernelGGL(fs, grid, dim3(256), 0, sn, a, 1, (float2*)h->d_part);
+        HIPCHK(h, hipGetLastError());
+        hipLaunchKernelGGL(k_p2p_sym_gather<float2>, grid, dim3(128), 0, sn, a, 1, (const float2*)h->d_part);
+      } else {
+        void (*fs)(PassArgs, int, double2*) = tpl == 1 ? k_p2p_sym<double, 1, 4> : k_p2p_sym<double, 2, 4>;
+        hipLaunchKernelGGL(fs, grid, dim3(256), 0, sn, a, 1, (double2*)h->d_part);
+        HIPCHK(h, hipGetLastError());
+        hipLaunchKernelGGL(k_p2p_sym_gather<double2>, grid, dim3(128), 0, sn, a, 1, (const double2*)h->d_part);
+      }
       HIPCHK(h, hipGetLastError());
       continue;
     }

@@ -1149,6 +1149,101 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
   }
 }
 
+// FP64 form of p2p_sym8 on physical coordinates.  FP64 differences keep their
+// digits, so no near-pair fix-up is needed; in the leaf's own pass (not SYM) a
+// pair at distance 0 (a particle with itself) gets weight 0.  SMALL: k r <= pi/4
+// for every pair of the 3 x 3 x 3 leaf block, so sin and cos need no reduction.
+// The two 32-bit halves of a double go through the lane swaps one after the other.
+__device__ __forceinline__ void swap32_f64(double& x, double& y) {
+  const unsigned long long xb = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long yb = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)xb, (unsigned)yb, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ void swap16_f64(double& x, double& y) {
+  const unsigned long long xb = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long yb = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)xb, (unsigned)yb, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(xb >> 32), (unsigned)(yb >> 32), false, false);
+  x = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
+template <int T, bool SYM, bool SMALL>
+__device__ __forceinline__ void p2p_sym8_f64(int t, const double (&tx)[T], const double (&ty)[T],
+                                             const double (&tz)[T], const double (&qri)[T], const double (&qii)[T],
+                                             const double4* s4, const double* sqi, double k, double (&accr)[T],
+                                             double (&acci)[T], double* psw) {
+  const int lane = threadIdx.x & 63;
+  typedef double d16v __attribute__((ext_vector_type(16)));
+  d16v c;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const double4 sp = s4[t + v];
+    const double qr = sp.w, qi = sqi[t + v];
+    double cr = 0.0, ci = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < T; ++kk) {
+      const double dx = tx[kk] - sp.x, dy = ty[kk] - sp.y, dz = tz[kk] - sp.z;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const bool self = !SYM && !(r2 > 0);
+      const double ri = rsqrt_f64(self ? 1.0 : r2);
+      double sn, cs;
+      if (SMALL)
+        sincos_f64_small(k * (r2 * ri), &sn, &cs);
+      else
+        sincos_f64(k * (r2 * ri), &sn, &cs);
+      const double er = cs * ri, ei = sn * ri;
+      const double wr = self ? 0.0 : qr, wi = self ? 0.0 : qi;
+      accr[kk] = fma(wr, er, fma(-wi, ei, accr[kk]));
+      acci[kk] = fma(wr, ei, fma(wi, er, acci[kk]));
+      if (SYM) {
+        cr = fma(qri[kk], er, fma(-qii[kk], ei, cr));
+        ci = fma(qri[kk], ei, fma(qii[kk], er, ci));
+      }
+    }
+    // the sums are kept with this source (else the compiler defers them and holds
+    // every pair value)
+    if (SYM) {
+      asm volatile("" : "+v"(cr), "+v"(ci));
+      c[2 * v] = cr, c[2 * v + 1] = ci;
+    }
+#pragma unroll
+    for (int kk = 0; kk < T; ++kk) asm volatile("" : "+v"(accr[kk]), "+v"(acci[kk]));
+  }
+  if (SYM) {
+    // the transposing butterfly of p2p_sym8: lane 4 u ends with the wave's sum of value u
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      double x = c[kk], y = c[kk + 8];
+      swap32_f64(x, y);
+      c[kk] = x + y;
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      double x = c[kk], y = c[kk + 4];
+      swap16_f64(x, y);
+      c[kk] = x + y;
+    }
+#pragma unroll
+    for (int st = 2; st < 4; ++st) {
+      const int m = 32 >> st, H = 8 >> st;
+      const bool hi = (lane & m) != 0;
+#pragma unroll
+      for (int kk = 0; kk < H; ++kk) {
+        const double send = hi ? c[kk] : c[kk + H];
+        const double keep = hi ? c[kk + H] : c[kk];
+        c[kk] = keep + __shfl_xor(send, m);
+      }
+    }
+    double tot = c[0] + __shfl_xor(c[0], 2);
+    tot += __shfl_xor(tot, 1);
+    if (!(lane & 3)) psw[2 * t + (lane >> 2)] = tot;
+  }
+}
+
 // Within a wave, data written to LDS by some lanes and read by others: the
 // wave's LDS operations complete in order, so only the compiler must keep them
 // in order.
@@ -1162,22 +1257,29 @@ __device__ __forceinline__ void wave_lds_sync() {
 // sources; chunk c of the pass, counted over the ranges, goes to wave c mod NW).
 // Each wave stages, evaluates and writes its chunks' source-side sums on its
 // own; at the end of the pass the waves' target sums are added in wave order.
-template <int T, int NW>
-__global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float2* part) {
+template <typename R, int T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, typename SymTypes<R>::R2* part) {
+  typedef typename SymTypes<R>::R4 R4;
+  typedef typename SymTypes<R>::R2 R2;
+  constexpr bool F32 = std::is_same<R, float>::value;
   constexpr int SC = 128, TP = 64 * T;  // sources per chunk, targets per pass
-  __shared__ float4 s4[NW][SC];  // scaled x, y, z and the real part of the charge
-  __shared__ float sqi[NW][SC];
-  __shared__ int sidx[NW][SC];
-  __shared__ float psw[NW][2 * SC];
-  __shared__ float dps[NW][2 * SC];  // near-singular corrections of the source-side sums
-  __shared__ int nl[NW][4 * 64];     // near-pair masks of the current eight sources, per step and lane
-  __shared__ float2 tacc[NW > 1 ? NW : 1][NW > 1 ? TP : 1];
+  __shared__ R4 s4[NW][SC];  // x, y, z (FP32: scaled) and the real part of the charge
+  __shared__ R sqi[NW][SC];
+  __shared__ R psw[NW][2 * SC];
+  // FP32 only: source indices, near-singular corrections of the source-side sums and
+  // near-pair masks of the current eight sources (per step and lane)
+  __shared__ int sidx[F32 ? NW : 1][F32 ? SC : 1];
+  __shared__ float dps[F32 ? NW : 1][F32 ? 2 * SC : 1];
+  __shared__ int nl[F32 ? NW : 1][F32 ? 4 * 64 : 1];
+  __shared__ R2 tacc[NW > 1 ? NW : 1][NW > 1 ? TP : 1];
   const int r = blockIdx.y, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int nb = a.nbox_dim;
-  // coordinates in units of 2 pi / k (see pair_kernel)
-  const double kap = a.k / 6.283185307179586477;
+  // FP32: coordinates in units of 2 pi / k (see pair_kernel); FP64: physical
+  const double kap = F32 ? a.k / 6.283185307179586477 : 1.0;
   const float rns2 = (float)(0.0025 * a.h * a.h * kap * kap);
   const float eps2 = 1e-8f * rns2;
+  // FP64: k r <= pi/4 over the 3 x 3 x 3 leaf block (its longest pair: 2 sqrt(3) h)
+  const bool small = a.k * 3.4641016151377546 * a.h <= 0.78539816339744831;
   const double2* q = a.q + (int64_t)r * a.n;
   // leaves blockIdx.x, blockIdx.x + gridDim.x, ...
   for (int leaf = blockIdx.x; leaf < nb * nb * nb; leaf += gridDim.x) {
@@ -1186,7 +1288,7 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float
     // one pass over the neighbourhood for 64 TT targets from c0 on
     auto pass = [&](auto tt, int c0) {
       constexpr int TT = decltype(tt)::value;
-      float tx[TT], ty[TT], tz[TT], qri[TT], qii[TT], accr[TT], acci[TT];
+      R tx[TT], ty[TT], tz[TT], qri[TT], qii[TT], accr[TT], acci[TT];
       bool act[TT];
       const int tbase = start + c0 + lane;  // target index of slot k: tbase + 64 k
 #pragma unroll
@@ -1194,12 +1296,12 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float
         const int c = c0 + 64 * k + lane;
         act[k] = c < cnt;
         const int64_t i = start + (act[k] ? c : 0);
-        tx[k] = (float)((a.xs[i] - a.lo[0]) * kap);
-        ty[k] = (float)((a.xs[a.n + i] - a.lo[1]) * kap);
-        tz[k] = (float)((a.xs[2 * a.n + i] - a.lo[2]) * kap);
+        tx[k] = (R)((a.xs[i] - a.lo[0]) * kap);
+        ty[k] = (R)((a.xs[a.n + i] - a.lo[1]) * kap);
+        tz[k] = (R)((a.xs[2 * a.n + i] - a.lo[2]) * kap);
         const double2 qv = act[k] ? q[i] : make_double2(0.0, 0.0);
-        qri[k] = (float)qv.x, qii[k] = (float)qv.y;
-        accr[k] = 0.0f, acci[k] = 0.0f;
+        qri[k] = (R)qv.x, qii[k] = (R)qv.y;
+        accr[k] = 0, acci[k] = 0;
       }
       int chunk = 0;
       // ranges: 0 = the leaf itself, 1..4 = forward columns, 5 = the leaf above
@@ -1230,27 +1332,50 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float
             // eight-aligned tail: copies of the first source with charge 0 and no index
             const int64_t j = s0 + (e < m ? e : 0);
             const double2 qj = q[j];
-            s4[w][e] = make_float4((float)((a.xs[j] - a.lo[0]) * kap), (float)((a.xs[a.n + j] - a.lo[1]) * kap),
-                                   (float)((a.xs[2 * a.n + j] - a.lo[2]) * kap), e < m ? (float)qj.x : 0.0f);
-            sqi[w][e] = e < m ? (float)qj.y : 0.0f;
-            sidx[w][e] = e < m ? (int)j : -1;
-            dps[w][2 * e] = 0.0f, dps[w][2 * e + 1] = 0.0f;
+            R4 sv;
+            sv.x = (R)((a.xs[j] - a.lo[0]) * kap), sv.y = (R)((a.xs[a.n + j] - a.lo[1]) * kap);
+            sv.z = (R)((a.xs[2 * a.n + j] - a.lo[2]) * kap), sv.w = e < m ? (R)qj.x : (R)0;
+            s4[w][e] = sv;
+            sqi[w][e] = e < m ? (R)qj.y : (R)0;
+            if constexpr (F32) {
+              sidx[w][e] = e < m ? (int)j : -1;
+              dps[w][2 * e] = 0.0f, dps[w][2 * e + 1] = 0.0f;
+            }
           }
           wave_lds_sync();
           const int mu = __builtin_amdgcn_readfirstlane(m8);
-          if (rg == 0) {
+          if constexpr (F32) {
+            if (rg == 0) {
+              for (int t = 0; t < mu; t += 8)
+                p2p_sym8<TT, false>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2,
+                                    kap * kap, a, accr, acci, psw[w], dps[w], nl[w]);
+              continue;
+            }
             for (int t = 0; t < mu; t += 8)
-              p2p_sym8<TT, false>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap,
-                                 a, accr, acci, psw[w], dps[w], nl[w]);
-            continue;
+              p2p_sym8<TT, true>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2,
+                                 kap * kap, a, accr, acci, psw[w], dps[w], nl[w]);
+          } else {
+            if (rg == 0) {
+              for (int t = 0; t < mu; t += 8) {
+                if (small)
+                  p2p_sym8_f64<TT, false, true>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
+                else
+                  p2p_sym8_f64<TT, false, false>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
+              }
+              continue;
+            }
+            for (int t = 0; t < mu; t += 8) {
+              if (small)
+                p2p_sym8_f64<TT, true, true>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
+              else
+                p2p_sym8_f64<TT, true, false>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
+            }
           }
-          for (int t = 0; t < mu; t += 8)
-            p2p_sym8<TT, true>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2, kap * kap, a,
-                              accr, acci, psw[w], dps[w], nl[w]);
           wave_lds_sync();
           for (int e = lane; e < m; e += 64) {
             const int64_t j = s0 + e;
-            const float pr = psw[w][2 * e] + dps[w][2 * e], pi = psw[w][2 * e + 1] + dps[w][2 * e + 1];
+            R pr = psw[w][2 * e], pi = psw[w][2 * e + 1];
+            if constexpr (F32) pr += dps[w][2 * e], pi += dps[w][2 * e + 1];
             int slot = 12;
             if (rg < 5) {
               const int zj = (z1 > iz && j >= a.leaf_start[kl + iz + 1]) ? iz + 1
@@ -1258,18 +1383,17 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float
                                                                            : iz - 1;
               slot = 3 * (rg - 1) + (zj - iz + 1);
             }
-            float2* dst = part + ((int64_t)slot * nrhs + r) * a.n + j;
-            if (c0 == 0)
-              *dst = make_float2(pr, pi);
-            else
-              *dst = make_float2(dst->x + pr, dst->y + pi);
+            R2* dst = part + ((int64_t)slot * nrhs + r) * a.n + j;
+            R2 v;
+            v.x = c0 == 0 ? pr : dst->x + pr, v.y = c0 == 0 ? pi : dst->y + pi;
+            *dst = v;
           }
         }
       }
       if (NW > 1) {
         // the waves' target sums, added in wave order
 #pragma unroll
-        for (int k = 0; k < TT; ++k) tacc[w][64 * k + lane] = make_float2(accr[k], acci[k]);
+        for (int k = 0; k < TT; ++k) tacc[w][64 * k + lane].x = accr[k], tacc[w][64 * k + lane].y = acci[k];
         __syncthreads();
         if (w == 0) {
 #pragma unroll
@@ -1299,7 +1423,9 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, float
 // Adds to each particle of leaf B the source-side sums that its backward
 // neighbours A = B - o (o in the forward half, A inside the grid and not empty)
 // left in part, in slot order (see k_p2p_sym).
-__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, const float2* part) {
+template <typename R2>
+__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, const R2* part) {
+  typedef decltype(R2::x) R;
   const int leaf = blockIdx.x, r = blockIdx.y;
   const int nb = a.nbox_dim;
   const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
@@ -1313,13 +1439,14 @@ __global__ void k_p2p_sym_gather(PassArgs a, int nrhs, const float2* part) {
     if (ax < 0 || ay < 0 || az < 0 || ax >= nb || ay >= nb || az >= nb) continue;
     if (a.leaf_count[a.leaf_base + ((int64_t)ax * nb + ay) * nb + az] > 0) have |= 1u << slot;
   }
-  const double kap = a.k / 6.283185307179586477;
+  // FP32 sums are in the scaled units of k_p2p_sym
+  const double kap = sizeof(R) == 4 ? a.k / 6.283185307179586477 : 1.0;
   for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
     const int64_t j = start + c;
-    float sr = 0.0f, si = 0.0f;
+    R sr = 0, si = 0;
     for (int slot = 0; slot < 13; ++slot)
       if ((have >> slot) & 1) {
-        const float2 v = part[((int64_t)slot * nrhs + r) * a.n + j];
+        const R2 v = part[((int64_t)slot * nrhs + r) * a.n + j];
         sr += v.x, si += v.y;
       }
     double2* o = a.phi + (int64_t)r * a.n + j;
@@ -1327,12 +1454,13 @@ __global__ void k_p2p_sym_gather(PassArgs a, int nrhs, const float2* part) {
   }
 }
 
-template __global__ void k_p2p_sym<1, 1>(PassArgs, int, float2*);
-template __global__ void k_p2p_sym<2, 1>(PassArgs, int, float2*);
-template __global__ void k_p2p_sym<4, 1>(PassArgs, int, float2*);
-template __global__ void k_p2p_sym<1, 4>(PassArgs, int, float2*);
-template __global__ void k_p2p_sym<2, 4>(PassArgs, int, float2*);
-template __global__ void k_p2p_sym<4, 4>(PassArgs, int, float2*);
+template __global__ void k_p2p_sym<float, 1, 4>(PassArgs, int, float2*);
+template __global__ void k_p2p_sym<float, 2, 4>(PassArgs, int, float2*);
+template __global__ void k_p2p_sym<float, 4, 4>(PassArgs, int, float2*);
+template __global__ void k_p2p_sym<double, 1, 4>(PassArgs, int, double2*);
+template __global__ void k_p2p_sym<double, 2, 4>(PassArgs, int, double2*);
+template __global__ void k_p2p_sym_gather<float2>(PassArgs, int, const float2*);
+template __global__ void k_p2p_sym_gather<double2>(PassArgs, int, const double2*);
 
 template __global__ void k_p2p<double, 64, 1>(PassArgs, int);
 template __global__ void k_p2p<float, 64, 1>(PassArgs, int);

@@ -173,9 +173,22 @@ __global__ void k_l2l(PassArgs a);
 __global__ void k_l2p(PassArgs a);
 template <typename T, int BS, int RB>
 __global__ void k_p2p(PassArgs a, int nrhs);
-template <int T, int NW>
-__global__ void k_p2p_sym(PassArgs a, int nrhs, float2* part);
-__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, const float2* part);
+template <typename R>
+struct SymTypes;
+template <>
+struct SymTypes<float> {
+  typedef float4 R4;
+  typedef float2 R2;
+};
+template <>
+struct SymTypes<double> {
+  typedef double4 R4;
+  typedef double2 R2;
+};
+template <typename R, int T, int NW>
+__global__ void k_p2p_sym(PassArgs a, int nrhs, typename SymTypes<R>::R2* part);
+template <typename R2>
+__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, const R2* part);
 
 // M2L launcher (picks the row-block instantiation for nRB).
 hipError_t launch_m2l(const M2LArgs& a, int nrhs, bool fp32, hipStream_t s);

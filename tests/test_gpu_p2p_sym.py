@@ -1,6 +1,7 @@
-"""Near field in FP32 with each pair of particles in different leaves evaluated once
-(the kernel value applied in both directions) against the kernel that evaluates every
-ordered pair on its own: same pairs, same FP32 arithmetic per pair, different sums."""
+"""Near field with each pair of particles in different leaves evaluated once (the
+kernel value applied in both directions) against the kernel that evaluates every
+ordered pair on its own: same pairs, same arithmetic per pair, different sums.  FP32
+(the default near field of the mixed mode) and FP64 (chosen by p2p_targets > 0)."""
 import numpy as np
 import pytest
 
@@ -71,3 +72,43 @@ def test_sym_deterministic():
     b = f.evaluate(qt).cpu().numpy()
     f.close()
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("depth", [2, 3, 5])
+@pytest.mark.parametrize("tpl", [1, 2])
+def test_sym_fp64_matches_one_sided(tpl, depth):
+    """FP64: only the order of the sums differs.  Depths 2 and 3 take the sine and
+    cosine with argument reduction (k r above pi/4 inside a leaf block), depth 5 the
+    short series (about one particle per leaf: mostly one-target passes)."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c2", n=30_000)
+    xyz, q, _ = inputs.with_close_pairs(xyz, q, 16, 1e-6, seed=7)
+    a, sa = _run(xyz, q, p=8, precision="fp64", depth=depth, p2p_targets=tpl)
+    b, sb = _run(xyz, q, p=8, precision="fp64", depth=depth, p2p_targets=-1)
+    e = _rel(a, b)
+    print(f"FP64 symmetric ({tpl} targets/lane) vs one-sided, depth {depth}: rel diff {e:.3e}")
+    assert sa["p2p_pairs"] == sb["p2p_pairs"]
+    assert e < 1e-12
+
+
+def test_sym_fp64_empty_leaves_and_deterministic():
+    """FP64 on two clusters (mostly empty leaves), and a bitwise-equal repeat."""
+    import torch
+    from paper_1902_05875_amd import api
+    rng = np.random.default_rng(12)
+    n = 5000
+    c1 = np.array([-0.3, -0.3, -0.9]) + rng.uniform(-0.05, 0.05, size=(n, 3))
+    c2 = np.array([0.3, 0.3, -0.3]) + rng.uniform(-0.05, 0.05, size=(n, 3))
+    xyz = np.concatenate([c1, c2])
+    q = rng.uniform(-1, 1, 2 * n) + 1j * rng.uniform(-1, 1, 2 * n)
+    b, _ = _run(xyz, q, p=8, precision="fp64", depth=4, p2p_targets=-1)
+    f = api.TEFMM(K3, D3, p=8, precision="fp64", depth=4, p2p_targets=2)
+    f.set_particles(xyz)
+    qt = torch.from_numpy(q).cuda()
+    a1 = f.evaluate(qt).cpu().numpy()
+    a2 = f.evaluate(qt).cpu().numpy()
+    f.close()
+    e = _rel(a1, b)
+    print(f"FP64 clusters, symmetric vs one-sided: rel diff {e:.3e}")
+    assert e < 1e-12
+    assert np.array_equal(a1, a2)
