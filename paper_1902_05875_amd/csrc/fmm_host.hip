@@ -1169,52 +1169,64 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
   HIPCHK(h, hipStreamIsCapturing(s, &cap));
   const bool fork = cap == hipStreamCaptureStatusNone;
   hipStream_t sn = fork ? h->s2 : s;
-  if (fork) {
-    HIPCHK(h, hipEventRecord(h->e_fork, s));
-    HIPCHK(h, hipStreamWaitEvent(h->s2, h->e_fork, 0));
-  }
-  if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + 8], sn));
-  for (auto& g : h->groups) {
-    PassArgs a = pass_args(g);
-    a.phi = h->d_phi_near;
-    a.nbox_dim = 1 << g.depth, a.h = g.side / (1 << g.depth);
-    const bool wide = g.count > 96 * g.nbox[g.depth];  // mean leaf occupancy above 96
-    // several charge vectors share each pair kernel, 8 per block
-    const bool multi = nrhs > 1;
-    if (!multi && h->d_part) {
-      // each pair of particles in different leaves once (k_p2p_sym); targets per
-      // lane unless set: 2 above a mean leaf occupancy of 96 (4 holds more
-      // registers than it saves work), else 1
-      int tpl = h->opt.p2p_targets;
-      if (tpl == 0) tpl = wide ? 2 : 1;
-      const dim3 grid((unsigned)g.nbox[g.depth], 1);
-      if (fp32) {
-        void (*fs)(PassArgs, int, float2*) =
-            tpl == 1 ? k_p2p_sym<float, 1, 4> : tpl == 2 ? k_p2p_sym<float, 2, 4> : k_p2p_sym<float, 4, 4>;
-        hipLaunchKernelGGL(fs, grid, dim3(256), 0, sn, a, 1, (float2*)h->d_part);
-        HIPCHK(h, hipGetLastError());
-        hipLaunchKernelGGL(k_p2p_sym_gather<float2>, grid, dim3(128), 0, sn, a, 1, (const float2*)h->d_part);
-      } else {
-        void (*fs)(PassArgs, int, double2*) = tpl == 1 ? k_p2p_sym<double, 1, 4> : k_p2p_sym<double, 2, 4>;
-        hipLaunchKernelGGL(fs, grid, dim3(256), 0, sn, a, 1, (double2*)h->d_part);
-        HIPCHK(h, hipGetLastError());
-        hipLaunchKernelGGL(k_p2p_sym_gather<double2>, grid, dim3(128), 0, sn, a, 1, (const double2*)h->d_part);
-      }
-      HIPCHK(h, hipGetLastError());
-      continue;
+  // In FP64 the far field is the longer branch: the upward pass (P2M, M2M and the
+  // reduced moments; short, narrow kernels) then runs alone, and the near field
+  // starts beside the M2L.  In FP32 the near field is the longer branch and starts
+  // at once.
+  const bool late = fork && !fp32;
+  auto near_field = [&]() -> int {
+    if (fork) {
+      HIPCHK(h, hipEventRecord(h->e_fork, s));
+      HIPCHK(h, hipStreamWaitEvent(h->s2, h->e_fork, 0));
     }
-    const dim3 grid((unsigned)g.nbox[g.depth], multi ? (nrhs + 7) / 8 : 1);
-    void (*fn)(PassArgs, int) = nullptr;
-    if (fp32)
-      fn = wide ? (multi ? k_p2p<float, 256, 8> : k_p2p<float, 256, 1>) : (multi ? k_p2p<float, 64, 8> : k_p2p<float, 64, 1>);
-    else
-      fn = wide ? (multi ? k_p2p<double, 256, 8> : k_p2p<double, 256, 1>)
-                : (multi ? k_p2p<double, 64, 8> : k_p2p<double, 64, 1>);
-    hipLaunchKernelGGL(fn, grid, dim3(wide ? 256 : 64), 0, sn, a, nrhs);
-    HIPCHK(h, hipGetLastError());
+    if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + 8], sn));
+    for (auto& g : h->groups) {
+      PassArgs a = pass_args(g);
+      a.phi = h->d_phi_near;
+      a.nbox_dim = 1 << g.depth, a.h = g.side / (1 << g.depth);
+      const bool wide = g.count > 96 * g.nbox[g.depth];  // mean leaf occupancy above 96
+      // several charge vectors share each pair kernel, 8 per block
+      const bool multi = nrhs > 1;
+      if (!multi && h->d_part) {
+        // each pair of particles in different leaves once (k_p2p_sym); targets per
+        // lane unless set: 2 above a mean leaf occupancy of 96 (4 holds more
+        // registers than it saves work), else 1
+        int tpl = h->opt.p2p_targets;
+        if (tpl == 0) tpl = wide ? 2 : 1;
+        const dim3 grid((unsigned)g.nbox[g.depth], 1);
+        if (fp32) {
+          void (*fs)(PassArgs, int, float2*) =
+              tpl == 1 ? k_p2p_sym<float, 1, 4> : tpl == 2 ? k_p2p_sym<float, 2, 4> : k_p2p_sym<float, 4, 4>;
+          hipLaunchKernelGGL(fs, grid, dim3(256), 0, sn, a, 1, (float2*)h->d_part);
+          HIPCHK(h, hipGetLastError());
+          hipLaunchKernelGGL(k_p2p_sym_gather<float2>, grid, dim3(128), 0, sn, a, 1, (const float2*)h->d_part);
+        } else {
+          void (*fs)(PassArgs, int, double2*) = tpl == 1 ? k_p2p_sym<double, 1, 4> : k_p2p_sym<double, 2, 4>;
+          hipLaunchKernelGGL(fs, grid, dim3(256), 0, sn, a, 1, (double2*)h->d_part);
+          HIPCHK(h, hipGetLastError());
+          hipLaunchKernelGGL(k_p2p_sym_gather<double2>, grid, dim3(128), 0, sn, a, 1, (const double2*)h->d_part);
+        }
+        HIPCHK(h, hipGetLastError());
+        continue;
+      }
+      const dim3 grid((unsigned)g.nbox[g.depth], multi ? (nrhs + 7) / 8 : 1);
+      void (*fn)(PassArgs, int) = nullptr;
+      if (fp32)
+        fn = wide ? (multi ? k_p2p<float, 256, 8> : k_p2p<float, 256, 1>) : (multi ? k_p2p<float, 64, 8> : k_p2p<float, 64, 1>);
+      else
+        fn = wide ? (multi ? k_p2p<double, 256, 8> : k_p2p<double, 256, 1>)
+                  : (multi ? k_p2p<double, 64, 8> : k_p2p<double, 64, 1>);
+      hipLaunchKernelGGL(fn, grid, dim3(wide ? 256 : 64), 0, sn, a, nrhs);
+      HIPCHK(h, hipGetLastError());
+    }
+    if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + 6], sn));
+    if (fork) HIPCHK(h, hipEventRecord(h->e_join, h->s2));
+    return TEFMM_OK;
+  };
+  if (!late) {
+    const int rc = near_field();
+    if (rc != TEFMM_OK) return rc;
   }
-  if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + 6], sn));
-  if (fork) HIPCHK(h, hipEventRecord(h->e_join, h->s2));
   // P2M at the leaves (Sec. 3.1)
   for (auto& g : h->groups) {
     const int H = g.depth;
@@ -1233,9 +1245,15 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       PassArgs a = pass_args(g);
       a.nbox_dim = 1 << lev, a.alpha = g.alpha[lev], a.rhs_stride = g.nbox[lev] * h->nC;
       a.alpha_child = g.alpha[lev + 1], a.rhs_stride_child = g.nbox[lev + 1] * h->nC;
-      const size_t lds = (3 * sizeof(double2) + sizeof(int)) * h->nC;
+      // waves per parent (each takes 8 / W children).  Beside the near field, one: a
+      // wider workgroup waits for a CU with that many free wave slots, which the near
+      // field's workgroups hold until they end.  Otherwise the most whose two buffers
+      // fit 96 KiB.
+      int W = fork && !late ? 1 : 8;
+      while (W > 1 && (size_t)W * 2 * sizeof(double2) * h->nC + sizeof(int) * h->nC > 96 * 1024) W /= 2;
+      const size_t lds = (size_t)W * 2 * sizeof(double2) * h->nC + sizeof(int) * h->nC;
       HIPCHK(h, hipFuncSetAttribute((const void*)k_m2m, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      hipLaunchKernelGGL(k_m2m, dim3((unsigned)g.nbox[lev], nrhs), dim3(64), lds, s, a);
+      hipLaunchKernelGGL(k_m2m, dim3((unsigned)g.nbox[lev], nrhs), dim3(64 * W), lds, s, a);
       HIPCHK(h, hipGetLastError());
     }
     for (int lev = 2; lev <= H; ++lev) {
@@ -1254,6 +1272,10 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     }
   }
   EVREC(2);
+  if (late) {
+    const int rc = near_field();
+    if (rc != TEFMM_OK) return rc;
+  }
   // M2L: same-layer families, then cross-layer components (Algorithm 2).  The groups'
   // launches are independent (each writes only its own locals): with several groups
   // and no graph capture, group gi > 0 runs on stream sg[gi], joined before the locals.

@@ -546,54 +546,87 @@ __device__ __forceinline__ double quarter_pow(int neg, int e) {
   return (neg && (e & 1)) ? -v : v;
 }
 
-// One pass along axis `ax` of the upward shift: dst[k] = sum_{j <= k_ax} C(k_ax, j)
-// delta^{k_ax - j} 2^{-j} src[k with k_ax -> j]
-__device__ __forceinline__ void m2m_pass(const double2* src, double2* dst, const int* mi, int nC, int ax,
-                                         int neg, int tid) {
-  for (int k = tid; k < nC; k += 64) {
-    const int pk = mi[k];
-    int c[3] = {pk & 255, (pk >> 8) & 255, pk >> 16};
-    const int ka = c[ax];
-    double sx = 0, sy = 0;
-    for (int j = 0; j <= ka; ++j) {
-      c[ax] = j;
-      const double f = c_binom[ka][j] * quarter_pow(neg, ka - j) * ldexp(1.0, -j);
-      const double2 v = src[mi_index(c[0], c[1], c[2])];
-      sx += f * v.x;
-      sy += f * v.y;
-    }
-    dst[k] = make_double2(sx, sy);
+// One coefficient of a pass along axis `ax` of the upward shift: for the packed
+// multi-index pk = k, sum_{j <= k_ax} C(k_ax, j) delta^{k_ax - j} 2^{-j} src[k with k_ax -> j]
+__device__ __forceinline__ double2 m2m_coef(const double2* src, int pk, int ax, int neg) {
+  int c[3] = {pk & 255, (pk >> 8) & 255, pk >> 16};
+  const int ka = c[ax];
+  double sx = 0, sy = 0;
+  for (int j = 0; j <= ka; ++j) {
+    c[ax] = j;
+    const double f = c_binom[ka][j] * quarter_pow(neg, ka - j) * ldexp(1.0, -j);
+    const double2 v = src[mi_index(c[0], c[1], c[2])];
+    sx += f * v.x;
+    sy += f * v.y;
   }
+  return make_double2(sx, sy);
 }
 
-__global__ __launch_bounds__(64) void k_m2m(PassArgs a) {
-  extern __shared__ double2 lds_m2m[];  // buf0, buf1, acc: 3 x nC
-  double2* b0 = lds_m2m;
-  double2* b1 = b0 + a.nC;
-  double2* acc = b1 + a.nC;
-  int* smi = (int*)(acc + a.nC);
-  const int pb = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+// Within a wave, data written to LDS by some lanes and read by others: the
+// wave's LDS operations complete in order, so only the compiler must keep them
+// in order.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One workgroup per parent box; its W waves (W = blockDim.x / 64, a divisor of 8)
+// take the children c = w, w + W, ...  Each wave stages its child in its own two
+// LDS buffers, applies the x and y passes there and the z pass straight into its
+// registers (coefficient lane + 64 i in slot i), so the waves need no barrier until
+// their sums of shifted children are added, in wave order.
+constexpr int M2M_SLOTS = 16;  // coefficients per lane: nC <= 1024 (p <= 16)
+__global__ __launch_bounds__(512) void k_m2m(PassArgs a) {
+  extern __shared__ double2 lds_m2m[];  // per wave 2 x nC, then the multi-indices (nC ints)
+  const int W = blockDim.x >> 6, nC = a.nC;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  double2* b0 = lds_m2m + (size_t)w * 2 * nC;
+  double2* b1 = b0 + nC;
+  int* smi = (int*)(lds_m2m + (size_t)W * 2 * nC);
+  const int pb = blockIdx.x, r = blockIdx.y;
   const int np = a.nbox_dim;  // parent grid size
   const int nc = 2 * np;
   const int ix = pb / (np * np), iy = (pb / np) % np, iz = pb % np;
   const double2* ch = a.alpha_child + (int64_t)r * a.rhs_stride_child;
-  for (int k = tid; k < a.nC; k += 64) acc[k] = make_double2(0.0, 0.0), smi[k] = a.mi[k];
-  for (int c = 0; c < 8; ++c) {
+  for (int k = tid; k < nC; k += blockDim.x) smi[k] = a.mi[k];
+  __syncthreads();
+  double sx[M2M_SLOTS], sy[M2M_SLOTS];
+#pragma unroll
+  for (int i = 0; i < M2M_SLOTS; ++i) sx[i] = 0.0, sy[i] = 0.0;
+  for (int c = w; c < 8; c += W) {
     const int cx = (c >> 2) & 1, cy = (c >> 1) & 1, cz = c & 1;
     const int64_t cb = ((int64_t)(2 * ix + cx) * nc + (2 * iy + cy)) * nc + (2 * iz + cz);
-    __syncthreads();
-    for (int k = tid; k < a.nC; k += 64) b0[k] = ch[cb * a.nC + k];
-    __syncthreads();
-    m2m_pass(b0, b1, smi, a.nC, 0, !cx, tid);
-    __syncthreads();
-    m2m_pass(b1, b0, smi, a.nC, 1, !cy, tid);
-    __syncthreads();
-    m2m_pass(b0, b1, smi, a.nC, 2, !cz, tid);
-    __syncthreads();
-    for (int k = tid; k < a.nC; k += 64) acc[k] = make_double2(acc[k].x + b1[k].x, acc[k].y + b1[k].y);
+    for (int k = lane; k < nC; k += 64) b0[k] = ch[cb * nC + k];
+    wave_lds_sync();
+    for (int k = lane; k < nC; k += 64) b1[k] = m2m_coef(b0, smi[k], 0, !cx);
+    wave_lds_sync();
+    for (int k = lane; k < nC; k += 64) b0[k] = m2m_coef(b1, smi[k], 1, !cy);
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < M2M_SLOTS; ++i) {
+      const int k = lane + 64 * i;
+      if (k < nC) {
+        const double2 v = m2m_coef(b0, smi[k], 2, !cz);
+        sx[i] += v.x, sy[i] += v.y;
+      }
+    }
+    wave_lds_sync();  // the next child overwrites b0
   }
-  double2* out = a.alpha + (int64_t)r * a.rhs_stride + (int64_t)pb * a.nC;
-  for (int k = tid; k < a.nC; k += 64) out[k] = acc[k];
+#pragma unroll
+  for (int i = 0; i < M2M_SLOTS; ++i) {
+    const int k = lane + 64 * i;
+    if (k < nC) b1[k] = make_double2(sx[i], sy[i]);
+  }
+  __syncthreads();
+  double2* out = a.alpha + (int64_t)r * a.rhs_stride + (int64_t)pb * nC;
+  for (int k = tid; k < nC; k += blockDim.x) {
+    double2 v = lds_m2m[nC + k];
+    for (int ww = 1; ww < W; ++ww) {
+      const double2 u = lds_m2m[(size_t)ww * 2 * nC + nC + k];
+      v.x += u.x, v.y += u.y;
+    }
+    out[k] = v;
+  }
 }
 
 // One pass of the downward shift: dst[k] = 2^{-k_ax} sum_{j >= k_ax} C(j, k_ax) delta^{j - k_ax}
@@ -1242,14 +1275,6 @@ __device__ __forceinline__ void p2p_sym8_f64(int t, const double (&tx)[T], const
     tot += __shfl_xor(tot, 1);
     if (!(lane & 3)) psw[2 * t + (lane >> 2)] = tot;
   }
-}
-
-// Within a wave, data written to LDS by some lanes and read by others: the
-// wave's LDS operations complete in order, so only the compiler must keep them
-// in order.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
 }
 
 // One workgroup per leaf A, T targets per lane: the 64 T targets of a pass are

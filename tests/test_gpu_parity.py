@@ -89,18 +89,27 @@ def test_c2_sampled(p, precision, tol):
 
 
 def test_multi_rhs_matches_single():
-    """Several charge vectors in one evaluate equal separate evaluations (bit-exact work per vector)."""
+    """Several charge vectors in one evaluate equal separate evaluations: bit-exact with
+    the near-field kernel they share (every ordered pair on its own), and to rounding
+    with the default one-vector near field (each cross-leaf pair once, other sum order)."""
     import torch
     from paper_1902_05875_amd import api, inputs
     xyz, q = inputs.workload("c2", n=20_000, n_rhs=3)
-    f = api.TEFMM(K3, D3, p=6)
-    f.set_particles(xyz)
     Q = torch.from_numpy(np.ascontiguousarray(q.T)).cuda()
+    f = api.TEFMM(K3, D3, p=6, p2p_targets=-1)
+    f.set_particles(xyz)
     both = f.evaluate(Q).cpu().numpy()
     for r in range(3):
         one = f.evaluate(Q[r].clone()).cpu().numpy()
         assert np.array_equal(both[r], one)
     f.close()
+    g = api.TEFMM(K3, D3, p=6)
+    g.set_particles(xyz)
+    assert np.array_equal(g.evaluate(Q).cpu().numpy(), both)
+    for r in range(3):
+        one = g.evaluate(Q[r].clone()).cpu().numpy()
+        assert np.linalg.norm(one - both[r]) <= 1e-13 * np.linalg.norm(both[r])
+    g.close()
 
 
 def test_deterministic_repeat():
