@@ -153,19 +153,28 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     const int id = w + 4 * j;
     const int rb = id % a.nRB, cb = id / a.nRB;
     const int k = 16 * rb + col;
-    rowo[j] = -1, tcb[j] = cb;
+    // rows past nR (and missing tiles) gather entry 0: finite, and dropped by the epilogue
+    rowo[j] = 0, tcb[j] = cb;
     if (id < ntile && k < a.nR) {
       const int pk = a.rmi[k];
       const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
       rowo[j] = (k1 * P2 + k2 + k3) * P2 + k3;
     }
   }
-  AC accR[TW], accI[TW];
+  // B operand offset of each tile: column block tcb, target col
+  int boff[TW];
+#pragma unroll
+  for (int j = 0; j < TW; ++j) boff[j] = (16 * tcb[j] + col) * a.nRsP;
+  // FP32: Re G Re a and Im G Im a in accumulators of their own (subtracted at the end:
+  // no negation per step); FP64 negates Im G (its accumulators take twice the registers)
+  constexpr bool F32 = sizeof(T) == 4;
+  AC accR[TW], accI[TW], accN[F32 ? TW : 1];
   const bool last_ok = w + 4 * (TW - 1) < ntile;  // wave-uniform
 #pragma unroll
   for (int j = 0; j < TW; ++j) {
     accR[j] = AC{0, 0, 0, 0};
     accI[j] = AC{0, 0, 0, 0};
+    if (F32) accN[j] = AC{0, 0, 0, 0};
   }
 
   // staging constants: thread's first element, the per-step advance, and the
@@ -180,6 +189,17 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   for (int xi = 0; xi < 4; ++xi)
     tbase[xi] = (((px + 2 * (4 * X0 + xi)) * N + (py + 8 * NCB * Y0)) * N + iz) * a.nR;
   const int tbase_y = 2 * N * a.nR;
+  // Staging by runs: with one phase, E = NT Lp / 256 even and dividing Lp, and nR even,
+  // each thread stages E consecutive entries of one target (loaded two at a time),
+  // with the validity and the Sigma sign of each entry fixed per thread.
+  const int E = (NT * Lp) / 256;
+  const bool runs = a.kph == 1 && (NT * Lp) % 256 == 0 && E % 2 == 0 && E <= 8 && Lp % E == 0 && a.nR % 2 == 0;
+  const int rn = runs ? (tid * E) / Lp : 0, rk = runs ? (tid * E) % Lp : 0;
+  unsigned rvalid = 0, rsign = 0;
+  __syncthreads();  // sCol complete
+  if (runs)
+    for (int i = 0; i < E; ++i)
+      if (rk + i < a.nR) rvalid |= 1u << i, rsign |= (unsigned)((sCol[rk + i] >> 20) & 1) << i;
   for (int pass = 0; pass < 2; ++pass) {
     const T2* table = pass ? (const T2*)Ty::tableS(L) : (const T2*)Ty::tableF(L);
     if (!table) continue;
@@ -207,9 +227,32 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
               const T2* g = table + (int64_t)key * a.nG;
               for (int e = tid; e < a.nG; e += 256) sG[a.gpad[e]] = g[e];
             }
-            // element e = tid + 256 i of the NT x Lp moment block: target n, index kk
-            // (advanced by 256 = q Lp + rem per step, without a division per element)
-            {
+            if (runs) {
+              const bool on = (smask >> rn) & 1;
+              const int64_t at = tbase[rn & 3] + tbase_y * (rn >> 2) + rk + delta;
+              const unsigned neg = mirror ? rsign : 0u;
+              T2* dst = sA + rn * a.nRsP + rk;
+#pragma unroll
+              for (int i = 0; i < 8; i += 2) {
+                if (i >= E) break;
+                T2 v0, v1;
+                v0.x = 0, v0.y = 0, v1.x = 0, v1.y = 0;
+                if (on && ((rvalid >> i) & 1)) {
+                  if (F32) {
+                    const float4 q = *(const float4*)(alpha32 + at + i);
+                    v0.x = (T)q.x, v0.y = (T)q.y, v1.x = (T)q.z, v1.y = (T)q.w;
+                  } else {
+                    const double2 q0 = alpha[at + i], q1 = alpha[at + i + 1];
+                    v0 = Ty::cvt(q0), v1 = Ty::cvt(q1);
+                  }
+                  if ((neg >> i) & 1) v0.x = -v0.x, v0.y = -v0.y;
+                  if ((neg >> (i + 1)) & 1) v1.x = -v1.x, v1.y = -v1.y;
+                }
+                dst[i] = v0, dst[i + 1] = v1;
+              }
+            } else {
+              // element e = tid + 256 i of the NT x Lp moment block: target n, index kk
+              // (advanced by 256 = q Lp + rem per step, without a division per element)
               int n = n0, kl = kk0;
               for (int e = tid; e < NT * Lp; e += 256) {
                 const int kk = kbase + kl;
@@ -237,40 +280,54 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
             // operands of block kb: B from the staged moments, A gathered from the table
             // (sG[padG] = 0 where the lane has no entry); those of kb + 1 are loaded while
             // the MFMAs of kb run
-            auto load = [&](int kb, T2& b0, T2& b1, T2 (&g)[TW]) {
+            // operands of block kb: B from the staged moments (per tile when the wave has
+            // at most two tiles, else the two column blocks and a select), A gathered from the
+            // table; those of the next block are loaded while the MFMAs of this one run (two
+            // register sets used in turn)
+            constexpr bool BT = TW <= 2;
+            auto load = [&](int kb, T2 (&bb)[TW], T2 (&g)[TW]) {
               const int kp = 4 * kb + krow;
-              const int ci = sCol[kp];
-              const bool cvalid = (ci >> 21) & 1;
-              const int co = ci & 0xFFFFF;
-              b0 = sA[col * a.nRsP + kp - kbase];
-              b1 = NCB == 2 ? sA[(16 + col) * a.nRsP + kp - kbase] : b0;
+              // column offset; 0 past nR, where the staged moments are zero
+              const int co = sCol[kp] & 0xFFFFF;
+              if (BT) {
 #pragma unroll
-              for (int j = 0; j < TW; ++j) g[j] = sG[(rowo[j] >= 0 && cvalid) ? rowo[j] + co : padG];
+                for (int j = 0; j < TW; ++j) bb[j] = sA[boff[j] + kp - kbase];
+              } else {
+                bb[0] = sA[col * a.nRsP + kp - kbase];
+                bb[1] = NCB == 2 ? sA[(16 + col) * a.nRsP + kp - kbase] : bb[0];
+              }
+#pragma unroll
+              for (int j = 0; j < TW; ++j) g[j] = sG[rowo[j] + co];
             };
-            T2 bv0, bv1, gv[TW];
-            if (kb0 < kb1) load(kb0, bv0, bv1, gv);
-            for (int kb = kb0; kb < kb1; ++kb) {
-              T2 nb0, nb1, ngv[TW];
-              if (kb + 1 < kb1) load(kb + 1, nb0, nb1, ngv);
+            auto mma = [&](const T2 (&bb)[TW], const T2 (&g)[TW]) {
               // independent MFMAs between the two updates of each accumulator; only the
               // wave's last tile can be missing (ntile > 4 (TW - 1)), a uniform test
 #pragma unroll
               for (int j = 0; j < TW; ++j)
                 if (EX || j < TW - 1 || last_ok) {
-                  const T2 b = tcb[j] ? bv1 : bv0;
-                  accR[j] = Ty::mfma(gv[j].x, b.x, accR[j]);
-                  accI[j] = Ty::mfma(gv[j].x, b.y, accI[j]);
+                  const T2 b = BT ? bb[j] : (tcb[j] ? bb[1] : bb[0]);
+                  accR[j] = Ty::mfma(g[j].x, b.x, accR[j]);
+                  accI[j] = Ty::mfma(g[j].x, b.y, accI[j]);
                 }
 #pragma unroll
               for (int j = 0; j < TW; ++j)
                 if (EX || j < TW - 1 || last_ok) {
-                  const T2 b = tcb[j] ? bv1 : bv0;
-                  accR[j] = Ty::mfma(-gv[j].y, b.y, accR[j]);
-                  accI[j] = Ty::mfma(gv[j].y, b.x, accI[j]);
+                  const T2 b = BT ? bb[j] : (tcb[j] ? bb[1] : bb[0]);
+                  if (F32)
+                    accN[j] = Ty::mfma(g[j].y, b.y, accN[j]);
+                  else
+                    accR[j] = Ty::mfma(-g[j].y, b.y, accR[j]);
+                  accI[j] = Ty::mfma(g[j].y, b.x, accI[j]);
                 }
-              bv0 = nb0, bv1 = nb1;
-#pragma unroll
-              for (int j = 0; j < TW; ++j) gv[j] = ngv[j];
+            };
+            T2 b1[TW], g1[TW], b2[TW], g2[TW];
+            if (kb0 < kb1) load(kb0, b1, g1);
+            for (int kb = kb0; kb < kb1; kb += 2) {
+              if (kb + 1 < kb1) load(kb + 1, b2, g2);
+              mma(b1, g1);
+              if (kb + 1 >= kb1) break;
+              if (kb + 2 < kb1) load(kb + 2, b1, g1);
+              mma(b2, g2);
             }
           }
         }
@@ -291,7 +348,10 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int k = 16 * rb + Ty::row(krow, i);
-      if (k < a.nR) beta[tb * a.nR + k] = make_double2((double)accR[j][i], (double)accI[j][i]);
+      if (k < a.nR) {
+        const double re = F32 ? (double)accR[j][i] - (double)accN[F32 ? j : 0][i] : (double)accR[j][i];
+        beta[tb * a.nR + k] = make_double2(re, (double)accI[j][i]);
+      }
     }
   }
 }
