@@ -356,225 +356,6 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   }
 }
 
-// FP32 M2L with the staging of the next offset overlapped with the contraction
-// of the current one: the workgroup's offsets (the same set and order as in
-// k_m2l) are listed in LDS first; the table entries and moments of offset o + 1
-// are loaded into registers (at most PG table entries and PM moments per thread)
-// while offset o is contracted, and written to LDS after it.  One staging phase
-// (all source moments at once).
-template <int TW, int NCB, int PG, int PM, bool EX>
-__global__ __launch_bounds__(256) void k_m2l_pipe(M2LArgs a) {
-  typedef float2 T2;
-  typedef f4 AC;
-  constexpr int NT = 16 * NCB;
-  extern __shared__ double lds_m2l[];
-  const int P2 = a.P2;
-  const int padG = 3 * P2 * P2;
-  T2* sG = (T2*)lds_m2l;
-  T2* sA = sG + padG + 1;  // sG[padG]: a zero read by lanes with no table entry
-  int* sCol = (int*)(sA + NT * a.nRsP);
-  int* sOff = sCol + 4 * a.nKB;  // [2 * 216]: pass | (dx + 3) << 1 | (dy + 3) << 4 | (dz + 3) << 7
-  __shared__ int sNoff;
-
-  int li = 0, tile = 0;
-  const int widest = a.nlev - 1;
-  if ((int)blockIdx.x < a.tile_start[widest]) {
-    while ((int)blockIdx.x >= a.tile_start[li + 1]) ++li;
-    tile = blockIdx.x - a.tile_start[li];
-  } else {
-    li = widest;
-    const int b = blockIdx.x - a.tile_start[widest];
-    const int nt = a.lev[li].ntiles;
-    const int per = (nt + 7) / 8;
-    tile = (b % 8) * per + b / 8;
-    if (tile >= nt) return;
-  }
-  const M2LLevel& L = a.lev[li];
-  const int r = blockIdx.y, split = blockIdx.z;
-  const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  int t = tile;
-  const int X0 = t % L.tiles_x;
-  t /= L.tiles_x;
-  const int Y0 = t % L.tiles_y;
-  t /= L.tiles_y;
-  const int px = t & 1, py = (t >> 1) & 1, iz = t >> 2;
-  const int N = L.n, pz = iz & 1;
-  unsigned tmask = 0;
-  for (int n = 0; n < NT; ++n) {
-    const int ix = px + 2 * (4 * X0 + (n & 3)), iy = py + 2 * (4 * NCB * Y0 + (n >> 2));
-    if (ix < N && iy < N) tmask |= 1u << n;
-  }
-  const float2* alpha = L.a32 + (int64_t)r * L.rhs_stride;
-  for (int e = tid; e < NT * a.nRsP; e += 256) sA[e] = make_float2(0.0f, 0.0f);
-  for (int e = tid; e <= padG; e += 256) sG[e] = make_float2(0.0f, 0.0f);
-  for (int e = tid; e < 4 * a.nKB; e += 256) {
-    int v = 0;
-    if (e < a.nR) {
-      const int pk = a.rmi[e];
-      const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
-      v = ((k1 * P2 + k2 + k3) * P2 + k3) | ((k3 & 1) << 20) | (1 << 21);
-    }
-    sCol[e] = v;
-  }
-  // the workgroup's offsets, in the order of k_m2l
-  if (tid == 0) {
-    int cnt = 0, ocount = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-      if (!(pass ? L.TS32 : L.Tfd32)) continue;
-      const bool near_ok = pass ? L.near_s : L.near_fd;
-      for (int oz = 0; oz < 6; ++oz) {
-        const int dz = oz - 2 - pz;
-        if (iz + dz < 0 || iz + dz >= N) continue;
-        for (int oy = 0; oy < 6; ++oy) {
-          const int dy = oy - 2 - py;
-          for (int ox = 0; ox < 6; ++ox) {
-            const int dx = ox - 2 - px;
-            const bool nearb = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
-            if (nearb && !(L.leaf && near_ok)) continue;
-            if (!tile_mask<NCB>(N, px, py, X0, Y0, dx, dy)) continue;
-            if ((ocount++) % a.nsplit != split) continue;
-            sOff[cnt++] = pass | ((dx + 3) << 1) | ((dy + 3) << 4) | ((dz + 3) << 7);
-          }
-        }
-      }
-    }
-    sNoff = cnt;
-  }
-  __syncthreads();
-  const int noff = sNoff;
-
-  const int col = lane & 15, krow = lane >> 4;
-  const int ntile = a.nRB * NCB;
-  int rowo[TW], tcb[TW];
-#pragma unroll
-  for (int j = 0; j < TW; ++j) {
-    const int id = w + 4 * j;
-    const int rb = id % a.nRB, cb = id / a.nRB;
-    const int k = 16 * rb + col;
-    rowo[j] = -1, tcb[j] = cb;
-    if (id < ntile && k < a.nR) {
-      const int pk = a.rmi[k];
-      const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
-      rowo[j] = (k1 * P2 + k2 + k3) * P2 + k3;
-    }
-  }
-  AC accR[TW], accI[TW];
-  const bool last_ok = w + 4 * (TW - 1) < ntile;  // wave-uniform
-#pragma unroll
-  for (int j = 0; j < TW; ++j) {
-    accR[j] = AC{0, 0, 0, 0};
-    accI[j] = AC{0, 0, 0, 0};
-  }
-  // this thread's staging slots: table entries e = tid + 256 i, moment elements
-  // e = tid + 256 i of the NT x Lp block (target n, index kk)
-  const int Lp = 4 * a.nKB;
-  int gpos[PG];
-#pragma unroll
-  for (int i = 0; i < PG; ++i) gpos[i] = tid + 256 * i < a.nG ? a.gpad[tid + 256 * i] : -1;
-  int mslot[PM];  // n << 16 | kk, or -1
-  {
-    const int n0 = tid / Lp, kk0 = tid - n0 * Lp;
-    const int step_q = 256 / Lp, step_r = 256 - step_q * Lp;
-    int n = n0, kl = kk0;
-#pragma unroll
-    for (int i = 0; i < PM; ++i) {
-      mslot[i] = (n < NT) ? (n << 16) | kl : -1;
-      n += step_q, kl += step_r;
-      if (kl >= Lp) kl -= Lp, ++n;
-    }
-  }
-  int tbase[4];
-#pragma unroll
-  for (int xi = 0; xi < 4; ++xi)
-    tbase[xi] = (((px + 2 * (4 * X0 + xi)) * N + (py + 8 * NCB * Y0)) * N + iz) * a.nR;
-  const int tbase_y = 2 * N * a.nR;
-
-  T2 greg[PG], mreg[PM];
-  auto fetch = [&](int o) {
-    const int code = sOff[o];
-    const int pass = code & 1, dx = ((code >> 1) & 7) - 3, dy = ((code >> 4) & 7) - 3, dz = ((code >> 7) & 7) - 3;
-    const int key = pass ? ((dx + 3) * 7 + (dy + 3)) * (2 * N - 1) + (2 * iz + dz)
-                         : ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
-    const T2* g = (pass ? L.TS32 : L.Tfd32) + (int64_t)key * a.nG;
-#pragma unroll
-    for (int i = 0; i < PG; ++i) greg[i] = gpos[i] >= 0 ? g[tid + 256 * i] : make_float2(0.0f, 0.0f);
-    const unsigned smask = tile_mask<NCB>(N, px, py, X0, Y0, dx, dy);
-    const int delta = ((dx * N + dy) * N + dz) * a.nR;
-#pragma unroll
-    for (int i = 0; i < PM; ++i) {
-      T2 v = make_float2(0.0f, 0.0f);
-      const int n = mslot[i] >> 16, kk = mslot[i] & 0xFFFF;
-      if (mslot[i] >= 0 && kk < a.nR && ((smask >> n) & 1)) {
-        v = alpha[tbase[n & 3] + tbase_y * (n >> 2) + kk + delta];
-        // Sigma family: source derivatives in z enter with a plus sign
-        if (pass && ((sCol[kk] >> 20) & 1)) v.x = -v.x, v.y = -v.y;
-      }
-      mreg[i] = v;
-    }
-  };
-  if (noff > 0) fetch(0);
-  for (int o = 0; o < noff; ++o) {
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < PG; ++i)
-      if (gpos[i] >= 0) sG[gpos[i]] = greg[i];
-#pragma unroll
-    for (int i = 0; i < PM; ++i)
-      if (mslot[i] >= 0) sA[(mslot[i] >> 16) * a.nRsP + (mslot[i] & 0xFFFF)] = mreg[i];
-    __syncthreads();
-    if (o + 1 < noff) fetch(o + 1);
-    auto load = [&](int kb, T2& b0, T2& b1, T2 (&g)[TW]) {
-      const int kp = 4 * kb + krow;
-      const int ci = sCol[kp];
-      const bool cvalid = (ci >> 21) & 1;
-      const int co = ci & 0xFFFFF;
-      b0 = sA[col * a.nRsP + kp];
-      b1 = NCB == 2 ? sA[(16 + col) * a.nRsP + kp] : b0;
-#pragma unroll
-      for (int j = 0; j < TW; ++j) g[j] = sG[(rowo[j] >= 0 && cvalid) ? rowo[j] + co : padG];
-    };
-    T2 bv0, bv1, gv[TW];
-    load(0, bv0, bv1, gv);
-    for (int kb = 0; kb < a.nKB; ++kb) {
-      T2 nb0, nb1, ngv[TW];
-      if (kb + 1 < a.nKB) load(kb + 1, nb0, nb1, ngv);
-#pragma unroll
-      for (int j = 0; j < TW; ++j)
-        if (EX || j < TW - 1 || last_ok) {
-          const T2 b = tcb[j] ? bv1 : bv0;
-          accR[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[j].x, b.x, accR[j], 0, 0, 0);
-          accI[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[j].x, b.y, accI[j], 0, 0, 0);
-        }
-#pragma unroll
-      for (int j = 0; j < TW; ++j)
-        if (EX || j < TW - 1 || last_ok) {
-          const T2 b = tcb[j] ? bv1 : bv0;
-          accR[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-gv[j].y, b.y, accR[j], 0, 0, 0);
-          accI[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[j].y, b.x, accI[j], 0, 0, 0);
-        }
-      bv0 = nb0, bv1 = nb1;
-#pragma unroll
-      for (int j = 0; j < TW; ++j) gv[j] = ngv[j];
-    }
-  }
-  double2* beta = L.b + (int64_t)split * L.split_stride + (int64_t)r * L.rhs_stride;
-#pragma unroll
-  for (int j = 0; j < TW; ++j) {
-    const int id = w + 4 * j;
-    if (id >= ntile) continue;
-    const int rb = id % a.nRB, cb = id / a.nRB;
-    const int n = 16 * cb + col;
-    if (!((tmask >> n) & 1)) continue;
-    const int ix = px + 2 * (4 * X0 + (n & 3)), iy = py + 2 * (4 * NCB * Y0 + (n >> 2));
-    const int64_t tb = ((int64_t)ix * N + iy) * N + iz;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int k = 16 * rb + M2LTypes<float>::row(krow, i);
-      if (k < a.nR) beta[tb * a.nR + k] = make_double2((double)accR[j][i], (double)accI[j][i]);
-    }
-  }
-}
-
 template <typename T, int NCB>
 static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
   typedef typename M2LTypes<T>::T2 T2;
@@ -606,29 +387,6 @@ static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
   if (a.nsplit < 1) a.nsplit = 1;
   dim3 grid(total, nrhs, a.nsplit), block(256);
   void (*fn)(M2LArgs) = nullptr;
-  // FP32 with one staging phase: the pipelined kernel, with the fewest register
-  // slots that hold this thread's share of a table and of the moments
-  if (sizeof(T) == 4 && a.pipe && a.kph == 1 && TW <= 6) {
-    const int need_g = (a.nG + 255) / 256, need_m = (16 * NCB * 4 * a.nKB + 255) / 256;
-    const int cfg = (need_g <= 4 && need_m <= 12) ? 0 : (need_g <= 8 && need_m <= 16) ? 1 : -1;
-    if (cfg >= 0) {
-      void (*fp[2][2][6])(M2LArgs) = {
-          {{k_m2l_pipe<1, NCB, 4, 12, false>, k_m2l_pipe<2, NCB, 4, 12, false>, k_m2l_pipe<3, NCB, 4, 12, false>,
-            k_m2l_pipe<4, NCB, 4, 12, false>, k_m2l_pipe<5, NCB, 4, 12, false>, k_m2l_pipe<6, NCB, 4, 12, false>},
-           {k_m2l_pipe<1, NCB, 8, 16, false>, k_m2l_pipe<2, NCB, 8, 16, false>, k_m2l_pipe<3, NCB, 8, 16, false>,
-            k_m2l_pipe<4, NCB, 8, 16, false>, k_m2l_pipe<5, NCB, 8, 16, false>, k_m2l_pipe<6, NCB, 8, 16, false>}},
-          {{k_m2l_pipe<1, NCB, 4, 12, true>, k_m2l_pipe<2, NCB, 4, 12, true>, k_m2l_pipe<3, NCB, 4, 12, true>,
-            k_m2l_pipe<4, NCB, 4, 12, true>, k_m2l_pipe<5, NCB, 4, 12, true>, k_m2l_pipe<6, NCB, 4, 12, true>},
-           {k_m2l_pipe<1, NCB, 8, 16, true>, k_m2l_pipe<2, NCB, 8, 16, true>, k_m2l_pipe<3, NCB, 8, 16, true>,
-            k_m2l_pipe<4, NCB, 8, 16, true>, k_m2l_pipe<5, NCB, 8, 16, true>, k_m2l_pipe<6, NCB, 8, 16, true>}}};
-      fn = fp[ex ? 1 : 0][cfg][TW - 1];
-      const size_t lds_p = lds + sizeof(int) * 2 * 216;
-      hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_p);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(fn, grid, block, lds_p, s, a);
-      return hipGetLastError();
-    }
-  }
   switch (TW) {
     case 1: fn = ex ? k_m2l<T, 1, NCB, true> : k_m2l<T, 1, NCB, false>; break;
     case 2: fn = ex ? k_m2l<T, 2, NCB, true> : k_m2l<T, 2, NCB, false>; break;
