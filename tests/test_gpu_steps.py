@@ -76,3 +76,25 @@ def test_p2m_and_m2m_moments():
             ref = _p2m_ref(xyz, q, lo, t["side"], level, 6, box)
             np.testing.assert_allclose(mom[box], ref, rtol=1e-11, atol=1e-11 * np.max(np.abs(ref)))
     f.close()
+
+
+@pytest.mark.parametrize("p", [7, 8])
+@pytest.mark.parametrize("tile", [1, 2])
+def test_m2l_fp32_matches_fp64(p, tile):
+    """Mixed FP32 against FP64 at the same order, depth and M2L tile width: only rounding
+    differs.  p = 7 (an even number of reduced moments) stages the source moments in runs
+    of 4 (16 targets per workgroup) or 8 (32) entries per thread, p = 8 element by element;
+    depth 3 leaves the coarse levels' tiles partly filled."""
+    import torch
+    from paper_1902_05875_amd import inputs
+    api = _api()
+    xyz, q = inputs.workload("c2", n=20_000)
+    out = []
+    for prec in ("fp64", "fp32"):
+        f = api.TEFMM(K3, D3, p=p, depth=3, precision=prec, m2l_tile=tile)
+        f.set_particles(xyz)
+        out.append(f.evaluate(torch.from_numpy(q).cuda()).cpu().numpy())
+        f.close()
+    e = np.linalg.norm(out[1] - out[0]) / np.linalg.norm(out[0])
+    print(f"p={p} tile={tile}: FP32 vs FP64 rel diff {e:.3e}")
+    assert e < 1e-5
