@@ -500,19 +500,32 @@ __global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
     const int id = w + 4 * j;
     const int rb = id % a.nRB, cb = id / a.nRB;
     const int k = 16 * rb + col;
-    rowo[j] = -1, tcb[j] = cb;
+    // rows past nR (and missing tiles) gather entry 0: finite, and dropped by the epilogue
+    rowo[j] = 0, tcb[j] = cb;
     if (id < ntile && k < a.nR) {
       const int pk = a.rzmi[k];
       const int k1 = pk & 255, k2 = (pk >> 8) & 255, k3 = pk >> 16;
       rowo[j] = (k3 * P2 + k1 + k2) * P2 + k1;
     }
   }
-  AC accR[TW], accI[TW];
+  // B operand offset of each tile (column block tcb, target col); FP32 keeps Re G Re a
+  // and Im G Im a apart (no negation per step), as in k_m2l
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr bool BT = TW <= 2;
+  int boff[TW];
+#pragma unroll
+  for (int j = 0; j < TW; ++j) boff[j] = (16 * tcb[j] + col) * a.nRs;
+  AC accR[TW], accI[TW], accN[F32 ? TW : 1];
 #pragma unroll
   for (int j = 0; j < TW; ++j) {
     accR[j] = AC{0, 0, 0, 0};
     accI[j] = AC{0, 0, 0, 0};
+    if (F32) accN[j] = AC{0, 0, 0, 0};
   }
+  // staging walk: element e = tid + 256 i of the NT x nR block is (n, kk), advanced by
+  // 256 = q nR + rem per step
+  const int n0 = tid / a.nR, kk0 = tid - n0 * a.nR;
+  const int step_q = 256 / a.nR, step_r = 256 - step_q * a.nR;
   const int cls = 4 * iz + px + 2 * py;
   const int e0 = L.list_start[cls], e1 = L.list_start[cls + 1];
   for (int ei = e0 + split; ei < e1; ei += a.nsplit) {
@@ -538,47 +551,65 @@ __global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
         if (pos >= 0) sG[kk3 * sub + pos] = g[e];
       }
     }
-    for (int e = tid; e < NT * a.nR; e += 256) {
-      const int n = e / a.nR, kk = e - n * a.nR;
-      T2 v;
-      v.x = 0;
-      v.y = 0;
-      if ((smask >> n) & 1) {
-        const int ix = px + 2 * (4 * X0 + (n & 3)) + ce.dx, iy = py + 2 * (4 * NCB * Y0 + (n >> 2)) + ce.dy;
-        const int64_t sb = ((int64_t)ix * N + iy) * N + ce.izs;
-        v = Ty::cvt(alpha[sb * a.nR + kk]);
+    {
+      int n = n0, kk = kk0;
+      for (int e = tid; e < NT * a.nR; e += 256) {
+        T2 v;
+        v.x = 0;
+        v.y = 0;
+        if ((smask >> n) & 1) {
+          const int ix = px + 2 * (4 * X0 + (n & 3)) + ce.dx, iy = py + 2 * (4 * NCB * Y0 + (n >> 2)) + ce.dy;
+          const int64_t sb = ((int64_t)ix * N + iy) * N + ce.izs;
+          v = Ty::cvt(alpha[sb * a.nR + kk]);
+        }
+        sA[n * a.nRs + kk] = v;
+        n += step_q, kk += step_r;
+        if (kk >= a.nR) kk -= a.nR, ++n;
       }
-      sA[n * a.nRs + kk] = v;
     }
     __syncthreads();
-    for (int kb = 0; kb < a.nKB; ++kb) {
+    // operands of block kb (column offset 0 past nR, where the staged moments are zero);
+    // those of the next block are loaded while the MFMAs of this one run
+    auto load = [&](int kb, T2 (&bb)[TW], T2 (&g)[TW]) {
       const int kp = 4 * kb + krow;
-      const int ci = sCol[kp];
-      const bool cvalid = (ci >> 24) & 1;
-      const int co = ci & 0xFFFFFF;
-      const T2 bv0 = sA[col * a.nRs + kp];
-      const T2 bv1 = NCB == 2 ? sA[(16 + col) * a.nRs + kp] : bv0;
-      T2 gv[TW];
+      const int co = sCol[kp] & 0xFFFFFF;
+      if (BT) {
 #pragma unroll
-      for (int j = 0; j < TW; ++j) {
-        gv[j].x = 0;
-        gv[j].y = 0;
-        if (rowo[j] >= 0 && cvalid) gv[j] = sG[rowo[j] + co];
+        for (int j = 0; j < TW; ++j) bb[j] = sA[boff[j] + kp];
+      } else {
+        bb[0] = sA[col * a.nRs + kp];
+        bb[1] = NCB == 2 ? sA[(16 + col) * a.nRs + kp] : bb[0];
       }
 #pragma unroll
+      for (int j = 0; j < TW; ++j) g[j] = sG[rowo[j] + co];
+    };
+    auto mma = [&](const T2 (&bb)[TW], const T2 (&g)[TW]) {
+#pragma unroll
       for (int j = 0; j < TW; ++j)
         if (w + 4 * j < ntile) {
-          const T2 b = tcb[j] ? bv1 : bv0;
-          accR[j] = Ty::mfma(gv[j].x, b.x, accR[j]);
-          accI[j] = Ty::mfma(gv[j].x, b.y, accI[j]);
+          const T2 b = BT ? bb[j] : (tcb[j] ? bb[1] : bb[0]);
+          accR[j] = Ty::mfma(g[j].x, b.x, accR[j]);
+          accI[j] = Ty::mfma(g[j].x, b.y, accI[j]);
         }
 #pragma unroll
       for (int j = 0; j < TW; ++j)
         if (w + 4 * j < ntile) {
-          const T2 b = tcb[j] ? bv1 : bv0;
-          accR[j] = Ty::mfma(-gv[j].y, b.y, accR[j]);
-          accI[j] = Ty::mfma(gv[j].y, b.x, accI[j]);
+          const T2 b = BT ? bb[j] : (tcb[j] ? bb[1] : bb[0]);
+          if (F32)
+            accN[j] = Ty::mfma(g[j].y, b.y, accN[j]);
+          else
+            accR[j] = Ty::mfma(-g[j].y, b.y, accR[j]);
+          accI[j] = Ty::mfma(g[j].y, b.x, accI[j]);
         }
+    };
+    T2 b1[TW], g1[TW], b2[TW], g2[TW];
+    load(0, b1, g1);
+    for (int kb = 0; kb < a.nKB; kb += 2) {
+      if (kb + 1 < a.nKB) load(kb + 1, b2, g2);
+      mma(b1, g1);
+      if (kb + 1 >= a.nKB) break;
+      if (kb + 2 < a.nKB) load(kb + 2, b1, g1);
+      mma(b2, g2);
     }
   }
   double2* beta = L.b + (int64_t)split * L.split_stride + (int64_t)r * L.rhs_stride;
@@ -594,7 +625,10 @@ __global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int k = 16 * rb + Ty::row(krow, i);
-      if (k < a.nR) beta[tb * a.nR + k] = make_double2((double)accR[j][i], (double)accI[j][i]);
+      if (k < a.nR) {
+        const double re = F32 ? (double)accR[j][i] - (double)accN[F32 ? j : 0][i] : (double)accR[j][i];
+        beta[tb * a.nR + k] = make_double2(re, (double)accI[j][i]);
+      }
     }
   }
 }
