@@ -853,8 +853,12 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
                                              float eci, double kap, const PassArgs& a, int64_t i, double txd,
                                              double tyd, double tzd, int r0, int nrhs, float* accr, float* acci,
                                              double* nsr, double* nsi) {
+  // a pair at distance 0 (a particle with itself) gets weight 0 in the FP32 sum; pairs
+  // with 0 < r2 < rns2 are taken back and redone in FP64
+  const unsigned near_lim = (unsigned)__float_as_int(rns2) - 1u;
+  auto nearp = [&](float r2) { return (unsigned)__float_as_int(r2) - 1u < near_lim; };
   auto fixup = [&](int t, float r2) {
-    if (!(r2 < rns2)) return;
+    if (!nearp(r2)) return;
     const int64_t j = sidx[t];
     double er = 0.0, ei = 0.0;
     if (j != i) {
@@ -874,6 +878,7 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
     // max of two non-negative floats as the max of their bit patterns (no canonicalising)
     float er, ei;
     pair_kernel(__int_as_float(max(__float_as_int(r2), __float_as_int(rns2))), 0.0f, &er, &ei);
+    if (!(r2 > 0.0f)) er = 0.0f, ei = 0.0f;
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
       const float qr = sq[t][2 * b], qi = sq[t][2 * b + 1];
@@ -895,8 +900,9 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) pair(t + u, r2[u]);
-    const float mn = fminf(fminf(r2[0], r2[1]), fminf(r2[2], r2[3]));
-    if (__any(mn < rns2)) {
+    const unsigned mn = min(min((unsigned)__float_as_int(r2[0]) - 1u, (unsigned)__float_as_int(r2[1]) - 1u),
+                            min((unsigned)__float_as_int(r2[2]) - 1u, (unsigned)__float_as_int(r2[3]) - 1u));
+    if (__any(mn < near_lim)) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) fixup(t + u, r2[u]);
     }
@@ -1040,13 +1046,15 @@ __device__ __forceinline__ float sym_r2(float tx, float ty, float tz, const floa
 // Eight staged sources [t, t + 8) against this lane's T targets.  SYM: also the
 // eight source-side sums over the wave's 64 T targets, written to
 // psw[2 (t + u) + c] (c = 0 real, 1 imaginary part).  Every pair is applied
-// with the FP32 value at the squared distance from sym_r2.  Pairs closer than
-// the threshold rns2 (rare: the pair of a particle with itself, or two
-// particles closer than 5% of the leaf side, whose FP32 coordinate differences
-// have lost digits) are marked in nl (a bit mask per step and lane) and, after
-// the eight sources, taken one by one: the value used is replaced by the one
-// from FP64 differences (0 for the pair with itself), its source-side part
-// added to dps[2 (t + u) + c].
+// with the FP32 value at the squared distance from sym_r2, except a pair at
+// distance 0 in the leaf's own pass (a particle with itself), which gets weight
+// 0: its clamped value would be of the order of the inverse threshold, and
+// taking it back later would cancel against everything else in the FP32 sum.
+// Pairs closer than the threshold rns2 (rare: two particles closer than 5% of
+// the leaf side, whose FP32 coordinate differences have lost digits) are marked
+// in nl (a bit mask per step and lane) and, after the eight sources, taken one
+// by one: the value used is replaced by the one from FP64 differences, its
+// source-side part added to dps[2 (t + u) + c].
 template <int T, bool SYM>
 __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T], const float (&ty)[T],
                                          const float (&tz)[T], const float (&qri)[T], const float (&qii)[T],
@@ -1059,6 +1067,8 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
   typedef float f16v __attribute__((ext_vector_type(16)));
   f16v c;
   int steps = 0;  // steps with marked pairs
+  // near test on the bit patterns less one: 0 < r2 < rns2 (a pair at distance 0 wraps to the top)
+  const unsigned near_lim = (unsigned)__float_as_int(rns2) - 1u;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {  // two sources at a time
     float r2[2][T];
@@ -1080,6 +1090,7 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
         }
         float er, ei;
         pair_kernel(used, 0.0f, &er, &ei);
+        if (!SYM && !(r2[u][k] > 0.0f)) er = 0.0f, ei = 0.0f;
         accr[k] = fmaf(qr, er, fmaf(-qi, ei, accr[k]));
         acci[k] = fmaf(qr, ei, fmaf(qi, er, acci[k]));
         if (SYM) {
@@ -1096,15 +1107,28 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
 #pragma unroll
       for (int k = 0; k < T; ++k) asm volatile("" : "+v"(accr[k]), "+v"(acci[k]));
     }
-    float mn = r2[0][0];
+    bool anynear;
+    if (SYM) {
+      float mn = r2[0][0];
 #pragma unroll
-    for (int k = 0; k < T; ++k) mn = fminf(mn, fminf(r2[0][k], r2[1][k]));
-    if (__any(mn < rns2)) {
+      for (int k = 0; k < T; ++k) mn = fminf(mn, fminf(r2[0][k], r2[1][k]));
+      anynear = mn < rns2;
+    } else {
+      unsigned mn = 0xFFFFFFFFu;
+#pragma unroll
+      for (int k = 0; k < T; ++k)
+        mn = min(mn, min((unsigned)__float_as_int(r2[0][k]) - 1u, (unsigned)__float_as_int(r2[1][k]) - 1u));
+      anynear = mn < near_lim;
+    }
+    if (__any(anynear)) {
       unsigned m = 0;  // bit u T + k: pair (source 2 v + u, target slot k)
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int k = 0; k < T; ++k) m |= (act[k] && r2[u][k] < rns2) ? 1u << (u * T + k) : 0u;
+        for (int k = 0; k < T; ++k) {
+          const bool nr = SYM ? r2[u][k] < rns2 : (unsigned)__float_as_int(r2[u][k]) - 1u < near_lim;
+          m |= (act[k] && nr) ? 1u << (u * T + k) : 0u;
+        }
       nl[64 * v + lane] = (int)m;
       steps |= 1 << v;
     }

@@ -184,3 +184,31 @@ def test_c4_full_size_sampled(p, precision, depth, tol):
     e = _err(phi[idx], ref)
     print(f"C4 N=1M p={p} {precision} depth {depth}: rel err {e:.3e}")
     assert e < tol
+
+
+@pytest.mark.parametrize("n", [1, 2, 5])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tiny_inputs(n, precision):
+    """A handful of particles in the middle layer against the oracle's direct sum (every pair
+    is a near pair; with one particle the result is its own reaction term alone).  The root
+    cube shrinks to the particles' extent (a point for one particle)."""
+    from oracle import direct
+    from oracle.medium import Medium
+    rng = np.random.default_rng(300 + n)
+    xyz = np.column_stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.3, 0.3, n), rng.uniform(-0.9, -0.3, n)])
+    q = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
+    phi, _ = _run(xyz, q, p=12 if precision == "fp64" else 8, precision=precision)
+    ref = direct.potential(Medium(K3, D3), xyz, q)
+    e = _err(phi, ref)
+    print(f"n={n} {precision}: rel err {e:.3e}")
+    assert np.all(np.isfinite(phi))
+    assert e < (1e-6 if precision == "fp64" else 1e-4)
+
+
+def test_no_particles_rejected():
+    """An empty particle set is an argument error, not a launch."""
+    from paper_1902_05875_amd import api
+    f = api.TEFMM(K3, D3, p=6)
+    with pytest.raises(api.TefmmError):
+        f.set_particles(np.zeros((0, 3)))
+    f.close()
