@@ -111,3 +111,59 @@ def test_free_part_excludes_self():
     q = np.array([1.0, 2.0, 5.0]) + 0j
     got = direct.free_part(med, xyz, q, np.array([0]))
     np.testing.assert_allclose(got[0], 2.0 * np.exp(1.5j * 0.3) / (4 * np.pi * 0.3), rtol=1e-14)
+
+
+# Media other than the three-layer one of the workloads: two layers (one interface) and
+# four layers (three interfaces).  Points per layer for each.
+MEDIA = {
+    "two": (Medium((1.0, 2.0), (0.0,)), {0: 0.4, 1: -0.6}),
+    "four": (Medium((0.8, 1.5, 2.0, 1.2), (0.0, -1.2, -2.0)), {0: 0.35, 1: -0.55, 2: -1.6, 3: -2.5}),
+}
+
+
+@pytest.mark.parametrize("name", ["two", "four"])
+def test_weighted_reciprocity_other_media(name):
+    """k_l G_{l,lp}(r, r') = k_lp G_{lp,l}(r', r) for every layer pair (the flux condition of Sec. 2.1)."""
+    med, zs = MEDIA[name]
+    for l in zs:
+        for lp in zs:
+            r = (0.1, -0.2, zs[l] + 0.07)
+            rp = (-0.3, 0.25, zs[lp] - 0.04)
+            a = med.k[l] * _full_g(med, l, lp, r, rp)
+            b = med.k[lp] * _full_g(med, lp, l, rp, r)
+            np.testing.assert_allclose(a, b, rtol=1e-10)
+
+
+@pytest.mark.parametrize("name", ["two", "four"])
+def test_interface_conditions_other_media(name):
+    """G and k dG/dz continuous across every interface, for a source in every layer."""
+    med, zs = MEDIA[name]
+    h = 1e-3
+    for j, zi in enumerate(med.d):
+        for lp in zs:
+            rp = (0.2, -0.1, zs[lp] + 0.03)
+
+            def g(l, z):
+                return _full_g(med, l, lp, (-0.15, 0.3, z), rp)
+
+            va, vb = g(j, zi + 1e-9), g(j + 1, zi - 1e-9)
+            sa = (-3 * g(j, zi) + 4 * g(j, zi + h) - g(j, zi + 2 * h)) / (2 * h)
+            sb = (3 * g(j + 1, zi) - 4 * g(j + 1, zi - h) + g(j + 1, zi - 2 * h)) / (2 * h)
+            np.testing.assert_allclose(va, vb, rtol=1e-7)
+            np.testing.assert_allclose(med.k[j] * sa, med.k[j + 1] * sb, rtol=2e-5)
+
+
+def test_four_layers_reduce_to_three():
+    """A fourth layer with the third layer's wave number is no interface at all: the four-layer
+    kernel equals the three-layer one for points in the first three layers (and in the merged
+    bottom layer)."""
+    m4 = Medium((0.8, 1.5, 2.0, 2.0), (0.0, -1.2, -2.0))
+    m3 = Medium((0.8, 1.5, 2.0), (0.0, -1.2))
+    pts = {0: 0.35, 1: -0.55, 2: -1.6}
+    for l, z in pts.items():
+        for lp, zp in pts.items():
+            r, rp = (0.1, -0.2, z + 0.05), (-0.3, 0.25, zp - 0.03)
+            np.testing.assert_allclose(_full_g(m4, l, lp, r, rp), _full_g(m3, l, lp, r, rp), rtol=1e-9)
+    # below the removed interface: layer 3 of the four-layer medium is layer 2 of the three-layer one
+    r, rp = (0.1, -0.2, -2.4), (-0.3, 0.25, -0.6)
+    np.testing.assert_allclose(_full_g(m4, 3, 1, r, rp), _full_g(m3, 2, 1, r, rp), rtol=1e-9)
