@@ -189,17 +189,20 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   for (int xi = 0; xi < 4; ++xi)
     tbase[xi] = (((px + 2 * (4 * X0 + xi)) * N + (py + 8 * NCB * Y0)) * N + iz) * a.nR;
   const int tbase_y = 2 * N * a.nR;
-  // Staging by runs: with one phase, E = NT Lp / 256 even and dividing Lp, and nR even,
-  // each thread stages E consecutive entries of one target (loaded two at a time),
-  // with the validity and the Sigma sign of each entry fixed per thread.
+  // Staging by runs: with at most two phases, E = NT Lp / 256 even and dividing Lp, and
+  // nR even, each thread stages E consecutive entries of one target (loaded two at a
+  // time), with the validity and the Sigma sign of each entry fixed per thread and phase.
   const int E = (NT * Lp) / 256;
-  const bool runs = a.kph == 1 && (NT * Lp) % 256 == 0 && E % 2 == 0 && E <= 8 && Lp % E == 0 && a.nR % 2 == 0;
+  const bool runs = a.kph <= 2 && (NT * Lp) % 256 == 0 && E % 2 == 0 && E <= 8 && Lp % E == 0 && a.nR % 2 == 0;
   const int rn = runs ? (tid * E) / Lp : 0, rk = runs ? (tid * E) % Lp : 0;
-  unsigned rvalid = 0, rsign = 0;
+  unsigned rvalid[2] = {0u, 0u}, rsign[2] = {0u, 0u};
   __syncthreads();  // sCol complete
   if (runs)
-    for (int i = 0; i < E; ++i)
-      if (rk + i < a.nR) rvalid |= 1u << i, rsign |= (unsigned)((sCol[rk + i] >> 20) & 1) << i;
+    for (int ph = 0; ph < a.kph; ++ph)
+      for (int i = 0; i < E; ++i) {
+        const int kk = Lp * ph + rk + i;
+        if (kk < a.nR) rvalid[ph] |= 1u << i, rsign[ph] |= (unsigned)((sCol[kk] >> 20) & 1) << i;
+      }
   for (int pass = 0; pass < 2; ++pass) {
     const T2* table = pass ? (const T2*)Ty::tableS(L) : (const T2*)Ty::tableF(L);
     if (!table) continue;
@@ -229,15 +232,15 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
             }
             if (runs) {
               const bool on = (smask >> rn) & 1;
-              const int64_t at = tbase[rn & 3] + tbase_y * (rn >> 2) + rk + delta;
-              const unsigned neg = mirror ? rsign : 0u;
+              const int64_t at = tbase[rn & 3] + tbase_y * (rn >> 2) + kbase + rk + delta;
+              const unsigned neg = mirror ? rsign[ph] : 0u;
               T2* dst = sA + rn * a.nRsP + rk;
 #pragma unroll
               for (int i = 0; i < 8; i += 2) {
                 if (i >= E) break;
                 T2 v0, v1;
                 v0.x = 0, v0.y = 0, v1.x = 0, v1.y = 0;
-                if (on && ((rvalid >> i) & 1)) {
+                if (on && ((rvalid[ph] >> i) & 1)) {
                   if (F32) {
                     const float4 q = *(const float4*)(alpha32 + at + i);
                     v0.x = (T)q.x, v0.y = (T)q.y, v1.x = (T)q.z, v1.y = (T)q.w;
@@ -371,17 +374,22 @@ static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
   }
   a.tile_start[a.nlev] = total;
   // stage the source moments in two phases when that lets two workgroups share a CU
-  auto lds_of = [&](int kph) {
-    const int kpb = (a.nKB + kph - 1) / kph;
+  auto lds_of = [&](int kpb) {
     int rs = 4 * kpb;
     while (rs % 16 != 1) ++rs;
     return std::make_pair(((size_t)3 * a.P2 * a.P2 + 1) * sizeof(T2) + (size_t)16 * NCB * rs * sizeof(T2) +
                               4 * (size_t)a.nKB * sizeof(int), rs);
   };
-  a.kph = (lds_of(1).first > 80 * 1024 && lds_of(2).first <= 80 * 1024) ? 2 : 1;
-  a.kpb = (a.nKB + a.kph - 1) / a.kph;
-  const size_t lds = lds_of(a.kph).first;
-  a.nRsP = lds_of(a.kph).second;
+  const int kpb1 = a.nKB, kpb2 = (a.nKB + 1) / 2;
+  a.kph = (lds_of(kpb1).first > 80 * 1024 && lds_of(kpb2).first <= 80 * 1024) ? 2 : 1;
+  a.kpb = a.kph == 1 ? kpb1 : kpb2;
+  if (a.kph == 2 && a.nR % 2 == 0) {
+    // blocks per phase rounded up so that each thread stages a run of 2, 4, 6 or 8 entries
+    const int m = NCB == 1 ? 8 : 4, up = (a.kpb + m - 1) / m * m;
+    if (NCB * up / 4 <= 8 && lds_of(up).first <= 80 * 1024) a.kpb = up;
+  }
+  const size_t lds = lds_of(a.kpb).first;
+  a.nRsP = lds_of(a.kpb).second;
   const int TW = (a.nRB * NCB + 3) / 4;
   const bool ex = 4 * TW == a.nRB * NCB;
   if (a.nsplit < 1) a.nsplit = 1;
