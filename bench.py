@@ -106,9 +106,13 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload, surrogate=
     phases = {k: st[k] for k in ("t_p2m_ms", "t_m2m_ms", "t_m2l_ms", "t_l2l_ms", "t_l2p_ms", "t_p2p_ms", "t_total_ms")}
     phi = out[0].cpu().numpy() if out.dim() == 2 else out.cpu().numpy()
     err, nchk = _sampled_error(workload, phi)
+    n_eval = q.shape[0] * q.shape[1] if q.ndim == 2 else xyz.shape[0]
     res = {
         "p": p, "precision": precision, "ms_per_step": ms, "setup_s": setup_s,
-        "evals_per_s": q.shape[0] * q.shape[1] / (ms / 1e3) if q.ndim == 2 else xyz.shape[0] / (ms / 1e3),
+        "evals_per_s": n_eval / (ms / 1e3),
+        # set-up (tree, image fits, tables) spread over 1, 10, 100 evaluations of one geometry, as an
+        # iterative solver applies the operator; the autotuner's trial runs are not included
+        "amortised_evals_per_s": {str(m): n_eval * m / (setup_s + m * ms / 1e3) for m in (1, 10, 100)},
         "phases_ms": {k[2:-3]: round(v, 4) for k, v in phases.items()},
         "m2l_flops": st["m2l_flops"], "m2l_launches": st["m2l_launches"], "depth": st["depth"][0],
         "p2p_flops": _p2p_flops(st, precision, q), "p2p_sym": _p2p_sym(precision, q),
