@@ -41,13 +41,14 @@ P2P_FLOPS_PER_PAIR = 23
 P2P_FLOPS_PER_SYM_PAIR = 31
 SHAPES = {"c1": "uniform unit cube centred (0,0,-0.6)", "c2": "uniform unit cube centred (0,0,-0.6)",
           "c4": "uniform unit cube centred (0,0,-0.6)", "c5": "uniform unit cube centred (0,0,-0.6)",
-          "c3": "split over three unit cubes centred (0,0,0.6), (0,0,-0.6), (0,0,-1.8), one per layer"}
+          "c3": "split over three unit cubes centred (0,0,0.6), (0,0,-0.6), (0,0,-1.8), one per layer",
+          "ex2": "in the Example-2 domain r = 1/2 - a + a P4(cos theta), a = 0.15, centred (0,0,-0.6)"}
 
 
 def _sampled_error(workload, phi):
     """Relative 2-norm error on the targets whose oracle values are stored (if any)."""
     import numpy as np
-    name = {"c4": "c4s", "c2": "c2s", "c1": "c1", "c3": "c3s"}.get(workload)
+    name = {"c4": "c4s", "c2": "c2s", "c1": "c1", "c3": "c3s", "ex2": "ex2s"}.get(workload)
     path = os.path.join(ROOT, "tests", "golden", f"expected_{name}.txt") if name else None
     if not path or not os.path.exists(path):
         return None, 0
@@ -299,7 +300,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c4",
                     help="c4: N=1M mid-layer cube (default); c2: N=200k; c3: N=1M over three layers; "
-                         "c5: the batched workload (its own JSON line)")
+                         "ex2: N=1M in the Example-2 domain; c5: the batched workload (its own JSON line)")
     ap.add_argument("--n", type=int, default=None, help="override N (same recipe)")
     ap.add_argument("--p64", type=int, default=13, help="Taylor order of the plain FP64 mode")
     ap.add_argument("--p32", type=int, default=7,

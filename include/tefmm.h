@@ -177,7 +177,10 @@ int tefmm_evaluate_batch(tefmm_t* hs, int n_geom, const double* const* q, const 
 /* Autotuner: times the evaluation of the handle's own geometry (unit charges)
  * for tree depths d-1, d, d+1 (d the current depth, clamped to [2, 7]) and for
  * 16 or 32 target boxes per M2L workgroup, then rebuilds the handle with the
- * fastest choice.  *depth_out / *ncb_out (may be NULL) receive it.  Synchronous. */
+ * fastest choice; for it, also whether the near field runs beside the far field
+ * from the start, beside it from the end of the upward pass (P2M, M2M), or before
+ * it on the same stream, keeping the fastest.  *depth_out / *ncb_out
+ * (may be NULL) receive the depth and tile width.  Synchronous. */
 int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_out);
 
 /* Statistics of the last set_particles / evaluate (timings need the stream

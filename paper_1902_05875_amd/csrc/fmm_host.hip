@@ -122,6 +122,10 @@ struct tefmm_ctx {
   // copy of the caller's positions (SoA), kept for re-building the tree (autotuner)
   double* d_xyz_user = nullptr;
   int m2l_ncb = 0;  // M2L tile width override (0 = automatic)
+  // where the near field forks from the far field: -1 by precision (FP32 at once, FP64
+  // after the upward pass), 0 at once, 1 after the upward pass, 2 not at all (the near
+  // field first, then the far field, on the caller's stream); set by the autotuner
+  int fork_late = -1;
   tefmm_surrogate* sur = nullptr;  // surrogate for the Sigma tables (borrowed)
   uint64_t gen = 0; // changes whenever device buffers are (re)allocated
   // graph of the last batched evaluation
@@ -1167,13 +1171,13 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
   // stays on the captured stream.
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIPCHK(h, hipStreamIsCapturing(s, &cap));
-  const bool fork = cap == hipStreamCaptureStatusNone;
+  const bool fork = cap == hipStreamCaptureStatusNone && h->fork_late != 2;
   hipStream_t sn = fork ? h->s2 : s;
-  // In FP64 the far field is the longer branch: the upward pass (P2M, M2M and the
-  // reduced moments; short, narrow kernels) then runs alone, and the near field
-  // starts beside the M2L.  In FP32 the near field is the longer branch and starts
-  // at once.
-  const bool late = fork && !fp32;
+  // When the far field is the longer branch (FP64 by default) the upward pass (P2M,
+  // M2M and the reduced moments; short, narrow kernels) runs alone and the near field
+  // starts beside the M2L; when the near field is the longer one (FP32 by default) it
+  // starts at once.  The autotuner measures both.
+  const bool late = fork && (h->fork_late < 0 ? !fp32 : h->fork_late == 1);
   auto near_field = [&]() -> int {
     if (fork) {
       HIPCHK(h, hipEventRecord(h->e_fork, s));
@@ -1280,7 +1284,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
   // launches are independent (each writes only its own locals): with several groups
   // and no graph capture, group gi > 0 runs on stream sg[gi], joined before the locals.
   const int ngr = (int)h->groups.size();
-  const bool gfork = fork && ngr > 1;
+  const bool gfork = cap == hipStreamCaptureStatusNone && ngr > 1;
   if (gfork) {
     HIPCHK(h, hipEventRecord(h->e_gfork, s));
     for (int gi = 1; gi < ngr; ++gi) HIPCHK(h, hipStreamWaitEvent(h->sg[gi], h->e_gfork, 0));
@@ -1528,17 +1532,41 @@ extern "C" int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_
       if (rc == TEFMM_OK && ms < best) best = ms, bd = cand, bn = ncb;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  dfree(q1);
-  dfree(phi1);
   if (rc != TEFMM_OK) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dfree(q1);
+    dfree(phi1);
     h->opt.depth = depth_opt;
     return rc;
   }
   h->opt.depth = bd;
   rc = tefmm_set_particles(h, n, h->d_xyz_user, 1, stream);
   h->m2l_ncb = bn;
+  // the fork point of the near field, for the chosen depth and tile width (set_particles
+  // rebuilt the levels: their moment and local buffers first)
+  if (rc == TEFMM_OK) rc = ensure_rhs(h, 1);
+  if (rc == TEFMM_OK) {
+    float bf = 1e30f;
+    int bfm = -1;
+    for (int fm = 0; fm <= 2 && rc == TEFMM_OK; ++fm) {
+      h->fork_late = fm;
+      rc = enqueue_evaluate(h, (const double*)q1, 1, (double*)phi1, s, false);
+      if (rc != TEFMM_OK) break;
+      (void)hipEventRecord(e0, s);
+      for (int it = 0; it < 2 && rc == TEFMM_OK; ++it) rc = enqueue_evaluate(h, (const double*)q1, 1, (double*)phi1, s, false);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rc == TEFMM_OK && ms < bf) bf = ms, bfm = fm;
+    }
+    h->fork_late = bfm;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  dfree(q1);
+  dfree(phi1);
   if (depth_out) *depth_out = bd;
   if (ncb_out) *ncb_out = bn;
   return rc;

@@ -56,6 +56,7 @@ def workload(name: str, n: int | None = None, n_rhs: int | None = None):
     c3: N=1,000,000 over three cubes (one per layer), seed 3.
     c4: N=1,000,000 mid-layer cube, seed 4.
     c5: N=500,000 mid-layer cube with 32 charge vectors, seed 5.
+    ex2: N=1,000,000 in the Example-2 domain (a = 0.15) centred in the middle layer, seed 6.
     ``n`` overrides the size (same recipe, smaller or larger)."""
     name = name.lower()
     if name == "c1":
@@ -86,6 +87,11 @@ def workload(name: str, n: int | None = None, n_rhs: int | None = None):
         n = n or 500_000
         xyz = cube(rng, n, MID_CENTRE)
         return xyz, charges(rng, n, n_rhs or 32)
+    if name == "ex2":
+        rng = np.random.default_rng(6)
+        n = n or 1_000_000
+        xyz = irregular(rng, n, MID_CENTRE, 0.15)
+        return xyz, charges(rng, n, n_rhs or 1)
     raise ValueError(name)
 
 

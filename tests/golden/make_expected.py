@@ -5,7 +5,9 @@ Calls only oracle/ (and the seeded input generators).  Usage:
 Cases: c1 (N=1000, all targets), c2s (N=200,000, 64 sampled targets),
 c4s (N=1,000,000, 16 sampled targets), n20k (N=20,000, 128 sampled targets),
 c3small (three layers, N=3000, 300 targets), c3s (three layers, N=1,000,000, 6 targets per layer),
-c1ns (c1 plus 24 particles at distance 1e-6 from existing ones; the 48 particles of those pairs).
+c1ns (c1 plus 24 particles at distance 1e-6 from existing ones; the 48 particles of those pairs),
+ex2small (the Example-2 domain, N=20,000, 64 sampled targets), ex2s (the same domain, N=1,000,000,
+16 sampled targets).
 Output: tests/golden/expected_<case>.txt with columns  index  re  im.
 """
 from __future__ import annotations
@@ -60,6 +62,12 @@ def case_spec(name):
     if name == "n20k":
         xyz, q = inputs.workload("c2", n=20_000)
         return xyz, q, inputs.sample_targets(xyz, 96, 32, seed=120)
+    if name == "ex2small":
+        xyz, q = inputs.workload("ex2", n=20_000)
+        return xyz, q, inputs.sample_targets(xyz, 48, 16, seed=160)
+    if name == "ex2s":
+        xyz, q = inputs.workload("ex2")
+        return xyz, q, inputs.sample_targets(xyz, 12, 4, seed=106)
     raise ValueError(name)
 
 
