@@ -103,7 +103,7 @@ struct tefmm_ctx {
   std::vector<Group> groups;
   // evaluate buffers
   double2 *d_q = nullptr, *d_phi = nullptr, *d_phi_near = nullptr;
-  // source-side sums of the symmetric near field: [13 slots][n] float2 (FP32) or double2 (FP64)
+  // source-side sums of the symmetric near field: [13 slots x 2 halves][n] float2 (FP32) or double2 (FP64)
   void* d_part = nullptr;
   // the near field runs on a second stream beside the far field (fork/join by events)
   hipStream_t s2 = nullptr;
@@ -1074,7 +1074,7 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
   HIPCHK(h, hipMalloc(&h->d_phi_near, sizeof(double2) * h->n * nrhs));
   dfree(h->d_part);
   if (sym_near(h->opt))
-    HIPCHK(h, hipMalloc(&h->d_part, (h->opt.precision == TEFMM_FP64 ? sizeof(double2) : sizeof(float2)) * 13 * h->n));
+    HIPCHK(h, hipMalloc(&h->d_part, (h->opt.precision == TEFMM_FP64 ? sizeof(double2) : sizeof(float2)) * 26 * h->n));
   for (auto& g : h->groups) {
     g.alpha.assign(g.depth + 1, nullptr);
     g.beta.assign(g.depth + 1, nullptr);
@@ -1197,18 +1197,20 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
         // registers than it saves work), else 1
         int tpl = h->opt.p2p_targets;
         if (tpl == 0) tpl = wide ? 2 : 1;
-        const dim3 grid((unsigned)g.nbox[g.depth], 1);
+        // two workgroups per leaf (halves of its target passes), then one per leaf to gather
+        const dim3 grid2((unsigned)(2 * g.nbox[g.depth]), 1), grid((unsigned)g.nbox[g.depth], 1);
+        const int tp = 64 * tpl;
         if (fp32) {
           void (*fs)(PassArgs, int, float2*) =
               tpl == 1 ? k_p2p_sym<float, 1, 4> : tpl == 2 ? k_p2p_sym<float, 2, 4> : k_p2p_sym<float, 4, 4>;
-          hipLaunchKernelGGL(fs, grid, dim3(256), 0, sn, a, 1, (float2*)h->d_part);
+          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, (float2*)h->d_part);
           HIPCHK(h, hipGetLastError());
-          hipLaunchKernelGGL(k_p2p_sym_gather<float2>, grid, dim3(128), 0, sn, a, 1, (const float2*)h->d_part);
+          hipLaunchKernelGGL(k_p2p_sym_gather<float2>, grid, dim3(128), 0, sn, a, 1, tp, (const float2*)h->d_part);
         } else {
           void (*fs)(PassArgs, int, double2*) = tpl == 1 ? k_p2p_sym<double, 1, 4> : k_p2p_sym<double, 2, 4>;
-          hipLaunchKernelGGL(fs, grid, dim3(256), 0, sn, a, 1, (double2*)h->d_part);
+          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, (double2*)h->d_part);
           HIPCHK(h, hipGetLastError());
-          hipLaunchKernelGGL(k_p2p_sym_gather<double2>, grid, dim3(128), 0, sn, a, 1, (const double2*)h->d_part);
+          hipLaunchKernelGGL(k_p2p_sym_gather<double2>, grid, dim3(128), 0, sn, a, 1, tp, (const double2*)h->d_part);
         }
         HIPCHK(h, hipGetLastError());
         continue;
