@@ -63,6 +63,9 @@ struct Group {
   std::vector<float2*> XT032, XT132;
   double cross_flops_per_rhs = 0;
   int64_t cross_pairs = 0, cross_forced = 0;  // forced: leaf pairs translated below the acceptance test
+  // symmetric near field: targets per lane and workgroups per leaf (each taking every
+  // p2p_split-th pass of 64 p2p_tpl targets), from the leaf occupancy
+  int p2p_tpl = 1, p2p_split = 1;
   int n_cross_fits = 0;
   double cross_fit_err = 0;
   bool has_cross = false;
@@ -103,7 +106,7 @@ struct tefmm_ctx {
   std::vector<Group> groups;
   // evaluate buffers
   double2 *d_q = nullptr, *d_phi = nullptr, *d_phi_near = nullptr;
-  // source-side sums of the symmetric near field: [13 slots x 2 halves][n] float2 (FP32) or double2 (FP64)
+  // source-side sums of the symmetric near field: [13 slots x G][n] float2 (FP32) or double2 (FP64)
   void* d_part = nullptr;
   // the near field runs on a second stream beside the far field (fork/join by events)
   hipStream_t s2 = nullptr;
@@ -957,6 +960,15 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
           h->p2p_pairs += c * nbsum - c;
           h->p2p_same += c * c - c;
         }
+    // targets per lane: 2 above a mean occupancy of 96 over all leaves, else 1 (unless
+    // set); workgroups per leaf: the passes a leaf of mean occupied size needs (at most 8)
+    // (the per-level box counts are set up later, with the buffers: the leaf count directly)
+    const int64_t nleaf = (int64_t)1 << (3 * g.depth);
+    int64_t occ = 0;
+    for (int64_t b = 0; b < nleaf; ++b) occ += lc[g.leaf_base + b] > 0;
+    g.p2p_tpl = h->opt.p2p_targets > 0 ? h->opt.p2p_targets : (g.count > 96 * nleaf ? 2 : 1);
+    const double mean_occ = occ ? (double)g.count / (double)occ : 0.0;
+    g.p2p_split = std::max(1, std::min(8, (int)std::ceil(mean_occ / (64.0 * g.p2p_tpl))));
     for (int lev = 2; lev <= g.depth; ++lev) {
       const int nb2 = 1 << lev;
       // valid (target, source) pairs for one parity class window, split into far and near
@@ -1073,8 +1085,12 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
   HIPCHK(h, hipMalloc(&h->d_phi, sizeof(double2) * h->n * nrhs));
   HIPCHK(h, hipMalloc(&h->d_phi_near, sizeof(double2) * h->n * nrhs));
   dfree(h->d_part);
-  if (sym_near(h->opt))
-    HIPCHK(h, hipMalloc(&h->d_part, (h->opt.precision == TEFMM_FP64 ? sizeof(double2) : sizeof(float2)) * 26 * h->n));
+  if (sym_near(h->opt)) {
+    int gmax = 1;
+    for (auto& g : h->groups) gmax = std::max(gmax, g.p2p_split);
+    HIPCHK(h, hipMalloc(&h->d_part,
+                        (h->opt.precision == TEFMM_FP64 ? sizeof(double2) : sizeof(float2)) * 13 * gmax * h->n));
+  }
   for (auto& g : h->groups) {
     g.alpha.assign(g.depth + 1, nullptr);
     g.beta.assign(g.depth + 1, nullptr);
@@ -1192,25 +1208,23 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       // several charge vectors share each pair kernel, 8 per block
       const bool multi = nrhs > 1;
       if (!multi && h->d_part) {
-        // each pair of particles in different leaves once (k_p2p_sym); targets per
-        // lane unless set: 2 above a mean leaf occupancy of 96 (4 holds more
-        // registers than it saves work), else 1
-        int tpl = h->opt.p2p_targets;
-        if (tpl == 0) tpl = wide ? 2 : 1;
-        // two workgroups per leaf (halves of its target passes), then one per leaf to gather
-        const dim3 grid2((unsigned)(2 * g.nbox[g.depth]), 1), grid((unsigned)g.nbox[g.depth], 1);
+        // each pair of particles in different leaves once (k_p2p_sym): 1 or 2 targets per
+        // lane (4 holds more registers than it saves work), G workgroups per leaf, then one
+        // per leaf to gather the source-side sums
+        const int tpl = g.p2p_tpl, G = g.p2p_split;
+        const dim3 grid2((unsigned)(G * g.nbox[g.depth]), 1), grid((unsigned)g.nbox[g.depth], 1);
         const int tp = 64 * tpl;
         if (fp32) {
-          void (*fs)(PassArgs, int, float2*) =
+          void (*fs)(PassArgs, int, int, float2*) =
               tpl == 1 ? k_p2p_sym<float, 1, 4> : tpl == 2 ? k_p2p_sym<float, 2, 4> : k_p2p_sym<float, 4, 4>;
-          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, (float2*)h->d_part);
+          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, G, (float2*)h->d_part);
           HIPCHK(h, hipGetLastError());
-          hipLaunchKernelGGL(k_p2p_sym_gather<float2>, grid, dim3(128), 0, sn, a, 1, tp, (const float2*)h->d_part);
+          hipLaunchKernelGGL(k_p2p_sym_gather<float2>, grid, dim3(128), 0, sn, a, 1, tp, G, (const float2*)h->d_part);
         } else {
-          void (*fs)(PassArgs, int, double2*) = tpl == 1 ? k_p2p_sym<double, 1, 4> : k_p2p_sym<double, 2, 4>;
-          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, (double2*)h->d_part);
+          void (*fs)(PassArgs, int, int, double2*) = tpl == 1 ? k_p2p_sym<double, 1, 4> : k_p2p_sym<double, 2, 4>;
+          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, G, (double2*)h->d_part);
           HIPCHK(h, hipGetLastError());
-          hipLaunchKernelGGL(k_p2p_sym_gather<double2>, grid, dim3(128), 0, sn, a, 1, tp, (const double2*)h->d_part);
+          hipLaunchKernelGGL(k_p2p_sym_gather<double2>, grid, dim3(128), 0, sn, a, 1, tp, G, (const double2*)h->d_part);
         }
         HIPCHK(h, hipGetLastError());
         continue;

@@ -1307,7 +1307,7 @@ __device__ __forceinline__ void p2p_sym8_f64(int t, const double (&tx)[T], const
 // Each wave stages, evaluates and writes its chunks' source-side sums on its
 // own; at the end of the pass the waves' target sums are added in wave order.
 template <typename R, int T, int NW>
-__global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, typename SymTypes<R>::R2* part) {
+__global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part) {
   typedef typename SymTypes<R>::R4 R4;
   typedef typename SymTypes<R>::R2 R2;
   constexpr bool F32 = std::is_same<R, float>::value;
@@ -1330,11 +1330,11 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, typen
   // FP64: k r <= pi/4 over the 3 x 3 x 3 leaf block (its longest pair: 2 sqrt(3) h)
   const bool small = a.k * 3.4641016151377546 * a.h <= 0.78539816339744831;
   const double2* q = a.q + (int64_t)r * a.n;
-  // two workgroups per leaf, half = 0 taking the target passes 0, 2, 4, ... and half = 1
-  // the passes 1, 3, 5, ... (more, shorter workgroups: less of a tail when the last ones
-  // run); each half keeps its own source-side sums, part[2 slot + half]
-  for (int wi = blockIdx.x; wi < 2 * nb * nb * nb; wi += gridDim.x) {
-    const int leaf = wi >> 1, half = wi & 1;
+  // G workgroups per leaf, the one with index `half` taking the target passes half,
+  // half + G, half + 2 G, ... (more, shorter workgroups: less of a tail when the last ones
+  // run); each keeps its own source-side sums, part[G slot + half]
+  for (int wi = blockIdx.x; wi < G * nb * nb * nb; wi += gridDim.x) {
+    const int leaf = wi / G, half = wi - leaf * G;
     const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
     const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
     if (half * TP >= cnt) continue;
@@ -1436,7 +1436,7 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, typen
                                                                            : iz - 1;
               slot = 3 * (rg - 1) + (zj - iz + 1);
             }
-            R2* dst = part + ((int64_t)(2 * slot + half) * nrhs + r) * a.n + j;
+            R2* dst = part + ((int64_t)(G * slot + half) * nrhs + r) * a.n + j;
             const bool first = c0 == half * TP;
             R2 v;
             v.x = first ? pr : dst->x + pr, v.y = first ? pi : dst->y + pi;
@@ -1464,9 +1464,9 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, typen
           if (act[k])
             a.phi[(int64_t)r * a.n + tbase + 64 * k] = make_double2((double)accr[k] * kap, (double)acci[k] * kap);
     };
-    // passes of 64 T targets (this half's: every second one); a last one of at most 64
+    // passes of 64 T targets (this workgroup's: every G-th one); a last one of at most 64
     // with one target per lane
-    for (int c0 = half * TP; c0 < cnt; c0 += 2 * TP) {
+    for (int c0 = half * TP; c0 < cnt; c0 += G * TP) {
       if (T > 1 && cnt - c0 <= 64)
         pass(std::integral_constant<int, 1>(), c0);
       else
@@ -1479,16 +1479,17 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, typen
 // neighbours A = B - o (o in the forward half, A inside the grid and not empty)
 // left in part, in slot order (see k_p2p_sym).
 template <typename R2>
-__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, const R2* part) {
+__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* part) {
   typedef decltype(R2::x) R;
   const int leaf = blockIdx.x, r = blockIdx.y;
   const int nb = a.nbox_dim;
   const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
   const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
   if (cnt == 0) return;
-  // have: A exists and holds particles; have2: A has more than tp targets, so its
-  // second workgroup wrote slot sums too
-  unsigned have = 0, have2 = 0;
+  // have: A exists and holds particles (and wrote slot sums from its workgroups with
+  // index below ceil(count / tp), at most G); count per slot in ca
+  unsigned have = 0;
+  int ca_s[13];
   for (int slot = 0; slot < 13; ++slot) {
     int dx = 0, dy = 0, dz = 1;
     if (slot < 12) fwd_column(slot / 3, &dx, &dy), dz = slot % 3 - 1;
@@ -1496,35 +1497,31 @@ __global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, const R2* part) {
     if (ax < 0 || ay < 0 || az < 0 || ax >= nb || ay >= nb || az >= nb) continue;
     const int ca = a.leaf_count[a.leaf_base + ((int64_t)ax * nb + ay) * nb + az];
     if (ca > 0) have |= 1u << slot;
-    if (ca > tp) have2 |= 1u << slot;
+    ca_s[slot] = ca;
   }
   // FP32 sums are in the scaled units of k_p2p_sym
   const double kap = sizeof(R) == 4 ? a.k / 6.283185307179586477 : 1.0;
   for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
     const int64_t j = start + c;
     R sr = 0, si = 0;
-    for (int slot = 0; slot < 13; ++slot) {
-      if ((have >> slot) & 1) {
-        const R2 v = part[((int64_t)(2 * slot) * nrhs + r) * a.n + j];
-        sr += v.x, si += v.y;
-      }
-      if ((have2 >> slot) & 1) {
-        const R2 v = part[((int64_t)(2 * slot + 1) * nrhs + r) * a.n + j];
-        sr += v.x, si += v.y;
-      }
-    }
+    for (int slot = 0; slot < 13; ++slot)
+      if ((have >> slot) & 1)
+        for (int hf = 0; hf < G && hf * tp < ca_s[slot]; ++hf) {
+          const R2 v = part[((int64_t)(G * slot + hf) * nrhs + r) * a.n + j];
+          sr += v.x, si += v.y;
+        }
     double2* o = a.phi + (int64_t)r * a.n + j;
     *o = make_double2(o->x + (double)sr * kap, o->y + (double)si * kap);
   }
 }
 
-template __global__ void k_p2p_sym<float, 1, 4>(PassArgs, int, float2*);
-template __global__ void k_p2p_sym<float, 2, 4>(PassArgs, int, float2*);
-template __global__ void k_p2p_sym<float, 4, 4>(PassArgs, int, float2*);
-template __global__ void k_p2p_sym<double, 1, 4>(PassArgs, int, double2*);
-template __global__ void k_p2p_sym<double, 2, 4>(PassArgs, int, double2*);
-template __global__ void k_p2p_sym_gather<float2>(PassArgs, int, int, const float2*);
-template __global__ void k_p2p_sym_gather<double2>(PassArgs, int, int, const double2*);
+template __global__ void k_p2p_sym<float, 1, 4>(PassArgs, int, int, float2*);
+template __global__ void k_p2p_sym<float, 2, 4>(PassArgs, int, int, float2*);
+template __global__ void k_p2p_sym<float, 4, 4>(PassArgs, int, int, float2*);
+template __global__ void k_p2p_sym<double, 1, 4>(PassArgs, int, int, double2*);
+template __global__ void k_p2p_sym<double, 2, 4>(PassArgs, int, int, double2*);
+template __global__ void k_p2p_sym_gather<float2>(PassArgs, int, int, int, const float2*);
+template __global__ void k_p2p_sym_gather<double2>(PassArgs, int, int, int, const double2*);
 
 template __global__ void k_p2p<double, 64, 1>(PassArgs, int);
 template __global__ void k_p2p<float, 64, 1>(PassArgs, int);

@@ -184,9 +184,9 @@ struct SymTypes<double> {
   typedef double2 R2;
 };
 template <typename R, int T, int NW>
-__global__ void k_p2p_sym(PassArgs a, int nrhs, typename SymTypes<R>::R2* part);
+__global__ void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part);
 template <typename R2>
-__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, const R2* part);
+__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* part);
 
 // M2L launcher (picks the row-block instantiation for nRB).
 hipError_t launch_m2l(const M2LArgs& a, int nrhs, bool fp32, hipStream_t s);
