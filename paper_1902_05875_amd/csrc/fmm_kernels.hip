@@ -1009,20 +1009,20 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
 
 // ---------------------------------------------------------------------------
 // Near field with each pair of particles in different leaves evaluated once
-// (FP32, one charge vector).  The free-space kernel e^{ikr}/r is symmetric in
-// its two points, so the pair (i, j) adds q_j G to phi_i and q_i G to phi_j.
-// Of the 26 neighbour leaves of a leaf A only the forward half is visited: the
-// columns (dx, dy) = (0, 1), (1, -1), (1, 0), (1, 1) with dz = -1, 0, 1 (slots
-// 3 c + dz + 1, c the column) and the leaf (0, 0, 1) (slot 12); A's own leaf is
-// done in full.  The workgroup of A adds the q_j G terms to its targets in
-// registers; the q_i G terms for a source j of a forward neighbour B are
-// summed over A's targets (per wave, a transposing butterfly over the 64
-// lanes, sixteen sources at a time; then over the waves in LDS, in a fixed
-// order) and written to part[slot][j].  k_p2p_sym_gather then adds to each
-// particle of B the slots of its existing, non-empty backward neighbours, in
-// slot order: the result is deterministic.
-// Near-singular pairs (closer than 5% of the leaf side) get G from FP64
-// coordinates, rounded to FP32; the pair with itself gets 0.
+// (one charge vector, FP32 or FP64).  The free-space kernel e^{ikr}/r is
+// symmetric in its two points, so the pair (i, j) adds q_j G to phi_i and q_i G
+// to phi_j.  Of the 26 neighbour leaves of a leaf A only the forward half is
+// visited: the columns (dx, dy) = (0, 1), (1, -1), (1, 0), (1, 1) with
+// dz = -1, 0, 1 (slots 3 c + dz + 1, c the column) and the leaf (0, 0, 1)
+// (slot 12); A's own leaf is done in full.  A workgroup of A adds the q_j G terms
+// to its targets in registers; the q_i G terms for a source j of a forward
+// neighbour B are summed over the pass's targets (per wave, a transposing
+// butterfly over the 64 lanes, eight sources at a time) and written to
+// part[G slot + h][j] (h the workgroup's index among A's G).  k_p2p_sym_gather
+// then adds to each particle of B the slots of its existing, non-empty backward
+// neighbours, in slot order: the result is deterministic.
+// FP32: near-singular pairs (closer than 5% of the leaf side) get G from FP64
+// coordinate differences; in both precisions the pair with itself gets 0.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void fwd_column(int c, int* dx, int* dy) {
   *dx = c == 0 ? 0 : 1;
@@ -1301,9 +1301,10 @@ __device__ __forceinline__ void p2p_sym8_f64(int t, const double (&tx)[T], const
   }
 }
 
-// One workgroup per leaf A, T targets per lane: the 64 T targets of a pass are
-// the same for the NW waves, which share out the staged source chunks (SC
-// sources; chunk c of the pass, counted over the ranges, goes to wave c mod NW).
+// G workgroups per leaf A (each taking every G-th pass), T targets per lane: the
+// 64 T targets of a pass are the same for the NW waves, which share out the staged
+// source chunks (SC sources; chunk c of the pass, counted over the ranges, goes to
+// wave c mod NW).
 // Each wave stages, evaluates and writes its chunks' source-side sums on its
 // own; at the end of the pass the waves' target sums are added in wave order.
 template <typename R, int T, int NW>
