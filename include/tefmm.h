@@ -100,9 +100,9 @@ typedef struct {
 /* Timings (ms, measured with HIP events; averages over the evaluations since
  * the last tefmm_reset_timers, at most the last 64) and counters.  The far
  * field (P2M .. L2P) runs on the caller's stream; the near field (P2P) runs
- * concurrently on a second stream of the handle, joined before the final
- * scaling, so t_p2p_ms overlaps the far-field phases and t_total_ms is the
- * whole evaluation. */
+ * concurrently on a second stream of the handle (by default; see
+ * tefmm_autotune), joined before the final scaling, so t_p2p_ms overlaps the
+ * far-field phases and t_total_ms is the whole evaluation. */
 typedef struct {
   double t_setup_tree_ms, t_setup_tables_ms, t_setup_dcim_ms;
   double t_p2m_ms, t_m2m_ms, t_m2l_ms, t_l2l_ms, t_l2p_ms, t_p2p_ms, t_total_ms;
@@ -156,9 +156,10 @@ int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz_soa, int on_devi
  * (re, im), column-major n x n_rhs (vector r starts at q + 2*n*r).
  * phi: device, same layout, written (not accumulated), in the caller's
  * particle order.  Stream ordered on `stream`: the near field forks to the
- * handle's second stream after the charges are read and joins back before the
- * result is written, by events (when `stream` is being captured into a graph
- * the near field stays on `stream`).  Returns after enqueueing (call
+ * handle's second stream (after the charges are read, or after the upward
+ * pass: by default in FP64; the autotuner may also keep it on `stream`) and
+ * joins back before the result is written, by events (when `stream` is being
+ * captured into a graph the near field stays on `stream`).  Returns after enqueueing (call
  * hipStreamSynchronize to wait). */
 int tefmm_evaluate(tefmm_t h, const double* q, int n_rhs, double* phi, void* stream);
 
