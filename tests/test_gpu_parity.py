@@ -74,6 +74,19 @@ def test_n20k_sampled(p, tol):
     assert e < tol
 
 
+@pytest.mark.parametrize("tile", [1, 2])
+def test_n20k_fp64_p13_tiles(tile):
+    """FP64 p = 13 (196 reduced moments: staged in runs) with 16 and 32 targets per M2L
+    workgroup (two phases of source moments, and one phase in 136 KiB of LDS)."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c2", n=20_000)
+    idx, ref = _expected("n20k")
+    phi, st = _run(xyz, q, p=13, m2l_tile=tile)
+    e = _err(phi[idx], ref)
+    print(f"N=20k p=13 tile {tile} depth {st['depth'][0]} rel err {e:.3e}")
+    assert e < 1e-6
+
+
 @pytest.mark.parametrize("p,precision,tol", [(8, "fp64", 3e-5), (12, "fp64", 1e-6), (8, "fp32", 1e-4)])
 def test_c2_sampled(p, precision, tol):
     """N = 200,000 mid-layer cube (adaptive depth 4), 64 sampled targets incl. the 16 closest to an
