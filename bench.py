@@ -119,6 +119,7 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload, surrogate=
         "p2p_flops": _p2p_flops(st, precision, q), "p2p_sym": _p2p_sym(precision, q),
         "n_groups": sum(1 for d in st["depth"] if d),
         "images": st["n_images"], "p2p_pairs": st["p2p_pairs"], "p2p_pairs_same_leaf": st["p2p_pairs_same_leaf"],
+        "p2p_poly_err": st["p2p_poly_err"],
         "rel_err_sampled": err, "n_checked": nchk, "t_setup_tables_ms": st["t_setup_tables_ms"],
         "sigma_keys": st["sigma_keys"], "surrogate_keys": st["surrogate_keys"], "surrogate": sur_info,
         "cross_pairs": st["cross_pairs"], "autotune": tuned, "workload": workload,
@@ -171,7 +172,8 @@ def roofline(head):
         same = head["p2p_pairs_same_leaf"]
         what = (f"k_p2p_sym<{'float' if prec == 'fp32' else 'double'}> + k_p2p_sym_gather (vector ALU), {n_launch} launch(es)/step, avg "
                 f"{ph['p2p'] / n_launch:.3f} ms; {P2P_FLOPS_PER_SYM_PAIR} flop x {(head['p2p_pairs'] - same) // 2} "
-                f"cross-leaf pairs (each once) + {P2P_FLOPS_PER_PAIR} flop x {same} same-leaf ordered pairs")
+                f"cross-leaf pairs (each once) + {P2P_FLOPS_PER_PAIR} flop x {same} same-leaf ordered pairs"
+                + (" (FP32 pair value from quadratics in r^2)" if head.get("p2p_poly_err") else ""))
     else:
         what = (f"k_p2p<{'float' if prec == 'fp32' else 'double'}> (vector ALU), {n_launch} launch(es)/step, "
                 f"avg {ph['p2p'] / n_launch:.3f} ms; {P2P_FLOPS_PER_PAIR} flop per pair x {head['p2p_pairs']} pairs")

@@ -95,6 +95,11 @@ typedef struct {
                          rejected); 0 = that kernel with 2 targets per lane above a mean leaf
                          occupancy of 96, else 1; -1 = every ordered pair evaluated on its own
                          (also the kernel for several charge vectors) */
+  int p2p_poly;       /* FP32 near field with one charge vector: 0 = the pair value e^{ikr}/r from
+                         two quadratics in r^2 fitted on the host over the distances of a leaf's
+                         3 x 3 x 3 block (k r is small there), used where the fit is within 3e-7 of
+                         cos(k r) and sin(k r) (see p2p_poly_err; else, and with -1, the hardware
+                         sine and cosine) */
 } tefmm_options;
 
 /* Timings (ms, measured with HIP events; averages over the evaluations since
@@ -125,6 +130,8 @@ typedef struct {
   int64_t surrogate_keys; /* of those, rows produced by the attached surrogate network */
   int timed_evaluations; /* evaluations the phase times t_p2m_ms .. t_total_ms average over */
   int64_t p2p_pairs_same_leaf; /* of p2p_pairs, the ordered pairs inside one leaf */
+  double p2p_poly_err;   /* largest error of the near-field quadratics in use (of cos(k r) and of
+                            r sin(k r) / r, relative to the pair value's size 1/r); 0 if none */
 } tefmm_stats;
 
 /* Fill an options struct with the defaults (p = 8, depth auto, max_leaf 64,

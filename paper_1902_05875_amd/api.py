@@ -47,7 +47,7 @@ class OptionsC(ctypes.Structure):
                 ("precision", ctypes.c_int), ("normalization", ctypes.c_int), ("dcim_T1", ctypes.c_double),
                 ("dcim_samples", ctypes.c_int), ("dcim_svd_tol", ctypes.c_double),
                 ("interface_eps", ctypes.c_double), ("n_rhs_max", ctypes.c_int), ("dcim_T1_cross", ctypes.c_double),
-                ("m2l_tile", ctypes.c_int), ("p2p_targets", ctypes.c_int)]
+                ("m2l_tile", ctypes.c_int), ("p2p_targets", ctypes.c_int), ("p2p_poly", ctypes.c_int)]
 
 
 class StatsC(ctypes.Structure):
@@ -59,7 +59,8 @@ class StatsC(ctypes.Structure):
         ("m2l_flops", ctypes.c_double), ("m2l_launches", ctypes.c_int), ("n_rhs", ctypes.c_int),
         ("cross_pairs", ctypes.c_int64), ("cross_pairs_forced", ctypes.c_int64), ("n_cross_fits", ctypes.c_int),
         ("cross_fit_err", ctypes.c_double), ("sigma_keys", ctypes.c_int64), ("surrogate_keys", ctypes.c_int64),
-        ("timed_evaluations", ctypes.c_int), ("p2p_pairs_same_leaf", ctypes.c_int64)]
+        ("timed_evaluations", ctypes.c_int), ("p2p_pairs_same_leaf", ctypes.c_int64),
+        ("p2p_poly_err", ctypes.c_double)]
 
 
 class SurOptionsC(ctypes.Structure):

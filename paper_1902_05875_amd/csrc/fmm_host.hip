@@ -38,6 +38,63 @@ namespace {
 
 const double PI = 3.14159265358979323846;
 
+// Solve the 3 x 3 system A x = b (Cramer's rule; A symmetric positive definite here).
+void solve3(const double (&A)[3][3], const double (&b)[3], double (&x)[3]) {
+  auto det = [](const double (&M)[3][3]) {
+    return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+           M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+  };
+  const double d = det(A);
+  for (int c = 0; c < 3; ++c) {
+    double M[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M[i][j] = j == c ? b[i] : A[i][j];
+    x[c] = det(M) / d;
+  }
+}
+
+// The FP32 near field's pair value in scaled units (r = k |x - y| / (2 pi)) is
+// cos(2 pi r) / r + i sin(2 pi r) / r.  Over a leaf's 3 x 3 x 3 block r stays below
+// rmax = 2 sqrt(3) h k / (2 pi), where both cos(2 pi r) and sin(2 pi r) / r are smooth
+// functions of s = r^2 with rapidly falling Taylor terms; fit each by a quadratic in s
+// (least squares at 64 Chebyshev points of [0, rmax^2], in t = s / rmax^2), then take
+// the largest error of the FP32-rounded coefficients over 4097 points, as a fraction of
+// the pair value's size 1/r: |cos error| and r |sine error|.  Returns whether it is
+// within tol.
+bool fit_near_poly(double k, double h, double tol, NearPoly* np, double* err) {
+  const double rmax = 2.0 * std::sqrt(3.0) * h * k / (2.0 * PI) * (1.0 + 1e-6);
+  const double S = rmax * rmax;
+  auto fc = [](double s) { return std::cos(2.0 * PI * std::sqrt(s)); };
+  auto fs = [](double s) {
+    const double r = std::sqrt(s);
+    return r > 0 ? std::sin(2.0 * PI * r) / r : 2.0 * PI;
+  };
+  double A[3][3] = {}, bc[3] = {}, bs[3] = {};
+  const int m = 64;
+  for (int i = 0; i < m; ++i) {
+    const double t = 0.5 - 0.5 * std::cos(PI * (i + 0.5) / m);
+    const double ph[3] = {1.0, t, t * t};
+    for (int u = 0; u < 3; ++u) {
+      for (int v = 0; v < 3; ++v) A[u][v] += ph[u] * ph[v];
+      bc[u] += ph[u] * fc(t * S), bs[u] += ph[u] * fs(t * S);
+    }
+  }
+  double xc[3], xs[3];
+  solve3(A, bc, xc);
+  solve3(A, bs, xs);
+  np->c0 = (float)xc[0], np->c1 = (float)(xc[1] / S), np->c2 = (float)(xc[2] / (S * S));
+  np->s0 = (float)xs[0], np->s1 = (float)(xs[1] / S), np->s2 = (float)(xs[2] / (S * S));
+  double e = 0;
+  for (int i = 0; i <= 4096; ++i) {
+    const double s = S * i / 4096.0, r = std::sqrt(s);
+    const double pc = ((double)np->c2 * s + np->c1) * s + np->c0;
+    const double ps = ((double)np->s2 * s + np->s1) * s + np->s0;
+    e = std::max(e, std::max(std::fabs(pc - fc(s)), r * std::fabs(ps - fs(s))));
+  }
+  *err = e;
+  return std::isfinite(e) && e <= tol;
+}
+
 struct Group {
   int layer = 0, depth = 2;
   double lo[3] = {0, 0, 0}, side = 1;
@@ -66,6 +123,10 @@ struct Group {
   // symmetric near field: targets per lane and workgroups per leaf (each taking every
   // p2p_split-th pass of 64 p2p_tpl targets), from the leaf occupancy
   int p2p_tpl = 1, p2p_split = 1;
+  // FP32 near-field pair value from quadratics in r^2 (np_on) and the fit's error
+  NearPoly np{};
+  bool np_on = false;
+  double np_err = 0;
   int n_cross_fits = 0;
   double cross_fit_err = 0;
   bool has_cross = false;
@@ -316,7 +377,7 @@ extern "C" int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefm
       !(o.interface_eps >= 0) || o.n_rhs_max < 1 ||
       !(o.p2p_targets == -1 || o.p2p_targets == 0 || o.p2p_targets == 1 || o.p2p_targets == 2 ||
         o.p2p_targets == 4) ||
-      (o.precision == TEFMM_FP64 && o.p2p_targets == 4)) {
+      (o.precision == TEFMM_FP64 && o.p2p_targets == 4) || !(o.p2p_poly == 0 || o.p2p_poly == -1)) {
     delete h;
     return TEFMM_ERR_INVALID_ARG;
   }
@@ -969,6 +1030,9 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     g.p2p_tpl = h->opt.p2p_targets > 0 ? h->opt.p2p_targets : (g.count > 96 * nleaf ? 2 : 1);
     const double mean_occ = occ ? (double)g.count / (double)occ : 0.0;
     g.p2p_split = std::max(1, std::min(8, (int)std::ceil(mean_occ / (64.0 * g.p2p_tpl))));
+    g.np_err = 0;
+    g.np_on = h->opt.p2p_poly == 0 &&
+              fit_near_poly(h->med.k[g.layer], g.side / (double)(1 << g.depth), 3e-7, &g.np, &g.np_err);
     for (int lev = 2; lev <= g.depth; ++lev) {
       const int nb2 = 1 << lev;
       // valid (target, source) pairs for one parity class window, split into far and near
@@ -1054,6 +1118,10 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   }
   h->st.p2p_pairs = h->p2p_pairs;
   h->st.p2p_pairs_same_leaf = h->p2p_same;
+  h->st.p2p_poly_err = 0;
+  if (h->opt.precision == TEFMM_MIXED_FP32)
+    for (auto& g : h->groups)
+      if (g.np_on) h->st.p2p_poly_err = std::max(h->st.p2p_poly_err, g.np_err);
   h->st.m2l_pairs = h->m2l_pairs;
   h->ready = true;
   h->gen = g_generation++;
@@ -1215,14 +1283,18 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
         const dim3 grid2((unsigned)(G * g.nbox[g.depth]), 1), grid((unsigned)g.nbox[g.depth], 1);
         const int tp = 64 * tpl;
         if (fp32) {
-          void (*fs)(PassArgs, int, int, float2*) =
-              tpl == 1 ? k_p2p_sym<float, 1, 4> : tpl == 2 ? k_p2p_sym<float, 2, 4> : k_p2p_sym<float, 4, 4>;
-          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, G, (float2*)h->d_part);
+          void (*fs)(PassArgs, int, int, float2*, NearPoly) =
+              g.np_on ? (tpl == 1 ? k_p2p_sym<float, 1, 4, true> : tpl == 2 ? k_p2p_sym<float, 2, 4, true>
+                                                                           : k_p2p_sym<float, 4, 4, true>)
+                      : (tpl == 1 ? k_p2p_sym<float, 1, 4, false> : tpl == 2 ? k_p2p_sym<float, 2, 4, false>
+                                                                            : k_p2p_sym<float, 4, 4, false>);
+          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, G, (float2*)h->d_part, g.np);
           HIPCHK(h, hipGetLastError());
           hipLaunchKernelGGL(k_p2p_sym_gather<float2>, grid, dim3(128), 0, sn, a, 1, tp, G, (const float2*)h->d_part);
         } else {
-          void (*fs)(PassArgs, int, int, double2*) = tpl == 1 ? k_p2p_sym<double, 1, 4> : k_p2p_sym<double, 2, 4>;
-          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, G, (double2*)h->d_part);
+          void (*fs)(PassArgs, int, int, double2*, NearPoly) =
+              tpl == 1 ? k_p2p_sym<double, 1, 4, false> : k_p2p_sym<double, 2, 4, false>;
+          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, G, (double2*)h->d_part, g.np);
           HIPCHK(h, hipGetLastError());
           hipLaunchKernelGGL(k_p2p_sym_gather<double2>, grid, dim3(128), 0, sn, a, 1, tp, G, (const double2*)h->d_part);
         }

@@ -810,6 +810,19 @@ __device__ __forceinline__ void pair_kernel(float r2, float, float* er, float* e
   const float rv = r2 * ri;
   *er = __builtin_amdgcn_cosf(rv) * ri, *ei = __builtin_amdgcn_sinf(rv) * ri;
 }
+// The same value with cos(2 pi r) and sin(2 pi r) / r from quadratics in r2 fitted
+// over the distances at hand (POLY): one transcendental (the reciprocal square root)
+// and five multiply-adds in place of three transcendentals and three products.
+template <bool POLY>
+__device__ __forceinline__ void pair_value(float r2, const NearPoly& np, float* er, float* ei) {
+  if (POLY) {
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    *er = fmaf(fmaf(np.c2, r2, np.c1), r2, np.c0) * ri;
+    *ei = fmaf(fmaf(np.s2, r2, np.s1), r2, np.s0);
+  } else {
+    pair_kernel(r2, 0.0f, er, ei);
+  }
+}
 
 // FP64 pair loop over m staged sources (see k_p2p).
 template <int RB, bool SMALL, bool SELF, typename T>
@@ -1055,13 +1068,13 @@ __device__ __forceinline__ float sym_r2(float tx, float ty, float tz, const floa
 // in nl (a bit mask per step and lane) and, after the eight sources, taken one
 // by one: the value used is replaced by the one from FP64 differences, its
 // source-side part added to dps[2 (t + u) + c].
-template <int T, bool SYM>
+template <int T, bool SYM, bool POLY>
 __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T], const float (&ty)[T],
                                          const float (&tz)[T], const float (&qri)[T], const float (&qii)[T],
                                          const bool (&act)[T], const float4* s4, const float* sqi,
                                          const int* sidx, float rns2, float eps2, double kap2,
                                          const PassArgs& a, float (&accr)[T], float (&acci)[T], float* psw,
-                                         float* dps, int* nl) {
+                                         float* dps, int* nl, const NearPoly& np) {
   const int lane = threadIdx.x & 63;
   // a vector value, not an array: the butterfly's selects stay selects of values
   typedef float f16v __attribute__((ext_vector_type(16)));
@@ -1089,7 +1102,7 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
           used = __int_as_float(max(__float_as_int(r2[u][k]), __float_as_int(rns2)));
         }
         float er, ei;
-        pair_kernel(used, 0.0f, &er, &ei);
+        pair_value<POLY>(used, np, &er, &ei);
         if (!SYM && !(r2[u][k] > 0.0f)) er = 0.0f, ei = 0.0f;
         accr[k] = fmaf(qr, er, fmaf(-qi, ei, accr[k]));
         acci[k] = fmaf(qr, ei, fmaf(qi, er, acci[k]));
@@ -1189,10 +1202,10 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
           if (j >= 0 && j != i) {
             const double ex = a.xs[i] - a.xs[j], ey = a.xs[a.n + i] - a.xs[a.n + j],
                          ez = a.xs[2 * a.n + i] - a.xs[2 * a.n + j];
-            pair_kernel((float)((ex * ex + ey * ey + ez * ez) * kap2), 0.0f, &er, &ei);
+            pair_value<POLY>((float)((ex * ex + ey * ey + ez * ez) * kap2), np, &er, &ei);
           }
           float ur, ui;  // the value used above
-          pair_kernel(sym_r2<SYM>(tx[k], ty[k], tz[k], s4[t + uu], eps2, rns2), 0.0f, &ur, &ui);
+          pair_value<POLY>(sym_r2<SYM>(tx[k], ty[k], tz[k], s4[t + uu], eps2, rns2), np, &ur, &ui);
           const float der = er - ur, dei = ei - ui;
           const float qr = s4[t + uu].w, qi = sqi[t + uu];
           accr[k] = fmaf(qr, der, fmaf(-qi, dei, accr[k]));
@@ -1307,8 +1320,9 @@ __device__ __forceinline__ void p2p_sym8_f64(int t, const double (&tx)[T], const
 // wave c mod NW).
 // Each wave stages, evaluates and writes its chunks' source-side sums on its
 // own; at the end of the pass the waves' target sums are added in wave order.
-template <typename R, int T, int NW>
-__global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part) {
+template <typename R, int T, int NW, bool POLY>
+__global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part,
+                                                     NearPoly np) {
   typedef typename SymTypes<R>::R4 R4;
   typedef typename SymTypes<R>::R2 R2;
   constexpr bool F32 = std::is_same<R, float>::value;
@@ -1401,13 +1415,13 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G
           if constexpr (F32) {
             if (rg == 0) {
               for (int t = 0; t < mu; t += 8)
-                p2p_sym8<TT, false>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2,
-                                    kap * kap, a, accr, acci, psw[w], dps[w], nl[w]);
+                p2p_sym8<TT, false, POLY>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2,
+                                          eps2, kap * kap, a, accr, acci, psw[w], dps[w], nl[w], np);
               continue;
             }
             for (int t = 0; t < mu; t += 8)
-              p2p_sym8<TT, true>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2,
-                                 kap * kap, a, accr, acci, psw[w], dps[w], nl[w]);
+              p2p_sym8<TT, true, POLY>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2,
+                                       kap * kap, a, accr, acci, psw[w], dps[w], nl[w], np);
           } else {
             if (rg == 0) {
               for (int t = 0; t < mu; t += 8) {
@@ -1516,11 +1530,14 @@ __global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* 
   }
 }
 
-template __global__ void k_p2p_sym<float, 1, 4>(PassArgs, int, int, float2*);
-template __global__ void k_p2p_sym<float, 2, 4>(PassArgs, int, int, float2*);
-template __global__ void k_p2p_sym<float, 4, 4>(PassArgs, int, int, float2*);
-template __global__ void k_p2p_sym<double, 1, 4>(PassArgs, int, int, double2*);
-template __global__ void k_p2p_sym<double, 2, 4>(PassArgs, int, int, double2*);
+template __global__ void k_p2p_sym<float, 1, 4, false>(PassArgs, int, int, float2*, NearPoly);
+template __global__ void k_p2p_sym<float, 2, 4, false>(PassArgs, int, int, float2*, NearPoly);
+template __global__ void k_p2p_sym<float, 4, 4, false>(PassArgs, int, int, float2*, NearPoly);
+template __global__ void k_p2p_sym<float, 1, 4, true>(PassArgs, int, int, float2*, NearPoly);
+template __global__ void k_p2p_sym<float, 2, 4, true>(PassArgs, int, int, float2*, NearPoly);
+template __global__ void k_p2p_sym<float, 4, 4, true>(PassArgs, int, int, float2*, NearPoly);
+template __global__ void k_p2p_sym<double, 1, 4, false>(PassArgs, int, int, double2*, NearPoly);
+template __global__ void k_p2p_sym<double, 2, 4, false>(PassArgs, int, int, double2*, NearPoly);
 template __global__ void k_p2p_sym_gather<float2>(PassArgs, int, int, int, const float2*);
 template __global__ void k_p2p_sym_gather<double2>(PassArgs, int, int, int, const double2*);
 

@@ -183,8 +183,14 @@ struct SymTypes<double> {
   typedef double4 R4;
   typedef double2 R2;
 };
-template <typename R, int T, int NW>
-__global__ void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part);
+// Coefficients of the FP32 near-field pair value as quadratics in s = r^2 (scaled
+// units, r = k |x - y| / (2 pi)): cos(2 pi r) ~ c0 + c1 s + c2 s^2 and
+// sin(2 pi r) / r ~ s0 + s1 s + s2 s^2.
+struct NearPoly {
+  float c0, c1, c2, s0, s1, s2;
+};
+template <typename R, int T, int NW, bool POLY>
+__global__ void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part, NearPoly np);
 template <typename R2>
 __global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* part);
 

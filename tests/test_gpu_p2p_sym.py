@@ -112,3 +112,31 @@ def test_sym_fp64_empty_leaves_and_deterministic():
     print(f"FP64 clusters, symmetric vs one-sided: rel diff {e:.3e}")
     assert e < 1e-12
     assert np.array_equal(a1, a2)
+
+
+@pytest.mark.parametrize("depth,tpl", [(4, 1), (4, 2), (3, 2)])
+def test_poly_pair_value(depth, tpl):
+    """FP32 near field with the pair value from quadratics in r^2 (the default where their
+    fit is within 3e-7) against the hardware sine and cosine, close pairs included.  At
+    depth 3 the mid layer's k r over a leaf block is too large for the fit: both runs then
+    take the hardware path and agree bitwise."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c2", n=60_000)
+    xyz, q, _ = inputs.with_close_pairs(xyz, q, 16, 1e-6, seed=9)
+    a, sa = _run(xyz, q, p=6, precision="fp32", depth=depth, p2p_targets=tpl)
+    b, sb = _run(xyz, q, p=6, precision="fp32", depth=depth, p2p_targets=tpl, p2p_poly=-1)
+    e = _rel(a, b)
+    print(f"depth {depth}, {tpl} targets/lane: fit error {sa['p2p_poly_err']:.2e}, rel diff {e:.3e}")
+    assert sb["p2p_poly_err"] == 0
+    if depth == 4:
+        assert 0 < sa["p2p_poly_err"] <= 3e-7
+        assert e < 1e-6
+    else:
+        assert sa["p2p_poly_err"] == 0
+        assert np.array_equal(a, b)
+
+
+def test_poly_option_checked():
+    from paper_1902_05875_amd import api
+    with pytest.raises(api.TefmmError):
+        api.TEFMM(K3, D3, p=6, precision="fp32", p2p_poly=1)
