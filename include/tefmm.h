@@ -95,7 +95,7 @@ typedef struct {
                          rejected); 0 = that kernel with 2 targets per lane above a mean leaf
                          occupancy of 96, else 1; -1 = every ordered pair evaluated on its own
                          (also the kernel for several charge vectors) */
-  int p2p_poly;       /* FP32 near field with one charge vector: 0 = the pair value e^{ikr}/r from
+  int p2p_poly;       /* FP32 near field (both kernels): 0 = the pair value e^{ikr}/r from
                          two quadratics in r^2 fitted on the host over the distances of a leaf's
                          3 x 3 x 3 block (k r is small there), used where the fit is within 3e-7 of
                          cos(k r) and sin(k r) (see p2p_poly_err; else, and with -1, the hardware

@@ -1302,13 +1302,17 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
         continue;
       }
       const dim3 grid((unsigned)g.nbox[g.depth], multi ? (nrhs + 7) / 8 : 1);
-      void (*fn)(PassArgs, int) = nullptr;
-      if (fp32)
-        fn = wide ? (multi ? k_p2p<float, 256, 8> : k_p2p<float, 256, 1>) : (multi ? k_p2p<float, 64, 8> : k_p2p<float, 64, 1>);
+      void (*fn)(PassArgs, int, NearPoly) = nullptr;
+      if (fp32 && g.np_on)
+        fn = wide ? (multi ? k_p2p<float, 256, 8, true> : k_p2p<float, 256, 1, true>)
+                  : (multi ? k_p2p<float, 64, 8, true> : k_p2p<float, 64, 1, true>);
+      else if (fp32)
+        fn = wide ? (multi ? k_p2p<float, 256, 8, false> : k_p2p<float, 256, 1, false>)
+                  : (multi ? k_p2p<float, 64, 8, false> : k_p2p<float, 64, 1, false>);
       else
-        fn = wide ? (multi ? k_p2p<double, 256, 8> : k_p2p<double, 256, 1>)
-                  : (multi ? k_p2p<double, 64, 8> : k_p2p<double, 64, 1>);
-      hipLaunchKernelGGL(fn, grid, dim3(wide ? 256 : 64), 0, sn, a, nrhs);
+        fn = wide ? (multi ? k_p2p<double, 256, 8, false> : k_p2p<double, 256, 1, false>)
+                  : (multi ? k_p2p<double, 64, 8, false> : k_p2p<double, 64, 1, false>);
+      hipLaunchKernelGGL(fn, grid, dim3(wide ? 256 : 64), 0, sn, a, nrhs, g.np);
       HIPCHK(h, hipGetLastError());
     }
     if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + 6], sn));

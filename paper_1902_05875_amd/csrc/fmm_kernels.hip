@@ -860,12 +860,12 @@ __device__ __forceinline__ void p2p_f64_rows(int m, T tx, T ty, T tz, const T* s
 // four at a time and one wave-wide test per four decides whether any lane met
 // such a pair; only then (rare) the known FP32 term is taken back in FP64 and
 // the pair redone in FP64 from the stored coordinates (the pair with itself: 0).
-template <int RB>
+template <int RB, bool POLY>
 __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz, const float4* s4,
                                              const float (*sq)[2 * RB], const int* sidx, float rns2, float ecr,
                                              float eci, double kap, const PassArgs& a, int64_t i, double txd,
                                              double tyd, double tzd, int r0, int nrhs, float* accr, float* acci,
-                                             double* nsr, double* nsi) {
+                                             double* nsr, double* nsi, const NearPoly& np) {
   // a pair at distance 0 (a particle with itself) gets weight 0 in the FP32 sum; pairs
   // with 0 < r2 < rns2 are taken back and redone in FP64
   const unsigned near_lim = (unsigned)__float_as_int(rns2) - 1u;
@@ -890,7 +890,7 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
   auto pair = [&](int t, float r2) {
     // max of two non-negative floats as the max of their bit patterns (no canonicalising)
     float er, ei;
-    pair_kernel(__int_as_float(max(__float_as_int(r2), __float_as_int(rns2))), 0.0f, &er, &ei);
+    pair_value<POLY>(__int_as_float(max(__float_as_int(r2), __float_as_int(rns2))), np, &er, &ei);
     if (!(r2 > 0.0f)) er = 0.0f, ei = 0.0f;
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
@@ -931,8 +931,8 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
 
 // RB charge vectors per block (blockIdx.y = group of RB): the pair kernel is
 // computed once and applied to all of them, in the same order as for one vector.
-template <typename T, int BS, int RB>
-__global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
+template <typename T, int BS, int RB, bool POLY>
+__global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs, NearPoly np) {
   constexpr bool F32 = sizeof(T) == 4;
   // FP64 sources as three coordinate arrays; FP32 sources as (x, y, z, unused)
   __shared__ T sx[F32 ? 1 : BS], sy[F32 ? 1 : BS], sz[F32 ? 1 : BS];
@@ -949,7 +949,7 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
   const float rns2 = (float)(0.0025 * a.h * a.h * kap * kap);
   // the FP32 pair term at squared distance rns2, as every lane computes it
   float ecr = 0.0f, eci = 0.0f;
-  if (F32) pair_kernel(rns2, 0.0f, &ecr, &eci);
+  if (F32) pair_value<POLY>(rns2, np, &ecr, &eci);
   const int z0 = max(iz - 1, 0), z1 = min(iz + 1, nb - 1);
   // largest k r in the 3 x 3 x 3 leaf block: the corners of a 2 x 2 x 2 span, sqrt(3) 2 h
   const bool small = a.k * 3.4641016151377546 * a.h <= 0.78539816339744831;
@@ -990,8 +990,8 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs) {
         __syncthreads();
         if (!act) continue;
         if constexpr (F32) {
-          p2p_f32_rows<RB>(m, tx, ty, tz, s4, sq, sidx, rns2, ecr, eci, kap, a, i, txd, tyd, tzd, r0, nrhs, accr,
-                           acci, nsr, nsi);
+          p2p_f32_rows<RB, POLY>(m, tx, ty, tz, s4, sq, sidx, rns2, ecr, eci, kap, a, i, txd, tyd, tzd, r0, nrhs,
+                                 accr, acci, nsr, nsi, np);
         } else {
           // Only the centre column holds the target itself; there the pair with
           // r2 = 0 (same coordinates, same arithmetic) gets weight 0, branch free.
@@ -1541,14 +1541,18 @@ template __global__ void k_p2p_sym<double, 2, 4, false>(PassArgs, int, int, doub
 template __global__ void k_p2p_sym_gather<float2>(PassArgs, int, int, int, const float2*);
 template __global__ void k_p2p_sym_gather<double2>(PassArgs, int, int, int, const double2*);
 
-template __global__ void k_p2p<double, 64, 1>(PassArgs, int);
-template __global__ void k_p2p<float, 64, 1>(PassArgs, int);
-template __global__ void k_p2p<double, 256, 1>(PassArgs, int);
-template __global__ void k_p2p<float, 256, 1>(PassArgs, int);
-template __global__ void k_p2p<double, 64, 8>(PassArgs, int);
-template __global__ void k_p2p<float, 64, 8>(PassArgs, int);
-template __global__ void k_p2p<double, 256, 8>(PassArgs, int);
-template __global__ void k_p2p<float, 256, 8>(PassArgs, int);
+template __global__ void k_p2p<double, 64, 1, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 64, 1, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 64, 1, true>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<double, 256, 1, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 256, 1, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 256, 1, true>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<double, 64, 8, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 64, 8, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 64, 8, true>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<double, 256, 8, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 256, 8, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 256, 8, true>(PassArgs, int, NearPoly);
 
 // ---------------------------------------------------------------------------
 // Surrogate tables.  Entry g of a reaction table at (x, y, S) is scaled by the

@@ -169,8 +169,14 @@ __global__ void k_expand_z_add(ReduceArgs a);
 __global__ void k_m2m(PassArgs a);
 __global__ void k_l2l(PassArgs a);
 __global__ void k_l2p(PassArgs a);
-template <typename T, int BS, int RB>
-__global__ void k_p2p(PassArgs a, int nrhs);
+// Coefficients of the FP32 near-field pair value as quadratics in s = r^2 (scaled
+// units, r = k |x - y| / (2 pi)): cos(2 pi r) ~ c0 + c1 s + c2 s^2 and
+// sin(2 pi r) / r ~ s0 + s1 s + s2 s^2.
+struct NearPoly {
+  float c0, c1, c2, s0, s1, s2;
+};
+template <typename T, int BS, int RB, bool POLY>
+__global__ void k_p2p(PassArgs a, int nrhs, NearPoly np);
 template <typename R>
 struct SymTypes;
 template <>
@@ -182,12 +188,6 @@ template <>
 struct SymTypes<double> {
   typedef double4 R4;
   typedef double2 R2;
-};
-// Coefficients of the FP32 near-field pair value as quadratics in s = r^2 (scaled
-// units, r = k |x - y| / (2 pi)): cos(2 pi r) ~ c0 + c1 s + c2 s^2 and
-// sin(2 pi r) / r ~ s0 + s1 s + s2 s^2.
-struct NearPoly {
-  float c0, c1, c2, s0, s1, s2;
 };
 template <typename R, int T, int NW, bool POLY>
 __global__ void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part, NearPoly np);

@@ -140,3 +140,18 @@ def test_poly_option_checked():
     from paper_1902_05875_amd import api
     with pytest.raises(api.TefmmError):
         api.TEFMM(K3, D3, p=6, precision="fp32", p2p_poly=1)
+
+
+def test_poly_pair_value_several_vectors():
+    """The one-sided FP32 kernel (several charge vectors, 8 per pair value) with the
+    quadratic pair value against the hardware sine and cosine."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c2", n=60_000, n_rhs=4)
+    q = np.ascontiguousarray(q.T)  # (vectors, N)
+    a, sa = _run(xyz, q, p=6, precision="fp32", depth=4)
+    b, sb = _run(xyz, q, p=6, precision="fp32", depth=4, p2p_poly=-1)
+    e = _rel(a, b)
+    print(f"4 vectors: fit error {sa['p2p_poly_err']:.2e}, rel diff {e:.3e}")
+    assert a.shape == (4, xyz.shape[0])
+    assert 0 < sa["p2p_poly_err"] <= 3e-7 and sb["p2p_poly_err"] == 0
+    assert e < 1e-6
