@@ -60,10 +60,12 @@ void solve3(const double (&A)[3][3], const double (&b)[3], double (&x)[3]) {
 // (least squares at 64 Chebyshev points of [0, rmax^2], in t = s / rmax^2), then take
 // the largest error of the FP32-rounded coefficients over 4097 points, as a fraction of
 // the pair value's size 1/r: |cos error| and r |sine error|.  Returns whether it is
-// within tol.
+// within tol (never for a leaf of zero size, where all particles coincide).
 bool fit_near_poly(double k, double h, double tol, NearPoly* np, double* err) {
   const double rmax = 2.0 * std::sqrt(3.0) * h * k / (2.0 * PI) * (1.0 + 1e-6);
   const double S = rmax * rmax;
+  *err = 0;
+  if (!(S > 0) || !std::isfinite(S)) return false;
   auto fc = [](double s) { return std::cos(2.0 * PI * std::sqrt(s)); };
   auto fs = [](double s) {
     const double r = std::sqrt(s);
@@ -85,14 +87,17 @@ bool fit_near_poly(double k, double h, double tol, NearPoly* np, double* err) {
   np->c0 = (float)xc[0], np->c1 = (float)(xc[1] / S), np->c2 = (float)(xc[2] / (S * S));
   np->s0 = (float)xs[0], np->s1 = (float)(xs[1] / S), np->s2 = (float)(xs[2] / (S * S));
   double e = 0;
+  bool finite = true;
   for (int i = 0; i <= 4096; ++i) {
     const double s = S * i / 4096.0, r = std::sqrt(s);
     const double pc = ((double)np->c2 * s + np->c1) * s + np->c0;
     const double ps = ((double)np->s2 * s + np->s1) * s + np->s0;
-    e = std::max(e, std::max(std::fabs(pc - fc(s)), r * std::fabs(ps - fs(s))));
+    const double d = std::max(std::fabs(pc - fc(s)), r * std::fabs(ps - fs(s)));
+    finite = finite && std::isfinite(d);  // std::max passes over a NaN
+    e = std::max(e, d);
   }
-  *err = e;
-  return std::isfinite(e) && e <= tol;
+  *err = finite ? e : 0;
+  return finite && e <= tol;
 }
 
 struct Group {
