@@ -1644,16 +1644,16 @@ extern "C" int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_
   // rebuilt the levels: their moment and local buffers first)
   if (rc == TEFMM_OK) rc = ensure_rhs(h, 1);
   if (rc == TEFMM_OK) {
-    // the three choices in turn, three rounds, the best time of each (the differences
-    // can be a few percent)
+    // the three choices in turn, five rounds of four evaluations, the best time of each
+    // (the differences can be a percent or two)
     float bt[3] = {1e30f, 1e30f, 1e30f};
-    for (int round = 0; round < 3 && rc == TEFMM_OK; ++round)
+    for (int round = 0; round < 5 && rc == TEFMM_OK; ++round)
       for (int fm = 0; fm <= 2 && rc == TEFMM_OK; ++fm) {
         h->fork_late = fm;
         rc = enqueue_evaluate(h, (const double*)q1, 1, (double*)phi1, s, false);
         if (rc != TEFMM_OK) break;
         (void)hipEventRecord(e0, s);
-        for (int it = 0; it < 2 && rc == TEFMM_OK; ++it) rc = enqueue_evaluate(h, (const double*)q1, 1, (double*)phi1, s, false);
+        for (int it = 0; it < 4 && rc == TEFMM_OK; ++it) rc = enqueue_evaluate(h, (const double*)q1, 1, (double*)phi1, s, false);
         (void)hipEventRecord(e1, s);
         (void)hipEventSynchronize(e1);
         float ms = 0;
