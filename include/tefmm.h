@@ -290,6 +290,19 @@ int tefmm_mlp_set_params(tefmm_mlp_t m, const float* theta_host);
 int tefmm_mlp_get_params(tefmm_mlp_t m, float* theta_host);
 /* y[n x n_out] = network(x[n x n_in]) (device arrays). */
 int tefmm_mlp_forward(tefmm_mlp_t m, const float* x, int64_t n, float* y, void* stream);
+/* Forward pass that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops).  Same kernels and
+ * result as tefmm_mlp_forward (bitwise), y[n x n_out] = network(x[n x n_in]),
+ * x and y device arrays owned by the caller; the hidden activations live in a
+ * fixed device array of the library (TEFMM_MLP_SCRATCH_BYTES per GPU, held
+ * until the process ends) instead of the handle's workspace, so at most
+ * TEFMM_MLP_SCRATCH_BYTES / (8 width) rows per call (more: TEFMM_ERR_INVALID_ARG,
+ * nothing enqueued).  The first call on a device looks up that device's copy.
+ * Every call on one GPU shares the array, so calls that overlap on one GPU
+ * (other streams or host threads) race and must be serialised by the caller.
+ * Stream ordered on `stream`. */
+#define TEFMM_MLP_SCRATCH_BYTES (32LL << 20)
+int tefmm_mlp_forward_noalloc(tefmm_mlp_t m, const float* x, int64_t n, float* y, void* stream);
 /* Loss of (x, t) (device, n rows) and its gradient: *loss and grad_host
  * (num_params floats) on the host, either may be NULL.  Synchronous. */
 int tefmm_mlp_loss_grad(tefmm_mlp_t m, const float* x, const float* t, int64_t n, double* loss, float* grad_host,

@@ -25,7 +25,8 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_dcim_family", "tefmm_taylor_coefficients", "tefmm_get_moments", "tefmm_get_tree",
            "tefmm_selftest_mfma", "tefmm_evaluate_batch", "tefmm_autotune", "tefmm_dcim_cross",
            "tefmm_mlp_create", "tefmm_mlp_destroy", "tefmm_mlp_num_params", "tefmm_mlp_last_error",
-           "tefmm_mlp_set_params", "tefmm_mlp_get_params", "tefmm_mlp_forward", "tefmm_mlp_loss_grad",
+           "tefmm_mlp_set_params", "tefmm_mlp_get_params", "tefmm_mlp_forward", "tefmm_mlp_forward_noalloc",
+           "tefmm_mlp_loss_grad",
            "tefmm_mlp_adam_step", "tefmm_mlp_train", "tefmm_surrogate_default_options", "tefmm_surrogate_train",
            "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
            "tefmm_reset_timers"]
@@ -124,6 +125,7 @@ def lib():
         L.tefmm_mlp_set_params.argtypes = [vp, vp]
         L.tefmm_mlp_get_params.argtypes = [vp, vp]
         L.tefmm_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.tefmm_mlp_forward_noalloc.argtypes = [vp, vp, i64, vp, vp]
         L.tefmm_mlp_loss_grad.argtypes = [vp, vp, vp, i64, ctypes.POINTER(dbl), vp, vp]
         L.tefmm_mlp_adam_step.argtypes = [vp, ctypes.c_float, vp]
         L.tefmm_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float, ctypes.c_uint64, vp, vp]
@@ -381,6 +383,14 @@ class MLP:
         y = torch.empty(x.shape[0], self.dims[3], dtype=torch.float32, device=x.device)
         self._chk(lib().tefmm_mlp_forward(self.h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
                                           ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)))
+        return y
+
+    def forward_noalloc(self, x, y, stream=None):
+        """tefmm_mlp_forward_noalloc into the caller's y (n x n_out, float32, on the device)."""
+        assert x.is_contiguous() and x.dtype == y.dtype and y.is_contiguous()
+        assert y.shape == (x.shape[0], self.dims[3])
+        self._chk(lib().tefmm_mlp_forward_noalloc(self.h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                                  ctypes.c_void_p(y.data_ptr()), _stream_ptr(stream)))
         return y
 
     def loss_grad(self, x, t, stream=None):

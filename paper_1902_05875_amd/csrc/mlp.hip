@@ -14,6 +14,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -265,13 +266,20 @@ hipError_t Mlp::reserve(int64_t n) {
 
 // forward of n <= cap rows; activations a_1..a_H kept in acts, outputs in out
 hipError_t Mlp::forward(const float* x, int64_t n, float* out, hipStream_t s) {
+  return forward_in(x, n, out, s, acts, cap * width, n_hidden);
+}
+
+// forward of n rows with the hidden activation a_{l+1} in slab l % nslab of buf (slabs
+// `stride` floats apart, each holding n x width): nslab = n_hidden keeps every layer (for
+// the backward pass), nslab = 2 only the two a product reads and writes
+hipError_t Mlp::forward_in(const float* x, int64_t n, float* out, hipStream_t s, float* buf, int64_t stride,
+                           int nslab) {
   hipError_t e;
-  float* a1 = acts;
   hipLaunchKernelGGL(k_mlp_in, dim3(nblk(n * width)), dim3(256), 0, s, x, n, n_in, width, theta + off_W[0],
-                     theta + off_b[0], a1);
+                     theta + off_b[0], buf);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int l = 1; l <= n_hidden; ++l) {
-    const float* ain = acts + (int64_t)(l - 1) * cap * width;
+    const float* ain = buf + (int64_t)((l - 1) % nslab) * stride;
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.M = (int)n, g.N = rows[l], g.K = cols[l];
@@ -279,7 +287,7 @@ hipError_t Mlp::forward(const float* x, int64_t n, float* out, hipStream_t s) {
     g.B = theta + off_W[l], g.sbk = 1, g.sbj = cols[l];  // B(k, j) = W[j][k]
     g.bias = theta + off_b[l];
     if (l < n_hidden) {
-      g.C = acts + (int64_t)l * cap * width, g.ldc = width, g.act = 1;
+      g.C = buf + (int64_t)(l % nslab) * stride, g.ldc = width, g.act = 1;
     } else {
       g.C = out, g.ldc = n_out, g.act = 0;
     }
@@ -476,6 +484,52 @@ extern "C" int tefmm_mlp_forward(tefmm_mlp_t m, const float* x, int64_t n, float
     const int64_t cnt = std::min<int64_t>(m->net.cap, n - r0);
     MLPCHK(m->net.forward(x + r0 * m->net.n_in, cnt, y + r0 * m->net.n_out, s));
   }
+  return TEFMM_OK;
+}
+
+// Fixed device workspace of the forward pass that allocates nothing: two activation
+// slabs of n x width floats.  Each GPU the library runs on holds its own copy until the
+// process ends.  Host code never passes `scratch` itself (its host-side name is not a
+// device address): the entry point looks up each device's address once.
+static constexpr int64_t MLP_SCRATCH_FLOATS = (int64_t)TEFMM_MLP_SCRATCH_BYTES / sizeof(float);
+static __device__ __align__(256) float scratch[MLP_SCRATCH_FLOATS];
+
+static constexpr int MAX_DEVICES = 64;
+static float* g_scratch_ptr[MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+// Address of this device's copy of `scratch` (looked up on the first call per device).
+static hipError_t scratch_address(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = (float*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+extern "C" int tefmm_mlp_forward_noalloc(tefmm_mlp_t m, const float* x, int64_t n, float* y, void* stream) {
+  if (!m || n < 0 || (n > 0 && (!x || !y))) return TEFMM_ERR_INVALID_ARG;
+  const int64_t need = 2 * n * (int64_t)m->net.width;  // two slabs of n x width
+  if (need > MLP_SCRATCH_FLOATS) {
+    m->err = "tefmm_mlp_forward_noalloc: " + std::to_string(n) + " rows x width " +
+             std::to_string(m->net.width) + " need " + std::to_string(need * sizeof(float)) +
+             " bytes of workspace, more than the fixed " + std::to_string((int64_t)TEFMM_MLP_SCRATCH_BYTES) +
+             " (at most " + std::to_string(MLP_SCRATCH_FLOATS / (2 * m->net.width)) + " rows per call)";
+    return TEFMM_ERR_INVALID_ARG;
+  }
+  float* buf = nullptr;
+  MLPCHK(scratch_address(&buf));
+  if (n == 0) return TEFMM_OK;
+  MLPCHK(m->net.forward_in(x, n, y, (hipStream_t)stream, buf, n * m->net.width, 2));
   return TEFMM_OK;
 }
 

@@ -25,6 +25,8 @@ struct Mlp {
   hipError_t init(int n_in, int width, int n_hidden, int n_out, uint64_t seed);
   hipError_t reserve(int64_t n);
   hipError_t forward(const float* x, int64_t n, float* out, hipStream_t s);
+  hipError_t forward_in(const float* x, int64_t n, float* out, hipStream_t s, float* buf, int64_t stride,
+                        int nslab);
   hipError_t loss_grad(const float* x, const float* t, int64_t n, hipStream_t s);
   hipError_t adam(float lr, hipStream_t s);
   hipError_t train(const float* X, const float* T, int64_t n, int epochs, int batch, float lr, uint64_t seed,
