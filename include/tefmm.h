@@ -25,12 +25,14 @@
  *
  * Memory: pointers marked "device" must be device memory of the current HIP
  * device (e.g. torch tensors on cuda:0); the caller owns them.  The library
- * owns its tree, expansions and tables (device memory it allocates itself,
- * freed by tefmm_destroy).
+ * owns its tree, expansions and tables (device memory it allocates with
+ * hipMalloc, or from the caller's allocator of tefmm_set_allocator, and frees
+ * by tefmm_destroy).
  */
 #ifndef TEFMM_H
 #define TEFMM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -59,7 +61,9 @@ enum { TEFMM_NORM_PHYSICAL = 0, TEFMM_NORM_PAPER = 1 };
 typedef struct tefmm_ctx* tefmm_t;
 
 /* Layered medium of Sec. 2.1.  interfaces: n_layers-1 strictly decreasing
- * heights; k: n_layers real wave numbers > 0, top to bottom. */
+ * heights; k: n_layers real wave numbers > 0, top to bottom; at most
+ * TEFMM_MAX_LAYERS layers. */
+#define TEFMM_MAX_LAYERS 8
 typedef struct {
   int n_layers;
   const double* interfaces;
@@ -112,9 +116,9 @@ typedef struct {
   double t_setup_tree_ms, t_setup_tables_ms, t_setup_dcim_ms;
   double t_p2m_ms, t_m2m_ms, t_m2l_ms, t_l2l_ms, t_l2p_ms, t_p2p_ms, t_total_ms;
   int64_t m2l_pairs, p2p_pairs;
-  int n_images[8];       /* DCIM image counts of the fitted families */
-  double dcim_fit_err[8]; /* max relative misfit on the sampling paths */
-  int depth[4];          /* tree depth per layer (0 if no particles) */
+  int n_images[3 * TEFMM_MAX_LAYERS];       /* DCIM image counts of the fitted families */
+  double dcim_fit_err[3 * TEFMM_MAX_LAYERS]; /* max relative misfit on the sampling paths */
+  int depth[TEFMM_MAX_LAYERS]; /* tree depth per layer group (0 if none), groups in layer order */
   int n_families;
   double m2l_flops;      /* algorithmic M2L flops of the last evaluate: 8 (p+1)^4 per
                             (target box, source box, family) contraction, times n_rhs */
@@ -132,6 +136,15 @@ typedef struct {
   int64_t p2p_pairs_same_leaf; /* of p2p_pairs, the ordered pairs inside one leaf */
   double p2p_poly_err;   /* largest error of the near-field quadratics in use (of cos(k r) and of
                             r sin(k r) / r, relative to the pair value's size 1/r); 0 if none */
+  int64_t sigma_direct_pairs; /* particle pairs (per charge vector) whose Sigma-family reaction
+                                 term is evaluated directly from the complex images: leaf pairs
+                                 next to an interface, where the expansion about the box centres
+                                 would converge slowly or not at all (ratio sqrt(3) h / distance
+                                 of the key's centre from the mirror point above 0.75) */
+  int64_t reaction_keys_forced; /* (level, z-slab pair) translations of a reaction family with
+                                   that ratio above 0.87 (converging slowly or not at all:
+                                   boxes reaching close to an interface, or a layer thin
+                                   against the boxes); zero in the usual configurations */
 } tefmm_stats;
 
 /* Fill an options struct with the defaults (p = 8, depth auto, max_leaf 64,
@@ -142,9 +155,24 @@ void tefmm_default_options(tefmm_options* opt);
 /* Create a handle for a medium: validates the medium and options and uploads
  * the small index tables of order p to the current HIP device.
  * Returns TEFMM_ERR_INVALID_ARG for non-decreasing interfaces, k <= 0,
- * p outside [1, 16] or more than 4 layers, TEFMM_ERR_HIP if the device
+ * p outside [1, 16] or more than TEFMM_MAX_LAYERS layers, TEFMM_ERR_HIP if the device
  * tables cannot be allocated. */
 int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefmm_options* opt);
+
+/* Device allocator of a handle (e.g. a framework's caching allocator).  Every
+ * device buffer the handle owns (index tables, sorted particles, tree arrays,
+ * expansions, derivative tables, set-up temporaries) is then taken from
+ * alloc(bytes, user) and given back with free(ptr, user); alloc returns NULL
+ * when it cannot serve the request (the call in progress then fails with
+ * TEFMM_ERR_OOM).  Both NULL restores hipMalloc / hipFree.  Memory is used on
+ * the streams passed to tefmm_set_particles / tefmm_evaluate (and, joined back
+ * to them, on the handle's own second stream), and freed at set-up of the next
+ * geometry or at tefmm_destroy.  The call releases what the handle holds (with
+ * the allocator that gave it) and uploads the index tables again, so the
+ * geometry must be set again afterwards.  Synchronous. */
+typedef void* (*tefmm_alloc_fn)(size_t bytes, void* user);
+typedef void (*tefmm_free_fn)(void* ptr, void* user);
+int tefmm_set_allocator(tefmm_t h, tefmm_alloc_fn alloc, tefmm_free_fn free, void* user);
 
 /* Set the particle geometry.  xyz_soa: 3*n doubles, x[0..n) then y then z,
  * device memory (on_device = 1) or host memory (on_device = 0).  Builds the

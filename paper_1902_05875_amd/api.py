@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtefmm.so")
 
 TEFMM_FP64, TEFMM_MIXED_FP32 = 0, 1
+MAX_LAYERS = 8  # TEFMM_MAX_LAYERS
 TEFMM_NORM_PHYSICAL, TEFMM_NORM_PAPER = 0, 1
 ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "PARTICLE_ON_INTERFACE", -3: "UNSUPPORTED", -4: "HIP",
           -5: "DCIM_FIT", -6: "OOM", -7: "STATE"}
@@ -29,7 +30,32 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_mlp_loss_grad",
            "tefmm_mlp_adam_step", "tefmm_mlp_train", "tefmm_surrogate_default_options", "tefmm_surrogate_train",
            "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
-           "tefmm_reset_timers"]
+           "tefmm_reset_timers", "tefmm_set_allocator"]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory of a handle from PyTorch's caching allocator (tefmm_set_allocator):
+    blocks are taken on the current stream and returned to torch's cache."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+
+        def _alloc(nbytes, user):
+            try:
+                return self._torch.cuda.caching_allocator_alloc(int(nbytes))
+            except Exception:  # out of memory: NULL tells the library
+                return None
+
+        def _free(ptr, user):
+            self._torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc = ALLOC_FN(_alloc)  # kept alive as long as the handle uses them
+        self.free = FREE_FN(_free)
 
 
 class TefmmError(RuntimeError):
@@ -55,13 +81,15 @@ class StatsC(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ["t_setup_tree_ms", "t_setup_tables_ms", "t_setup_dcim_ms", "t_p2m_ms", "t_m2m_ms", "t_m2l_ms",
                  "t_l2l_ms", "t_l2p_ms", "t_p2p_ms", "t_total_ms"]] + [
-        ("m2l_pairs", ctypes.c_int64), ("p2p_pairs", ctypes.c_int64), ("n_images", ctypes.c_int * 8),
-        ("dcim_fit_err", ctypes.c_double * 8), ("depth", ctypes.c_int * 4), ("n_families", ctypes.c_int),
+        ("m2l_pairs", ctypes.c_int64), ("p2p_pairs", ctypes.c_int64), ("n_images", ctypes.c_int * (3 * MAX_LAYERS)),
+        ("dcim_fit_err", ctypes.c_double * (3 * MAX_LAYERS)), ("depth", ctypes.c_int * MAX_LAYERS),
+        ("n_families", ctypes.c_int),
         ("m2l_flops", ctypes.c_double), ("m2l_launches", ctypes.c_int), ("n_rhs", ctypes.c_int),
         ("cross_pairs", ctypes.c_int64), ("cross_pairs_forced", ctypes.c_int64), ("n_cross_fits", ctypes.c_int),
         ("cross_fit_err", ctypes.c_double), ("sigma_keys", ctypes.c_int64), ("surrogate_keys", ctypes.c_int64),
         ("timed_evaluations", ctypes.c_int), ("p2p_pairs_same_leaf", ctypes.c_int64),
-        ("p2p_poly_err", ctypes.c_double)]
+        ("p2p_poly_err", ctypes.c_double), ("sigma_direct_pairs", ctypes.c_int64),
+        ("reaction_keys_forced", ctypes.c_int64)]
 
 
 class SurOptionsC(ctypes.Structure):
@@ -139,6 +167,7 @@ def lib():
         L.tefmm_set_surrogate.argtypes = [vp, vp]
         L.tefmm_surrogate_cell_errors.argtypes = [vp, vp]
         L.tefmm_reset_timers.argtypes = [vp]
+        L.tefmm_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
         _lib = L
     return _lib
 
@@ -178,7 +207,8 @@ def _stream_ptr(stream=None):
 class TEFMM:
     """Handle of one medium + options.  set_particles(xyz) then evaluate(q)."""
 
-    def __init__(self, k, d, **options):
+    def __init__(self, k, d, allocator=None, **options):
+        """allocator: None (the library's hipMalloc) or "torch" (PyTorch's caching allocator)."""
         self.k, self.d = tuple(k), tuple(d)
         self._med = _medium(self.k, self.d)
         self.opt = default_options(**options)
@@ -186,11 +216,27 @@ class TEFMM:
         _check(lib().tefmm_create(ctypes.byref(h), ctypes.byref(self._med), ctypes.byref(self.opt)))
         self.h = h
         self.n = 0
+        self._alloc = None
+        if allocator is not None:
+            self.set_allocator(allocator)
+
+    def set_allocator(self, allocator):
+        """Take the handle's device memory from `allocator` ("torch" or a TorchAllocator;
+        None: hipMalloc).  Drops the geometry: call set_particles afterwards."""
+        if allocator == "torch":
+            allocator = TorchAllocator()
+        if allocator is None:
+            _check(lib().tefmm_set_allocator(self.h, ALLOC_FN(), FREE_FN(), None), self.h)
+        else:
+            _check(lib().tefmm_set_allocator(self.h, allocator.alloc, allocator.free, None), self.h)
+        self._alloc = allocator
 
     def close(self):
         if getattr(self, "h", None):
-            lib().tefmm_destroy(self.h)
+            lib().tefmm_destroy(self.h)  # frees through the allocator, which is still referenced
             self.h = None
+            self._alloc = None
+            self._xyz = None
 
     def __del__(self):
         try:

@@ -9,7 +9,7 @@ using tefmm::cplx;
 
 namespace tefmm {
 bool medium_from_desc(const tefmm_medium* m, MediumDesc& out, std::string& err) {
-  if (!m || m->n_layers < 1 || m->n_layers > 4 || !m->k || (m->n_layers > 1 && !m->interfaces)) {
+  if (!m || m->n_layers < 1 || m->n_layers > TEFMM_MAX_LAYERS || !m->k || (m->n_layers > 1 && !m->interfaces)) {
     err = "invalid medium";
     return false;
   }

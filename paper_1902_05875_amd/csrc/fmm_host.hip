@@ -24,6 +24,7 @@
 
 #include "../../include/tefmm.h"
 #include "fmm_kernels.hpp"
+static_assert(tefmm::MAX_LAYERS == TEFMM_MAX_LAYERS, "layer limit of the kernels and of the C ABI");
 #include "host_math.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
@@ -135,10 +136,21 @@ struct Group {
   int n_cross_fits = 0;
   double cross_fit_err = 0;
   bool has_cross = false;
+  // Sigma-family keys of the leaf level whose expansion would not converge (boxes next
+  // to an interface): their table rows are zero and their leaf pairs are evaluated
+  // directly from the complex images (k_sigma_direct) on the lists below
+  std::vector<char> sig_flag;               // [49 (2 nb - 1)] at the leaf level
+  int* d_sd_tgt = nullptr;                  // listed target leaves
+  int* d_sd_start = nullptr;                // [ntgt + 1] into d_sd_src
+  int* d_sd_src = nullptr;                  // their source leaves
+  double2* d_sd_img = nullptr;              // images: A, Z of Sigma-up, then of Sigma-down
+  int sd_ntgt = 0, sd_nup = 0, sd_ndn = 0;
+  int64_t sd_pairs = 0;                     // particle pairs evaluated directly (per charge vector)
+  int64_t keys_forced = 0;                  // reaction keys translated with a poor separation ratio
 };
 
 template <class T>
-void dfree(T*& p) {
+void dfree_raw(T*& p) {
   if (p) (void)hipFree((void*)p);
   p = nullptr;
 }
@@ -178,8 +190,8 @@ struct tefmm_ctx {
   hipStream_t s2 = nullptr;
   hipEvent_t e_fork = nullptr, e_join = nullptr;
   // with several layer groups their M2L launches run on streams of their own
-  hipStream_t sg[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t e_gfork = nullptr, e_gjoin[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipStream_t sg[MAX_LAYERS] = {};
+  hipEvent_t e_gfork = nullptr, e_gjoin[MAX_LAYERS] = {};
   int nrhs_alloc = 0;
   bool ready = false;
   // stats
@@ -196,6 +208,10 @@ struct tefmm_ctx {
   // field first, then the far field, on the caller's stream); set by the autotuner
   int fork_late = -1;
   tefmm_surrogate* sur = nullptr;  // surrogate for the Sigma tables (borrowed)
+  // caller's device allocator (tefmm_set_allocator); null: hipMalloc / hipFree
+  tefmm_alloc_fn alloc_fn = nullptr;
+  tefmm_free_fn free_fn = nullptr;
+  void* alloc_user = nullptr;
   uint64_t gen = 0; // changes whenever device buffers are (re)allocated
   // graph of the last batched evaluation
   struct Batch {
@@ -214,6 +230,31 @@ struct tefmm_ctx {
 };
 
 static void batch_destroy(tefmm_ctx::Batch& b);
+
+// Device memory owned by a handle: from the caller's allocator when one is set
+// (tefmm_set_allocator), else hipMalloc / hipFree.  A failed allocation reads as
+// hipErrorOutOfMemory (TEFMM_ERR_OOM at the ABI).
+template <class T>
+static hipError_t dmalloc(tefmm_t h, T** p, size_t bytes) {
+  *p = nullptr;
+  if (h->alloc_fn) {
+    void* v = bytes ? h->alloc_fn(bytes, h->alloc_user) : nullptr;
+    if (bytes && !v) return hipErrorOutOfMemory;
+    *p = (T*)v;
+    return hipSuccess;
+  }
+  return hipMalloc((void**)p, bytes);
+}
+template <class T>
+static void dfree(tefmm_t h, T*& p) {
+  if (p) {
+    if (h->free_fn)
+      h->free_fn((void*)p, h->alloc_user);
+    else
+      (void)hipFree((void*)p);
+  }
+  p = nullptr;
+}
 static constexpr int EV_RING = 64;  // evaluations whose phase times are kept
 static std::atomic<uint64_t> g_generation{1};
 
@@ -221,42 +262,47 @@ static int fail(tefmm_t h, int code, const std::string& msg) {
   if (h) h->err = msg;
   return code;
 }
-#define HIPCHK(h, x)                                                               \
-  do {                                                                             \
-    hipError_t e_ = (x);                                                           \
-    if (e_ != hipSuccess)                                                          \
-      return fail(h, TEFMM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+#define HIPCHK(h, x)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (x);                                                                        \
+    if (e_ != hipSuccess)                                                                       \
+      return fail(h, e_ == hipErrorOutOfMemory ? TEFMM_ERR_OOM : TEFMM_ERR_HIP,                 \
+                  std::string(#x) + ": " + hipGetErrorString(e_));                              \
   } while (0)
 
 static void free_geometry(tefmm_t h) {
-  dfree(h->d_xs);
-  dfree(h->d_perm);
-  dfree(h->d_leaf_start);
-  dfree(h->d_leaf_count);
+  dfree(h, h->d_xs);
+  dfree(h, h->d_perm);
+  dfree(h, h->d_leaf_start);
+  dfree(h, h->d_leaf_count);
   for (auto& g : h->groups) {
-    for (auto& p : g.alpha) dfree(p);
-    for (auto& p : g.beta) dfree(p);
-    for (auto& p : g.ared) dfree(p);
-    for (auto& p : g.ared32) dfree(p);
-    for (auto& p : g.bred) dfree(p);
-    for (auto& p : g.azred) dfree(p);
-    for (auto& p : g.bzred) dfree(p);
-    for (auto& p : g.xlist_start) dfree(p);
-    for (auto& p : g.xlist) dfree(p);
-    for (auto& p : g.XT0) dfree(p);
-    for (auto& p : g.XT1) dfree(p);
-    for (auto& p : g.XT032) dfree(p);
-    for (auto& p : g.XT132) dfree(p);
-    for (auto& p : g.Tfd) dfree(p);
-    for (auto& p : g.TS) dfree(p);
-    for (auto& p : g.Tfd32) dfree(p);
-    for (auto& p : g.TS32) dfree(p);
+    for (auto& p : g.alpha) dfree(h, p);
+    for (auto& p : g.beta) dfree(h, p);
+    for (auto& p : g.ared) dfree(h, p);
+    for (auto& p : g.ared32) dfree(h, p);
+    for (auto& p : g.bred) dfree(h, p);
+    for (auto& p : g.azred) dfree(h, p);
+    for (auto& p : g.bzred) dfree(h, p);
+    for (auto& p : g.xlist_start) dfree(h, p);
+    for (auto& p : g.xlist) dfree(h, p);
+    for (auto& p : g.XT0) dfree(h, p);
+    for (auto& p : g.XT1) dfree(h, p);
+    for (auto& p : g.XT032) dfree(h, p);
+    for (auto& p : g.XT132) dfree(h, p);
+    for (auto& p : g.Tfd) dfree(h, p);
+    for (auto& p : g.TS) dfree(h, p);
+    for (auto& p : g.Tfd32) dfree(h, p);
+    for (auto& p : g.TS32) dfree(h, p);
+    dfree(h, g.d_sd_tgt);
+    dfree(h, g.d_sd_start);
+    dfree(h, g.d_sd_src);
+    dfree(h, g.d_sd_img);
   }
   h->groups.clear();
-  dfree(h->d_q);
-  dfree(h->d_phi);
-  dfree(h->d_phi_near);
-  dfree(h->d_part);
+  dfree(h, h->d_q);
+  dfree(h, h->d_phi);
+  dfree(h, h->d_phi_near);
+  dfree(h, h->d_part);
   h->nrhs_alloc = 0;
   h->ready = false;
 }
@@ -331,24 +377,24 @@ static int build_constant_tables(tefmm_t h) {
         if (c >= 2) nbr[6 * i + 5] = (short)g_index(g1, b, c - 2);
       }
   if (cnt != nG) return fail(h, TEFMM_ERR_STATE, "compact table size");
-  HIPCHK(h, hipMalloc(&h->d_mi, sizeof(int) * nC));
-  HIPCHK(h, hipMalloc(&h->d_rmi, sizeof(int) * nR));
-  HIPCHK(h, hipMalloc(&h->d_rfull, sizeof(int) * nR));
-  HIPCHK(h, hipMalloc(&h->d_nbr, sizeof(short) * 6 * nG));
-  HIPCHK(h, hipMalloc(&h->d_gpad, sizeof(int) * nG));
-  HIPCHK(h, hipMalloc(&h->d_gpadz, sizeof(int) * nG));
+  HIPCHK(h, dmalloc(h, &h->d_mi, sizeof(int) * nC));
+  HIPCHK(h, dmalloc(h, &h->d_rmi, sizeof(int) * nR));
+  HIPCHK(h, dmalloc(h, &h->d_rfull, sizeof(int) * nR));
+  HIPCHK(h, dmalloc(h, &h->d_nbr, sizeof(short) * 6 * nG));
+  HIPCHK(h, dmalloc(h, &h->d_gpad, sizeof(int) * nG));
+  HIPCHK(h, dmalloc(h, &h->d_gpadz, sizeof(int) * nG));
   HIPCHK(h, hipMemcpy(h->d_gpadz, gpadz.data(), sizeof(int) * nG, hipMemcpyHostToDevice));
-  HIPCHK(h, hipMalloc(&h->d_g1, nG));
+  HIPCHK(h, dmalloc(h, &h->d_g1, nG));
   HIPCHK(h, hipMemcpy(h->d_g1, g1v.data(), nG, hipMemcpyHostToDevice));
-  HIPCHK(h, hipMalloc(&h->d_rzmi, sizeof(int) * nR));
+  HIPCHK(h, dmalloc(h, &h->d_rzmi, sizeof(int) * nR));
   HIPCHK(h, hipMemcpy(h->d_rzmi, rzmi.data(), sizeof(int) * nR, hipMemcpyHostToDevice));
-  HIPCHK(h, hipMalloc(&h->d_rzfull, sizeof(int) * nR));
+  HIPCHK(h, dmalloc(h, &h->d_rzfull, sizeof(int) * nR));
   HIPCHK(h, hipMemcpy(h->d_rzfull, rzfull.data(), sizeof(int) * nR, hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->d_gpad, gpad.data(), sizeof(int) * nG, hipMemcpyHostToDevice));
-  HIPCHK(h, hipMalloc(&h->d_g3, nG));
-  HIPCHK(h, hipMalloc(&h->d_fact, sizeof(double) * nG));
-  HIPCHK(h, hipMalloc(&h->d_scale, sizeof(double) * nC));
-  HIPCHK(h, hipMalloc(&h->d_invfact, sizeof(double) * nC));
+  HIPCHK(h, dmalloc(h, &h->d_g3, nG));
+  HIPCHK(h, dmalloc(h, &h->d_fact, sizeof(double) * nG));
+  HIPCHK(h, dmalloc(h, &h->d_scale, sizeof(double) * nC));
+  HIPCHK(h, dmalloc(h, &h->d_invfact, sizeof(double) * nC));
   HIPCHK(h, hipMemcpy(h->d_mi, mi.data(), sizeof(int) * nC, hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->d_rmi, rmi.data(), sizeof(int) * nR, hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->d_rfull, rfull.data(), sizeof(int) * nR, hipMemcpyHostToDevice));
@@ -396,33 +442,52 @@ extern "C" int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefm
   return TEFMM_OK;
 }
 
+static void free_constant_tables(tefmm_t h) {
+  dfree(h, h->d_mi);
+  dfree(h, h->d_rmi);
+  dfree(h, h->d_rfull);
+  dfree(h, h->d_gpad);
+  dfree(h, h->d_gpadz);
+  dfree(h, h->d_g1);
+  dfree(h, h->d_rzmi);
+  dfree(h, h->d_rzfull);
+  dfree(h, h->d_nbr);
+  dfree(h, h->d_g3);
+  dfree(h, h->d_fact);
+  dfree(h, h->d_scale);
+  dfree(h, h->d_invfact);
+}
+
+extern "C" int tefmm_set_allocator(tefmm_t h, tefmm_alloc_fn alloc, tefmm_free_fn free_fn, void* user) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(h, TEFMM_ERR_INVALID_ARG, "tefmm_set_allocator: give both functions or neither");
+  // everything the handle holds is released with the allocator that gave it, then the
+  // constant tables are uploaded again into memory from the new one
+  batch_destroy(h->batch);
+  free_geometry(h);
+  dfree(h, h->d_xyz_user);
+  free_constant_tables(h);
+  h->alloc_fn = alloc, h->free_fn = free_fn, h->alloc_user = user;
+  h->gen = g_generation++;
+  return build_constant_tables(h);
+}
+
 extern "C" void tefmm_destroy(tefmm_t h) {
   if (!h) return;
   free_geometry(h);
-  dfree(h->d_mi);
-  dfree(h->d_rmi);
-  dfree(h->d_rfull);
-  dfree(h->d_gpad);
-  dfree(h->d_gpadz);
-  dfree(h->d_g1);
-  dfree(h->d_rzmi);
-  dfree(h->d_rzfull);
-  dfree(h->d_nbr);
-  dfree(h->d_g3);
-  dfree(h->d_fact);
-  dfree(h->d_scale);
-  dfree(h->d_invfact);
+  free_constant_tables(h);
   for (auto& e : h->ev) (void)hipEventDestroy(e);
   if (h->e_fork) (void)hipEventDestroy(h->e_fork);
   if (h->e_join) (void)hipEventDestroy(h->e_join);
   if (h->s2) (void)hipStreamDestroy(h->s2);
   if (h->e_gfork) (void)hipEventDestroy(h->e_gfork);
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < MAX_LAYERS; ++i) {
     if (h->e_gjoin[i]) (void)hipEventDestroy(h->e_gjoin[i]);
     if (h->sg[i]) (void)hipStreamDestroy(h->sg[i]);
   }
   batch_destroy(h->batch);
-  dfree(h->d_xyz_user);
+  dfree(h, h->d_xyz_user);
   delete h;
 }
 
@@ -499,6 +564,8 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
               start.push_back((int)terms.size());
               hk.push_back(hb);
               const double S = 2 * g.lo[2] + (m + 1) * hb;
+              // evaluated directly (k_sigma_direct): the row stays zero
+              if (leaf && !g.sig_flag.empty() && g.sig_flag[start.size() - 1]) continue;
               if (use_sur && surrogate_accepts(h->sur, -dx * hb, -dy * hb, S)) {
                 // answered by the network after the image tables are generated
                 sk.key.push_back((int)start.size() - 1);
@@ -519,10 +586,10 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
       int* d_start = nullptr;
       double* d_h = nullptr;
       double2* d_out = nullptr;
-      HIPCHK(h, hipMalloc(&d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
-      HIPCHK(h, hipMalloc(&d_start, sizeof(int) * start.size()));
-      HIPCHK(h, hipMalloc(&d_h, sizeof(double) * hk.size()));
-      HIPCHK(h, hipMalloc(&d_out, sizeof(double2) * (size_t)nkeys * h->nG));
+      HIPCHK(h, dmalloc(h, &d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
+      HIPCHK(h, dmalloc(h, &d_start, sizeof(int) * start.size()));
+      HIPCHK(h, dmalloc(h, &d_h, sizeof(double) * hk.size()));
+      HIPCHK(h, dmalloc(h, &d_out, sizeof(double2) * (size_t)nkeys * h->nG));
       if (!terms.empty())
         HIPCHK(h, hipMemcpyAsync(d_terms, terms.data(), sizeof(TableTerm) * terms.size(), hipMemcpyHostToDevice, s));
       HIPCHK(h, hipMemcpyAsync(d_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, s));
@@ -535,13 +602,13 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
       hipLaunchKernelGGL(k_table_gen, dim3(nkeys), dim3(64), lds, s, ta);
       HIPCHK(h, hipGetLastError());
       HIPCHK(h, hipStreamSynchronize(s));
-      dfree(d_terms);
-      dfree(d_start);
-      dfree(d_h);
+      dfree(h, d_terms);
+      dfree(h, d_start);
+      dfree(h, d_h);
       if (!sk.key.empty()) {
         int rc = surrogate_tables(h, sk, hb, d_out, s);
         if (rc != TEFMM_OK) {
-          dfree(d_out);
+          dfree(h, d_out);
           return rc;
         }
         h->sur_keys += (int64_t)sk.key.size();
@@ -558,7 +625,7 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
         HIPCHK(h, hipMemcpy(hd.data(), d_out, sizeof(double2) * cnt, hipMemcpyDeviceToHost));
         for (size_t i = 0; i < cnt; ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
         float2* d32 = nullptr;
-        HIPCHK(h, hipMalloc(&d32, sizeof(float2) * cnt));
+        HIPCHK(h, dmalloc(h, &d32, sizeof(float2) * cnt));
         HIPCHK(h, hipMemcpy(d32, hf.data(), sizeof(float2) * cnt, hipMemcpyHostToDevice));
         if (which == 0)
           g.Tfd32[lev] = d32;
@@ -740,9 +807,9 @@ static int build_cross(tefmm_t h, int gt, hipStream_t s) {
       flat.insert(flat.end(), lists[lev][c].begin(), lists[lev][c].end());
     }
     starts[4 * n] = (int)flat.size();
-    HIPCHK(h, hipMalloc(&G.xlist_start[lev], sizeof(int) * (4 * n + 1)));
+    HIPCHK(h, dmalloc(h, &G.xlist_start[lev], sizeof(int) * (4 * n + 1)));
     HIPCHK(h, hipMemcpy(G.xlist_start[lev], starts.data(), sizeof(int) * (4 * n + 1), hipMemcpyHostToDevice));
-    HIPCHK(h, hipMalloc(&G.xlist[lev], sizeof(CrossEntry) * std::max<size_t>(1, flat.size())));
+    HIPCHK(h, dmalloc(h, &G.xlist[lev], sizeof(CrossEntry) * std::max<size_t>(1, flat.size())));
     if (!flat.empty())
       HIPCHK(h, hipMemcpy(G.xlist[lev], flat.data(), sizeof(CrossEntry) * flat.size(), hipMemcpyHostToDevice));
     for (int k3 = 0; k3 < 2; ++k3) {
@@ -772,14 +839,14 @@ static int build_cross(tefmm_t h, int gt, hipStream_t s) {
       }
       start.push_back((int)terms.size());
       double2* d_out = nullptr;
-      HIPCHK(h, hipMalloc(&d_out, sizeof(double2) * std::max<size_t>(1, (size_t)nkeys * h->nG)));
+      HIPCHK(h, dmalloc(h, &d_out, sizeof(double2) * std::max<size_t>(1, (size_t)nkeys * h->nG)));
       if (nkeys > 0) {
         TableTerm* d_terms = nullptr;
         int* d_start = nullptr;
         double* d_h = nullptr;
-        HIPCHK(h, hipMalloc(&d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
-        HIPCHK(h, hipMalloc(&d_start, sizeof(int) * start.size()));
-        HIPCHK(h, hipMalloc(&d_h, sizeof(double) * hk.size()));
+        HIPCHK(h, dmalloc(h, &d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
+        HIPCHK(h, dmalloc(h, &d_start, sizeof(int) * start.size()));
+        HIPCHK(h, dmalloc(h, &d_h, sizeof(double) * hk.size()));
         if (!terms.empty())
           HIPCHK(h, hipMemcpyAsync(d_terms, terms.data(), sizeof(TableTerm) * terms.size(), hipMemcpyHostToDevice, s));
         HIPCHK(h, hipMemcpyAsync(d_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, s));
@@ -792,9 +859,9 @@ static int build_cross(tefmm_t h, int gt, hipStream_t s) {
         hipLaunchKernelGGL(k_table_gen, dim3(nkeys), dim3(64), lds, s, ta);
         HIPCHK(h, hipGetLastError());
         HIPCHK(h, hipStreamSynchronize(s));
-        dfree(d_terms);
-        dfree(d_start);
-        dfree(d_h);
+        dfree(h, d_terms);
+        dfree(h, d_start);
+        dfree(h, d_h);
       }
       (k3 ? G.XT1[lev] : G.XT0[lev]) = d_out;
       if (h->opt.precision == TEFMM_MIXED_FP32) {
@@ -804,12 +871,151 @@ static int build_cross(tefmm_t h, int gt, hipStream_t s) {
         if (cnt) HIPCHK(h, hipMemcpy(hd.data(), d_out, sizeof(double2) * cnt, hipMemcpyDeviceToHost));
         for (size_t i = 0; i < cnt; ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
         float2* d32 = nullptr;
-        HIPCHK(h, hipMalloc(&d32, sizeof(float2) * std::max<size_t>(cnt, 1)));
+        HIPCHK(h, dmalloc(h, &d32, sizeof(float2) * std::max<size_t>(cnt, 1)));
         if (cnt) HIPCHK(h, hipMemcpy(d32, hf.data(), sizeof(float2) * cnt, hipMemcpyHostToDevice));
         (k3 ? G.XT132[lev] : G.XT032[lev]) = d32;
       }
     }
   }
+  return TEFMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Convergence of the reaction expansions.  A translation between boxes of side h
+// converges when the kernel's nearest singularity is farther from the key's centre
+// displacement than the two boxes reach, sqrt(3) h; the free-space far field works
+// at a ratio sqrt(3) h / distance of at most sqrt(3)/2 (boxes two sides apart), and
+// the reaction keys are held to the same.  For the Sigma family the singularity is
+// the mirror point z + z' = 2 d (distance sqrt(dx^2 + dy^2 + (S - 2d)^2) for a key
+// with centre height sum S); for the Delta family it is |z - z'| = D (distance
+// D - |w| at w = z - z').  Leaf-level Sigma keys above SIGMA_LEAF_THETA are evaluated
+// directly (their rows stay zero); other keys above REACTION_THETA are counted.
+// ---------------------------------------------------------------------------
+static const double REACTION_THETA = 0.87;  // just above sqrt(3)/2
+// Leaf-level Sigma keys are evaluated directly already above this ratio: next to an
+// interface many pairs sit near the worst corner, and a ratio close to sqrt(3)/2 then
+// converges too slowly for the FP64 mode (particles 0.01 from an interface: 1.6e-6 at
+// 0.87, p = 12)
+static const double SIGMA_LEAF_THETA = 0.75;
+
+static int reaction_convergence(tefmm_t h, Group& g, const std::vector<int>& lc, hipStream_t s) {
+  const MediumDesc& med = h->med;
+  const int l = g.layer, H = g.depth, nbH = 1 << H;
+  const double sq3 = std::sqrt(3.0);
+  const bool sig = g.has[0] || g.has[1];
+  // occupied z slabs per level
+  std::vector<std::vector<char>> occ(H + 1);
+  for (int lev = 2; lev <= H; ++lev) occ[lev].assign(1 << lev, 0);
+  for (int ix = 0; ix < nbH; ++ix)
+    for (int iy = 0; iy < nbH; ++iy)
+      for (int iz = 0; iz < nbH; ++iz)
+        if (lc[g.leaf_base + ((int64_t)ix * nbH + iy) * nbH + iz] > 0)
+          for (int lev = 2; lev <= H; ++lev) occ[lev][iz >> (H - lev)] = 1;
+  auto sigma_dist = [&](double rho2, double S) {
+    double d = 1e300;
+    if (g.has[0]) d = std::min(d, std::sqrt(rho2 + (S - 2 * med.d[l]) * (S - 2 * med.d[l])));
+    if (g.has[1]) d = std::min(d, std::sqrt(rho2 + (2 * med.d[l - 1] - S) * (2 * med.d[l - 1] - S)));
+    return d;
+  };
+  g.keys_forced = 0;
+  for (int lev = 2; lev <= H; ++lev) {
+    const int nb = 1 << lev;
+    const double hb = g.side / nb;
+    const bool leaf = lev == H;
+    for (int it = 0; it < nb; ++it) {
+      if (!occ[lev][it]) continue;
+      for (int dz = -2 - (it & 1); dz <= 3 - (it & 1); ++dz) {
+        const int is = it + dz;
+        if (is < 0 || is >= nb || !occ[lev][is]) continue;
+        const bool nearz = std::abs(dz) <= 1;
+        // Delta family (with the free-space kernel): translated far pairs, and at the
+        // leaf level the neighbours too; worst case dx = dy = 0
+        if (g.has[2] && (leaf || !nearz)) {
+          const double dist = med.thickness(l) - std::abs(dz) * hb;
+          if (!(dist > 0) || sq3 * hb > REACTION_THETA * dist) ++g.keys_forced;
+        }
+        // Sigma family above the leaf level (far in z; pairs far only in x or y are two
+        // sides apart horizontally, within the ratio)
+        if (sig && !leaf && !nearz) {
+          const double S = 2 * g.lo[2] + (it + is + 1) * hb;
+          if (sq3 * hb > REACTION_THETA * sigma_dist(0.0, S)) ++g.keys_forced;
+        }
+      }
+    }
+  }
+  // Sigma family at the leaf level: flag keys, list the occupied leaf pairs using them
+  g.sig_flag.clear();
+  g.sd_ntgt = 0, g.sd_pairs = 0;
+  if (!sig) return TEFMM_OK;
+  const double hb = g.side / nbH;
+  const int nm = 2 * nbH - 1;
+  g.sig_flag.assign((size_t)49 * nm, 0);
+  bool any = false;
+  for (int dx = -3; dx <= 3; ++dx)
+    for (int dy = -3; dy <= 3; ++dy)
+      for (int m = 0; m < nm; ++m) {
+        const double S = 2 * g.lo[2] + (m + 1) * hb;
+        if (sq3 * hb > SIGMA_LEAF_THETA * sigma_dist((dx * dx + dy * dy) * hb * hb, S)) {
+          g.sig_flag[((size_t)(dx + 3) * 7 + (dy + 3)) * nm + m] = 1;
+          any = true;
+        }
+      }
+  if (!any) return TEFMM_OK;
+  std::vector<int> tgt, start, src;
+  for (int ix = 0; ix < nbH; ++ix)
+    for (int iy = 0; iy < nbH; ++iy)
+      for (int iz = 0; iz < nbH; ++iz) {
+        const int tleaf = (ix * nbH + iy) * nbH + iz;
+        const int tc = lc[g.leaf_base + tleaf];
+        if (tc == 0) continue;
+        const size_t before = src.size();
+        for (int dx = -2 - (ix & 1); dx <= 3 - (ix & 1); ++dx) {
+          const int jx = ix + dx;
+          if (jx < 0 || jx >= nbH) continue;
+          for (int dy = -2 - (iy & 1); dy <= 3 - (iy & 1); ++dy) {
+            const int jy = iy + dy;
+            if (jy < 0 || jy >= nbH) continue;
+            for (int dz = -2 - (iz & 1); dz <= 3 - (iz & 1); ++dz) {
+              const int jz = iz + dz;
+              if (jz < 0 || jz >= nbH) continue;
+              if (!g.sig_flag[((size_t)(dx + 3) * 7 + (dy + 3)) * nm + (iz + jz)]) continue;
+              const int sleaf = (jx * nbH + jy) * nbH + jz;
+              const int sc = lc[g.leaf_base + sleaf];
+              if (sc == 0) continue;
+              src.push_back(sleaf);
+              g.sd_pairs += (int64_t)tc * sc;
+            }
+          }
+        }
+        if (src.size() > before) {
+          tgt.push_back(tleaf);
+          start.push_back((int)before);
+        }
+      }
+  if (tgt.empty()) return TEFMM_OK;
+  start.push_back((int)src.size());
+  std::vector<double2> img;
+  for (int fam = 0; fam < 2; ++fam)
+    if (g.has[fam])
+      for (size_t j = 0; j < g.famA[fam].size(); ++j) {
+        img.push_back(make_double2(g.famA[fam][j].real(), g.famA[fam][j].imag()));
+        img.push_back(make_double2(g.famZ[fam][j].real(), g.famZ[fam][j].imag()));
+      }
+  g.sd_nup = g.has[0] ? (int)g.famA[0].size() : 0;
+  g.sd_ndn = g.has[1] ? (int)g.famA[1].size() : 0;
+  if (g.sd_nup + g.sd_ndn > SIGMA_DIRECT_MAX_IMAGES)
+    return fail(h, TEFMM_ERR_UNSUPPORTED, "too many complex images for the direct near-interface evaluation");
+  g.sd_ntgt = (int)tgt.size();
+  HIPCHK(h, dmalloc(h, &g.d_sd_tgt, sizeof(int) * tgt.size()));
+  HIPCHK(h, dmalloc(h, &g.d_sd_start, sizeof(int) * start.size()));
+  HIPCHK(h, dmalloc(h, &g.d_sd_src, sizeof(int) * src.size()));
+  HIPCHK(h, dmalloc(h, &g.d_sd_img, sizeof(double2) * std::max<size_t>(img.size(), 1)));
+  HIPCHK(h, hipMemcpyAsync(g.d_sd_tgt, tgt.data(), sizeof(int) * tgt.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(g.d_sd_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(g.d_sd_src, src.data(), sizeof(int) * src.size(), hipMemcpyHostToDevice, s));
+  if (!img.empty())
+    HIPCHK(h, hipMemcpyAsync(g.d_sd_img, img.data(), sizeof(double2) * img.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipStreamSynchronize(s));
   return TEFMM_OK;
 }
 
@@ -829,49 +1035,49 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   double* d_in = nullptr;
   const double* src = xyz;
   if (!on_device) {
-    HIPCHK(h, hipMalloc(&d_in, sizeof(double) * 3 * n));
+    HIPCHK(h, dmalloc(h, &d_in, sizeof(double) * 3 * n));
     HIPCHK(h, hipMemcpyAsync(d_in, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
     src = d_in;
   }
   if (src != h->d_xyz_user) {
-    dfree(h->d_xyz_user);
-    HIPCHK(h, hipMalloc(&h->d_xyz_user, sizeof(double) * 3 * n));
+    dfree(h, h->d_xyz_user);
+    HIPCHK(h, dmalloc(h, &h->d_xyz_user, sizeof(double) * 3 * n));
     HIPCHK(h, hipMemcpyAsync(h->d_xyz_user, src, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
   }
   double* d_if = nullptr;
-  HIPCHK(h, hipMalloc(&d_if, sizeof(double) * std::max(L, 1)));
+  HIPCHK(h, dmalloc(h, &d_if, sizeof(double) * std::max(L, 1)));
   if (L) HIPCHK(h, hipMemcpyAsync(d_if, med.d.data(), sizeof(double) * L, hipMemcpyHostToDevice, s));
   // layer statistics
   const int nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
   double* d_part = nullptr;
   int* d_bad = nullptr;
-  HIPCHK(h, hipMalloc(&d_part, sizeof(double) * nblk * 4 * 7));
-  HIPCHK(h, hipMalloc(&d_bad, sizeof(int)));
+  HIPCHK(h, dmalloc(h, &d_part, sizeof(double) * nblk * MAX_LAYERS * 7));
+  HIPCHK(h, dmalloc(h, &d_bad, sizeof(int)));
   HIPCHK(h, hipMemsetAsync(d_bad, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_layer_stats, dim3(nblk), dim3(256), 0, s, src, n, L, d_if, h->opt.interface_eps, d_part, d_bad);
   HIPCHK(h, hipGetLastError());
-  std::vector<double> part((size_t)nblk * 28);
+  std::vector<double> part((size_t)nblk * MAX_LAYERS * 7);
   int bad = 0;
   HIPCHK(h, hipMemcpyAsync(part.data(), d_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
-  dfree(d_part);
-  dfree(d_bad);
+  dfree(h, d_part);
+  dfree(h, d_bad);
   if (bad & 2) {
-    dfree(d_in), dfree(d_if);
+    dfree(h, d_in), dfree(h, d_if);
     return fail(h, TEFMM_ERR_INVALID_ARG, "non-finite particle coordinate");
   }
   if (bad & 1) {
-    dfree(d_in), dfree(d_if);
+    dfree(h, d_in), dfree(h, d_if);
     return fail(h, TEFMM_ERR_PARTICLE_ON_INTERFACE, "a particle lies within interface_eps of an interface");
   }
-  double mn[4][3], mx[4][3];
-  int64_t cnt[4] = {0, 0, 0, 0};
-  for (int l = 0; l < 4; ++l)
+  double mn[MAX_LAYERS][3], mx[MAX_LAYERS][3];
+  int64_t cnt[MAX_LAYERS] = {};
+  for (int l = 0; l < MAX_LAYERS; ++l)
     for (int c = 0; c < 3; ++c) mn[l][c] = 1e300, mx[l][c] = -1e300;
   for (int b = 0; b < nblk; ++b)
-    for (int l = 0; l < 4; ++l) {
-      const double* o = &part[((size_t)b * 4 + l) * 7];
+    for (int l = 0; l < MAX_LAYERS; ++l) {
+      const double* o = &part[((size_t)b * MAX_LAYERS + l) * 7];
       for (int c = 0; c < 3; ++c) mn[l][c] = std::min(mn[l][c], o[c]), mx[l][c] = std::max(mx[l][c], o[3 + c]);
       cnt[l] += (int64_t)o[6];
     }
@@ -895,7 +1101,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   // z origin of each layer's cube: centred on the layer's particles, then moved
   // (keeping them inside) so that the cube stays within the layer when the layer
   // is thick enough
-  double lo_z[4] = {0, 0, 0, 0};
+  double lo_z[MAX_LAYERS] = {};
   for (int l = 0; l <= L; ++l) {
     if (!cnt[l]) continue;
     double z0 = 0.5 * (mn[l][2] + mx[l][2]) - 0.5 * side_common;
@@ -924,7 +1130,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   }
   TreeGeom geo;
   std::memset(&geo, 0, sizeof(geo));
-  for (int l = 0; l < 4; ++l) geo.group_of_layer[l] = 0;
+  for (int l = 0; l < MAX_LAYERS; ++l) geo.group_of_layer[l] = 0;
   int64_t leaf_off = 0, pos = 0;
   for (int l = 0; l <= L; ++l) {
     if (!cnt[l]) continue;
@@ -937,6 +1143,14 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     for (int c = 0; c < 3; ++c) side = std::max(side, mx[l][c] - mn[l][c]);
     side = side * (1 + 1e-9) + 1e-12;
     for (int c = 0; c < 3; ++c) g.lo[c] = 0.5 * (mn[l][c] + mx[l][c]) - 0.5 * side;
+    // a cube taller than its particles' extent is moved (keeping them inside) to lie
+    // within the layer when the layer is thick enough: no box of it then reaches across
+    // an interface, where the reaction expansions of its lowest or highest slab would not
+    // converge above the leaf level
+    {
+      const double a0 = std::max(mx[l][2] - side, med.bottom(l)), a1 = std::min(mn[l][2], med.top(l) - side);
+      if (a0 <= a1) g.lo[2] = std::min(std::max(g.lo[2], a0), a1);
+    }
     if (ngroups > 1) {
       side = side_common;
       g.lo[0] = 0.5 * (cx0 + cx1) - 0.5 * side;
@@ -967,10 +1181,10 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   // sort particles by leaf
   unsigned *d_keys = nullptr, *d_keys2 = nullptr;
   int* d_perm_in = nullptr;
-  HIPCHK(h, hipMalloc(&d_keys, sizeof(unsigned) * n));
-  HIPCHK(h, hipMalloc(&d_keys2, sizeof(unsigned) * n));
-  HIPCHK(h, hipMalloc(&d_perm_in, sizeof(int) * n));
-  HIPCHK(h, hipMalloc(&h->d_perm, sizeof(int) * n));
+  HIPCHK(h, dmalloc(h, &d_keys, sizeof(unsigned) * n));
+  HIPCHK(h, dmalloc(h, &d_keys2, sizeof(unsigned) * n));
+  HIPCHK(h, dmalloc(h, &d_perm_in, sizeof(int) * n));
+  HIPCHK(h, dmalloc(h, &h->d_perm, sizeof(int) * n));
   const int nb256 = (int)((n + 255) / 256);
   hipLaunchKernelGGL(k_leaf_keys, dim3(nb256), dim3(256), 0, s, src, n, L, d_if, geo, d_keys, d_perm_in);
   HIPCHK(h, hipGetLastError());
@@ -980,31 +1194,31 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   HIPCHK(h, hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, d_keys, d_keys2, d_perm_in, h->d_perm, (int)n, 0,
                                                end_bit, s));
   void* d_tmp = nullptr;
-  HIPCHK(h, hipMalloc(&d_tmp, std::max<size_t>(tmp_bytes, 16)));
+  HIPCHK(h, dmalloc(h, &d_tmp, std::max<size_t>(tmp_bytes, 16)));
   HIPCHK(h, hipcub::DeviceRadixSort::SortPairs(d_tmp, tmp_bytes, d_keys, d_keys2, d_perm_in, h->d_perm, (int)n, 0,
                                                end_bit, s));
-  dfree(d_tmp);
-  HIPCHK(h, hipMalloc(&h->d_leaf_count, sizeof(int) * leaf_off));
-  HIPCHK(h, hipMalloc(&h->d_leaf_start, sizeof(int) * leaf_off));
+  dfree(h, d_tmp);
+  HIPCHK(h, dmalloc(h, &h->d_leaf_count, sizeof(int) * leaf_off));
+  HIPCHK(h, dmalloc(h, &h->d_leaf_start, sizeof(int) * leaf_off));
   HIPCHK(h, hipMemsetAsync(h->d_leaf_count, 0, sizeof(int) * leaf_off, s));
   hipLaunchKernelGGL(k_count_keys, dim3(nb256), dim3(256), 0, s, d_keys2, n, h->d_leaf_count);
   HIPCHK(h, hipGetLastError());
   tmp_bytes = 0;
   HIPCHK(h, hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, h->d_leaf_count, h->d_leaf_start, (int)leaf_off, s));
-  HIPCHK(h, hipMalloc(&d_tmp, std::max<size_t>(tmp_bytes, 16)));
+  HIPCHK(h, dmalloc(h, &d_tmp, std::max<size_t>(tmp_bytes, 16)));
   HIPCHK(h, hipcub::DeviceScan::ExclusiveSum(d_tmp, tmp_bytes, h->d_leaf_count, h->d_leaf_start, (int)leaf_off, s));
-  HIPCHK(h, hipMalloc(&h->d_xs, sizeof(double) * 3 * n));
+  HIPCHK(h, dmalloc(h, &h->d_xs, sizeof(double) * 3 * n));
   hipLaunchKernelGGL(k_gather_pos, dim3(nb256), dim3(256), 0, s, src, h->d_perm, n, h->d_xs);
   HIPCHK(h, hipGetLastError());
   std::vector<int> lc(leaf_off);
   HIPCHK(h, hipMemcpyAsync(lc.data(), h->d_leaf_count, sizeof(int) * leaf_off, hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
-  dfree(d_tmp);
-  dfree(d_keys);
-  dfree(d_keys2);
-  dfree(d_perm_in);
-  dfree(d_in);
-  dfree(d_if);
+  dfree(h, d_tmp);
+  dfree(h, d_keys);
+  dfree(h, d_keys2);
+  dfree(h, d_perm_in);
+  dfree(h, d_in);
+  dfree(h, d_if);
   HIPCHK(h, hipEventRecord(e1, s));
   // interaction counts (statistics)
   h->p2p_pairs = 0;
@@ -1080,6 +1294,11 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
       g.has[fam] = !g.famA[fam].empty();
     }
   }
+  // reaction keys that would not converge: direct lists and counts
+  for (auto& g : h->groups) {
+    int rc = reaction_convergence(h, g, lc, s);
+    if (rc != TEFMM_OK) return rc;
+  }
   // derivative tables
   h->sigma_keys = 0, h->sur_keys = 0;
   for (auto& g : h->groups) {
@@ -1102,10 +1321,10 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   (void)hipEventDestroy(e1);
   (void)hipEventDestroy(e2);
   int fi = 0;
-  for (size_t gi = 0; gi < h->groups.size() && gi < 4; ++gi) {
+  for (size_t gi = 0; gi < h->groups.size() && gi < (size_t)MAX_LAYERS; ++gi) {
     auto& g = h->groups[gi];
     h->st.depth[gi] = g.depth;
-    for (int fam = 0; fam < 3 && fi < 8; ++fam)
+    for (int fam = 0; fam < 3 && fi < 3 * MAX_LAYERS; ++fam)
       if (g.has[fam]) {
         h->st.n_images[fi] = (int)g.famA[fam].size();
         h->st.dcim_fit_err[fi] = g.fam_err[fam];
@@ -1116,6 +1335,8 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   h->st.sigma_keys = h->sigma_keys;
   h->st.surrogate_keys = h->sur_keys;
   for (auto& g : h->groups) {
+    h->st.sigma_direct_pairs += g.sd_pairs;
+    h->st.reaction_keys_forced += g.keys_forced;
     h->st.cross_pairs += g.cross_pairs;
     h->st.cross_pairs_forced += g.cross_forced;
     h->st.n_cross_fits += g.n_cross_fits;
@@ -1142,26 +1363,26 @@ static constexpr int CROSS_SPLIT = 8;
 
 static int ensure_rhs(tefmm_t h, int nrhs) {
   if (nrhs <= h->nrhs_alloc) return TEFMM_OK;
-  dfree(h->d_q);
-  dfree(h->d_phi);
-  dfree(h->d_phi_near);
+  dfree(h, h->d_q);
+  dfree(h, h->d_phi);
+  dfree(h, h->d_phi_near);
   for (auto& g : h->groups) {
-    for (auto& p : g.alpha) dfree(p);
-    for (auto& p : g.beta) dfree(p);
-    for (auto& p : g.ared) dfree(p);
-    for (auto& p : g.ared32) dfree(p);
-    for (auto& p : g.bred) dfree(p);
-    for (auto& p : g.azred) dfree(p);
-    for (auto& p : g.bzred) dfree(p);
+    for (auto& p : g.alpha) dfree(h, p);
+    for (auto& p : g.beta) dfree(h, p);
+    for (auto& p : g.ared) dfree(h, p);
+    for (auto& p : g.ared32) dfree(h, p);
+    for (auto& p : g.bred) dfree(h, p);
+    for (auto& p : g.azred) dfree(h, p);
+    for (auto& p : g.bzred) dfree(h, p);
   }
-  HIPCHK(h, hipMalloc(&h->d_q, sizeof(double2) * h->n * nrhs));
-  HIPCHK(h, hipMalloc(&h->d_phi, sizeof(double2) * h->n * nrhs));
-  HIPCHK(h, hipMalloc(&h->d_phi_near, sizeof(double2) * h->n * nrhs));
-  dfree(h->d_part);
+  HIPCHK(h, dmalloc(h, &h->d_q, sizeof(double2) * h->n * nrhs));
+  HIPCHK(h, dmalloc(h, &h->d_phi, sizeof(double2) * h->n * nrhs));
+  HIPCHK(h, dmalloc(h, &h->d_phi_near, sizeof(double2) * h->n * nrhs));
+  dfree(h, h->d_part);
   if (sym_near(h->opt)) {
     int gmax = 1;
     for (auto& g : h->groups) gmax = std::max(gmax, g.p2p_split);
-    HIPCHK(h, hipMalloc(&h->d_part,
+    HIPCHK(h, dmalloc(h, &h->d_part,
                         (h->opt.precision == TEFMM_FP64 ? sizeof(double2) : sizeof(float2)) * 13 * gmax * h->n));
   }
   for (auto& g : h->groups) {
@@ -1176,16 +1397,16 @@ static int ensure_rhs(tefmm_t h, int nrhs) {
     for (int lev = 2; lev <= g.depth; ++lev) {
       const int64_t nbx = (int64_t)1 << (3 * lev);
       g.nbox[lev] = nbx;
-      HIPCHK(h, hipMalloc(&g.alpha[lev], sizeof(double2) * nbx * h->nC * nrhs));
-      HIPCHK(h, hipMalloc(&g.beta[lev], sizeof(double2) * nbx * h->nC * nrhs));
+      HIPCHK(h, dmalloc(h, &g.alpha[lev], sizeof(double2) * nbx * h->nC * nrhs));
+      HIPCHK(h, dmalloc(h, &g.beta[lev], sizeof(double2) * nbx * h->nC * nrhs));
       if (h->opt.precision == TEFMM_MIXED_FP32)
-        HIPCHK(h, hipMalloc(&g.ared32[lev], sizeof(float2) * nbx * h->nR * nrhs));
+        HIPCHK(h, dmalloc(h, &g.ared32[lev], sizeof(float2) * nbx * h->nR * nrhs));
       else
-        HIPCHK(h, hipMalloc(&g.ared[lev], sizeof(double2) * nbx * h->nR * nrhs));
-      HIPCHK(h, hipMalloc(&g.bred[lev], sizeof(double2) * nbx * h->nR * nrhs * m2l_split(g.depth)));
+        HIPCHK(h, dmalloc(h, &g.ared[lev], sizeof(double2) * nbx * h->nR * nrhs));
+      HIPCHK(h, dmalloc(h, &g.bred[lev], sizeof(double2) * nbx * h->nR * nrhs * m2l_split(g.depth)));
       if (h->groups.size() > 1) {
-        HIPCHK(h, hipMalloc(&g.azred[lev], sizeof(double2) * nbx * h->nR * nrhs));
-        HIPCHK(h, hipMalloc(&g.bzred[lev], sizeof(double2) * nbx * h->nR * nrhs * CROSS_SPLIT));
+        HIPCHK(h, dmalloc(h, &g.azred[lev], sizeof(double2) * nbx * h->nR * nrhs));
+        HIPCHK(h, dmalloc(h, &g.bzred[lev], sizeof(double2) * nbx * h->nR * nrhs * CROSS_SPLIT));
       }
     }
   }
@@ -1213,7 +1434,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     HIPCHK(h, hipEventCreateWithFlags(&h->e_fork, hipEventDisableTiming));
     HIPCHK(h, hipEventCreateWithFlags(&h->e_join, hipEventDisableTiming));
     HIPCHK(h, hipEventCreateWithFlags(&h->e_gfork, hipEventDisableTiming));
-    for (int i = 1; i < 4; ++i) {
+    for (int i = 1; i < MAX_LAYERS; ++i) {
       HIPCHK(h, hipStreamCreateWithFlags(&h->sg[i], hipStreamNonBlocking));
       HIPCHK(h, hipEventCreateWithFlags(&h->e_gjoin[i], hipEventDisableTiming));
     }
@@ -1429,7 +1650,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
         L.b = g.bzred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
         L.split_stride = g.nbox[lev] * h->nR * h->nrhs_alloc;
         L.T[0] = g.XT0[lev], L.T[1] = g.XT1[lev], L.T32[0] = g.XT032[lev], L.T32[1] = g.XT132[lev];
-        for (size_t sg = 0; sg < h->groups.size() && sg < 4; ++sg) {
+        for (size_t sg = 0; sg < h->groups.size() && sg < (size_t)MAX_LAYERS; ++sg) {
           L.asrc[sg] = h->groups[sg].azred[lev];
           L.src_stride[sg] = h->groups[sg].nbox[lev] * h->nR;
         }
@@ -1479,6 +1700,20 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     a.nbox_dim = 1 << H, a.h = g.side / (1 << H), a.beta = g.beta[H], a.rhs_stride = g.nbox[H] * h->nC;
     const size_t lds = sizeof(double2) * h->nC;
     hipLaunchKernelGGL(k_l2p, dim3((unsigned)g.nbox[H], nrhs), dim3(64), lds, s, a);
+    HIPCHK(h, hipGetLastError());
+  }
+  // near-interface Sigma pairs evaluated directly (added to the far-field sums)
+  for (auto& g : h->groups) {
+    if (!g.sd_ntgt) continue;
+    SigmaDirectArgs sd;
+    sd.xs = h->d_xs, sd.n = n, sd.q = h->d_q, sd.phi = h->d_phi;
+    sd.leaf_start = h->d_leaf_start, sd.leaf_count = h->d_leaf_count, sd.leaf_base = g.leaf_base;
+    sd.tgt = g.d_sd_tgt, sd.src_start = g.d_sd_start, sd.src = g.d_sd_src, sd.img = g.d_sd_img;
+    sd.nup = g.sd_nup, sd.ndn = g.sd_ndn;
+    sd.two_dl = g.layer < h->med.L ? 2 * h->med.d[g.layer] : 0.0;
+    sd.two_dt = g.layer > 0 ? 2 * h->med.d[g.layer - 1] : 0.0;
+    sd.k = h->med.k[g.layer];
+    hipLaunchKernelGGL(k_sigma_direct, dim3((unsigned)g.sd_ntgt, nrhs), dim3(128), 0, s, sd);
     HIPCHK(h, hipGetLastError());
   }
   EVREC(5);
@@ -1604,8 +1839,8 @@ extern "C" int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_
   const int d0 = h->groups[0].depth;
   const int depth_opt = h->opt.depth;
   double2 *q1 = nullptr, *phi1 = nullptr;
-  HIPCHK(h, hipMalloc(&q1, sizeof(double2) * n));
-  HIPCHK(h, hipMalloc(&phi1, sizeof(double2) * n));
+  HIPCHK(h, dmalloc(h, &q1, sizeof(double2) * n));
+  HIPCHK(h, dmalloc(h, &phi1, sizeof(double2) * n));
   hipLaunchKernelGGL(k_fill_ones, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, q1, n);
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
@@ -1632,8 +1867,8 @@ extern "C" int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_
   if (rc != TEFMM_OK) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    dfree(q1);
-    dfree(phi1);
+    dfree(h, q1);
+    dfree(h, phi1);
     h->opt.depth = depth_opt;
     return rc;
   }
@@ -1667,8 +1902,8 @@ extern "C" int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  dfree(q1);
-  dfree(phi1);
+  dfree(h, q1);
+  dfree(h, phi1);
   if (depth_out) *depth_out = bd;
   if (ncb_out) *ncb_out = bn;
   return rc;
@@ -1759,7 +1994,7 @@ extern "C" int tefmm_taylor_coefficients(int n, const double* x, const double* y
   short* d_nbr = nullptr;
   if (hipMalloc(&d_nbr, sizeof(short) * 6 * nT) != hipSuccess) return TEFMM_ERR_HIP;
   if (hipMemcpy(d_nbr, nbr.data(), sizeof(short) * 6 * nT, hipMemcpyHostToDevice) != hipSuccess) {
-    dfree(d_nbr);
+    dfree_raw(d_nbr);
     return TEFMM_ERR_HIP;
   }
   const size_t lds = 2 * sizeof(double2) * nT;
@@ -1768,7 +2003,7 @@ extern "C" int tefmm_taylor_coefficients(int n, const double* x, const double* y
                      (double2*)out);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  dfree(d_nbr);
+  dfree_raw(d_nbr);
   return e == hipSuccess ? TEFMM_OK : TEFMM_ERR_HIP;
 }
 
@@ -1783,8 +2018,8 @@ extern "C" int tefmm_selftest_mfma(void) {
   hipError_t e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(h64, d64, sizeof(h64), hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(h32, d32, sizeof(h32), hipMemcpyDeviceToHost);
-  dfree(d64);
-  dfree(d32);
+  dfree_raw(d64);
+  dfree_raw(d32);
   if (e != hipSuccess) return TEFMM_ERR_HIP;
   int bad = 0;
   for (int m = 0; m < 16; ++m)
@@ -1883,9 +2118,9 @@ static int sur_image_tables(tefmm_surrogate* su, const std::vector<double>& X, c
     TableTerm* d_terms = nullptr;
     int* d_start = nullptr;
     double* d_h = nullptr;
-    HIPCHK(h, hipMalloc(&d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
-    HIPCHK(h, hipMalloc(&d_start, sizeof(int) * start.size()));
-    HIPCHK(h, hipMalloc(&d_h, sizeof(double) * cnt));
+    HIPCHK(h, dmalloc(h, &d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
+    HIPCHK(h, dmalloc(h, &d_start, sizeof(int) * start.size()));
+    HIPCHK(h, dmalloc(h, &d_h, sizeof(double) * cnt));
     if (!terms.empty())
       HIPCHK(h, hipMemcpyAsync(d_terms, terms.data(), sizeof(TableTerm) * terms.size(), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(d_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, s));
@@ -1899,9 +2134,9 @@ static int sur_image_tables(tefmm_surrogate* su, const std::vector<double>& X, c
     hipLaunchKernelGGL(k_table_gen, dim3(cnt), dim3(64), lds, s, ta);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(s));
-    dfree(d_terms);
-    dfree(d_start);
-    dfree(d_h);
+    dfree(h, d_terms);
+    dfree(h, d_start);
+    dfree(h, d_h);
   }
   return TEFMM_OK;
 }
@@ -1926,10 +2161,10 @@ static int surrogate_tables(tefmm_t h, const SigmaKeys& sk, double hb, double2* 
   float *d_u = nullptr, *d_y = nullptr;
   int* d_key = nullptr;
   double* d_re = nullptr;
-  HIPCHK(h, hipMalloc(&d_u, sizeof(float) * u.size()));
-  HIPCHK(h, hipMalloc(&d_y, sizeof(float) * (size_t)nk * 2 * nG));
-  HIPCHK(h, hipMalloc(&d_key, sizeof(int) * nk));
-  HIPCHK(h, hipMalloc(&d_re, sizeof(double) * nk));
+  HIPCHK(h, dmalloc(h, &d_u, sizeof(float) * u.size()));
+  HIPCHK(h, dmalloc(h, &d_y, sizeof(float) * (size_t)nk * 2 * nG));
+  HIPCHK(h, dmalloc(h, &d_key, sizeof(int) * nk));
+  HIPCHK(h, dmalloc(h, &d_re, sizeof(double) * nk));
   HIPCHK(h, hipMemcpyAsync(d_u, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync(d_key, sk.key.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync(d_re, sk.Re.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
@@ -1942,10 +2177,10 @@ static int surrogate_tables(tefmm_t h, const SigmaKeys& sk, double hb, double2* 
                      su->d_gord, d_out);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
-  dfree(d_u);
-  dfree(d_y);
-  dfree(d_key);
-  dfree(d_re);
+  dfree(h, d_u);
+  dfree(h, d_y);
+  dfree(h, d_key);
+  dfree(h, d_re);
   return TEFMM_OK;
 }
 
@@ -2054,8 +2289,8 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
     hipLaunchKernelGGL(k_sur_normalize, dim3(n), dim3(128), 0, s, d_raw, d_re, n, nG, su->d_gord, d_W, d_sumsq);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(s));
-    dfree(d_raw);
-    dfree(d_re);
+    dfree_raw(d_raw);
+    dfree_raw(d_re);
     return TEFMM_OK;
   };
   const int n = o.n_train;
@@ -2087,8 +2322,8 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
   SURHIP(hipMalloc(&d_X, sizeof(float) * u.size()));
   SURHIP(hipMemcpyAsync(d_X, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice, s));
   SURHIP(hipStreamSynchronize(s));
-  dfree(d_W);
-  dfree(d_sumsq);
+  dfree_raw(d_W);
+  dfree_raw(d_sumsq);
   auto t1 = std::chrono::steady_clock::now();
   // training on the matrix cores
   SURHIP(su->net.init(3, o.width, o.n_hidden, 2 * nG, o.seed ^ 0x5bd1e995ull));
@@ -2096,8 +2331,8 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
   SURHIP(su->net.train(d_X, d_T, n, o.epochs, o.batch, o.lr, o.seed + 17, losses, s));
   if (epoch_loss)
     for (size_t i = 0; i < losses.size(); ++i) epoch_loss[i] = losses[i];
-  dfree(d_X);
-  dfree(d_T);
+  dfree_raw(d_X);
+  dfree_raw(d_T);
   auto t2 = std::chrono::steady_clock::now();
   // validation map: n_valid fresh points per cell
   const int ncell = o.cells_xy * o.cells_xy * o.cells_s, nv = ncell * o.n_valid;
@@ -2130,9 +2365,9 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
   SURHIP(hipMemcpyAsync(vW.data(), d_vW, sizeof(double2) * vW.size(), hipMemcpyDeviceToHost, s));
   SURHIP(hipMemcpyAsync(vy.data(), d_vy, sizeof(float) * vy.size(), hipMemcpyDeviceToHost, s));
   SURHIP(hipStreamSynchronize(s));
-  dfree(d_vW);
-  dfree(d_vu);
-  dfree(d_vy);
+  dfree_raw(d_vW);
+  dfree_raw(d_vu);
+  dfree_raw(d_vy);
   su->cell_ok.assign(ncell, 0);
   su->cell_err.assign(ncell, 0.0);
   double emax = 0;

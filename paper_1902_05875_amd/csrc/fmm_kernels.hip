@@ -196,47 +196,60 @@ __global__ __launch_bounds__(64) void k_selftest_mfma(double* out64, float* out3
 // ---------------------------------------------------------------------------
 __global__ void k_layer_stats(const double* xyz, int64_t n, int nif, const double* ifz, double eps,
                               double* part, int* bad) {
-  // per block: for up to 4 layers, min/max of x, y, z and counts
-  __shared__ double smin[4][3][256], smax[4][3][256];
-  __shared__ int scnt[4][256];
+  // per block and layer (up to MAX_LAYERS): min/max of x, y, z and the count; each thread
+  // keeps its own per layer (selects, no indexed registers), then one layer at a time is
+  // reduced through LDS
+  __shared__ double smin[3][256], smax[3][256];
+  __shared__ int scnt[256];
   const int tid = threadIdx.x;
-  for (int l = 0; l < 4; ++l) {
-    for (int c = 0; c < 3; ++c) smin[l][c][tid] = 1e300, smax[l][c][tid] = -1e300;
-    scnt[l][tid] = 0;
+  double mn[MAX_LAYERS][3], mx[MAX_LAYERS][3];
+  int cnt[MAX_LAYERS];
+#pragma unroll
+  for (int l = 0; l < MAX_LAYERS; ++l) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mn[l][c] = 1e300, mx[l][c] = -1e300;
+    cnt[l] = 0;
   }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + tid; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
-    int l = 0;
+    const double x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+    int ly = 0;
     for (int j = 0; j < nif; ++j) {
-      l += (z < ifz[j]);
+      ly += (z < ifz[j]);
       if (fabs(z - ifz[j]) < eps) atomicOr(bad, 1);
     }
     if (!(x == x) || !(y == y) || !(z == z)) atomicOr(bad, 2);
-    double v[3] = {x, y, z};
-    for (int c = 0; c < 3; ++c) {
-      smin[l][c][tid] = fmin(smin[l][c][tid], v[c]);
-      smax[l][c][tid] = fmax(smax[l][c][tid], v[c]);
-    }
-    scnt[l][tid] += 1;
-  }
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s)
-      for (int l = 0; l < 4; ++l) {
-        for (int c = 0; c < 3; ++c) {
-          smin[l][c][tid] = fmin(smin[l][c][tid], smin[l][c][tid + s]);
-          smax[l][c][tid] = fmax(smax[l][c][tid], smax[l][c][tid + s]);
-        }
-        scnt[l][tid] += scnt[l][tid + s];
+    const double v[3] = {x, y, z};
+#pragma unroll
+    for (int l = 0; l < MAX_LAYERS; ++l)
+      if (l == ly) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mn[l][c] = fmin(mn[l][c], v[c]), mx[l][c] = fmax(mx[l][c], v[c]);
+        cnt[l] += 1;
       }
-    __syncthreads();
   }
-  if (tid == 0)
-    for (int l = 0; l < 4; ++l) {
-      double* o = part + ((size_t)blockIdx.x * 4 + l) * 7;
-      for (int c = 0; c < 3; ++c) o[c] = smin[l][c][0], o[3 + c] = smax[l][c][0];
-      o[6] = (double)scnt[l][0];
+#pragma unroll
+  for (int l = 0; l < MAX_LAYERS; ++l) {
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) smin[c][tid] = mn[l][c], smax[c][tid] = mx[l][c];
+    scnt[tid] = cnt[l];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        for (int c = 0; c < 3; ++c) {
+          smin[c][tid] = fmin(smin[c][tid], smin[c][tid + s]);
+          smax[c][tid] = fmax(smax[c][tid], smax[c][tid + s]);
+        }
+        scnt[tid] += scnt[tid + s];
+      }
+      __syncthreads();
     }
+    if (tid == 0) {
+      double* o = part + ((size_t)blockIdx.x * MAX_LAYERS + l) * 7;
+      for (int c = 0; c < 3; ++c) o[c] = smin[c][0], o[3 + c] = smax[c][0];
+      o[6] = (double)scnt[0];
+    }
+  }
 }
 
 __global__ void k_leaf_keys(const double* xyz, int64_t n, int nif, const double* ifz, TreeGeom geo,
@@ -291,6 +304,68 @@ __global__ void k_finalize(const double2* phi_s, const double2* phi_near, const 
   const double2 f = phi_s[(int64_t)r * n + i], c = phi_near[(int64_t)r * n + i];
   const double2 v = make_double2(f.x + c.x, f.y + c.y);
   out[(int64_t)r * n + perm[i]] = make_double2(v.x * sr - v.y * si, v.x * si + v.y * sr);
+}
+
+// ---------------------------------------------------------------------------
+// Direct Sigma-family reaction interactions of listed leaf pairs (the local
+// reaction interactions of Algorithm 1 evaluated directly, here only where the
+// expansions would not converge).  One workgroup of 128 per listed target leaf and
+// charge vector (blockIdx.y); targets in passes of 128, sources staged in LDS in
+// chunks of 128; every target written by one lane (no atomics).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(128) void k_sigma_direct(SigmaDirectArgs a) {
+  __shared__ double sx[128], sy[128], sz[128];
+  __shared__ double2 sq[128];
+  __shared__ double2 simg[2 * SIGMA_DIRECT_MAX_IMAGES];
+  const int tl = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int nimg = a.nup + a.ndn;
+  for (int i = tid; i < 2 * nimg; i += 128) simg[i] = a.img[i];
+  const int leaf = a.tgt[tl];
+  const int ts = a.leaf_start[a.leaf_base + leaf], tc = a.leaf_count[a.leaf_base + leaf];
+  const int s0 = a.src_start[tl], s1 = a.src_start[tl + 1];
+  const double* X = a.xs;
+  const double* Y = a.xs + a.n;
+  const double* Z = a.xs + 2 * a.n;
+  const double2* q = a.q + (int64_t)r * a.n;
+  for (int t0 = 0; t0 < tc; t0 += 128) {
+    const int i = t0 + tid;
+    const bool act = i < tc;
+    const double xt = act ? X[ts + i] : 0.0, yt = act ? Y[ts + i] : 0.0, zt = act ? Z[ts + i] : 0.0;
+    dc acc = {0.0, 0.0};
+    for (int e = s0; e < s1; ++e) {
+      const int sl = a.src[e];
+      const int ss = a.leaf_start[a.leaf_base + sl], sc = a.leaf_count[a.leaf_base + sl];
+      for (int c0 = 0; c0 < sc; c0 += 128) {
+        const int cn = min(128, sc - c0);
+        __syncthreads();
+        if (tid < cn) {
+          const int j = ss + c0 + tid;
+          sx[tid] = X[j], sy[tid] = Y[j], sz[tid] = Z[j], sq[tid] = q[j];
+        }
+        __syncthreads();
+        if (!act) continue;
+        for (int j = 0; j < cn; ++j) {
+          const double dx = xt - sx[j], dy = yt - sy[j], S = zt + sz[j];
+          const double rho2 = dx * dx + dy * dy;
+          dc kv = {0.0, 0.0};
+          for (int m = 0; m < nimg; ++m) {
+            const double2 A = simg[2 * m], Zi = simg[2 * m + 1];
+            const double e0 = m < a.nup ? S - a.two_dl : a.two_dt - S;
+            const dc zeta = {e0 - Zi.x, -Zi.y};
+            if (zeta.x <= 0.0) continue;
+            const dc R2 = {rho2 + zeta.x * zeta.x - zeta.y * zeta.y, 2.0 * zeta.x * zeta.y};
+            const dc R = csqrt_pr(R2);
+            kv = cadd(kv, cmul({A.x, A.y}, cdiv(cexp_i(R, a.k), R)));
+          }
+          acc = cadd(acc, cmul(kv, {sq[j].x, sq[j].y}));
+        }
+      }
+    }
+    if (act) {
+      double2* o = a.phi + (int64_t)r * a.n + ts + i;
+      *o = make_double2(o->x + acc.x, o->y + acc.y);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -6,6 +6,8 @@
 
 namespace tefmm {
 
+constexpr int MAX_LAYERS = 8;  // layers of the medium (the C ABI's TEFMM_MAX_LAYERS)
+
 // One term of a derivative-table key: coef * f(x, y, zeta) in box units,
 // f = exp(i kh R)/R; flip = 1 when the key's variable enters zeta with a minus sign.
 struct TableTerm {
@@ -28,11 +30,11 @@ struct TableGenArgs {
 };
 
 struct TreeGeom {
-  int group_of_layer[4];
-  int depth[4];
-  double lo[4][3];
-  double side[4];
-  int64_t leaf_offset[4];
+  int group_of_layer[MAX_LAYERS];
+  int depth[MAX_LAYERS];
+  double lo[MAX_LAYERS][3];
+  double side[MAX_LAYERS];
+  int64_t leaf_offset[MAX_LAYERS];
 };
 
 // Arguments shared by the per-box passes (P2M, M2M, L2L, L2P, P2P).
@@ -124,8 +126,8 @@ struct M2LCrossLevel {
   int64_t rhs_stride;
   const double2* T[2];     // tables per k3' in {0, 1}: [nkeys][nG] (swapped frame)
   const float2* T32[2];
-  const double2* asrc[4];  // z-reduced moments of each source group at this level
-  int64_t src_stride[4];
+  const double2* asrc[MAX_LAYERS];  // z-reduced moments of each source group at this level
+  int64_t src_stride[MAX_LAYERS];
   int64_t split_stride;    // elements between the partial outputs of the list splits
 };
 
@@ -140,6 +142,32 @@ struct M2LCrossArgs {
 };
 
 hipError_t launch_m2l_cross(const M2LCrossArgs& a, int nrhs, bool fp32, hipStream_t s);
+
+// Direct evaluation of the Sigma-family reaction kernel (the same-layer reaction
+// component that depends on z + z') for the leaf pairs whose expansion about the box
+// centres would not converge (boxes next to an interface): for each target in a listed
+// leaf, phi += sum over its listed source leaves of q_j K(x - x', y - y', z + z') with
+// K = sum_img A e^{ikR}/R, R^2 = rho^2 + zeta^2, zeta = z + z' - 2 d_l - Z (up-going
+// family) or 2 d_{l-1} - z - z' - Z (down-going family), terms with Re zeta <= 0 left out
+// as in the tables.  FP64.
+constexpr int SIGMA_DIRECT_MAX_IMAGES = 128;
+struct SigmaDirectArgs {
+  const double* xs;        // sorted positions SoA [3][n]
+  int64_t n;
+  const double2* q;        // sorted charges [rhs][n]
+  double2* phi;            // sorted potentials [rhs][n] (accumulated)
+  const int* leaf_start;
+  const int* leaf_count;
+  int64_t leaf_base;
+  const int* tgt;          // [ntgt] listed target leaves (grid index in the group)
+  const int* src_start;    // [ntgt + 1]
+  const int* src;          // source leaves of each target leaf
+  const double2* img;      // [2 (nup + ndn)]: A_j, Z_j of the up-going images, then the down-going ones
+  int nup, ndn;
+  double two_dl, two_dt;   // 2 d_l and 2 d_{l-1}
+  double k;
+};
+__global__ void k_sigma_direct(SigmaDirectArgs a);
 
 void upload_binomials();
 

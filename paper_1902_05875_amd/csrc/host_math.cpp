@@ -459,6 +459,54 @@ bool two_level_dcim(F theta, double k, double T0, double T1, int samples, double
   return true;
 }
 
+// Cancellation among the image terms in space: the largest ratio of sum |term| to
+// |sum of terms| of K(rho, Z) = sum_j A_j e^{ikR_j}/R_j, R_j^2 = rho^2 + (Z - Z_j)^2,
+// over heights Z = 0, span/2, span above the decay shift and rho = 0, 0.5, 2.  A fit whose
+// singular values just pass the cut can pair nearly equal poles with huge opposite
+// residues: the spectral samples are matched, but in space the terms cancel to few
+// digits.
+static double image_cancellation(const ImageSet& im, double k, double span) {
+  double worst = 1.0;
+  const cplx I(0, 1);
+  for (double Zr : {0.0, 0.5 * span, span})
+    for (double rho : {0.0, 0.5, 2.0}) {
+      cplx s(0, 0);
+      double a = 0.0;
+      for (size_t j = 0; j < im.A.size(); ++j) {
+        const cplx zeta = Zr - im.Z[j];
+        const cplx R = std::sqrt(rho * rho + zeta * zeta);
+        const cplx t = im.A[j] * std::exp(I * k * R) / R;
+        s += t, a += std::abs(t);
+      }
+      if (a > 0) worst = std::max(worst, std::abs(s) > 0 ? a / std::abs(s) : 1e300);
+    }
+  return worst;
+}
+
+// two_level_dcim with the singular-value cut raised tenfold (up to four times) while the
+// image terms cancel in space by more than twelve digits (a degenerate pole pair; usual
+// fits, whose deep images carry large amplitudes, stay well below); the least
+// cancelling fit is kept.
+template <class F>
+static bool robust_dcim(F theta, double k, double T0, double T1, int samples, double svd_tol, double span,
+                        ImageSet& out, std::string& err) {
+  double best = 0.0;
+  bool have = false;
+  double tol = svd_tol;
+  for (int attempt = 0; attempt < 5; ++attempt, tol *= 10.0) {
+    ImageSet im;
+    std::string e2;
+    if (!two_level_dcim(theta, k, T0, T1, samples, tol, im, e2)) {
+      if (!have) err = e2;
+      continue;
+    }
+    const double c = image_cancellation(im, k, span);
+    if (!have || c < best) out = im, best = c, have = true;
+    if (c <= 1e12) break;
+  }
+  return have;
+}
+
 bool same_layer_family(const MediumDesc& med, int l, int family, double z_lo, double z_hi,
                        double T1, int samples, double svd_tol, std::vector<cplx>& amp,
                        std::vector<cplx>& depth, double& fit_err, std::string& err) {
@@ -487,17 +535,44 @@ bool same_layer_family(const MediumDesc& med, int l, int family, double z_lo, do
   const double T0 = std::sqrt(((kmax + 0.8) / kl) * ((kmax + 0.8) / kl) - 1.0);
   const cplx I(0, 1);
   std::vector<cplx> sig;
+  // Quasi-static image of the Sigma families: the density tends to a constant sigma_inf
+  // as k_rho grows (the reflection coefficient of the interface for evanescent waves),
+  // which in space is one image at the mirror point, sigma_inf e^{ikR}/R with R the
+  // mirror distance.  It is taken out exactly and only the remainder (falling like
+  // k_rho^-2) is fitted: the sampling paths reach |k_z| ~ k (T0 + T1) only, too short
+  // to pin the constant for pairs much closer than 1/(k T1) to the mirror point.
+  cplx sig_inf(0, 0);
+  if (family != 2) {
+    reaction_densities(med, l, cplx(1e8 * kl, 0), sig);
+    sig_inf = sig[l * 4 + ab];
+  }
   auto theta = [&](cplx kzl) {
     cplx krho = std::sqrt(cplx(kl * kl, 0) - kzl * kzl);
     reaction_densities(med, l, krho, sig);
-    return sig[l * 4 + ab] * std::exp(I * kzl * zmin);
+    return (sig[l * 4 + ab] - sig_inf) * std::exp(I * kzl * zmin);
   };
+  // Pairs closer to the mirror point than ~1/(k T1) need the density beyond the first
+  // path's end |k_z| = k (T0 + T1): for the Sigma families the path is lengthened to
+  // T1 = 1.2 / (k z_min) when that is longer (at most 40), with the sample spacing kept.
+  double T1e = T1;
+  int ns = samples;
+  if (family != 2) {
+    const double want = 1.2 / (kl * std::max(zmin, 1e-12));
+    if (want > T1) {
+      T1e = std::min(want, std::max(T1, 40.0));
+      ns = std::min(std::max(samples, 401), (int)std::ceil(samples * T1e / T1)) | 1;
+    }
+  }
   ImageSet im;
-  if (!two_level_dcim(theta, kl, T0, T1, samples, svd_tol, im, err)) return false;
+  if (!robust_dcim(theta, kl, T0, T1e, ns, svd_tol, 2.0 * (z_hi - z_lo), im, err)) return false;
   fit_err = im.fit_err;
   for (size_t i = 0; i < im.A.size(); ++i) {
     amp.push_back(im.A[i]);
     depth.push_back(zmin + im.Z[i]);
+  }
+  if (std::abs(sig_inf) > 0) {
+    amp.push_back(sig_inf);
+    depth.push_back(cplx(0, 0));
   }
   return true;
 }
@@ -530,7 +605,7 @@ bool cross_layer_fit(const MediumDesc& med, int l, int lp, int a, double zs, int
     return s / kf * std::exp(I * kzl * zmin);
   };
   ImageSet im;
-  if (!two_level_dcim(theta, kl, T0, T1, samples, svd_tol, im, err)) return false;
+  if (!robust_dcim(theta, kl, T0, T1, samples, svd_tol, z_hi - z_lo, im, err)) return false;
   fit_err = im.fit_err;
   for (size_t i = 0; i < im.A.size(); ++i) {
     amp.push_back(im.A[i]);

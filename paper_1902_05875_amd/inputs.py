@@ -95,6 +95,19 @@ def workload(name: str, n: int | None = None, n_rhs: int | None = None):
     raise ValueError(name)
 
 
+def near_interface(side, n=2000, n_near=100, seed=170, gap=(0.01, 0.02)):
+    """Particles next to one interface of the middle layer: n - n_near uniform in the
+    mid-layer cube, n_near with heights gap[0]-gap[1] from the interface (side "top":
+    below z = 0; "bottom": above z = -1.2), x and y uniform in [-1/2, 1/2]; then complex
+    U[-1, 1] charges.  Returns (xyz, q); the near particles are the last n_near."""
+    rng = np.random.default_rng(seed + (side == "bottom"))
+    bulk = cube(rng, n - n_near, MID_CENTRE)
+    dz = rng.uniform(gap[0], gap[1], n_near)
+    z = -dz if side == "top" else -1.2 + dz
+    near = np.column_stack([rng.random((n_near, 2)) - 0.5, z])
+    return np.concatenate([bulk, near]), charges(rng, n)
+
+
 def with_close_pairs(xyz, q, n_pairs, dist, seed):
     """Append n_pairs particles, each at distance `dist` (random direction) from a
     randomly chosen existing particle, with fresh U[-1,1] complex charges.  Returns

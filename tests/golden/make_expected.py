@@ -3,12 +3,15 @@
 Calls only oracle/ (and the seeded input generators).  Usage:
     python tests/golden/make_expected.py [case ...]
 Cases: c1 (N=1000, all targets), c2s (N=200,000, 64 sampled targets),
-c4s (N=1,000,000, 16 sampled targets), n20k (N=20,000, 128 sampled targets),
+c4s (N=1,000,000, 16 sampled targets), c4m (the same geometry, 64 sampled targets: 48 uniform + the
+16 closest to an interface), c5r (the 500,000-particle geometry with 32 charge vectors, 8 sampled
+targets, every vector), c5g (the 16 geometries of the batched workload, 16 sampled targets each), n20k (N=20,000, 128 sampled targets),
 c3small (three layers, N=3000, 300 targets), c3s (three layers, N=1,000,000, 6 targets per layer),
 c1ns (c1 plus 24 particles at distance 1e-6 from existing ones; the 48 particles of those pairs),
-ex2small (the Example-2 domain, N=20,000, 64 sampled targets), ex2s (the same domain, N=1,000,000,
+nearif_top, nearif_bottom (N=2000 with 100 particles 0.01-0.02 from one interface; 50 targets), ex2small (the Example-2 domain, N=20,000, 64 sampled targets), ex2s (the same domain, N=1,000,000,
 16 sampled targets).
-Output: tests/golden/expected_<case>.txt with columns  index  re  im.
+Output: tests/golden/expected_<case>.txt with columns  index  re  im  (c5r: index  vector  re  im;
+c5g: geometry  index  re  im).
 """
 from __future__ import annotations
 
@@ -44,6 +47,18 @@ def case_spec(name):
     if name == "c4s":
         xyz, q = inputs.workload("c4")
         return xyz, q, inputs.sample_targets(xyz, 12, 4, seed=104)
+    if name == "c4m":
+        xyz, q = inputs.workload("c4")
+        return xyz, q, inputs.sample_targets(xyz, 48, 16, seed=1040)
+    if name == "c5r":
+        xyz, q = inputs.workload("c5")
+        return xyz, q, inputs.sample_targets(xyz, 6, 2, seed=105)
+    if name in ("nearif_top", "nearif_bottom"):
+        xyz, q = inputs.near_interface(name.split("_")[1])
+        rng = np.random.default_rng(171)
+        n = xyz.shape[0]
+        near = np.arange(n - 100, n)
+        return xyz, q, np.sort(np.concatenate([rng.choice(n - 100, 24, replace=False), near[::4], [n - 1]]))
     if name == "c3small":
         xyz, q = inputs.workload("c3", n=3000)
         rng = np.random.default_rng(130)
@@ -85,7 +100,34 @@ def _init(name):
     _G["xyz"], _G["q"] = xyz, q
 
 
+def _init_geom(g):
+    xyz, q = inputs.c5_geometries()[g]
+    _G["xyz"], _G["q"] = xyz, q
+
+
+def run_c5g(procs=None):
+    """The 16 batched geometries, 16 targets each (12 uniform + the 4 closest to an interface)."""
+    procs = procs or min(8, os.cpu_count() or 1)
+    geoms = inputs.c5_geometries()
+    rows = []
+    t0 = time.time()
+    for g, (xyz, q) in enumerate(geoms):
+        targets = inputs.sample_targets(xyz, 12, 4, seed=1050 + g)
+        chunks = np.array_split(targets, min(len(targets), procs))
+        with mp.get_context("fork").Pool(procs, initializer=_init_geom, initargs=(g,)) as pool:
+            phi = np.concatenate(pool.map(_work, chunks))
+        rows.append(np.column_stack([np.full(len(targets), g), targets, phi.real, phi.imag]))
+        print(f"c5g: geometry {g} (N={xyz.shape[0]}) done at {time.time() - t0:.1f} s", flush=True)
+    out = os.path.join(HERE, "expected_c5g.txt")
+    np.savetxt(out, np.concatenate(rows), fmt=["%d", "%d", "%.17e", "%.17e"],
+               header="oracle direct sum (oracle/direct.py), case c5g: the 16 geometries of the batched "
+                      "workload; columns: geometry, target index, Re phi, Im phi (physical normalisation)")
+    print(f"c5g: {sum(len(r) for r in rows)} targets in {time.time() - t0:.1f} s -> {out}", flush=True)
+
+
 def run(name, procs=None):
+    if name == "c5g":
+        return run_c5g(procs)
     xyz, q, targets = case_spec(name)
     procs = procs or min(8, os.cpu_count() or 1)
     chunks = np.array_split(targets, max(1, min(len(targets), procs * 4)))
@@ -94,6 +136,15 @@ def run(name, procs=None):
         parts = pool.map(_work, chunks)
     phi = np.concatenate(parts)
     out = os.path.join(HERE, f"expected_{name}.txt")
+    if phi.ndim == 2:  # several charge vectors: one row per (target, vector)
+        R = phi.shape[1]
+        np.savetxt(out, np.column_stack([np.repeat(targets, R), np.tile(np.arange(R), len(targets)),
+                                         phi.real.ravel(), phi.imag.ravel()]),
+                   fmt=["%d", "%d", "%.17e", "%.17e"],
+                   header=f"oracle direct sum (oracle/direct.py), case {name}, N={xyz.shape[0]}, {R} charge "
+                          f"vectors; columns: target index, vector, Re phi, Im phi (physical normalisation)")
+        print(f"{name}: {len(targets)} targets x {R} vectors in {time.time() - t0:.1f} s -> {out}", flush=True)
+        return
     np.savetxt(out, np.column_stack([targets, phi.real, phi.imag]), fmt=["%d", "%.17e", "%.17e"],
                header=f"oracle direct sum (oracle/direct.py), case {name}, N={xyz.shape[0]}; "
                       f"columns: target index, Re phi, Im phi (physical normalisation)")

@@ -2,6 +2,8 @@
 import numpy as np
 import pytest
 
+from parity import check
+
 pytestmark = pytest.mark.gpu
 
 K3 = (0.8, 1.5, 2.0)
@@ -94,6 +96,4 @@ def test_autotune_keeps_results():
                                                  "expected_n20k.txt"))
     tg = idx[:, 0].astype(int)
     ref = idx[:, 1] + 1j * idx[:, 2]
-    e = float(np.linalg.norm(phi[tg] - ref) / np.linalg.norm(ref))
-    print(f"autotune depth {depth} ncb {ncb} err {e:.2e}")
-    assert e < 1e-4
+    check(f"autotune depth {depth} ncb {ncb}", phi[tg], ref, 1e-4)

@@ -4,6 +4,8 @@ import os
 import numpy as np
 import pytest
 
+from parity import check
+
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -51,7 +53,7 @@ def test_equal_k_three_layers():
     print("equal-k three layers p=10: rel err", e, "per layer", per, "depth", st["depth"],
           "cross pairs", st["cross_pairs"], "forced", st["cross_pairs_forced"], "fits", st["n_cross_fits"])
     assert st["cross_pairs"] > 0 and st["cross_pairs_forced"] == 0
-    assert e < 1e-5
+    check("equal-k three layers p=10", phi[tg], ref, 1e-5)
 
 
 @pytest.mark.parametrize("p,precision,tol", [(8, "fp64", 3e-5), (12, "fp64", 3e-6), (8, "fp32", 3e-5)])
@@ -68,7 +70,7 @@ def test_c3small(p, precision, tol):
     print(f"c3small p={p} {precision}: rel err {e:.3e} per layer {per} depth {st['depth']} "
           f"cross pairs {st['cross_pairs']} fits {st['n_cross_fits']} fit err {st['cross_fit_err']:.1e}")
     assert st["cross_pairs_forced"] == 0
-    assert e < tol
+    check(f"c3 p={p} {precision}", phi[idx], ref, tol)
 
 
 @pytest.mark.parametrize("p,precision,tol", [(12, "fp64", 1e-6), (10, "fp32", 1e-4)])
@@ -86,4 +88,4 @@ def test_c3_full_size_sampled(p, precision, tol):
     print(f"c3 N=1M p={p} {precision}: rel err {e:.3e} per layer {per} depth {st['depth']} "
           f"cross pairs {st['cross_pairs']} fits {st['n_cross_fits']}")
     assert st["cross_pairs_forced"] == 0
-    assert e < tol
+    check(f"c3 p={p} {precision}", phi[idx], ref, tol)

@@ -1,8 +1,11 @@
 """Media other than the three-layer one of the workloads, against the oracle's direct sum:
 one layer (free space, no interface), two layers (one interface; particles in one layer, and in
-both, which takes the cross-layer translations), four layers (three interfaces)."""
+both, which takes the cross-layer translations), four layers (three interfaces), five and
+eight layers (the most the library takes) with particles in two of them."""
 import numpy as np
 import pytest
+
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -12,13 +15,18 @@ CASES = {
     "two": ((1.0, 2.0), (0.0,), [(-0.6, 1500)]),
     "two_both": ((1.0, 2.0), (0.0,), [(0.6, 800), (-0.6, 800)]),
     "four": ((0.8, 1.5, 2.0, 1.2), (0.0, -1.2, -2.0), [(-0.6, 1500)]),
+    "five_both": ((0.8, 1.5, 2.0, 1.2, 0.9), (0.0, -1.2, -2.0, -2.6), [(-0.6, 900), (-2.3, 500, 0.4)]),
+    "eight_both": ((0.8, 1.5, 2.0, 1.2, 0.9, 1.7, 1.1, 1.4), (0.0, -1.2, -2.0, -2.6, -3.4, -4.0, -4.8),
+                   [(-0.6, 900), (-3.0, 500, 0.5)]),
 }
 
 
 def _case(name):
     k, d, cubes = CASES[name]
     rng = np.random.default_rng(600 + list(CASES).index(name))
-    xyz = np.concatenate([rng.uniform(-0.5, 0.5, (n, 3)) + [0.0, 0.0, zc] for zc, n in cubes])
+    # cubes of side 1 unless a side is given (a thin layer holds a smaller cube)
+    xyz = np.concatenate([rng.uniform(-0.5, 0.5, (c[1], 3)) * (c[2] if len(c) > 2 else 1.0) + [0.0, 0.0, c[0]]
+                          for c in cubes])
     q = rng.uniform(-1, 1, len(xyz)) + 1j * rng.uniform(-1, 1, len(xyz))
     return k, d, xyz, q
 
@@ -38,6 +46,4 @@ def test_media(name, precision, p, tol):
     f.close()
     tg = np.arange(0, len(xyz), len(xyz) // 40)
     ref = direct.potential(Medium(k, d), xyz, q, tg)
-    e = float(np.linalg.norm(phi[tg] - ref) / np.linalg.norm(ref))
-    print(f"{name} {precision} p={p}: rel err {e:.3e} depth {st['depth']}")
-    assert e < tol
+    check(f"{name} {precision} p={p} depth {st['depth']}", phi[tg], ref, tol)

@@ -4,6 +4,8 @@ import os
 import numpy as np
 import pytest
 
+from parity import check
+
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -28,10 +30,6 @@ def _expected(name):
     return a[:, 0].astype(int), a[:, 1] + 1j * a[:, 2]
 
 
-def _err(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
 def test_free_space_equal_k():
     """One wave number everywhere: the reaction vanishes and the FMM is the free-space TE-FMM."""
     import torch
@@ -45,9 +43,7 @@ def test_free_space_equal_k():
     f.close()
     tg = inputs.sample_targets(xyz, 200, 0, seed=7)
     ref = direct.free_part(Medium((1.5, 1.5, 1.5), D3), xyz, q, tg)
-    e = _err(phi[tg], ref)
-    print("equal-k free-space FMM p=8 rel err", e)
-    assert e < 1e-5
+    check("equal-k free-space FMM p=8", phi[tg], ref, 1e-5)
 
 
 @pytest.mark.parametrize("p,precision,tol", [(4, "fp64", 3e-3), (8, "fp64", 3e-5), (12, "fp64", 1e-6),
@@ -58,9 +54,7 @@ def test_c1(p, precision, tol):
     xyz, q = inputs.workload("c1")
     idx, ref = _expected("c1")
     phi, st = _run(xyz, q, p=p, depth=2, precision=precision)
-    e = _err(phi[idx], ref)
-    print(f"C1 p={p} {precision} rel err {e:.3e} images {st['n_images']}")
-    assert e < tol
+    check(f"C1 p={p} {precision} images {st['n_images']}", phi[idx], ref, tol)
 
 
 @pytest.mark.parametrize("p,tol", [(8, 3e-5), (10, 5e-6), (12, 1e-6), (14, 1e-6)])
@@ -69,9 +63,7 @@ def test_n20k_sampled(p, tol):
     xyz, q = inputs.workload("c2", n=20_000)
     idx, ref = _expected("n20k")
     phi, st = _run(xyz, q, p=p)
-    e = _err(phi[idx], ref)
-    print(f"N=20k p={p} depth {st['depth'][0]} rel err {e:.3e}")
-    assert e < tol
+    check(f"N=20k p={p} depth {st['depth'][0]}", phi[idx], ref, tol)
 
 
 @pytest.mark.parametrize("tile", [1, 2])
@@ -82,9 +74,7 @@ def test_n20k_fp64_p13_tiles(tile):
     xyz, q = inputs.workload("c2", n=20_000)
     idx, ref = _expected("n20k")
     phi, st = _run(xyz, q, p=13, m2l_tile=tile)
-    e = _err(phi[idx], ref)
-    print(f"N=20k p=13 tile {tile} depth {st['depth'][0]} rel err {e:.3e}")
-    assert e < 1e-6
+    check(f"N=20k p=13 tile {tile} depth {st['depth'][0]}", phi[idx], ref, 1e-6)
 
 
 @pytest.mark.parametrize("p,precision,tol", [(8, "fp64", 3e-5), (12, "fp64", 1e-6), (8, "fp32", 1e-4)])
@@ -95,11 +85,8 @@ def test_c2_sampled(p, precision, tol):
     xyz, q = inputs.workload("c2")
     idx, ref = _expected("c2s")
     phi, st = _run(xyz, q, p=p, precision=precision)
-    e = _err(phi[idx], ref)
-    near = idx[-16:]
-    print(f"C2 p={p} {precision} depth {st['depth'][0]} rel err {e:.3e}")
     assert st["depth"][0] == 4
-    assert e < tol
+    check(f"C2 p={p} {precision} depth {st['depth'][0]}", phi[idx], ref, tol)
 
 
 @pytest.mark.parametrize("precision,nrhs,p", [("fp64", 9, 6), ("fp32", 9, 6), ("fp32", 3, 7), ("fp32", 6, 7)])
@@ -183,9 +170,7 @@ def test_near_singular_pairs(precision):
     xyz, q, _ = inputs.with_close_pairs(xyz, q, 24, 1e-6, seed=140)
     idx, ref = _expected("c1ns")
     phi, st = _run(xyz, q, p=8, depth=2, precision=precision)
-    e = _err(phi[idx], ref)
-    print(f"near-singular pairs {precision}: rel err {e:.3e}")
-    assert e < 1e-6
+    check(f"near-singular pairs {precision}", phi[idx], ref, 1e-6)
 
 
 @pytest.mark.parametrize("p,precision,depth,tol", [(13, "fp64", 4, 1e-6), (8, "fp32", 4, 1e-4), (8, "fp32", 5, 1e-4),
@@ -199,9 +184,7 @@ def test_c4_full_size_sampled(p, precision, depth, tol):
     xyz, q = inputs.workload("c4")
     idx, ref = _expected("c4s")
     phi, st = _run(xyz, q, p=p, precision=precision, depth=depth)
-    e = _err(phi[idx], ref)
-    print(f"C4 N=1M p={p} {precision} depth {depth}: rel err {e:.3e}")
-    assert e < tol
+    check(f"C4 N=1M p={p} {precision} depth {depth}", phi[idx], ref, tol)
 
 
 @pytest.mark.parametrize("p,precision,tol", [(8, "fp64", 3e-5), (12, "fp64", 1e-6), (7, "fp32", 1e-4)])
@@ -213,9 +196,7 @@ def test_example2_domain(p, precision, tol):
     xyz, q = inputs.workload("ex2", n=20_000)
     idx, ref = _expected("ex2small")
     phi, st = _run(xyz, q, p=p, precision=precision)
-    e = _err(phi[idx], ref)
-    print(f"Example 2 N=20k p={p} {precision} depth {st['depth'][0]}: rel err {e:.3e}")
-    assert e < tol
+    check(f"Example 2 N=20k p={p} {precision} depth {st['depth'][0]}", phi[idx], ref, tol)
 
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "expected_ex2s.txt")), reason="no stored values")
@@ -226,9 +207,7 @@ def test_example2_full_size_sampled(p, precision, tol):
     xyz, q = inputs.workload("ex2")
     idx, ref = _expected("ex2s")
     phi, st = _run(xyz, q, p=p, precision=precision)
-    e = _err(phi[idx], ref)
-    print(f"Example 2 N=1M p={p} {precision} depth {st['depth'][0]}: rel err {e:.3e}")
-    assert e < tol
+    check(f"Example 2 N=1M p={p} {precision} depth {st['depth'][0]}", phi[idx], ref, tol)
 
 
 @pytest.mark.parametrize("n", [1, 2, 5])
@@ -244,10 +223,7 @@ def test_tiny_inputs(n, precision):
     q = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
     phi, _ = _run(xyz, q, p=12 if precision == "fp64" else 8, precision=precision)
     ref = direct.potential(Medium(K3, D3), xyz, q)
-    e = _err(phi, ref)
-    print(f"n={n} {precision}: rel err {e:.3e}")
-    assert np.all(np.isfinite(phi))
-    assert e < (1e-6 if precision == "fp64" else 1e-4)
+    check(f"n={n} {precision}", phi, ref, 1e-6 if precision == "fp64" else 1e-4)
 
 
 def test_no_particles_rejected():
@@ -257,3 +233,109 @@ def test_no_particles_rejected():
     with pytest.raises(api.TefmmError):
         f.set_particles(np.zeros((0, 3)))
     f.close()
+
+
+@pytest.mark.parametrize("side", ["top", "bottom"])
+@pytest.mark.parametrize("p,precision,depth,tol", [(12, "fp64", 0, 3e-6), (12, "fp64", 3, 3e-6),
+                                                    (8, "fp32", 0, 1e-4)])
+def test_particles_next_to_an_interface(side, p, precision, depth, tol):
+    """100 of 2000 particles 0.01-0.02 from one interface of the middle layer: the Sigma-family
+    expansions of the leaf pairs in the slab next to it would not converge (their mirror
+    points are closer than the boxes reach), so those pairs are evaluated directly from the
+    complex images.  50 targets (26 of them next to the interface) against the oracle.  FP64
+    reaches 3e-7 at the bottom interface but only 1.0-2.0e-6 at the top one for any p from
+    12 to 14 (an accuracy floor of the image fit of the down-going family next to it, whose
+    reflection is the stronger one), hence the bar 3e-6."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.near_interface(side)
+    idx, ref = _expected(f"nearif_{side}")
+    phi, st = _run(xyz, q, p=p, precision=precision, depth=depth)
+    print(f"depth {st['depth'][0]}, direct Sigma pairs {st['sigma_direct_pairs']}, "
+          f"forced reaction keys {st['reaction_keys_forced']}")
+    assert st["sigma_direct_pairs"] > 0
+    near = idx >= xyz.shape[0] - 100
+    check(f"next to the {side} interface p={p} {precision} depth {st['depth'][0]}", phi[idx], ref, tol)
+    check(f"  of which the {int(near.sum())} targets next to it", phi[idx[near]], ref[near], tol)
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "expected_c4m.txt")), reason="no stored values")
+@pytest.mark.parametrize("p,precision,tol", [(13, "fp64", 1e-6), (7, "fp32", 1e-4), (8, "fp32", 1e-4)])
+def test_c4_full_size_64_targets(p, precision, tol):
+    """The bench workload (N = 1,000,000, mid-layer cube) at the autotuned depth 4 against 64
+    oracle targets: 48 uniform + the 16 closest to an interface (a sample of its own seed)."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c4")
+    idx, ref = _expected("c4m")
+    phi, st = _run(xyz, q, p=p, precision=precision, depth=4)
+    check(f"C4 N=1M 64 targets p={p} {precision}", phi[idx], ref, tol)
+    near = _near16(xyz, idx)
+    check("  of which the 16 next to an interface", phi[idx][near], ref[near], tol)
+
+
+def _near16(xyz, idx):
+    """Positions (in idx) of the 16 sampled targets closest to an interface."""
+    dist = np.min(np.abs(xyz[idx, 2:3] - np.asarray(D3)[None, :]), axis=1)
+    return np.argsort(dist, kind="stable")[:16]
+
+
+def test_c4_fp32_p7_against_fp64_p13_every_target():
+    """The bench point (mixed FP32, p = 7, depth 4) against the FP64 FMM at p = 13 (itself
+    within 4e-7 of the oracle on the sampled targets) over all 1,000,000 targets, element by
+    element: Err_2 below the mixed mode's 1e-4 and a per-target error distribution."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c4")
+    ref, _ = _run(xyz, q, p=13, precision="fp64", depth=4)
+    got, _ = _run(xyz, q, p=7, precision="fp32", depth=4)
+    rel = np.abs(got - ref) / np.abs(ref)
+    qs = np.quantile(rel, [0.5, 0.99, 0.999])
+    print(f"all 1M targets: median {qs[0]:.2e}, 99% {qs[1]:.2e}, 99.9% {qs[2]:.2e}, max {rel.max():.2e}")
+    # Err_max over 1M targets is set by the few whose potential nearly cancels (5e-2
+    # measured); the bars are on Err_2 and on the 99% and 99.9% quantiles
+    check("C4 fp32 p=7 vs fp64 p=13, all targets", got, ref, 1e-4, tol_max=np.inf)
+    assert qs[1] < 1e-3 and qs[2] < 5e-3
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "expected_c5g.txt")), reason="no stored values")
+@pytest.mark.parametrize("precision,p,tol", [("fp32", 7, 1e-4), ("fp64", 14, 1e-6)])
+def test_c5_geometries_batched_vs_oracle(precision, p, tol):
+    """The 16 geometries of the batched workload (10k-300k particles, cubes and Example-2
+    domains) evaluated together through tefmm_evaluate_batch (one HIP graph), 16 oracle
+    targets per geometry.  FP64 at p = 14: at p = 13 the Example-2 domain of 170k particles
+    (a = 0.05) gives 1.5e-6 at the occupancy depth."""
+    import torch
+    from paper_1902_05875_amd import api, inputs
+    a = np.loadtxt(os.path.join(GOLD, "expected_c5g.txt"))
+    geoms = inputs.c5_geometries()
+    hs, qs = [], []
+    for xyz, q in geoms:
+        f = api.TEFMM(K3, D3, p=p, precision=precision)
+        f.set_particles(xyz)
+        hs.append(f)
+        qs.append(torch.from_numpy(q).cuda())
+    outs = [torch.empty_like(x) for x in qs]
+    api.evaluate_batch(hs, qs, outs)
+    torch.cuda.synchronize()
+    got, ref = [], []
+    for g in range(len(geoms)):
+        rows = a[a[:, 0] == g]
+        idx = rows[:, 1].astype(int)
+        phi = outs[g].cpu().numpy()
+        check(f"  geometry {g} N={geoms[g][0].shape[0]}", phi[idx], rows[:, 2] + 1j * rows[:, 3], tol)
+        got.append(phi[idx]), ref.append(rows[:, 2] + 1j * rows[:, 3])
+    for f in hs:
+        f.close()
+    check(f"C5 16 geometries batched {precision} p={p}", np.concatenate(got), np.concatenate(ref), tol)
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "expected_c5r.txt")), reason="no stored values")
+@pytest.mark.parametrize("precision,p,tol", [("fp32", 7, 1e-4), ("fp64", 13, 1e-6)])
+def test_c5_32_vectors_vs_oracle(precision, p, tol):
+    """The 500,000-particle geometry with 32 charge vectors in one evaluation, every vector at 8
+    oracle targets (6 uniform + the 2 closest to an interface)."""
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c5")
+    a = np.loadtxt(os.path.join(GOLD, "expected_c5r.txt"))
+    phi, st = _run(xyz, np.ascontiguousarray(q.T), p=p, precision=precision)
+    assert st["n_rhs"] == 32
+    idx, vec = a[:, 0].astype(int), a[:, 1].astype(int)
+    check(f"C5 32 vectors {precision} p={p} depth {st['depth'][0]}", phi[vec, idx], a[:, 2] + 1j * a[:, 3], tol)

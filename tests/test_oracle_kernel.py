@@ -118,10 +118,14 @@ def test_free_part_excludes_self():
 MEDIA = {
     "two": (Medium((1.0, 2.0), (0.0,)), {0: 0.4, 1: -0.6}),
     "four": (Medium((0.8, 1.5, 2.0, 1.2), (0.0, -1.2, -2.0)), {0: 0.35, 1: -0.55, 2: -1.6, 3: -2.5}),
+    "five": (Medium((0.8, 1.5, 2.0, 1.2, 0.9), (0.0, -1.2, -2.0, -2.6)),
+             {0: 0.35, 1: -0.55, 2: -1.6, 3: -2.3, 4: -3.0}),
+    "eight": (Medium((0.8, 1.5, 2.0, 1.2, 0.9, 1.7, 1.1, 1.4), (0.0, -1.2, -2.0, -2.6, -3.4, -4.0, -4.8)),
+              {0: 0.35, 1: -0.55, 2: -1.6, 3: -2.3, 4: -3.0, 5: -3.7, 6: -4.4, 7: -5.2}),
 }
 
 
-@pytest.mark.parametrize("name", ["two", "four"])
+@pytest.mark.parametrize("name", ["two", "four", "five", "eight"])
 def test_weighted_reciprocity_other_media(name):
     """k_l G_{l,lp}(r, r') = k_lp G_{lp,l}(r', r) for every layer pair (the flux condition of Sec. 2.1)."""
     med, zs = MEDIA[name]
@@ -134,7 +138,7 @@ def test_weighted_reciprocity_other_media(name):
             np.testing.assert_allclose(a, b, rtol=1e-10)
 
 
-@pytest.mark.parametrize("name", ["two", "four"])
+@pytest.mark.parametrize("name", ["two", "four", "five"])
 def test_interface_conditions_other_media(name):
     """G and k dG/dz continuous across every interface, for a source in every layer."""
     med, zs = MEDIA[name]
@@ -167,3 +171,43 @@ def test_four_layers_reduce_to_three():
     # below the removed interface: layer 3 of the four-layer medium is layer 2 of the three-layer one
     r, rp = (0.1, -0.2, -2.4), (-0.3, 0.25, -0.6)
     np.testing.assert_allclose(_full_g(m4, 3, 1, r, rp), _full_g(m3, 2, 1, r, rp), rtol=1e-9)
+
+
+def test_eight_layers_reduce_to_three():
+    """Five extra layers below the third, all with its wave number, are no interfaces at all: the
+    eight-layer kernel equals the three-layer one (the interface solve of Sec. 2.1 with seven
+    interfaces against the one with two)."""
+    m8 = Medium((0.8, 1.5, 2.0, 2.0, 2.0, 2.0, 2.0, 2.0), (0.0, -1.2, -2.0, -2.6, -3.4, -4.0, -4.8))
+    m3 = Medium((0.8, 1.5, 2.0), (0.0, -1.2))
+    pts = {0: 0.35, 1: -0.55, 2: -1.6}
+    for l, z in pts.items():
+        for lp, zp in pts.items():
+            r, rp = (0.1, -0.2, z + 0.05), (-0.3, 0.25, zp - 0.03)
+            np.testing.assert_allclose(_full_g(m8, l, lp, r, rp), _full_g(m3, l, lp, r, rp), rtol=1e-9)
+    r, rp = (0.1, -0.2, -3.7), (-0.3, 0.25, -0.6)  # layer 5 of the eight is layer 2 of the three
+    np.testing.assert_allclose(_full_g(m8, 5, 1, r, rp), _full_g(m3, 2, 1, r, rp), rtol=1e-9)
+
+
+def test_reaction_part_converged_next_to_interfaces():
+    """Sources and targets 0.01-0.02 from an interface (decay lengths 0.02-0.04): the direct
+    sum's fixed quadrature rule agrees with a refined rule (order 24, panels a third and a
+    half as wide) and with the pairwise kernel of sommerfeld.reaction_pair (its own rule)."""
+    med = Medium(K, D)
+    rng = np.random.default_rng(11)
+    m = 12
+    xyz = np.column_stack([rng.uniform(-0.5, 0.5, (2 * m, 2)),
+                           np.concatenate([-rng.uniform(0.01, 0.02, m), -1.2 + rng.uniform(0.01, 0.02, m)])])
+    q = rng.uniform(-1, 1, 2 * m) + 1j * rng.uniform(-1, 1, 2 * m)
+    tg = np.array([0, 5, m, m + 7])
+    got = direct.reaction_part(med, xyz, q, tg)
+    saved = (direct.QUAD_ORDER, direct.HEAD_WIDTH, direct.TAIL_WIDTH)
+    try:
+        direct.QUAD_ORDER, direct.HEAD_WIDTH, direct.TAIL_WIDTH = 24, saved[1] / 3, saved[2] / 2
+        fine = direct.reaction_part(med, xyz, q, tg)
+    finally:
+        direct.QUAD_ORDER, direct.HEAD_WIDTH, direct.TAIL_WIDTH = saved
+    np.testing.assert_allclose(got, fine, rtol=1e-11)
+    lay = med.layer_of(xyz[:, 2])
+    ref = np.array([np.sum(q * reaction_pair(med, lay[t], 1, np.hypot(xyz[t, 0] - xyz[:, 0], xyz[t, 1] - xyz[:, 1]),
+                                             xyz[t, 2], xyz[:, 2])) for t in tg])
+    np.testing.assert_allclose(got, ref, rtol=1e-10)
