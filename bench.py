@@ -123,6 +123,8 @@ def run_mode(xyz, q, p, precision, max_leaf, steps, warmup, workload, surrogate=
         "rel_err_sampled": err, "n_checked": nchk, "t_setup_tables_ms": st["t_setup_tables_ms"],
         "sigma_keys": st["sigma_keys"], "surrogate_keys": st["surrogate_keys"], "surrogate": sur_info,
         "cross_pairs": st["cross_pairs"], "autotune": tuned, "workload": workload,
+        "mean_leaf_occupancy": round(xyz.shape[0] / max(1, st["occupied_leaves"]), 2),
+        "max_leaf_count": st["max_leaf_count"], "sigma_direct_pairs": st["sigma_direct_pairs"],
     }
     f.close()
     del xt, qt, out
@@ -194,33 +196,43 @@ def roofline(head):
     return (p2p, m2l) if ph["p2p"] >= ph["m2l"] else (m2l, p2p)
 
 
-def cpu_baseline(xyz, q):
-    """The oracle (direct sum with Sommerfeld quadrature), unchanged, on the host cores:
-    each worker process evaluates one target against a random eighth of the sources
-    and times its own computation; the per-target time is scaled to all N sources."""
-    import multiprocessing as mp
+def _cpu_sample(workload, n, procs):
+    """The bounded oracle sample: a random eighth of the sources (at least 2000) and one
+    target among them per worker (seeded: every worker rebuilds the same sample)."""
     import numpy as np
-    procs = max(1, min(16, os.cpu_count() or 1))
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload(workload, n=n)
+    if q.ndim == 2:
+        q = q[:, 0]
     N = xyz.shape[0]
     n_sub = max(2000, N // 8)
     rng = np.random.default_rng(77)
     src = np.sort(rng.choice(N, size=n_sub, replace=False))
     targets = rng.choice(src, size=procs, replace=False)
-    args = [(xyz[src], q[src], int(np.searchsorted(src, t))) for t in targets]
-    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
-    for k in saved:
-        os.environ[k] = "1"
-    try:
-        t0 = time.perf_counter()
-        with mp.get_context("spawn").Pool(procs) as pool:
-            secs = pool.map(_oracle_one, args)
-        wall = time.perf_counter() - t0
-    finally:
-        for k, v in saved.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+    return xyz[src], q[src], [int(np.searchsorted(src, t)) for t in targets], N, n_sub
+
+
+def cpu_baseline(workload, n):
+    """The oracle (direct sum with Sommerfeld quadrature), unchanged, on the host cores: each
+    worker process (a child of its own, one BLAS thread) evaluates one target against a random
+    eighth of the sources and times its own computation; the per-target time is scaled to all
+    N sources.  The workers are plain subprocesses, all waited for."""
+    import subprocess
+    import numpy as np
+    procs = max(1, min(16, os.cpu_count() or 1))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", workload, "--cpu-procs", str(procs)]
+    if n:
+        cmd += ["--n", str(n)]
+    t0 = time.perf_counter()
+    workers = [subprocess.Popen(cmd + ["--cpu-worker", str(k)], env=env, stdout=subprocess.PIPE, text=True)
+               for k in range(procs)]
+    outs = [json.loads(w.communicate()[0].strip().splitlines()[-1]) for w in workers]
+    wall = time.perf_counter() - t0
+    if any(w.returncode != 0 for w in workers):
+        raise RuntimeError("cpu baseline worker failed")
+    secs = [o["secs"] for o in outs]
+    N, n_sub = outs[0]["N"], outs[0]["n_sub"]
     per_target = float(np.mean(secs)) * (N / n_sub)  # one core, one target, all N sources
     return {"value": procs / per_target, "unit": "evals/s", "cores": procs, "kind": "oracle",
             "sample": f"{procs} worker processes x 1 target each against {n_sub} of the {N} sources "
@@ -228,16 +240,16 @@ def cpu_baseline(xyz, q):
                       f"{np.mean(secs):.1f} s per worker, scaled by N/{n_sub}; wall {wall:.1f} s"}
 
 
-def _oracle_one(args):
-    sys.path.insert(0, ROOT)
+def _cpu_worker(workload, n, procs, k):
+    """One oracle target of the bounded sample (no GPU use); prints its compute time."""
     import numpy as np
     from oracle import direct
     from oracle.medium import Medium
     from paper_1902_05875_amd import inputs
-    xyz, q, t = args
+    xyz, q, tg, N, n_sub = _cpu_sample(workload, n, procs)
     t0 = time.perf_counter()
-    direct.potential(Medium(inputs.MEDIUM_K, inputs.MEDIUM_D), xyz, q, np.array([t]))
-    return time.perf_counter() - t0
+    direct.potential(Medium(inputs.MEDIUM_K, inputs.MEDIUM_D), xyz, q, np.array([tg[k]]))
+    print(json.dumps({"secs": time.perf_counter() - t0, "N": N, "n_sub": n_sub}))
 
 
 def run_batch(steps, warmup, p):
@@ -311,13 +323,19 @@ def main():
     ap.add_argument("--max-leaf", type=int, default=64)
     ap.add_argument("--n-rhs", type=int, default=1)
     ap.add_argument("--headline", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--modes", default="fp64,fp32")
+    ap.add_argument("--modes", default="fp64,fp32,fp32_p8",
+                    help="comma-separated: fp64 (order --p64), fp32 (order --p32), fp32_pN (mixed at order N)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="FP32 mode without the Sigma-table surrogate")
     ap.add_argument("--no-autotune", action="store_true", help="keep the occupancy-based depth and tile width")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device copy of this many MiB (calibrates HBM counters under a profiler)")
+    ap.add_argument("--cpu-worker", type=int, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-procs", type=int, default=1, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker is not None:
+        _cpu_worker(args.workload, args.n, args.cpu_procs, args.cpu_worker)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition "
               f"is a design, not a build", file=sys.stderr)
@@ -351,10 +369,12 @@ def main():
     N = xyz.shape[0]
     modes = {}
     for m in args.modes.split(","):
-        p = args.p64 if m == "fp64" else args.p32
+        # "fp32_p8": the mixed mode at another order (the surrogate configuration's p = 8)
+        prec, _, po = m.partition("_p")
+        p = int(po) if po else (args.p64 if prec == "fp64" else args.p32)
         print(f"[bench] mode {m} p={p} N={N} n_rhs={qm.shape[0]}", file=sys.stderr, flush=True)
-        modes[m] = run_mode(xyz, qm, p, m, args.max_leaf, args.steps, args.warmup, args.workload,
-                            surrogate=(m == "fp32" and not args.no_surrogate and args.workload != "c3"),
+        modes[m] = run_mode(xyz, qm, p, prec, args.max_leaf, args.steps, args.warmup, args.workload,
+                            surrogate=(prec == "fp32" and not args.no_surrogate and args.workload != "c3"),
                             autotune=not args.no_autotune)
         print(f"[bench] {m}: {modes[m]['ms_per_step']:.2f} ms/step, err {modes[m]['rel_err_sampled']}",
               file=sys.stderr, flush=True)
@@ -363,7 +383,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(xyz, q if q.ndim == 1 else q[:, 0])
+        cpu = cpu_baseline(args.workload, args.n)
     line = {
         "metric": METRIC, "value": head["evals_per_s"] * 1.0, "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -371,7 +391,8 @@ def main():
         "dtype": "f32+f64" if head["precision"] == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: N={N} {SHAPES.get(args.workload, '')}, 3 layers "
                                f"(d=0,-1.2; k=0.8,1.5,2.0), {qm.shape[0]} complex charge vector(s)",
-                   "p": head["p"], "precision": head["precision"], "max_leaf": args.max_leaf,
+                   "p": head["p"], "precision": head["precision"],
+                   "mean_leaf_occupancy": head["mean_leaf_occupancy"], "max_leaf_count": head["max_leaf_count"],
                    "depth": head["depth"], "m2l_tile": (head["autotune"] or {}).get("m2l_tile"),
                    "parallelism": "single GPU"},
         "roofline": roof, "roofline_other": roof_other, "cpu_baseline": cpu, "modes": modes,

@@ -52,8 +52,12 @@ enum {
 
 /* Precision.  TEFMM_FP64: every step in FP64.  TEFMM_MIXED_FP32: the M2L
  * contractions (FP32 MFMA, FP32 accumulation within one launch) and the P2P
- * sums run in FP32, with pairs closer than 5% of the leaf side redone in FP64;
- * complex-image fits, table generation, P2M/M2M/L2L/L2P and the final
+ * sums run in FP32.  Near-field pairs closer than 5% of the leaf side, whose FP32
+ * coordinate differences have lost digits, take those differences from the FP64
+ * positions: with one charge vector (each pair evaluated once) the pair value and
+ * its accumulation then stay FP32 (the digits lost were those of the difference);
+ * with several vectors the pair is redone in FP64 and summed in FP64.
+ * Complex-image fits, table generation, P2M/M2M/L2L/L2P and the final
  * accumulation of the potential stay FP64. */
 enum { TEFMM_FP64 = 0, TEFMM_MIXED_FP32 = 1 };
 enum { TEFMM_NORM_PHYSICAL = 0, TEFMM_NORM_PAPER = 1 };
@@ -141,6 +145,8 @@ typedef struct {
                                  next to an interface, where the expansion about the box centres
                                  would converge slowly or not at all (ratio sqrt(3) h / distance
                                  of the key's centre from the mirror point above 0.75) */
+  int64_t occupied_leaves; /* leaves holding particles, over all layer groups */
+  int64_t max_leaf_count;  /* particles in the fullest leaf */
   int64_t reaction_keys_forced; /* (level, z-slab pair) translations of a reaction family with
                                    that ratio above 0.87 (converging slowly or not at all:
                                    boxes reaching close to an interface, or a layer thin

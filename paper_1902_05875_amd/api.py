@@ -89,6 +89,7 @@ class StatsC(ctypes.Structure):
         ("cross_fit_err", ctypes.c_double), ("sigma_keys", ctypes.c_int64), ("surrogate_keys", ctypes.c_int64),
         ("timed_evaluations", ctypes.c_int), ("p2p_pairs_same_leaf", ctypes.c_int64),
         ("p2p_poly_err", ctypes.c_double), ("sigma_direct_pairs", ctypes.c_int64),
+        ("occupied_leaves", ctypes.c_int64), ("max_leaf_count", ctypes.c_int64),
         ("reaction_keys_forced", ctypes.c_int64)]
 
 

@@ -1220,7 +1220,9 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   dfree(h, d_in);
   dfree(h, d_if);
   HIPCHK(h, hipEventRecord(e1, s));
-  // interaction counts (statistics)
+  // leaf occupancy and interaction counts (statistics)
+  int64_t occ_leaves = 0, max_leaf = 0;
+  for (int64_t b = 0; b < leaf_off; ++b) occ_leaves += lc[b] > 0, max_leaf = std::max<int64_t>(max_leaf, lc[b]);
   h->p2p_pairs = 0;
   h->p2p_same = 0;
   h->m2l_pairs = 0;
@@ -1344,6 +1346,8 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   }
   h->st.p2p_pairs = h->p2p_pairs;
   h->st.p2p_pairs_same_leaf = h->p2p_same;
+  h->st.occupied_leaves = occ_leaves;
+  h->st.max_leaf_count = max_leaf;
   h->st.p2p_poly_err = 0;
   if (h->opt.precision == TEFMM_MIXED_FP32)
     for (auto& g : h->groups)

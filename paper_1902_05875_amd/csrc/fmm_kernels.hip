@@ -935,16 +935,18 @@ __device__ __forceinline__ void p2p_f64_rows(int m, T tx, T ty, T tz, const T* s
 // four at a time and one wave-wide test per four decides whether any lane met
 // such a pair; only then (rare) the known FP32 term is taken back in FP64 and
 // the pair redone in FP64 from the stored coordinates (the pair with itself: 0).
-template <int RB, bool POLY>
+template <int RB, bool POLY, bool OWN>
 __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz, const float4* s4,
                                              const float (*sq)[2 * RB], const int* sidx, float rns2, float ecr,
                                              float eci, double kap, const PassArgs& a, int64_t i, double txd,
                                              double tyd, double tzd, int r0, int nrhs, float* accr, float* acci,
                                              double* nsr, double* nsi, const NearPoly& np) {
-  // a pair at distance 0 (a particle with itself) gets weight 0 in the FP32 sum; pairs
-  // with 0 < r2 < rns2 are taken back and redone in FP64
-  const unsigned near_lim = (unsigned)__float_as_int(rns2) - 1u;
-  auto nearp = [&](float r2) { return (unsigned)__float_as_int(r2) - 1u < near_lim; };
+  // OWN (the column holding the target itself): the pair of a particle with itself,
+  // found by its index, gets weight 0 in the FP32 sum and is moved out of the near test;
+  // pairs with r2 < rns2 (a distinct particle at FP32 distance 0 included) are taken
+  // back and redone in FP64
+  const unsigned near_lim = (unsigned)__float_as_int(rns2);
+  auto nearp = [&](float r2) { return (unsigned)__float_as_int(r2) < near_lim; };
   auto fixup = [&](int t, float r2) {
     if (!nearp(r2)) return;
     const int64_t j = sidx[t];
@@ -966,7 +968,7 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
     // max of two non-negative floats as the max of their bit patterns (no canonicalising)
     float er, ei;
     pair_value<POLY>(__int_as_float(max(__float_as_int(r2), __float_as_int(rns2))), np, &er, &ei);
-    if (!(r2 > 0.0f)) er = 0.0f, ei = 0.0f;
+    if (OWN && sidx[t] == i) er = 0.0f, ei = 0.0f;
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
       const float qr = sq[t][2 * b], qi = sq[t][2 * b + 1];
@@ -988,8 +990,13 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) pair(t + u, r2[u]);
-    const unsigned mn = min(min((unsigned)__float_as_int(r2[0]) - 1u, (unsigned)__float_as_int(r2[1]) - 1u),
-                            min((unsigned)__float_as_int(r2[2]) - 1u, (unsigned)__float_as_int(r2[3]) - 1u));
+    // the self pair's stand-in distance: beyond the near test (after its use above,
+    // where only its weight mattered)
+    if (OWN)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) r2[u] = sidx[t + u] == i ? 3.0e38f : r2[u];
+    const unsigned mn = min(min((unsigned)__float_as_int(r2[0]), (unsigned)__float_as_int(r2[1])),
+                            min((unsigned)__float_as_int(r2[2]), (unsigned)__float_as_int(r2[3])));
     if (__any(mn < near_lim)) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) fixup(t + u, r2[u]);
@@ -998,8 +1005,9 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
   for (; t < m; ++t) {
     const float4 s = s4[t];
     const float dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
-    const float r2 = dx * dx + dy * dy + dz * dz;
+    float r2 = dx * dx + dy * dy + dz * dz;
     pair(t, r2);
+    if (OWN && sidx[t] == i) r2 = 3.0e38f;
     fixup(t, r2);
   }
 }
@@ -1065,8 +1073,12 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs, NearPoly np) {
         __syncthreads();
         if (!act) continue;
         if constexpr (F32) {
-          p2p_f32_rows<RB, POLY>(m, tx, ty, tz, s4, sq, sidx, rns2, ecr, eci, kap, a, i, txd, tyd, tzd, r0, nrhs,
-                                 accr, acci, nsr, nsi, np);
+          if (col == 4)
+            p2p_f32_rows<RB, POLY, true>(m, tx, ty, tz, s4, sq, sidx, rns2, ecr, eci, kap, a, i, txd, tyd, tzd, r0,
+                                         nrhs, accr, acci, nsr, nsi, np);
+          else
+            p2p_f32_rows<RB, POLY, false>(m, tx, ty, tz, s4, sq, sidx, rns2, ecr, eci, kap, a, i, txd, tyd, tzd, r0,
+                                          nrhs, accr, acci, nsr, nsi, np);
         } else {
           // Only the centre column holds the target itself; there the pair with
           // r2 = 0 (same coordinates, same arithmetic) gets weight 0, branch free.
@@ -1134,9 +1146,9 @@ __device__ __forceinline__ float sym_r2(float tx, float ty, float tz, const floa
 // Eight staged sources [t, t + 8) against this lane's T targets.  SYM: also the
 // eight source-side sums over the wave's 64 T targets, written to
 // psw[2 (t + u) + c] (c = 0 real, 1 imaginary part).  Every pair is applied
-// with the FP32 value at the squared distance from sym_r2, except a pair at
-// distance 0 in the leaf's own pass (a particle with itself), which gets weight
-// 0: its clamped value would be of the order of the inverse threshold, and
+// with the FP32 value at the squared distance from sym_r2, except the pair of a
+// particle with itself in the leaf's own pass (found by its index), which gets
+// weight 0: its clamped value would be of the order of the inverse threshold, and
 // taking it back later would cancel against everything else in the FP32 sum.
 // Pairs closer than the threshold rns2 (rare: two particles closer than 5% of
 // the leaf side, whose FP32 coordinate differences have lost digits) are marked
@@ -1155,8 +1167,9 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
   typedef float f16v __attribute__((ext_vector_type(16)));
   f16v c;
   int steps = 0;  // steps with marked pairs
-  // near test on the bit patterns less one: 0 < r2 < rns2 (a pair at distance 0 wraps to the top)
-  const unsigned near_lim = (unsigned)__float_as_int(rns2) - 1u;
+  // near test on the bit patterns: r2 < rns2 (in the own pass the pair of a particle with
+  // itself, found by its index, is moved out of the test's range)
+  const unsigned near_lim = (unsigned)__float_as_int(rns2);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {  // two sources at a time
     float r2[2][T];
@@ -1164,6 +1177,7 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
     for (int u = 0; u < 2; ++u) {
       const float4 sp = s4[t + 2 * v + u];
       const float qr = sp.w, qi = sqi[t + 2 * v + u];
+      const int sj = SYM ? 0 : sidx[t + 2 * v + u];
       float cr = 0.0f, ci = 0.0f;
 #pragma unroll
       for (int k = 0; k < T; ++k) {
@@ -1171,14 +1185,17 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
         // plain one, and the clamp only ever raises it to the threshold itself)
         r2[u][k] = SYM ? sym_r2<true>(tx[k], ty[k], tz[k], sp, eps2, rns2) : 0.0f;
         float used = r2[u][k];
+        bool self = false;
         if (!SYM) {
           const float dx = tx[k] - sp.x, dy = ty[k] - sp.y, dz = tz[k] - sp.z;
-          r2[u][k] = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          self = sj == tbase + 64 * k;
+          // a distinct particle at FP32 distance 0 is a near pair like any other
+          r2[u][k] = self ? 3.0e38f : fmaf(dz, dz, fmaf(dy, dy, dx * dx));
           used = __int_as_float(max(__float_as_int(r2[u][k]), __float_as_int(rns2)));
         }
         float er, ei;
         pair_value<POLY>(used, np, &er, &ei);
-        if (!SYM && !(r2[u][k] > 0.0f)) er = 0.0f, ei = 0.0f;
+        if (self) er = 0.0f, ei = 0.0f;
         accr[k] = fmaf(qr, er, fmaf(-qi, ei, accr[k]));
         acci[k] = fmaf(qr, ei, fmaf(qi, er, acci[k]));
         if (SYM) {
@@ -1205,7 +1222,7 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
       unsigned mn = 0xFFFFFFFFu;
 #pragma unroll
       for (int k = 0; k < T; ++k)
-        mn = min(mn, min((unsigned)__float_as_int(r2[0][k]) - 1u, (unsigned)__float_as_int(r2[1][k]) - 1u));
+        mn = min(mn, min((unsigned)__float_as_int(r2[0][k]), (unsigned)__float_as_int(r2[1][k])));
       anynear = mn < near_lim;
     }
     if (__any(anynear)) {
@@ -1214,7 +1231,7 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
       for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int k = 0; k < T; ++k) {
-          const bool nr = SYM ? r2[u][k] < rns2 : (unsigned)__float_as_int(r2[u][k]) - 1u < near_lim;
+          const bool nr = SYM ? r2[u][k] < rns2 : (unsigned)__float_as_int(r2[u][k]) < near_lim;
           m |= (act[k] && nr) ? 1u << (u * T + k) : 0u;
         }
       nl[64 * v + lane] = (int)m;

@@ -339,3 +339,22 @@ def test_c5_32_vectors_vs_oracle(precision, p, tol):
     assert st["n_rhs"] == 32
     idx, vec = a[:, 0].astype(int), a[:, 1].astype(int)
     check(f"C5 32 vectors {precision} p={p} depth {st['depth'][0]}", phi[vec, idx], a[:, 2] + 1j * a[:, 3], tol)
+
+
+@pytest.mark.parametrize("p2p_targets", [0, -1])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_pairs_closer_than_fp32_resolution(precision, p2p_targets):
+    """C1 plus 8 particles 1e-10 from existing ones: in FP32 their scaled coordinates round to
+    the same values, so the pair would look like a particle with itself by distance; the pair of
+    a particle with itself is found by its index, and the coincident distinct pair is redone
+    from FP64 coordinate differences (both near-field kernels: each pair once, p2p_targets 0,
+    and every ordered pair, -1).  The 16 particles of the pairs against the oracle."""
+    from oracle import direct
+    from oracle.medium import Medium
+    from paper_1902_05875_amd import inputs
+    xyz, q = inputs.workload("c1")
+    xyz, q, pairs = inputs.with_close_pairs(xyz, q, 8, 1e-10, seed=141)
+    tg = np.sort(pairs.ravel())
+    ref = direct.potential(Medium(K3, D3), xyz, q, tg)
+    phi, st = _run(xyz, q, p=8, depth=2, precision=precision, p2p_targets=p2p_targets)
+    check(f"pairs 1e-10 apart {precision} p2p_targets {p2p_targets}", phi[tg], ref, 1e-6)
