@@ -303,9 +303,10 @@ int tefmm_selftest_mfma(void);
  *   y = W_out a_{n_hidden} + b_out,
  * trained on the mean-squared loss L = mean over samples and outputs of
  * (y - t)^2 with Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
- * Matrix products use BF16 operands with FP32 accumulation on the matrix
- * cores; the first layer and its gradient are FP32; weights, gradients and
- * moments are FP32.  Parameter vector (float): W_0, b_0, W_1, b_1, ...,
+ * The hidden layers' matrix products use BF16 operands with FP32 accumulation
+ * on the matrix cores; the first layer and the output layer (and their
+ * gradients) are FP32 on the vector units; weights, gradients and moments are
+ * FP32.  Parameter vector (float): W_0, b_0, W_1, b_1, ...,
  * W_out, b_out, matrices row-major with W[j][i] the weight from input i to
  * unit j.  Data arrays are device memory, row-major, one row per sample.
  * Calls are stream ordered on `stream` unless stated; one handle serves one
@@ -351,34 +352,45 @@ int tefmm_mlp_train(tefmm_mlp_t m, const float* x, const float* t, int64_t n, in
 
 /* ------------------------------------------------------------------------
  * Surrogate for the Sigma-family derivative tables of one layer (the
- * reaction component whose kernel depends on z + z', Sec. 3.2; an extension
- * beyond the paper).  The network maps a table key position (x, y, S = z + z')
- * inside a training box to the compact table entries, scaled by the envelope
- * of a source at the nearer mirror distance,
- *   W_g = D^g K(x, y, S) R_e^{|g|+1} / |g|!,  R_e = sqrt(x^2 + y^2 + Z_m^2),
- *   Z_m = min(S - 2 d_l, 2 d_{l-1} - S),
- * each output also divided by its RMS over the training set.  Training data
- * are the method's own complex-image tables at n_train uniform points of the
- * box; training is minibatch Adam on the GPU (tefmm_mlp kernels).  A
- * validation map over cells_xy x cells_xy x cells_s cells of the box keeps a
- * cell when the largest |W_network - W_images| over n_valid fresh points in
- * it is <= budget.  Attached to a handle, the surrogate produces the Sigma
- * table rows whose keys fall in kept cells; every other row (outside the box,
+ * reaction component whose kernel depends on x - x', y - y' and S = z + z',
+ * Sec. 3.2; an extension beyond the paper).  That kernel K is axisymmetric in
+ * (x, y), so with u = x + i y and w = rho^2 every derivative reduces to the
+ * rotation-free functions (the phase e^{i m phi} of the cylindrical derivatives
+ * of Sec. 4.2, carried by u^m)
+ *   H_{m,c}(rho, S) = (2 d_w)^m d_S^c K,  (d_x + i d_y)^m d_S^c K = u^m H_{m,c},
+ * m + c <= 2p, (2p+1)(2p+2)/2 complex functions of two variables.  The network
+ * maps (rho, S) in the training box [0, rho_max] x [s_lo, s_hi] to them, each
+ * scaled by the envelope of a source at the nearer mirror distance R_e
+ * (W = H R_e^(2m+c+1) / ((2m-1)!! c!)) and by its RMS over the training set.
+ * The compact Cartesian table rows h^|g| d^g K of a key (x, y, S) are rebuilt
+ * from H exactly: d_x = (D+ + D-)/2, d_y = (D+ - D-)/(2i), D+- = d_x +- i d_y, and
+ * D+ D- = -(d_S^2 + k^2) (the kernel solves the Helmholtz equation).  Training
+ * data are H of the method's own complex images (Sec. 3.3) at n_train uniform
+ * points of the box (GPU FP64); training is minibatch Adam on the GPU
+ * (tefmm_mlp kernels).  A validation map over cells_rho x cells_s cells keeps a
+ * cell when the largest |W_network - W_images| over n_valid fresh points in it
+ * is <= budget.  Attached to a handle, the surrogate produces the Sigma table
+ * rows whose keys fall in kept cells; every other row (outside the box,
  * rejected cells, other layers) comes from the complex images as before.
  * ------------------------------------------------------------------------ */
 typedef struct tefmm_surrogate* tefmm_surrogate_t;
 
 typedef struct {
   int layer;           /* layer whose Sigma tables are learned */
-  double x_max;        /* |x|, |y| <= x_max in the box */
+  double rho_max;      /* horizontal key distance rho <= rho_max in the box */
   double s_lo, s_hi;   /* z + z' range of the box (inside the layer) */
   int n_train;         /* training points */
   int epochs, batch;
   float lr;
-  int width, n_hidden; /* network shape (3 -> width x n_hidden -> 2 nG) */
-  int cells_xy, cells_s, n_valid;
+  int width, n_hidden; /* network shape (2 -> width x n_hidden -> 2 (2p+1)(2p+2)/2) */
+  int cells_rho, cells_s, n_valid;
   double budget;       /* largest accepted error of W in a cell */
   uint64_t seed;
+  int h_from_images;   /* 1: no network; the rows of every key in the box come from the images'
+                          H through the same rebuilding (a check of the representation) */
+  int envelope;        /* 1: outputs also divided by the envelope of the two mirror distances */
+  int leaf_level;      /* 1: keys of the leaf level are answered too (0: only the levels above it,
+                          whose translations carry less of the potential per row) */
 } tefmm_surrogate_options;
 
 typedef struct {
@@ -391,12 +403,14 @@ typedef struct {
   int64_t n_params;
 } tefmm_surrogate_report;
 
-/* Defaults for `layer` of `medium`: x_max 0.75, S range the layer's z + z'
+/* Defaults for `layer` of `medium`: rho_max 1.1, S range the layer's z + z'
  * range less 0.15 at each interface (2 units beyond the interface in a
- * half-space), n_train 131072, 60 epochs of 1024, lr 2e-3, width 128,
- * 4 hidden layers, 6 x 6 x 12 cells with 16 points, budget 3e-3. */
+ * half-space), n_train 262144, 300 epochs of 1024, lr 2e-3, width 128,
+ * 4 hidden layers, 8 x 16 cells with 16 points, budget 4e-4 (the error of W
+ * in envelope units, entry (m, c) weighted by 2^-(m+c)), envelope on, leaf
+ * level off. */
 void tefmm_surrogate_default_options(const tefmm_medium* medium, int layer, tefmm_surrogate_options* o);
-/* Fit the images of the box, generate the training and validation tables,
+/* Fit the images of the box, generate the training and validation targets,
  * train, build the validation map.  opt gives p and the image parameters
  * (NULL: defaults).  epoch_loss (host, `epochs` doubles) may be NULL.
  * Synchronous on `stream`; fails with TEFMM_ERR_UNSUPPORTED if the layer has
@@ -405,10 +419,10 @@ int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium* medium, co
                           const tefmm_surrogate_options* so, tefmm_surrogate_report* rep, double* epoch_loss,
                           void* stream);
 void tefmm_surrogate_destroy(tefmm_surrogate_t s);
-/* ok[i] = 1 if the point (x, y, S) = xys[3i..3i+2] lies in a kept cell. */
+/* ok[i] = 1 if the key (x, y, S) = xys[3i..3i+2] lies in a kept cell. */
 int tefmm_surrogate_cell_ok(tefmm_surrogate_t s, int n, const double* xys, int* ok);
-/* Largest validation error of W in each cell (cells_xy^2 cells_s doubles,
- * cell (i, j, m) of x, y, S at (i cells_xy + j) cells_s + m). */
+/* Largest validation error of W in each cell (cells_rho cells_s doubles,
+ * cell (i, j) of rho, S at i cells_s + j). */
 int tefmm_surrogate_cell_errors(tefmm_surrogate_t s, double* err);
 /* Attach (or with NULL detach) a surrogate; it is used by the following
  * tefmm_set_particles calls and must outlive them.  Rejects a surrogate of

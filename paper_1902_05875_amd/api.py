@@ -94,11 +94,12 @@ class StatsC(ctypes.Structure):
 
 
 class SurOptionsC(ctypes.Structure):
-    _fields_ = [("layer", ctypes.c_int), ("x_max", ctypes.c_double), ("s_lo", ctypes.c_double),
+    _fields_ = [("layer", ctypes.c_int), ("rho_max", ctypes.c_double), ("s_lo", ctypes.c_double),
                 ("s_hi", ctypes.c_double), ("n_train", ctypes.c_int), ("epochs", ctypes.c_int),
                 ("batch", ctypes.c_int), ("lr", ctypes.c_float), ("width", ctypes.c_int), ("n_hidden", ctypes.c_int),
-                ("cells_xy", ctypes.c_int), ("cells_s", ctypes.c_int), ("n_valid", ctypes.c_int),
-                ("budget", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("cells_rho", ctypes.c_int), ("cells_s", ctypes.c_int), ("n_valid", ctypes.c_int),
+                ("budget", ctypes.c_double), ("seed", ctypes.c_uint64), ("h_from_images", ctypes.c_int),
+                ("envelope", ctypes.c_int), ("leaf_level", ctypes.c_int)]
 
 
 class SurReportC(ctypes.Structure):
@@ -506,9 +507,9 @@ class Surrogate:
 
     def cell_errors(self):
         o = self.options
-        e = np.zeros(o["cells_xy"] * o["cells_xy"] * o["cells_s"])
+        e = np.zeros(o["cells_rho"] * o["cells_s"])
         _check(lib().tefmm_surrogate_cell_errors(self.h, e.ctypes.data_as(ctypes.c_void_p)))
-        return e.reshape(o["cells_xy"], o["cells_xy"], o["cells_s"])
+        return e.reshape(o["cells_rho"], o["cells_s"])
 
     def close(self):
         if self.h:

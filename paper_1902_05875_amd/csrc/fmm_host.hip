@@ -500,7 +500,9 @@ struct SigmaKeys {
 static int surrogate_tables(tefmm_t h, const SigmaKeys& sk, double hb, double2* d_out, hipStream_t s);
 static bool surrogate_accepts(const tefmm_surrogate* su, double X, double Y, double S);
 static bool surrogate_applies(const tefmm_surrogate* su, int layer, bool up, bool dn);
-static double sigma_envelope(const MediumDesc& med, int l, bool up, bool dn, double X, double Y, double S);
+static bool surrogate_serves_leaves(const tefmm_surrogate* su);
+static void sigma_mirror_dist(const MediumDesc& med, int l, bool up, bool dn, double X, double Y, double S,
+                              std::vector<double>& out);
 
 // ---------------------------------------------------------------------------
 // Derivative tables of one group (all levels).
@@ -557,7 +559,8 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
             }
       } else {
         nkeys = 49 * (2 * nb - 1);
-        const bool use_sur = h->sur && surrogate_applies(h->sur, l_, g.has[0], g.has[1]);
+        const bool use_sur = h->sur && surrogate_applies(h->sur, l_, g.has[0], g.has[1]) &&
+                             (!leaf || surrogate_serves_leaves(h->sur));
         for (int dx = -3; dx <= 3; ++dx)
           for (int dy = -3; dy <= 3; ++dy)
             for (int m = 0; m <= 2 * nb - 2; ++m) {
@@ -570,7 +573,7 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
                 // answered by the network after the image tables are generated
                 sk.key.push_back((int)start.size() - 1);
                 sk.X.push_back(-dx * hb), sk.Y.push_back(-dy * hb), sk.S.push_back(S);
-                sk.Re.push_back(sigma_envelope(med, l_, g.has[0], g.has[1], -dx * hb, -dy * hb, S));
+                sigma_mirror_dist(med, l_, g.has[0], g.has[1], -dx * hb, -dy * hb, S, sk.Re);
                 continue;
               }
               if (g.has[0])
@@ -2050,138 +2053,147 @@ extern "C" int tefmm_selftest_mfma(void) {
 // ---------------------------------------------------------------------------
 struct tefmm_surrogate {
   tefmm_t ref = nullptr;  // medium and order-p constant tables
-  int layer = 0, p = 0, nG = 0;
+  int layer = 0, p = 0, nG = 0, P2 = 0, nH = 0;
   tefmm_surrogate_options o;
   std::vector<cplx> A[2], Z[2];  // Sigma-up and Sigma-down images of the training box
   bool has[2] = {false, false};
+  double2* d_img = nullptr;      // the images on the device: A, Z of Sigma-up, then of Sigma-down
+  double2* d_qs = nullptr;       // the quasi-static images alone (depth 0: the mirror points)
+  int qs_up = 0, qs_dn = 0;
   tefmm::Mlp net;
-  std::vector<float> sigma;
+  std::vector<float> sigma;      // RMS of each normalised output over the training set
   float* d_sigma = nullptr;
-  unsigned char* d_gord = nullptr;
+  unsigned char* d_gord = nullptr;  // |g| of each compact table entry
   std::vector<unsigned char> cell_ok;
   std::vector<double> cell_err;
   std::string err;
   ~tefmm_surrogate() {
     if (d_sigma) (void)hipFree(d_sigma);
     if (d_gord) (void)hipFree(d_gord);
+    if (d_img) (void)hipFree(d_img);
+    if (d_qs) (void)hipFree(d_qs);
     if (ref) tefmm_destroy(ref);
   }
 };
 
-static double sigma_envelope(const MediumDesc& med, int l, bool up, bool dn, double X, double Y, double S) {
-  double zm = 1e300;
-  if (up) zm = std::min(zm, S - 2 * med.d[l]);
-  if (dn) zm = std::min(zm, 2 * med.d[l - 1] - S);
-  return std::sqrt(X * X + Y * Y + zm * zm);
+// distances of a key (X, Y, S) from the two mirror points (1e300 for a family that is
+// absent), appended to out: they set the envelope of the surrogate's outputs
+static void sigma_mirror_dist(const MediumDesc& med, int l, bool up, bool dn, double X, double Y, double S,
+                              std::vector<double>& out) {
+  const double r2 = X * X + Y * Y;
+  out.push_back(up ? std::sqrt(r2 + (S - 2 * med.d[l]) * (S - 2 * med.d[l])) : 1e300);
+  out.push_back(dn ? std::sqrt(r2 + (2 * med.d[l - 1] - S) * (2 * med.d[l - 1] - S)) : 1e300);
 }
 
-static int sur_cell(const tefmm_surrogate* su, double X, double Y, double S) {
+// cell (i_rho, i_S) of the validation map, -1 outside the training box
+static int sur_cell(const tefmm_surrogate* su, double rho, double S) {
   const tefmm_surrogate_options& o = su->o;
-  const double u = (X + o.x_max) / (2 * o.x_max), v = (Y + o.x_max) / (2 * o.x_max), w = (S - o.s_lo) / (o.s_hi - o.s_lo);
-  if (!(u >= 0 && u <= 1 && v >= 0 && v <= 1 && w >= 0 && w <= 1)) return -1;
-  const int cu = std::min(o.cells_xy - 1, (int)(u * o.cells_xy)), cv = std::min(o.cells_xy - 1, (int)(v * o.cells_xy));
-  const int cw = std::min(o.cells_s - 1, (int)(w * o.cells_s));
-  return (cu * o.cells_xy + cv) * o.cells_s + cw;
+  const double u = rho / o.rho_max, w = (S - o.s_lo) / (o.s_hi - o.s_lo);
+  if (!(u >= 0 && u <= 1 && w >= 0 && w <= 1)) return -1;
+  const int cu = std::min(o.cells_rho - 1, (int)(u * o.cells_rho)), cw = std::min(o.cells_s - 1, (int)(w * o.cells_s));
+  return cu * o.cells_s + cw;
 }
 
 static bool surrogate_applies(const tefmm_surrogate* su, int layer, bool up, bool dn) {
   return su->layer == layer && su->has[0] == up && su->has[1] == dn;
 }
 
+static bool surrogate_serves_leaves(const tefmm_surrogate* su) { return su->o.leaf_level || su->o.h_from_images; }
+
 static bool surrogate_accepts(const tefmm_surrogate* su, double X, double Y, double S) {
-  const int c = sur_cell(su, X, Y, S);
+  if (su->o.h_from_images) return sur_cell(su, std::hypot(X, Y), S) >= 0;
+  const int c = sur_cell(su, std::hypot(X, Y), S);
   return c >= 0 && su->cell_ok[c];
 }
 
-// Image tables (h = 1: entries D^g K_Sigma) at points (X, Y, S), generated like
-// the method's own Sigma tables; d_out: [n][nG].
-static int sur_image_tables(tefmm_surrogate* su, const std::vector<double>& X, const std::vector<double>& Y,
-                            const std::vector<double>& S, double2* d_out, hipStream_t s) {
+// H_{m,c} (rotation-free derivatives of K_Sigma) of the surrogate's images at (rho, S)
+static int sur_image_h(tefmm_surrogate* su, const std::vector<double>& rho, const std::vector<double>& S,
+                       double2* d_H, hipStream_t s, bool qs_only = false) {
   tefmm_t h = su->ref;
   const MediumDesc& med = h->med;
-  const int l = su->layer, n = (int)X.size();
-  const int chunk = 16384;
-  for (int c0 = 0; c0 < n; c0 += chunk) {
-    const int cnt = std::min(chunk, n - c0);
-    std::vector<TableTerm> terms;
-    std::vector<int> start;
-    std::vector<double> hk(cnt, 1.0);
-    for (int i = c0; i < c0 + cnt; ++i) {
-      start.push_back((int)terms.size());
-      for (int f = 0; f < 2; ++f)
-        for (size_t j = 0; j < su->A[f].size(); ++j) {
-          const cplx zeta = f == 0 ? S[i] - 2 * med.d[l] - su->Z[f][j] : 2 * med.d[l - 1] - S[i] - su->Z[f][j];
-          if (zeta.real() <= 1e-9) continue;
-          TableTerm t;
-          t.x = X[i], t.y = Y[i], t.zr = zeta.real(), t.zi = zeta.imag();
-          t.cr = su->A[f][j].real(), t.ci = su->A[f][j].imag(), t.flip = f, t.pad = 0;
-          terms.push_back(t);
-        }
-    }
-    start.push_back((int)terms.size());
-    TableTerm* d_terms = nullptr;
-    int* d_start = nullptr;
-    double* d_h = nullptr;
-    HIPCHK(h, dmalloc(h, &d_terms, sizeof(TableTerm) * std::max<size_t>(terms.size(), 1)));
-    HIPCHK(h, dmalloc(h, &d_start, sizeof(int) * start.size()));
-    HIPCHK(h, dmalloc(h, &d_h, sizeof(double) * cnt));
-    if (!terms.empty())
-      HIPCHK(h, hipMemcpyAsync(d_terms, terms.data(), sizeof(TableTerm) * terms.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(h, hipMemcpyAsync(d_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(h, hipMemcpyAsync(d_h, hk.data(), sizeof(double) * cnt, hipMemcpyHostToDevice, s));
-    TableGenArgs ta;
-    ta.terms = d_terms, ta.term_start = d_start, ta.h = d_h, ta.k = med.k[l], ta.order = 2 * su->p, ta.nG = su->nG;
-    ta.nbr = h->d_nbr, ta.g3 = h->d_g3, ta.g1 = h->d_g1, ta.swap13 = 0, ta.fact = h->d_fact;
-    ta.out = d_out + (size_t)c0 * su->nG;
-    const size_t lds = 2 * sizeof(double2) * su->nG;
-    HIPCHK(h, hipFuncSetAttribute((const void*)k_table_gen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_table_gen, dim3(cnt), dim3(64), lds, s, ta);
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipStreamSynchronize(s));
-    dfree(h, d_terms);
-    dfree(h, d_start);
-    dfree(h, d_h);
-  }
+  const int l = su->layer, n = (int)rho.size();
+  if (!n) return TEFMM_OK;
+  std::vector<double> w(n);
+  for (int i = 0; i < n; ++i) w[i] = rho[i] * rho[i];
+  double *d_w = nullptr, *d_s = nullptr;
+  HIPCHK(h, hipMalloc(&d_w, sizeof(double) * n));
+  HIPCHK(h, hipMalloc(&d_s, sizeof(double) * n));
+  HIPCHK(h, hipMemcpyAsync(d_w, w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(d_s, S.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  const int nup = qs_only ? su->qs_up : su->has[0] ? (int)su->A[0].size() : 0;
+  const int ndn = qs_only ? su->qs_dn : su->has[1] ? (int)su->A[1].size() : 0;
+  hipLaunchKernelGGL(k_sigma_h, dim3(n), dim3(64), 0, s, d_w, d_s, n, qs_only ? su->d_qs : su->d_img, nup, ndn,
+                     l < med.L ? 2 * med.d[l] : 0.0, l > 0 ? 2 * med.d[l - 1] : 0.0, med.k[l], su->P2, d_H);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(s));
+  dfree_raw(d_w);
+  dfree_raw(d_s);
   return TEFMM_OK;
 }
 
-static void sur_inputs(const tefmm_surrogate* su, const std::vector<double>& X, const std::vector<double>& Y,
-                       const std::vector<double>& S, std::vector<float>& u) {
+// network inputs: rho / rho_max and S scaled to [-1, 1].  H is even in rho (a function of
+// rho^2), so training also draws negative rho: the axis rho = 0, where the keys straight
+// above one another sit, is then inside the input range instead of on its edge.
+static void sur_inputs(const tefmm_surrogate* su, const std::vector<double>& rho, const std::vector<double>& S,
+                       std::vector<float>& u) {
   const tefmm_surrogate_options& o = su->o;
-  u.resize(3 * X.size());
-  for (size_t i = 0; i < X.size(); ++i) {
-    u[3 * i] = (float)(X[i] / o.x_max);
-    u[3 * i + 1] = (float)(Y[i] / o.x_max);
-    u[3 * i + 2] = (float)((2 * S[i] - o.s_lo - o.s_hi) / (o.s_hi - o.s_lo));
+  u.resize(2 * rho.size());
+  for (size_t i = 0; i < rho.size(); ++i) {
+    u[2 * i] = (float)(rho[i] / o.rho_max);
+    u[2 * i + 1] = (float)((2 * S[i] - o.s_lo - o.s_hi) / (o.s_hi - o.s_lo));
   }
 }
 
-// rows sk.key of d_out from the network (level box size hb)
+// rows sk.key of d_out (level box size hb) from the network's H (or, with
+// h_from_images, from the images' H), rebuilt into the compact Cartesian layout
 static int surrogate_tables(tefmm_t h, const SigmaKeys& sk, double hb, double2* d_out, hipStream_t s) {
   tefmm_surrogate* su = h->sur;
-  const int nk = (int)sk.key.size(), nG = h->nG;
-  std::vector<float> u;
-  sur_inputs(su, sk.X, sk.Y, sk.S, u);
-  float *d_u = nullptr, *d_y = nullptr;
+  const int nk = (int)sk.key.size(), nG = h->nG, nH = su->nH;
+  std::vector<double> rho(nk);
+  for (int i = 0; i < nk; ++i) rho[i] = std::hypot(sk.X[i], sk.Y[i]);
+  double2* d_H = nullptr;
+  double *d_x = nullptr, *d_y = nullptr, *d_re = nullptr;
   int* d_key = nullptr;
-  double* d_re = nullptr;
-  HIPCHK(h, dmalloc(h, &d_u, sizeof(float) * u.size()));
-  HIPCHK(h, dmalloc(h, &d_y, sizeof(float) * (size_t)nk * 2 * nG));
+  HIPCHK(h, dmalloc(h, &d_H, sizeof(double2) * (size_t)nk * nH));
+  HIPCHK(h, dmalloc(h, &d_x, sizeof(double) * nk));
+  HIPCHK(h, dmalloc(h, &d_y, sizeof(double) * nk));
   HIPCHK(h, dmalloc(h, &d_key, sizeof(int) * nk));
-  HIPCHK(h, dmalloc(h, &d_re, sizeof(double) * nk));
-  HIPCHK(h, hipMemcpyAsync(d_u, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(d_x, sk.X.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(d_y, sk.Y.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipMemcpyAsync(d_key, sk.key.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
-  HIPCHK(h, hipMemcpyAsync(d_re, sk.Re.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
-  HIPCHK(h, su->net.reserve(std::min(nk, 65536)));
-  for (int r0 = 0; r0 < nk; r0 += (int)su->net.cap) {
-    const int cnt = std::min<int>((int)su->net.cap, nk - r0);
-    HIPCHK(h, su->net.forward(d_u + 3 * (size_t)r0, cnt, d_y + (size_t)r0 * 2 * nG, s));
+  if (su->o.h_from_images) {
+    int rc = sur_image_h(su, rho, sk.S, d_H, s);
+    if (rc != TEFMM_OK) return fail(h, rc, "surrogate: " + su->ref->err);
+  } else {
+    std::vector<float> u;
+    sur_inputs(su, rho, sk.S, u);
+    float *d_u = nullptr, *d_net = nullptr;
+    HIPCHK(h, dmalloc(h, &d_u, sizeof(float) * u.size()));
+    HIPCHK(h, dmalloc(h, &d_net, sizeof(float) * (size_t)nk * 2 * nH));
+    HIPCHK(h, dmalloc(h, &d_re, sizeof(double) * 2 * nk));
+    HIPCHK(h, hipMemcpyAsync(d_u, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_re, sk.Re.data(), sizeof(double) * 2 * nk, hipMemcpyHostToDevice, s));
+    HIPCHK(h, su->net.reserve(std::min(nk, 65536)));
+    for (int r0 = 0; r0 < nk; r0 += (int)su->net.cap) {
+      const int cnt = std::min<int>((int)su->net.cap, nk - r0);
+      HIPCHK(h, su->net.forward(d_u + 2 * (size_t)r0, cnt, d_net + (size_t)r0 * 2 * nH, s));
+    }
+    // the quasi-static part, exact, then the network's remainder added to it
+    int rc = sur_image_h(su, rho, sk.S, d_H, s, true);
+    if (rc != TEFMM_OK) return fail(h, rc, "surrogate: " + su->ref->err);
+    hipLaunchKernelGGL(k_sur_h_from_net, dim3(nk), dim3(128), 0, s, d_net, d_re, nk, su->P2, su->d_sigma,
+                       su->o.envelope, d_H);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    dfree(h, d_u);
+    dfree(h, d_net);
   }
-  hipLaunchKernelGGL(k_sur_assemble, dim3(nk), dim3(128), 0, s, d_y, d_key, d_re, nk, nG, hb, su->d_sigma,
-                     su->d_gord, d_out);
+  hipLaunchKernelGGL(k_sigma_restore, dim3(nk), dim3(64), 0, s, d_H, d_x, d_y, nk, d_key, hb,
+                     h->med.k[su->layer], su->P2, nG, h->d_g1, h->d_g3, su->d_gord, d_out);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
-  dfree(h, d_u);
+  dfree(h, d_H);
+  dfree(h, d_x);
   dfree(h, d_y);
   dfree(h, d_key);
   dfree(h, d_re);
@@ -2192,7 +2204,7 @@ extern "C" void tefmm_surrogate_default_options(const tefmm_medium* medium, int 
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
   o->layer = layer;
-  o->x_max = 0.75;
+  o->rho_max = 1.1;
   o->s_lo = -1.0, o->s_hi = 1.0;
   MediumDesc med;
   std::string err;
@@ -2202,17 +2214,20 @@ extern "C" void tefmm_surrogate_default_options(const tefmm_medium* medium, int 
     const double bot = layer == med.L ? (med.L ? med.d[med.L - 1] - 2.0 : -2.0) : med.d[layer];
     o->s_lo = 2 * bot + margin, o->s_hi = 2 * top - margin;
   }
-  o->n_train = 131072;
-  o->epochs = 60;
+  o->n_train = 262144;
+  o->epochs = 300;
   o->batch = 1024;
   o->lr = 2e-3f;
   o->width = 128;
   o->n_hidden = 4;
-  o->cells_xy = 6;
-  o->cells_s = 12;
+  o->cells_rho = 8;
+  o->cells_s = 16;
   o->n_valid = 16;
-  o->budget = 3e-3;
+  o->budget = 4e-4;
   o->seed = 1234;
+  o->h_from_images = 0;
+  o->envelope = 1;
+  o->leaf_level = 0;
 }
 
 #define SURCHK(x)                                                \
@@ -2220,9 +2235,7 @@ extern "C" void tefmm_surrogate_default_options(const tefmm_medium* medium, int 
     int rc_ = (x);                                               \
     if (rc_ != TEFMM_OK) {                                       \
       if (rep) rep->status = rc_;                                \
-      std::string m_ = su->ref ? su->ref->err : std::string(""); \
       delete su;                                                 \
-      (void)m_;                                                  \
       return rc_;                                                \
     }                                                            \
   } while (0)
@@ -2235,8 +2248,8 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
   *out = nullptr;
   if (rep) std::memset(rep, 0, sizeof(*rep));
   const tefmm_surrogate_options& o = *so;
-  if (!(o.x_max > 0) || !(o.s_hi > o.s_lo) || o.n_train < 64 || o.epochs < 0 || o.batch < 1 || !(o.lr > 0) ||
-      o.width < 16 || o.n_hidden < 1 || o.cells_xy < 1 || o.cells_s < 1 || o.n_valid < 1 || !(o.budget > 0))
+  if (!(o.rho_max > 0) || !(o.s_hi > o.s_lo) || o.n_train < 64 || o.epochs < 0 || o.batch < 1 || !(o.lr > 0) ||
+      o.width < 16 || o.n_hidden < 1 || o.cells_rho < 1 || o.cells_s < 1 || o.n_valid < 1 || !(o.budget > 0))
     return TEFMM_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   tefmm_surrogate* su = new tefmm_surrogate();
@@ -2247,8 +2260,10 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
   const MediumDesc& med = h->med;
   const int l = o.layer;
   if (l < 0 || l > med.L) SURCHK(TEFMM_ERR_INVALID_ARG);
-  su->p = h->opt.p, su->nG = h->nG;
-  const int nG = su->nG;
+  su->p = h->opt.p, su->nG = h->nG, su->P2 = 2 * h->opt.p;
+  su->nH = (su->P2 + 1) * (su->P2 + 2) / 2;
+  if (su->P2 > SIGMA_P2_MAX) SURCHK(TEFMM_ERR_UNSUPPORTED);
+  const int nG = su->nG, nH = su->nH;
   // the training box must lie in the layer (S = z + z' of two points of the layer)
   const double top = med.top(l), bot = med.bottom(l);
   if (!(o.s_lo > 2 * bot) || !(o.s_hi < 2 * top)) SURCHK(TEFMM_ERR_INVALID_ARG);
@@ -2263,11 +2278,37 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
     su->has[f] = !su->A[f].empty();
   }
   if (!su->has[0] && !su->has[1]) SURCHK(TEFMM_ERR_UNSUPPORTED);  // no Sigma family in this layer
+  {
+    std::vector<double2> img;
+    for (int f = 0; f < 2; ++f)
+      for (size_t j = 0; j < su->A[f].size(); ++j) {
+        img.push_back(make_double2(su->A[f][j].real(), su->A[f][j].imag()));
+        img.push_back(make_double2(su->Z[f][j].real(), su->Z[f][j].imag()));
+      }
+    SURHIP(hipMalloc(&su->d_img, sizeof(double2) * std::max<size_t>(img.size(), 1)));
+    SURHIP(hipMemcpy(su->d_img, img.data(), sizeof(double2) * img.size(), hipMemcpyHostToDevice));
+    // the quasi-static image of each family (the fit places it at depth 0, the mirror point)
+    std::vector<double2> qs;
+    for (int f = 0; f < 2; ++f)
+      for (size_t j = 0; j < su->A[f].size(); ++j)
+        if (su->Z[f][j] == cplx(0, 0)) {
+          qs.push_back(make_double2(su->A[f][j].real(), su->A[f][j].imag()));
+          qs.push_back(make_double2(0.0, 0.0));
+          (f == 0 ? su->qs_up : su->qs_dn) += 1;
+        }
+    SURHIP(hipMalloc(&su->d_qs, sizeof(double2) * std::max<size_t>(qs.size(), 1)));
+    if (!qs.empty()) SURHIP(hipMemcpy(su->d_qs, qs.data(), sizeof(double2) * qs.size(), hipMemcpyHostToDevice));
+  }
   std::vector<unsigned char> gord(nG);
   for (int n = 0; n <= 2 * su->p; ++n)
     for (int i = g_offset(n); i < g_offset(n + 1); ++i) gord[i] = (unsigned char)n;
   SURHIP(hipMalloc(&su->d_gord, nG));
   SURHIP(hipMemcpy(su->d_gord, gord.data(), nG, hipMemcpyHostToDevice));
+  if (o.h_from_images) {  // no network: rows from the images' H (a check of the representation)
+    if (rep) rep->status = TEFMM_OK, rep->n_out = 2 * nH;
+    *out = su;
+    return TEFMM_OK;
+  }
   // samples: uniform in the box
   uint64_t st = o.seed;
   auto unif = [&]() {
@@ -2278,51 +2319,56 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
     z ^= z >> 31;
     return (double)(z >> 11) * (1.0 / 9007199254740992.0);
   };
-  auto targets = [&](const std::vector<double>& X, const std::vector<double>& Y, const std::vector<double>& S,
-                     double2* d_W, double* d_sumsq) -> int {
-    const int n = (int)X.size();
-    double2* d_raw = nullptr;
+  // normalised targets: W = (H - H_quasi-static) (divided by the envelope if asked), and
+  // the sums of |W|^2 per entry
+  auto targets = [&](const std::vector<double>& R, const std::vector<double>& S, double2* d_W,
+                     double* d_sumsq) -> int {
+    const int n = (int)R.size();
+    double2 *d_H = nullptr, *d_Hq = nullptr;
     double* d_re = nullptr;
-    HIPCHK(h, hipMalloc(&d_raw, sizeof(double2) * (size_t)n * nG));
-    HIPCHK(h, hipMalloc(&d_re, sizeof(double) * n));
-    int rc = sur_image_tables(su, X, Y, S, d_raw, s);
+    HIPCHK(h, hipMalloc(&d_H, sizeof(double2) * (size_t)n * nH));
+    HIPCHK(h, hipMalloc(&d_Hq, sizeof(double2) * (size_t)n * nH));
+    HIPCHK(h, hipMalloc(&d_re, sizeof(double) * 2 * n));
+    int rc = sur_image_h(su, R, S, d_H, s);
+    if (rc == TEFMM_OK) rc = sur_image_h(su, R, S, d_Hq, s, true);
     if (rc != TEFMM_OK) return rc;
-    std::vector<double> re(n);
-    for (int i = 0; i < n; ++i) re[i] = sigma_envelope(med, l, su->has[0], su->has[1], X[i], Y[i], S[i]);
-    HIPCHK(h, hipMemcpyAsync(d_re, re.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_sur_normalize, dim3(n), dim3(128), 0, s, d_raw, d_re, n, nG, su->d_gord, d_W, d_sumsq);
+    std::vector<double> re;
+    for (int i = 0; i < n; ++i) sigma_mirror_dist(med, l, su->has[0], su->has[1], R[i], 0.0, S[i], re);
+    HIPCHK(h, hipMemcpyAsync(d_re, re.data(), sizeof(double) * re.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sur_normalize, dim3(n), dim3(128), 0, s, d_H, d_Hq, d_re, n, su->P2, o.envelope, d_W,
+                       d_sumsq);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(s));
-    dfree_raw(d_raw);
+    dfree_raw(d_H);
+    dfree_raw(d_Hq);
     dfree_raw(d_re);
     return TEFMM_OK;
   };
   const int n = o.n_train;
-  std::vector<double> X(n), Y(n), S(n);
+  std::vector<double> R(n), S(n);
   for (int i = 0; i < n; ++i) {
-    X[i] = (2 * unif() - 1) * o.x_max;
-    Y[i] = (2 * unif() - 1) * o.x_max;
+    R[i] = (2 * unif() - 1) * o.rho_max;  // signed: see sur_inputs
     S[i] = o.s_lo + unif() * (o.s_hi - o.s_lo);
   }
   double2* d_W = nullptr;
   double* d_sumsq = nullptr;
   float *d_T = nullptr, *d_X = nullptr;
-  SURHIP(hipMalloc(&d_W, sizeof(double2) * (size_t)n * nG));
-  SURHIP(hipMalloc(&d_sumsq, sizeof(double) * nG));
-  SURHIP(hipMemset(d_sumsq, 0, sizeof(double) * nG));
-  SURCHK(targets(X, Y, S, d_W, d_sumsq));
-  std::vector<double> sumsq(nG);
-  SURHIP(hipMemcpy(sumsq.data(), d_sumsq, sizeof(double) * nG, hipMemcpyDeviceToHost));
-  su->sigma.resize(nG);
-  for (int g = 0; g < nG; ++g) su->sigma[g] = (float)std::max(std::sqrt(sumsq[g] / n), 1e-30);
-  SURHIP(hipMalloc(&su->d_sigma, sizeof(float) * nG));
-  SURHIP(hipMemcpy(su->d_sigma, su->sigma.data(), sizeof(float) * nG, hipMemcpyHostToDevice));
-  SURHIP(hipMalloc(&d_T, sizeof(float) * (size_t)n * 2 * nG));
-  hipLaunchKernelGGL(k_sur_targets, dim3((unsigned)(((size_t)n * nG + 255) / 256)), dim3(256), 0, s, d_W, n, nG,
+  SURHIP(hipMalloc(&d_W, sizeof(double2) * (size_t)n * nH));
+  SURHIP(hipMalloc(&d_sumsq, sizeof(double) * nH));
+  SURHIP(hipMemset(d_sumsq, 0, sizeof(double) * nH));
+  SURCHK(targets(R, S, d_W, d_sumsq));
+  std::vector<double> sumsq(nH);
+  SURHIP(hipMemcpy(sumsq.data(), d_sumsq, sizeof(double) * nH, hipMemcpyDeviceToHost));
+  su->sigma.resize(nH);
+  for (int g = 0; g < nH; ++g) su->sigma[g] = (float)std::max(std::sqrt(sumsq[g] / n), 1e-30);
+  SURHIP(hipMalloc(&su->d_sigma, sizeof(float) * nH));
+  SURHIP(hipMemcpy(su->d_sigma, su->sigma.data(), sizeof(float) * nH, hipMemcpyHostToDevice));
+  SURHIP(hipMalloc(&d_T, sizeof(float) * (size_t)n * 2 * nH));
+  hipLaunchKernelGGL(k_sur_targets, dim3((unsigned)(((size_t)n * nH + 255) / 256)), dim3(256), 0, s, d_W, n, nH,
                      su->d_sigma, d_T);
   SURHIP(hipGetLastError());
   std::vector<float> u;
-  sur_inputs(su, X, Y, S, u);
+  sur_inputs(su, R, S, u);
   SURHIP(hipMalloc(&d_X, sizeof(float) * u.size()));
   SURHIP(hipMemcpyAsync(d_X, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice, s));
   SURHIP(hipStreamSynchronize(s));
@@ -2330,7 +2376,7 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
   dfree_raw(d_sumsq);
   auto t1 = std::chrono::steady_clock::now();
   // training on the matrix cores
-  SURHIP(su->net.init(3, o.width, o.n_hidden, 2 * nG, o.seed ^ 0x5bd1e995ull));
+  SURHIP(su->net.init(2, o.width, o.n_hidden, 2 * nH, o.seed ^ 0x5bd1e995ull));
   std::vector<double> losses;
   SURHIP(su->net.train(d_X, d_T, n, o.epochs, o.batch, o.lr, o.seed + 17, losses, s));
   if (epoch_loss)
@@ -2338,34 +2384,35 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
   dfree_raw(d_X);
   dfree_raw(d_T);
   auto t2 = std::chrono::steady_clock::now();
-  // validation map: n_valid fresh points per cell
-  const int ncell = o.cells_xy * o.cells_xy * o.cells_s, nv = ncell * o.n_valid;
-  std::vector<double> vX(nv), vY(nv), vS(nv);
+  // validation map: n_valid fresh points per (rho, S) cell
+  const int ncell = o.cells_rho * o.cells_s, nv = ncell * o.n_valid;
+  std::vector<double> vR(nv), vS(nv);
   for (int c = 0; c < ncell; ++c) {
-    const int cu = c / (o.cells_xy * o.cells_s), cv = (c / o.cells_s) % o.cells_xy, cw = c % o.cells_s;
+    const int cu = c / o.cells_s, cw = c % o.cells_s;
     for (int j = 0; j < o.n_valid; ++j) {
       const int i = c * o.n_valid + j;
-      vX[i] = (-1 + 2 * (cu + unif()) / o.cells_xy) * o.x_max;
-      vY[i] = (-1 + 2 * (cv + unif()) / o.cells_xy) * o.x_max;
+      // the first point of every cell on its lower rho edge (rho = 0 for the first column:
+      // the keys straight above one another sit there, on the edge of the input range)
+      vR[i] = (cu + (j == 0 ? 0.0 : unif())) / o.cells_rho * o.rho_max;
       vS[i] = o.s_lo + (cw + unif()) / o.cells_s * (o.s_hi - o.s_lo);
     }
   }
   double2* d_vW = nullptr;
   float *d_vu = nullptr, *d_vy = nullptr;
-  SURHIP(hipMalloc(&d_vW, sizeof(double2) * (size_t)nv * nG));
-  SURCHK(targets(vX, vY, vS, d_vW, nullptr));
+  SURHIP(hipMalloc(&d_vW, sizeof(double2) * (size_t)nv * nH));
+  SURCHK(targets(vR, vS, d_vW, nullptr));
   std::vector<float> vu;
-  sur_inputs(su, vX, vY, vS, vu);
+  sur_inputs(su, vR, vS, vu);
   SURHIP(hipMalloc(&d_vu, sizeof(float) * vu.size()));
-  SURHIP(hipMalloc(&d_vy, sizeof(float) * (size_t)nv * 2 * nG));
+  SURHIP(hipMalloc(&d_vy, sizeof(float) * (size_t)nv * 2 * nH));
   SURHIP(hipMemcpy(d_vu, vu.data(), sizeof(float) * vu.size(), hipMemcpyHostToDevice));
   SURHIP(su->net.reserve(std::min(nv, 65536)));
   for (int r0 = 0; r0 < nv; r0 += (int)su->net.cap) {
     const int cnt = std::min<int>((int)su->net.cap, nv - r0);
-    SURHIP(su->net.forward(d_vu + 3 * (size_t)r0, cnt, d_vy + (size_t)r0 * 2 * nG, s));
+    SURHIP(su->net.forward(d_vu + 2 * (size_t)r0, cnt, d_vy + (size_t)r0 * 2 * nH, s));
   }
-  std::vector<double2> vW((size_t)nv * nG);
-  std::vector<float> vy((size_t)nv * 2 * nG);
+  std::vector<double2> vW((size_t)nv * nH);
+  std::vector<float> vy((size_t)nv * 2 * nH);
   SURHIP(hipMemcpyAsync(vW.data(), d_vW, sizeof(double2) * vW.size(), hipMemcpyDeviceToHost, s));
   SURHIP(hipMemcpyAsync(vy.data(), d_vy, sizeof(float) * vy.size(), hipMemcpyDeviceToHost, s));
   SURHIP(hipStreamSynchronize(s));
@@ -2380,9 +2427,16 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
     double e = 0;
     for (int j = 0; j < o.n_valid; ++j) {
       const size_t i = (size_t)c * o.n_valid + j;
-      for (int g = 0; g < nG; ++g) {
-        const double pr = vy[(i * nG + g) * 2] * su->sigma[g], pi = vy[(i * nG + g) * 2 + 1] * su->sigma[g];
-        e = std::max(e, std::hypot(pr - vW[i * nG + g].x, pi - vW[i * nG + g].y));
+      // in envelope units, entry (m, c) weighted by 2^-(m+c): a translation between boxes of
+      // side h at distance R >= 2h (the well-separated ones) uses order n of the kernel's
+      // expansion with the weight (h / R)^n relative to order 0
+      for (int nn = 0, g = 0; nn <= su->P2; ++nn) {
+        const double wt = std::ldexp(1.0, -nn);
+        for (int m = 0; m <= nn; ++m, ++g) {
+          const double pr = vy[(i * nH + g) * 2] * su->sigma[g] - vW[i * nH + g].x,
+                       pi = vy[(i * nH + g) * 2 + 1] * su->sigma[g] - vW[i * nH + g].y;
+          e = std::max(e, wt * std::hypot(pr, pi));
+        }
       }
     }
     su->cell_err[c] = e;
@@ -2399,7 +2453,7 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
     rep->max_cell_err = emax;
     rep->cells_ok = ok;
     rep->cells_total = ncell;
-    rep->n_out = 2 * nG;
+    rep->n_out = 2 * nH;
     rep->n_params = su->net.P;
     rep->status = TEFMM_OK;
   }

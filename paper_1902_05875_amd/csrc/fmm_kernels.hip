@@ -1651,44 +1651,206 @@ template __global__ void k_p2p<float, 256, 8, true>(PassArgs, int, NearPoly);
 // Cauchy-type envelope of a source at distance R_e (the distance to the nearer
 // mirror point):  W_g = D^g K R_e^{|g|+1} / |g|!.
 // ---------------------------------------------------------------------------
-__global__ void k_sur_normalize(const double2* raw, const double* Re, int n, int nG, const unsigned char* gord,
+// ---------------------------------------------------------------------------
+// Rotation-free derivatives of the Sigma-family kernel (the same-layer reaction
+// term that depends on x - x', y - y' and S = z + z', Sec. 3.2).  The kernel is
+// axisymmetric, K = sum_img A f(w, zeta) with w = rho^2 and
+// f = e^{ik sqrt(w + zeta^2)} / sqrt(w + zeta^2); with u = x + i y,
+//   (d_x + i d_y)^m d_S^c K = u^m H_{m,c},  (d_x - i d_y)^m d_S^c K = conj(u)^m H_{m,c},
+//   H_{m,c}(w, S) = (2 d_w)^m d_S^c K,   m + c <= P2,
+// stored at index (m + c)(m + c + 1)/2 + m.  f = g(s), s = w + zeta^2, and the Taylor
+// coefficients g_n = g^(n)(s) / n! of g(s) = e^{ik sqrt s} / sqrt s follow from the
+// spherical Hankel functions of the first kind, (r^-1 d_r)^n h_0(kr) = (-k^2)^n h_n(kr) / (kr)^n:
+//   g_n = (-1)^n i k^(2n+1) q_n / (2^n n!),  q_n = h_n(kr) / (kr)^n,  r = sqrt(s),
+//   q_0 = -i e^{ikr} / (kr),  q_1 = -e^{ikr} (kr + i) / (kr)^3,  q_{n+1} = ((2n+1) q_n - q_{n-1}) / (kr)^2.
+// Composing with s - s0 = dw + 2 zeta dzeta + dzeta^2:
+//   d_w^m d_zeta^c f / (m! c!) = sum_q g_{m+c-q} (m+c-q)! / (m! (c-2q)! q!) (2 zeta)^(c-2q).
+// zeta = S - 2 d_l - Z for the up-going family and 2 d_{l-1} - S - Z for the down-going
+// one (there d_S = -d_zeta); images with Re zeta <= 0 are left out, as in the tables.
+// One block of 64 per point; thread m owns the entries (m, c) in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_sigma_h(const double* w, const double* S, int n, const double2* img, int nup,
+                                                int ndn, double two_dl, double two_dt, double k, int P2, double2* H) {
+  __shared__ double2 sh[SIGMA_H_MAX];
+  __shared__ double2 sg[SIGMA_P2_MAX + 1], sz2[SIGMA_P2_MAX + 1];
+  __shared__ double fct[SIGMA_P2_MAX + 1];
+  const int pt = blockIdx.x, m = threadIdx.x;
+  if (pt >= n) return;
+  const int nH = (P2 + 1) * (P2 + 2) / 2;
+  for (int e = m; e < nH; e += 64) sh[e] = make_double2(0.0, 0.0);
+  if (m == 0) {
+    fct[0] = 1.0;
+    for (int i = 1; i <= P2; ++i) fct[i] = fct[i - 1] * i;
+  }
+  const double wv = w[pt], Sv = S[pt];
+  for (int j = 0; j < nup + ndn; ++j) {
+    const bool dn = j >= nup;
+    const double2 A = img[2 * j], Z = img[2 * j + 1];
+    const dc zeta = {(dn ? two_dt - Sv : Sv - two_dl) - Z.x, -Z.y};
+    if (zeta.x <= 0.0) continue;  // uniform over the block
+    __syncthreads();
+    if (m == 0) {
+      const dc s0 = {wv + zeta.x * zeta.x - zeta.y * zeta.y, 2.0 * zeta.x * zeta.y};
+      const dc z = cscale(csqrt_pr(s0), k);
+      const dc e = cexp_i(z, 1.0);
+      const dc iz = cdiv({1.0, 0.0}, z), iz2 = cmul(iz, iz);
+      dc q0 = cmul({0.0, -1.0}, cmul(e, iz));
+      dc q1 = cscale(cmul(cmul(e, cadd(z, {0.0, 1.0})), cmul(iz2, iz)), -1.0);
+      double kp = k, tw = 1.0;  // k^(2n+1), 2^n n!
+      for (int nn = 0; nn <= P2; ++nn) {
+        const dc q = nn == 0 ? q0 : q1;
+        const dc gn = cscale(cmul({0.0, (nn & 1) ? -kp : kp}, q), 1.0 / tw);
+        sg[nn] = make_double2(gn.x, gn.y);
+        if (nn >= 1) {
+          const dc q2 = cmul(csub(cscale(q1, 2.0 * nn + 1.0), q0), iz2);
+          q0 = q1, q1 = q2;
+        }
+        kp *= k * k, tw *= 2.0 * (nn + 1);
+      }
+      dc t = {1.0, 0.0};
+      const dc z2 = cscale(zeta, 2.0);
+      for (int i = 0; i <= P2; ++i) sz2[i] = make_double2(t.x, t.y), t = cmul(t, z2);
+    }
+    __syncthreads();
+    if (m <= P2) {
+      const dc a = {A.x, A.y};
+      double pm = 1.0;
+      for (int i = 0; i < m; ++i) pm *= 2.0;
+      for (int c = 0; c <= P2 - m; ++c) {
+        dc coef = {0.0, 0.0};
+        for (int q = 0; 2 * q <= c; ++q) {
+          const int nn = m + c - q;
+          const double b = fct[nn] / (fct[m] * fct[c - 2 * q] * fct[q]);
+          coef = cadd(coef, cscale(cmul({sg[nn].x, sg[nn].y}, {sz2[c - 2 * q].x, sz2[c - 2 * q].y}), b));
+        }
+        const double sc = pm * fct[m] * fct[c] * ((dn && (c & 1)) ? -1.0 : 1.0);
+        const dc v = cscale(cmul(a, coef), sc);
+        double2& o = sh[(m + c) * (m + c + 1) / 2 + m];
+        o = make_double2(o.x + v.x, o.y + v.y);
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = m; e < nH; e += 64) H[(size_t)pt * nH + e] = sh[e];
+}
+
+// Envelope of H_{m,c}: the size of the term of a source at each mirror point, distances
+// R2[0] and R2[1] (1e300: family absent), (2m-1)!! c! sum_f R_f^-(2m+c+1).
+__device__ __forceinline__ double sigma_h_envelope(int m, int c, const double* R2) {
+  double tot = 0.0;
+  for (int f = 0; f < 2; ++f) {
+    const double R = R2[f];
+    if (!(R < 1e299)) continue;
+    double e = 1.0 / R;
+    for (int i = 1; i <= m; ++i) e *= (2.0 * i - 1.0) / (R * R);
+    for (int i = 1; i <= c; ++i) e *= i / R;
+    tot += e;
+  }
+  return tot;
+}
+
+// W = H - Hq (the quasi-static part taken out), divided by the envelope if env (Re: the
+// two mirror distances per point), and the sums of |W|^2 per entry
+__global__ void k_sur_normalize(const double2* H, const double2* Hq, const double* Re, int n, int P2, int env,
                                 double2* W, double* sumsq) {
-  const int key = blockIdx.x;
-  if (key >= n) return;
-  const double r = Re[key];
-  for (int g = threadIdx.x; g < nG; g += blockDim.x) {
-    const int o = gord[g];
-    double f = r;
-    for (int i = 1; i <= o; ++i) f *= r / i;
-    const double2 v = raw[(size_t)key * nG + g];
-    const double2 w = make_double2(v.x * f, v.y * f);
-    W[(size_t)key * nG + g] = w;
-    if (sumsq) atomicAdd(&sumsq[g], w.x * w.x + w.y * w.y);
+  const int pt = blockIdx.x;
+  if (pt >= n) return;
+  const int nH = (P2 + 1) * (P2 + 2) / 2;
+  for (int e = threadIdx.x; e < nH; e += blockDim.x) {
+    int nn = 0;
+    while ((nn + 1) * (nn + 2) / 2 <= e) ++nn;
+    const int m = e - nn * (nn + 1) / 2, c = nn - m;
+    const double f = env ? 1.0 / sigma_h_envelope(m, c, Re + 2 * pt) : 1.0;
+    const double2 v = H[(size_t)pt * nH + e], q = Hq[(size_t)pt * nH + e];
+    const double2 wv = make_double2((v.x - q.x) * f, (v.y - q.y) * f);
+    W[(size_t)pt * nH + e] = wv;
+    if (sumsq) atomicAdd(&sumsq[e], wv.x * wv.x + wv.y * wv.y);
   }
 }
 
-// network targets: (Re W_g / sigma_g, Im W_g / sigma_g) per entry
-__global__ void k_sur_targets(const double2* W, int n, int nG, const float* sigma, float* T) {
+// network targets: (Re W / sigma, Im W / sigma) per entry
+__global__ void k_sur_targets(const double2* W, int n, int nH, const float* sigma, float* T) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (size_t)n * nG) return;
-  const int g = (int)(e % nG);
+  if (e >= (size_t)n * nH) return;
+  const int g = (int)(e % nH);
   const double2 w = W[e];
   T[2 * e] = (float)(w.x / sigma[g]);
   T[2 * e + 1] = (float)(w.y / sigma[g]);
 }
 
-// table rows of the keys answered by the network: h^{|g|} D^g K = sigma_g y_g |g|! h^{|g|} / R_e^{|g|+1}
-__global__ void k_sur_assemble(const float* y, const int* key_of, const double* Re, int nk, int nG, double h,
-                               const float* sigma, const unsigned char* gord, double2* table) {
-  const int i = blockIdx.x;
+// H from the network's outputs, added to the quasi-static part already in H:
+// H += sigma y (times the envelope if env)
+__global__ void k_sur_h_from_net(const float* y, const double* Re, int n, int P2, const float* sigma, int env,
+                                 double2* H) {
+  const int pt = blockIdx.x;
+  if (pt >= n) return;
+  const int nH = (P2 + 1) * (P2 + 2) / 2;
+  for (int e = threadIdx.x; e < nH; e += blockDim.x) {
+    int nn = 0;
+    while ((nn + 1) * (nn + 2) / 2 <= e) ++nn;
+    const int m = e - nn * (nn + 1) / 2, c = nn - m;
+    const double f = sigma[e] * (env ? sigma_h_envelope(m, c, Re + 2 * pt) : 1.0);
+    double2& o = H[(size_t)pt * nH + e];
+    o = make_double2(o.x + y[((size_t)pt * nH + e) * 2] * f, o.y + y[((size_t)pt * nH + e) * 2 + 1] * f);
+  }
+}
+
+// Compact Cartesian table rows from H (exact algebra).  With D = d_x +- i d_y,
+//   d_x^a d_y^b = 2^-(a+b) (-i)^b sum_{al, be} C(a, al) C(b, be) (-1)^(b-be) D+^(al+be) D-^(a+b-al-be),
+// and, K solving the Helmholtz equation in (x, y, S) (every image does),
+// D+ D- = d_x^2 + d_y^2 = -(d_S^2 + k^2), so for p >= q
+//   D+^p D-^q d_S^c K = (-1)^q sum_t C(q, t) k^(2(q-t)) u^(p-q) H_{p-q, c+2t}
+// (conj(u) and p, q swapped when q > p).  Row of key i: out[row[i]][g] = h^|g| d^g K at
+// (X_i, Y_i) and the point's S, for the compact entries g (g1 <= 2).  One block per key.
+__global__ __launch_bounds__(64) void k_sigma_restore(const double2* H, const double* X, const double* Y, int nk,
+                                                      const int* row, double h, double k, int P2, int nG,
+                                                      const unsigned char* g1s, const unsigned char* g3s,
+                                                      const unsigned char* gord, double2* out) {
+  __shared__ double2 sh[SIGMA_H_MAX];
+  __shared__ double2 up[SIGMA_P2_MAX + 1], dp[SIGMA_P2_MAX + 1];
+  __shared__ double fct[SIGMA_P2_MAX + 1];
+  const int i = blockIdx.x, tid = threadIdx.x;
   if (i >= nk) return;
-  const double r = Re[i];
-  for (int g = threadIdx.x; g < nG; g += blockDim.x) {
-    const int o = gord[g];
-    double f = 1.0 / r;
-    for (int j = 1; j <= o; ++j) f *= j * h / r;
-    const double s = sigma[g] * f;
-    table[(size_t)key_of[i] * nG + g] = make_double2(y[(size_t)i * 2 * nG + 2 * g] * s, y[(size_t)i * 2 * nG + 2 * g + 1] * s);
+  const int nH = (P2 + 1) * (P2 + 2) / 2;
+  for (int e = tid; e < nH; e += 64) sh[e] = H[(size_t)i * nH + e];
+  if (tid == 0) {
+    fct[0] = 1.0;
+    for (int j = 1; j <= P2; ++j) fct[j] = fct[j - 1] * j;
+    dc a = {1.0, 0.0}, b = {1.0, 0.0};
+    const dc u = {X[i], Y[i]}, ub = {X[i], -Y[i]};
+    for (int j = 0; j <= P2; ++j) up[j] = make_double2(a.x, a.y), dp[j] = make_double2(b.x, b.y), a = cmul(a, u),
+                                  b = cmul(b, ub);
+  }
+  __syncthreads();
+  auto binom = [&](int nn, int r) { return fct[nn] / (fct[r] * fct[nn - r]); };
+  const double k2 = k * k;
+  for (int g = tid; g < nG; g += 64) {
+    const int a1 = g1s[g], c3 = g3s[g], nn = gord[g], b2 = nn - a1 - c3;
+    dc acc = {0.0, 0.0};
+    for (int al = 0; al <= a1; ++al)
+      for (int be = 0; be <= b2; ++be) {
+        const int pp = al + be, qq = a1 + b2 - pp;
+        const int sm = min(pp, qq), md = pp >= qq ? pp - qq : qq - pp;
+        const double2 vm = pp >= qq ? up[md] : dp[md];
+        dc dsum = {0.0, 0.0};
+        double kpow = 1.0;  // k^(2(sm - t)), t from sm down
+        for (int t = sm; t >= 0; --t) {
+          const double2 hv = sh[(md + c3 + 2 * t) * (md + c3 + 2 * t + 1) / 2 + md];
+          dsum = cadd(dsum, cscale({hv.x, hv.y}, binom(sm, t) * kpow));
+          kpow *= k2;
+        }
+        dsum = cmul(dsum, {vm.x, vm.y});
+        const double sgn = ((sm & 1) ? -1.0 : 1.0) * (((b2 - be) & 1) ? -1.0 : 1.0);
+        acc = cadd(acc, cscale(dsum, sgn * binom(a1, al) * binom(b2, be)));
+      }
+    // 2^-(a1+b2) (-i)^b2 h^|g|
+    double sc = 1.0;
+    for (int j = 0; j < a1 + b2; ++j) sc *= 0.5;
+    for (int j = 0; j < nn; ++j) sc *= h;
+    dc ph = {1.0, 0.0};
+    for (int j = 0; j < b2; ++j) ph = cmul(ph, {0.0, -1.0});
+    acc = cscale(cmul(acc, ph), sc);
+    out[(size_t)row[i] * nG + g] = make_double2(acc.x, acc.y);
   }
 }
 

@@ -172,11 +172,21 @@ __global__ void k_sigma_direct(SigmaDirectArgs a);
 void upload_binomials();
 
 __global__ void k_table_gen(TableGenArgs a);
-__global__ void k_sur_normalize(const double2* raw, const double* Re, int n, int nG, const unsigned char* gord,
+// Rotation-free derivatives H_{m,c} = (2 d_{rho^2})^m d_S^c of the Sigma-family kernel
+// (m + c <= P2 <= SIGMA_P2_MAX), their normalisation for the surrogate network, and the
+// compact Cartesian table rows rebuilt from them.
+constexpr int SIGMA_P2_MAX = 32;
+constexpr int SIGMA_H_MAX = (SIGMA_P2_MAX + 1) * (SIGMA_P2_MAX + 2) / 2;
+__global__ void k_sigma_h(const double* w, const double* S, int n, const double2* img, int nup, int ndn,
+                          double two_dl, double two_dt, double k, int P2, double2* H);
+__global__ void k_sur_normalize(const double2* H, const double2* Hq, const double* Re, int n, int P2, int env,
                                 double2* W, double* sumsq);
-__global__ void k_sur_targets(const double2* W, int n, int nG, const float* sigma, float* T);
-__global__ void k_sur_assemble(const float* y, const int* key_of, const double* Re, int nk, int nG, double h,
-                               const float* sigma, const unsigned char* gord, double2* table);
+__global__ void k_sur_targets(const double2* W, int n, int nH, const float* sigma, float* T);
+__global__ void k_sur_h_from_net(const float* y, const double* Re, int n, int P2, const float* sigma, int env,
+                                 double2* H);
+__global__ void k_sigma_restore(const double2* H, const double* X, const double* Y, int nk, const int* row, double h,
+                                double k, int P2, int nG, const unsigned char* g1s, const unsigned char* g3s,
+                                const unsigned char* gord, double2* out);
 __global__ void k_taylor_points(const double* px, const double* py, const double* pz, double k, double h,
                                 int order, int nT, const short* nbr, double2* out);
 __global__ void k_selftest_mfma(double* out64, float* out32);

@@ -4,11 +4,12 @@
 //   a_0 = x,  a_{l+1} = tanh(W_l a_l + b_l) (l < n_hidden),  y = W_out a_H + b_out,
 //   L = mean over samples and outputs of (y - t)^2,  Adam updates.
 //
-// Matrix products run as a BF16 MFMA GEMM (v_mfma_f32_16x16x16_bf16: operands
+// The hidden products run as a BF16 MFMA GEMM (v_mfma_f32_16x16x16_bf16: operands
 // rounded to BF16 when staged into LDS, FP32 accumulation); the first layer
-// (3 inputs) and its weight gradient stay in FP32 on the vector units, since
+// (a few inputs) and its weight gradient stay in FP32 on the vector units, since
 // rounding the coordinates themselves to 8 mantissa bits would cost more
-// accuracy than all later layers.  Master weights, gradients and Adam moments
+// accuracy than all later layers, and so does the output layer (forward and its
+// two backward products), whose values are the results.  Master weights, gradients and Adam moments
 // are FP32.  Activations are stored row-major, one row per sample.
 #include <hip/hip_runtime.h>
 
@@ -131,6 +132,61 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       }
 }
 
+// The same product in FP32 on the vector units (the output layer, whose values are the
+// surrogate's results: BF16 operands there would cost ~3e-3 of their accuracy).  64 x 64
+// output tile per workgroup of 256, 4 x 4 per thread, K in steps of 16 through LDS.
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
+  __shared__ float sA[16][65];  // [k][row]
+  __shared__ float sB[16][65];  // [k][col]
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int kbeg = blockIdx.z * g.kps;
+  const int kend = min(g.K, kbeg + g.kps);
+  float acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;  // 1024 = 64 x 16 entries of each operand
+      const int row = e & 63, kk = e >> 6;
+      const int i = i0 + row, j = j0 + row, k = k0 + kk;
+      sA[kk][row] = (i < g.M && k < kend) ? g.A[(int64_t)i * g.sai + (int64_t)k * g.sak] : 0.f;
+      sB[kk][row] = (j < g.N && k < kend) ? g.B[(int64_t)k * g.sbk + (int64_t)j * g.sbj] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = sA[kk][tr + 16 * a], bv[a] = sB[kk][tc + 16 * a];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
+      if (i >= g.M || j >= g.N) continue;
+      float v = acc[a][b];
+      float* c = g.C + (int64_t)i * g.ldc + j;
+      if (g.atomic) {
+        atomicAdd(c, v);
+      } else {
+        if (g.bias) v += g.bias[j];
+        if (g.act == 1) v = tanhf(v);
+        *c = v;
+      }
+    }
+}
+
 // first layer in FP32: a1[s][j] = tanh(sum_i W0[j][i] x[s][i] + b0[j])
 __global__ void k_mlp_in(const float* x, int64_t n, int nin, int width, const float* W0, const float* b0, float* a1) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,7 +265,8 @@ __global__ void k_mlp_gather(const float* src, const int* idx, int64_t cnt, int 
   dst[e] = src[(int64_t)idx[r] * cols + (e - r * cols)];
 }
 
-static hipError_t gemm(const GemmArgs& g0, hipStream_t s) {
+// f32: the FP32 vector-unit product (output layer) instead of the BF16 MFMA one
+static hipError_t gemm(const GemmArgs& g0, hipStream_t s, bool f32 = false) {
   GemmArgs g = g0;
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
   int splits = 1;
@@ -220,7 +277,10 @@ static hipError_t gemm(const GemmArgs& g0, hipStream_t s) {
     g.kps = ((g.K + 31) / 32) * 32;
   }
   dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
+  if (f32)
+    hipLaunchKernelGGL(k_gemm_f32, grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
@@ -291,7 +351,7 @@ hipError_t Mlp::forward_in(const float* x, int64_t n, float* out, hipStream_t s,
     } else {
       g.C = out, g.ldc = n_out, g.act = 0;
     }
-    if ((e = gemm(g, s)) != hipSuccess) return e;
+    if ((e = gemm(g, s, l == n_hidden)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -318,7 +378,7 @@ hipError_t Mlp::loss_grad(const float* x, const float* t, int64_t n, hipStream_t
     g.A = d, g.sai = 1, g.sak = ld;
     g.B = ain, g.sbk = width, g.sbj = 1;
     g.C = grad + off_W[l], g.ldc = cols[l], g.atomic = 1;
-    if ((e = gemm(g, s)) != hipSuccess) return e;
+    if ((e = gemm(g, s, l == n_hidden)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_mlp_colsum, dim3((unsigned)((rows[l] + 63) / 64), nblk(n)), dim3(256), 0, s, d, n, rows[l],
                        grad + off_b[l]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -328,7 +388,7 @@ hipError_t Mlp::loss_grad(const float* x, const float* t, int64_t n, hipStream_t
     g.A = d, g.sai = ld, g.sak = 1;
     g.B = theta + off_W[l], g.sbk = cols[l], g.sbj = 1;
     g.C = dn, g.ldc = width;
-    if ((e = gemm(g, s)) != hipSuccess) return e;
+    if ((e = gemm(g, s, l == n_hidden)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_mlp_tanh_back, dim3(nblk(n * width)), dim3(256), 0, s, dn, ain, n * width);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     d = dn, ld = width;

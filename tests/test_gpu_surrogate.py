@@ -1,80 +1,133 @@
-"""Surrogate for the Sigma tables: training on the GPU, validation map, fallback, and what it gains."""
+"""Surrogate for the Sigma tables: the rotation-free representation, training on the GPU,
+the validation map, the rows it serves and what it gains."""
+import os
+import time
+
 import numpy as np
 import pytest
+
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
 K3 = (0.8, 1.5, 2.0)
 D3 = (0.0, -1.2)
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
 @pytest.fixture(scope="module")
 def sur():
     from paper_1902_05875_amd import api
-    s = api.Surrogate(K3, D3, 1, p=8, n_train=32768, epochs=20, batch=512)
-    print("surrogate report", s.report, "loss first/last", s.losses[0], s.losses[-1])
+    t0 = time.perf_counter()
+    s = api.Surrogate(K3, D3, 1, p=8)
+    s.wall = time.perf_counter() - t0
+    print("surrogate report", s.report, "loss first/last", s.losses[0], s.losses[-1], f"wall {s.wall:.1f} s")
     yield s
     s.close()
 
 
-def test_training_and_validation_map(sur):
-    """The network is trained by the library's own kernels (loss falls) and the map
-    keeps exactly the cells whose validated error is within the budget."""
-    r = sur.report
-    assert r["status"] == 0 and r["n_out"] == 2 * (1 + 3 * 8 * 17)  # 2 g_count(16)
-    assert sur.losses[-1] < 0.5 * sur.losses[0]
-    err = sur.cell_errors()
-    assert r["cells_ok"] == int(np.sum(err <= sur.options["budget"]))
-    assert np.isclose(r["max_cell_err"], err.max())
-    # a point's cell decides (x, y, S inside the box), points outside the box are refused
-    o = sur.options
-    pts = np.array([[0.0, 0.0, 0.5 * (o["s_lo"] + o["s_hi"])], [0.0, 0.0, o["s_hi"] + 0.1],
-                    [2 * o["x_max"], 0.0, o["s_lo"] + 0.01]])
-    ok = sur.cell_ok(pts)
-    assert not ok[1] and not ok[2]
-
-
-def _c2(sur, prec, budget_all=False):
+def _c2(sur, prec, p=8):
     import torch
     from paper_1902_05875_amd import api, inputs
-    xyz, q = inputs.workload("c2", n=50_000)
-    f = api.TEFMM(K3, D3, p=8, precision=prec)
+    xyz, q = inputs.workload("c2")
+    f = api.TEFMM(K3, D3, p=p, precision=prec)
     if sur is not None:
         f.set_surrogate(sur)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     f.set_particles(xyz)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
     phi = f.evaluate(torch.from_numpy(q).cuda()).cpu().numpy()
     st = f.stats()
+    st["setup_s"] = setup
     f.close()
     return phi, st
 
 
-def test_fallback_keeps_results(sur):
-    """Rows from rejected cells come from the complex images: with the default budget
-    the surrogate answers only validated rows, and the potential differs from the
-    image-table run by at most the budget's effect (identical when no cell is kept)."""
+def _gold():
+    a = np.loadtxt(os.path.join(GOLD, "expected_c2s.txt"))
+    return a[:, 0].astype(int), a[:, 1] + 1j * a[:, 2]
+
+
+def test_rotation_free_representation_is_exact():
+    """With no network, every Sigma row rebuilt from H_{m,c} of the complex images (the
+    rotation-free derivatives, the phase carried by (x + i y)^m, Helmholtz for the mixed
+    ones) equals the image tables of the recurrence: the FMM result moves by rounding only."""
+    from paper_1902_05875_amd import api
+    ex = api.Surrogate(K3, D3, 1, p=8, h_from_images=1)
     ref, st0 = _c2(None, "fp64")
-    phi, st = _c2(sur, "fp64")
+    phi, st = _c2(ex, "fp64")
     d = float(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
-    print("surrogate rows", st["surrogate_keys"], "of", st["sigma_keys"], "rel diff to image tables", d)
+    print(f"rows from H: {st['surrogate_keys']} of {st['sigma_keys']}, potential moves by {d:.2e}")
+    assert st["surrogate_keys"] == st["sigma_keys"] > 0
+    assert d < 1e-8
+    ex.close()
+
+
+def test_training_and_validation_map(sur):
+    """The network is trained by the library's own kernels (loss falls) and the map keeps
+    exactly the cells whose validated error is within the budget."""
+    r = sur.report
+    assert r["status"] == 0 and r["n_out"] == 2 * (17 * 18 // 2)  # (m, c), m + c <= 2p = 16
+    assert sur.losses[-1] < 0.01 * sur.losses[0]
+    err = sur.cell_errors()
+    assert r["cells_ok"] == int(np.sum(err <= sur.options["budget"]))
+    assert np.isclose(r["max_cell_err"], err.max())
+    o = sur.options
+    pts = np.array([[0.0, 0.0, 0.5 * (o["s_lo"] + o["s_hi"])], [0.0, 0.0, o["s_hi"] + 0.1],
+                    [o["rho_max"] + 0.1, 0.0, o["s_lo"] + 0.01]])
+    ok = sur.cell_ok(pts)
+    assert not ok[1] and not ok[2]
+
+
+def test_served_rows_keep_the_budget(sur):
+    """The rows of validated cells (levels above the leaves) come from the network, the rest
+    from the complex images: the mixed mode at p = 8 stays within 1e-4 of the oracle, and it
+    moves by no more than the served rows' share of the budget (identical if none)."""
+    idx, gold = _gold()
+    ref, st0 = _c2(None, "fp32")
+    phi, st = _c2(sur, "fp32")
+    d = float(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
+    print(f"cells ok {sur.report['cells_ok']}/{sur.report['cells_total']}; rows from the network "
+          f"{st['surrogate_keys']} of {st['sigma_keys']}; potential moves by {d:.2e}")
     assert st["sigma_keys"] == st0["sigma_keys"] > 0
+    if sur.report["cells_ok"] == 0:
+        assert st["surrogate_keys"] == 0
     if st["surrogate_keys"] == 0:
         assert np.array_equal(phi, ref)
-    else:
-        assert d < 1e-4
+    check("C2 N=200k fp32 p=8 with the surrogate", phi[idx], gold, 1e-4)
+    assert d < 1e-4
+
+
+def test_all_rows_from_the_network(sur):
+    """Every Sigma row above the leaf level from the network, the budget switched off: what
+    the network's accuracy costs in the potential (measured, reported; bounded only loosely:
+    it is the reason the validation map keeps the cells it keeps)."""
+    from paper_1902_05875_amd import api
+    all_in = api.Surrogate(K3, D3, 1, p=8, budget=1e30)
+    ref, _ = _c2(None, "fp32")
+    phi, st = _c2(all_in, "fp32")
+    d = float(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
+    print(f"all {st['surrogate_keys']} rows above the leaf level from the network: potential moves by {d:.2e}")
+    assert st["surrogate_keys"] > 0 and d < 1e-2
+    all_in.close()
 
 
 def test_gain_is_measured(sur):
-    """What the network gains: table-generation time with every Sigma row from the
-    network (budget switched off) against the image tables, and the accuracy it
-    costs.  Reported, not asserted: the measured answer is that the rows are
-    cheaper to produce but far outside the accuracy budget."""
-    from paper_1902_05875_amd import api
-    import time
-    all_in = api.Surrogate(K3, D3, 1, p=8, n_train=32768, epochs=20, batch=512, budget=1e30)
-    ref, st0 = _c2(None, "fp32")
-    phi, st = _c2(all_in, "fp32")
-    d = float(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
-    print(f"tables: images {st0['t_setup_tables_ms']:.2f} ms, network for all {st['surrogate_keys']} Sigma rows "
-          f"{st['t_setup_tables_ms']:.2f} ms; potential changes by {d:.2e} (budget 1e-4)")
-    assert st["surrogate_keys"] == st["sigma_keys"]
-    all_in.close()
+    """What the network gains: the set-up of the same geometry with and without it (table
+    generation with the rows it serves, whole set-up), and its training cost once per medium.
+    Measured and reported; the assertion is only that the served rows leave the result
+    within the budget (the gain itself is near zero in this design: the rows are produced by
+    the network and rebuilt, the images are still fitted for the rest)."""
+    idx, gold = _gold()
+    runs = {}
+    for name, s in (("images", None), ("surrogate", sur)):
+        for _ in range(2):  # the second of two set-ups (the first also pays the launches' loading)
+            phi, st = _c2(s, "fp32")
+        runs[name] = (phi, st)
+    (p0, s0), (p1, s1) = runs["images"], runs["surrogate"]
+    print(f"tables {s0['t_setup_tables_ms']:.2f} -> {s1['t_setup_tables_ms']:.2f} ms, set-up "
+          f"{1e3 * s0['setup_s']:.1f} -> {1e3 * s1['setup_s']:.1f} ms with {s1['surrogate_keys']} of "
+          f"{s1['sigma_keys']} Sigma rows from the network; training {sur.wall:.1f} s once per medium")
+    check("with the surrogate vs oracle", p1[idx], gold, 1e-4)
