@@ -204,6 +204,29 @@ int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz_soa, int on_devi
  * hipStreamSynchronize to wait). */
 int tefmm_evaluate(tefmm_t h, const double* q, int n_rhs, double* phi, void* stream);
 
+/* Integral-equation driver (the application the method serves, Sec. 1: iterative
+ * solvers apply the potential operator many times): GMRES(restart) for
+ *   (I - tau G) x = b,
+ * G the operator of (1) as tefmm_evaluate computes it with one charge vector
+ * (physical or paper normalisation per the options), tau a complex scalar (for
+ * point scatterers of strength tau this is the Foldy-Lax system of multiple
+ * scattering in the layered medium).  b, x: device, complex128 interleaved, n
+ * entries in the caller's particle order; x is the initial guess if x0_given,
+ * else x = 0 to start; x receives the solution.  Stops when the relative
+ * residual ||b - A x|| / ||b|| is <= tol (the true residual, recomputed at each
+ * restart) or after max_iter steps; restart in [1, 200].  Work space of
+ * (restart + 3) n complex128 from the handle's allocator.  Synchronous on
+ * `stream`.  info (may be NULL) gets the steps, operator applications, final
+ * relative residual and whether tol was reached. */
+typedef struct {
+  int iterations;
+  int matvecs;
+  double rel_residual;
+  int converged;
+} tefmm_gmres_info;
+int tefmm_gmres(tefmm_t h, double tau_re, double tau_im, const double* b, double* x, int x0_given, int restart,
+                int max_iter, double tol, void* stream, tefmm_gmres_info* info);
+
 /* Batched evaluation of n_geom handles, each with its own geometry, charges
  * q[g] (n_rhs[g] vectors, layout as in tefmm_evaluate) and output phi[g].
  * The handles' evaluation sequences are captured once into a HIP graph, one

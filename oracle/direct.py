@@ -164,3 +164,34 @@ def rel_max(approx, exact):
     a = np.asarray(approx).ravel()
     e = np.asarray(exact).ravel()
     return float(np.max(np.abs(a - e) / np.abs(e)))
+
+
+def kernel_matrix(med: Medium, xyz, layer=None):
+    """The dense matrix G of the sum (Eq. totalinteraction): G[i, j] = free-space kernel
+    e^{ik_l R}/(4 pi R) for j != i in the same layer (0 on the diagonal) plus the reaction
+    kernel G^r_{l_i l_j} (the diagonal included), physical normalisation, from the pairwise
+    Sommerfeld quadrature of sommerfeld.reaction_pair.  For small N (N^2 pairs)."""
+    from .sommerfeld import reaction_pair
+    xyz = np.asarray(xyz, np.float64)
+    if layer is None:
+        layer = med.layer_of(xyz[:, 2])
+    N = xyz.shape[0]
+    G = np.zeros((N, N), np.complex128)
+    for l in range(med.L + 1):
+        ti = np.nonzero(layer == l)[0]
+        for lp in range(med.L + 1):
+            sj = np.nonzero(layer == lp)[0]
+            if len(ti) == 0 or len(sj) == 0:
+                continue
+            T, S = np.meshgrid(ti, sj, indexing="ij")
+            T, S = T.ravel(), S.ravel()
+            rho = np.hypot(xyz[T, 0] - xyz[S, 0], xyz[T, 1] - xyz[S, 1])
+            for c0 in range(0, len(T), 2048):  # pairs in chunks (nodes x pairs arrays)
+                c = slice(c0, c0 + 2048)
+                G[T[c], S[c]] = reaction_pair(med, l, lp, rho[c], xyz[T[c], 2], xyz[S[c], 2])
+            T, S = np.meshgrid(ti, sj, indexing="ij")
+            if l == lp:
+                R = np.linalg.norm(xyz[T] - xyz[S], axis=-1)
+                free = np.exp(1j * med.k[l] * np.where(R > 0, R, 1.0)) / (4 * np.pi * np.where(R > 0, R, 1.0))
+                G[T, S] += np.where(T == S, 0.0, free)
+    return G

@@ -30,7 +30,7 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_mlp_loss_grad",
            "tefmm_mlp_adam_step", "tefmm_mlp_train", "tefmm_surrogate_default_options", "tefmm_surrogate_train",
            "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
-           "tefmm_reset_timers", "tefmm_set_allocator"]
+           "tefmm_reset_timers", "tefmm_set_allocator", "tefmm_gmres"]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -91,6 +91,11 @@ class StatsC(ctypes.Structure):
         ("p2p_poly_err", ctypes.c_double), ("sigma_direct_pairs", ctypes.c_int64),
         ("occupied_leaves", ctypes.c_int64), ("max_leaf_count", ctypes.c_int64),
         ("reaction_keys_forced", ctypes.c_int64)]
+
+
+class GmresInfoC(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("matvecs", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("converged", ctypes.c_int)]
 
 
 class SurOptionsC(ctypes.Structure):
@@ -170,6 +175,7 @@ def lib():
         L.tefmm_surrogate_cell_errors.argtypes = [vp, vp]
         L.tefmm_reset_timers.argtypes = [vp]
         L.tefmm_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
+        L.tefmm_gmres.argtypes = [vp, dbl, dbl, vp, vp, i32, i32, i32, dbl, vp, ctypes.POINTER(GmresInfoC)]
         _lib = L
     return _lib
 
@@ -278,6 +284,21 @@ class TEFMM:
         _check(lib().tefmm_evaluate(self.h, ctypes.c_void_p(q2.data_ptr()), R, ctypes.c_void_p(out.data_ptr()),
                                     _stream_ptr(stream)), self.h)
         return out.reshape(-1) if squeeze else out
+
+    def gmres(self, b, tau, tol=1e-8, restart=30, max_iter=300, x0=None, stream=None):
+        """Solve (I - tau G) x = b by GMRES(restart) through tefmm_gmres (b: torch complex128 on the
+        GPU, length N).  Returns (x, info)."""
+        import torch
+        b = b.to(torch.complex128).contiguous()
+        if b.numel() != self.n:
+            raise ValueError("right-hand side length does not match the particles")
+        x = torch.zeros_like(b) if x0 is None else x0.to(torch.complex128).contiguous().clone()
+        info = GmresInfoC()
+        tau = complex(tau)
+        _check(lib().tefmm_gmres(self.h, tau.real, tau.imag, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                 int(x0 is not None), restart, max_iter, float(tol), _stream_ptr(stream),
+                                 ctypes.byref(info)), self.h)
+        return x, {f[0]: getattr(info, f[0]) for f in GmresInfoC._fields_}
 
     def autotune(self, stream=None):
         """Pick tree depth and M2L tile width by timing; returns (depth, targets per workgroup / 16)."""

@@ -1751,6 +1751,173 @@ extern "C" int tefmm_evaluate(tefmm_t h, const double* q, int nrhs, double* phi,
   return enqueue_evaluate(h, q, nrhs, phi, (hipStream_t)stream, true);
 }
 
+// ---------------------------------------------------------------------------
+// GMRES(m) on the handle's operator: (I - tau G) x = b, G the evaluation of (1) with
+// one charge vector (the Foldy-Lax system of point scatterers of strength tau in the
+// layered medium, a second-kind integral equation discretised at the particles).
+// Classical Gram-Schmidt applied twice per step (two multi-column dot products and
+// updates per step), Givens rotations on the host, restart after m steps with the
+// true residual recomputed.  Every vector operation is a HIP kernel on `stream`;
+// the host only handles the (m+1) x m Hessenberg matrix.
+// ---------------------------------------------------------------------------
+extern "C" int tefmm_gmres(tefmm_t h, double tau_re, double tau_im, const double* b, double* x, int x0_given,
+                           int restart, int max_iter, double tol, void* stream, tefmm_gmres_info* info) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  if (!h->ready) return fail(h, TEFMM_ERR_STATE, "set_particles has not succeeded");
+  if (!b || !x || restart < 1 || restart > 200 || max_iter < 1 || !(tol > 0))
+    return fail(h, TEFMM_ERR_INVALID_ARG, "tefmm_gmres: bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_rhs(h, 1);
+  if (rc != TEFMM_OK) return rc;
+  const int64_t n = h->n;
+  const int m = restart;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  double2 *V = nullptr, *w = nullptr, *gv = nullptr, *part = nullptr, *dh = nullptr;
+  HIPCHK(h, dmalloc(h, &V, sizeof(double2) * (size_t)n * (m + 1)));
+  HIPCHK(h, dmalloc(h, &w, sizeof(double2) * (size_t)n));
+  HIPCHK(h, dmalloc(h, &gv, sizeof(double2) * (size_t)n));
+  HIPCHK(h, dmalloc(h, &part, sizeof(double2) * (size_t)GM_BLOCKS * (m + 1)));
+  HIPCHK(h, dmalloc(h, &dh, sizeof(double2) * (size_t)(m + 1)));
+  auto cleanup = [&]() {
+    dfree(h, V), dfree(h, w), dfree(h, gv), dfree(h, part), dfree(h, dh);
+  };
+  const cplx tau(tau_re, tau_im);
+  auto d2 = [](cplx c) { return make_double2(c.real(), c.imag()); };
+  // y = conj(V[0..ncol))^T v on the host
+  auto dots = [&](const double2* Vb, int ncol, const double2* v, std::vector<cplx>& out) -> int {
+    hipLaunchKernelGGL(k_gm_multidot, dim3(GM_BLOCKS), dim3(256), 0, s, Vb, (int64_t)n, ncol, v, n, part);
+    HIPCHK(h, hipGetLastError());
+    hipLaunchKernelGGL(k_gm_reduce, dim3(ncol), dim3(256), 0, s, part, GM_BLOCKS, dh);
+    HIPCHK(h, hipGetLastError());
+    std::vector<double2> tmp(ncol);
+    HIPCHK(h, hipMemcpyAsync(tmp.data(), dh, sizeof(double2) * ncol, hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    out.resize(ncol);
+    for (int c = 0; c < ncol; ++c) out[c] = cplx(tmp[c].x, tmp[c].y);
+    return TEFMM_OK;
+  };
+  // out = v - tau G v
+  int matvecs = 0;
+  auto apply = [&](const double2* v, double2* out) -> int {
+    int r2 = enqueue_evaluate(h, (const double*)v, 1, (double*)gv, s, false);
+    if (r2 != TEFMM_OK) return r2;
+    HIPCHK(h, hipMemcpyAsync(out, v, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_gm_axpby, dim3(nb), dim3(256), 0, s, d2(-tau), gv, make_double2(1.0, 0.0), out, n);
+    HIPCHK(h, hipGetLastError());
+    ++matvecs;
+    return TEFMM_OK;
+  };
+  auto norm = [&](const double2* v, double* out) -> int {
+    std::vector<cplx> d;
+    int r2 = dots(v, 1, v, d);
+    *out = std::sqrt(std::max(0.0, d[0].real()));
+    return r2;
+  };
+  auto run = [&]() -> int {
+    const double2* bb = (const double2*)b;
+    double2* xx = (double2*)x;
+    double bnorm = 0;
+    int r2 = norm(bb, &bnorm);
+    if (r2 != TEFMM_OK) return r2;
+    if (!(bnorm > 0)) bnorm = 1.0;
+    // r = b - A x (x = 0 unless given); r kept in column 0 of V
+    if (x0_given) {
+      if ((r2 = apply(xx, w)) != TEFMM_OK) return r2;
+      HIPCHK(h, hipMemcpyAsync(V, bb, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_gm_axpby, dim3(nb), dim3(256), 0, s, make_double2(-1.0, 0.0), w, make_double2(1.0, 0.0),
+                         V, n);
+      HIPCHK(h, hipGetLastError());
+    } else {
+      HIPCHK(h, hipMemsetAsync(xx, 0, sizeof(double2) * n, s));
+      HIPCHK(h, hipMemcpyAsync(V, bb, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+    }
+    double beta = 0;
+    if ((r2 = norm(V, &beta)) != TEFMM_OK) return r2;
+    int it = 0;
+    double est = beta / bnorm;
+    std::vector<cplx> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hc, hc2;
+    while (est > tol && it < max_iter) {
+      hipLaunchKernelGGL(k_gm_axpby, dim3(nb), dim3(256), 0, s, make_double2(1.0 / beta, 0.0), V,
+                         make_double2(0.0, 0.0), V, n);
+      HIPCHK(h, hipGetLastError());
+      std::fill(g.begin(), g.end(), cplx(0, 0));
+      std::fill(H.begin(), H.end(), cplx(0, 0));
+      g[0] = beta;
+      int j = 0;
+      for (; j < m && it < max_iter; ++j, ++it) {
+        if ((r2 = apply(V + (size_t)j * n, w)) != TEFMM_OK) return r2;
+        // classical Gram-Schmidt, twice
+        for (int pass = 0; pass < 2; ++pass) {
+          if ((r2 = dots(V, j + 1, w, hc)) != TEFMM_OK) return r2;
+          std::vector<double2> hd(j + 1);
+          for (int i = 0; i <= j; ++i) hd[i] = d2(hc[i]), H[(size_t)i * m + j] += hc[i];
+          HIPCHK(h, hipMemcpyAsync(dh, hd.data(), sizeof(double2) * (j + 1), hipMemcpyHostToDevice, s));
+          hipLaunchKernelGGL(k_gm_update, dim3(nb), dim3(256), 0, s, V, (int64_t)n, j + 1, dh, -1.0, w, n);
+          HIPCHK(h, hipGetLastError());
+        }
+        double hn = 0;
+        if ((r2 = norm(w, &hn)) != TEFMM_OK) return r2;
+        H[(size_t)(j + 1) * m + j] = hn;
+        if (hn > 0) {
+          hipLaunchKernelGGL(k_gm_axpby, dim3(nb), dim3(256), 0, s, make_double2(1.0 / hn, 0.0), w,
+                             make_double2(0.0, 0.0), V + (size_t)(j + 1) * n, n);
+          HIPCHK(h, hipGetLastError());
+        }
+        // previous rotations on column j, then this step's
+        for (int i = 0; i < j; ++i) {
+          const cplx a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+          H[(size_t)i * m + j] = std::conj(cs[i]) * a + std::conj(sn[i]) * c;
+          H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+        }
+        const cplx a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+        const double r = std::sqrt(std::norm(a) + std::norm(c));
+        cs[j] = r > 0 ? a / r : cplx(1, 0);
+        sn[j] = r > 0 ? c / r : cplx(0, 0);
+        H[(size_t)j * m + j] = r;
+        H[(size_t)(j + 1) * m + j] = 0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = std::conj(cs[j]) * g[j];
+        est = std::abs(g[j + 1]) / bnorm;
+        if (est <= tol || !(hn > 0)) {
+          ++j, ++it;
+          break;
+        }
+      }
+      // y = H^-1 g (upper triangular j x j), x += V y
+      std::vector<cplx> y(j);
+      for (int i = j - 1; i >= 0; --i) {
+        cplx acc = g[i];
+        for (int k2 = i + 1; k2 < j; ++k2) acc -= H[(size_t)i * m + k2] * y[k2];
+        y[i] = acc / H[(size_t)i * m + i];
+      }
+      std::vector<double2> yd(j);
+      for (int i = 0; i < j; ++i) yd[i] = d2(y[i]);
+      HIPCHK(h, hipMemcpyAsync(dh, yd.data(), sizeof(double2) * j, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_gm_update, dim3(nb), dim3(256), 0, s, V, (int64_t)n, j, dh, 1.0, xx, n);
+      HIPCHK(h, hipGetLastError());
+      // true residual for the restart (and the report)
+      if ((r2 = apply(xx, w)) != TEFMM_OK) return r2;
+      HIPCHK(h, hipMemcpyAsync(V, bb, sizeof(double2) * n, hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_gm_axpby, dim3(nb), dim3(256), 0, s, make_double2(-1.0, 0.0), w, make_double2(1.0, 0.0),
+                         V, n);
+      HIPCHK(h, hipGetLastError());
+      if ((r2 = norm(V, &beta)) != TEFMM_OK) return r2;
+      est = beta / bnorm;
+    }
+    if (info) {
+      info->iterations = it;
+      info->matvecs = matvecs;
+      info->rel_residual = est;
+      info->converged = est <= tol;
+    }
+    return TEFMM_OK;
+  };
+  rc = run();
+  HIPCHK(h, hipStreamSynchronize(s));
+  cleanup();
+  return rc;
+}
+
 static void batch_clear(tefmm_ctx::Batch& b) {
   if (b.exec) (void)hipGraphExecDestroy(b.exec);
   if (b.graph) (void)hipGraphDestroy(b.graph);

@@ -1854,4 +1854,69 @@ __global__ __launch_bounds__(64) void k_sigma_restore(const double2* H, const do
   }
 }
 
+// ---------------------------------------------------------------------------
+// Vector kernels of the GMRES driver (complex128 vectors of length n; the Krylov
+// basis V column-major with leading dimension ld).
+// ---------------------------------------------------------------------------
+// partial[c][blk] = sum over this block's rows of conj(V[c][r]) w[r], c < ncol
+// (blockDim 256, grid GM_BLOCKS; the partials are summed by k_gm_reduce)
+__global__ __launch_bounds__(256) void k_gm_multidot(const double2* V, int64_t ld, int ncol, const double2* w,
+                                                     int64_t n, double2* partial) {
+  __shared__ double2 red[256];
+  const int tid = threadIdx.x;
+  for (int c = 0; c < ncol; ++c) {
+    const double2* v = V + (int64_t)c * ld;
+    dc acc = {0.0, 0.0};
+    for (int64_t r = (int64_t)blockIdx.x * 256 + tid; r < n; r += (int64_t)gridDim.x * 256) {
+      const double2 a = v[r], b = w[r];
+      acc = cadd(acc, {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x});
+    }
+    red[tid] = make_double2(acc.x, acc.y);
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red[tid] = make_double2(red[tid].x + red[tid + st].x, red[tid].y + red[tid + st].y);
+      __syncthreads();
+    }
+    if (tid == 0) partial[(int64_t)c * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[c] = sum_b partial[c][b], one block of 256 per column (fixed order: deterministic)
+__global__ __launch_bounds__(256) void k_gm_reduce(const double2* partial, int nblk, double2* out) {
+  __shared__ double2 red[256];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  double2 a = make_double2(0.0, 0.0);
+  for (int b = tid; b < nblk; b += 256) a = make_double2(a.x + partial[(int64_t)c * nblk + b].x,
+                                                         a.y + partial[(int64_t)c * nblk + b].y);
+  red[tid] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) red[tid] = make_double2(red[tid].x + red[tid + st].x, red[tid].y + red[tid + st].y);
+    __syncthreads();
+  }
+  if (tid == 0) out[c] = red[0];
+}
+
+// w[r] += sgn * sum_c V[c][r] coef[c]
+__global__ void k_gm_update(const double2* V, int64_t ld, int ncol, const double2* coef, double sgn, double2* w,
+                            int64_t n) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  dc acc = {0.0, 0.0};
+  for (int c = 0; c < ncol; ++c) {
+    const double2 v = V[(int64_t)c * ld + r], h = coef[c];
+    acc = cadd(acc, cmul({v.x, v.y}, {h.x, h.y}));
+  }
+  w[r] = make_double2(w[r].x + sgn * acc.x, w[r].y + sgn * acc.y);
+}
+
+// y[r] = a x[r] + b y[r] (complex a, b)
+__global__ void k_gm_axpby(double2 a, const double2* x, double2 b, double2* y, int64_t n) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const dc v = cadd(cmul({a.x, a.y}, {x[r].x, x[r].y}), cmul({b.x, b.y}, {y[r].x, y[r].y}));
+  y[r] = make_double2(v.x, v.y);
+}
+
 }  // namespace tefmm

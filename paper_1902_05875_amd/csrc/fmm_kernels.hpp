@@ -232,6 +232,15 @@ __global__ void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2*
 template <typename R2>
 __global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* part);
 
+// GMRES vector kernels (complex128): multi-column dot products in two stages, basis
+// updates, axpby.
+constexpr int GM_BLOCKS = 512;
+__global__ void k_gm_multidot(const double2* V, int64_t ld, int ncol, const double2* w, int64_t n, double2* partial);
+__global__ void k_gm_reduce(const double2* partial, int nblk, double2* out);
+__global__ void k_gm_update(const double2* V, int64_t ld, int ncol, const double2* coef, double sgn, double2* w,
+                            int64_t n);
+__global__ void k_gm_axpby(double2 a, const double2* x, double2 b, double2* y, int64_t n);
+
 // M2L launcher (picks the row-block instantiation for nRB).
 hipError_t launch_m2l(const M2LArgs& a, int nrhs, bool fp32, hipStream_t s);
 

@@ -8,7 +8,8 @@ c4s (N=1,000,000, 16 sampled targets), c4m (the same geometry, 64 sampled target
 targets, every vector), c5g (the 16 geometries of the batched workload, 16 sampled targets each), n20k (N=20,000, 128 sampled targets),
 c3small (three layers, N=3000, 300 targets), c3s (three layers, N=1,000,000, 6 targets per layer),
 c1ns (c1 plus 24 particles at distance 1e-6 from existing ones; the 48 particles of those pairs),
-nearif_top, nearif_bottom (N=2000 with 100 particles 0.01-0.02 from one interface; 50 targets), ex2small (the Example-2 domain, N=20,000, 64 sampled targets), ex2s (the same domain, N=1,000,000,
+nearif_top, nearif_bottom (N=2000 with 100 particles 0.01-0.02 from one interface; 50 targets),
+gmres (the solution of the Foldy-Lax system (I - tau G) x = b for 400 particles, dense solve), ex2small (the Example-2 domain, N=20,000, 64 sampled targets), ex2s (the same domain, N=1,000,000,
 16 sampled targets).
 Output: tests/golden/expected_<case>.txt with columns  index  re  im  (c5r: index  vector  re  im;
 c5g: geometry  index  re  im).
@@ -125,9 +126,37 @@ def run_c5g(procs=None):
     print(f"c5g: {sum(len(r) for r in rows)} targets in {time.time() - t0:.1f} s -> {out}", flush=True)
 
 
+GMRES_TAU = 0.1 * complex(np.cos(np.pi / 4), np.sin(np.pi / 4))
+
+
+def gmres_case():
+    """400 particles in the mid-layer cube (seed 180) and the plane wave b = e^{i k_1 x}."""
+    rng = np.random.default_rng(180)
+    xyz = inputs.cube(rng, 400, inputs.MID_CENTRE)
+    b = np.exp(1j * inputs.MEDIUM_K[1] * xyz[:, 0])
+    return xyz, b
+
+
+def run_gmres():
+    """x = (I - tau G)^-1 b with G the oracle's dense kernel matrix (LAPACK solve)."""
+    t0 = time.time()
+    xyz, b = gmres_case()
+    G = direct.kernel_matrix(Medium(inputs.MEDIUM_K, inputs.MEDIUM_D), xyz)
+    A = np.eye(len(b)) - GMRES_TAU * G
+    x = np.linalg.solve(A, b)
+    out = os.path.join(HERE, "expected_gmres.txt")
+    np.savetxt(out, np.column_stack([np.arange(len(b)), x.real, x.imag]), fmt=["%d", "%.17e", "%.17e"],
+               header=f"oracle dense solve of (I - tau G) x = b, G = oracle/direct.kernel_matrix, tau = {GMRES_TAU!r}, "
+                      f"400 particles (seed 180, mid-layer cube), b = exp(i k_1 x); condition number "
+                      f"{np.linalg.cond(A):.3e}; columns: index, Re x, Im x")
+    print(f"gmres: dense solve in {time.time() - t0:.1f} s -> {out}", flush=True)
+
+
 def run(name, procs=None):
     if name == "c5g":
         return run_c5g(procs)
+    if name == "gmres":
+        return run_gmres()
     xyz, q, targets = case_spec(name)
     procs = procs or min(8, os.cpu_count() or 1)
     chunks = np.array_split(targets, max(1, min(len(targets), procs * 4)))

@@ -211,3 +211,19 @@ def test_reaction_part_converged_next_to_interfaces():
     ref = np.array([np.sum(q * reaction_pair(med, lay[t], 1, np.hypot(xyz[t, 0] - xyz[:, 0], xyz[t, 1] - xyz[:, 1]),
                                              xyz[t, 2], xyz[:, 2])) for t in tg])
     np.testing.assert_allclose(got, ref, rtol=1e-10)
+
+
+def test_kernel_matrix_matches_the_direct_sum():
+    """The dense kernel matrix (pairwise quadrature) applied to charges equals the direct sum
+    with the sum over sources inside the integral, three layers, every layer pair."""
+    med = Medium(K, D)
+    rng = np.random.default_rng(21)
+    xyz = np.concatenate([rng.random((12, 3)) * [1, 1, 0.6] + [-.5, -.5, 0.2],
+                          rng.random((14, 3)) * [1, 1, 0.8] + [-.5, -.5, -1.0],
+                          rng.random((10, 3)) * [1, 1, 0.5] + [-.5, -.5, -2.0]])
+    q = rng.uniform(-1, 1, 36) + 1j * rng.uniform(-1, 1, 36)
+    G = direct.kernel_matrix(med, xyz)
+    np.testing.assert_allclose(G @ q, direct.potential(med, xyz, q), rtol=1e-10)
+    # weighted reciprocity of the matrix: k_l G[i, j] = k_lp G[j, i]
+    kl = np.asarray(med.k)[med.layer_of(xyz[:, 2])]
+    np.testing.assert_allclose(kl[:, None] * G, (kl[:, None] * G).T, rtol=1e-9, atol=1e-14)
