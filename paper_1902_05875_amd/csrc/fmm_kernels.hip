@@ -1143,6 +1143,55 @@ __device__ __forceinline__ float sym_r2(float tx, float ty, float tz, const floa
   return __int_as_float(max(__float_as_int(fmaf(dz, dz, fmaf(dy, dy, dx * dx))), __float_as_int(rns2)));
 }
 
+// Lane exchanges inside rows of 16 lanes through the DPP crossbar (no LDS round
+// trip, usually folded into the add that uses them): MIRROR16 takes lane 15 - l of
+// the row, MIRROR8 lane 7 - l of the eight, XOR2 and XOR1 the quad permutations
+// (2, 3, 0, 1) and (1, 0, 3, 2).  Each pairs every lane with one whose bit 3, 2, 1
+// or 0 respectively differs and whose higher bits agree, which is all a
+// butterfly reduction needs.
+enum : int { DPP_MIRROR16 = 0x140, DPP_MIRROR8 = 0x141, DPP_XOR2 = 0x4E, DPP_XOR1 = 0xB1 };
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// The last four stages of the transposing butterfly over 64 lanes (masks 8, 4,
+// 2, 1) for the four values left, c0 .. c3: after the stages with masks 8 and 4
+// lane l keeps value ((l >> 2) & 3), summed over its group of 16 lanes, and the
+// two quad stages complete the sum.  The values come in as separate registers
+// (pinned), so that the selects stay selects of values and do not turn into an
+// indexed read of a vector.
+template <typename R>
+__device__ __forceinline__ R butterfly_tail(R c0, R c1, R c2, R c3, int lane) {
+  asm volatile("" : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3));
+  const bool h8 = (lane & 8) != 0, h4 = (lane & 4) != 0;
+  R s0 = h8 ? c0 : c2, s1 = h8 ? c1 : c3;
+  R k0 = h8 ? c2 : c0, k1 = h8 ? c3 : c1;
+  if constexpr (sizeof(R) == 4) {
+    k0 += dpp_f32<DPP_MIRROR16>(s0), k1 += dpp_f32<DPP_MIRROR16>(s1);
+  } else {
+    k0 += dpp_f64<DPP_MIRROR16>(s0), k1 += dpp_f64<DPP_MIRROR16>(s1);
+  }
+  const R send = h4 ? k0 : k1, keep = h4 ? k1 : k0;
+  R tot;
+  if constexpr (sizeof(R) == 4) {
+    tot = keep + dpp_f32<DPP_MIRROR8>(send);
+    tot += dpp_f32<DPP_XOR2>(tot);
+    tot += dpp_f32<DPP_XOR1>(tot);
+  } else {
+    tot = keep + dpp_f64<DPP_MIRROR8>(send);
+    tot += dpp_f64<DPP_XOR2>(tot);
+    tot += dpp_f64<DPP_XOR1>(tot);
+  }
+  return tot;
+}
+
 // Eight staged sources [t, t + 8) against this lane's T targets.  SYM: also the
 // eight source-side sums over the wave's 64 T targets, written to
 // psw[2 (t + u) + c] (c = 0 real, 1 imaginary part).  Every pair is applied
@@ -1151,9 +1200,10 @@ __device__ __forceinline__ float sym_r2(float tx, float ty, float tz, const floa
 // weight 0: its clamped value would be of the order of the inverse threshold, and
 // taking it back later would cancel against everything else in the FP32 sum.
 // Pairs closer than the threshold rns2 (rare: two particles closer than 5% of
-// the leaf side, whose FP32 coordinate differences have lost digits) are marked
-// in nl (a bit mask per step and lane) and, after the eight sources, taken one
-// by one: the value used is replaced by the one from FP64 differences, its
+// the leaf side, whose FP32 coordinate differences have lost digits) are found
+// by one wave-wide test of the least squared distance over the eight sources;
+// only then the lanes that met one redo their tests and take those pairs one by
+// one: the value used is replaced by the one from FP64 differences, its
 // source-side part added to dps[2 (t + u) + c].
 template <int T, bool SYM, bool POLY>
 __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T], const float (&ty)[T],
@@ -1161,18 +1211,23 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
                                          const bool (&act)[T], const float4* s4, const float* sqi,
                                          const int* sidx, float rns2, float eps2, double kap2,
                                          const PassArgs& a, float (&accr)[T], float (&acci)[T], float* psw,
-                                         float* dps, int* nl, const NearPoly& np) {
+                                         float* dps, const NearPoly& np) {
   const int lane = threadIdx.x & 63;
   // a vector value, not an array: the butterfly's selects stay selects of values
   typedef float f16v __attribute__((ext_vector_type(16)));
   f16v c;
-  int steps = 0;  // steps with marked pairs
-  // near test on the bit patterns: r2 < rns2 (in the own pass the pair of a particle with
-  // itself, found by its index, is moved out of the test's range)
-  const unsigned near_lim = (unsigned)__float_as_int(rns2);
+  // the squared distance a pair is tested with: SYM, the one used; the own pass, the
+  // plain one (the clamp only ever raises it to the threshold itself), with the pair
+  // of a particle with itself moved out of the test's range
+  auto tested = [&](int k, const float4& sp, int sj) -> float {
+    if (SYM) return sym_r2<true>(tx[k], ty[k], tz[k], sp, eps2, rns2);
+    const float dx = tx[k] - sp.x, dy = ty[k] - sp.y, dz = tz[k] - sp.z;
+    // a distinct particle at FP32 distance 0 is a near pair like any other
+    return sj == tbase + 64 * k ? 3.0e38f : fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  };
+  float mn = 3.0e38f;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {  // two sources at a time
-    float r2[2][T];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const float4 sp = s4[t + 2 * v + u];
@@ -1181,18 +1236,10 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
       float cr = 0.0f, ci = 0.0f;
 #pragma unroll
       for (int k = 0; k < T; ++k) {
-        // SYM: r2 as used; otherwise the clamped value (the test below needs the
-        // plain one, and the clamp only ever raises it to the threshold itself)
-        r2[u][k] = SYM ? sym_r2<true>(tx[k], ty[k], tz[k], sp, eps2, rns2) : 0.0f;
-        float used = r2[u][k];
-        bool self = false;
-        if (!SYM) {
-          const float dx = tx[k] - sp.x, dy = ty[k] - sp.y, dz = tz[k] - sp.z;
-          self = sj == tbase + 64 * k;
-          // a distinct particle at FP32 distance 0 is a near pair like any other
-          r2[u][k] = self ? 3.0e38f : fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-          used = __int_as_float(max(__float_as_int(r2[u][k]), __float_as_int(rns2)));
-        }
+        const float r2 = tested(k, sp, sj);
+        mn = fminf(mn, r2);
+        const bool self = !SYM && sj == tbase + 64 * k;
+        const float used = SYM ? r2 : __int_as_float(max(__float_as_int(r2), __float_as_int(rns2)));
         float er, ei;
         pair_value<POLY>(used, np, &er, &ei);
         if (self) er = 0.0f, ei = 0.0f;
@@ -1212,31 +1259,8 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
 #pragma unroll
       for (int k = 0; k < T; ++k) asm volatile("" : "+v"(accr[k]), "+v"(acci[k]));
     }
-    bool anynear;
-    if (SYM) {
-      float mn = r2[0][0];
-#pragma unroll
-      for (int k = 0; k < T; ++k) mn = fminf(mn, fminf(r2[0][k], r2[1][k]));
-      anynear = mn < rns2;
-    } else {
-      unsigned mn = 0xFFFFFFFFu;
-#pragma unroll
-      for (int k = 0; k < T; ++k)
-        mn = min(mn, min((unsigned)__float_as_int(r2[0][k]), (unsigned)__float_as_int(r2[1][k])));
-      anynear = mn < near_lim;
-    }
-    if (__any(anynear)) {
-      unsigned m = 0;  // bit u T + k: pair (source 2 v + u, target slot k)
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int k = 0; k < T; ++k) {
-          const bool nr = SYM ? r2[u][k] < rns2 : (unsigned)__float_as_int(r2[u][k]) < near_lim;
-          m |= (act[k] && nr) ? 1u << (u * T + k) : 0u;
-        }
-      nl[64 * v + lane] = (int)m;
-      steps |= 1 << v;
-    }
+    // the least distance taken at each step (else every distance stays alive to the end)
+    asm volatile("" : "+v"(mn));
     // one step at a time: interleaving the steps would only raise register pressure
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -1244,9 +1268,8 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
     // transposing butterfly over the 16 values: after the stage with mask m a
     // lane holds the half of its values selected by (lane & m), summed with the
     // partner's same half.  Masks 32 and 16 by the lane-swap instructions (value
-    // k to the low half of the lanes, k + H to the high half), masks 8 and 4 by
-    // a select and a shuffle; then lane l holds value (l >> 2) summed over 16
-    // lanes, and two plain steps (masks 2, 1) complete the sum over 64 lanes.
+    // k to the low half of the lanes, k + H to the high half), the rest through
+    // the DPP crossbar; lane l ends with value (l >> 2) summed over the 64 lanes.
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[k]), __float_as_uint(c[k + 8]), false, false);
@@ -1257,57 +1280,47 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
       const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(c[k]), __float_as_uint(c[k + 4]), false, false);
       c[k] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
     }
-#pragma unroll
-    for (int st = 2; st < 4; ++st) {
-      const int m = 32 >> st, H = 8 >> st;
-      const bool hi = (lane & m) != 0;
-#pragma unroll
-      for (int k = 0; k < H; ++k) {
-        const float send = hi ? c[k] : c[k + H];
-        const float keep = hi ? c[k + H] : c[k];
-        c[k] = keep + __shfl_xor(send, m);
-      }
-    }
-    float tot = c[0] + __shfl_xor(c[0], 2);
-    tot += __shfl_xor(tot, 1);
+    const float tot = butterfly_tail<float>(c[0], c[1], c[2], c[3], lane);
     if (!(lane & 3)) psw[2 * t + (lane >> 2)] = tot;
   }
-  // the marked pairs, step by step, lane by lane, pair by pair (a fixed order)
-  for (int v = 0; v < 4; ++v) {
-    if (!((steps >> v) & 1)) continue;
-    const unsigned mine = (unsigned)nl[64 * v + lane];
-    unsigned long long bal = __ballot(mine != 0);
-    while (bal) {
-      const int l = __builtin_ctzll(bal);
-      bal &= bal - 1;
-      if (lane != l) continue;
+  if (!__any(mn < rns2)) return;
+  // the near pairs, lane by lane, pair by pair (a fixed order)
+  unsigned mine = 0;  // bit uu T + k: pair (source uu, target slot k)
+#pragma unroll 1
+  for (int uu = 0; uu < 8; ++uu)
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+    for (int k = 0; k < T; ++k)
+      mine |= (act[k] && tested(k, s4[t + uu], SYM ? 0 : sidx[t + uu]) < rns2) ? 1u << (uu * T + k) : 0u;
+  unsigned long long bal = __ballot(mine != 0);
+  while (bal) {
+    const int l = __builtin_ctzll(bal);
+    bal &= bal - 1;
+    if (lane != l) continue;
+#pragma unroll 1
+    for (int uu = 0; uu < 8; ++uu)
 #pragma unroll
-        for (int k = 0; k < T; ++k) {
-          if (!((mine >> (u * T + k)) & 1)) continue;
-          const int uu = 2 * v + u;
-          const int64_t j = sidx[t + uu], i = tbase + 64 * k;
-          // the digits lost are those of the coordinate differences: those in FP64,
-          // the rest of the pair in FP32 as above
-          float er = 0.0f, ei = 0.0f;
-          if (j >= 0 && j != i) {
-            const double ex = a.xs[i] - a.xs[j], ey = a.xs[a.n + i] - a.xs[a.n + j],
-                         ez = a.xs[2 * a.n + i] - a.xs[2 * a.n + j];
-            pair_value<POLY>((float)((ex * ex + ey * ey + ez * ez) * kap2), np, &er, &ei);
-          }
-          float ur, ui;  // the value used above
-          pair_value<POLY>(sym_r2<SYM>(tx[k], ty[k], tz[k], s4[t + uu], eps2, rns2), np, &ur, &ui);
-          const float der = er - ur, dei = ei - ui;
-          const float qr = s4[t + uu].w, qi = sqi[t + uu];
-          accr[k] = fmaf(qr, der, fmaf(-qi, dei, accr[k]));
-          acci[k] = fmaf(qr, dei, fmaf(qi, der, acci[k]));
-          if (SYM) {
-            dps[2 * (t + uu)] += fmaf(qri[k], der, -qii[k] * dei);
-            dps[2 * (t + uu) + 1] += fmaf(qri[k], dei, qii[k] * der);
-          }
+      for (int k = 0; k < T; ++k) {
+        if (!((mine >> (uu * T + k)) & 1)) continue;
+        const int64_t j = sidx[t + uu], i = tbase + 64 * k;
+        // the digits lost are those of the coordinate differences: those in FP64,
+        // the rest of the pair in FP32 as above
+        float er = 0.0f, ei = 0.0f;
+        if (j >= 0 && j != i) {
+          const double ex = a.xs[i] - a.xs[j], ey = a.xs[a.n + i] - a.xs[a.n + j],
+                       ez = a.xs[2 * a.n + i] - a.xs[2 * a.n + j];
+          pair_value<POLY>((float)((ex * ex + ey * ey + ez * ez) * kap2), np, &er, &ei);
         }
-    }
+        float ur, ui;  // the value used above
+        pair_value<POLY>(sym_r2<SYM>(tx[k], ty[k], tz[k], s4[t + uu], eps2, rns2), np, &ur, &ui);
+        const float der = er - ur, dei = ei - ui;
+        const float qr = s4[t + uu].w, qi = sqi[t + uu];
+        accr[k] = fmaf(qr, der, fmaf(-qi, dei, accr[k]));
+        acci[k] = fmaf(qr, dei, fmaf(qi, der, acci[k]));
+        if (SYM) {
+          dps[2 * (t + uu)] += fmaf(qri[k], der, -qii[k] * dei);
+          dps[2 * (t + uu) + 1] += fmaf(qri[k], dei, qii[k] * der);
+        }
+      }
   }
 }
 
@@ -1389,19 +1402,7 @@ __device__ __forceinline__ void p2p_sym8_f64(int t, const double (&tx)[T], const
       swap16_f64(x, y);
       c[kk] = x + y;
     }
-#pragma unroll
-    for (int st = 2; st < 4; ++st) {
-      const int m = 32 >> st, H = 8 >> st;
-      const bool hi = (lane & m) != 0;
-#pragma unroll
-      for (int kk = 0; kk < H; ++kk) {
-        const double send = hi ? c[kk] : c[kk + H];
-        const double keep = hi ? c[kk + H] : c[kk];
-        c[kk] = keep + __shfl_xor(send, m);
-      }
-    }
-    double tot = c[0] + __shfl_xor(c[0], 2);
-    tot += __shfl_xor(tot, 1);
+    const double tot = butterfly_tail<double>(c[0], c[1], c[2], c[3], lane);
     if (!(lane & 3)) psw[2 * t + (lane >> 2)] = tot;
   }
 }
@@ -1426,7 +1427,6 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G
   // near-pair masks of the current eight sources (per step and lane)
   __shared__ int sidx[F32 ? NW : 1][F32 ? SC : 1];
   __shared__ float dps[F32 ? NW : 1][F32 ? 2 * SC : 1];
-  __shared__ int nl[F32 ? NW : 1][F32 ? 4 * 64 : 1];
   __shared__ R2 tacc[NW > 1 ? NW : 1][NW > 1 ? TP : 1];
   const int r = blockIdx.y, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int nb = a.nbox_dim;
@@ -1437,6 +1437,11 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G
   // FP64: k r <= pi/4 over the 3 x 3 x 3 leaf block (its longest pair: 2 sqrt(3) h)
   const bool small = a.k * 3.4641016151377546 * a.h <= 0.78539816339744831;
   const double2* q = a.q + (int64_t)r * a.n;
+  // the quadratics' middle coefficients in vector registers for the whole kernel: a
+  // multiply-add takes at most one scalar operand, and left in scalar registers they
+  // are copied over for every pair
+  NearPoly npv = np;
+  if constexpr (F32 && POLY) asm volatile("" : "+v"(npv.c1), "+v"(npv.s1));
   // G workgroups per leaf, the one with index `half` taking the target passes half,
   // half + G, half + 2 G, ... (more, shorter workgroups: less of a tail when the last ones
   // run); each keeps its own source-side sums, part[G slot + half]
@@ -1508,12 +1513,12 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G
             if (rg == 0) {
               for (int t = 0; t < mu; t += 8)
                 p2p_sym8<TT, false, POLY>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2,
-                                          eps2, kap * kap, a, accr, acci, psw[w], dps[w], nl[w], np);
+                                          eps2, kap * kap, a, accr, acci, psw[w], dps[w], npv);
               continue;
             }
             for (int t = 0; t < mu; t += 8)
               p2p_sym8<TT, true, POLY>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2,
-                                       kap * kap, a, accr, acci, psw[w], dps[w], nl[w], np);
+                                       kap * kap, a, accr, acci, psw[w], dps[w], npv);
           } else {
             if (rg == 0) {
               for (int t = 0; t < mu; t += 8) {
