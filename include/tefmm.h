@@ -108,7 +108,15 @@ typedef struct {
                          3 x 3 x 3 block (k r is small there), used where the fit is within 3e-7 of
                          cos(k r) and sin(k r) (see p2p_poly_err; else, and with -1, the hardware
                          sine and cosine) */
+  int sigma_tables;   /* translation tables of the Sigma families (the same-layer reaction terms
+                         that depend on z + z'): TEFMM_SIGMA_IMAGES from the complex images
+                         (Sec. 3.3); TEFMM_SIGMA_SOMMERFELD from the Sommerfeld integrals of the
+                         rotation-free derivatives on the deformed contour of Sec. 4.2 (the
+                         integrals of Eq. symmetricdetable, no fit), rebuilt exactly into the
+                         Cartesian rows.  Rows answered by an attached surrogate stay the
+                         surrogate's; the near-interface pairs evaluated directly keep the images. */
 } tefmm_options;
+enum { TEFMM_SIGMA_IMAGES = 0, TEFMM_SIGMA_SOMMERFELD = 1 };
 
 /* Timings (ms, measured with HIP events; averages over the evaluations since
  * the last tefmm_reset_timers, at most the last 64) and counters.  The far
@@ -151,6 +159,9 @@ typedef struct {
                                    that ratio above 0.87 (converging slowly or not at all:
                                    boxes reaching close to an interface, or a layer thin
                                    against the boxes); zero in the usual configurations */
+  int64_t sigma_quad_nodes; /* TEFMM_SIGMA_SOMMERFELD: contour nodes of the largest Sigma
+                               quadrature of the geometry (0 otherwise) */
+  int64_t sigma_quad_keys;  /* TEFMM_SIGMA_SOMMERFELD: Sigma rows produced from the integrals */
 } tefmm_stats;
 
 /* Fill an options struct with the defaults (p = 8, depth auto, max_leaf 64,
@@ -296,6 +307,27 @@ int tefmm_dcim_family(const tefmm_medium* medium, const tefmm_options* opt, int 
 int tefmm_dcim_cross(const tefmm_medium* medium, const tefmm_options* opt, int l, int lp, int a, double zs,
                      int k3p, double z_lo, double z_hi, int cap, int* m, double* amp, double* depth,
                      double* fit_err);
+
+/* Rotation-free derivatives of the Sigma-family kernel of layer `layer`
+ * (Sec. 4.2; the same-layer reaction terms with sigma^{uu} and sigma^{dd},
+ * which depend on rho and S = z + z'):
+ *   H_{m,c}(rho, S) = (2 d_w)^m d_S^c K,  w = rho^2,  m + c <= 2p (p of the handle),
+ * K = 4 pi G in the physical normalisation (the form sum_j A_j e^{ikR_j}/R_j of the
+ * images), stored at index (m + c)(m + c + 1)/2 + m.  With u = x + i y the Cartesian
+ * derivatives follow as (d_x + i d_y)^m d_S^c K = u^m H_{m,c}.
+ * method TEFMM_SIGMA_IMAGES: from the complex images of the layer's families, fitted
+ * for the height range min(S)/2 .. max(S)/2 (Sec. 3.3);
+ * TEFMM_SIGMA_SOMMERFELD: from the Sommerfeld integrals on the deformed contour of
+ * Sec. 4.2 (the integrals of Eq. symmetricdetable in rotation-free form; the
+ * k_rho -> infinity limit of each density is the image at the mirror point, added
+ * exactly).  rho, S: host arrays of n >= 1 values, S with both mirror distances
+ * S - 2 d_l and 2 d_{l-1} - S positive where the interface exists; out: host array
+ * of n (2p+1)(2p+2)/2 complex values (re, im interleaved), written on success.
+ * Needs no particles; synchronous on `stream`.  Errors: TEFMM_ERR_INVALID_ARG (bad
+ * layer, method, size or a point outside the layer), TEFMM_ERR_UNSUPPORTED (layer
+ * without interfaces, or 2p above 32), TEFMM_ERR_DCIM_FIT, TEFMM_ERR_HIP. */
+int tefmm_sigma_derivatives(tefmm_t h, int layer, int method, int64_t n, const double* rho, const double* S,
+                            double* out, void* stream);
 
 /* Scaled Taylor coefficients h^{|g|} D^g f / g! of f = exp(i k R)/R at n
  * points (x, y, zeta) with complex zeta (device arrays x, y: n doubles;

@@ -258,9 +258,10 @@ def evaluate_local(beta, d, p):
 
 # --- layered media -----------------------------------------------------------------
 
-def s_integrals(med: Medium, l: int, lp: int, comp: str, rho, z, zp, p, b=B_CONTOUR):
+def s_integrals(med: Medium, l: int, lp: int, comp: str, rho, z, zp, p, b=B_CONTOUR, src=("u", "d")):
     """S[M, S, a, bb] = S^{M,S}_{a,bb}(rho, z, z') of Eq. symmetricdetable for
-    M <= 2p, S <= M, a, bb <= p (zero-filled elsewhere), target-side wave comp."""
+    M <= 2p, S <= M, a, bb <= p (zero-filled elsewhere), target-side wave comp;
+    src selects the source-side waves kept in sigma~ (both by default)."""
     dt = (z - med.bottom(l)) if comp == "u" else (med.top(l) - z)
     ds = min((zp - med.bottom(lp)) if lp < med.L else np.inf, (med.top(lp) - zp) if lp > 0 else np.inf)
     kmax = float(np.max(med.k))
@@ -279,14 +280,14 @@ def s_integrals(med: Medium, l: int, lp: int, comp: str, rho, z, zp, p, b=B_CONT
     out = np.zeros((2 * p + 1, 2 * p + 1, p + 1, p + 1), np.complex128)
     f = math.factorial
     for bb in range(p + 1):
-        src = 0
-        if Eu is not None and su is not None:
-            src = src + Eu * su
-        if Ed is not None and sd is not None:
-            src = src + (-1) ** bb * Ed * sd
-        src = src * (1j * klp) ** bb
+        sv = 0
+        if Eu is not None and su is not None and "u" in src:
+            sv = sv + Eu * su
+        if Ed is not None and sd is not None and "d" in src:
+            sv = sv + (-1) ** bb * Ed * sd
+        sv = sv * (1j * klp) ** bb
         for a in range(p + 1):
-            vert = (tsign * 1j * kl) ** a * P / kl * src
+            vert = (tsign * 1j * kl) ** a * P / kl * sv
             for M in range(2 * p + 1):
                 base = nodes ** (M + 1) * vert / (2.0 ** M * f(M) * f(a) * f(bb))
                 for S in range(M + 1):

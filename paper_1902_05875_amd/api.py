@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libtefmm.so")
 TEFMM_FP64, TEFMM_MIXED_FP32 = 0, 1
 MAX_LAYERS = 8  # TEFMM_MAX_LAYERS
 TEFMM_NORM_PHYSICAL, TEFMM_NORM_PAPER = 0, 1
+TEFMM_SIGMA_IMAGES, TEFMM_SIGMA_SOMMERFELD = 0, 1
+SIGMA_TABLES = {"images": TEFMM_SIGMA_IMAGES, "sommerfeld": TEFMM_SIGMA_SOMMERFELD}
 ERRORS = {0: "OK", -1: "INVALID_ARG", -2: "PARTICLE_ON_INTERFACE", -3: "UNSUPPORTED", -4: "HIP",
           -5: "DCIM_FIT", -6: "OOM", -7: "STATE"}
 
@@ -30,7 +32,7 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_mlp_loss_grad",
            "tefmm_mlp_adam_step", "tefmm_mlp_train", "tefmm_surrogate_default_options", "tefmm_surrogate_train",
            "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
-           "tefmm_reset_timers", "tefmm_set_allocator", "tefmm_gmres"]
+           "tefmm_reset_timers", "tefmm_set_allocator", "tefmm_gmres", "tefmm_sigma_derivatives"]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -74,7 +76,8 @@ class OptionsC(ctypes.Structure):
                 ("precision", ctypes.c_int), ("normalization", ctypes.c_int), ("dcim_T1", ctypes.c_double),
                 ("dcim_samples", ctypes.c_int), ("dcim_svd_tol", ctypes.c_double),
                 ("interface_eps", ctypes.c_double), ("n_rhs_max", ctypes.c_int), ("dcim_T1_cross", ctypes.c_double),
-                ("m2l_tile", ctypes.c_int), ("p2p_targets", ctypes.c_int), ("p2p_poly", ctypes.c_int)]
+                ("m2l_tile", ctypes.c_int), ("p2p_targets", ctypes.c_int), ("p2p_poly", ctypes.c_int),
+                ("sigma_tables", ctypes.c_int)]
 
 
 class StatsC(ctypes.Structure):
@@ -90,7 +93,8 @@ class StatsC(ctypes.Structure):
         ("timed_evaluations", ctypes.c_int), ("p2p_pairs_same_leaf", ctypes.c_int64),
         ("p2p_poly_err", ctypes.c_double), ("sigma_direct_pairs", ctypes.c_int64),
         ("occupied_leaves", ctypes.c_int64), ("max_leaf_count", ctypes.c_int64),
-        ("reaction_keys_forced", ctypes.c_int64)]
+        ("reaction_keys_forced", ctypes.c_int64), ("sigma_quad_nodes", ctypes.c_int64),
+        ("sigma_quad_keys", ctypes.c_int64)]
 
 
 class GmresInfoC(ctypes.Structure):
@@ -176,6 +180,7 @@ def lib():
         L.tefmm_reset_timers.argtypes = [vp]
         L.tefmm_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
         L.tefmm_gmres.argtypes = [vp, dbl, dbl, vp, vp, i32, i32, i32, dbl, vp, ctypes.POINTER(GmresInfoC)]
+        L.tefmm_sigma_derivatives.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -196,6 +201,8 @@ def default_options(**kw) -> OptionsC:
             v = {"fp64": TEFMM_FP64, "fp32": TEFMM_MIXED_FP32, "mixed": TEFMM_MIXED_FP32}[v]
         if name == "normalization" and isinstance(v, str):
             v = {"physical": TEFMM_NORM_PHYSICAL, "paper": TEFMM_NORM_PAPER}[v]
+        if name == "sigma_tables" and isinstance(v, str):
+            v = SIGMA_TABLES[v]
         setattr(o, name, v)
     return o
 
@@ -284,6 +291,21 @@ class TEFMM:
         _check(lib().tefmm_evaluate(self.h, ctypes.c_void_p(q2.data_ptr()), R, ctypes.c_void_p(out.data_ptr()),
                                     _stream_ptr(stream)), self.h)
         return out.reshape(-1) if squeeze else out
+
+    def sigma_derivatives(self, layer, rho, S, method="sommerfeld", stream=None):
+        """H_{m,c}(rho_i, S_i) of the layer's Sigma families (tefmm_sigma_derivatives):
+        numpy (n, (2p+1)(2p+2)/2) complex128, entry (m + c)(m + c + 1)/2 + m."""
+        import numpy as np
+        rho = np.ascontiguousarray(rho, np.float64).ravel()
+        S = np.ascontiguousarray(S, np.float64).ravel()
+        if rho.shape != S.shape:
+            raise ValueError("rho and S differ in length")
+        P2 = 2 * self.opt.p
+        out = np.empty((rho.size, (P2 + 1) * (P2 + 2) // 2), np.complex128)
+        m = SIGMA_TABLES[method] if isinstance(method, str) else int(method)
+        _check(lib().tefmm_sigma_derivatives(self.h, int(layer), m, rho.size, rho.ctypes.data, S.ctypes.data,
+                                              out.ctypes.data, _stream_ptr(stream)), self.h)
+        return out
 
     def gmres(self, b, tau, tol=1e-8, restart=30, max_iter=300, x0=None, stream=None):
         """Solve (I - tau G) x = b by GMRES(restart) through tefmm_gmres (b: torch complex128 on the

@@ -173,6 +173,7 @@ struct tefmm_ctx {
   unsigned char* d_g1 = nullptr;
   short* d_nbr = nullptr;   // [nG][6] compact-table recurrence neighbours
   unsigned char* d_g3 = nullptr;
+  unsigned char* d_gord = nullptr;  // [nG] order |g| of each compact table entry
   double *d_fact = nullptr, *d_scale = nullptr, *d_invfact = nullptr;
   // geometry
   int64_t n = 0;
@@ -200,6 +201,7 @@ struct tefmm_ctx {
   int ev_next = 0, ev_count = 0;
   int64_t p2p_pairs = 0, m2l_pairs = 0, p2p_same = 0;
   int64_t sigma_keys = 0, sur_keys = 0;  // Sigma table rows of the geometry / answered by the surrogate
+  int64_t som_nodes = 0, som_keys = 0;   // Sigma quadrature: largest node count / rows produced
   // copy of the caller's positions (SoA), kept for re-building the tree (autotuner)
   double* d_xyz_user = nullptr;
   int m2l_ncb = 0;  // M2L tile width override (0 = automatic)
@@ -400,6 +402,13 @@ static int build_constant_tables(tefmm_t h) {
   HIPCHK(h, hipMemcpy(h->d_rfull, rfull.data(), sizeof(int) * nR, hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->d_nbr, nbr.data(), sizeof(short) * 6 * nG, hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->d_g3, g3.data(), nG, hipMemcpyHostToDevice));
+  {
+    std::vector<unsigned char> gord(nG);
+    for (int n = 0; n <= 2 * h->opt.p; ++n)
+      for (int i = g_offset(n); i < g_offset(n + 1) && i < nG; ++i) gord[i] = (unsigned char)n;
+    HIPCHK(h, dmalloc(h, &h->d_gord, nG));
+    HIPCHK(h, hipMemcpy(h->d_gord, gord.data(), nG, hipMemcpyHostToDevice));
+  }
   HIPCHK(h, hipMemcpy(h->d_fact, fact.data(), sizeof(double) * nG, hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->d_scale, scale.data(), sizeof(double) * nC, hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->d_invfact, invfact.data(), sizeof(double) * nC, hipMemcpyHostToDevice));
@@ -453,6 +462,7 @@ static void free_constant_tables(tefmm_t h) {
   dfree(h, h->d_rzfull);
   dfree(h, h->d_nbr);
   dfree(h, h->d_g3);
+  dfree(h, h->d_gord);
   dfree(h, h->d_fact);
   dfree(h, h->d_scale);
   dfree(h, h->d_invfact);
@@ -505,6 +515,176 @@ static void sigma_mirror_dist(const MediumDesc& med, int l, bool up, bool dn, do
                               std::vector<double>& out);
 
 // ---------------------------------------------------------------------------
+// Sigma-family tables from the Sommerfeld integrals (Sec. 4.2).  The path is the
+// paper's: Gamma1 from 0 to -ib, Gamma2 from -ib to t_max - ib (b = 1), with
+// composite 16-point Gauss-Legendre panels.  Along Gamma2 the integrand of H_{m,c}
+// is at most of size t^(2 P2 + 1) e^{-t zeta_min} (zeta_min: the least mirror
+// distance of the keys served), so the path ends where that bound falls to 1e-18 of
+// its peak (at most t = 8000); Gamma2 panels are at most min(2, pi / rho_max) wide
+// (J_m(k_rho rho) oscillates with period 2 pi / rho).  Per node the host solves the
+// interface system for the densities and keeps cu, cd = w i (sigma - sigma_inf) / k_z
+// of the up- and down-going families; sigma_inf (the density at k_rho = 1e8 k) is the
+// weight of the image at each mirror point, which k_sigma_h adds exactly.
+// ---------------------------------------------------------------------------
+static const double SOM_B = 1.0;
+static const double SOM_T_CAP = 8000.0;
+struct SomPath {
+  std::vector<cplx> krho, kz, cu, cd;
+  cplx sinf_u = 0.0, sinf_d = 0.0;
+};
+
+static void sommerfeld_path(const MediumDesc& med, int l, bool up, bool dn, double zeta_min, double rho_max, int P2,
+                            SomPath& P) {
+  const int ORD = 16;
+  std::vector<double> gx, gw;
+  gauss_legendre01(ORD, gx, gw);
+  const double q = 2.0 * P2 + 1.0, Z = std::max(zeta_min, 1e-3);
+  const double tpk = std::max(q / Z, 1.0);
+  double t_max = tpk;
+  while (t_max < SOM_T_CAP && q * std::log(t_max / tpk) - Z * (t_max - tpk) > -41.5) t_max *= 1.05;
+  double kmax = 0;
+  for (double kk : med.k) kmax = std::max(kmax, kk);
+  t_max = std::max(std::min(t_max, SOM_T_CAP), kmax + 4.0);
+  const double wmax = std::min(2.0, 3.14159265358979324 / std::max(rho_max, 1e-12));
+  const int npan = (int)std::ceil(t_max / wmax);
+  const double wp = t_max / npan;
+  std::vector<cplx> wts;
+  P.krho.clear(), P.kz.clear(), P.cu.clear(), P.cd.clear();
+  for (int j = 0; j < ORD; ++j) P.krho.push_back(cplx(0.0, -SOM_B * gx[j])), wts.push_back(cplx(0.0, -SOM_B * gw[j]));
+  for (int pn = 0; pn < npan; ++pn)
+    for (int j = 0; j < ORD; ++j) P.krho.push_back(cplx((pn + gx[j]) * wp, -SOM_B)), wts.push_back(wp * gw[j]);
+  std::vector<cplx> sig;
+  reaction_densities(med, l, cplx(1e8 * med.k[l], 0.0), sig);
+  P.sinf_u = up ? sig[l * 4 + 0] : cplx(0.0);
+  P.sinf_d = dn ? sig[l * 4 + 3] : cplx(0.0);
+  const cplx I(0.0, 1.0);
+  for (size_t t = 0; t < P.krho.size(); ++t) {
+    reaction_densities(med, l, P.krho[t], sig);
+    const cplx kz = vertical_wavenumber(med.k[l], P.krho[t]);
+    P.kz.push_back(kz);
+    P.cu.push_back(up ? wts[t] * I * (sig[l * 4 + 0] - P.sinf_u) / kz : cplx(0.0));
+    P.cd.push_back(dn ? wts[t] * I * (sig[l * 4 + 3] - P.sinf_d) / kz : cplx(0.0));
+  }
+}
+
+// H (one row per pair) of the Sigma families of layer l at the pairs (rho[pr[i]], S[ps[i]]):
+// the mirror-point images by k_sigma_h, then the node contraction added to them.
+static int sommerfeld_h(tefmm_t h, int l, bool up, bool dn, const SomPath& P, int P2, const std::vector<double>& rho,
+                        const std::vector<double>& S, const std::vector<int>& pr, const std::vector<int>& ps,
+                        double2* d_H, hipStream_t s) {
+  const MediumDesc& med = h->med;
+  const int nn = (int)P.krho.size(), np = (int)pr.size(), nr = (int)rho.size(), nsv = (int)S.size(), M = P2;
+  if (!np) return TEFMM_OK;
+  const double two_dl = l < med.L ? 2 * med.d[l] : 0.0, two_dt = l > 0 ? 2 * med.d[l - 1] : 0.0;
+  auto pack = [](const std::vector<cplx>& v) {
+    std::vector<double2> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = make_double2(v[i].real(), v[i].imag());
+    return o;
+  };
+  const std::vector<double2> hk = pack(P.krho), hz = pack(P.kz), hu = pack(P.cu), hd = pack(P.cd);
+  std::vector<double2> qs;
+  int nup = 0, ndn = 0;
+  if (up && P.sinf_u != 0.0) qs.push_back(make_double2(P.sinf_u.real(), P.sinf_u.imag())), qs.push_back({0, 0}), nup = 1;
+  if (dn && P.sinf_d != 0.0) qs.push_back(make_double2(P.sinf_d.real(), P.sinf_d.imag())), qs.push_back({0, 0}), ndn = 1;
+  std::vector<double> w(np), Sp(np);
+  for (int i = 0; i < np; ++i) w[i] = rho[pr[i]] * rho[pr[i]], Sp[i] = S[ps[i]];
+  double2 *d_k = nullptr, *d_z = nullptr, *d_u = nullptr, *d_d = nullptr, *d_qs = nullptr, *d_A = nullptr, *d_B = nullptr;
+  double *d_rho = nullptr, *d_S = nullptr, *d_w = nullptr, *d_Sp = nullptr;
+  int *d_pr = nullptr, *d_ps = nullptr;
+  int rc = TEFMM_OK;
+  auto run = [&]() -> int {
+    HIPCHK(h, dmalloc(h, &d_k, sizeof(double2) * nn));
+    HIPCHK(h, dmalloc(h, &d_z, sizeof(double2) * nn));
+    HIPCHK(h, dmalloc(h, &d_u, sizeof(double2) * nn));
+    HIPCHK(h, dmalloc(h, &d_d, sizeof(double2) * nn));
+    HIPCHK(h, dmalloc(h, &d_qs, sizeof(double2) * std::max<size_t>(qs.size(), 1)));
+    HIPCHK(h, dmalloc(h, &d_A, sizeof(double2) * (size_t)nr * (M + 1) * nn));
+    HIPCHK(h, dmalloc(h, &d_B, sizeof(double2) * (size_t)nsv * (M + 1) * nn));
+    HIPCHK(h, dmalloc(h, &d_rho, sizeof(double) * nr));
+    HIPCHK(h, dmalloc(h, &d_S, sizeof(double) * nsv));
+    HIPCHK(h, dmalloc(h, &d_w, sizeof(double) * np));
+    HIPCHK(h, dmalloc(h, &d_Sp, sizeof(double) * np));
+    HIPCHK(h, dmalloc(h, &d_pr, sizeof(int) * np));
+    HIPCHK(h, dmalloc(h, &d_ps, sizeof(int) * np));
+    HIPCHK(h, hipMemcpyAsync(d_k, hk.data(), sizeof(double2) * nn, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_z, hz.data(), sizeof(double2) * nn, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_u, hu.data(), sizeof(double2) * nn, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_d, hd.data(), sizeof(double2) * nn, hipMemcpyHostToDevice, s));
+    if (!qs.empty())
+      HIPCHK(h, hipMemcpyAsync(d_qs, qs.data(), sizeof(double2) * qs.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_rho, rho.data(), sizeof(double) * nr, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_S, S.data(), sizeof(double) * nsv, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_w, w.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_Sp, Sp.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_pr, pr.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_ps, ps.data(), sizeof(int) * np, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sigma_h, dim3(np), dim3(64), 0, s, d_w, d_Sp, np, d_qs, nup, ndn, two_dl, two_dt, med.k[l],
+                       P2, d_H);
+    HIPCHK(h, hipGetLastError());
+    hipLaunchKernelGGL(k_som_radial, dim3((nn + 63) / 64, nr), dim3(64), 0, s, d_k, nn, d_rho, M, d_A);
+    HIPCHK(h, hipGetLastError());
+    hipLaunchKernelGGL(k_som_vertical, dim3((nn + 63) / 64, nsv), dim3(64), 0, s, d_z, d_u, d_d, nn, d_S, two_dl,
+                       two_dt, up ? 1 : 0, dn ? 1 : 0, 0.0, M, d_B);
+    HIPCHK(h, hipGetLastError());
+    const size_t lds = 2 * sizeof(double2) * (M + 1) * 65;
+    HIPCHK(h, hipFuncSetAttribute((const void*)k_som_contract, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_som_contract, dim3(np), dim3(256), lds, s, d_A, d_B, nn, M, d_pr, d_ps, d_H);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    return TEFMM_OK;
+  };
+  rc = run();
+  dfree(h, d_k), dfree(h, d_z), dfree(h, d_u), dfree(h, d_d), dfree(h, d_qs), dfree(h, d_A), dfree(h, d_B);
+  dfree(h, d_rho), dfree(h, d_S), dfree(h, d_w), dfree(h, d_Sp), dfree(h, d_pr), dfree(h, d_ps);
+  return rc;
+}
+
+// Rows sk.key of d_out (level box size hb) from the Sommerfeld H, computed once per
+// distinct (rho, S) of the keys and rebuilt into the compact Cartesian layout.
+static int sommerfeld_tables(tefmm_t h, const Group& g, const SomPath& P, const SigmaKeys& sk, double hb,
+                             double2* d_out, hipStream_t s) {
+  const int nk = (int)sk.key.size(), P2 = 2 * h->opt.p, nH = (P2 + 1) * (P2 + 2) / 2;
+  std::map<double, int> rmap, smap;
+  std::map<std::pair<int, int>, int> pmap;
+  std::vector<double> rho, S;
+  std::vector<int> pr, ps, hrow(nk);
+  for (int i = 0; i < nk; ++i) {
+    const double r2 = sk.X[i] * sk.X[i] + sk.Y[i] * sk.Y[i];
+    auto ri = rmap.emplace(r2, (int)rho.size());
+    if (ri.second) rho.push_back(std::sqrt(r2));
+    auto si = smap.emplace(sk.S[i], (int)S.size());
+    if (si.second) S.push_back(sk.S[i]);
+    auto pi = pmap.emplace(std::make_pair(ri.first->second, si.first->second), (int)pr.size());
+    if (pi.second) pr.push_back(ri.first->second), ps.push_back(si.first->second);
+    hrow[i] = pi.first->second;
+  }
+  double2* d_H = nullptr;
+  double *d_x = nullptr, *d_y = nullptr;
+  int *d_key = nullptr, *d_hrow = nullptr;
+  auto run = [&]() -> int {
+    HIPCHK(h, dmalloc(h, &d_H, sizeof(double2) * pr.size() * nH));
+    const int rc = sommerfeld_h(h, g.layer, g.has[0], g.has[1], P, P2, rho, S, pr, ps, d_H, s);
+    if (rc != TEFMM_OK) return rc;
+    HIPCHK(h, dmalloc(h, &d_x, sizeof(double) * nk));
+    HIPCHK(h, dmalloc(h, &d_y, sizeof(double) * nk));
+    HIPCHK(h, dmalloc(h, &d_key, sizeof(int) * nk));
+    HIPCHK(h, dmalloc(h, &d_hrow, sizeof(int) * nk));
+    HIPCHK(h, hipMemcpyAsync(d_x, sk.X.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_y, sk.Y.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_key, sk.key.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_hrow, hrow.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sigma_restore, dim3(nk), dim3(64), 0, s, d_H, d_x, d_y, nk, d_key, hb, h->med.k[g.layer], P2,
+                       h->nG, h->d_g1, h->d_g3, h->d_gord, d_out, d_hrow);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(s));
+    return TEFMM_OK;
+  };
+  const int rc = run();
+  dfree(h, d_H), dfree(h, d_x), dfree(h, d_y), dfree(h, d_key), dfree(h, d_hrow);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
 // Derivative tables of one group (all levels).
 // ---------------------------------------------------------------------------
 static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
@@ -517,6 +697,31 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
   g.Tfd32.assign(g.depth + 1, nullptr);
   g.TS32.assign(g.depth + 1, nullptr);
   const bool has_sigma = g.has[0] || g.has[1];
+  // Sigma rows from the Sommerfeld integrals: one contour for all levels, ending where
+  // the least mirror distance of the keys served needs it
+  SomPath som;
+  const bool som_on = has_sigma && h->opt.sigma_tables == TEFMM_SIGMA_SOMMERFELD;
+  if (som_on) {
+    if (2 * h->opt.p > SIGMA_P2_MAX)
+      return fail(h, TEFMM_ERR_UNSUPPORTED, "Sommerfeld Sigma tables need 2p <= " + std::to_string(SIGMA_P2_MAX));
+    double zmin = 1e300;
+    for (int lev = 2; lev <= g.depth; ++lev) {
+      const int nb = 1 << lev, nm = 2 * nb - 1;
+      const double hb = g.side / nb;
+      for (int m = 0; m < nm; ++m) {
+        if (lev == g.depth && !g.sig_flag.empty()) {
+          bool all = true;  // every key of this S evaluated directly
+          for (int c = 0; c < 49 && all; ++c) all = g.sig_flag[(size_t)c * nm + m] != 0;
+          if (all) continue;
+        }
+        const double S = 2 * g.lo[2] + (m + 1) * hb;
+        if (g.has[0] && S - 2 * med.d[l_] > 0) zmin = std::min(zmin, S - 2 * med.d[l_]);
+        if (g.has[1] && 2 * med.d[l_ - 1] - S > 0) zmin = std::min(zmin, 2 * med.d[l_ - 1] - S);
+      }
+    }
+    sommerfeld_path(med, l_, g.has[0], g.has[1], zmin, 3.0 * std::sqrt(2.0) * g.side / 4, 2 * h->opt.p, som);
+    h->som_nodes = std::max<int64_t>(h->som_nodes, (int64_t)som.krho.size());
+  }
   for (int lev = 2; lev <= g.depth; ++lev) {
     const int nb = 1 << lev;
     const double hb = g.side / nb;
@@ -526,7 +731,7 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
       std::vector<TableTerm> terms;
       std::vector<int> start;
       std::vector<double> hk;
-      SigmaKeys sk;
+      SigmaKeys sk, sq;  // rows answered by the surrogate / by the Sommerfeld integrals
       int nkeys;
       auto push = [&](double x, double y, cplx zeta, cplx coef, int flip, bool image) {
         // an image term is valid only for Re(zeta) > 0; keys failing this join
@@ -576,6 +781,11 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
                 sigma_mirror_dist(med, l_, g.has[0], g.has[1], -dx * hb, -dy * hb, S, sk.Re);
                 continue;
               }
+              if (som_on) {
+                sq.key.push_back((int)start.size() - 1);
+                sq.X.push_back(-dx * hb), sq.Y.push_back(-dy * hb), sq.S.push_back(S);
+                continue;
+              }
               if (g.has[0])
                 for (size_t j = 0; j < g.famA[0].size(); ++j)
                   push(-dx, -dy, (S - 2 * med.d[l_] - g.famZ[0][j]) / hb, g.famA[0][j], 0, true);
@@ -615,6 +825,14 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
           return rc;
         }
         h->sur_keys += (int64_t)sk.key.size();
+      }
+      if (!sq.key.empty()) {
+        int rc = sommerfeld_tables(h, g, som, sq, hb, d_out, s);
+        if (rc != TEFMM_OK) {
+          dfree(h, d_out);
+          return rc;
+        }
+        h->som_keys += (int64_t)sq.key.size();
       }
       if (which == 1) h->sigma_keys += nkeys;
       if (which == 0)
@@ -1305,7 +1523,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     if (rc != TEFMM_OK) return rc;
   }
   // derivative tables
-  h->sigma_keys = 0, h->sur_keys = 0;
+  h->sigma_keys = 0, h->sur_keys = 0, h->som_nodes = 0, h->som_keys = 0;
   for (auto& g : h->groups) {
     int rc = build_tables(h, g, s);
     if (rc != TEFMM_OK) return rc;
@@ -1339,6 +1557,8 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   h->st.n_families = fi;
   h->st.sigma_keys = h->sigma_keys;
   h->st.surrogate_keys = h->sur_keys;
+  h->st.sigma_quad_nodes = h->som_nodes;
+  h->st.sigma_quad_keys = h->som_keys;
   for (auto& g : h->groups) {
     h->st.sigma_direct_pairs += g.sd_pairs;
     h->st.reaction_keys_forced += g.keys_forced;
@@ -2356,7 +2576,7 @@ static int surrogate_tables(tefmm_t h, const SigmaKeys& sk, double hb, double2* 
     dfree(h, d_net);
   }
   hipLaunchKernelGGL(k_sigma_restore, dim3(nk), dim3(64), 0, s, d_H, d_x, d_y, nk, d_key, hb,
-                     h->med.k[su->layer], su->P2, nG, h->d_g1, h->d_g3, su->d_gord, d_out);
+                     h->med.k[su->layer], su->P2, nG, h->d_g1, h->d_g3, su->d_gord, d_out, nullptr);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
   dfree(h, d_H);
@@ -2653,4 +2873,83 @@ extern "C" int tefmm_set_surrogate(tefmm_t h, tefmm_surrogate_t su) {
   }
   h->sur = su;
   return TEFMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// H_{m,c} of the Sigma families of one layer at given points, by the complex
+// images (Sec. 3.3) or by the Sommerfeld integrals (Sec. 4.2).
+// ---------------------------------------------------------------------------
+extern "C" int tefmm_sigma_derivatives(tefmm_t h, int layer, int method, int64_t n, const double* rho,
+                                       const double* S, double* out, void* stream) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  const MediumDesc& med = h->med;
+  if (layer < 0 || layer > med.L) return fail(h, TEFMM_ERR_INVALID_ARG, "layer out of range");
+  if (method != TEFMM_SIGMA_IMAGES && method != TEFMM_SIGMA_SOMMERFELD)
+    return fail(h, TEFMM_ERR_INVALID_ARG, "unknown method");
+  if (n < 1 || n > (1 << 22) || !rho || !S || !out) return fail(h, TEFMM_ERR_INVALID_ARG, "need 1 <= n <= 2^22 points");
+  const bool up = layer < med.L, dn = layer > 0;
+  if (!up && !dn) return fail(h, TEFMM_ERR_UNSUPPORTED, "a medium of one layer has no reaction term");
+  const int P2 = 2 * h->opt.p, nH = (P2 + 1) * (P2 + 2) / 2;
+  if (P2 > SIGMA_P2_MAX) return fail(h, TEFMM_ERR_UNSUPPORTED, "needs 2p <= " + std::to_string(SIGMA_P2_MAX));
+  double zmin = 1e300, rmax = 0.0, slo = 1e300, shi = -1e300;
+  for (int64_t i = 0; i < n; ++i) {
+    const double zu = up ? S[i] - 2 * med.d[layer] : 1e300, zd = dn ? 2 * med.d[layer - 1] - S[i] : 1e300;
+    if (!(rho[i] >= 0 && rho[i] < 1e300) || !(zu > 0) || !(zd > 0))
+      return fail(h, TEFMM_ERR_INVALID_ARG, "point " + std::to_string(i) + " outside the layer's Sigma range");
+    zmin = std::min(zmin, std::min(zu, zd));
+    rmax = std::max(rmax, rho[i]);
+    slo = std::min(slo, S[i]), shi = std::max(shi, S[i]);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const std::vector<double> vr(rho, rho + n), vS(S, S + n);
+  double2* d_H = nullptr;
+  double2* d_img = nullptr;
+  double *d_w = nullptr, *d_s = nullptr;
+  auto run = [&]() -> int {
+    HIPCHK(h, dmalloc(h, &d_H, sizeof(double2) * (size_t)n * nH));
+    if (method == TEFMM_SIGMA_SOMMERFELD) {
+      SomPath P;
+      sommerfeld_path(med, layer, up, dn, zmin, rmax, P2, P);
+      std::vector<int> idx(n);
+      for (int64_t i = 0; i < n; ++i) idx[i] = (int)i;
+      return sommerfeld_h(h, layer, up, dn, P, P2, vr, vS, idx, idx, d_H, s);
+    }
+    std::vector<double2> img;
+    int cnt[2] = {0, 0};
+    for (int f = 0; f < 2; ++f) {
+      if ((f == 0 && !up) || (f == 1 && !dn)) continue;
+      std::vector<cplx> A, Z;
+      double fe = 0;
+      std::string err;
+      if (!same_layer_family(med, layer, f, 0.5 * slo, 0.5 * shi, h->opt.dcim_T1, h->opt.dcim_samples,
+                             h->opt.dcim_svd_tol, A, Z, fe, err))
+        return fail(h, TEFMM_ERR_DCIM_FIT, err);
+      for (size_t j = 0; j < A.size(); ++j) {
+        img.push_back(make_double2(A[j].real(), A[j].imag()));
+        img.push_back(make_double2(Z[j].real(), Z[j].imag()));
+      }
+      cnt[f] = (int)A.size();
+    }
+    std::vector<double> w(n);
+    for (int64_t i = 0; i < n; ++i) w[i] = rho[i] * rho[i];
+    HIPCHK(h, dmalloc(h, &d_img, sizeof(double2) * std::max<size_t>(img.size(), 1)));
+    HIPCHK(h, dmalloc(h, &d_w, sizeof(double) * n));
+    HIPCHK(h, dmalloc(h, &d_s, sizeof(double) * n));
+    if (!img.empty())
+      HIPCHK(h, hipMemcpyAsync(d_img, img.data(), sizeof(double2) * img.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_w, w.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_s, S, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_sigma_h, dim3((unsigned)n), dim3(64), 0, s, d_w, d_s, (int)n, d_img, cnt[0], cnt[1],
+                       up ? 2 * med.d[layer] : 0.0, dn ? 2 * med.d[layer - 1] : 0.0, med.k[layer], P2, d_H);
+    HIPCHK(h, hipGetLastError());
+    return TEFMM_OK;
+  };
+  int rc = run();
+  if (rc == TEFMM_OK) {
+    if (hipMemcpyAsync(out, d_H, sizeof(double2) * (size_t)n * nH, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      rc = fail(h, TEFMM_ERR_HIP, "copy of the derivatives");
+  }
+  dfree(h, d_H), dfree(h, d_img), dfree(h, d_w), dfree(h, d_s);
+  return rc;
 }

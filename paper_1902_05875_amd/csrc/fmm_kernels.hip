@@ -1806,18 +1806,21 @@ __global__ void k_sur_h_from_net(const float* y, const double* Re, int n, int P2
 // D+ D- = d_x^2 + d_y^2 = -(d_S^2 + k^2), so for p >= q
 //   D+^p D-^q d_S^c K = (-1)^q sum_t C(q, t) k^(2(q-t)) u^(p-q) H_{p-q, c+2t}
 // (conj(u) and p, q swapped when q > p).  Row of key i: out[row[i]][g] = h^|g| d^g K at
-// (X_i, Y_i) and the point's S, for the compact entries g (g1 <= 2).  One block per key.
+// (X_i, Y_i) and the point's S, for the compact entries g (g1 <= 2).  One block per key;
+// key i reads H row hrow[i] (row i when hrow is null).
 __global__ __launch_bounds__(64) void k_sigma_restore(const double2* H, const double* X, const double* Y, int nk,
                                                       const int* row, double h, double k, int P2, int nG,
                                                       const unsigned char* g1s, const unsigned char* g3s,
-                                                      const unsigned char* gord, double2* out) {
+                                                      const unsigned char* gord, double2* out,
+                                                      const int* hrow) {
   __shared__ double2 sh[SIGMA_H_MAX];
   __shared__ double2 up[SIGMA_P2_MAX + 1], dp[SIGMA_P2_MAX + 1];
   __shared__ double fct[SIGMA_P2_MAX + 1];
   const int i = blockIdx.x, tid = threadIdx.x;
   if (i >= nk) return;
   const int nH = (P2 + 1) * (P2 + 2) / 2;
-  for (int e = tid; e < nH; e += 64) sh[e] = H[(size_t)i * nH + e];
+  const size_t hr = hrow ? (size_t)hrow[i] : (size_t)i;
+  for (int e = tid; e < nH; e += 64) sh[e] = H[hr * nH + e];
   if (tid == 0) {
     fct[0] = 1.0;
     for (int j = 1; j <= P2; ++j) fct[j] = fct[j - 1] * j;
@@ -1856,6 +1859,167 @@ __global__ __launch_bounds__(64) void k_sigma_restore(const double2* H, const do
     for (int j = 0; j < b2; ++j) ph = cmul(ph, {0.0, -1.0});
     acc = cscale(cmul(acc, ph), sc);
     out[(size_t)row[i] * nG + g] = make_double2(acc.x, acc.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sigma-family derivatives from the Sommerfeld integrals (Sec. 4.2: the
+// integrals of Eq. symmetricdetable in rotation-free form, no image fit).
+// Each family has the spectral form
+//   K = i int k_rho J0(k_rho rho) e^{i k_z zeta} sigma(k_rho) / k_z dk_rho,
+//   zeta = S - 2 d_l (up-going), 2 d_{l-1} - S (down-going, where d_S = -d_zeta),
+// and (rho^-1 d_rho)^m J0(k_rho rho) = (-k_rho^2)^m J_m(x) / x^m, x = k_rho rho, so that
+// on the nodes t (weights w) of the deformed contour
+//   H_{m,c}(rho, S) = sum_t A_m(rho, t) B_c(S, t),
+//   A_m = k_rho (-k_rho^2)^m J_m(x) / x^m,
+//   B_c = (i k_z)^c e^{i k_z zeta_u} cu_t + (-i k_z)^c e^{i k_z zeta_d} cd_t,
+//   cu, cd = w i (sigma - sigma_inf) / k_z.
+// The limits sigma_inf (k_rho -> infinity) are one image at each mirror point,
+// added exactly by k_sigma_h.  A and B are stored [row][index][node].
+// ---------------------------------------------------------------------------
+// J_m(x) / x^m for m = 0 .. M at complex x, times k_rho (-k_rho^2)^m, into
+// out[m * ld] (one thread per node; ld = node count).  Power series for |x| <= 4;
+// otherwise normalised backward recurrence (Miller's method: J_{n-1} = (2n/x) J_n - J_{n+1}
+// from zero far above max(M, |x|), scaled by J_0 + 2 sum_k J_{2k} = 1).
+__device__ void bessel_ratio_row(dc x, dc krho, int M, double2* out, int64_t ld) {
+  const double ax = hypot(x.x, x.y);
+  const dc mk2 = {-(krho.x * krho.x - krho.y * krho.y), -2.0 * krho.x * krho.y};  // -k_rho^2
+  if (ax <= 4.0) {
+    const dc q = cscale(cmul(x, x), -0.25);
+    double inv = 1.0;  // 1 / (2^m m!)
+    dc pk = krho;      // k_rho (-k_rho^2)^m
+    for (int m = 0; m <= M; ++m) {
+      dc term = {inv, 0.0}, sum = term;
+      for (int kk = 1; kk < 200; ++kk) {
+        term = cscale(cmul(term, q), 1.0 / ((double)kk * (m + kk)));
+        sum = cadd(sum, term);
+        if (hypot(term.x, term.y) <= 1e-17 * hypot(sum.x, sum.y)) break;
+      }
+      const dc v = cmul(sum, pk);
+      out[(int64_t)m * ld] = make_double2(v.x, v.y);
+      inv /= 2.0 * (m + 1);
+      pk = cmul(pk, mk2);
+    }
+    return;
+  }
+  const dc ix = cdiv({1.0, 0.0}, x);
+  int N = (int)(ax + 30.0) + M;
+  N += N & 1;
+  dc f1 = {0.0, 0.0}, f0 = {1e-250, 0.0};  // f_{n+1}, f_n
+  dc norm = {0.0, 0.0};
+  for (int n = N; n >= 1; --n) {
+    if (n <= M) out[(int64_t)n * ld] = make_double2(f0.x, f0.y);
+    if (!(n & 1)) norm = cadd(norm, cscale(f0, 2.0));
+    const dc fm = csub(cmul(cscale(ix, 2.0 * n), f0), f1);
+    f1 = f0, f0 = fm;
+    if (fabs(f0.x) + fabs(f0.y) > 1e250) {  // rescale everything kept so far
+      const double s = 1e-250;
+      f0 = cscale(f0, s), f1 = cscale(f1, s), norm = cscale(norm, s);
+      for (int j = n; j <= M; ++j) {
+        const double2 v = out[(int64_t)j * ld];
+        out[(int64_t)j * ld] = make_double2(v.x * s, v.y * s);
+      }
+    }
+  }
+  out[0] = make_double2(f0.x, f0.y);
+  norm = cadd(norm, f0);
+  // J_m = f_m / norm first (values of order one), then the factor k_rho (-k_rho^2 / x)^m:
+  // the two scales apart can each exceed the double range
+  const dc inorm = cdiv({1.0, 0.0}, norm);
+  dc fac = krho;
+  const dc step = cmul(mk2, ix);
+  for (int m = 0; m <= M; ++m) {
+    const double2 v = out[(int64_t)m * ld];
+    const dc r = cmul(cmul({v.x, v.y}, inorm), fac);
+    out[(int64_t)m * ld] = make_double2(r.x, r.y);
+    fac = cmul(fac, step);
+  }
+}
+
+// A[(ir (M+1) + m) nn + t] for the radial distances rho[ir] (grid: ceil(nn / 64) x nrho)
+__global__ __launch_bounds__(64) void k_som_radial(const double2* krho, int nn, const double* rho, int M,
+                                                   double2* A) {
+  const int t = blockIdx.x * 64 + threadIdx.x, ir = blockIdx.y;
+  if (t >= nn) return;
+  const dc kr = {krho[t].x, krho[t].y};
+  const dc x = cscale(kr, rho[ir]);
+  bessel_ratio_row(x, kr, M, A + (int64_t)ir * (M + 1) * nn + t, nn);
+}
+
+// B[(is (M+1) + c) nn + t] for the heights S[is] (grid: ceil(nn / 64) x nS); a family
+// takes part where zeta > zeta_eps (the image tables' validity rule) and cu / cd exist
+__global__ __launch_bounds__(64) void k_som_vertical(const double2* kz, const double2* cu, const double2* cd, int nn,
+                                                     const double* S, double two_dl, double two_dt, int has_up,
+                                                     int has_dn, double zeta_eps, int M, double2* B) {
+  const int t = blockIdx.x * 64 + threadIdx.x, is = blockIdx.y;
+  if (t >= nn) return;
+  const dc kzv = {kz[t].x, kz[t].y};
+  const dc ikz = {-kzv.y, kzv.x};
+  const double zu = S[is] - two_dl, zd = two_dt - S[is];
+  dc eu = {0.0, 0.0}, ed = {0.0, 0.0};
+  if (has_up && zu > zeta_eps) eu = cmul(cexp_i(kzv, zu), {cu[t].x, cu[t].y});
+  if (has_dn && zd > zeta_eps) ed = cmul(cexp_i(kzv, zd), {cd[t].x, cd[t].y});
+  double2* o = B + (int64_t)is * (M + 1) * nn + t;
+  for (int c = 0; c <= M; ++c) {
+    const dc v = cadd(eu, ed);
+    o[(int64_t)c * nn] = make_double2(v.x, v.y);
+    eu = cmul(eu, ikz), ed = cmul(ed, {-ikz.x, -ikz.y});
+  }
+}
+
+// H[pair][(m + c)(m + c + 1)/2 + m] += sum_t A[ir][m][t] B[is][c][t] for m + c <= M, one
+// block of 256 per pair (ir, is) = (pr[pair], ps[pair]); node chunks of 64 staged in LDS
+// (rows padded to 65 so that the lanes' rows fall on different banks)
+__global__ __launch_bounds__(256) void k_som_contract(const double2* A, const double2* B, int nn, int M,
+                                                      const int* pr, const int* ps, double2* H) {
+  extern __shared__ double2 lds_som[];
+  constexpr int CH = 64, LD = CH + 1;
+  double2* sa = lds_som;
+  double2* sb = lds_som + (M + 1) * LD;
+  const int pair = blockIdx.x, tid = threadIdx.x;
+  const int nH = (M + 1) * (M + 2) / 2;
+  const double2* Ar = A + (int64_t)pr[pair] * (M + 1) * nn;
+  const double2* Bs = B + (int64_t)ps[pair] * (M + 1) * nn;
+  constexpr int EPT = (SIGMA_H_MAX + 255) / 256;  // entries per thread at most
+  dc acc[EPT];
+  int em[EPT], ec[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    acc[j] = {0.0, 0.0};
+    const int e = tid + 256 * j;
+    int nn2 = 0;
+    while ((nn2 + 1) * (nn2 + 2) / 2 <= e) ++nn2;
+    em[j] = e - nn2 * (nn2 + 1) / 2, ec[j] = nn2 - em[j];
+  }
+  for (int t0 = 0; t0 < nn; t0 += CH) {
+    const int cnt = min(CH, nn - t0);
+    __syncthreads();
+    for (int i = tid; i < (M + 1) * CH; i += 256) {
+      const int r = i / CH, t = i - r * CH;
+      sa[r * LD + t] = t < cnt ? Ar[(int64_t)r * nn + t0 + t] : make_double2(0.0, 0.0);
+      sb[r * LD + t] = t < cnt ? Bs[(int64_t)r * nn + t0 + t] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      if (tid + 256 * j >= nH) break;
+      const double2* a = sa + em[j] * LD;
+      const double2* b = sb + ec[j] * LD;
+      dc s = acc[j];
+      for (int t = 0; t < CH; ++t) {
+        const double2 av = a[t], bv = b[t];
+        s.x = fma(av.x, bv.x, fma(-av.y, bv.y, s.x));
+        s.y = fma(av.x, bv.y, fma(av.y, bv.x, s.y));
+      }
+      acc[j] = s;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = tid + 256 * j;
+    if (e >= nH) break;
+    double2& o = H[(int64_t)pair * nH + e];
+    o = make_double2(o.x + acc[j].x, o.y + acc[j].y);
   }
 }
 

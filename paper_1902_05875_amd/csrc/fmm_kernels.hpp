@@ -186,7 +186,14 @@ __global__ void k_sur_h_from_net(const float* y, const double* Re, int n, int P2
                                  double2* H);
 __global__ void k_sigma_restore(const double2* H, const double* X, const double* Y, int nk, const int* row, double h,
                                 double k, int P2, int nG, const unsigned char* g1s, const unsigned char* g3s,
-                                const unsigned char* gord, double2* out);
+                                const unsigned char* gord, double2* out, const int* hrow);
+// Sigma-family H_{m,c} from the Sommerfeld integrals on the deformed contour
+__global__ void k_som_radial(const double2* krho, int nn, const double* rho, int M, double2* A);
+__global__ void k_som_vertical(const double2* kz, const double2* cu, const double2* cd, int nn, const double* S,
+                               double two_dl, double two_dt, int has_up, int has_dn, double zeta_eps, int M,
+                               double2* B);
+__global__ void k_som_contract(const double2* A, const double2* B, int nn, int M, const int* pr, const int* ps,
+                               double2* H);
 __global__ void k_taylor_points(const double* px, const double* py, const double* pz, double k, double h,
                                 int order, int nT, const short* nbr, double2* out);
 __global__ void k_selftest_mfma(double* out64, float* out32);

@@ -577,6 +577,37 @@ bool same_layer_family(const MediumDesc& med, int l, int family, double z_lo, do
   return true;
 }
 
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+  // roots of P_n by Newton's method from the Chebyshev-like first guesses, then mapped to [0, 1]
+  x.assign(n, 0.0), w.assign(n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double t = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1, p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      const double dt = p1 / dp;
+      t -= dt;
+      if (std::abs(dt) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = t;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1, p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+    }
+    const double wt = 2.0 / ((1.0 - t * t) * dp * dp);
+    x[i] = 0.5 * (1.0 - t), x[n - 1 - i] = 0.5 * (1.0 + t);
+    w[i] = w[n - 1 - i] = 0.5 * wt;
+  }
+}
+
 bool cross_layer_fit(const MediumDesc& med, int l, int lp, int a, double zs, int k3p, double z_lo, double z_hi,
                      double T1, int samples, double svd_tol, std::vector<cplx>& amp, std::vector<cplx>& depth,
                      double& fit_err, std::string& err) {

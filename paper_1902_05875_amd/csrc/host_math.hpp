@@ -58,6 +58,9 @@ bool same_layer_family(const MediumDesc& med, int l, int family, double z_lo, do
                        double T1, int samples, double svd_tol, std::vector<cplx>& amp,
                        std::vector<cplx>& depth, double& fit_err, std::string& err);
 
+// n-point Gauss-Legendre rule on [0, 1] (nodes ascending).
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);
+
 // Cross-layer complex images (Sec. 3.3, the paper's per source height and per
 // z' derivative fits): target layer l, source layer lp != l, target-side wave
 // a (0 = up-going, needs l < L; 1 = down-going, needs l > 0), source height zs,
