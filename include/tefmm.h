@@ -338,6 +338,17 @@ int tefmm_sigma_derivatives(tefmm_t h, int layer, int method, int64_t n, const d
 int tefmm_taylor_coefficients(int n, const double* x, const double* y, const double* zeta,
                               double k, double h, int order, double* out);
 
+/* The tree build's primitives, for checking them alone.  tefmm_radix_sort: stable
+ * sort of n (key, value) pairs by the key bits [0, end_bit) (least significant digit
+ * first, 4-bit digits, per-tile counts scanned in digit-major order; deterministic);
+ * keys and vals are device arrays of n entries, sorted in place; 1 <= n <= 2^31 - 1,
+ * 0 <= end_bit <= 32.  tefmm_exclusive_scan: out[i] = sum_{j < i} in[j] in unsigned
+ * 32-bit arithmetic (wrapping), device arrays, in and out may be the same array.
+ * Both take their scratch from hipMalloc, free it before returning and are
+ * synchronous on `stream`.  Errors: TEFMM_ERR_INVALID_ARG, TEFMM_ERR_HIP. */
+int tefmm_radix_sort(int64_t n, unsigned* keys, int* vals, int end_bit, void* stream);
+int tefmm_exclusive_scan(int64_t n, const unsigned* in, unsigned* out, void* stream);
+
 /* Multipole moments of the last evaluate (rhs 0) for layer group g at tree
  * level l: host copy, n_box * C(p+3,3) complex interleaved, boxes in
  * grid order (ix * n + iy) * n + iz, moments normalised by the box size. */

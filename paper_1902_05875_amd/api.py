@@ -32,7 +32,8 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_mlp_loss_grad",
            "tefmm_mlp_adam_step", "tefmm_mlp_train", "tefmm_surrogate_default_options", "tefmm_surrogate_train",
            "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
-           "tefmm_reset_timers", "tefmm_set_allocator", "tefmm_gmres", "tefmm_sigma_derivatives"]
+           "tefmm_reset_timers", "tefmm_set_allocator", "tefmm_gmres", "tefmm_sigma_derivatives",
+           "tefmm_radix_sort", "tefmm_exclusive_scan"]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -181,8 +182,22 @@ def lib():
         L.tefmm_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
         L.tefmm_gmres.argtypes = [vp, dbl, dbl, vp, vp, i32, i32, i32, dbl, vp, ctypes.POINTER(GmresInfoC)]
         L.tefmm_sigma_derivatives.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
+        L.tefmm_radix_sort.argtypes = [i64, vp, vp, i32, vp]
+        L.tefmm_exclusive_scan.argtypes = [i64, vp, vp, vp]
         _lib = L
     return _lib
+
+
+def radix_sort(keys, vals, end_bit, stream=None):
+    """Stable in-place sort of device int32 tensors (keys read as unsigned) by the key bits
+    [0, end_bit) (tefmm_radix_sort)."""
+    _check(lib().tefmm_radix_sort(keys.numel(), keys.data_ptr(), vals.data_ptr(), int(end_bit), _stream_ptr(stream)))
+
+
+def exclusive_scan(x, out, stream=None):
+    """out = exclusive prefix sums of the device int32 tensor x, unsigned 32-bit
+    arithmetic (tefmm_exclusive_scan)."""
+    _check(lib().tefmm_exclusive_scan(x.numel(), x.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
 
 
 def _medium(k, d):

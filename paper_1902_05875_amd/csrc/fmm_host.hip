@@ -15,7 +15,6 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <hipcub/hipcub.hpp>
 #include <map>
 #include <string>
 #include <thread>
@@ -28,6 +27,7 @@ static_assert(tefmm::MAX_LAYERS == TEFMM_MAX_LAYERS, "layer limit of the kernels
 #include "host_math.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
+#include "sort_scan.hpp"
 
 namespace tefmm {
 bool medium_from_desc(const tefmm_medium* m, MediumDesc& out, std::string& err);
@@ -1411,23 +1411,17 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   HIPCHK(h, hipGetLastError());
   int end_bit = 1;
   while (((int64_t)1 << end_bit) < leaf_off) ++end_bit;
-  size_t tmp_bytes = 0;
-  HIPCHK(h, hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, d_keys, d_keys2, d_perm_in, h->d_perm, (int)n, 0,
-                                               end_bit, s));
+  // stable radix sort by leaf key and the leaf starts by an exclusive scan of the counts
+  // (sort_scan.hip), with scratch from the handle's allocator
   void* d_tmp = nullptr;
-  HIPCHK(h, dmalloc(h, &d_tmp, std::max<size_t>(tmp_bytes, 16)));
-  HIPCHK(h, hipcub::DeviceRadixSort::SortPairs(d_tmp, tmp_bytes, d_keys, d_keys2, d_perm_in, h->d_perm, (int)n, 0,
-                                               end_bit, s));
-  dfree(h, d_tmp);
+  HIPCHK(h, dmalloc(h, &d_tmp, std::max(sort_scratch_bytes(n), scan_scratch_bytes(leaf_off))));
+  HIPCHK(h, radix_sort_pairs(d_keys, d_keys2, d_perm_in, h->d_perm, n, end_bit, d_tmp, s));
   HIPCHK(h, dmalloc(h, &h->d_leaf_count, sizeof(int) * leaf_off));
   HIPCHK(h, dmalloc(h, &h->d_leaf_start, sizeof(int) * leaf_off));
   HIPCHK(h, hipMemsetAsync(h->d_leaf_count, 0, sizeof(int) * leaf_off, s));
   hipLaunchKernelGGL(k_count_keys, dim3(nb256), dim3(256), 0, s, d_keys2, n, h->d_leaf_count);
   HIPCHK(h, hipGetLastError());
-  tmp_bytes = 0;
-  HIPCHK(h, hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, h->d_leaf_count, h->d_leaf_start, (int)leaf_off, s));
-  HIPCHK(h, dmalloc(h, &d_tmp, std::max<size_t>(tmp_bytes, 16)));
-  HIPCHK(h, hipcub::DeviceScan::ExclusiveSum(d_tmp, tmp_bytes, h->d_leaf_count, h->d_leaf_start, (int)leaf_off, s));
+  HIPCHK(h, exclusive_scan((const unsigned*)h->d_leaf_count, (unsigned*)h->d_leaf_start, leaf_off, d_tmp, s));
   HIPCHK(h, dmalloc(h, &h->d_xs, sizeof(double) * 3 * n));
   hipLaunchKernelGGL(k_gather_pos, dim3(nb256), dim3(256), 0, s, src, h->d_perm, n, h->d_xs);
   HIPCHK(h, hipGetLastError());
@@ -2951,5 +2945,40 @@ extern "C" int tefmm_sigma_derivatives(tefmm_t h, int layer, int method, int64_t
       rc = fail(h, TEFMM_ERR_HIP, "copy of the derivatives");
   }
   dfree(h, d_H), dfree(h, d_img), dfree(h, d_w), dfree(h, d_s);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// The tree build's sort and scan alone (sort_scan.hip).
+// ---------------------------------------------------------------------------
+extern "C" int tefmm_radix_sort(int64_t n, unsigned* keys, int* vals, int end_bit, void* stream) {
+  if (n < 1 || n > 2147483647LL || !keys || !vals || end_bit < 0 || end_bit > 32) return TEFMM_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned* k2 = nullptr;
+  int* v2 = nullptr;
+  void* sc = nullptr;
+  int rc = TEFMM_OK;
+  if (hipMalloc(&k2, sizeof(unsigned) * n) != hipSuccess || hipMalloc(&v2, sizeof(int) * n) != hipSuccess ||
+      hipMalloc(&sc, sort_scratch_bytes(n)) != hipSuccess ||
+      radix_sort_pairs(keys, k2, vals, v2, n, end_bit, sc, s) != hipSuccess ||
+      hipMemcpyAsync(keys, k2, sizeof(unsigned) * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(vals, v2, sizeof(int) * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = TEFMM_ERR_HIP;
+  if (k2) (void)hipFree(k2);
+  if (v2) (void)hipFree(v2);
+  if (sc) (void)hipFree(sc);
+  return rc;
+}
+
+extern "C" int tefmm_exclusive_scan(int64_t n, const unsigned* in, unsigned* out, void* stream) {
+  if (n < 1 || n > 2147483647LL || !in || !out) return TEFMM_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  void* sc = nullptr;
+  int rc = TEFMM_OK;
+  if (hipMalloc(&sc, scan_scratch_bytes(n)) != hipSuccess || exclusive_scan(in, out, n, sc, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = TEFMM_ERR_HIP;
+  if (sc) (void)hipFree(sc);
   return rc;
 }
