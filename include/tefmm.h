@@ -250,6 +250,27 @@ int tefmm_gmres(tefmm_t h, double tau_re, double tau_im, const double* b, double
 int tefmm_evaluate_batch(tefmm_t* hs, int n_geom, const double* const* q, const int* n_rhs,
                          double* const* phi, void* stream);
 
+/* The same batched evaluation with the near fields of all geometries in one
+ * persistent launch (the C5 batching of the paper's workloads, E2): a work queue
+ * of (geometry, phase, tile) items, taken in ticket order by a fixed grid of
+ * workgroups: first the symmetric near-field items of every geometry and layer
+ * group (workgroup h of leaf A, Sec. 3.2's local direct interactions), then one
+ * gather item per leaf, which waits until its geometry's near-field items are done
+ * (a bounded wait; see tefmm_batch_check).  The far fields stay graph branches, one
+ * per geometry, running beside the queue; each geometry's final scaling follows the
+ * queue.  Needs one charge vector per geometry, one precision for all handles and
+ * the symmetric near field with 1 or 2 targets per lane (tefmm_options.p2p_targets),
+ * else TEFMM_ERR_UNSUPPORTED.  Results equal tefmm_evaluate_batch's bit for bit (the
+ * same per-item arithmetic in the same order).  The graph and the queue's work list
+ * (allocated with hs[0]'s allocator) are owned by hs[0]. */
+int tefmm_evaluate_batch_queue(tefmm_t* hs, int n_geom, const double* const* q, const int* n_rhs,
+                               double* const* phi, void* stream);
+
+/* Synchronise `stream` and report whether the last queue launch of the batch owned by
+ * h had a gather item stop waiting (after about 4M polls: TEFMM_ERR_STATE, its
+ * results are wrong); TEFMM_OK otherwise (also for a batch without a queue). */
+int tefmm_batch_check(tefmm_t h, void* stream);
+
 /* Autotuner: times the evaluation of the handle's own geometry (unit charges)
  * for tree depths d-1, d, d+1 (d the current depth, clamped to [2, 7]) and for
  * 16 or 32 target boxes per M2L workgroup, then rebuilds the handle with the

@@ -33,7 +33,7 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_mlp_adam_step", "tefmm_mlp_train", "tefmm_surrogate_default_options", "tefmm_surrogate_train",
            "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
            "tefmm_reset_timers", "tefmm_set_allocator", "tefmm_gmres", "tefmm_sigma_derivatives",
-           "tefmm_radix_sort", "tefmm_exclusive_scan"]
+           "tefmm_radix_sort", "tefmm_exclusive_scan", "tefmm_evaluate_batch_queue", "tefmm_batch_check"]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -152,6 +152,9 @@ def lib():
         L.tefmm_selftest_mfma.argtypes = []
         L.tefmm_evaluate_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i32),
                                            ctypes.POINTER(vp), vp]
+        L.tefmm_evaluate_batch_queue.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
+                                                 ctypes.POINTER(i32), ctypes.POINTER(vp), vp]
+        L.tefmm_batch_check.argtypes = [vp, vp]
         L.tefmm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.tefmm_dcim_cross.argtypes = [ctypes.POINTER(MediumC), ctypes.POINTER(OptionsC), i32, i32, i32, dbl, i32,
                                        dbl, dbl, i32, ctypes.POINTER(i32), vp, vp, ctypes.POINTER(dbl)]
@@ -198,6 +201,12 @@ def exclusive_scan(x, out, stream=None):
     """out = exclusive prefix sums of the device int32 tensor x, unsigned 32-bit
     arithmetic (tefmm_exclusive_scan)."""
     _check(lib().tefmm_exclusive_scan(x.numel(), x.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
+
+
+def batch_check(handle, stream=None):
+    """Synchronise and raise if the batch's near-field queue had a wait give up
+    (tefmm_batch_check)."""
+    _check(lib().tefmm_batch_check(handle.h, _stream_ptr(stream)), handle.h)
 
 
 def _medium(k, d):
@@ -371,9 +380,10 @@ class TEFMM:
         return out.reshape(nb, nC)
 
 
-def evaluate_batch(handles, qs, outs=None, stream=None):
+def evaluate_batch(handles, qs, outs=None, stream=None, queue=False):
     """Evaluate several TEFMM handles in one graph launch.  qs: list of torch complex128 tensors
-    (N_g,) or (R_g, N_g) on the GPU.  Returns the list of outputs (same shapes)."""
+    (N_g,) or (R_g, N_g) on the GPU.  Returns the list of outputs (same shapes).  queue: the
+    near fields of all geometries in one persistent launch (tefmm_evaluate_batch_queue)."""
     import torch
     n = len(handles)
     qs2, outs2, shapes = [], [], []
@@ -389,7 +399,8 @@ def evaluate_batch(handles, qs, outs=None, stream=None):
     Q = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs2])
     P = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs2])
     R = (ctypes.c_int * n)(*[q.shape[0] for q in qs2])
-    _check(lib().tefmm_evaluate_batch(H, n, Q, R, P, _stream_ptr(stream)), handles[0].h)
+    fn = lib().tefmm_evaluate_batch_queue if queue else lib().tefmm_evaluate_batch
+    _check(fn(H, n, Q, R, P, _stream_ptr(stream)), handles[0].h)
     # keep the inputs alive until the caller synchronises (the graph reads them)
     evaluate_batch._keep = (qs2, outs2)
     return [o.reshape(s) for o, s in zip(outs2, shapes)]

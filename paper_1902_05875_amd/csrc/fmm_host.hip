@@ -228,10 +228,21 @@ struct tefmm_ctx {
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> ev;  // EV_RING sets of 8 phase events
   int ev_next = 0, ev_count = 0;
+    // the persistent near-field queue (tefmm_evaluate_batch_queue)
+    bool queue = false;
+    hipStream_t nf = nullptr;
+    std::vector<hipEvent_t> evq;  // charges of geometry g in tree order
+    hipEvent_t ev_nf = nullptr;   // the queue's near fields done
+    NFQueueGeom* d_geo = nullptr;
+    int* d_start = nullptr;       // p2p_start then gather_start
+    unsigned* d_ctr = nullptr;    // ticket, then done[ngeo]
+    int* d_err = nullptr;
+    int ngeo = 0, qgrid = 0;
+    bool f32q = false;
   } batch;
 };
 
-static void batch_destroy(tefmm_ctx::Batch& b);
+static void batch_destroy(tefmm_t h, tefmm_ctx::Batch& b);
 
 // Device memory owned by a handle: from the caller's allocator when one is set
 // (tefmm_set_allocator), else hipMalloc / hipFree.  A failed allocation reads as
@@ -474,7 +485,7 @@ extern "C" int tefmm_set_allocator(tefmm_t h, tefmm_alloc_fn alloc, tefmm_free_f
     return fail(h, TEFMM_ERR_INVALID_ARG, "tefmm_set_allocator: give both functions or neither");
   // everything the handle holds is released with the allocator that gave it, then the
   // constant tables are uploaded again into memory from the new one
-  batch_destroy(h->batch);
+  batch_destroy(h, h->batch);
   free_geometry(h);
   dfree(h, h->d_xyz_user);
   free_constant_tables(h);
@@ -496,7 +507,7 @@ extern "C" void tefmm_destroy(tefmm_t h) {
     if (h->e_gjoin[i]) (void)hipEventDestroy(h->e_gjoin[i]);
     if (h->sg[i]) (void)hipStreamDestroy(h->sg[i]);
   }
-  batch_destroy(h->batch);
+  batch_destroy(h, h->batch);
   dfree(h, h->d_xyz_user);
   delete h;
 }
@@ -1645,7 +1656,26 @@ static int check_eval_args(tefmm_t h, const double* q, int nrhs, double* phi) {
 
 // Enqueue one evaluation on stream s (buffers must already be sized for nrhs).
 // With timed = false no events are recorded (graph capture).
-static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, hipStream_t s, bool timed) {
+// The final scaling of the far- and near-field sums into the caller's order (k_finalize).
+static int enqueue_finalize(tefmm_t h, int nrhs, double* phi, hipStream_t s) {
+  for (auto& g : h->groups) {
+    double sr = 1.0 / (4 * PI), si = 0.0;
+    if (h->opt.normalization == TEFMM_NORM_PAPER) {  // divide by i k of the target layer
+      const double kk = h->med.k[g.layer];
+      sr = 0.0, si = -1.0 / kk;
+    }
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((g.count + 255) / 256), nrhs), dim3(256), 0, s, h->d_phi,
+                       h->d_phi_near, h->d_perm, g.start, g.count, h->n, sr, si, (double2*)phi);
+    HIPCHK(h, hipGetLastError());
+  }
+  return TEFMM_OK;
+}
+
+// q_ready: the near field is run elsewhere (the batched queue of tefmm_evaluate_batch_queue):
+// record q_ready once the charges are in tree order, leave the near field out and stop
+// before the final scaling (enqueue_finalize, after the near field is done).
+static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, hipStream_t s, bool timed,
+                            hipEvent_t q_ready = nullptr) {
   if (timed && h->ev.empty()) {
     h->ev.resize(9 * EV_RING);
     for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
@@ -1696,6 +1726,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
   hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, (const double2*)q,
                      h->d_perm, n, h->d_q);
   HIPCHK(h, hipGetLastError());
+  if (q_ready) HIPCHK(h, hipEventRecord(q_ready, s));
   // near field (P2P, Eq. totalinteraction free part) on the second stream: it reads only
   // particles and charges and writes its own sum, so it overlaps the far field.  Under
   // graph capture (the batch, whose geometries are already concurrent branches) it
@@ -1766,7 +1797,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     if (fork) HIPCHK(h, hipEventRecord(h->e_join, h->s2));
     return TEFMM_OK;
   };
-  if (!late) {
+  if (!late && !q_ready) {
     const int rc = near_field();
     if (rc != TEFMM_OK) return rc;
   }
@@ -1815,7 +1846,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     }
   }
   EVREC(2);
-  if (late) {
+  if (late && !q_ready) {
     const int rc = near_field();
     if (rc != TEFMM_OK) return rc;
   }
@@ -1938,22 +1969,15 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     HIPCHK(h, hipGetLastError());
   }
   EVREC(5);
-  if (fork) HIPCHK(h, hipStreamWaitEvent(s, h->e_join, 0));
-  for (auto& g : h->groups) {
-    double sr = 1.0 / (4 * PI), si = 0.0;
-    if (h->opt.normalization == TEFMM_NORM_PAPER) {  // divide by i k of the target layer
-      const double kk = h->med.k[g.layer];
-      sr = 0.0, si = -1.0 / kk;
-    }
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((g.count + 255) / 256), nrhs), dim3(256), 0, s, h->d_phi,
-                       h->d_phi_near, h->d_perm, g.start, g.count, n, sr, si, (double2*)phi);
-    HIPCHK(h, hipGetLastError());
-  }
-  EVREC(7);
-#undef EVREC
   h->st.m2l_flops = m2l_flops;
   h->st.m2l_launches = m2l_launches;
   h->st.n_rhs = nrhs;
+  if (q_ready) return TEFMM_OK;
+  if (fork) HIPCHK(h, hipStreamWaitEvent(s, h->e_join, 0));
+  const int rc = enqueue_finalize(h, nrhs, phi, s);
+  if (rc != TEFMM_OK) return rc;
+  EVREC(7);
+#undef EVREC
   return TEFMM_OK;
 }
 
@@ -2132,19 +2156,38 @@ extern "C" int tefmm_gmres(tefmm_t h, double tau_re, double tau_im, const double
   return rc;
 }
 
-static void batch_clear(tefmm_ctx::Batch& b) {
+static void batch_clear(tefmm_t h, tefmm_ctx::Batch& b) {
   if (b.exec) (void)hipGraphExecDestroy(b.exec);
   if (b.graph) (void)hipGraphDestroy(b.graph);
   b.exec = nullptr, b.graph = nullptr;
   b.hs.clear(), b.gens.clear(), b.q.clear(), b.phi.clear(), b.nrhs.clear();
+  dfree(h, b.d_geo), dfree(h, b.d_start), dfree(h, b.d_ctr), dfree(h, b.d_err);
+  b.queue = false;
 }
 
-static void batch_destroy(tefmm_ctx::Batch& b) {
-  batch_clear(b);
+static void batch_destroy(tefmm_t h, tefmm_ctx::Batch& b) {
+  batch_clear(h, b);
   for (auto& e : b.ev) (void)hipEventDestroy(e);
+  for (auto& e : b.evq) (void)hipEventDestroy(e);
+  if (b.ev_nf) (void)hipEventDestroy(b.ev_nf);
   for (auto& st : b.side) (void)hipStreamDestroy(st);
   if (b.origin) (void)hipStreamDestroy(b.origin);
-  b.ev.clear(), b.side.clear(), b.origin = nullptr;
+  if (b.nf) (void)hipStreamDestroy(b.nf);
+  b.ev.clear(), b.evq.clear(), b.side.clear(), b.origin = nullptr, b.nf = nullptr, b.ev_nf = nullptr;
+}
+
+// Whether the geometries' near fields can run as one queue: one charge vector each, one
+// precision, the symmetric near field with at most 2 targets per lane.
+static bool queue_eligible(tefmm_t* hs, int n_geom, const int* nrhs, std::string& why) {
+  for (int g = 0; g < n_geom; ++g) {
+    tefmm_t h = hs[g];
+    if (nrhs[g] != 1) return why = "several charge vectors", false;
+    if (h->opt.precision != hs[0]->opt.precision) return why = "mixed precisions", false;
+    if (!h->d_part) return why = "the one-sided near field (p2p_targets = -1)", false;
+    for (auto& gr : h->groups)
+      if (gr.p2p_tpl > 2) return why = "4 targets per lane", false;
+  }
+  return true;
 }
 
 // Batched evaluation (E2): the geometries' evaluation sequences are captured once
@@ -2164,12 +2207,12 @@ extern "C" int tefmm_evaluate_batch(tefmm_t* hs, int n_geom, const double* const
     if (rc != TEFMM_OK) return fail(h0, rc, "geometry " + std::to_string(g) + ": " + hs[g]->err);
   }
   tefmm_ctx::Batch& b = h0->batch;
-  bool same = b.exec && (int)b.hs.size() == n_geom;
+  bool same = b.exec && (int)b.hs.size() == n_geom && !b.queue;
   for (int g = 0; same && g < n_geom; ++g)
     same = b.hs[g] == hs[g] && b.gens[g] == hs[g]->gen && b.q[g] == q[g] && b.phi[g] == phi[g] &&
            b.nrhs[g] == nrhs[g];
   if (!same) {
-    batch_clear(b);
+    batch_clear(h0, b);
     if (!b.origin) HIPCHK(h0, hipStreamCreateWithFlags(&b.origin, hipStreamNonBlocking));
     while ((int)b.side.size() < n_geom) {
       hipStream_t st;
@@ -2209,6 +2252,130 @@ extern "C" int tefmm_evaluate_batch(tefmm_t* hs, int n_geom, const double* const
     b.nrhs.assign(nrhs, nrhs + n_geom);
   }
   HIPCHK(h0, hipGraphLaunch(b.exec, (hipStream_t)stream));
+  return TEFMM_OK;
+}
+
+// Batched evaluation with the near fields of all geometries in one persistent launch
+// (k_nf_queue), enqueued directly on streams (no graph): per geometry the charges are put
+// in tree order and the far field runs on a stream of its own; the queue waits for every
+// geometry's charges, and each geometry's final scaling waits for the queue.
+extern "C" int tefmm_evaluate_batch_queue(tefmm_t* hs, int n_geom, const double* const* q, const int* nrhs,
+                                          double* const* phi, void* stream) {
+  if (!hs || n_geom < 1 || !q || !nrhs || !phi || !hs[0]) return TEFMM_ERR_INVALID_ARG;
+  tefmm_t h0 = hs[0];
+  for (int g = 0; g < n_geom; ++g) {
+    if (!hs[g]) return fail(h0, TEFMM_ERR_INVALID_ARG, "null handle in batch");
+    for (int g2 = 0; g2 < g; ++g2)
+      if (hs[g2] == hs[g]) return fail(h0, TEFMM_ERR_INVALID_ARG, "a handle appears twice in the batch");
+    int rc = check_eval_args(hs[g], q[g], nrhs[g], phi[g]);
+    if (rc != TEFMM_OK) return fail(h0, rc, "geometry " + std::to_string(g) + ": " + hs[g]->err);
+    rc = ensure_rhs(hs[g], nrhs[g]);
+    if (rc != TEFMM_OK) return fail(h0, rc, "geometry " + std::to_string(g) + ": " + hs[g]->err);
+  }
+  std::string why;
+  if (!queue_eligible(hs, n_geom, nrhs, why))
+    return fail(h0, TEFMM_ERR_UNSUPPORTED, "near-field queue: " + why + " (use tefmm_evaluate_batch)");
+  hipStream_t s = (hipStream_t)stream;
+  tefmm_ctx::Batch& b = h0->batch;
+  // the work list (one entry per geometry and layer group) is uploaded when the handle
+  // list or a handle's buffers changed
+  bool same = b.queue && (int)b.hs.size() == n_geom;
+  for (int g = 0; same && g < n_geom; ++g) same = b.hs[g] == hs[g] && b.gens[g] == hs[g]->gen;
+  while ((int)b.side.size() < n_geom) {
+    hipStream_t st;
+    HIPCHK(h0, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    b.side.push_back(st);
+  }
+  while ((int)b.ev.size() < n_geom + 1) {
+    hipEvent_t e;
+    HIPCHK(h0, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b.ev.push_back(e);
+  }
+  if (!same) {
+    batch_clear(h0, b);
+    if (!b.nf) HIPCHK(h0, hipStreamCreateWithFlags(&b.nf, hipStreamNonBlocking));
+    if (!b.ev_nf) HIPCHK(h0, hipEventCreateWithFlags(&b.ev_nf, hipEventDisableTiming));
+    while ((int)b.evq.size() < n_geom) {
+      hipEvent_t e;
+      HIPCHK(h0, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b.evq.push_back(e);
+    }
+    std::vector<NFQueueGeom> geo;
+    std::vector<int> st{0}, gs{0};
+    for (int g = 0; g < n_geom; ++g) {
+      tefmm_t h = hs[g];
+      for (auto& gr : h->groups) {
+        NFQueueGeom e;
+        std::memset(&e, 0, sizeof(e));
+        PassArgs& a = e.a;
+        a.p = h->opt.p, a.nC = h->nC, a.k = h->med.k[gr.layer], a.n = h->n, a.xs = h->d_xs, a.q = h->d_q;
+        a.phi = h->d_phi_near, a.leaf_start = h->d_leaf_start, a.leaf_count = h->d_leaf_count;
+        a.leaf_base = gr.leaf_base, a.mi = h->d_mi;
+        for (int c = 0; c < 3; ++c) a.lo[c] = gr.lo[c];
+        a.nbox_dim = 1 << gr.depth, a.h = gr.side / (1 << gr.depth);
+        const int nl = 1 << (3 * gr.depth);
+        e.np = gr.np, e.part = h->d_part, e.G = gr.p2p_split, e.tpl = gr.p2p_tpl;
+        e.poly = h->opt.precision == TEFMM_MIXED_FP32 && gr.np_on ? 1 : 0;
+        e.p2p_items = e.G * nl, e.gather_items = nl;
+        geo.push_back(e);
+        st.push_back(st.back() + e.p2p_items);
+        gs.push_back(gs.back() + e.gather_items);
+      }
+    }
+    const int ng = (int)geo.size();
+    std::vector<int> starts(st);
+    starts.insert(starts.end(), gs.begin(), gs.end());
+    HIPCHK(h0, dmalloc(h0, &b.d_geo, sizeof(NFQueueGeom) * ng));
+    HIPCHK(h0, dmalloc(h0, &b.d_start, sizeof(int) * starts.size()));
+    HIPCHK(h0, dmalloc(h0, &b.d_ctr, sizeof(unsigned) * (1 + ng)));
+    HIPCHK(h0, dmalloc(h0, &b.d_err, sizeof(int)));
+    HIPCHK(h0, hipMemcpy(b.d_geo, geo.data(), sizeof(NFQueueGeom) * ng, hipMemcpyHostToDevice));
+    HIPCHK(h0, hipMemcpy(b.d_start, starts.data(), sizeof(int) * starts.size(), hipMemcpyHostToDevice));
+    HIPCHK(h0, hipMemset(b.d_err, 0, sizeof(int)));
+    b.ngeo = ng;
+    b.qgrid = (int)std::min<int64_t>((int64_t)st.back() + gs.back(), 1024);
+    b.f32q = hs[0]->opt.precision == TEFMM_MIXED_FP32;
+    b.hs.assign(hs, hs + n_geom);
+    b.gens.clear();
+    for (int g = 0; g < n_geom; ++g) b.gens.push_back(hs[g]->gen);
+    b.queue = true;
+  }
+  NFQueueArgs qa;
+  std::memset(&qa, 0, sizeof(qa));
+  qa.geo = b.d_geo, qa.ngeo = b.ngeo, qa.p2p_start = b.d_start, qa.gather_start = b.d_start + (b.ngeo + 1);
+  qa.ticket = b.d_ctr, qa.done = b.d_ctr + 1, qa.err = b.d_err, qa.spin_limit = 1 << 22;
+  HIPCHK(h0, hipEventRecord(b.ev[n_geom], s));
+  for (int g = 0; g < n_geom; ++g) {
+    HIPCHK(h0, hipStreamWaitEvent(b.side[g], b.ev[n_geom], 0));
+    const int rc = enqueue_evaluate(hs[g], q[g], nrhs[g], phi[g], b.side[g], false, b.evq[g]);
+    if (rc != TEFMM_OK) return fail(h0, rc, "geometry " + std::to_string(g) + ": " + hs[g]->err);
+    HIPCHK(h0, hipStreamWaitEvent(b.nf, b.evq[g], 0));
+  }
+  hipLaunchKernelGGL(k_nf_queue_reset, dim3(1), dim3(64), 0, b.nf, qa.ticket, qa.done, qa.ngeo, qa.err);
+  HIPCHK(h0, hipGetLastError());
+  if (b.f32q)
+    hipLaunchKernelGGL(k_nf_queue<float>, dim3(b.qgrid), dim3(256), 0, b.nf, qa);
+  else
+    hipLaunchKernelGGL(k_nf_queue<double>, dim3(b.qgrid), dim3(256), 0, b.nf, qa);
+  HIPCHK(h0, hipGetLastError());
+  HIPCHK(h0, hipEventRecord(b.ev_nf, b.nf));
+  for (int g = 0; g < n_geom; ++g) {
+    HIPCHK(h0, hipStreamWaitEvent(b.side[g], b.ev_nf, 0));
+    const int rc = enqueue_finalize(hs[g], nrhs[g], phi[g], b.side[g]);
+    if (rc != TEFMM_OK) return fail(h0, rc, "geometry " + std::to_string(g) + ": " + hs[g]->err);
+    HIPCHK(h0, hipEventRecord(b.ev[g], b.side[g]));
+    HIPCHK(h0, hipStreamWaitEvent(s, b.ev[g], 0));
+  }
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_batch_check(tefmm_t h, void* stream) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  HIPCHK(h, hipStreamSynchronize((hipStream_t)stream));
+  if (!h->batch.queue || !h->batch.d_err) return TEFMM_OK;
+  int err = 0;
+  HIPCHK(h, hipMemcpy(&err, h->batch.d_err, sizeof(int), hipMemcpyDeviceToHost));
+  if (err) return fail(h, TEFMM_ERR_STATE, "near-field queue: a gather item stopped waiting (its result is wrong)");
   return TEFMM_OK;
 }
 

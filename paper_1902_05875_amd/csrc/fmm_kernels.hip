@@ -1407,28 +1407,43 @@ __device__ __forceinline__ void p2p_sym8_f64(int t, const double (&tx)[T], const
   }
 }
 
-// G workgroups per leaf A (each taking every G-th pass), T targets per lane: the
-// 64 T targets of a pass are the same for the NW waves, which share out the staged
-// source chunks (SC sources; chunk c of the pass, counted over the ranges, goes to
-// wave c mod NW).
-// Each wave stages, evaluates and writes its chunks' source-side sums on its
-// own; at the end of the pass the waves' target sums are added in wave order.
-template <typename R, int T, int NW, bool POLY>
-__global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part,
-                                                     NearPoly np) {
+// The symmetric near field's LDS: NW waves, up to TMAX targets per lane.
+template <typename R, int TMAX, int NW>
+struct SymShared {
+  typedef typename SymTypes<R>::R4 R4;
+  typedef typename SymTypes<R>::R2 R2;
+  static constexpr bool F32 = std::is_same<R, float>::value;
+  static constexpr int SC = 128;
+  R4 s4[NW][SC];  // x, y, z (FP32: scaled) and the real part of the charge
+  R sqi[NW][SC];
+  R psw[NW][2 * SC];
+  // FP32 only: source indices and near-singular corrections of the source-side sums
+  int sidx[F32 ? NW : 1][F32 ? SC : 1];
+  float dps[F32 ? NW : 1][F32 ? 2 * SC : 1];
+  R2 tacc[NW > 1 ? NW : 1][NW > 1 ? 64 * TMAX : 1];
+};
+
+// One work item of the symmetric near field, wi = leaf G + half: workgroup `half` of
+// the G of leaf A takes A's target passes half, half + G, ... (T targets per lane;
+// the 64 T targets of a pass are the same for the NW waves, which share out the
+// staged source chunks of SC sources: chunk c of the pass, counted over the ranges,
+// goes to wave c mod NW).  Each wave stages, evaluates and writes its chunks'
+// source-side sums on its own (part[G slot + half]); at the end of a pass the waves'
+// target sums are added in wave order.  Charge vector r of nrhs.
+template <typename R, int T, int NW, bool POLY, typename SH>
+__device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r, int G,
+                                             typename SymTypes<R>::R2* part, const NearPoly& np, int wi, SH& sh) {
   typedef typename SymTypes<R>::R4 R4;
   typedef typename SymTypes<R>::R2 R2;
   constexpr bool F32 = std::is_same<R, float>::value;
   constexpr int SC = 128, TP = 64 * T;  // sources per chunk, targets per pass
-  __shared__ R4 s4[NW][SC];  // x, y, z (FP32: scaled) and the real part of the charge
-  __shared__ R sqi[NW][SC];
-  __shared__ R psw[NW][2 * SC];
-  // FP32 only: source indices, near-singular corrections of the source-side sums and
-  // near-pair masks of the current eight sources (per step and lane)
-  __shared__ int sidx[F32 ? NW : 1][F32 ? SC : 1];
-  __shared__ float dps[F32 ? NW : 1][F32 ? 2 * SC : 1];
-  __shared__ R2 tacc[NW > 1 ? NW : 1][NW > 1 ? TP : 1];
-  const int r = blockIdx.y, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  auto& s4 = sh.s4;
+  auto& sqi = sh.sqi;
+  auto& psw = sh.psw;
+  auto& sidx = sh.sidx;
+  auto& dps = sh.dps;
+  auto& tacc = sh.tacc;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int nb = a.nbox_dim;
   // FP32: coordinates in units of 2 pi / k (see pair_kernel); FP64: physical
   const double kap = F32 ? a.k / 6.283185307179586477 : 1.0;
@@ -1437,19 +1452,16 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G
   // FP64: k r <= pi/4 over the 3 x 3 x 3 leaf block (its longest pair: 2 sqrt(3) h)
   const bool small = a.k * 3.4641016151377546 * a.h <= 0.78539816339744831;
   const double2* q = a.q + (int64_t)r * a.n;
-  // the quadratics' middle coefficients in vector registers for the whole kernel: a
-  // multiply-add takes at most one scalar operand, and left in scalar registers they
-  // are copied over for every pair
+  // the quadratics' middle coefficients in vector registers: a multiply-add takes at
+  // most one scalar operand, and left in scalar registers they are copied over for
+  // every pair
   NearPoly npv = np;
   if constexpr (F32 && POLY) asm volatile("" : "+v"(npv.c1), "+v"(npv.s1));
-  // G workgroups per leaf, the one with index `half` taking the target passes half,
-  // half + G, half + 2 G, ... (more, shorter workgroups: less of a tail when the last ones
-  // run); each keeps its own source-side sums, part[G slot + half]
-  for (int wi = blockIdx.x; wi < G * nb * nb * nb; wi += gridDim.x) {
+  {
     const int leaf = wi / G, half = wi - leaf * G;
     const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
     const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
-    if (half * TP >= cnt) continue;
+    if (half * TP >= cnt) return;
     // one pass over the neighbourhood for 64 TT targets from c0 on
     auto pass = [&](auto tt, int c0) {
       constexpr int TT = decltype(tt)::value;
@@ -1587,13 +1599,23 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G
   }
 }
 
+// G workgroups per leaf (see p2p_sym_item), charge vector blockIdx.y.
+template <typename R, int T, int NW, bool POLY>
+__global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part,
+                                                     NearPoly np) {
+  __shared__ SymShared<R, T, NW> sh;
+  const int nb = a.nbox_dim;
+  for (int wi = blockIdx.x; wi < G * nb * nb * nb; wi += gridDim.x)
+    p2p_sym_item<R, T, NW, POLY>(a, nrhs, blockIdx.y, G, part, np, wi, sh);
+}
+
 // Adds to each particle of leaf B the source-side sums that its backward
 // neighbours A = B - o (o in the forward half, A inside the grid and not empty)
 // left in part, in slot order (see k_p2p_sym).
 template <typename R2>
-__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* part) {
+__device__ __forceinline__ void p2p_sym_gather_leaf(const PassArgs& a, int nrhs, int tp, int G, const R2* part,
+                                                    int leaf, int r) {
   typedef decltype(R2::x) R;
-  const int leaf = blockIdx.x, r = blockIdx.y;
   const int nb = a.nbox_dim;
   const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
   const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
@@ -1626,6 +1648,90 @@ __global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* 
     *o = make_double2(o->x + (double)sr * kap, o->y + (double)si * kap);
   }
 }
+
+template <typename R2>
+__global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* part) {
+  p2p_sym_gather_leaf<R2>(a, nrhs, tp, G, part, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------------------
+// The batched near field as one persistent launch (see NFQueueGeom).  Items are
+// taken in ticket order, so a gather item only ever waits for pair items that
+// workgroups already hold and finish without waiting: the wait ends.  It is still
+// bounded (spin_limit polls, then err is set and the item goes on).  A pair item's
+// stores reach the other workgroups through a release at agent scope after the
+// workgroup barrier; a gather item acquires before its reads.
+// ---------------------------------------------------------------------------
+__global__ void k_nf_queue_reset(unsigned* ticket, unsigned* done, int ngeo, int* err) {
+  const int t = threadIdx.x;
+  if (t == 0) *ticket = 0u, *err = 0;
+  for (int g = t; g < ngeo; g += blockDim.x) done[g] = 0u;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_nf_queue(NFQueueArgs q) {
+  typedef typename SymTypes<R>::R2 R2;
+  constexpr bool F32 = std::is_same<R, float>::value;
+  __shared__ SymShared<R, 2, 4> sh;
+  __shared__ unsigned s_it;
+  const unsigned P = (unsigned)q.p2p_start[q.ngeo], Q = P + (unsigned)q.gather_start[q.ngeo];
+  for (;;) {
+    __syncthreads();  // the previous item no longer needs s_it or the LDS
+    if (threadIdx.x == 0) s_it = atomicAdd(q.ticket, 1u);
+    __syncthreads();
+    const unsigned it = s_it;
+    if (it >= Q) return;
+    if (it < P) {
+      int g = 0;
+      while ((unsigned)q.p2p_start[g + 1] <= it) ++g;
+      const NFQueueGeom& ge = q.geo[g];
+      const int wi = (int)(it - (unsigned)q.p2p_start[g]);
+      R2* part = (R2*)ge.part;
+      if constexpr (F32) {
+        if (ge.tpl == 2) {
+          if (ge.poly)
+            p2p_sym_item<float, 2, 4, true>(ge.a, 1, 0, ge.G, part, ge.np, wi, sh);
+          else
+            p2p_sym_item<float, 2, 4, false>(ge.a, 1, 0, ge.G, part, ge.np, wi, sh);
+        } else {
+          if (ge.poly)
+            p2p_sym_item<float, 1, 4, true>(ge.a, 1, 0, ge.G, part, ge.np, wi, sh);
+          else
+            p2p_sym_item<float, 1, 4, false>(ge.a, 1, 0, ge.G, part, ge.np, wi, sh);
+        }
+      } else {
+        if (ge.tpl == 2)
+          p2p_sym_item<double, 2, 4, false>(ge.a, 1, 0, ge.G, part, ge.np, wi, sh);
+        else
+          p2p_sym_item<double, 1, 4, false>(ge.a, 1, 0, ge.G, part, ge.np, wi, sh);
+      }
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_fetch_add(&q.done[g], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const unsigned j = it - P;
+      int g = 0;
+      while ((unsigned)q.gather_start[g + 1] <= j) ++g;
+      const NFQueueGeom& ge = q.geo[g];
+      if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(&q.done[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)ge.p2p_items) {
+          if (++spins > q.spin_limit) {
+            atomicExch(q.err, 1);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(8);
+        }
+      }
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      p2p_sym_gather_leaf<R2>(ge.a, 1, 64 * ge.tpl, ge.G, (const R2*)ge.part, (int)(j - (unsigned)q.gather_start[g]),
+                              0);
+    }
+  }
+}
+template __global__ void k_nf_queue<float>(NFQueueArgs);
+template __global__ void k_nf_queue<double>(NFQueueArgs);
 
 template __global__ void k_p2p_sym<float, 1, 4, false>(PassArgs, int, int, float2*, NearPoly);
 template __global__ void k_p2p_sym<float, 2, 4, false>(PassArgs, int, int, float2*, NearPoly);

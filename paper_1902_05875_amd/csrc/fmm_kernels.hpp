@@ -239,6 +239,31 @@ __global__ void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2*
 template <typename R2>
 __global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* part);
 
+// Near fields of several geometries in one persistent launch: a work queue of
+// (geometry, phase, tile) items taken in ticket order, first every symmetric-pair
+// item (geometry g: G nb^3 of them), then every gather item (one per leaf), which
+// waits until its geometry's pair items are done.  One charge vector.
+struct NFQueueGeom {
+  PassArgs a;    // a.phi: the geometry's near-field sums
+  NearPoly np;
+  void* part;    // source-side slot sums (float2 or double2)
+  int G, tpl, poly;
+  int p2p_items, gather_items;
+};
+struct NFQueueArgs {
+  const NFQueueGeom* geo;
+  int ngeo;
+  const int* p2p_start;     // [ngeo + 1] prefix sums of p2p_items
+  const int* gather_start;  // [ngeo + 1] prefix sums of gather_items
+  unsigned* ticket;         // next item
+  unsigned* done;           // [ngeo] pair items finished
+  int* err;                 // set to 1 when a wait gives up (spin_limit polls)
+  int spin_limit;
+};
+template <typename R>
+__global__ void k_nf_queue(NFQueueArgs q);
+__global__ void k_nf_queue_reset(unsigned* ticket, unsigned* done, int ngeo, int* err);
+
 // GMRES vector kernels (complex128): multi-column dot products in two stages, basis
 // updates, axpby.
 constexpr int GM_BLOCKS = 512;

@@ -97,3 +97,50 @@ def test_autotune_keeps_results():
     tg = idx[:, 0].astype(int)
     ref = idx[:, 1] + 1j * idx[:, 2]
     check(f"autotune depth {depth} ncb {ncb}", phi[tg], ref, 1e-4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_queue_equals_graph_batch(precision):
+    """The near fields of all geometries in one persistent launch (work queue of pair items,
+    then gather items waiting on their geometry) give the graph batch's result bit for bit,
+    over three replays with the charges changed in place and eager work between them."""
+    import torch
+    from paper_1902_05875_amd import api, inputs
+    hs, qs = [], []
+    for g, (n, a) in enumerate([(12_000, None), (30_000, 0.1), (7_000, None), (20_000, 0.15), (2_000, None)]):
+        r = np.random.default_rng(950 + g)
+        xyz = inputs.cube(r, n, inputs.MID_CENTRE) if a is None else inputs.irregular(r, n, inputs.MID_CENTRE, a)
+        f = api.TEFMM(K3, D3, p=8, precision=precision)
+        f.set_particles(xyz)
+        hs.append(f)
+        qs.append(torch.from_numpy(inputs.charges(r, n)).cuda())
+    outs_g = [torch.empty_like(q) for q in qs]
+    outs_q = [torch.empty_like(q) for q in qs]
+    for rep in range(3):
+        for q in qs:
+            q.mul_(1.0 + 0.5 * rep)
+        api.evaluate_batch(hs, qs, outs_g)
+        torch.cuda.synchronize()
+        api.evaluate_batch(hs, qs, outs_q, queue=True)
+        api.batch_check(hs[0])
+        x = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")
+        torch.cuda.synchronize()
+        for g in range(len(hs)):
+            a, b = outs_g[g].cpu().numpy(), outs_q[g].cpu().numpy()
+            assert np.array_equal(a, b), (precision, rep, g, np.max(np.abs(a - b)))
+        del x
+    for f in hs:
+        f.close()
+
+
+def test_batch_queue_rejects_several_vectors():
+    import torch
+    from paper_1902_05875_amd import api, inputs
+    r = np.random.default_rng(5)
+    xyz = inputs.cube(r, 3000, inputs.MID_CENTRE)
+    f = api.TEFMM(K3, D3, p=6)
+    f.set_particles(xyz)
+    q = torch.from_numpy(np.ascontiguousarray(inputs.charges(r, 3000, 2).T)).cuda()
+    with pytest.raises(api.TefmmError):
+        api.evaluate_batch([f], [q], queue=True)
+    f.close()

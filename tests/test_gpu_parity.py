@@ -297,9 +297,11 @@ def test_c4_fp32_p7_against_fp64_p13_every_target():
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "expected_c5g.txt")), reason="no stored values")
 @pytest.mark.parametrize("precision,p,tol", [("fp32", 7, 1e-4), ("fp64", 14, 1e-6)])
-def test_c5_geometries_batched_vs_oracle(precision, p, tol):
+@pytest.mark.parametrize("queue", [False, True])
+def test_c5_geometries_batched_vs_oracle(precision, p, tol, queue):
     """The 16 geometries of the batched workload (10k-300k particles, cubes and Example-2
-    domains) evaluated together through tefmm_evaluate_batch (one HIP graph), 16 oracle
+    domains) evaluated together through tefmm_evaluate_batch (one HIP graph; with queue,
+    tefmm_evaluate_batch_queue: the near fields in one persistent launch), 16 oracle
     targets per geometry.  FP64 at p = 14: at p = 13 the Example-2 domain of 170k particles
     (a = 0.05) gives 1.5e-6 at the occupancy depth."""
     import torch
@@ -313,8 +315,8 @@ def test_c5_geometries_batched_vs_oracle(precision, p, tol):
         hs.append(f)
         qs.append(torch.from_numpy(q).cuda())
     outs = [torch.empty_like(x) for x in qs]
-    api.evaluate_batch(hs, qs, outs)
-    torch.cuda.synchronize()
+    api.evaluate_batch(hs, qs, outs, queue=queue)
+    api.batch_check(hs[0])
     got, ref = [], []
     for g in range(len(geoms)):
         rows = a[a[:, 0] == g]
@@ -324,7 +326,8 @@ def test_c5_geometries_batched_vs_oracle(precision, p, tol):
         got.append(phi[idx]), ref.append(rows[:, 2] + 1j * rows[:, 3])
     for f in hs:
         f.close()
-    check(f"C5 16 geometries batched {precision} p={p}", np.concatenate(got), np.concatenate(ref), tol)
+    check(f"C5 16 geometries batched {precision} p={p} queue={queue}", np.concatenate(got), np.concatenate(ref),
+          tol)
 
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(GOLD, "expected_c5r.txt")), reason="no stored values")
