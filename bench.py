@@ -253,10 +253,30 @@ def _cpu_worker(workload, n, procs, k):
     print(json.dumps({"secs": time.perf_counter() - t0, "N": N, "n_sub": n_sub}))
 
 
+def _c5g_error(outs):
+    """Err_2 and Err_max against the oracle's stored values of the 16 geometries (16 targets
+    each; tests/golden/expected_c5g.txt), or None without them."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "expected_c5g.txt")
+    if not os.path.exists(path):
+        return None
+    a = np.loadtxt(path)
+    got, ref = [], []
+    for g, o in enumerate(outs):
+        rows = a[a[:, 0] == g]
+        got.append(o.cpu().numpy()[rows[:, 1].astype(int)])
+        ref.append(rows[:, 2] + 1j * rows[:, 3])
+    got, ref = np.concatenate(got), np.concatenate(ref)
+    return {"err_2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "err_max": float(np.max(np.abs(got - ref) / np.abs(ref))), "targets": int(ref.size)}
+
+
 def run_batch(steps, warmup, p):
     """C5: (i) one geometry of 500,000 particles with 32 charge vectors; (ii) 16 geometries of
-    10k-300k particles evaluated together through tefmm_evaluate_batch (one HIP graph), against
-    the same 16 evaluated one after another.  Mixed FP32, autotuned per geometry."""
+    10k-300k particles evaluated together through tefmm_evaluate_batch (one HIP graph) and
+    through tefmm_evaluate_batch_queue (the near fields in one persistent launch), against the
+    same 16 evaluated one after another, each path's result checked against the oracle's
+    stored values.  Mixed FP32, autotuned per geometry."""
     import numpy as np
     import torch
     from paper_1902_05875_amd import api, inputs
@@ -290,6 +310,20 @@ def run_batch(steps, warmup, p):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_b = ev0.elapsed_time(ev1) / steps
+    err_b = _c5g_error(outs)
+    # the near fields of all 16 geometries in one persistent launch (work queue), far
+    # fields on per-geometry streams beside it
+    for _ in range(warmup):
+        api.evaluate_batch(hs, qs, outs, queue=True)
+    api.batch_check(hs[0])
+    ev0.record(stream)
+    for _ in range(steps):
+        api.evaluate_batch(hs, qs, outs, queue=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    api.batch_check(hs[0])
+    ms_q = ev0.elapsed_time(ev1) / steps
+    err_q = _c5g_error(outs)
     for f, qg, og in zip(hs, qs, outs):
         f.evaluate(qg, out=og)
     torch.cuda.synchronize()
@@ -301,8 +335,9 @@ def run_batch(steps, warmup, p):
     torch.cuda.synchronize()
     ms_s = ev0.elapsed_time(ev1) / steps
     res["geometries"] = {"count": len(geoms), "n_total": ntot, "sizes": [int(x.shape[0]) for x, _ in geoms],
-                         "ms_per_step_batched": ms_b, "ms_per_step_one_by_one": ms_s,
-                         "evals_per_s_batched": ntot / (ms_b / 1e3), "setup_s": round(setup, 3)}
+                         "ms_per_step_batched": ms_b, "ms_per_step_queue": ms_q, "ms_per_step_one_by_one": ms_s,
+                         "evals_per_s_batched": ntot / (ms_b / 1e3), "evals_per_s_queue": ntot / (ms_q / 1e3),
+                         "err_vs_oracle_batched": err_b, "err_vs_oracle_queue": err_q, "setup_s": round(setup, 3)}
     for f in hs:
         f.close()
     return res

@@ -182,6 +182,7 @@ struct tefmm_ctx {
   int* d_leaf_start = nullptr;
   int* d_leaf_count = nullptr;
   int64_t total_leaves = 0;
+  std::vector<int> leaf_count_host;  // copy of d_leaf_count (work lists of the batched near field)
   std::vector<Group> groups;
   // evaluate buffers
   double2 *d_q = nullptr, *d_phi = nullptr, *d_phi_near = nullptr;
@@ -231,10 +232,12 @@ struct tefmm_ctx {
     // the persistent near-field queue (tefmm_evaluate_batch_queue)
     bool queue = false;
     hipStream_t nf = nullptr;
-    std::vector<hipEvent_t> evq;  // charges of geometry g in tree order
     hipEvent_t ev_nf = nullptr;   // the queue's near fields done
+    hipEvent_t ev_q = nullptr;    // every geometry's charges in tree order
+    hipEvent_t ev_ff = nullptr;   // the far-field graph done
     NFQueueGeom* d_geo = nullptr;
-    int* d_start = nullptr;       // p2p_start then gather_start
+    unsigned* d_start = nullptr;  // the work list: pair items, then gather items
+    int n_p2p = 0, n_gather = 0;
     unsigned* d_ctr = nullptr;    // ticket, then done[ngeo]
     int* d_err = nullptr;
     int ngeo = 0, qgrid = 0;
@@ -1436,7 +1439,8 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   HIPCHK(h, dmalloc(h, &h->d_xs, sizeof(double) * 3 * n));
   hipLaunchKernelGGL(k_gather_pos, dim3(nb256), dim3(256), 0, s, src, h->d_perm, n, h->d_xs);
   HIPCHK(h, hipGetLastError());
-  std::vector<int> lc(leaf_off);
+  std::vector<int>& lc = h->leaf_count_host;
+  lc.assign(leaf_off, 0);
   HIPCHK(h, hipMemcpyAsync(lc.data(), h->d_leaf_count, sizeof(int) * leaf_off, hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   dfree(h, d_tmp);
@@ -1671,11 +1675,19 @@ static int enqueue_finalize(tefmm_t h, int nrhs, double* phi, hipStream_t s) {
   return TEFMM_OK;
 }
 
-// q_ready: the near field is run elsewhere (the batched queue of tefmm_evaluate_batch_queue):
-// record q_ready once the charges are in tree order, leave the near field out and stop
-// before the final scaling (enqueue_finalize, after the near field is done).
+// The charges in tree order (k_gather_q).
+static int enqueue_gather_q(tefmm_t h, const double* q, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((h->n + 255) / 256), nrhs), dim3(256), 0, s, (const double2*)q,
+                     h->d_perm, h->n, h->d_q);
+  HIPCHK(h, hipGetLastError());
+  return TEFMM_OK;
+}
+
+// far_only: the far field alone (the batched queue of tefmm_evaluate_batch_queue puts the
+// charges in tree order before, runs the near fields in one launch and the final scaling
+// after): no k_gather_q, no near field, no enqueue_finalize.
 static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, hipStream_t s, bool timed,
-                            hipEvent_t q_ready = nullptr) {
+                            bool far_only = false) {
   if (timed && h->ev.empty()) {
     h->ev.resize(9 * EV_RING);
     for (auto& e : h->ev) HIPCHK(h, hipEventCreate(&e));
@@ -1723,10 +1735,10 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     return ra;
   };
   EVREC(0);
-  hipLaunchKernelGGL(k_gather_q, dim3((unsigned)((n + 255) / 256), nrhs), dim3(256), 0, s, (const double2*)q,
-                     h->d_perm, n, h->d_q);
-  HIPCHK(h, hipGetLastError());
-  if (q_ready) HIPCHK(h, hipEventRecord(q_ready, s));
+  if (!far_only) {
+    const int rc = enqueue_gather_q(h, q, nrhs, s);
+    if (rc != TEFMM_OK) return rc;
+  }
   // near field (P2P, Eq. totalinteraction free part) on the second stream: it reads only
   // particles and charges and writes its own sum, so it overlaps the far field.  Under
   // graph capture (the batch, whose geometries are already concurrent branches) it
@@ -1797,7 +1809,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     if (fork) HIPCHK(h, hipEventRecord(h->e_join, h->s2));
     return TEFMM_OK;
   };
-  if (!late && !q_ready) {
+  if (!late && !far_only) {
     const int rc = near_field();
     if (rc != TEFMM_OK) return rc;
   }
@@ -1846,7 +1858,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     }
   }
   EVREC(2);
-  if (late && !q_ready) {
+  if (late && !far_only) {
     const int rc = near_field();
     if (rc != TEFMM_OK) return rc;
   }
@@ -1972,7 +1984,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
   h->st.m2l_flops = m2l_flops;
   h->st.m2l_launches = m2l_launches;
   h->st.n_rhs = nrhs;
-  if (q_ready) return TEFMM_OK;
+  if (far_only) return TEFMM_OK;
   if (fork) HIPCHK(h, hipStreamWaitEvent(s, h->e_join, 0));
   const int rc = enqueue_finalize(h, nrhs, phi, s);
   if (rc != TEFMM_OK) return rc;
@@ -2168,12 +2180,14 @@ static void batch_clear(tefmm_t h, tefmm_ctx::Batch& b) {
 static void batch_destroy(tefmm_t h, tefmm_ctx::Batch& b) {
   batch_clear(h, b);
   for (auto& e : b.ev) (void)hipEventDestroy(e);
-  for (auto& e : b.evq) (void)hipEventDestroy(e);
   if (b.ev_nf) (void)hipEventDestroy(b.ev_nf);
+  if (b.ev_q) (void)hipEventDestroy(b.ev_q);
+  if (b.ev_ff) (void)hipEventDestroy(b.ev_ff);
   for (auto& st : b.side) (void)hipStreamDestroy(st);
   if (b.origin) (void)hipStreamDestroy(b.origin);
   if (b.nf) (void)hipStreamDestroy(b.nf);
-  b.ev.clear(), b.evq.clear(), b.side.clear(), b.origin = nullptr, b.nf = nullptr, b.ev_nf = nullptr;
+  b.ev.clear(), b.side.clear(), b.origin = nullptr, b.nf = nullptr, b.ev_nf = nullptr;
+  b.ev_q = nullptr, b.ev_ff = nullptr;
 }
 
 // Whether the geometries' near fields can run as one queue: one charge vector each, one
@@ -2256,9 +2270,9 @@ extern "C" int tefmm_evaluate_batch(tefmm_t* hs, int n_geom, const double* const
 }
 
 // Batched evaluation with the near fields of all geometries in one persistent launch
-// (k_nf_queue), enqueued directly on streams (no graph): per geometry the charges are put
-// in tree order and the far field runs on a stream of its own; the queue waits for every
-// geometry's charges, and each geometry's final scaling waits for the queue.
+// (k_nf_queue): the charges of every geometry are put in tree order on the caller's
+// stream, then the far fields (a graph with one branch per geometry, captured once) and
+// the queue run side by side, then every geometry's final scaling follows both.
 extern "C" int tefmm_evaluate_batch_queue(tefmm_t* hs, int n_geom, const double* const* q, const int* nrhs,
                                           double* const* phi, void* stream) {
   if (!hs || n_geom < 1 || !q || !nrhs || !phi || !hs[0]) return TEFMM_ERR_INVALID_ARG;
@@ -2295,13 +2309,11 @@ extern "C" int tefmm_evaluate_batch_queue(tefmm_t* hs, int n_geom, const double*
     batch_clear(h0, b);
     if (!b.nf) HIPCHK(h0, hipStreamCreateWithFlags(&b.nf, hipStreamNonBlocking));
     if (!b.ev_nf) HIPCHK(h0, hipEventCreateWithFlags(&b.ev_nf, hipEventDisableTiming));
-    while ((int)b.evq.size() < n_geom) {
-      hipEvent_t e;
-      HIPCHK(h0, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      b.evq.push_back(e);
-    }
     std::vector<NFQueueGeom> geo;
-    std::vector<int> st{0}, gs{0};
+    // items: (estimated cost, geometry << 24 | work index); pair items sorted longest
+    // first, so that the queue's tail holds the short ones; empty leaves have no item
+    std::vector<std::pair<double, unsigned>> pitems;
+    std::vector<unsigned> gitems;
     for (int g = 0; g < n_geom; ++g) {
       tefmm_t h = hs[g];
       for (auto& gr : h->groups) {
@@ -2316,25 +2328,82 @@ extern "C" int tefmm_evaluate_batch_queue(tefmm_t* hs, int n_geom, const double*
         const int nl = 1 << (3 * gr.depth);
         e.np = gr.np, e.part = h->d_part, e.G = gr.p2p_split, e.tpl = gr.p2p_tpl;
         e.poly = h->opt.precision == TEFMM_MIXED_FP32 && gr.np_on ? 1 : 0;
-        e.p2p_items = e.G * nl, e.gather_items = nl;
+        const int gi = (int)geo.size(), nb = 1 << gr.depth, tp = 64 * e.tpl;
+        const int* lcg = h->leaf_count_host.data() + gr.leaf_base;
+        int np = 0;
+        for (int leaf = 0; leaf < nl; ++leaf) {
+          const int cnt = lcg[leaf];
+          if (!cnt) continue;
+          gitems.push_back((unsigned)gi << 24 | (unsigned)leaf);
+          // sources of a pass: the leaf itself and its forward half of neighbours
+          const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
+          int64_t src = cnt;
+          for (int dx = 0; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dz = -1; dz <= 1; ++dz) {
+                const bool fwd = dx == 1 || (dx == 0 && dy == 1) || (dx == 0 && dy == 0 && dz == 1);
+                const int jx = ix + dx, jy = iy + dy, jz = iz + dz;
+                if (!fwd || jx >= nb || jy < 0 || jy >= nb || jz < 0 || jz >= nb) continue;
+                src += lcg[((int64_t)jx * nb + jy) * nb + jz];
+              }
+          for (int half = 0; half < e.G && half * tp < cnt; ++half) {
+            int64_t tg = 0;
+            for (int c0 = half * tp; c0 < cnt; c0 += e.G * tp) tg += std::min(tp, cnt - c0);
+            pitems.push_back({(double)tg * (double)src, (unsigned)gi << 24 | (unsigned)(leaf * e.G + half)});
+            ++np;
+          }
+        }
+        e.p2p_items = np, e.gather_items = 0;
         geo.push_back(e);
-        st.push_back(st.back() + e.p2p_items);
-        gs.push_back(gs.back() + e.gather_items);
       }
     }
     const int ng = (int)geo.size();
-    std::vector<int> starts(st);
-    starts.insert(starts.end(), gs.begin(), gs.end());
+    if (ng > 255 || pitems.size() > 0x7fffffffu)
+      return fail(h0, TEFMM_ERR_UNSUPPORTED, "near-field queue: at most 255 layer groups in a batch");
+    std::stable_sort(pitems.begin(), pitems.end(),
+                     [](const std::pair<double, unsigned>& x, const std::pair<double, unsigned>& y) {
+                       return x.first > y.first;
+                     });
+    std::vector<unsigned> starts;  // the pair items, then the gather items
+    for (auto& it : pitems) starts.push_back(it.second);
+    starts.insert(starts.end(), gitems.begin(), gitems.end());
+    b.n_p2p = (int)pitems.size(), b.n_gather = (int)gitems.size();
     HIPCHK(h0, dmalloc(h0, &b.d_geo, sizeof(NFQueueGeom) * ng));
-    HIPCHK(h0, dmalloc(h0, &b.d_start, sizeof(int) * starts.size()));
+    HIPCHK(h0, dmalloc(h0, &b.d_start, sizeof(unsigned) * std::max<size_t>(starts.size(), 1)));
     HIPCHK(h0, dmalloc(h0, &b.d_ctr, sizeof(unsigned) * (1 + ng)));
     HIPCHK(h0, dmalloc(h0, &b.d_err, sizeof(int)));
     HIPCHK(h0, hipMemcpy(b.d_geo, geo.data(), sizeof(NFQueueGeom) * ng, hipMemcpyHostToDevice));
-    HIPCHK(h0, hipMemcpy(b.d_start, starts.data(), sizeof(int) * starts.size(), hipMemcpyHostToDevice));
+    if (!starts.empty())
+      HIPCHK(h0, hipMemcpy(b.d_start, starts.data(), sizeof(unsigned) * starts.size(), hipMemcpyHostToDevice));
     HIPCHK(h0, hipMemset(b.d_err, 0, sizeof(int)));
     b.ngeo = ng;
-    b.qgrid = (int)std::min<int64_t>((int64_t)st.back() + gs.back(), 1024);
+    b.qgrid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)starts.size(), 1280));
     b.f32q = hs[0]->opt.precision == TEFMM_MIXED_FP32;
+    // the far fields of all geometries, captured once as a graph with one branch per
+    // geometry (forks from and joins to the origin stream only)
+    if (!b.origin) HIPCHK(h0, hipStreamCreateWithFlags(&b.origin, hipStreamNonBlocking));
+    if (!b.ev_q) HIPCHK(h0, hipEventCreateWithFlags(&b.ev_q, hipEventDisableTiming));
+    if (!b.ev_ff) HIPCHK(h0, hipEventCreateWithFlags(&b.ev_ff, hipEventDisableTiming));
+    HIPCHK(h0, hipStreamBeginCapture(b.origin, hipStreamCaptureModeThreadLocal));
+    int rc = TEFMM_OK;
+    hipError_t e = hipEventRecord(b.ev[n_geom], b.origin);
+    for (int g = 0; g < n_geom && rc == TEFMM_OK && e == hipSuccess; ++g) {
+      e = hipStreamWaitEvent(b.side[g], b.ev[n_geom], 0);
+      if (e != hipSuccess) break;
+      rc = enqueue_evaluate(hs[g], q[g], nrhs[g], phi[g], b.side[g], false, true);
+      if (rc != TEFMM_OK) break;
+      e = hipEventRecord(b.ev[g], b.side[g]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b.origin, b.ev[g], 0);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b.origin, &graph);
+    if (rc != TEFMM_OK || e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      if (rc != TEFMM_OK) return fail(h0, rc, "capture: " + std::string(h0->err));
+      return fail(h0, TEFMM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b.graph = graph;
+    HIPCHK(h0, hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
     b.hs.assign(hs, hs + n_geom);
     b.gens.clear();
     for (int g = 0; g < n_geom; ++g) b.gens.push_back(hs[g]->gen);
@@ -2342,15 +2411,19 @@ extern "C" int tefmm_evaluate_batch_queue(tefmm_t* hs, int n_geom, const double*
   }
   NFQueueArgs qa;
   std::memset(&qa, 0, sizeof(qa));
-  qa.geo = b.d_geo, qa.ngeo = b.ngeo, qa.p2p_start = b.d_start, qa.gather_start = b.d_start + (b.ngeo + 1);
+  qa.geo = b.d_geo, qa.ngeo = b.ngeo, qa.items = b.d_start, qa.n_p2p = b.n_p2p, qa.n_gather = b.n_gather;
   qa.ticket = b.d_ctr, qa.done = b.d_ctr + 1, qa.err = b.d_err, qa.spin_limit = 1 << 22;
-  HIPCHK(h0, hipEventRecord(b.ev[n_geom], s));
+  // charges in tree order on the caller's stream; then the far-field graph and the queue
+  // side by side; then every geometry's final scaling on the caller's stream
   for (int g = 0; g < n_geom; ++g) {
-    HIPCHK(h0, hipStreamWaitEvent(b.side[g], b.ev[n_geom], 0));
-    const int rc = enqueue_evaluate(hs[g], q[g], nrhs[g], phi[g], b.side[g], false, b.evq[g]);
+    const int rc = enqueue_gather_q(hs[g], q[g], nrhs[g], s);
     if (rc != TEFMM_OK) return fail(h0, rc, "geometry " + std::to_string(g) + ": " + hs[g]->err);
-    HIPCHK(h0, hipStreamWaitEvent(b.nf, b.evq[g], 0));
   }
+  HIPCHK(h0, hipEventRecord(b.ev_q, s));
+  HIPCHK(h0, hipStreamWaitEvent(b.origin, b.ev_q, 0));
+  HIPCHK(h0, hipGraphLaunch(b.exec, b.origin));
+  HIPCHK(h0, hipEventRecord(b.ev_ff, b.origin));
+  HIPCHK(h0, hipStreamWaitEvent(b.nf, b.ev_q, 0));
   hipLaunchKernelGGL(k_nf_queue_reset, dim3(1), dim3(64), 0, b.nf, qa.ticket, qa.done, qa.ngeo, qa.err);
   HIPCHK(h0, hipGetLastError());
   if (b.f32q)
@@ -2359,12 +2432,11 @@ extern "C" int tefmm_evaluate_batch_queue(tefmm_t* hs, int n_geom, const double*
     hipLaunchKernelGGL(k_nf_queue<double>, dim3(b.qgrid), dim3(256), 0, b.nf, qa);
   HIPCHK(h0, hipGetLastError());
   HIPCHK(h0, hipEventRecord(b.ev_nf, b.nf));
+  HIPCHK(h0, hipStreamWaitEvent(s, b.ev_ff, 0));
+  HIPCHK(h0, hipStreamWaitEvent(s, b.ev_nf, 0));
   for (int g = 0; g < n_geom; ++g) {
-    HIPCHK(h0, hipStreamWaitEvent(b.side[g], b.ev_nf, 0));
-    const int rc = enqueue_finalize(hs[g], nrhs[g], phi[g], b.side[g]);
+    const int rc = enqueue_finalize(hs[g], nrhs[g], phi[g], s);
     if (rc != TEFMM_OK) return fail(h0, rc, "geometry " + std::to_string(g) + ": " + hs[g]->err);
-    HIPCHK(h0, hipEventRecord(b.ev[g], b.side[g]));
-    HIPCHK(h0, hipStreamWaitEvent(s, b.ev[g], 0));
   }
   return TEFMM_OK;
 }

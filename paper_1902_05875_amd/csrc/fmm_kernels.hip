@@ -1669,12 +1669,12 @@ __global__ void k_nf_queue_reset(unsigned* ticket, unsigned* done, int ngeo, int
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_nf_queue(NFQueueArgs q) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_nf_queue(NFQueueArgs q) {
   typedef typename SymTypes<R>::R2 R2;
   constexpr bool F32 = std::is_same<R, float>::value;
   __shared__ SymShared<R, 2, 4> sh;
   __shared__ unsigned s_it;
-  const unsigned P = (unsigned)q.p2p_start[q.ngeo], Q = P + (unsigned)q.gather_start[q.ngeo];
+  const unsigned P = (unsigned)q.n_p2p, Q = P + (unsigned)q.n_gather;
   for (;;) {
     __syncthreads();  // the previous item no longer needs s_it or the LDS
     if (threadIdx.x == 0) s_it = atomicAdd(q.ticket, 1u);
@@ -1682,10 +1682,9 @@ __global__ __launch_bounds__(256) void k_nf_queue(NFQueueArgs q) {
     const unsigned it = s_it;
     if (it >= Q) return;
     if (it < P) {
-      int g = 0;
-      while ((unsigned)q.p2p_start[g + 1] <= it) ++g;
+      const unsigned itm = q.items[it];
+      const int g = (int)(itm >> 24), wi = (int)(itm & 0xFFFFFFu);
       const NFQueueGeom& ge = q.geo[g];
-      const int wi = (int)(it - (unsigned)q.p2p_start[g]);
       R2* part = (R2*)ge.part;
       if constexpr (F32) {
         if (ge.tpl == 2) {
@@ -1709,9 +1708,8 @@ __global__ __launch_bounds__(256) void k_nf_queue(NFQueueArgs q) {
       __syncthreads();
       if (threadIdx.x == 0) __hip_atomic_fetch_add(&q.done[g], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      const unsigned j = it - P;
-      int g = 0;
-      while ((unsigned)q.gather_start[g + 1] <= j) ++g;
+      const unsigned itm = q.items[it];
+      const int g = (int)(itm >> 24), leaf = (int)(itm & 0xFFFFFFu);
       const NFQueueGeom& ge = q.geo[g];
       if (threadIdx.x == 0) {
         int spins = 0;
@@ -1725,8 +1723,7 @@ __global__ __launch_bounds__(256) void k_nf_queue(NFQueueArgs q) {
       }
       __syncthreads();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      p2p_sym_gather_leaf<R2>(ge.a, 1, 64 * ge.tpl, ge.G, (const R2*)ge.part, (int)(j - (unsigned)q.gather_start[g]),
-                              0);
+      p2p_sym_gather_leaf<R2>(ge.a, 1, 64 * ge.tpl, ge.G, (const R2*)ge.part, leaf, 0);
     }
   }
 }

@@ -240,21 +240,22 @@ template <typename R2>
 __global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* part);
 
 // Near fields of several geometries in one persistent launch: a work queue of
-// (geometry, phase, tile) items taken in ticket order, first every symmetric-pair
-// item (geometry g: G nb^3 of them), then every gather item (one per leaf), which
-// waits until its geometry's pair items are done.  One charge vector.
+// (geometry, phase, tile) items taken in ticket order, first the symmetric-pair items
+// (one per leaf and workgroup index, longest first), then one gather item per
+// non-empty leaf, which waits until its geometry's pair items are done.  Items are
+// packed geometry << 24 | index.  One charge vector.
 struct NFQueueGeom {
   PassArgs a;    // a.phi: the geometry's near-field sums
   NearPoly np;
   void* part;    // source-side slot sums (float2 or double2)
   int G, tpl, poly;
-  int p2p_items, gather_items;
+  int p2p_items, gather_items;  // pair items of this geometry in the list; unused
 };
 struct NFQueueArgs {
   const NFQueueGeom* geo;
   int ngeo;
-  const int* p2p_start;     // [ngeo + 1] prefix sums of p2p_items
-  const int* gather_start;  // [ngeo + 1] prefix sums of gather_items
+  const unsigned* items;    // n_p2p pair items, then n_gather gather items
+  int n_p2p, n_gather;
   unsigned* ticket;         // next item
   unsigned* done;           // [ngeo] pair items finished
   int* err;                 // set to 1 when a wait gives up (spin_limit polls)
