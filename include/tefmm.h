@@ -350,6 +350,23 @@ int tefmm_dcim_cross(const tefmm_medium* medium, const tefmm_options* opt, int l
 int tefmm_sigma_derivatives(tefmm_t h, int layer, int method, int64_t n, const double* rho, const double* S,
                             double* out, void* stream);
 
+/* TEFMM-II (Sec. 4.1) in free space, symmetric basis (n, m, s), 0 <= s <= m <= n,
+ * ordered by n, then m, then s (C(N+3,3) entries up to order N).
+ * tefmm_sym_derivatives: D^s_{nm} h0(k|R|) (Eq. sysdifferential applied to h0, derivatives
+ * in the first argument) for n <= order <= 32 at n_pts displacements R (host, 3 doubles
+ * each, none zero), from the Theorem 4.2 ladder on Omega^m_n = h_n Y^m_n; out: host,
+ * n_pts * C(order+3,3) complex (re, im interleaved).
+ * tefmm_sym_m2l: the translation of Eq. M2Ltransop, beta_i = L(R_i) alpha_i with
+ *   L[(n,m,s),(n',m',s')] = (-1)^n' D^{s+s'}_{n+n',m+m'} h0(k|R_i|) / (F(n,m,s) F(n',m',s')),
+ *   F(n,m,s) = 2^m (n-m)! s! (m-s)!,
+ * R_i = target centre - source centre (host, 3 doubles each, none zero); alpha, beta:
+ * device arrays of n_pairs * C(p+3,3) complex (Eq. mecoefficients moments in, the local
+ * coefficients of Corollary 4.1 out), p <= 16.  Both synchronous on `stream`, scratch from
+ * hipMalloc; TEFMM_ERR_INVALID_ARG or TEFMM_ERR_HIP on failure. */
+int tefmm_sym_derivatives(double k, int order, int64_t n_pts, const double* R, double* out, void* stream);
+int tefmm_sym_m2l(double k, int p, int64_t n_pairs, const double* R, const double* alpha, double* beta,
+                  void* stream);
+
 /* Scaled Taylor coefficients h^{|g|} D^g f / g! of f = exp(i k R)/R at n
  * points (x, y, zeta) with complex zeta (device arrays x, y: n doubles;
  * zeta: 2n doubles interleaved), orders |g| <= order, on the GPU with the

@@ -33,7 +33,8 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_mlp_adam_step", "tefmm_mlp_train", "tefmm_surrogate_default_options", "tefmm_surrogate_train",
            "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
            "tefmm_reset_timers", "tefmm_set_allocator", "tefmm_gmres", "tefmm_sigma_derivatives",
-           "tefmm_radix_sort", "tefmm_exclusive_scan", "tefmm_evaluate_batch_queue", "tefmm_batch_check"]
+           "tefmm_radix_sort", "tefmm_exclusive_scan", "tefmm_evaluate_batch_queue", "tefmm_batch_check",
+           "tefmm_sym_derivatives", "tefmm_sym_m2l"]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -155,6 +156,8 @@ def lib():
         L.tefmm_evaluate_batch_queue.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
                                                  ctypes.POINTER(i32), ctypes.POINTER(vp), vp]
         L.tefmm_batch_check.argtypes = [vp, vp]
+        L.tefmm_sym_derivatives.argtypes = [dbl, i32, i64, vp, vp, vp]
+        L.tefmm_sym_m2l.argtypes = [dbl, i32, i64, vp, vp, vp, vp]
         L.tefmm_autotune.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.tefmm_dcim_cross.argtypes = [ctypes.POINTER(MediumC), ctypes.POINTER(OptionsC), i32, i32, i32, dbl, i32,
                                        dbl, dbl, i32, ctypes.POINTER(i32), vp, vp, ctypes.POINTER(dbl)]
@@ -201,6 +204,31 @@ def exclusive_scan(x, out, stream=None):
     """out = exclusive prefix sums of the device int32 tensor x, unsigned 32-bit
     arithmetic (tefmm_exclusive_scan)."""
     _check(lib().tefmm_exclusive_scan(x.numel(), x.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
+
+
+def sym_derivatives(k, order, R, stream=None):
+    """D^s_{nm} h0(k|R|) for n <= order at the displacements R ((n, 3) array): numpy
+    (n, C(order+3,3)) complex128 (tefmm_sym_derivatives, Theorem 4.2)."""
+    import numpy as np
+    R = np.ascontiguousarray(R, np.float64).reshape(-1, 3)
+    cnt = (order + 1) * (order + 2) * (order + 3) // 6
+    out = np.empty((R.shape[0], cnt), np.complex128)
+    _check(lib().tefmm_sym_derivatives(float(k), int(order), R.shape[0], R.ctypes.data, out.ctypes.data,
+                                        _stream_ptr(stream)))
+    return out
+
+
+def sym_m2l(k, p, R, alpha, stream=None):
+    """TEFMM-II translation of Eq. M2Ltransop (tefmm_sym_m2l): R (n, 3) displacements (host),
+    alpha a (n, C(p+3,3)) complex128 tensor on the GPU; returns beta of the same shape."""
+    import numpy as np
+    import torch
+    R = np.ascontiguousarray(R, np.float64).reshape(-1, 3)
+    alpha = alpha.to(torch.complex128).contiguous()
+    beta = torch.empty_like(alpha)
+    _check(lib().tefmm_sym_m2l(float(k), int(p), R.shape[0], R.ctypes.data, alpha.data_ptr(), beta.data_ptr(),
+                               _stream_ptr(stream)))
+    return beta
 
 
 def batch_check(handle, stream=None):

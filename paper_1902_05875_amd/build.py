@@ -16,7 +16,7 @@ OUT = os.path.join(HERE, "libtefmm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["host_math.cpp", "capi_host.cpp", "fmm_kernels.hip", "fmm_m2l.hip", "fmm_host.hip", "mlp.hip",
-           "sort_scan.hip"]
+           "sort_scan.hip", "tefmm2.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -141,3 +141,63 @@ def test_sigma_derivatives_errors():
     with pytest.raises(api.TefmmError):
         f.sigma_derivatives(3, [0.1], [-1.0], "sommerfeld")
     f.close()
+
+
+# --- the symmetric-basis operators of Sec. 4.1 on the GPU ---------------------------------
+
+SYM_PTS = np.array([(0.7, -0.4, 1.1), (-1.3, 0.2, -0.6), (0.05, 0.9, 0.3), (0.0, 0.0, 0.8), (0.4, 0.3, 0.0)])
+
+
+@pytest.mark.parametrize("order", [8, 14])
+def test_sym_derivatives_vs_oracle(order):
+    """D^s_{nm} h0 by the Theorem 4.2 ladder on the GPU against the oracle's (itself pinned to
+    the Cartesian series), every (n, m, s) up to the order, five points (one on the z axis,
+    one in the x-y plane)."""
+    from oracle import tefmm2 as T
+    from paper_1902_05875_amd import api
+    k = 1.3
+    got = api.sym_derivatives(k, order, SYM_PTS)
+    for i, r in enumerate(SYM_PTS):
+        ref = T.symmetric_derivatives(r, k, order)
+        np.testing.assert_allclose(got[i], ref, rtol=1e-10, atol=1e-13 * np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("p", [4, 7])
+def test_sym_m2l_vs_oracle(p):
+    """beta = L(R) alpha of Eq. M2Ltransop on the GPU against the oracle's matrix, random
+    moment vectors at five displacements."""
+    import torch
+    from oracle import tefmm2 as T
+    from paper_1902_05875_amd import api
+    k = 1.5
+    C = len(T.index_set(p))
+    rng = np.random.default_rng(p)
+    R = SYM_PTS * 2.0
+    alpha = rng.standard_normal((len(R), C)) + 1j * rng.standard_normal((len(R), C))
+    beta = api.sym_m2l(k, p, R, torch.from_numpy(alpha).cuda()).cpu().numpy()
+    for i in range(len(R)):
+        ref = T.m2l_matrix(R[i], k, p) @ alpha[i]
+        np.testing.assert_allclose(beta[i], ref, rtol=1e-10, atol=1e-12 * np.max(np.abs(ref)))
+
+
+def test_sym_m2l_converges_to_direct_sum():
+    """Moments about the source centre (Eq. mecoefficients) -> GPU M2L -> local expansion about
+    the target centre (Corollary 4.1) against the direct sum of h0, p = 4, 8, 12."""
+    import torch
+    from oracle import tefmm2 as T
+    from paper_1902_05875_amd import api
+    k = 1.3
+    rng = np.random.default_rng(11)
+    xyz = rng.random((20, 3)) * 0.3
+    q = rng.random(20) - 0.5 + 1j * (rng.random(20) - 0.5)
+    sc, tc = np.array([0.15, 0.15, 0.15]), np.array([1.2, 0.3, 0.9])
+    tg = tc + (rng.random((6, 3)) - 0.5) * 0.3
+    h0 = lambda x: np.exp(1j * x) / (1j * x)
+    direct = np.array([np.sum(q * h0(k * np.linalg.norm(t - xyz, axis=1))) for t in tg])
+    errs = []
+    for p in (4, 8, 12):
+        a = T.moments(xyz, q, sc, p)[None, :]
+        b = api.sym_m2l(k, p, (tc - sc)[None, :], torch.from_numpy(a).cuda()).cpu().numpy()[0]
+        errs.append(np.max(np.abs(T.evaluate_local(b, tg - tc, p) - direct)) / np.max(np.abs(direct)))
+    print("GPU symmetric M2L against the direct sum, p = 4, 8, 12:", errs)
+    assert errs[1] < 1e-2 * errs[0] and errs[2] < 1e-2 * errs[1] and errs[2] < 1e-10
