@@ -116,6 +116,9 @@ struct Group {
   std::vector<float2*> Tfd32, TS32;
   std::vector<int64_t> nbox;          // boxes at level
   std::vector<int64_t> far_pairs, near_pairs;  // per level from 2: interaction-list / neighbour pairs
+                                               // between occupied boxes
+  std::vector<std::vector<unsigned char>> occ;  // per level: 1 where the box holds particles
+  std::vector<unsigned char*> d_occ;            // device copies (read by the M2L)
   double fit_zlo = 0, fit_zhi = 0;              // height range of the complex-image fits
   // cross-layer (this group as target): z-reduced moments/locals and per-level lists and tables
   std::vector<double2*> azred, bzred;
@@ -313,6 +316,7 @@ static void free_geometry(tefmm_t h) {
     dfree(h, g.d_sd_start);
     dfree(h, g.d_sd_src);
     dfree(h, g.d_sd_img);
+    for (auto& p : g.d_occ) dfree(h, p);
   }
   h->groups.clear();
   dfree(h, h->d_q);
@@ -1484,26 +1488,72 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     g.np_err = 0;
     g.np_on = h->opt.p2p_poly == 0 &&
               fit_near_poly(h->med.k[g.layer], g.side / (double)(1 << g.depth), 3e-7, &g.np, &g.np_err);
+    // box occupancy per level (leaf counts, then the parents of occupied boxes), on the
+    // device for the M2L, which skips empty targets and sources
+    g.occ.assign(g.depth + 1, {});
+    g.d_occ.assign(g.depth + 1, nullptr);
+    {
+      auto& o = g.occ[g.depth];
+      o.resize((size_t)nleaf);
+      for (int64_t b = 0; b < nleaf; ++b) o[b] = lc[g.leaf_base + b] > 0;
+      for (int lev = g.depth - 1; lev >= 2; --lev) {
+        const int nc = 1 << (lev + 1), np = 1 << lev;
+        auto& po = g.occ[lev];
+        const auto& co = g.occ[lev + 1];
+        po.assign((size_t)np * np * np, 0);
+        for (int ix = 0; ix < nc; ++ix)
+          for (int iy = 0; iy < nc; ++iy)
+            for (int iz = 0; iz < nc; ++iz)
+              if (co[((size_t)ix * nc + iy) * nc + iz]) po[((size_t)(ix >> 1) * np + (iy >> 1)) * np + (iz >> 1)] = 1;
+      }
+      for (int lev = 2; lev <= g.depth; ++lev) {
+        HIPCHK(h, dmalloc(h, &g.d_occ[lev], g.occ[lev].size()));
+        HIPCHK(h, hipMemcpyAsync(g.d_occ[lev], g.occ[lev].data(), g.occ[lev].size(), hipMemcpyHostToDevice, s));
+      }
+    }
     for (int lev = 2; lev <= g.depth; ++lev) {
       const int nb2 = 1 << lev;
-      // valid (target, source) pairs for one parity class window, split into far and near
+      const auto& ol = g.occ[lev];
+      int64_t nocc = 0;
+      for (unsigned char v : ol) nocc += v;
+      // (target, source) pairs of the parity class windows between occupied boxes, split
+      // into far and near
       int64_t far1 = 0, near1 = 0;
-      for (int ix = 0; ix < nb2; ++ix)
-        for (int dx = -2 - (ix & 1); dx <= 3 - (ix & 1); ++dx) {
-          if (ix + dx < 0 || ix + dx >= nb2) continue;
+      if (nocc < (int64_t)ol.size()) {
+        for (int ix = 0; ix < nb2; ++ix)
           for (int iy = 0; iy < nb2; ++iy)
-            for (int dy = -2 - (iy & 1); dy <= 3 - (iy & 1); ++dy) {
-              if (iy + dy < 0 || iy + dy >= nb2) continue;
-              for (int iz = 0; iz < nb2; ++iz)
-                for (int dz = -2 - (iz & 1); dz <= 3 - (iz & 1); ++dz) {
-                  if (iz + dz < 0 || iz + dz >= nb2) continue;
-                  if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1)
-                    ++near1;
-                  else
-                    ++far1;
-                }
+            for (int iz = 0; iz < nb2; ++iz) {
+              if (!ol[((size_t)ix * nb2 + iy) * nb2 + iz]) continue;
+              for (int dx = -2 - (ix & 1); dx <= 3 - (ix & 1); ++dx)
+                for (int dy = -2 - (iy & 1); dy <= 3 - (iy & 1); ++dy)
+                  for (int dz = -2 - (iz & 1); dz <= 3 - (iz & 1); ++dz) {
+                    const int jx = ix + dx, jy = iy + dy, jz = iz + dz;
+                    if (jx < 0 || jy < 0 || jz < 0 || jx >= nb2 || jy >= nb2 || jz >= nb2) continue;
+                    if (!ol[((size_t)jx * nb2 + jy) * nb2 + jz]) continue;
+                    if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1)
+                      ++near1;
+                    else
+                      ++far1;
+                  }
             }
-        }
+      } else {
+        for (int ix = 0; ix < nb2; ++ix)
+          for (int dx = -2 - (ix & 1); dx <= 3 - (ix & 1); ++dx) {
+            if (ix + dx < 0 || ix + dx >= nb2) continue;
+            for (int iy = 0; iy < nb2; ++iy)
+              for (int dy = -2 - (iy & 1); dy <= 3 - (iy & 1); ++dy) {
+                if (iy + dy < 0 || iy + dy >= nb2) continue;
+                for (int iz = 0; iz < nb2; ++iz)
+                  for (int dz = -2 - (iz & 1); dz <= 3 - (iz & 1); ++dz) {
+                    if (iz + dz < 0 || iz + dz >= nb2) continue;
+                    if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1)
+                      ++near1;
+                    else
+                      ++far1;
+                  }
+              }
+          }
+      }
       g.far_pairs.push_back(far1);
       g.near_pairs.push_back(near1);
       h->m2l_pairs += far1;
@@ -1887,6 +1937,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       L.a = g.ared[lev], L.a32 = g.ared32[lev], L.b = g.bred[lev], L.rhs_stride = g.nbox[lev] * h->nR;
       L.split_stride = g.nbox[lev] * h->nR * h->nrhs_alloc;
       L.Tfd = g.Tfd[lev], L.TS = g.TS[lev], L.Tfd32 = g.Tfd32[lev], L.TS32 = g.TS32[lev];
+      L.occ = g.d_occ[lev];
     }
     m.ncb = h->m2l_ncb ? h->m2l_ncb : h->opt.m2l_tile;
     m.nsplit = m2l_split(H);

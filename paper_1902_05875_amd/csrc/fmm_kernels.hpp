@@ -93,6 +93,8 @@ struct M2LLevel {
   const float2* Tfd32;   // FP32 copies (mixed precision)
   const float2* TS32;
   int64_t split_stride;  // elements between the partial outputs of the offset splits
+  const unsigned char* occ;  // [n^3] 1 where the box holds particles, or null (all counted occupied):
+                             // empty targets get zero locals, empty sources are not staged
 };
 
 constexpr int M2L_MAX_LEVELS = 8;

@@ -122,6 +122,27 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     const int ix = px + 2 * (4 * X0 + (n & 3)), iy = py + 2 * (4 * NCB * Y0 + (n >> 2));
     if (ix < N && iy < N) tmask |= 1u << n;
   }
+  // Occupancy of the boxes the tile can reach (x from px + 8 X0 - 3, y from
+  // py + 8 NCB Y0 - 3, z from iz - 3: the offsets reach three boxes either way).
+  // Empty boxes have zero moments and no particle reads their locals, so empty
+  // targets keep zero locals and empty sources are skipped: the occupied boxes'
+  // locals are the same sums.
+  constexpr int WX = 13, WY = 8 * NCB + 5, WZ = 7;
+  unsigned char* sOcc = (unsigned char*)(sCol + 4 * a.nKB);
+  unsigned tocc = tmask;
+  if (L.occ) {
+    const int x0 = px + 8 * X0 - 3, y0 = py + 8 * NCB * Y0 - 3, z0 = iz - 3;
+    for (int e = tid; e < WX * WY * WZ; e += 256) {
+      const int wx = e / (WY * WZ), wy = (e / WZ) % WY, wz = e % WZ;
+      const int x = x0 + wx, y = y0 + wy, z = z0 + wz;
+      sOcc[e] = (x >= 0 && y >= 0 && z >= 0 && x < N && y < N && z < N) ? L.occ[((int64_t)x * N + y) * N + z] : 0;
+    }
+    __syncthreads();
+    unsigned m = 0;
+    for (int n = 0; n < NT; ++n)
+      if (sOcc[((3 + 2 * (n & 3)) * WY + 3 + 2 * (n >> 2)) * WZ + 3]) m |= 1u << n;
+    tocc = __builtin_amdgcn_readfirstlane(m) & tmask;
+  }
 
   // reduced moments: FP32 copies in the mixed mode
   const double2* alpha = L.a ? L.a + (int64_t)r * L.rhs_stride : nullptr;
@@ -203,7 +224,8 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
         const int kk = Lp * ph + rk + i;
         if (kk < a.nR) rvalid[ph] |= 1u << i, rsign[ph] |= (unsigned)((sCol[kk] >> 20) & 1) << i;
       }
-  for (int pass = 0; pass < 2; ++pass) {
+  const int npass = tocc ? 2 : 0;  // no occupied target: zero locals
+  for (int pass = 0; pass < npass; ++pass) {
     const T2* table = pass ? (const T2*)Ty::tableS(L) : (const T2*)Ty::tableF(L);
     if (!table) continue;
     const bool mirror = pass == 1;
@@ -217,7 +239,12 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
           const int dx = ox - 2 - px;
           const bool nearb = dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
           if (nearb && !(L.leaf && near_ok)) continue;
-          const unsigned smask = tile_mask<NCB>(N, px, py, X0, Y0, dx, dy);
+          unsigned smask = tile_mask<NCB>(N, px, py, X0, Y0, dx, dy);
+          if (L.occ) {  // lane n < NT tests target n's source box; the same mask in every wave
+            const int l = lane < NT ? lane : 0;
+            const bool o = lane < NT && sOcc[((3 + 2 * (l & 3) + dx) * WY + 3 + 2 * (l >> 2) + dy) * WZ + 3 + dz];
+            smask &= (unsigned)__ballot(o) & tocc;
+          }
           if (!smask) continue;
           if ((ocount++) % a.nsplit != split) continue;
           const int key = pass ? ((dx + 3) * 7 + (dy + 3)) * (2 * N - 1) + (2 * iz + dz)
@@ -378,7 +405,7 @@ static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
     int rs = 4 * kpb;
     while (rs % 16 != 1) ++rs;
     return std::make_pair(((size_t)3 * a.P2 * a.P2 + 1) * sizeof(T2) + (size_t)16 * NCB * rs * sizeof(T2) +
-                              4 * (size_t)a.nKB * sizeof(int), rs);
+                              4 * (size_t)a.nKB * sizeof(int) + (size_t)13 * (8 * NCB + 5) * 7, rs);
   };
   const int kpb1 = a.nKB, kpb2 = (a.nKB + 1) / 2;
   a.kph = (lds_of(kpb1).first > 80 * 1024 && lds_of(kpb2).first <= 80 * 1024) ? 2 : 1;
