@@ -1941,6 +1941,7 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
     }
     m.ncb = h->m2l_ncb ? h->m2l_ncb : h->opt.m2l_tile;
     m.nsplit = m2l_split(H);
+    m.ksplit = 1;
     HIPCHK(h, launch_m2l(m, nrhs, fp32, sm));
     const double per = 8.0 * (double)h->nR * (double)h->nR;
     for (int lev = 2; lev <= H; ++lev) {

@@ -107,6 +107,7 @@ struct M2LArgs {
   int nsplit;            // the offsets of a tile are split over nsplit workgroups (blockIdx.z),
                          // each writing its own partial locals (summed in fixed order by k_expand)
   int kph, kpb, nRsP;    // source moments staged in kph phases of kpb blocks of 4 (LDS row stride nRsP)
+  int ksplit;            // 1: one or two row-block tiles left over after 4 per wave are split along K
   int tile_start[M2L_MAX_LEVELS + 1];
   M2LLevel lev[M2L_MAX_LEVELS];
   const int* rmi;        // [nR] packed reduced multi-indices

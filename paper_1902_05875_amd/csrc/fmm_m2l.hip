@@ -75,8 +75,13 @@ __device__ __forceinline__ unsigned tile_mask(int N, int px, int py, int X0, int
   return m;
 }
 
-// EX: every wave has TW tiles (4 TW row-block x column-block tiles in all), no test
-template <typename T, int TW, int NCB, bool EX>
+// EX: every wave has TW tiles (4 TW row-block x column-block tiles in all), no test.
+// KS = 1 or 2: 4 (TW - 1) + KS tiles; each wave has TW - 1 tiles of its own, and the
+// last KS tiles are split along the contraction (KS = 1: the tile's K blocks in four
+// quarters, one per wave; KS = 2: each of the two tiles in two halves, waves 0 and 1
+// on the first, 2 and 3 on the second), so that every wave does the same number of
+// MFMAs; the waves' partial sums of a split tile are added in wave order in LDS.
+template <typename T, int TW, int NCB, bool EX, int KS>
 __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   typedef M2LTypes<T> Ty;
   typedef typename Ty::T2 T2;
@@ -171,7 +176,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   int rowo[TW], tcb[TW];
 #pragma unroll
   for (int j = 0; j < TW; ++j) {
-    const int id = w + 4 * j;
+    const int id = (KS && j == TW - 1) ? 4 * (TW - 1) + (KS == 1 ? 0 : (w >> 1)) : w + 4 * j;
     const int rb = id % a.nRB, cb = id / a.nRB;
     const int k = 16 * rb + col;
     // rows past nR (and missing tiles) gather entry 0: finite, and dropped by the epilogue
@@ -182,6 +187,9 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
       rowo[j] = (k1 * P2 + k2 + k3) * P2 + k3;
     }
   }
+  // K blocks [kq0, kq1) of the split tile taken by this wave (wave-uniform)
+  const int kq0 = KS == 1 ? (w * a.nKB) / 4 : KS == 2 ? ((w & 1) * a.nKB) / 2 : 0;
+  const int kq1 = KS == 1 ? ((w + 1) * a.nKB) / 4 : KS == 2 ? (((w & 1) + 1) * a.nKB) / 2 : 0;
   // B operand offset of each tile: column block tcb, target col
   int boff[TW];
 #pragma unroll
@@ -329,19 +337,21 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
 #pragma unroll
               for (int j = 0; j < TW; ++j) g[j] = sG[rowo[j] + co];
             };
-            auto mma = [&](const T2 (&bb)[TW], const T2 (&g)[TW]) {
+            auto mma = [&](const T2 (&bb)[TW], const T2 (&g)[TW], int kb) {
               // independent MFMAs between the two updates of each accumulator; only the
-              // wave's last tile can be missing (ntile > 4 (TW - 1)), a uniform test
+              // wave's last tile can be missing (ntile > 4 (TW - 1)) or split (its K
+              // blocks outside [kq0, kq1) are another wave's), a uniform test
+              const bool lon = KS ? (kb >= kq0 && kb < kq1) : last_ok;
 #pragma unroll
               for (int j = 0; j < TW; ++j)
-                if (EX || j < TW - 1 || last_ok) {
+                if (EX || j < TW - 1 || lon) {
                   const T2 b = BT ? bb[j] : (tcb[j] ? bb[1] : bb[0]);
                   accR[j] = Ty::mfma(g[j].x, b.x, accR[j]);
                   accI[j] = Ty::mfma(g[j].x, b.y, accI[j]);
                 }
 #pragma unroll
               for (int j = 0; j < TW; ++j)
-                if (EX || j < TW - 1 || last_ok) {
+                if (EX || j < TW - 1 || lon) {
                   const T2 b = BT ? bb[j] : (tcb[j] ? bb[1] : bb[0]);
                   if (F32)
                     accN[j] = Ty::mfma(g[j].y, b.y, accN[j]);
@@ -354,10 +364,10 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
             if (kb0 < kb1) load(kb0, b1, g1);
             for (int kb = kb0; kb < kb1; kb += 2) {
               if (kb + 1 < kb1) load(kb + 1, b2, g2);
-              mma(b1, g1);
+              mma(b1, g1, kb);
               if (kb + 1 >= kb1) break;
               if (kb + 2 < kb1) load(kb + 2, b1, g1);
-              mma(b2, g2);
+              mma(b2, g2, kb + 1);
             }
           }
         }
@@ -367,7 +377,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   // epilogue: result rows per the precision's MFMA layout, columns = targets
   double2* beta = L.b + (int64_t)split * L.split_stride + (int64_t)r * L.rhs_stride;
 #pragma unroll
-  for (int j = 0; j < TW; ++j) {
+  for (int j = 0; j < (KS ? TW - 1 : TW); ++j) {
     const int id = w + 4 * j;
     if (id >= ntile) continue;
     const int rb = id % a.nRB, cb = id / a.nRB;
@@ -384,6 +394,47 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
       }
     }
   }
+  if (KS) {
+    // the split tiles: each wave's partial sums to LDS ([wave][value][lane], 16 KiB over the
+    // tables and moments, which no wave reads any more), then added in wave order; KS = 1:
+    // wave w finishes value w of the tile, KS = 2: wave w value pair (w & 1) of tile w >> 1
+    constexpr int j = TW - 1;
+    double2* sP = (double2*)lds_m2l;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double re = F32 ? (double)accR[j][i] - (double)accN[F32 ? j : 0][i] : (double)accR[j][i];
+      sP[(w * 4 + i) * 64 + lane] = make_double2(re, (double)accI[j][i]);
+    }
+    __syncthreads();
+    const int id = 4 * (TW - 1) + (KS == 1 ? 0 : (w >> 1));
+    const int rb = id % a.nRB, cb = id / a.nRB;
+    const int n = 16 * cb + col;
+    if (id < ntile && ((tmask >> n) & 1)) {
+      const int ix = px + 2 * (4 * X0 + (n & 3)), iy = py + 2 * (4 * NCB * Y0 + (n >> 2));
+      const int64_t tb = ((int64_t)ix * N + iy) * N + iz;
+#pragma unroll
+      for (int q = 0; q < (KS == 1 ? 1 : 2); ++q) {
+        const int i = KS == 1 ? w : 2 * (w & 1) + q;
+        const int k = 16 * rb + Ty::row(krow, i);
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < (KS == 1 ? 4 : 2); ++u) {
+          const int src = KS == 1 ? u : 2 * (w >> 1) + u;
+          const double2 pv = sP[(src * 4 + i) * 64 + lane];
+          v.x += pv.x, v.y += pv.y;
+        }
+        if (k < a.nR) beta[tb * a.nR + k] = v;
+      }
+    }
+  }
+}
+
+template <typename T, int TW, int NCB>
+static void (*pick_m2l(bool ex, int ks))(M2LArgs) {
+  if (ks == 1) return k_m2l<T, TW, NCB, false, 1>;
+  if (ks == 2) return k_m2l<T, TW, NCB, false, 2>;
+  return ex ? k_m2l<T, TW, NCB, true, 0> : k_m2l<T, TW, NCB, false, 0>;
 }
 
 template <typename T, int NCB>
@@ -417,22 +468,24 @@ static hipError_t launch_t2(const M2LArgs& a0, int nrhs, hipStream_t s) {
   }
   const size_t lds = lds_of(a.kpb).first;
   a.nRsP = lds_of(a.kpb).second;
-  const int TW = (a.nRB * NCB + 3) / 4;
-  const bool ex = 4 * TW == a.nRB * NCB;
+  const int ntile = a.nRB * NCB, TW = (ntile + 3) / 4, rem = ntile % 4;
+  const bool ex = rem == 0;
+  // one or two tiles left over: split along K over the waves (the partial sums need 16 KiB of LDS)
+  const int ks = a.ksplit && (rem == 1 || rem == 2) && lds >= 16384 ? rem : 0;
   if (a.nsplit < 1) a.nsplit = 1;
   dim3 grid(total, nrhs, a.nsplit), block(256);
   void (*fn)(M2LArgs) = nullptr;
   switch (TW) {
-    case 1: fn = ex ? k_m2l<T, 1, NCB, true> : k_m2l<T, 1, NCB, false>; break;
-    case 2: fn = ex ? k_m2l<T, 2, NCB, true> : k_m2l<T, 2, NCB, false>; break;
-    case 3: fn = ex ? k_m2l<T, 3, NCB, true> : k_m2l<T, 3, NCB, false>; break;
-    case 4: fn = ex ? k_m2l<T, 4, NCB, true> : k_m2l<T, 4, NCB, false>; break;
-    case 5: fn = ex ? k_m2l<T, 5, NCB, true> : k_m2l<T, 5, NCB, false>; break;
-    case 6: fn = ex ? k_m2l<T, 6, NCB, true> : k_m2l<T, 6, NCB, false>; break;
-    case 7: fn = ex ? k_m2l<T, 7, NCB, true> : k_m2l<T, 7, NCB, false>; break;
-    case 8: fn = ex ? k_m2l<T, 8, NCB, true> : k_m2l<T, 8, NCB, false>; break;
-    case 9: fn = ex ? k_m2l<T, 9, NCB, true> : k_m2l<T, 9, NCB, false>; break;
-    case 10: fn = ex ? k_m2l<T, 10, NCB, true> : k_m2l<T, 10, NCB, false>; break;
+    case 1: fn = pick_m2l<T, 1, NCB>(ex, ks); break;
+    case 2: fn = pick_m2l<T, 2, NCB>(ex, ks); break;
+    case 3: fn = pick_m2l<T, 3, NCB>(ex, ks); break;
+    case 4: fn = pick_m2l<T, 4, NCB>(ex, ks); break;
+    case 5: fn = pick_m2l<T, 5, NCB>(ex, ks); break;
+    case 6: fn = pick_m2l<T, 6, NCB>(ex, ks); break;
+    case 7: fn = pick_m2l<T, 7, NCB>(ex, ks); break;
+    case 8: fn = pick_m2l<T, 8, NCB>(ex, ks); break;
+    case 9: fn = pick_m2l<T, 9, NCB>(ex, ks); break;
+    case 10: fn = pick_m2l<T, 10, NCB>(ex, ks); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
