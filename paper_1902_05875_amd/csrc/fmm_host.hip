@@ -1506,9 +1506,12 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
             for (int iz = 0; iz < nc; ++iz)
               if (co[((size_t)ix * nc + iy) * nc + iz]) po[((size_t)(ix >> 1) * np + (iy >> 1)) * np + (iz >> 1)] = 1;
       }
+      // a level with every box occupied keeps no map (the M2L then has nothing to skip)
       for (int lev = 2; lev <= g.depth; ++lev) {
-        HIPCHK(h, dmalloc(h, &g.d_occ[lev], g.occ[lev].size()));
-        HIPCHK(h, hipMemcpyAsync(g.d_occ[lev], g.occ[lev].data(), g.occ[lev].size(), hipMemcpyHostToDevice, s));
+        const auto& o = g.occ[lev];
+        if (std::find(o.begin(), o.end(), (unsigned char)0) == o.end()) continue;
+        HIPCHK(h, dmalloc(h, &g.d_occ[lev], o.size()));
+        HIPCHK(h, hipMemcpyAsync(g.d_occ[lev], o.data(), o.size(), hipMemcpyHostToDevice, s));
       }
     }
     for (int lev = 2; lev <= g.depth; ++lev) {
