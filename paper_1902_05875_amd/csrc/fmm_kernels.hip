@@ -1605,7 +1605,12 @@ __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G
                                                      NearPoly np) {
   __shared__ SymShared<R, T, NW> sh;
   const int nb = a.nbox_dim;
-  for (int wi = blockIdx.x; wi < G * nb * nb * nb; wi += gridDim.x)
+  // Workgroups are dealt round-robin over the 8 XCDs: each XCD takes a contiguous
+  // range of work items instead (neighbouring leaves, whose source leaves overlap in
+  // that XCD's L2).  The grid is G 8^depth workgroups, a multiple of 8.
+  const unsigned per = gridDim.x / 8;
+  const int b0 = gridDim.x % 8 ? (int)blockIdx.x : (int)((blockIdx.x % 8) * per + blockIdx.x / 8);
+  for (int wi = b0; wi < G * nb * nb * nb; wi += gridDim.x)
     p2p_sym_item<R, T, NW, POLY>(a, nrhs, blockIdx.y, G, part, np, wi, sh);
 }
 
