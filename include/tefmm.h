@@ -108,13 +108,15 @@ typedef struct {
                          3 x 3 x 3 block (k r is small there), used where the fit is within 3e-7 of
                          cos(k r) and sin(k r) (see p2p_poly_err; else, and with -1, the hardware
                          sine and cosine) */
-  int sigma_tables;   /* translation tables of the Sigma families (the same-layer reaction terms
-                         that depend on z + z'): TEFMM_SIGMA_IMAGES from the complex images
-                         (Sec. 3.3); TEFMM_SIGMA_SOMMERFELD from the Sommerfeld integrals of the
+  int sigma_tables;   /* translation tables of the same-layer reaction terms: the Sigma families
+                         (which depend on z + z') and the Delta family (on z - z').
+                         TEFMM_SIGMA_IMAGES from the complex images (Sec. 3.3);
+                         TEFMM_SIGMA_SOMMERFELD from the Sommerfeld integrals of the
                          rotation-free derivatives on the deformed contour of Sec. 4.2 (the
                          integrals of Eq. symmetricdetable, no fit), rebuilt exactly into the
                          Cartesian rows.  Rows answered by an attached surrogate stay the
-                         surrogate's; the near-interface pairs evaluated directly keep the images. */
+                         surrogate's; the near-interface pairs evaluated directly and the
+                         cross-layer terms keep the images. */
 } tefmm_options;
 enum { TEFMM_SIGMA_IMAGES = 0, TEFMM_SIGMA_SOMMERFELD = 1 };
 
@@ -348,6 +350,22 @@ int tefmm_dcim_cross(const tefmm_medium* medium, const tefmm_options* opt, int l
  * layer, method, size or a point outside the layer), TEFMM_ERR_UNSUPPORTED (layer
  * without interfaces, or 2p above 32), TEFMM_ERR_DCIM_FIT, TEFMM_ERR_HIP. */
 int tefmm_sigma_derivatives(tefmm_t h, int layer, int method, int64_t n, const double* rho, const double* S,
+                            double* out, void* stream);
+
+/* The same for the Delta family of layer `layer` (the same-layer reaction terms with
+ * sigma^{ud} e^{i k_z (D + w)} and sigma^{du} e^{i k_z (D - w)}, D the layer's thickness,
+ * which depend on rho and w = z - z'; Sec. 3.3 and Sec. 4.2):
+ *   H_{m,c}(rho, w) = (2 d_v)^m d_w^c K,  v = rho^2,  m + c <= 2p,
+ * stored as for tefmm_sigma_derivatives; d_w is the target's z derivative.
+ * TEFMM_SIGMA_IMAGES: from the family's complex images, fitted for heights spanning the
+ * largest |w|, each at D + w and D - w; TEFMM_SIGMA_SOMMERFELD: from the Sommerfeld
+ * integrals on the contour of Sec. 4.2 (these densities vanish as k_rho grows, so there
+ * is no mirror-point image).  rho, w: host arrays of n >= 1 values with |w| < D; out:
+ * host array of n (2p+1)(2p+2)/2 complex values, written on success.  Needs no
+ * particles; synchronous on `stream`.  Errors: TEFMM_ERR_INVALID_ARG (bad layer, method,
+ * size or |w| >= D), TEFMM_ERR_UNSUPPORTED (a layer without two interfaces, or 2p above
+ * 32), TEFMM_ERR_DCIM_FIT, TEFMM_ERR_HIP. */
+int tefmm_delta_derivatives(tefmm_t h, int layer, int method, int64_t n, const double* rho, const double* w,
                             double* out, void* stream);
 
 /* TEFMM-II (Sec. 4.1) in free space, symmetric basis (n, m, s), 0 <= s <= m <= n,

@@ -34,7 +34,7 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
            "tefmm_reset_timers", "tefmm_set_allocator", "tefmm_gmres", "tefmm_sigma_derivatives",
            "tefmm_radix_sort", "tefmm_exclusive_scan", "tefmm_evaluate_batch_queue", "tefmm_batch_check",
-           "tefmm_sym_derivatives", "tefmm_sym_m2l"]
+           "tefmm_sym_derivatives", "tefmm_sym_m2l", "tefmm_delta_derivatives"]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -188,6 +188,7 @@ def lib():
         L.tefmm_set_allocator.argtypes = [vp, ALLOC_FN, FREE_FN, vp]
         L.tefmm_gmres.argtypes = [vp, dbl, dbl, vp, vp, i32, i32, i32, dbl, vp, ctypes.POINTER(GmresInfoC)]
         L.tefmm_sigma_derivatives.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
+        L.tefmm_delta_derivatives.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
         L.tefmm_radix_sort.argtypes = [i64, vp, vp, i32, vp]
         L.tefmm_exclusive_scan.argtypes = [i64, vp, vp, vp]
         _lib = L
@@ -356,6 +357,21 @@ class TEFMM:
         out = np.empty((rho.size, (P2 + 1) * (P2 + 2) // 2), np.complex128)
         m = SIGMA_TABLES[method] if isinstance(method, str) else int(method)
         _check(lib().tefmm_sigma_derivatives(self.h, int(layer), m, rho.size, rho.ctypes.data, S.ctypes.data,
+                                              out.ctypes.data, _stream_ptr(stream)), self.h)
+        return out
+
+    def delta_derivatives(self, layer, rho, w, method="sommerfeld", stream=None):
+        """H_{m,c}(rho_i, w_i) of the layer's Delta family, w = z - z' (tefmm_delta_derivatives):
+        numpy (n, (2p+1)(2p+2)/2) complex128, entry (m + c)(m + c + 1)/2 + m."""
+        import numpy as np
+        rho = np.ascontiguousarray(rho, np.float64).ravel()
+        w = np.ascontiguousarray(w, np.float64).ravel()
+        if rho.shape != w.shape:
+            raise ValueError("rho and w differ in length")
+        P2 = 2 * self.opt.p
+        out = np.empty((rho.size, (P2 + 1) * (P2 + 2) // 2), np.complex128)
+        m = SIGMA_TABLES[method] if isinstance(method, str) else int(method)
+        _check(lib().tefmm_delta_derivatives(self.h, int(layer), m, rho.size, rho.ctypes.data, w.ctypes.data,
                                               out.ctypes.data, _stream_ptr(stream)), self.h)
         return out
 

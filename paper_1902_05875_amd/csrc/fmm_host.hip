@@ -551,8 +551,11 @@ struct SomPath {
   cplx sinf_u = 0.0, sinf_d = 0.0;
 };
 
+// delta: the Delta family of the layer instead, sigma^{ud} e^{i k_z (D + w)} + sigma^{du}
+// e^{i k_z (D - w)} (w = z - z', D the layer's thickness), whose densities vanish as
+// k_rho grows (no mirror-point image); cu, cd then hold sigma^{ud} and sigma^{du}.
 static void sommerfeld_path(const MediumDesc& med, int l, bool up, bool dn, double zeta_min, double rho_max, int P2,
-                            SomPath& P) {
+                            SomPath& P, bool delta = false) {
   const int ORD = 16;
   std::vector<double> gx, gw;
   gauss_legendre01(ORD, gx, gw);
@@ -572,28 +575,44 @@ static void sommerfeld_path(const MediumDesc& med, int l, bool up, bool dn, doub
   for (int pn = 0; pn < npan; ++pn)
     for (int j = 0; j < ORD; ++j) P.krho.push_back(cplx((pn + gx[j]) * wp, -SOM_B)), wts.push_back(wp * gw[j]);
   std::vector<cplx> sig;
+  const int iu = delta ? 1 : 0, id = delta ? 2 : 3;  // densities: uu, ud, du, dd
   reaction_densities(med, l, cplx(1e8 * med.k[l], 0.0), sig);
-  P.sinf_u = up ? sig[l * 4 + 0] : cplx(0.0);
-  P.sinf_d = dn ? sig[l * 4 + 3] : cplx(0.0);
+  P.sinf_u = up && !delta ? sig[l * 4 + iu] : cplx(0.0);
+  P.sinf_d = dn && !delta ? sig[l * 4 + id] : cplx(0.0);
   const cplx I(0.0, 1.0);
   for (size_t t = 0; t < P.krho.size(); ++t) {
     reaction_densities(med, l, P.krho[t], sig);
     const cplx kz = vertical_wavenumber(med.k[l], P.krho[t]);
     P.kz.push_back(kz);
-    P.cu.push_back(up ? wts[t] * I * (sig[l * 4 + 0] - P.sinf_u) / kz : cplx(0.0));
-    P.cd.push_back(dn ? wts[t] * I * (sig[l * 4 + 3] - P.sinf_d) / kz : cplx(0.0));
+    P.cu.push_back(up ? wts[t] * I * (sig[l * 4 + iu] - P.sinf_u) / kz : cplx(0.0));
+    P.cd.push_back(dn ? wts[t] * I * (sig[l * 4 + id] - P.sinf_d) / kz : cplx(0.0));
   }
 }
 
-// H (one row per pair) of the Sigma families of layer l at the pairs (rho[pr[i]], S[ps[i]]):
-// the mirror-point images by k_sigma_h, then the node contraction added to them.
+// Offsets of the two vertical distances: zeta_u = S - two_dl, zeta_d = two_dt - S.  The
+// Sigma families: S = z + z' against the mirror planes 2 d_l and 2 d_{l-1}; the Delta
+// family: S = w = z - z', zeta = D + w and D - w.
+static void som_offsets(const MediumDesc& med, int l, bool delta, double* two_dl, double* two_dt) {
+  if (delta) {
+    const double D = med.thickness(l);
+    *two_dl = -D, *two_dt = D;
+    return;
+  }
+  *two_dl = l < med.L ? 2 * med.d[l] : 0.0;
+  *two_dt = l > 0 ? 2 * med.d[l - 1] : 0.0;
+}
+
+// H (one row per pair) of the Sigma families (or, delta, the Delta family) of layer l at
+// the pairs (rho[pr[i]], S[ps[i]]): the mirror-point images by k_sigma_h (none for Delta),
+// then the node contraction added to them.
 static int sommerfeld_h(tefmm_t h, int l, bool up, bool dn, const SomPath& P, int P2, const std::vector<double>& rho,
                         const std::vector<double>& S, const std::vector<int>& pr, const std::vector<int>& ps,
-                        double2* d_H, hipStream_t s) {
+                        double2* d_H, hipStream_t s, bool delta = false) {
   const MediumDesc& med = h->med;
   const int nn = (int)P.krho.size(), np = (int)pr.size(), nr = (int)rho.size(), nsv = (int)S.size(), M = P2;
   if (!np) return TEFMM_OK;
-  const double two_dl = l < med.L ? 2 * med.d[l] : 0.0, two_dt = l > 0 ? 2 * med.d[l - 1] : 0.0;
+  double two_dl, two_dt;
+  som_offsets(med, l, delta, &two_dl, &two_dt);
   auto pack = [](const std::vector<cplx>& v) {
     std::vector<double2> o(v.size());
     for (size_t i = 0; i < v.size(); ++i) o[i] = make_double2(v[i].real(), v[i].imag());
@@ -658,9 +677,10 @@ static int sommerfeld_h(tefmm_t h, int l, bool up, bool dn, const SomPath& P, in
 }
 
 // Rows sk.key of d_out (level box size hb) from the Sommerfeld H, computed once per
-// distinct (rho, S) of the keys and rebuilt into the compact Cartesian layout.
+// distinct (rho, S) of the keys and rebuilt into the compact Cartesian layout.  delta:
+// the Delta family at (rho, w = sk.S), added to the rows (which hold the free-space part).
 static int sommerfeld_tables(tefmm_t h, const Group& g, const SomPath& P, const SigmaKeys& sk, double hb,
-                             double2* d_out, hipStream_t s) {
+                             double2* d_out, hipStream_t s, bool delta = false) {
   const int nk = (int)sk.key.size(), P2 = 2 * h->opt.p, nH = (P2 + 1) * (P2 + 2) / 2;
   std::map<double, int> rmap, smap;
   std::map<std::pair<int, int>, int> pmap;
@@ -681,7 +701,8 @@ static int sommerfeld_tables(tefmm_t h, const Group& g, const SomPath& P, const 
   int *d_key = nullptr, *d_hrow = nullptr;
   auto run = [&]() -> int {
     HIPCHK(h, dmalloc(h, &d_H, sizeof(double2) * pr.size() * nH));
-    const int rc = sommerfeld_h(h, g.layer, g.has[0], g.has[1], P, P2, rho, S, pr, ps, d_H, s);
+    const int rc = delta ? sommerfeld_h(h, g.layer, true, true, P, P2, rho, S, pr, ps, d_H, s, true)
+                         : sommerfeld_h(h, g.layer, g.has[0], g.has[1], P, P2, rho, S, pr, ps, d_H, s);
     if (rc != TEFMM_OK) return rc;
     HIPCHK(h, dmalloc(h, &d_x, sizeof(double) * nk));
     HIPCHK(h, dmalloc(h, &d_y, sizeof(double) * nk));
@@ -692,7 +713,7 @@ static int sommerfeld_tables(tefmm_t h, const Group& g, const SomPath& P, const 
     HIPCHK(h, hipMemcpyAsync(d_key, sk.key.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(d_hrow, hrow.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_sigma_restore, dim3(nk), dim3(64), 0, s, d_H, d_x, d_y, nk, d_key, hb, h->med.k[g.layer], P2,
-                       h->nG, h->d_g1, h->d_g3, h->d_gord, d_out, d_hrow);
+                       h->nG, h->d_g1, h->d_g3, h->d_gord, d_out, d_hrow, delta ? 1 : 0);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(s));
     return TEFMM_OK;
@@ -740,6 +761,23 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
     sommerfeld_path(med, l_, g.has[0], g.has[1], zmin, 3.0 * std::sqrt(2.0) * g.side / 4, 2 * h->opt.p, som);
     h->som_nodes = std::max<int64_t>(h->som_nodes, (int64_t)som.krho.size());
   }
+  // Delta rows from the Sommerfeld integrals too (functions of rho and w = z - z'); keys
+  // whose centres are a layer's thickness apart or more join a box outside the layer and
+  // are left out, as in the image route
+  SomPath somd;
+  const bool som_delta = g.has[2] && h->opt.sigma_tables == TEFMM_SIGMA_SOMMERFELD;
+  if (som_delta) {
+    if (2 * h->opt.p > SIGMA_P2_MAX)
+      return fail(h, TEFMM_ERR_UNSUPPORTED, "Sommerfeld Delta tables need 2p <= " + std::to_string(SIGMA_P2_MAX));
+    double zmin = 1e300;
+    for (int lev = 2; lev <= g.depth; ++lev)
+      for (int dz = 0; dz <= 3; ++dz) {
+        const double zd = D - dz * g.side / (1 << lev);
+        if (zd > 1e-9) zmin = std::min(zmin, zd);
+      }
+    sommerfeld_path(med, l_, true, true, zmin, 3.0 * std::sqrt(2.0) * g.side / 4, 2 * h->opt.p, somd, true);
+    h->som_nodes = std::max<int64_t>(h->som_nodes, (int64_t)somd.krho.size());
+  }
   for (int lev = 2; lev <= g.depth; ++lev) {
     const int nb = 1 << lev;
     const double hb = g.side / nb;
@@ -771,7 +809,13 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
               // the key (dx, dy, dz) is the source offset; the kernel is evaluated at the
               // centre displacement target - source = -(dx, dy, dz) h
               if (!nearb) push(-dx, -dy, cplx(-dz, 0), cplx(1, 0), 0, false);
-              if (g.has[2] && (!nearb || leaf)) {
+              if (g.has[2] && (!nearb || leaf) && som_delta) {
+                const double w = -dz * hb;
+                if (D - std::fabs(w) > 1e-9) {
+                  sq.key.push_back((int)start.size() - 1);
+                  sq.X.push_back(-dx * hb), sq.Y.push_back(-dy * hb), sq.S.push_back(w);
+                }
+              } else if (g.has[2] && (!nearb || leaf)) {
                 // w = z_t - z_s = -dz h enters as D + w (flip 0) and D - w (flip 1)
                 for (size_t j = 0; j < g.famA[2].size(); ++j) {
                   const cplx A = g.famA[2][j], Z = g.famZ[2][j];
@@ -845,7 +889,7 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
         h->sur_keys += (int64_t)sk.key.size();
       }
       if (!sq.key.empty()) {
-        int rc = sommerfeld_tables(h, g, som, sq, hb, d_out, s);
+        int rc = sommerfeld_tables(h, g, which == 0 ? somd : som, sq, hb, d_out, s, which == 0);
         if (rc != TEFMM_OK) {
           dfree(h, d_out);
           return rc;
@@ -2864,7 +2908,7 @@ static int surrogate_tables(tefmm_t h, const SigmaKeys& sk, double hb, double2* 
     dfree(h, d_net);
   }
   hipLaunchKernelGGL(k_sigma_restore, dim3(nk), dim3(64), 0, s, d_H, d_x, d_y, nk, d_key, hb,
-                     h->med.k[su->layer], su->P2, nG, h->d_g1, h->d_g3, su->d_gord, d_out, nullptr);
+                     h->med.k[su->layer], su->P2, nG, h->d_g1, h->d_g3, su->d_gord, d_out, nullptr, 0);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(s));
   dfree(h, d_H);
@@ -3229,6 +3273,85 @@ extern "C" int tefmm_sigma_derivatives(tefmm_t h, int layer, int method, int64_t
     HIPCHK(h, hipMemcpyAsync(d_s, S, sizeof(double) * n, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_sigma_h, dim3((unsigned)n), dim3(64), 0, s, d_w, d_s, (int)n, d_img, cnt[0], cnt[1],
                        up ? 2 * med.d[layer] : 0.0, dn ? 2 * med.d[layer - 1] : 0.0, med.k[layer], P2, d_H);
+    HIPCHK(h, hipGetLastError());
+    return TEFMM_OK;
+  };
+  int rc = run();
+  if (rc == TEFMM_OK) {
+    if (hipMemcpyAsync(out, d_H, sizeof(double2) * (size_t)n * nH, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      rc = fail(h, TEFMM_ERR_HIP, "copy of the derivatives");
+  }
+  dfree(h, d_H), dfree(h, d_img), dfree(h, d_w), dfree(h, d_s);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// H_{m,c} of the Delta family of one layer (functions of rho and w = z - z'), by the
+// complex images (Sec. 3.3) or by the Sommerfeld integrals (Sec. 4.2).
+// ---------------------------------------------------------------------------
+extern "C" int tefmm_delta_derivatives(tefmm_t h, int layer, int method, int64_t n, const double* rho,
+                                       const double* w, double* out, void* stream) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  const MediumDesc& med = h->med;
+  if (layer < 0 || layer > med.L) return fail(h, TEFMM_ERR_INVALID_ARG, "layer out of range");
+  if (method != TEFMM_SIGMA_IMAGES && method != TEFMM_SIGMA_SOMMERFELD)
+    return fail(h, TEFMM_ERR_INVALID_ARG, "unknown method");
+  if (n < 1 || n > (1 << 22) || !rho || !w || !out) return fail(h, TEFMM_ERR_INVALID_ARG, "need 1 <= n <= 2^22 points");
+  if (layer == 0 || layer == med.L)
+    return fail(h, TEFMM_ERR_UNSUPPORTED, "the Delta family needs a layer with two interfaces");
+  const int P2 = 2 * h->opt.p, nH = (P2 + 1) * (P2 + 2) / 2;
+  if (P2 > SIGMA_P2_MAX) return fail(h, TEFMM_ERR_UNSUPPORTED, "needs 2p <= " + std::to_string(SIGMA_P2_MAX));
+  const double D = med.thickness(layer);
+  double zmin = 1e300, rmax = 0.0, wmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(rho[i] >= 0 && rho[i] < 1e300) || !(D - std::fabs(w[i]) > 0))
+      return fail(h, TEFMM_ERR_INVALID_ARG, "point " + std::to_string(i) + " outside the layer's Delta range");
+    zmin = std::min(zmin, D - std::fabs(w[i]));
+    rmax = std::max(rmax, rho[i]);
+    wmax = std::max(wmax, std::fabs(w[i]));
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const std::vector<double> vr(rho, rho + n), vw(w, w + n);
+  double2* d_H = nullptr;
+  double2* d_img = nullptr;
+  double *d_w = nullptr, *d_s = nullptr;
+  auto run = [&]() -> int {
+    HIPCHK(h, dmalloc(h, &d_H, sizeof(double2) * (size_t)n * nH));
+    if (method == TEFMM_SIGMA_SOMMERFELD) {
+      SomPath P;
+      sommerfeld_path(med, layer, true, true, zmin, rmax, P2, P, true);
+      std::vector<int> idx(n);
+      for (int64_t i = 0; i < n; ++i) idx[i] = (int)i;
+      return sommerfeld_h(h, layer, true, true, P, P2, vr, vw, idx, idx, d_H, s, true);
+    }
+    // the images of the family fitted for heights spanning the largest |w|; each enters
+    // at D + w and at D - w with the same amplitude
+    std::vector<cplx> A, Z;
+    double fe = 0;
+    std::string err;
+    if (!same_layer_family(med, layer, 2, 0.0, wmax, h->opt.dcim_T1, h->opt.dcim_samples, h->opt.dcim_svd_tol, A, Z,
+                           fe, err))
+      return fail(h, TEFMM_ERR_DCIM_FIT, err);
+    std::vector<double2> img;
+    for (int f = 0; f < 2; ++f)
+      for (size_t j = 0; j < A.size(); ++j) {
+        img.push_back(make_double2(A[j].real(), A[j].imag()));
+        img.push_back(make_double2(Z[j].real(), Z[j].imag()));
+      }
+    std::vector<double> r2(n);
+    for (int64_t i = 0; i < n; ++i) r2[i] = rho[i] * rho[i];
+    HIPCHK(h, dmalloc(h, &d_img, sizeof(double2) * std::max<size_t>(img.size(), 1)));
+    HIPCHK(h, dmalloc(h, &d_w, sizeof(double) * n));
+    HIPCHK(h, dmalloc(h, &d_s, sizeof(double) * n));
+    if (!img.empty())
+      HIPCHK(h, hipMemcpyAsync(d_img, img.data(), sizeof(double2) * img.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_w, r2.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(d_s, w, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    double two_dl, two_dt;
+    som_offsets(med, layer, true, &two_dl, &two_dt);
+    hipLaunchKernelGGL(k_sigma_h, dim3((unsigned)n), dim3(64), 0, s, d_w, d_s, (int)n, d_img, (int)A.size(),
+                       (int)A.size(), two_dl, two_dt, med.k[layer], P2, d_H);
     HIPCHK(h, hipGetLastError());
     return TEFMM_OK;
   };

@@ -1914,13 +1914,15 @@ __global__ void k_sur_h_from_net(const float* y, const double* Re, int n, int P2
 // D+ D- = d_x^2 + d_y^2 = -(d_S^2 + k^2), so for p >= q
 //   D+^p D-^q d_S^c K = (-1)^q sum_t C(q, t) k^(2(q-t)) u^(p-q) H_{p-q, c+2t}
 // (conj(u) and p, q swapped when q > p).  Row of key i: out[row[i]][g] = h^|g| d^g K at
-// (X_i, Y_i) and the point's S, for the compact entries g (g1 <= 2).  One block per key;
-// key i reads H row hrow[i] (row i when hrow is null).
+// (X_i, Y_i) and the point's S, for the compact entries g (g1 <= 2), or added to the row
+// already there (accumulate).  The third variable can be any one the kernel depends on
+// through the target's z alone (S = z + z' for the Sigma families, w = z - z' for Delta).
+// One block per key; key i reads H row hrow[i] (row i when hrow is null).
 __global__ __launch_bounds__(64) void k_sigma_restore(const double2* H, const double* X, const double* Y, int nk,
                                                       const int* row, double h, double k, int P2, int nG,
                                                       const unsigned char* g1s, const unsigned char* g3s,
                                                       const unsigned char* gord, double2* out,
-                                                      const int* hrow) {
+                                                      const int* hrow, int accumulate) {
   __shared__ double2 sh[SIGMA_H_MAX];
   __shared__ double2 up[SIGMA_P2_MAX + 1], dp[SIGMA_P2_MAX + 1];
   __shared__ double fct[SIGMA_P2_MAX + 1];
@@ -1966,7 +1968,8 @@ __global__ __launch_bounds__(64) void k_sigma_restore(const double2* H, const do
     dc ph = {1.0, 0.0};
     for (int j = 0; j < b2; ++j) ph = cmul(ph, {0.0, -1.0});
     acc = cscale(cmul(acc, ph), sc);
-    out[(size_t)row[i] * nG + g] = make_double2(acc.x, acc.y);
+    double2& o = out[(size_t)row[i] * nG + g];
+    o = accumulate ? make_double2(o.x + acc.x, o.y + acc.y) : make_double2(acc.x, acc.y);
   }
 }
 

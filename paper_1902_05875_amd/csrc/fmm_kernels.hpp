@@ -189,7 +189,7 @@ __global__ void k_sur_h_from_net(const float* y, const double* Re, int n, int P2
                                  double2* H);
 __global__ void k_sigma_restore(const double2* H, const double* X, const double* Y, int nk, const int* row, double h,
                                 double k, int P2, int nG, const unsigned char* g1s, const unsigned char* g3s,
-                                const unsigned char* gord, double2* out, const int* hrow);
+                                const unsigned char* gord, double2* out, const int* hrow, int accumulate);
 // Sigma-family H_{m,c} from the Sommerfeld integrals on the deformed contour
 __global__ void k_som_radial(const double2* krho, int nn, const double* rho, int M, double2* A);
 __global__ void k_som_vertical(const double2* kz, const double2* cu, const double2* cd, int nn, const double* S,

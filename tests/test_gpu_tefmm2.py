@@ -1,5 +1,5 @@
-"""TEFMM-II on the GPU (Sec. 4.2): the Sigma-family derivatives from the Sommerfeld
-integrals on the deformed contour, against the oracle's integrals of Eq.
+"""TEFMM-II on the GPU (Sec. 4.2): the Sigma- and Delta-family derivatives from the
+Sommerfeld integrals on the deformed contour, against the oracle's integrals of Eq.
 symmetricdetable, against the complex-image route, and end to end through the FMM."""
 import math
 import os
@@ -102,14 +102,14 @@ def _run(xyz, q, **opt):
 @pytest.mark.parametrize("p,precision,tol", [(4, "fp64", 3e-3), (8, "fp64", 3e-5), (12, "fp64", 1e-6),
                                               (8, "fp32", 1e-4)])
 def test_c1_sommerfeld_tables(p, precision, tol):
-    """N = 1000, depth 2, all targets: the FMM with Sigma rows from the integrals meets the
-    bars of the image tables."""
+    """N = 1000, depth 2, all targets: the FMM with Sigma and Delta rows from the integrals
+    meets the bars of the image tables."""
     from paper_1902_05875_amd import inputs
     xyz, q = inputs.workload("c1")
     idx, ref = _expected("c1")
     phi, st = _run(xyz, q, p=p, depth=2, precision=precision, sigma_tables="sommerfeld")
     assert st["sigma_quad_keys"] > 0 and st["sigma_quad_nodes"] > 0
-    check(f"C1 p={p} {precision} Sommerfeld Sigma rows ({st['sigma_quad_keys']} rows, "
+    check(f"C1 p={p} {precision} Sommerfeld Sigma + Delta rows ({st['sigma_quad_keys']} rows, "
           f"{st['sigma_quad_nodes']} nodes)", phi[idx], ref, tol)
 
 
@@ -119,7 +119,7 @@ def test_n20k_sommerfeld_tables(p, tol):
     xyz, q = inputs.workload("c2", n=20_000)
     idx, ref = _expected("n20k")
     phi, st = _run(xyz, q, p=p, sigma_tables="sommerfeld")
-    check(f"N=20k p={p} depth {st['depth'][0]} Sommerfeld Sigma rows", phi[idx], ref, tol)
+    check(f"N=20k p={p} depth {st['depth'][0]} Sommerfeld Sigma + Delta rows", phi[idx], ref, tol)
 
 
 @pytest.mark.parametrize("p,tol", [(8, 3e-5), (12, 3e-6)])
@@ -130,7 +130,87 @@ def test_three_layers_sommerfeld_tables(p, tol):
     xyz, q = inputs.workload("c3", n=3000)
     idx, ref = _expected("c3small")
     phi, st = _run(xyz, q, p=p, sigma_tables="sommerfeld")
-    check(f"C3 N=3000 p={p} Sommerfeld Sigma rows", phi[idx], ref, tol)
+    check(f"C3 N=3000 p={p} Sommerfeld Sigma + Delta rows", phi[idx], ref, tol)
+
+
+# points (rho, z, z') of the middle layer (thickness 1.2) for the Delta family, w = z - z'
+PTS_D = [(0.1, -0.3, -0.9), (0.35, -0.5, -0.5), (0.8, -1.0, -0.2), (0.2, -0.1, -1.0), (0.6, -0.6, -0.4),
+         (1.0, -0.7, -0.3)]
+
+
+def _oracle_delta_h(p, rho, z, zp):
+    """H_{m,c} of the Delta family from the oracle: the target-up / source-down and
+    target-down / source-up terms of Eq. symmetricdetable, assembled as for the Sigma
+    families (target derivatives (d_x + i d_y)^m d_z^c)."""
+    from oracle import tefmm2 as T
+    from oracle.medium import Medium
+    med = Medium(K3, D3)
+    P2 = 2 * p
+    Sud = T.s_integrals(med, 1, 1, "u", rho, z, zp, p, src=("d",))
+    Sdu = T.s_integrals(med, 1, 1, "d", rho, z, zp, p, src=("u",))
+    H = np.zeros((P2 + 1) * (P2 + 2) // 2, np.complex128)
+    for m in range(P2 + 1):
+        for c in range(P2 + 1 - m):
+            if c > p:
+                H[(m + c) * (m + c + 1) // 2 + m] = np.nan
+                continue
+            v = 2 ** m * math.factorial(c) * math.factorial(m) * (-1) ** m * (Sud[m, 0, c, 0] + Sdu[m, 0, c, 0])
+            H[(m + c) * (m + c + 1) // 2 + m] = 1j * K3[1] * v / rho ** m
+    return H
+
+
+@pytest.mark.parametrize("p", [4, 7])
+def test_delta_h_sommerfeld_vs_oracle_integrals(p):
+    """The Delta family from the integrals (the GPU takes w = z - z' only) against the
+    oracle's integrals at (z, z'), for c <= p, each entry on the largest value of its order
+    m + c at that point: at w = 0 the family is even in w and its odd z derivatives vanish."""
+    from paper_1902_05875_amd import api
+    f = api.TEFMM(K3, D3, p=p)
+    rho = np.array([a for a, _, _ in PTS_D])
+    w = np.array([z - zp for _, z, zp in PTS_D])
+    got = f.delta_derivatives(1, rho, w, "sommerfeld")
+    f.close()
+    worst = 0.0
+    for i, (r, z, zp) in enumerate(PTS_D):
+        ref = _oracle_delta_h(p, r, z, zp)
+        for n in range(2 * p + 1):
+            sl = slice(n * (n + 1) // 2, (n + 1) * (n + 2) // 2)
+            rv, gv = ref[sl], got[i][sl]
+            ok = np.isfinite(rv)
+            worst = max(worst, float(np.max(np.abs(gv[ok] - rv[ok])) / np.max(np.abs(rv[ok]))))
+    print(f"p={p}: Delta family, largest relative difference to the oracle's integrals {worst:.2e}")
+    assert worst < 1e-9
+
+
+@pytest.mark.parametrize("p", [4, 7])
+def test_delta_h_images_vs_sommerfeld(p):
+    """The Delta family's complex images against its integrals, per order m + c on the
+    envelope of that order (printed), to the images' fit accuracy."""
+    from paper_1902_05875_amd import api
+    f = api.TEFMM(K3, D3, p=p)
+    rho = np.array([a for a, _, _ in PTS_D])
+    w = np.array([z - zp for _, z, zp in PTS_D])
+    a = f.delta_derivatives(1, rho, w, "sommerfeld")
+    b = f.delta_derivatives(1, rho, w, "images")
+    f.close()
+    per = []
+    for n in range(2 * p + 1):
+        sl = slice(n * (n + 1) // 2, (n + 1) * (n + 2) // 2)
+        scale = np.max(np.abs(a[:, sl]), axis=1, keepdims=True)
+        per.append(float(np.max(np.abs(a[:, sl] - b[:, sl]) / scale)))
+    print(f"p={p}: Delta images vs integrals, largest difference per order m + c: "
+          + " ".join(f"{e:.1e}" for e in per))
+    assert max(per[:p + 1]) < 1e-5 and max(per) < 1e-3
+
+
+def test_delta_derivatives_errors():
+    from paper_1902_05875_amd import api
+    f = api.TEFMM(K3, D3, p=4)
+    with pytest.raises(api.TefmmError):
+        f.delta_derivatives(1, [0.1], [1.3], "sommerfeld")  # |w| beyond the layer's thickness
+    with pytest.raises(api.TefmmError):
+        f.delta_derivatives(0, [0.1], [0.2], "sommerfeld")  # the top layer has one interface
+    f.close()
 
 
 def test_sigma_derivatives_errors():

@@ -191,3 +191,25 @@ def test_layered_m2l_converges_to_direct_reaction_sum(lp, sc):
         b = sum(T.layered_m2l_matrix(med, 1, lp, c, tc, sc, p) @ a for c in ("u", "d"))
         errs.append(np.max(np.abs(T.evaluate_local(b, tg - tc, p) - direct)) / np.max(np.abs(direct)))
     assert errs[1] < 0.05 * errs[0] and errs[2] < 0.05 * errs[1] and errs[2] < 1e-9, errs
+
+
+def test_delta_terms_depend_on_difference_and_complete_the_reaction():
+    """The two cross terms of Eq. symmetricdetable in one layer (target wave up with the
+    source's down-going part, and the reverse: the Delta family) depend on z - z' alone,
+    which is what lets the GPU tabulate them by offset; with the two Sigma terms they give
+    the whole same-layer reaction kernel of the plain J0 quadrature."""
+    med = Medium((0.8, 1.5, 2.0), (0.0, -1.2))
+
+    def s00(comp, src, rho, z, zp):
+        return T.s_integrals(med, 1, 1, comp, rho, z, zp, 2, src=src)[0, 0, 0, 0]
+
+    for rho, z, zp in [(0.4, -0.3, -0.8), (0.9, -1.0, -0.15)]:
+        delta = s00("u", ("d",), rho, z, zp) + s00("d", ("u",), rho, z, zp)
+        a = 0.1 if z < -0.5 else -0.1
+        shifted = s00("u", ("d",), rho, z + a, zp + a) + s00("d", ("u",), rho, z + a, zp + a)
+        other = s00("u", ("d",), rho, z, zp + a)
+        sigma = s00("u", ("u",), rho, z, zp) + s00("d", ("d",), rho, z, zp)
+        full = reaction_pair(med, 1, 1, np.array([rho]), z, np.array([zp]), normalization="paper")[0]
+        assert abs(delta - shifted) <= 1e-12 * abs(delta)
+        assert abs(other - s00("u", ("d",), rho, z, zp)) > 1e-3 * abs(delta)  # not constant in z'
+        assert abs(sigma + delta - full) <= 1e-10 * abs(full)
