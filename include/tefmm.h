@@ -368,6 +368,21 @@ int tefmm_sigma_derivatives(tefmm_t h, int layer, int method, int64_t n, const d
 int tefmm_delta_derivatives(tefmm_t h, int layer, int method, int64_t n, const double* rho, const double* w,
                             double* out, void* stream);
 
+/* Rotation-free derivatives of the cross-layer reaction kernel, target in layer `layer`
+ * and source in layer `src_layer` (Algorithm 2's components between different layers;
+ * Sec. 4.2): H_{m,c}(rho, z, z') = (2 d_v)^m d_z^c d_{z'}^{k3} K, v = rho^2, m + c <= 2p,
+ * K = i int k_rho J0(k_rho rho) / k_z sum_{a,b} P_a(z) sigma^{ab} E_b(z') dk_rho in the
+ * physical normalisation (k_z of the target layer, P_a the target layer's waves, E_b
+ * the source layer's), stored as for tefmm_sigma_derivatives, from the Sommerfeld
+ * integrals on the contour of Sec. 4.2 (the route of the cross tables under
+ * TEFMM_SIGMA_SOMMERFELD).  rho, z, zs: host arrays of n (1 .. 4096) values with z inside
+ * `layer` and zs inside `src_layer`; 0 <= k3 <= p; out: host array of n (2p+1)(2p+2)/2
+ * complex values, written on success.  Synchronous on `stream`.  Errors:
+ * TEFMM_ERR_INVALID_ARG (equal or bad layers, k3, size, or a point outside its layer),
+ * TEFMM_ERR_UNSUPPORTED (2p above 32), TEFMM_ERR_HIP. */
+int tefmm_cross_derivatives(tefmm_t h, int layer, int src_layer, int k3, int64_t n, const double* rho,
+                            const double* z, const double* zs, double* out, void* stream);
+
 /* TEFMM-II (Sec. 4.1) in free space, symmetric basis (n, m, s), 0 <= s <= m <= n,
  * ordered by n, then m, then s (C(N+3,3) entries up to order N).
  * tefmm_sym_derivatives: D^s_{nm} h0(k|R|) (Eq. sysdifferential applied to h0, derivatives

@@ -34,7 +34,7 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
            "tefmm_reset_timers", "tefmm_set_allocator", "tefmm_gmres", "tefmm_sigma_derivatives",
            "tefmm_radix_sort", "tefmm_exclusive_scan", "tefmm_evaluate_batch_queue", "tefmm_batch_check",
-           "tefmm_sym_derivatives", "tefmm_sym_m2l", "tefmm_delta_derivatives"]
+           "tefmm_sym_derivatives", "tefmm_sym_m2l", "tefmm_delta_derivatives", "tefmm_cross_derivatives"]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -189,6 +189,7 @@ def lib():
         L.tefmm_gmres.argtypes = [vp, dbl, dbl, vp, vp, i32, i32, i32, dbl, vp, ctypes.POINTER(GmresInfoC)]
         L.tefmm_sigma_derivatives.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
         L.tefmm_delta_derivatives.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp]
+        L.tefmm_cross_derivatives.argtypes = [vp, i32, i32, i32, i64, vp, vp, vp, vp, vp]
         L.tefmm_radix_sort.argtypes = [i64, vp, vp, i32, vp]
         L.tefmm_exclusive_scan.argtypes = [i64, vp, vp, vp]
         _lib = L
@@ -373,6 +374,22 @@ class TEFMM:
         m = SIGMA_TABLES[method] if isinstance(method, str) else int(method)
         _check(lib().tefmm_delta_derivatives(self.h, int(layer), m, rho.size, rho.ctypes.data, w.ctypes.data,
                                               out.ctypes.data, _stream_ptr(stream)), self.h)
+        return out
+
+    def cross_derivatives(self, layer, src_layer, k3, rho, z, zs, stream=None):
+        """H_{m,c}(rho_i, z_i, zs_i) of the cross-layer kernel with the source z' derivative of
+        order k3 (tefmm_cross_derivatives): numpy (n, (2p+1)(2p+2)/2) complex128."""
+        import numpy as np
+        rho = np.ascontiguousarray(rho, np.float64).ravel()
+        z = np.ascontiguousarray(z, np.float64).ravel()
+        zs = np.ascontiguousarray(zs, np.float64).ravel()
+        if not (rho.shape == z.shape == zs.shape):
+            raise ValueError("rho, z and zs differ in length")
+        P2 = 2 * self.opt.p
+        out = np.empty((rho.size, (P2 + 1) * (P2 + 2) // 2), np.complex128)
+        _check(lib().tefmm_cross_derivatives(self.h, int(layer), int(src_layer), int(k3), rho.size, rho.ctypes.data,
+                                              z.ctypes.data, zs.ctypes.data, out.ctypes.data, _stream_ptr(stream)),
+               self.h)
         return out
 
     def gmres(self, b, tau, tol=1e-8, restart=30, max_iter=300, x0=None, stream=None):

@@ -554,8 +554,10 @@ struct SomPath {
 // delta: the Delta family of the layer instead, sigma^{ud} e^{i k_z (D + w)} + sigma^{du}
 // e^{i k_z (D - w)} (w = z - z', D the layer's thickness), whose densities vanish as
 // k_rho grows (no mirror-point image); cu, cd then hold sigma^{ud} and sigma^{du}.
-static void sommerfeld_path(const MediumDesc& med, int l, bool up, bool dn, double zeta_min, double rho_max, int P2,
-                            SomPath& P, bool delta = false) {
+// The nodes and weights of the contour (see above) for derivative orders up to P2 and the
+// least vertical distance zeta_min of the keys served.
+static void som_nodes(const MediumDesc& med, double zeta_min, double rho_max, int P2, std::vector<cplx>& krho,
+                      std::vector<cplx>& wts) {
   const int ORD = 16;
   std::vector<double> gx, gw;
   gauss_legendre01(ORD, gx, gw);
@@ -569,11 +571,17 @@ static void sommerfeld_path(const MediumDesc& med, int l, bool up, bool dn, doub
   const double wmax = std::min(2.0, 3.14159265358979324 / std::max(rho_max, 1e-12));
   const int npan = (int)std::ceil(t_max / wmax);
   const double wp = t_max / npan;
-  std::vector<cplx> wts;
-  P.krho.clear(), P.kz.clear(), P.cu.clear(), P.cd.clear();
-  for (int j = 0; j < ORD; ++j) P.krho.push_back(cplx(0.0, -SOM_B * gx[j])), wts.push_back(cplx(0.0, -SOM_B * gw[j]));
+  krho.clear(), wts.clear();
+  for (int j = 0; j < ORD; ++j) krho.push_back(cplx(0.0, -SOM_B * gx[j])), wts.push_back(cplx(0.0, -SOM_B * gw[j]));
   for (int pn = 0; pn < npan; ++pn)
-    for (int j = 0; j < ORD; ++j) P.krho.push_back(cplx((pn + gx[j]) * wp, -SOM_B)), wts.push_back(wp * gw[j]);
+    for (int j = 0; j < ORD; ++j) krho.push_back(cplx((pn + gx[j]) * wp, -SOM_B)), wts.push_back(wp * gw[j]);
+}
+
+static void sommerfeld_path(const MediumDesc& med, int l, bool up, bool dn, double zeta_min, double rho_max, int P2,
+                            SomPath& P, bool delta = false) {
+  std::vector<cplx> wts;
+  som_nodes(med, zeta_min, rho_max, P2, P.krho, wts);
+  P.kz.clear(), P.cu.clear(), P.cd.clear();
   std::vector<cplx> sig;
   const int iu = delta ? 1 : 0, id = delta ? 2 : 3;  // densities: uu, ud, du, dd
   reaction_densities(med, l, cplx(1e8 * med.k[l], 0.0), sig);
@@ -607,12 +615,13 @@ static void som_offsets(const MediumDesc& med, int l, bool delta, double* two_dl
 // then the node contraction added to them.
 static int sommerfeld_h(tefmm_t h, int l, bool up, bool dn, const SomPath& P, int P2, const std::vector<double>& rho,
                         const std::vector<double>& S, const std::vector<int>& pr, const std::vector<int>& ps,
-                        double2* d_H, hipStream_t s, bool delta = false) {
+                        double2* d_H, hipStream_t s, bool delta = false, const double* offs = nullptr) {
   const MediumDesc& med = h->med;
   const int nn = (int)P.krho.size(), np = (int)pr.size(), nr = (int)rho.size(), nsv = (int)S.size(), M = P2;
   if (!np) return TEFMM_OK;
   double two_dl, two_dt;
   som_offsets(med, l, delta, &two_dl, &two_dt);
+  if (offs) two_dl = offs[0], two_dt = offs[1];  // explicit vertical offsets (cross-layer terms)
   auto pack = [](const std::vector<cplx>& v) {
     std::vector<double2> o(v.size());
     for (size_t i = 0; i < v.size(); ++i) o[i] = make_double2(v[i].real(), v[i].imag());
@@ -931,6 +940,130 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
 // ---------------------------------------------------------------------------
 static const double CROSS_THETA = 0.6;
 
+// ---------------------------------------------------------------------------
+// Cross-layer rows from the Sommerfeld integrals (Sec. 4.2).  For a target in layer l and
+// a source in layer l' the kernel is
+//   K = i int k_rho J0(k_rho rho) / k_z sum_{a,b} P_a(z) sigma^{ab}_{l l'} E_b(z') dk_rho
+// (k_z of the target layer; P_u = e^{i k_z (z - d_l)}, P_d = e^{i k_z (d_{l-1} - z)}; E_u,
+// E_d the source layer's waves at z').  For one source height it is the Sigma form in the
+// target's z, with the vertical distances z - d_l and d_{l-1} - z and the node coefficients
+//   cu, cd = w i / k_z sum_b sigma^{ab} (+-i k'_z)^{k3} E_b(z') (-h)^{k3}   (a = u, d),
+// so that the rows hold (-1)^{k3} h^{k3} h^{|g|} D^g d_{z'}^{k3} K as the image rows do.
+// Both waves fall off with k_rho (no mirror-point image).  The rows are written in the
+// frame (z, y, x) of the cross tables (the restore's x and z orders swapped).  Keys whose
+// target or source centre lies outside its layer join boxes without particles and stay zero.
+// ---------------------------------------------------------------------------
+struct CrossKey {
+  int sg, dx, dy, izt, izs;
+};
+
+static int sommerfeld_cross_rows(tefmm_t h, const Group& G, int lev, int k3, const std::vector<CrossKey>& keys,
+                                 double2* d_out, hipStream_t s) {
+  const MediumDesc& med = h->med;
+  const int lt = G.layer, L = med.L, P2 = 2 * h->opt.p, nH = (P2 + 1) * (P2 + 2) / 2;
+  const double hb = G.side / (1 << lev);
+  const bool up = lt < L, dn = lt > 0;
+  const double offs[2] = {up ? med.d[lt] : 0.0, dn ? med.d[lt - 1] : 0.0};
+  const cplx I(0.0, 1.0);
+  auto inside = [&](int l, double z) { return z > med.bottom(l) && z < med.top(l); };
+  std::map<int, std::map<int, std::vector<int>>> by;  // source group -> source slab -> keys
+  for (int i = 0; i < (int)keys.size(); ++i) {
+    const CrossKey& k = keys[i];
+    const Group& S = h->groups[k.sg];
+    const double zt = G.lo[2] + (k.izt + 0.5) * hb, zs = S.lo[2] + (k.izs + 0.5) * hb;
+    if (inside(lt, zt) && inside(S.layer, zs)) by[k.sg][k.izs].push_back(i);
+  }
+  for (auto& sgv : by) {
+    const Group& S = h->groups[sgv.first];
+    const int ls = S.layer;
+    // the least decay length (target to its interface plus source to its interface) and
+    // the largest horizontal distance of the keys served
+    double zmin = 1e300, rmax = 0.0;
+    for (auto& zv : sgv.second)
+      for (int i : zv.second) {
+        const CrossKey& k = keys[i];
+        const double zt = G.lo[2] + (k.izt + 0.5) * hb, zs = S.lo[2] + (k.izs + 0.5) * hb;
+        const double za = std::min(up ? zt - med.d[lt] : 1e300, dn ? med.d[lt - 1] - zt : 1e300);
+        const double zb = std::min(ls < L ? zs - med.d[ls] : 1e300, ls > 0 ? med.d[ls - 1] - zs : 1e300);
+        zmin = std::min(zmin, za + zb);
+        rmax = std::max(rmax, hb * std::hypot((double)k.dx, (double)k.dy));
+      }
+    std::vector<cplx> krho, wts;
+    som_nodes(med, zmin, rmax, P2 + 1, krho, wts);
+    const size_t nn = krho.size();
+    std::vector<cplx> kz(nn), kzp(nn), sg4(4 * nn);
+    std::vector<cplx> sig;
+    for (size_t t = 0; t < nn; ++t) {
+      reaction_densities(med, ls, krho[t], sig);
+      kz[t] = vertical_wavenumber(med.k[lt], krho[t]);
+      kzp[t] = vertical_wavenumber(med.k[ls], krho[t]);
+      for (int j = 0; j < 4; ++j) sg4[4 * t + j] = sig[lt * 4 + j];
+    }
+    h->som_nodes = std::max<int64_t>(h->som_nodes, (int64_t)nn);
+    for (auto& zv : sgv.second) {
+      const double zs = S.lo[2] + (zv.first + 0.5) * hb;
+      SomPath P;
+      P.krho = krho, P.kz = kz;
+      P.cu.resize(nn), P.cd.resize(nn);
+      const double sc = k3 ? -hb : 1.0;
+      for (size_t t = 0; t < nn; ++t) {
+        cplx eu = 0.0, ed = 0.0;
+        if (ls < L) eu = std::pow(I * kzp[t], (double)k3) * std::exp(I * kzp[t] * (zs - med.d[ls]));
+        if (ls > 0) ed = std::pow(-I * kzp[t], (double)k3) * std::exp(I * kzp[t] * (med.d[ls - 1] - zs));
+        const cplx f = wts[t] * I / kz[t] * sc;
+        P.cu[t] = up ? f * (sg4[4 * t + 0] * eu + sg4[4 * t + 1] * ed) : cplx(0.0);
+        P.cd[t] = dn ? f * (sg4[4 * t + 2] * eu + sg4[4 * t + 3] * ed) : cplx(0.0);
+      }
+      // distinct horizontal distances and target heights of these keys, and their pairs
+      std::map<long long, int> rmap, zmap;
+      std::map<std::pair<int, int>, int> pmap;
+      std::vector<double> rho, zt;
+      std::vector<int> pr, ps, hrow, rows;
+      std::vector<double> X, Y;
+      for (int i : zv.second) {
+        const CrossKey& k = keys[i];
+        const long long r2 = (long long)k.dx * k.dx + (long long)k.dy * k.dy;
+        auto ri = rmap.emplace(r2, (int)rho.size());
+        if (ri.second) rho.push_back(hb * std::sqrt((double)r2));
+        auto zi = zmap.emplace(k.izt, (int)zt.size());
+        if (zi.second) zt.push_back(G.lo[2] + (k.izt + 0.5) * hb);
+        auto pi = pmap.emplace(std::make_pair(ri.first->second, zi.first->second), (int)pr.size());
+        if (pi.second) pr.push_back(ri.first->second), ps.push_back(zi.first->second);
+        hrow.push_back(pi.first->second), rows.push_back(i);
+        X.push_back(-k.dx * hb), Y.push_back(-k.dy * hb);
+      }
+      const int nk = (int)rows.size();
+      double2* d_H = nullptr;
+      double *d_x = nullptr, *d_y = nullptr;
+      int *d_row = nullptr, *d_hrow = nullptr;
+      auto run = [&]() -> int {
+        HIPCHK(h, dmalloc(h, &d_H, sizeof(double2) * pr.size() * nH));
+        const int rc = sommerfeld_h(h, lt, up, dn, P, P2, rho, zt, pr, ps, d_H, s, false, offs);
+        if (rc != TEFMM_OK) return rc;
+        HIPCHK(h, dmalloc(h, &d_x, sizeof(double) * nk));
+        HIPCHK(h, dmalloc(h, &d_y, sizeof(double) * nk));
+        HIPCHK(h, dmalloc(h, &d_row, sizeof(int) * nk));
+        HIPCHK(h, dmalloc(h, &d_hrow, sizeof(int) * nk));
+        HIPCHK(h, hipMemcpyAsync(d_x, X.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipMemcpyAsync(d_y, Y.data(), sizeof(double) * nk, hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipMemcpyAsync(d_row, rows.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipMemcpyAsync(d_hrow, hrow.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
+        // frame (z, y, x): the compact entry's first order is the z order, its third the x order
+        hipLaunchKernelGGL(k_sigma_restore, dim3(nk), dim3(64), 0, s, d_H, d_x, d_y, nk, d_row, hb, med.k[lt], P2,
+                           h->nG, h->d_g3, h->d_g1, h->d_gord, d_out, d_hrow, 0);
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipStreamSynchronize(s));
+        return TEFMM_OK;
+      };
+      const int rc = run();
+      dfree(h, d_H), dfree(h, d_x), dfree(h, d_y), dfree(h, d_row), dfree(h, d_hrow);
+      if (rc != TEFMM_OK) return rc;
+      h->som_keys += nk;
+    }
+  }
+  return TEFMM_OK;
+}
+
 static int build_cross(tefmm_t h, int gt, hipStream_t s) {
   Group& G = h->groups[gt];
   const MediumDesc& med = h->med;
@@ -962,9 +1095,7 @@ static int build_cross(tefmm_t h, int gt, hipStream_t s) {
       if (i + d >= 0 && i + d < n) ++c;
     return c;
   };
-  struct KeyRec {
-    int sg, dx, dy, izt, izs;
-  };
+  typedef CrossKey KeyRec;
   std::vector<std::vector<KeyRec>> keys(H + 1);
   std::vector<std::vector<std::vector<CrossEntry>>> lists(H + 1);
   // fits needed: (sg, level, izs)
@@ -1027,7 +1158,10 @@ static int build_cross(tefmm_t h, int gt, hipStream_t s) {
     std::string err;
   };
   std::vector<Job> jobs;
+  // from the Sommerfeld integrals instead: no fits (sommerfeld_cross_rows)
+  const bool som_x = h->opt.sigma_tables == TEFMM_SIGMA_SOMMERFELD;
   for (auto& kv : fitmap) {
+    if (som_x) break;
     int idx = (int)jobs.size();
     kv.second = idx;
     for (int k3 = 0; k3 < 2; ++k3)
@@ -1102,6 +1236,7 @@ static int build_cross(tefmm_t h, int gt, hipStream_t s) {
       for (const KeyRec& kr : keys[lev]) {
         start.push_back((int)terms.size());
         hk.push_back(hb);
+        if (som_x) continue;  // rows written below
         const double zt = G.lo[2] + (kr.izt + 0.5) * hb;
         const int fi = fitmap.at(std::make_tuple(kr.sg, lev, kr.izs));
         for (int wi = 0; wi < (int)waves.size(); ++wi) {
@@ -1145,6 +1280,13 @@ static int build_cross(tefmm_t h, int gt, hipStream_t s) {
         dfree(h, d_terms);
         dfree(h, d_start);
         dfree(h, d_h);
+        if (som_x) {
+          const int rc = sommerfeld_cross_rows(h, G, lev, k3, keys[lev], d_out, s);
+          if (rc != TEFMM_OK) {
+            dfree(h, d_out);
+            return rc;
+          }
+        }
       }
       (k3 ? G.XT1[lev] : G.XT0[lev]) = d_out;
       if (h->opt.precision == TEFMM_MIXED_FP32) {
@@ -3362,6 +3504,67 @@ extern "C" int tefmm_delta_derivatives(tefmm_t h, int layer, int method, int64_t
       rc = fail(h, TEFMM_ERR_HIP, "copy of the derivatives");
   }
   dfree(h, d_H), dfree(h, d_img), dfree(h, d_w), dfree(h, d_s);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// H_{m,c} of the cross-layer kernel (target in `layer`, source in `src_layer`) with the
+// source-side z' derivative of order k3, from the Sommerfeld integrals (Sec. 4.2).
+// ---------------------------------------------------------------------------
+extern "C" int tefmm_cross_derivatives(tefmm_t h, int layer, int src_layer, int k3, int64_t n, const double* rho,
+                                       const double* z, const double* zs, double* out, void* stream) {
+  if (!h) return TEFMM_ERR_INVALID_ARG;
+  const MediumDesc& med = h->med;
+  const int L = med.L;
+  if (layer < 0 || layer > L || src_layer < 0 || src_layer > L || layer == src_layer)
+    return fail(h, TEFMM_ERR_INVALID_ARG, "need two different layers of the medium");
+  if (k3 < 0 || k3 > h->opt.p) return fail(h, TEFMM_ERR_INVALID_ARG, "k3 outside 0 .. p");
+  if (n < 1 || n > 4096 || !rho || !z || !zs || !out) return fail(h, TEFMM_ERR_INVALID_ARG, "need 1 <= n <= 4096 points");
+  const int P2 = 2 * h->opt.p, nH = (P2 + 1) * (P2 + 2) / 2;
+  if (P2 > SIGMA_P2_MAX) return fail(h, TEFMM_ERR_UNSUPPORTED, "needs 2p <= " + std::to_string(SIGMA_P2_MAX));
+  const bool up = layer < L, dn = layer > 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(rho[i] >= 0 && rho[i] < 1e300) || !(z[i] > med.bottom(layer) && z[i] < med.top(layer)) ||
+        !(zs[i] > med.bottom(src_layer) && zs[i] < med.top(src_layer)))
+      return fail(h, TEFMM_ERR_INVALID_ARG, "point " + std::to_string(i) + " outside its layer");
+  hipStream_t s = (hipStream_t)stream;
+  const double offs[2] = {up ? med.d[layer] : 0.0, dn ? med.d[layer - 1] : 0.0};
+  const cplx I(0.0, 1.0);
+  std::vector<double2> hostH((size_t)n * nH);
+  double2* d_H = nullptr;
+  int rc = TEFMM_OK;
+  for (int64_t i = 0; i < n && rc == TEFMM_OK; ++i) {
+    const double za = std::min(up ? z[i] - med.d[layer] : 1e300, dn ? med.d[layer - 1] - z[i] : 1e300);
+    const double zb = std::min(src_layer < L ? zs[i] - med.d[src_layer] : 1e300,
+                               src_layer > 0 ? med.d[src_layer - 1] - zs[i] : 1e300);
+    SomPath P;
+    std::vector<cplx> wts, sig;
+    som_nodes(med, za + zb, std::max(rho[i], 1e-3), P2 + k3, P.krho, wts);
+    for (size_t t = 0; t < P.krho.size(); ++t) {
+      reaction_densities(med, src_layer, P.krho[t], sig);
+      const cplx kz = vertical_wavenumber(med.k[layer], P.krho[t]), kzp = vertical_wavenumber(med.k[src_layer], P.krho[t]);
+      cplx eu = 0.0, ed = 0.0;
+      if (src_layer < L) eu = std::pow(I * kzp, (double)k3) * std::exp(I * kzp * (zs[i] - med.d[src_layer]));
+      if (src_layer > 0) ed = std::pow(-I * kzp, (double)k3) * std::exp(I * kzp * (med.d[src_layer - 1] - zs[i]));
+      const cplx f = wts[t] * I / kz;
+      P.kz.push_back(kz);
+      P.cu.push_back(up ? f * (sig[layer * 4 + 0] * eu + sig[layer * 4 + 1] * ed) : cplx(0.0));
+      P.cd.push_back(dn ? f * (sig[layer * 4 + 2] * eu + sig[layer * 4 + 3] * ed) : cplx(0.0));
+    }
+    const std::vector<double> vr(1, rho[i]), vz(1, z[i]);
+    const std::vector<int> idx(1, 0);
+    auto run = [&]() -> int {
+      HIPCHK(h, dmalloc(h, &d_H, sizeof(double2) * nH));
+      const int r2 = sommerfeld_h(h, layer, up, dn, P, P2, vr, vz, idx, idx, d_H, s, false, offs);
+      if (r2 != TEFMM_OK) return r2;
+      HIPCHK(h, hipMemcpyAsync(hostH.data() + (size_t)i * nH, d_H, sizeof(double2) * nH, hipMemcpyDeviceToHost, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+      return TEFMM_OK;
+    };
+    rc = run();
+    dfree(h, d_H);
+  }
+  if (rc == TEFMM_OK) std::memcpy(out, hostH.data(), sizeof(double2) * (size_t)n * nH);
   return rc;
 }
 

@@ -1,6 +1,7 @@
-"""TEFMM-II on the GPU (Sec. 4.2): the Sigma- and Delta-family derivatives from the
-Sommerfeld integrals on the deformed contour, against the oracle's integrals of Eq.
-symmetricdetable, against the complex-image route, and end to end through the FMM."""
+"""TEFMM-II on the GPU (Sec. 4.2): the Sigma-family, Delta-family and cross-layer
+derivatives from the Sommerfeld integrals on the deformed contour, against the oracle's
+integrals of Eq. symmetricdetable, against the complex-image route, and end to end through
+the FMM."""
 import math
 import os
 
@@ -125,12 +126,15 @@ def test_n20k_sommerfeld_tables(p, tol):
 @pytest.mark.parametrize("p,tol", [(8, 3e-5), (12, 3e-6)])
 def test_three_layers_sommerfeld_tables(p, tol):
     """Three cubes, one per layer (N = 3000, 300 targets): top and bottom layers have one
-    Sigma family each, the middle layer two."""
+    Sigma family each, the middle layer two and the Delta family; every layer pair has
+    cross-layer terms.  All of them from the integrals (no complex-image fit)."""
     from paper_1902_05875_amd import inputs
     xyz, q = inputs.workload("c3", n=3000)
     idx, ref = _expected("c3small")
     phi, st = _run(xyz, q, p=p, sigma_tables="sommerfeld")
-    check(f"C3 N=3000 p={p} Sommerfeld Sigma + Delta rows", phi[idx], ref, tol)
+    assert st["n_cross_fits"] == 0
+    check(f"C3 N=3000 p={p} Sommerfeld rows, same-layer and cross-layer ({st['sigma_quad_keys']} rows)",
+          phi[idx], ref, tol)
 
 
 # points (rho, z, z') of the middle layer (thickness 1.2) for the Delta family, w = z - z'
@@ -201,6 +205,52 @@ def test_delta_h_images_vs_sommerfeld(p):
     print(f"p={p}: Delta images vs integrals, largest difference per order m + c: "
           + " ".join(f"{e:.1e}" for e in per))
     assert max(per[:p + 1]) < 1e-5 and max(per) < 1e-3
+
+
+# (rho, z in the middle layer, z' in the top or bottom layer, source layer)
+PTS_X = [(0.3, -0.2, 0.3, 0), (0.7, -0.5, 0.1, 0), (0.2, -0.9, -1.5, 2), (1.1, -0.4, -1.3, 2)]
+
+
+def _oracle_cross_h(p, k3, rho, z, zs, ls):
+    """H_{m,c} with the source-side z' derivative of order k3 of the cross-layer kernel from
+    the oracle's Eq. symmetricdetable integrals (both target-side waves, both source-side)."""
+    from oracle import tefmm2 as T
+    from oracle.medium import Medium
+    med = Medium(K3, D3)
+    P2 = 2 * p
+    S = T.s_integrals(med, 1, ls, "u", rho, z, zs, p) + T.s_integrals(med, 1, ls, "d", rho, z, zs, p)
+    H = np.zeros((P2 + 1) * (P2 + 2) // 2, np.complex128)
+    for m in range(P2 + 1):
+        for c in range(P2 + 1 - m):
+            if c > p:
+                H[(m + c) * (m + c + 1) // 2 + m] = np.nan
+                continue
+            v = 2 ** m * math.factorial(c) * math.factorial(m) * math.factorial(k3) * (-1) ** m * S[m, 0, c, k3]
+            H[(m + c) * (m + c + 1) // 2 + m] = 1j * K3[1] * v / rho ** m
+    return H
+
+
+@pytest.mark.parametrize("p", [4, 7])
+@pytest.mark.parametrize("k3", [0, 1])
+def test_cross_h_sommerfeld_vs_oracle_integrals(p, k3):
+    """Cross-layer kernel (target in the middle layer, sources above and below) from the
+    integrals against the oracle's, for c <= p, on each order's largest value."""
+    from paper_1902_05875_amd import api
+    f = api.TEFMM(K3, D3, p=p)
+    worst = 0.0
+    for ls in (0, 2):
+        pts = [t for t in PTS_X if t[3] == ls]
+        got = f.cross_derivatives(1, ls, k3, [t[0] for t in pts], [t[1] for t in pts], [t[2] for t in pts])
+        for i, (r, z, zs, _) in enumerate(pts):
+            ref = _oracle_cross_h(p, k3, r, z, zs, ls)
+            for n in range(2 * p + 1):
+                sl = slice(n * (n + 1) // 2, (n + 1) * (n + 2) // 2)
+                rv, gv = ref[sl], got[i][sl]
+                ok = np.isfinite(rv)
+                worst = max(worst, float(np.max(np.abs(gv[ok] - rv[ok])) / np.max(np.abs(rv[ok]))))
+    f.close()
+    print(f"p={p} k3={k3}: cross-layer kernel, largest difference to the oracle's integrals {worst:.2e}")
+    assert worst < 1e-9
 
 
 def test_delta_derivatives_errors():
