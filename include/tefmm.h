@@ -115,8 +115,8 @@ typedef struct {
                          rotation-free derivatives on the deformed contour of Sec. 4.2 (the
                          integrals of Eq. symmetricdetable, no fit), rebuilt exactly into the
                          Cartesian rows.  Rows answered by an attached surrogate stay the
-                         surrogate's; the near-interface pairs evaluated directly and the
-                         cross-layer terms keep the images. */
+                         surrogate's; the near-interface pairs evaluated directly keep the
+                         images. */
 } tefmm_options;
 enum { TEFMM_SIGMA_IMAGES = 0, TEFMM_SIGMA_SOMMERFELD = 1 };
 

@@ -455,7 +455,8 @@ extern "C" int tefmm_create(tefmm_t* out, const tefmm_medium* medium, const tefm
       !(o.interface_eps >= 0) || o.n_rhs_max < 1 ||
       !(o.p2p_targets == -1 || o.p2p_targets == 0 || o.p2p_targets == 1 || o.p2p_targets == 2 ||
         o.p2p_targets == 4) ||
-      (o.precision == TEFMM_FP64 && o.p2p_targets == 4) || !(o.p2p_poly == 0 || o.p2p_poly == -1)) {
+      (o.precision == TEFMM_FP64 && o.p2p_targets == 4) || !(o.p2p_poly == 0 || o.p2p_poly == -1) ||
+      !(o.sigma_tables == TEFMM_SIGMA_IMAGES || o.sigma_tables == TEFMM_SIGMA_SOMMERFELD)) {
     delete h;
     return TEFMM_ERR_INVALID_ARG;
   }
