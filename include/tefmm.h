@@ -100,8 +100,9 @@ typedef struct {
   int p2p_targets;    /* near field with one charge vector: 1, 2 or 4 = each pair of particles in
                          different leaves is evaluated once and its kernel value applied in both
                          directions, with that many targets per GPU lane (FP64: 1 or 2, 4 is
-                         rejected); 0 = that kernel with 2 targets per lane above a mean leaf
-                         occupancy of 96, else 1; -1 = every ordered pair evaluated on its own
+                         rejected); 0 = that kernel with 2 targets per lane above a mean
+                         occupancy of 96 over the occupied leaves, else 1; -1 = every ordered
+                         pair evaluated on its own
                          (also the kernel for several charge vectors) */
   int p2p_poly;       /* FP32 near field (both kernels): 0 = the pair value e^{ikr}/r from
                          two quadratics in r^2 fitted on the host over the distances of a leaf's

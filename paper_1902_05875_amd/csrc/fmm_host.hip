@@ -132,6 +132,13 @@ struct Group {
   // symmetric near field: targets per lane and workgroups per leaf (each taking every
   // p2p_split-th pass of 64 p2p_tpl targets), from the leaf occupancy
   int p2p_tpl = 1, p2p_split = 1;
+  double mean_occ = 0;  // mean particles per occupied leaf
+  // work items of the symmetric near field (leaves with particles, halves with a pass), in
+  // leaf order, and their cut into 8 segments of about equal pair work (one per XCD)
+  std::vector<unsigned> nf_items;
+  XcdSegs nf_seg{};
+  int nf_seg_max = 0;
+  unsigned* d_nf_items = nullptr;
   // FP32 near-field pair value from quadratics in r^2 (np_on) and the fit's error
   NearPoly np{};
   bool np_on = false;
@@ -317,6 +324,7 @@ static void free_geometry(tefmm_t h) {
     dfree(h, g.d_sd_src);
     dfree(h, g.d_sd_img);
     for (auto& p : g.d_occ) dfree(h, p);
+    dfree(h, g.d_nf_items);
   }
   h->groups.clear();
   dfree(h, h->d_q);
@@ -1663,15 +1671,62 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
           h->p2p_pairs += c * nbsum - c;
           h->p2p_same += c * c - c;
         }
-    // targets per lane: 2 above a mean occupancy of 96 over all leaves, else 1 (unless
-    // set); workgroups per leaf: the passes a leaf of mean occupied size needs (at most 8)
+    // targets per lane: 2 above a mean occupancy of 96 over the occupied leaves, else 1
+    // (unless set); workgroups per leaf: the passes a leaf of mean occupied size needs (at
+    // most 8)
     // (the per-level box counts are set up later, with the buffers: the leaf count directly)
     const int64_t nleaf = (int64_t)1 << (3 * g.depth);
     int64_t occ = 0;
     for (int64_t b = 0; b < nleaf; ++b) occ += lc[g.leaf_base + b] > 0;
-    g.p2p_tpl = h->opt.p2p_targets > 0 ? h->opt.p2p_targets : (g.count > 96 * nleaf ? 2 : 1);
     const double mean_occ = occ ? (double)g.count / (double)occ : 0.0;
+    g.mean_occ = mean_occ;
+    g.p2p_tpl = h->opt.p2p_targets > 0 ? h->opt.p2p_targets : (mean_occ > 96 ? 2 : 1);
     g.p2p_split = std::max(1, std::min(8, (int)std::ceil(mean_occ / (64.0 * g.p2p_tpl))));
+    {
+      // the near field's work list: item leaf G + half for each half with a pass, its work
+      // the targets of its passes times the sources of the leaf's forward neighbourhood
+      const int nb = 1 << g.depth, G = g.p2p_split, TP = 64 * g.p2p_tpl;
+      auto cnt = [&](int x, int y, int z) -> int64_t {
+        if (x < 0 || y < 0 || z < 0 || x >= nb || y >= nb || z >= nb) return 0;
+        return lc[g.leaf_base + ((int64_t)x * nb + y) * nb + z];
+      };
+      g.nf_items.clear();
+      std::vector<double> work;
+      for (int ix = 0; ix < nb; ++ix)
+        for (int iy = 0; iy < nb; ++iy)
+          for (int iz = 0; iz < nb; ++iz) {
+            const int64_t c = cnt(ix, iy, iz);
+            if (!c) continue;
+            int64_t src = c + cnt(ix, iy, iz + 1);
+            const int cols[4][2] = {{0, 1}, {1, -1}, {1, 0}, {1, 1}};
+            for (auto& cc : cols)
+              for (int dz = -1; dz <= 1; ++dz) src += cnt(ix + cc[0], iy + cc[1], iz + dz);
+            const unsigned leaf = (unsigned)(((int64_t)ix * nb + iy) * nb + iz);
+            for (int half = 0; half < G && (int64_t)half * TP < c; ++half) {
+              int64_t tg = 0;
+              for (int64_t c0 = (int64_t)half * TP; c0 < c; c0 += (int64_t)G * TP) tg += std::min<int64_t>(TP, c - c0);
+              g.nf_items.push_back(leaf * (unsigned)G + (unsigned)half);
+              work.push_back((double)tg * (double)src);
+            }
+          }
+      double tot = 0;
+      for (double w : work) tot += w;
+      int x = 0;
+      double run = 0;
+      g.nf_seg.start[0] = 0;
+      for (size_t i = 0; i < work.size() && x < 7; ++i) {
+        run += work[i];
+        while (x < 7 && run >= tot * (x + 1) / 8.0) g.nf_seg.start[++x] = (int)i + 1;
+      }
+      while (x < 8) g.nf_seg.start[++x] = (int)work.size();
+      g.nf_seg_max = 0;
+      for (int s8 = 0; s8 < 8; ++s8) g.nf_seg_max = std::max(g.nf_seg_max, g.nf_seg.start[s8 + 1] - g.nf_seg.start[s8]);
+      if (!g.nf_items.empty()) {
+        HIPCHK(h, dmalloc(h, &g.d_nf_items, sizeof(unsigned) * g.nf_items.size()));
+        HIPCHK(h, hipMemcpyAsync(g.d_nf_items, g.nf_items.data(), sizeof(unsigned) * g.nf_items.size(),
+                                 hipMemcpyHostToDevice, s));
+      }
+    }
     g.np_err = 0;
     g.np_on = h->opt.p2p_poly == 0 &&
               fit_near_poly(h->med.k[g.layer], g.side / (double)(1 << g.depth), 3e-7, &g.np, &g.np_err);
@@ -2002,29 +2057,33 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       PassArgs a = pass_args(g);
       a.phi = h->d_phi_near;
       a.nbox_dim = 1 << g.depth, a.h = g.side / (1 << g.depth);
-      const bool wide = g.count > 96 * g.nbox[g.depth];  // mean leaf occupancy above 96
+      const bool wide = g.mean_occ > 96;  // mean occupancy of the occupied leaves above 96
       // several charge vectors share each pair kernel, 8 per block
       const bool multi = nrhs > 1;
       if (!multi && h->d_part) {
         // each pair of particles in different leaves once (k_p2p_sym): 1 or 2 targets per
-        // lane (4 holds more registers than it saves work), G workgroups per leaf, then one
-        // per leaf to gather the source-side sums
+        // lane (4 holds more registers than it saves work), up to G workgroups per leaf over
+        // the balanced work list, then one per leaf to gather the source-side sums
         const int tpl = g.p2p_tpl, G = g.p2p_split;
-        const dim3 grid2((unsigned)(G * g.nbox[g.depth]), 1), grid((unsigned)g.nbox[g.depth], 1);
+        const dim3 grid2((unsigned)(8 * g.nf_seg_max), 1), grid((unsigned)g.nbox[g.depth], 1);
         const int tp = 64 * tpl;
         if (fp32) {
-          void (*fs)(PassArgs, int, int, float2*, NearPoly) =
+          void (*fs)(PassArgs, int, int, float2*, NearPoly, const unsigned*, XcdSegs) =
               g.np_on ? (tpl == 1 ? k_p2p_sym<float, 1, 4, true> : tpl == 2 ? k_p2p_sym<float, 2, 4, true>
                                                                            : k_p2p_sym<float, 4, 4, true>)
                       : (tpl == 1 ? k_p2p_sym<float, 1, 4, false> : tpl == 2 ? k_p2p_sym<float, 2, 4, false>
                                                                             : k_p2p_sym<float, 4, 4, false>);
-          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, G, (float2*)h->d_part, g.np);
+          if (g.nf_seg_max > 0)
+            hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, G, (float2*)h->d_part, g.np,
+                               (const unsigned*)g.d_nf_items, g.nf_seg);
           HIPCHK(h, hipGetLastError());
           hipLaunchKernelGGL(k_p2p_sym_gather<float2>, grid, dim3(128), 0, sn, a, 1, tp, G, (const float2*)h->d_part);
         } else {
-          void (*fs)(PassArgs, int, int, double2*, NearPoly) =
+          void (*fs)(PassArgs, int, int, double2*, NearPoly, const unsigned*, XcdSegs) =
               tpl == 1 ? k_p2p_sym<double, 1, 4, false> : k_p2p_sym<double, 2, 4, false>;
-          hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, G, (double2*)h->d_part, g.np);
+          if (g.nf_seg_max > 0)
+            hipLaunchKernelGGL(fs, grid2, dim3(256), 0, sn, a, 1, G, (double2*)h->d_part, g.np,
+                               (const unsigned*)g.d_nf_items, g.nf_seg);
           HIPCHK(h, hipGetLastError());
           hipLaunchKernelGGL(k_p2p_sym_gather<double2>, grid, dim3(128), 0, sn, a, 1, tp, G, (const double2*)h->d_part);
         }

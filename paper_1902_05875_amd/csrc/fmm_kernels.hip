@@ -1599,19 +1599,17 @@ __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r,
   }
 }
 
-// G workgroups per leaf (see p2p_sym_item), charge vector blockIdx.y.
+// One work item per workgroup (see p2p_sym_item), charge vector blockIdx.y.  Workgroups
+// are dealt round-robin over the 8 XCDs; XCD x takes its segment of the work list in
+// order (neighbouring leaves, whose source leaves overlap in that XCD's L2), the
+// segments holding about equal pair work.  The grid is 8 times the longest segment.
 template <typename R, int T, int NW, bool POLY>
 __global__ __launch_bounds__(64 * NW) void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part,
-                                                     NearPoly np) {
+                                                     NearPoly np, const unsigned* items, XcdSegs seg) {
   __shared__ SymShared<R, T, NW> sh;
-  const int nb = a.nbox_dim;
-  // Workgroups are dealt round-robin over the 8 XCDs: each XCD takes a contiguous
-  // range of work items instead (neighbouring leaves, whose source leaves overlap in
-  // that XCD's L2).  The grid is G 8^depth workgroups, a multiple of 8.
-  const unsigned per = gridDim.x / 8;
-  const int b0 = gridDim.x % 8 ? (int)blockIdx.x : (int)((blockIdx.x % 8) * per + blockIdx.x / 8);
-  for (int wi = b0; wi < G * nb * nb * nb; wi += gridDim.x)
-    p2p_sym_item<R, T, NW, POLY>(a, nrhs, blockIdx.y, G, part, np, wi, sh);
+  const int x = blockIdx.x % 8, j = seg.start[x] + (int)(blockIdx.x / 8);
+  if (j >= seg.start[x + 1]) return;
+  p2p_sym_item<R, T, NW, POLY>(a, nrhs, blockIdx.y, G, part, np, (int)items[j], sh);
 }
 
 // Adds to each particle of leaf B the source-side sums that its backward
@@ -1735,14 +1733,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
 template __global__ void k_nf_queue<float>(NFQueueArgs);
 template __global__ void k_nf_queue<double>(NFQueueArgs);
 
-template __global__ void k_p2p_sym<float, 1, 4, false>(PassArgs, int, int, float2*, NearPoly);
-template __global__ void k_p2p_sym<float, 2, 4, false>(PassArgs, int, int, float2*, NearPoly);
-template __global__ void k_p2p_sym<float, 4, 4, false>(PassArgs, int, int, float2*, NearPoly);
-template __global__ void k_p2p_sym<float, 1, 4, true>(PassArgs, int, int, float2*, NearPoly);
-template __global__ void k_p2p_sym<float, 2, 4, true>(PassArgs, int, int, float2*, NearPoly);
-template __global__ void k_p2p_sym<float, 4, 4, true>(PassArgs, int, int, float2*, NearPoly);
-template __global__ void k_p2p_sym<double, 1, 4, false>(PassArgs, int, int, double2*, NearPoly);
-template __global__ void k_p2p_sym<double, 2, 4, false>(PassArgs, int, int, double2*, NearPoly);
+template __global__ void k_p2p_sym<float, 1, 4, false>(PassArgs, int, int, float2*, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p_sym<float, 2, 4, false>(PassArgs, int, int, float2*, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p_sym<float, 4, 4, false>(PassArgs, int, int, float2*, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p_sym<float, 1, 4, true>(PassArgs, int, int, float2*, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p_sym<float, 2, 4, true>(PassArgs, int, int, float2*, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p_sym<float, 4, 4, true>(PassArgs, int, int, float2*, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p_sym<double, 1, 4, false>(PassArgs, int, int, double2*, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p_sym<double, 2, 4, false>(PassArgs, int, int, double2*, NearPoly, const unsigned*, XcdSegs);
 template __global__ void k_p2p_sym_gather<float2>(PassArgs, int, int, int, const float2*);
 template __global__ void k_p2p_sym_gather<double2>(PassArgs, int, int, int, const double2*);
 

@@ -237,8 +237,15 @@ struct SymTypes<double> {
   typedef double4 R4;
   typedef double2 R2;
 };
+// Work items of the symmetric near field (leaf G + half, see p2p_sym_item) in leaf
+// order, cut into 8 contiguous segments of about equal pair work, one per XCD:
+// segment x is items[start[x] .. start[x + 1]).
+struct XcdSegs {
+  int start[9];
+};
 template <typename R, int T, int NW, bool POLY>
-__global__ void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part, NearPoly np);
+__global__ void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part, NearPoly np,
+                          const unsigned* items, XcdSegs seg);
 template <typename R2>
 __global__ void k_p2p_sym_gather(PassArgs a, int nrhs, int tp, int G, const R2* part);
 
