@@ -1721,6 +1721,17 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
       while (x < 8) g.nf_seg.start[++x] = (int)work.size();
       g.nf_seg_max = 0;
       for (int s8 = 0; s8 < 8; ++s8) g.nf_seg_max = std::max(g.nf_seg_max, g.nf_seg.start[s8 + 1] - g.nf_seg.start[s8]);
+      // within a segment the longest items first (stable), so that the last ones dealt out
+      // are short
+      for (int s8 = 0; s8 < 8; ++s8) {
+        const int b = g.nf_seg.start[s8], e = g.nf_seg.start[s8 + 1];
+        std::vector<int> ord(e - b);
+        for (int i = 0; i < e - b; ++i) ord[i] = b + i;
+        std::stable_sort(ord.begin(), ord.end(), [&](int u, int v) { return work[u] > work[v]; });
+        std::vector<unsigned> seg(e - b);
+        for (int i = 0; i < e - b; ++i) seg[i] = g.nf_items[ord[i]];
+        std::copy(seg.begin(), seg.end(), g.nf_items.begin() + b);
+      }
       if (!g.nf_items.empty()) {
         HIPCHK(h, dmalloc(h, &g.d_nf_items, sizeof(unsigned) * g.nf_items.size()));
         HIPCHK(h, hipMemcpyAsync(g.d_nf_items, g.nf_items.data(), sizeof(unsigned) * g.nf_items.size(),
