@@ -94,17 +94,20 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   T2* sA = sG + padG + 1;  // sG[padG]: a zero read by lanes with no table entry
   int* sCol = (int*)(sA + NT * a.nRsP);    // [4 nKB]: column offset | k3' parity << 20 | valid << 21
 
-  // Block -> (level, tile).  The coarse levels come first and keep the hardware's
-  // round-robin over the XCDs; tiles of the last (widest) level are remapped so
-  // that consecutive tiles (same z slab) stay on one XCD.
+  // Block -> (level, tile).  The widest level's tiles come first (they hold the most
+  // offsets, so the coarse levels' shorter workgroups are dealt out last), remapped so
+  // that consecutive tiles (same z slab) stay on one XCD; the coarse levels keep the
+  // hardware's round-robin over the XCDs.
   int li = 0, tile = 0;
   const int widest = a.nlev - 1;
-  if ((int)blockIdx.x < a.tile_start[widest]) {
-    while ((int)blockIdx.x >= a.tile_start[li + 1]) ++li;
-    tile = blockIdx.x - a.tile_start[li];
+  const int nwide = a.tile_start[widest + 1] - a.tile_start[widest];  // a multiple of 8
+  if ((int)blockIdx.x >= nwide) {
+    const int bc = blockIdx.x - nwide;
+    while (bc >= a.tile_start[li + 1]) ++li;
+    tile = bc - a.tile_start[li];
   } else {
     li = widest;
-    const int b = blockIdx.x - a.tile_start[widest];
+    const int b = blockIdx.x;
     const int nt = a.lev[li].ntiles;
     const int per = (nt + 7) / 8;
     tile = (b % 8) * per + b / 8;
