@@ -2068,7 +2068,9 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       PassArgs a = pass_args(g);
       a.phi = h->d_phi_near;
       a.nbox_dim = 1 << g.depth, a.h = g.side / (1 << g.depth);
-      const bool wide = g.mean_occ > 96;  // mean occupancy of the occupied leaves above 96
+      // one-sided kernel: one target per thread, a block of 64, 128 or 256 threads by the
+      // mean occupancy of the occupied leaves (a leaf's targets in as few passes as fill them)
+      const int bs = g.mean_occ > 192 ? 256 : g.mean_occ > 64 ? 128 : 64;
       // several charge vectors share each pair kernel, 8 per block
       const bool multi = nrhs > 1;
       if (!multi && h->d_part) {
@@ -2104,15 +2106,18 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
       const dim3 grid((unsigned)g.nbox[g.depth], multi ? (nrhs + 7) / 8 : 1);
       void (*fn)(PassArgs, int, NearPoly) = nullptr;
       if (fp32 && g.np_on)
-        fn = wide ? (multi ? k_p2p<float, 256, 8, true> : k_p2p<float, 256, 1, true>)
-                  : (multi ? k_p2p<float, 64, 8, true> : k_p2p<float, 64, 1, true>);
+        fn = bs == 256   ? (multi ? k_p2p<float, 256, 8, true> : k_p2p<float, 256, 1, true>)
+             : bs == 128 ? (multi ? k_p2p<float, 128, 8, true> : k_p2p<float, 128, 1, true>)
+                         : (multi ? k_p2p<float, 64, 8, true> : k_p2p<float, 64, 1, true>);
       else if (fp32)
-        fn = wide ? (multi ? k_p2p<float, 256, 8, false> : k_p2p<float, 256, 1, false>)
-                  : (multi ? k_p2p<float, 64, 8, false> : k_p2p<float, 64, 1, false>);
+        fn = bs == 256   ? (multi ? k_p2p<float, 256, 8, false> : k_p2p<float, 256, 1, false>)
+             : bs == 128 ? (multi ? k_p2p<float, 128, 8, false> : k_p2p<float, 128, 1, false>)
+                         : (multi ? k_p2p<float, 64, 8, false> : k_p2p<float, 64, 1, false>);
       else
-        fn = wide ? (multi ? k_p2p<double, 256, 8, false> : k_p2p<double, 256, 1, false>)
-                  : (multi ? k_p2p<double, 64, 8, false> : k_p2p<double, 64, 1, false>);
-      hipLaunchKernelGGL(fn, grid, dim3(wide ? 256 : 64), 0, sn, a, nrhs, g.np);
+        fn = bs == 256   ? (multi ? k_p2p<double, 256, 8, false> : k_p2p<double, 256, 1, false>)
+             : bs == 128 ? (multi ? k_p2p<double, 128, 8, false> : k_p2p<double, 128, 1, false>)
+                         : (multi ? k_p2p<double, 64, 8, false> : k_p2p<double, 64, 1, false>);
+      hipLaunchKernelGGL(fn, grid, dim3(bs), 0, sn, a, nrhs, g.np);
       HIPCHK(h, hipGetLastError());
     }
     if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + 6], sn));

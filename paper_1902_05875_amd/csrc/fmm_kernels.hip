@@ -940,11 +940,11 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
                                              const float (*sq)[2 * RB], const int* sidx, float rns2, float ecr,
                                              float eci, double kap, const PassArgs& a, int64_t i, double txd,
                                              double tyd, double tzd, int r0, int nrhs, float* accr, float* acci,
-                                             double* nsr, double* nsi, const NearPoly& np) {
+                                             double* ns, const NearPoly& np) {
   // OWN (the column holding the target itself): the pair of a particle with itself,
   // found by its index, gets weight 0 in the FP32 sum and is moved out of the near test;
   // pairs with r2 < rns2 (a distinct particle at FP32 distance 0 included) are taken
-  // back and redone in FP64
+  // back and redone in FP64, their sums kept in ns[2 b], ns[2 b + 1] (FP64, in LDS: rare)
   const unsigned near_lim = (unsigned)__float_as_int(rns2);
   auto nearp = [&](float r2) { return (unsigned)__float_as_int(r2) < near_lim; };
   auto fixup = [&](int t, float r2) {
@@ -960,18 +960,34 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
       if (r0 + b < nrhs) {
         const double2 qv = a.q[(int64_t)(r0 + b) * a.n + j];
         const double qr = sq[t][2 * b], qi = sq[t][2 * b + 1];
-        nsr[b] += qv.x * er - qv.y * ei - kap * (qr * ecr - qi * eci);
-        nsi[b] += qv.x * ei + qv.y * er - kap * (qr * eci + qi * ecr);
+        ns[2 * b] += qv.x * er - qv.y * ei - kap * (qr * ecr - qi * eci);
+        ns[2 * b + 1] += qv.x * ei + qv.y * er - kap * (qr * eci + qi * ecr);
       }
   };
-  auto pair = [&](int t, float r2) {
+  // a source's charges in registers: RB complex values, loaded four floats at a time
+  // (two at RB = 1), so that the next source's are in flight while this one's sums form
+  constexpr int Q4 = (2 * RB + 3) / 4;
+  struct QV {
+    float4 v[Q4];
+  };
+  auto qload = [&](int t, QV& q) {
+    if constexpr (RB == 1) {
+      const float2 c = *(const float2*)sq[t];
+      q.v[0] = make_float4(c.x, c.y, 0.0f, 0.0f);
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q4; ++k) q.v[k] = ((const float4*)sq[t])[k];
+    }
+  };
+  auto pair = [&](float r2, const QV& q, bool self) {
     // max of two non-negative floats as the max of their bit patterns (no canonicalising)
     float er, ei;
     pair_value<POLY>(__int_as_float(max(__float_as_int(r2), __float_as_int(rns2))), np, &er, &ei);
-    if (OWN && sidx[t] == i) er = 0.0f, ei = 0.0f;
+    if (self) er = 0.0f, ei = 0.0f;
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
-      const float qr = sq[t][2 * b], qi = sq[t][2 * b + 1];
+      const float4 w = q.v[b >> 1];
+      const float qr = (b & 1) ? w.z : w.x, qi = (b & 1) ? w.w : w.y;
       accr[b] = fmaf(qr, er, fmaf(-qi, ei, accr[b]));
       acci[b] = fmaf(qr, ei, fmaf(qi, er, acci[b]));
       // keep the sums with this source (else the compiler defers them and holds every pair value)
@@ -980,6 +996,8 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
   };
   m = __builtin_amdgcn_readfirstlane(m);
   int t = 0;
+  QV qa, qb;
+  if (m >= 4) qload(0, qa);
   for (; t + 4 <= m; t += 4) {
     float r2[4];
 #pragma unroll
@@ -989,7 +1007,14 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
       r2[u] = dx * dx + dy * dy + dz * dz;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) pair(t + u, r2[u]);
+    for (int u = 0; u < 4; ++u) {
+      // source t + u's charges are in qa (u even) or qb (u odd); the next source's go
+      // into the other set before this one's sums
+      QV& cur = (u & 1) ? qb : qa;
+      QV& nxt = (u & 1) ? qa : qb;
+      if (u < 3 || t + 4 < m) qload(t + u + 1, nxt);
+      pair(r2[u], cur, OWN && sidx[t + u] == i);
+    }
     // the self pair's stand-in distance: beyond the near test (after its use above,
     // where only its weight mattered)
     if (OWN)
@@ -1006,7 +1031,9 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
     const float4 s = s4[t];
     const float dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
     float r2 = dx * dx + dy * dy + dz * dz;
-    pair(t, r2);
+    QV q;
+    qload(t, q);
+    pair(r2, q, OWN && sidx[t] == i);
     if (OWN && sidx[t] == i) r2 = 3.0e38f;
     fixup(t, r2);
   }
@@ -1020,8 +1047,10 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs, NearPoly np) {
   // FP64 sources as three coordinate arrays; FP32 sources as (x, y, z, unused)
   __shared__ T sx[F32 ? 1 : BS], sy[F32 ? 1 : BS], sz[F32 ? 1 : BS];
   __shared__ float4 s4[F32 ? BS : 1];
-  __shared__ T sq[BS][2 * RB];
+  __shared__ __align__(16) T sq[BS][2 * RB];
   __shared__ int sidx[BS];
+  // FP32: each target's FP64 sums of its near-singular pairs (rare), per charge vector
+  __shared__ double sns[F32 ? BS : 1][2 * RB];
   const int leaf = blockIdx.x, r0 = blockIdx.y * RB, tid = threadIdx.x;
   const int nb = a.nbox_dim;
   const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
@@ -1043,9 +1072,11 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs, NearPoly np) {
     // coordinates relative to the root corner keep FP32 differences accurate
     const T tx = (T)((txd - a.lo[0]) * kap), ty = (T)((tyd - a.lo[1]) * kap), tz = (T)((tzd - a.lo[2]) * kap);
     T accr[RB], acci[RB];
-    double nsr[RB], nsi[RB];  // near-singular pairs (FP32 path only)
 #pragma unroll
-    for (int b = 0; b < RB; ++b) accr[b] = 0, acci[b] = 0, nsr[b] = 0.0, nsi[b] = 0.0;
+    for (int b = 0; b < RB; ++b) accr[b] = 0, acci[b] = 0;
+    if constexpr (F32)
+#pragma unroll
+      for (int b = 0; b < 2 * RB; ++b) sns[tid][b] = 0.0;
     for (int col = 0; col < 9; ++col) {
       const int jx = ix + col / 3 - 1, jy = iy + col % 3 - 1;
       if (jx < 0 || jy < 0 || jx >= nb || jy >= nb) continue;
@@ -1075,10 +1106,10 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs, NearPoly np) {
         if constexpr (F32) {
           if (col == 4)
             p2p_f32_rows<RB, POLY, true>(m, tx, ty, tz, s4, sq, sidx, rns2, ecr, eci, kap, a, i, txd, tyd, tzd, r0,
-                                         nrhs, accr, acci, nsr, nsi, np);
+                                         nrhs, accr, acci, sns[tid], np);
           else
             p2p_f32_rows<RB, POLY, false>(m, tx, ty, tz, s4, sq, sidx, rns2, ecr, eci, kap, a, i, txd, tyd, tzd, r0,
-                                          nrhs, accr, acci, nsr, nsi, np);
+                                          nrhs, accr, acci, sns[tid], np);
         } else {
           // Only the centre column holds the target itself; there the pair with
           // r2 = 0 (same coordinates, same arithmetic) gets weight 0, branch free.
@@ -1103,7 +1134,8 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs, NearPoly np) {
       for (int b = 0; b < RB; ++b)
         if (r0 + b < nrhs)
           a.phi[(int64_t)(r0 + b) * a.n + i] =
-              make_double2((double)accr[b] * kap + nsr[b], (double)acci[b] * kap + nsi[b]);
+              make_double2((double)accr[b] * kap + (F32 ? sns[tid][2 * b] : 0.0),
+                           (double)acci[b] * kap + (F32 ? sns[tid][2 * b + 1] : 0.0));
   }
 }
 
@@ -1756,6 +1788,12 @@ template __global__ void k_p2p<float, 64, 8, true>(PassArgs, int, NearPoly);
 template __global__ void k_p2p<double, 256, 8, false>(PassArgs, int, NearPoly);
 template __global__ void k_p2p<float, 256, 8, false>(PassArgs, int, NearPoly);
 template __global__ void k_p2p<float, 256, 8, true>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<double, 128, 1, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 128, 1, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 128, 1, true>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<double, 128, 8, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 128, 8, false>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<float, 128, 8, true>(PassArgs, int, NearPoly);
 
 // ---------------------------------------------------------------------------
 // Surrogate tables.  Entry g of a reaction table at (x, y, S) is scaled by the
