@@ -139,6 +139,12 @@ struct Group {
   XcdSegs nf_seg{};
   int nf_seg_max = 0;
   unsigned* d_nf_items = nullptr;
+  // the same for the one-sided near field: occupied leaves, work = targets x the particles of
+  // the 27-leaf block
+  std::vector<unsigned> p2p_items;
+  XcdSegs p2p_seg{};
+  int p2p_seg_max = 0;
+  unsigned* d_p2p_items = nullptr;
   // FP32 near-field pair value from quadratics in r^2 (np_on) and the fit's error
   NearPoly np{};
   bool np_on = false;
@@ -325,6 +331,7 @@ static void free_geometry(tefmm_t h) {
     dfree(h, g.d_sd_img);
     for (auto& p : g.d_occ) dfree(h, p);
     dfree(h, g.d_nf_items);
+    dfree(h, g.d_p2p_items);
   }
   h->groups.clear();
   dfree(h, h->d_q);
@@ -936,6 +943,34 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
     }
   }
   return TEFMM_OK;
+}
+
+// Near-field work list (items in leaf order, work per item) cut into 8 contiguous
+// segments of about equal work, one per XCD, the longest items first within a segment
+// (stable), so that the last workgroups dealt out are short.
+static void cut_xcd_segments(std::vector<unsigned>& items, const std::vector<double>& work, XcdSegs& seg,
+                             int& seg_max) {
+  double tot = 0;
+  for (double w : work) tot += w;
+  int x = 0;
+  double run = 0;
+  seg.start[0] = 0;
+  for (size_t i = 0; i < work.size() && x < 7; ++i) {
+    run += work[i];
+    while (x < 7 && run >= tot * (x + 1) / 8.0) seg.start[++x] = (int)i + 1;
+  }
+  while (x < 8) seg.start[++x] = (int)work.size();
+  seg_max = 0;
+  for (int s8 = 0; s8 < 8; ++s8) seg_max = std::max(seg_max, seg.start[s8 + 1] - seg.start[s8]);
+  for (int s8 = 0; s8 < 8; ++s8) {
+    const int b = seg.start[s8], e = seg.start[s8 + 1];
+    std::vector<int> ord(e - b);
+    for (int i = 0; i < e - b; ++i) ord[i] = b + i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int u, int v) { return work[u] > work[v]; });
+    std::vector<unsigned> sg(e - b);
+    for (int i = 0; i < e - b; ++i) sg[i] = items[ord[i]];
+    std::copy(sg.begin(), sg.end(), items.begin() + b);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1709,32 +1744,31 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
               work.push_back((double)tg * (double)src);
             }
           }
-      double tot = 0;
-      for (double w : work) tot += w;
-      int x = 0;
-      double run = 0;
-      g.nf_seg.start[0] = 0;
-      for (size_t i = 0; i < work.size() && x < 7; ++i) {
-        run += work[i];
-        while (x < 7 && run >= tot * (x + 1) / 8.0) g.nf_seg.start[++x] = (int)i + 1;
-      }
-      while (x < 8) g.nf_seg.start[++x] = (int)work.size();
-      g.nf_seg_max = 0;
-      for (int s8 = 0; s8 < 8; ++s8) g.nf_seg_max = std::max(g.nf_seg_max, g.nf_seg.start[s8 + 1] - g.nf_seg.start[s8]);
-      // within a segment the longest items first (stable), so that the last ones dealt out
-      // are short
-      for (int s8 = 0; s8 < 8; ++s8) {
-        const int b = g.nf_seg.start[s8], e = g.nf_seg.start[s8 + 1];
-        std::vector<int> ord(e - b);
-        for (int i = 0; i < e - b; ++i) ord[i] = b + i;
-        std::stable_sort(ord.begin(), ord.end(), [&](int u, int v) { return work[u] > work[v]; });
-        std::vector<unsigned> seg(e - b);
-        for (int i = 0; i < e - b; ++i) seg[i] = g.nf_items[ord[i]];
-        std::copy(seg.begin(), seg.end(), g.nf_items.begin() + b);
-      }
+      cut_xcd_segments(g.nf_items, work, g.nf_seg, g.nf_seg_max);
       if (!g.nf_items.empty()) {
         HIPCHK(h, dmalloc(h, &g.d_nf_items, sizeof(unsigned) * g.nf_items.size()));
         HIPCHK(h, hipMemcpyAsync(g.d_nf_items, g.nf_items.data(), sizeof(unsigned) * g.nf_items.size(),
+                                 hipMemcpyHostToDevice, s));
+      }
+      // the one-sided kernel's list: occupied leaves, work = targets x the 27-leaf block
+      g.p2p_items.clear();
+      work.clear();
+      for (int ix = 0; ix < nb; ++ix)
+        for (int iy = 0; iy < nb; ++iy)
+          for (int iz = 0; iz < nb; ++iz) {
+            const int64_t c = cnt(ix, iy, iz);
+            if (!c) continue;
+            int64_t src = 0;
+            for (int dx = -1; dx <= 1; ++dx)
+              for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) src += cnt(ix + dx, iy + dy, iz + dz);
+            g.p2p_items.push_back((unsigned)(((int64_t)ix * nb + iy) * nb + iz));
+            work.push_back((double)c * (double)src);
+          }
+      cut_xcd_segments(g.p2p_items, work, g.p2p_seg, g.p2p_seg_max);
+      if (!g.p2p_items.empty()) {
+        HIPCHK(h, dmalloc(h, &g.d_p2p_items, sizeof(unsigned) * g.p2p_items.size()));
+        HIPCHK(h, hipMemcpyAsync(g.d_p2p_items, g.p2p_items.data(), sizeof(unsigned) * g.p2p_items.size(),
                                  hipMemcpyHostToDevice, s));
       }
     }
@@ -2103,8 +2137,8 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
         HIPCHK(h, hipGetLastError());
         continue;
       }
-      const dim3 grid((unsigned)g.nbox[g.depth], multi ? (nrhs + 7) / 8 : 1);
-      void (*fn)(PassArgs, int, NearPoly) = nullptr;
+      const dim3 grid((unsigned)(8 * g.p2p_seg_max), multi ? (nrhs + 7) / 8 : 1);
+      void (*fn)(PassArgs, int, NearPoly, const unsigned*, XcdSegs) = nullptr;
       if (fp32 && g.np_on)
         fn = bs == 256   ? (multi ? k_p2p<float, 256, 8, true> : k_p2p<float, 256, 1, true>)
              : bs == 128 ? (multi ? k_p2p<float, 128, 8, true> : k_p2p<float, 128, 1, true>)
@@ -2117,7 +2151,8 @@ static int enqueue_evaluate(tefmm_t h, const double* q, int nrhs, double* phi, h
         fn = bs == 256   ? (multi ? k_p2p<double, 256, 8, false> : k_p2p<double, 256, 1, false>)
              : bs == 128 ? (multi ? k_p2p<double, 128, 8, false> : k_p2p<double, 128, 1, false>)
                          : (multi ? k_p2p<double, 64, 8, false> : k_p2p<double, 64, 1, false>);
-      hipLaunchKernelGGL(fn, grid, dim3(bs), 0, sn, a, nrhs, g.np);
+      if (g.p2p_seg_max > 0)
+        hipLaunchKernelGGL(fn, grid, dim3(bs), 0, sn, a, nrhs, g.np, (const unsigned*)g.d_p2p_items, g.p2p_seg);
       HIPCHK(h, hipGetLastError());
     }
     if (timed) HIPCHK(h, hipEventRecord(h->ev[9 * evset + 6], sn));

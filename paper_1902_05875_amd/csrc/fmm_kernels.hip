@@ -1042,7 +1042,7 @@ __device__ __forceinline__ void p2p_f32_rows(int m, float tx, float ty, float tz
 // RB charge vectors per block (blockIdx.y = group of RB): the pair kernel is
 // computed once and applied to all of them, in the same order as for one vector.
 template <typename T, int BS, int RB, bool POLY>
-__global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs, NearPoly np) {
+__global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs, NearPoly np, const unsigned* items, XcdSegs seg) {
   constexpr bool F32 = sizeof(T) == 4;
   // FP64 sources as three coordinate arrays; FP32 sources as (x, y, z, unused)
   __shared__ T sx[F32 ? 1 : BS], sy[F32 ? 1 : BS], sz[F32 ? 1 : BS];
@@ -1051,7 +1051,11 @@ __global__ __launch_bounds__(BS) void k_p2p(PassArgs a, int nrhs, NearPoly np) {
   __shared__ int sidx[BS];
   // FP32: each target's FP64 sums of its near-singular pairs (rare), per charge vector
   __shared__ double sns[F32 ? BS : 1][2 * RB];
-  const int leaf = blockIdx.x, r0 = blockIdx.y * RB, tid = threadIdx.x;
+  // the leaf: item blockIdx.x / 8 of XCD segment blockIdx.x % 8 (occupied leaves, the
+  // longest first within a segment)
+  const int xs_ = blockIdx.x % 8, j_ = seg.start[xs_] + (int)(blockIdx.x / 8);
+  if (j_ >= seg.start[xs_ + 1]) return;
+  const int leaf = (int)items[j_], r0 = blockIdx.y * RB, tid = threadIdx.x;
   const int nb = a.nbox_dim;
   const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
   const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
@@ -1776,24 +1780,24 @@ template __global__ void k_p2p_sym<double, 2, 4, false>(PassArgs, int, int, doub
 template __global__ void k_p2p_sym_gather<float2>(PassArgs, int, int, int, const float2*);
 template __global__ void k_p2p_sym_gather<double2>(PassArgs, int, int, int, const double2*);
 
-template __global__ void k_p2p<double, 64, 1, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 64, 1, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 64, 1, true>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<double, 256, 1, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 256, 1, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 256, 1, true>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<double, 64, 8, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 64, 8, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 64, 8, true>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<double, 256, 8, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 256, 8, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 256, 8, true>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<double, 128, 1, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 128, 1, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 128, 1, true>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<double, 128, 8, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 128, 8, false>(PassArgs, int, NearPoly);
-template __global__ void k_p2p<float, 128, 8, true>(PassArgs, int, NearPoly);
+template __global__ void k_p2p<double, 64, 1, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 64, 1, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 64, 1, true>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<double, 256, 1, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 256, 1, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 256, 1, true>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<double, 64, 8, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 64, 8, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 64, 8, true>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<double, 256, 8, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 256, 8, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 256, 8, true>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<double, 128, 1, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 128, 1, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 128, 1, true>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<double, 128, 8, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 128, 8, false>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
+template __global__ void k_p2p<float, 128, 8, true>(PassArgs, int, NearPoly, const unsigned*, XcdSegs);
 
 // ---------------------------------------------------------------------------
 // Surrogate tables.  Entry g of a reaction table at (x, y, S) is scaled by the

@@ -223,8 +223,14 @@ __global__ void k_l2p(PassArgs a);
 struct NearPoly {
   float c0, c1, c2, s0, s1, s2;
 };
+// Near-field work items (leaves, or leaf G + half for the symmetric kernel) cut into 8
+// contiguous segments of about equal pair work, one per XCD: segment x is
+// items[start[x] .. start[x + 1]).
+struct XcdSegs {
+  int start[9];
+};
 template <typename T, int BS, int RB, bool POLY>
-__global__ void k_p2p(PassArgs a, int nrhs, NearPoly np);
+__global__ void k_p2p(PassArgs a, int nrhs, NearPoly np, const unsigned* items, XcdSegs seg);
 template <typename R>
 struct SymTypes;
 template <>
@@ -236,12 +242,6 @@ template <>
 struct SymTypes<double> {
   typedef double4 R4;
   typedef double2 R2;
-};
-// Work items of the symmetric near field (leaf G + half, see p2p_sym_item) in leaf
-// order, cut into 8 contiguous segments of about equal pair work, one per XCD:
-// segment x is items[start[x] .. start[x + 1]).
-struct XcdSegs {
-  int start[9];
 };
 template <typename R, int T, int NW, bool POLY>
 __global__ void k_p2p_sym(PassArgs a, int nrhs, int G, typename SymTypes<R>::R2* part, NearPoly np,
