@@ -197,16 +197,18 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
   int boff[TW];
 #pragma unroll
   for (int j = 0; j < TW; ++j) boff[j] = (16 * tcb[j] + col) * a.nRsP;
-  // FP32: Re G Re a and Im G Im a in accumulators of their own (subtracted at the end:
-  // no negation per step); FP64 negates Im G (its accumulators take twice the registers)
+  // Complex products by three real products (Gauss): with G = g + i h and a = c + i d,
+  // s1 = (g + h) c, s2 = g (d - c), s3 = h (c + d), Re G a = s1 - s3, Im G a = s1 + s2;
+  // the three sums are formed in registers from the staged values and combined in FP64
+  // at the end
   constexpr bool F32 = sizeof(T) == 4;
-  AC accR[TW], accI[TW], accN[F32 ? TW : 1];
+  AC acc1[TW], acc2[TW], acc3[TW];
   const bool last_ok = w + 4 * (TW - 1) < ntile;  // wave-uniform
 #pragma unroll
   for (int j = 0; j < TW; ++j) {
-    accR[j] = AC{0, 0, 0, 0};
-    accI[j] = AC{0, 0, 0, 0};
-    if (F32) accN[j] = AC{0, 0, 0, 0};
+    acc1[j] = AC{0, 0, 0, 0};
+    acc2[j] = AC{0, 0, 0, 0};
+    acc3[j] = AC{0, 0, 0, 0};
   }
 
   // staging constants: thread's first element, the per-step advance, and the
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
                 for (int j = 0; j < TW; ++j) bb[j] = sA[boff[j] + kp - kbase];
               } else {
                 bb[0] = sA[col * a.nRsP + kp - kbase];
-                bb[1] = NCB == 2 ? sA[(16 + col) * a.nRsP + kp - kbase] : bb[0];
+                if (NCB == 2) bb[1] = sA[(16 + col) * a.nRsP + kp - kbase];
               }
 #pragma unroll
               for (int j = 0; j < TW; ++j) g[j] = sG[rowo[j] + co];
@@ -345,23 +347,22 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
               // wave's last tile can be missing (ntile > 4 (TW - 1)) or split (its K
               // blocks outside [kq0, kq1) are another wave's), a uniform test
               const bool lon = KS ? (kb >= kq0 && kb < kq1) : last_ok;
+              // B operand of tile j: its own load (BT), else column block tcb[j] (always 0
+              // with one column block)
+              constexpr int NB = BT ? TW : NCB;
+              auto bsel = [&](const T (&v)[NB], int j) { return BT ? v[j] : (NCB == 2 && tcb[j] ? v[NB - 1] : v[0]); };
+              T bc[NB], dmc[NB], cpd[NB];
+#pragma unroll
+              for (int u = 0; u < NB; ++u) bc[u] = bb[u].x, dmc[u] = bb[u].y - bb[u].x, cpd[u] = bb[u].x + bb[u].y;
 #pragma unroll
               for (int j = 0; j < TW; ++j)
-                if (EX || j < TW - 1 || lon) {
-                  const T2 b = BT ? bb[j] : (tcb[j] ? bb[1] : bb[0]);
-                  accR[j] = Ty::mfma(g[j].x, b.x, accR[j]);
-                  accI[j] = Ty::mfma(g[j].x, b.y, accI[j]);
-                }
+                if (EX || j < TW - 1 || lon) acc1[j] = Ty::mfma(g[j].x + g[j].y, bsel(bc, j), acc1[j]);
 #pragma unroll
               for (int j = 0; j < TW; ++j)
-                if (EX || j < TW - 1 || lon) {
-                  const T2 b = BT ? bb[j] : (tcb[j] ? bb[1] : bb[0]);
-                  if (F32)
-                    accN[j] = Ty::mfma(g[j].y, b.y, accN[j]);
-                  else
-                    accR[j] = Ty::mfma(-g[j].y, b.y, accR[j]);
-                  accI[j] = Ty::mfma(g[j].y, b.x, accI[j]);
-                }
+                if (EX || j < TW - 1 || lon) acc2[j] = Ty::mfma(g[j].x, bsel(dmc, j), acc2[j]);
+#pragma unroll
+              for (int j = 0; j < TW; ++j)
+                if (EX || j < TW - 1 || lon) acc3[j] = Ty::mfma(g[j].y, bsel(cpd, j), acc3[j]);
             };
             T2 b1[TW], g1[TW], b2[TW], g2[TW];
             if (kb0 < kb1) load(kb0, b1, g1);
@@ -392,8 +393,8 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     for (int i = 0; i < 4; ++i) {
       const int k = 16 * rb + Ty::row(krow, i);
       if (k < a.nR) {
-        const double re = F32 ? (double)accR[j][i] - (double)accN[F32 ? j : 0][i] : (double)accR[j][i];
-        beta[tb * a.nR + k] = make_double2(re, (double)accI[j][i]);
+        const double s1 = (double)acc1[j][i];
+        beta[tb * a.nR + k] = make_double2(s1 - (double)acc3[j][i], s1 + (double)acc2[j][i]);
       }
     }
   }
@@ -406,8 +407,8 @@ __global__ __launch_bounds__(256) void k_m2l(M2LArgs a) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const double re = F32 ? (double)accR[j][i] - (double)accN[F32 ? j : 0][i] : (double)accR[j][i];
-      sP[(w * 4 + i) * 64 + lane] = make_double2(re, (double)accI[j][i]);
+      const double s1 = (double)acc1[j][i];
+      sP[(w * 4 + i) * 64 + lane] = make_double2(s1 - (double)acc3[j][i], s1 + (double)acc2[j][i]);
     }
     __syncthreads();
     const int id = 4 * (TW - 1) + (KS == 1 ? 0 : (w >> 1));
@@ -599,19 +600,18 @@ __global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
       rowo[j] = (k3 * P2 + k1 + k2) * P2 + k1;
     }
   }
-  // B operand offset of each tile (column block tcb, target col); FP32 keeps Re G Re a
-  // and Im G Im a apart (no negation per step), as in k_m2l
-  constexpr bool F32 = sizeof(T) == 4;
+  // B operand offset of each tile (column block tcb, target col); complex products by
+  // three real products, as in k_m2l
   constexpr bool BT = TW <= 2;
   int boff[TW];
 #pragma unroll
   for (int j = 0; j < TW; ++j) boff[j] = (16 * tcb[j] + col) * a.nRs;
-  AC accR[TW], accI[TW], accN[F32 ? TW : 1];
+  AC acc1[TW], acc2[TW], acc3[TW];
 #pragma unroll
   for (int j = 0; j < TW; ++j) {
-    accR[j] = AC{0, 0, 0, 0};
-    accI[j] = AC{0, 0, 0, 0};
-    if (F32) accN[j] = AC{0, 0, 0, 0};
+    acc1[j] = AC{0, 0, 0, 0};
+    acc2[j] = AC{0, 0, 0, 0};
+    acc3[j] = AC{0, 0, 0, 0};
   }
   // staging walk: element e = tid + 256 i of the NT x nR block is (n, kk), advanced by
   // 256 = q nR + rem per step
@@ -669,29 +669,26 @@ __global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
         for (int j = 0; j < TW; ++j) bb[j] = sA[boff[j] + kp];
       } else {
         bb[0] = sA[col * a.nRs + kp];
-        bb[1] = NCB == 2 ? sA[(16 + col) * a.nRs + kp] : bb[0];
+        if (NCB == 2) bb[1] = sA[(16 + col) * a.nRs + kp];
       }
 #pragma unroll
       for (int j = 0; j < TW; ++j) g[j] = sG[rowo[j] + co];
     };
     auto mma = [&](const T2 (&bb)[TW], const T2 (&g)[TW]) {
+      constexpr int NB = BT ? TW : NCB;
+      auto bsel = [&](const T (&v)[NB], int j) { return BT ? v[j] : (NCB == 2 && tcb[j] ? v[NB - 1] : v[0]); };
+      T bc[NB], dmc[NB], cpd[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) bc[u] = bb[u].x, dmc[u] = bb[u].y - bb[u].x, cpd[u] = bb[u].x + bb[u].y;
 #pragma unroll
       for (int j = 0; j < TW; ++j)
-        if (w + 4 * j < ntile) {
-          const T2 b = BT ? bb[j] : (tcb[j] ? bb[1] : bb[0]);
-          accR[j] = Ty::mfma(g[j].x, b.x, accR[j]);
-          accI[j] = Ty::mfma(g[j].x, b.y, accI[j]);
-        }
+        if (w + 4 * j < ntile) acc1[j] = Ty::mfma(g[j].x + g[j].y, bsel(bc, j), acc1[j]);
 #pragma unroll
       for (int j = 0; j < TW; ++j)
-        if (w + 4 * j < ntile) {
-          const T2 b = BT ? bb[j] : (tcb[j] ? bb[1] : bb[0]);
-          if (F32)
-            accN[j] = Ty::mfma(g[j].y, b.y, accN[j]);
-          else
-            accR[j] = Ty::mfma(-g[j].y, b.y, accR[j]);
-          accI[j] = Ty::mfma(g[j].y, b.x, accI[j]);
-        }
+        if (w + 4 * j < ntile) acc2[j] = Ty::mfma(g[j].x, bsel(dmc, j), acc2[j]);
+#pragma unroll
+      for (int j = 0; j < TW; ++j)
+        if (w + 4 * j < ntile) acc3[j] = Ty::mfma(g[j].y, bsel(cpd, j), acc3[j]);
     };
     T2 b1[TW], g1[TW], b2[TW], g2[TW];
     load(0, b1, g1);
@@ -717,8 +714,8 @@ __global__ __launch_bounds__(256) void k_m2l_cross(M2LCrossArgs a) {
     for (int i = 0; i < 4; ++i) {
       const int k = 16 * rb + Ty::row(krow, i);
       if (k < a.nR) {
-        const double re = F32 ? (double)accR[j][i] - (double)accN[F32 ? j : 0][i] : (double)accR[j][i];
-        beta[tb * a.nR + k] = make_double2(re, (double)accI[j][i]);
+        const double s1 = (double)acc1[j][i];
+        beta[tb * a.nR + k] = make_double2(s1 - (double)acc3[j][i], s1 + (double)acc2[j][i]);
       }
     }
   }
