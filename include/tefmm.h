@@ -126,7 +126,11 @@ enum { TEFMM_SIGMA_IMAGES = 0, TEFMM_SIGMA_SOMMERFELD = 1 };
  * field (P2M .. L2P) runs on the caller's stream; the near field (P2P) runs
  * concurrently on a second stream of the handle (by default; see
  * tefmm_autotune), joined before the final scaling, so t_p2p_ms overlaps the
- * far-field phases and t_total_ms is the whole evaluation. */
+ * far-field phases and t_total_ms is the whole evaluation.  Set-up timings of the
+ * last tefmm_set_particles: t_setup_tree_ms (bounding cubes, sort, leaf ranges),
+ * t_setup_tables_ms (lists, complex images, derivative tables, cross-layer fits and
+ * tables), and within it t_setup_dcim_ms (host wall time of the same-layer
+ * complex-image fits, Sec. 3.3, run on host threads). */
 typedef struct {
   double t_setup_tree_ms, t_setup_tables_ms, t_setup_dcim_ms;
   double t_p2m_ms, t_m2m_ms, t_m2l_ms, t_l2l_ms, t_l2p_ms, t_p2p_ms, t_total_ms;

@@ -751,6 +751,31 @@ static int sommerfeld_tables(tefmm_t h, const Group& g, const SomPath& P, const 
 // ---------------------------------------------------------------------------
 // Derivative tables of one group (all levels).
 // ---------------------------------------------------------------------------
+// k_table_gen with as many waves per key (1, 2, 4 or 8) as fit 150 KiB of LDS
+// (two arrays of nG complex values per wave)
+static hipError_t launch_table_gen(const TableGenArgs& ta, int nkeys, hipStream_t s) {
+  const size_t per = 2 * sizeof(double2) * (size_t)ta.nG;
+  int nw = 8;
+  while (nw > 1 && nw * per > 150 * 1024) nw /= 2;
+  void (*fn)(TableGenArgs) = nw == 8 ? k_table_gen<8> : nw == 4 ? k_table_gen<4> : nw == 2 ? k_table_gen<2> : k_table_gen<1>;
+  const size_t lds = nw * per;
+  hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(nkeys), dim3(64 * nw), lds, s, ta);
+  return hipGetLastError();
+}
+
+// FP32 copy (the mixed mode's tables) of cnt complex values, from the handle's allocator
+static int tables_to_f32(tefmm_t h, const double2* d, size_t cnt, float2** out, hipStream_t s) {
+  HIPCHK(h, dmalloc(h, out, sizeof(float2) * std::max<size_t>(cnt, 1)));
+  if (cnt) {
+    const int blocks = (int)std::min<size_t>((cnt + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks), dim3(256), 0, s, d, cnt, *out);
+    HIPCHK(h, hipGetLastError());
+  }
+  return TEFMM_OK;
+}
+
 static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
   const MediumDesc& med = h->med;
   const int l_ = g.layer;
@@ -897,10 +922,7 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
       TableGenArgs ta;
       ta.terms = d_terms, ta.term_start = d_start, ta.h = d_h, ta.k = k, ta.order = 2 * h->opt.p, ta.nG = h->nG;
       ta.nbr = h->d_nbr, ta.g3 = h->d_g3, ta.g1 = h->d_g1, ta.swap13 = 0, ta.fact = h->d_fact, ta.out = d_out;
-      const size_t lds = 2 * sizeof(double2) * h->nG;
-      HIPCHK(h, hipFuncSetAttribute((const void*)k_table_gen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      hipLaunchKernelGGL(k_table_gen, dim3(nkeys), dim3(64), lds, s, ta);
-      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, launch_table_gen(ta, nkeys, s));
       HIPCHK(h, hipStreamSynchronize(s));
       dfree(h, d_terms);
       dfree(h, d_start);
@@ -927,14 +949,9 @@ static int build_tables(tefmm_t h, Group& g, hipStream_t s) {
       else
         g.TS[lev] = d_out;
       if (h->opt.precision == TEFMM_MIXED_FP32) {
-        const size_t cnt = (size_t)nkeys * h->nG;
-        std::vector<double2> hd(cnt);
-        std::vector<float2> hf(cnt);
-        HIPCHK(h, hipMemcpy(hd.data(), d_out, sizeof(double2) * cnt, hipMemcpyDeviceToHost));
-        for (size_t i = 0; i < cnt; ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
         float2* d32 = nullptr;
-        HIPCHK(h, dmalloc(h, &d32, sizeof(float2) * cnt));
-        HIPCHK(h, hipMemcpy(d32, hf.data(), sizeof(float2) * cnt, hipMemcpyHostToDevice));
+        const int rc = tables_to_f32(h, d_out, (size_t)nkeys * h->nG, &d32, s);
+        if (rc != TEFMM_OK) return rc;
         if (which == 0)
           g.Tfd32[lev] = d32;
         else
@@ -1316,10 +1333,7 @@ static int build_cross(tefmm_t h, int gt, hipStream_t s) {
         TableGenArgs ta;
         ta.terms = d_terms, ta.term_start = d_start, ta.h = d_h, ta.k = med.k[lt], ta.order = 2 * p, ta.nG = h->nG;
         ta.nbr = h->d_nbr, ta.g3 = h->d_g3, ta.g1 = h->d_g1, ta.swap13 = 1, ta.fact = h->d_fact, ta.out = d_out;
-        const size_t lds = 2 * sizeof(double2) * h->nG;
-        HIPCHK(h, hipFuncSetAttribute((const void*)k_table_gen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(k_table_gen, dim3(nkeys), dim3(64), lds, s, ta);
-        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, launch_table_gen(ta, nkeys, s));
         HIPCHK(h, hipStreamSynchronize(s));
         dfree(h, d_terms);
         dfree(h, d_start);
@@ -1334,14 +1348,9 @@ static int build_cross(tefmm_t h, int gt, hipStream_t s) {
       }
       (k3 ? G.XT1[lev] : G.XT0[lev]) = d_out;
       if (h->opt.precision == TEFMM_MIXED_FP32) {
-        const size_t cnt = (size_t)nkeys * h->nG;
-        std::vector<double2> hd(std::max<size_t>(cnt, 1));
-        std::vector<float2> hf(std::max<size_t>(cnt, 1));
-        if (cnt) HIPCHK(h, hipMemcpy(hd.data(), d_out, sizeof(double2) * cnt, hipMemcpyDeviceToHost));
-        for (size_t i = 0; i < cnt; ++i) hf[i] = make_float2((float)hd[i].x, (float)hd[i].y);
         float2* d32 = nullptr;
-        HIPCHK(h, dmalloc(h, &d32, sizeof(float2) * std::max<size_t>(cnt, 1)));
-        if (cnt) HIPCHK(h, hipMemcpy(d32, hf.data(), sizeof(float2) * cnt, hipMemcpyHostToDevice));
+        const int rc = tables_to_f32(h, d_out, (size_t)nkeys * h->nG, &d32, s);
+        if (rc != TEFMM_OK) return rc;
         (k3 ? G.XT132[lev] : G.XT032[lev]) = d32;
       }
     }
@@ -1849,7 +1858,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
       h->m2l_pairs += far1;
     }
   }
-  // complex images (host FP64)
+  // complex images (host FP64): every (group, family) fit is independent, one host thread each
   for (auto& g : h->groups) {
     const int l = g.layer;
     const double hleaf = g.side / (1 << g.depth);
@@ -1858,14 +1867,33 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
     zlo = std::max(zlo, bot + 1e-6);
     zhi = std::min(zhi, top - 1e-6);
     g.fit_zlo = zlo, g.fit_zhi = zhi;
-    for (int fam = 0; fam < 3; ++fam) {
-      std::string err;
-      if (!same_layer_family(med, l, fam, zlo, zhi, h->opt.dcim_T1, h->opt.dcim_samples, h->opt.dcim_svd_tol,
-                             g.famA[fam], g.famZ[fam], g.fam_err[fam], err))
-        return fail(h, TEFMM_ERR_DCIM_FIT, "complex-image fit failed: " + err);
-      g.has[fam] = !g.famA[fam].empty();
-    }
   }
+  const auto t_fit0 = std::chrono::steady_clock::now();
+  {
+    const int nfit = 3 * (int)h->groups.size();
+    std::vector<std::string> ferr(nfit);
+    std::vector<char> fok(nfit, 0);
+    const int nthr = std::max(1, std::min(nfit, std::min(16, (int)std::thread::hardware_concurrency())));
+    std::vector<std::thread> th;
+    std::atomic<int> next{0};
+    for (int t = 0; t < nthr; ++t)
+      th.emplace_back([&]() {
+        for (;;) {
+          const int i = next++;
+          if (i >= nfit) break;
+          Group& g = h->groups[i / 3];
+          const int fam = i % 3;
+          fok[i] = same_layer_family(med, g.layer, fam, g.fit_zlo, g.fit_zhi, h->opt.dcim_T1, h->opt.dcim_samples,
+                                     h->opt.dcim_svd_tol, g.famA[fam], g.famZ[fam], g.fam_err[fam], ferr[i]);
+        }
+      });
+    for (auto& t : th) t.join();
+    for (int i = 0; i < nfit; ++i)
+      if (!fok[i]) return fail(h, TEFMM_ERR_DCIM_FIT, "complex-image fit failed: " + ferr[i]);
+    for (auto& g : h->groups)
+      for (int fam = 0; fam < 3; ++fam) g.has[fam] = !g.famA[fam].empty();
+  }
+  const double fit_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_fit0).count();
   // reaction keys that would not converge: direct lists and counts
   for (auto& g : h->groups) {
     int rc = reaction_convergence(h, g, lc, s);
@@ -1889,6 +1917,7 @@ extern "C" int tefmm_set_particles(tefmm_t h, int64_t n, const double* xyz, int 
   std::memset(&h->st, 0, sizeof(h->st));
   h->st.t_setup_tree_ms = ms1;
   h->st.t_setup_tables_ms = ms2;
+  h->st.t_setup_dcim_ms = fit_ms;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipEventDestroy(e2);

@@ -37,24 +37,31 @@ void upload_binomials() {
 // k is replaced by k h; the table entry is  G_g = h^{|g|} D^g F = g! a_g / h
 // summed over the key's terms  F = sum coef * f(x, y, zeta)  (zeta -> -zeta
 // direction flips contribute (-1)^{g3}).
-// One 64-lane wave per key.
+// One workgroup of NW waves per key: wave w runs the recurrence for terms
+// t0 + w, t0 + w + NW, ... in an LDS region of its own, and the waves' sums are
+// added in wave order at the end.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_table_gen(TableGenArgs a) {
   // Only entries with g1 <= 2 are generated (compact order of g_index); the
   // recurrence for such g needs g - e_i and g - 2 e_i, which stay in that set.
   extern __shared__ double2 lds_tab[];
-  double2* sa = lds_tab;
-  double2* sb = lds_tab + a.nG;
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  double2* sa = lds_tab + (size_t)2 * a.nG * w;
+  double2* sb = sa + a.nG;
   const int key = blockIdx.x;
-  const int lane = threadIdx.x;
   const int t0 = a.term_start[key], t1 = a.term_start[key + 1];
   constexpr int MAXJ = 25;  // nG <= 1600 (order <= 32)
   dc acc[MAXJ];
 #pragma unroll
   for (int j = 0; j < MAXJ; ++j) acc[j] = {0.0, 0.0};
   const double kh = a.k * a.h[key];
-  for (int t = t0; t < t1; ++t) {
-    const TableTerm tm = a.terms[t];
+  // rounds of NW terms, the same number of barriers in every wave; a wave without a
+  // term in the last round repeats the round's first term and drops its result
+  for (int tb = t0; tb < t1; tb += NW) {
+    const bool on = tb + w < t1;
+    const TableTerm tm = a.terms[on ? tb + w : tb];
     // swap13: the table is generated in the frame (zeta, y, x), i.e. restricted
     // to small orders in z instead of x (cross-layer translations)
     const dc xr = {tm.x, 0.0}, zc = {tm.zr, tm.zi};
@@ -99,26 +106,56 @@ __global__ __launch_bounds__(64) void k_table_gen(TableGenArgs a) {
       __syncthreads();
     }
     const dc cf = {tm.cr, tm.ci};
+    if (on) {
 #pragma unroll
-    for (int j = 0; j < MAXJ; ++j) {
-      const int g = lane + 64 * j;
-      if (g < a.nG) {
-        dc v = cmul(cf, {sa[g].x, sa[g].y});
-        if (tm.flip && ((a.swap13 ? a.g1[g] : a.g3[g]) & 1)) v = {-v.x, -v.y};
-        acc[j] = cadd(acc[j], v);
+      for (int j = 0; j < MAXJ; ++j) {
+        const int g = lane + 64 * j;
+        if (g < a.nG) {
+          dc v = cmul(cf, {sa[g].x, sa[g].y});
+          if (tm.flip && ((a.swap13 ? a.g1[g] : a.g3[g]) & 1)) v = {-v.x, -v.y};
+          acc[j] = cadd(acc[j], v);
+        }
       }
     }
     __syncthreads();
   }
   const double invh = 1.0 / a.h[key];
+  if (NW == 1) {
+#pragma unroll
+    for (int j = 0; j < MAXJ; ++j) {
+      const int g = lane + 64 * j;
+      if (g < a.nG) {
+        const double sc = a.fact[g] * invh;
+        a.out[(size_t)key * a.nG + g] = make_double2(acc[j].x * sc, acc[j].y * sc);
+      }
+    }
+    return;
+  }
+  // each wave's sums to its own region, then added in wave order
 #pragma unroll
   for (int j = 0; j < MAXJ; ++j) {
     const int g = lane + 64 * j;
-    if (g < a.nG) {
-      const double sc = a.fact[g] * invh;
-      a.out[(size_t)key * a.nG + g] = make_double2(acc[j].x * sc, acc[j].y * sc);
-    }
+    if (g < a.nG) sa[g] = make_double2(acc[j].x, acc[j].y);
   }
+  __syncthreads();
+  for (int g = threadIdx.x; g < a.nG; g += 64 * NW) {
+    double2 v = lds_tab[g];
+    for (int u = 1; u < NW; ++u) {
+      const double2 o = lds_tab[(size_t)2 * a.nG * u + g];
+      v.x += o.x, v.y += o.y;
+    }
+    const double sc = a.fact[g] * invh;
+    a.out[(size_t)key * a.nG + g] = make_double2(v.x * sc, v.y * sc);
+  }
+}
+template __global__ void k_table_gen<1>(TableGenArgs);
+template __global__ void k_table_gen<2>(TableGenArgs);
+template __global__ void k_table_gen<4>(TableGenArgs);
+template __global__ void k_table_gen<8>(TableGenArgs);
+
+__global__ void k_to_f32(const double2* in, size_t n, float2* out) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = make_float2((float)in[i].x, (float)in[i].y);
 }
 
 // Scaled Taylor coefficients at arbitrary points (introspection): same

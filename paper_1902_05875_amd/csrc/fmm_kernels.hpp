@@ -174,7 +174,10 @@ __global__ void k_sigma_direct(SigmaDirectArgs a);
 
 void upload_binomials();
 
-__global__ void k_table_gen(TableGenArgs a);
+template <int NW>
+__global__ void k_table_gen(TableGenArgs a);  // NW = 1, 2, 4, 8 waves per key
+// FP32 copy of an FP64 complex array (the mixed mode's tables)
+__global__ void k_to_f32(const double2* in, size_t n, float2* out);
 // Rotation-free derivatives H_{m,c} = (2 d_{rho^2})^m d_S^c of the Sigma-family kernel
 // (m + c <= P2 <= SIGMA_P2_MAX), their normalisation for the surrogate network, and the
 // compact Cartesian table rows rebuilt from them.

@@ -125,55 +125,66 @@ void reaction_densities(const MediumDesc& med, int lp, cplx krho, std::vector<cp
 // ---------------------------------------------------------------------------
 static void jacobi_svd(CMat A, std::vector<double>& sv, CMat& V) {
   const int m = A.r, n = A.c;
-  V = CMat(n, n);
-  for (int i = 0; i < n; ++i) V(i, i) = 1.0;
+  // working copies by columns (contiguous), real and imaginary parts apart
+  std::vector<double> xr((size_t)m * n), xi((size_t)m * n), vr((size_t)n * n, 0.0), vi((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < m; ++i) xr[(size_t)j * m + i] = A(i, j).real(), xi[(size_t)j * m + i] = A(i, j).imag();
+    vr[(size_t)j * n + j] = 1.0;
+  }
+  // rotate columns p and q: with ph = <p, q> / |<p, q>| and w = q conj(ph),
+  // p <- c p - s w,  q <- (s p + c w) ph
+  auto rotate = [](double* pr, double* pi, double* qr, double* qi, int len, double c, double s, double phr,
+                   double phi) {
+    for (int i = 0; i < len; ++i) {
+      const double apr = pr[i], api = pi[i];
+      const double wr = qr[i] * phr + qi[i] * phi, wi = qi[i] * phr - qr[i] * phi;
+      pr[i] = c * apr - s * wr, pi[i] = c * api - s * wi;
+      const double tr = s * apr + c * wr, ti = s * api + c * wi;
+      qr[i] = tr * phr - ti * phi, qi[i] = tr * phi + ti * phr;
+    }
+  };
   for (int sweep = 0; sweep < 80; ++sweep) {
     double off = 0.0;
     for (int p = 0; p < n - 1; ++p)
       for (int q = p + 1; q < n; ++q) {
-        double al = 0, be = 0;
-        cplx ga(0, 0);
+        double* pr = &xr[(size_t)p * m];
+        double* pi = &xi[(size_t)p * m];
+        double* qr = &xr[(size_t)q * m];
+        double* qi = &xi[(size_t)q * m];
+        double al = 0, be = 0, gr = 0, gi = 0;  // |p|^2, |q|^2, <p, q> = sum conj(p) q
         for (int i = 0; i < m; ++i) {
-          al += std::norm(A(i, p));
-          be += std::norm(A(i, q));
-          ga += std::conj(A(i, p)) * A(i, q);
+          al += pr[i] * pr[i] + pi[i] * pi[i];
+          be += qr[i] * qr[i] + qi[i] * qi[i];
+          gr += pr[i] * qr[i] + pi[i] * qi[i];
+          gi += pr[i] * qi[i] - pi[i] * qr[i];
         }
-        double g = std::abs(ga);
+        const double g = std::hypot(gr, gi);
         if (g == 0.0 || g <= 1e-15 * std::sqrt(al * be)) continue;
         off = std::max(off, g / std::sqrt(al * be));
-        cplx ph = ga / g;
-        double zeta = (be - al) / (2.0 * g);
-        double t = (zeta >= 0 ? 1.0 : -1.0) / (std::abs(zeta) + std::sqrt(1.0 + zeta * zeta));
-        double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
-        for (int i = 0; i < m; ++i) {
-          cplx ap = A(i, p), aq = A(i, q) * std::conj(ph);
-          A(i, p) = c * ap - s * aq;
-          A(i, q) = (s * ap + c * aq) * ph;
-        }
-        for (int i = 0; i < n; ++i) {
-          cplx vp = V(i, p), vq = V(i, q) * std::conj(ph);
-          V(i, p) = c * vp - s * vq;
-          V(i, q) = (s * vp + c * vq) * ph;
-        }
+        const double phr = gr / g, phi = gi / g;
+        const double zeta = (be - al) / (2.0 * g);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::abs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+        rotate(pr, pi, qr, qi, m, c, s, phr, phi);
+        rotate(&vr[(size_t)p * n], &vi[(size_t)p * n], &vr[(size_t)q * n], &vi[(size_t)q * n], n, c, s, phr, phi);
       }
     if (off < 1e-15) break;
   }
   std::vector<double> nrm(n);
   for (int j = 0; j < n; ++j) {
     double s = 0;
-    for (int i = 0; i < m; ++i) s += std::norm(A(i, j));
+    for (int i = 0; i < m; ++i) s += xr[(size_t)j * m + i] * xr[(size_t)j * m + i] + xi[(size_t)j * m + i] * xi[(size_t)j * m + i];
     nrm[j] = std::sqrt(s);
   }
   std::vector<int> ord(n);
   for (int j = 0; j < n; ++j) ord[j] = j;
   std::sort(ord.begin(), ord.end(), [&](int a, int b) { return nrm[a] > nrm[b]; });
-  CMat Vs(n, n);
+  V = CMat(n, n);
   sv.resize(n);
   for (int j = 0; j < n; ++j) {
     sv[j] = nrm[ord[j]];
-    for (int i = 0; i < n; ++i) Vs(i, j) = V(i, ord[j]);
+    for (int i = 0; i < n; ++i) V(i, j) = cplx(vr[(size_t)ord[j] * n + i], vi[(size_t)ord[j] * n + i]);
   }
-  V = Vs;
 }
 
 // Householder QR least squares: minimise ||A X - B|| (A: m x n, m >= n; B: m x k).
