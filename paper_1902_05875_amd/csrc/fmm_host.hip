@@ -2861,8 +2861,16 @@ extern "C" int tefmm_autotune(tefmm_t h, void* stream, int* depth_out, int* ncb_
     if (rc == TEFMM_OK) rc = ensure_rhs(h, 1);
     for (int ncb = 1; ncb <= 2 && rc == TEFMM_OK; ++ncb) {
       h->m2l_ncb = ncb;
+      (void)hipEventRecord(e0, s);
       rc = enqueue_evaluate(h, (const double*)q1, 1, (double*)phi1, s, false);
       if (rc != TEFMM_OK) break;
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float warm = 0;
+      (void)hipEventElapsedTime(&warm, e0, e1);
+      // a candidate whose first (untimed) evaluation takes three times the best so far
+      // cannot win; its other tile width is not tried either
+      if (best < 1e30f && warm > 1.5f * best) break;
       (void)hipEventRecord(e0, s);
       for (int it = 0; it < 2 && rc == TEFMM_OK; ++it) rc = enqueue_evaluate(h, (const double*)q1, 1, (double*)phi1, s, false);
       (void)hipEventRecord(e1, s);

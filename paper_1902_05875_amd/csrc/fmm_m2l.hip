@@ -738,7 +738,6 @@ static hipError_t launch_cross_t2(const M2LCrossArgs& a0, int nrhs, hipStream_t 
   const size_t lds = (size_t)4 * a.P2 * a.P2 * sizeof(T2) + (size_t)16 * NCB * a.nRs * sizeof(T2) +
                      4 * (size_t)a.nKB * sizeof(int);
   const int TW = (a.nRB * NCB + 3) / 4;
-  const bool ex = 4 * TW == a.nRB * NCB;
   if (a.nsplit < 1) a.nsplit = 1;
   dim3 grid(total, nrhs, a.nsplit), block(256);
   void (*fn)(M2LCrossArgs) = nullptr;
