@@ -1278,16 +1278,23 @@ __device__ __forceinline__ R butterfly_tail(R c0, R c1, R c2, R c3, int lane) {
 // only then the lanes that met one redo their tests and take those pairs one by
 // one: the value used is replaced by the one from FP64 differences, its
 // source-side part added to dps[2 (t + u) + c].
-template <int T, bool SYM, bool POLY>
+// S = 2 or 4 (with T = 1): the wave holds 64 / S targets, lane l = (64 / S) g + j
+// taking target j and the 8 / S sources t + (8 / S) g, ...; the source-side sums are
+// then summed over the 64 / S lanes of the subgroup only (the butterfly without its
+// first one or two stages), and the caller adds the S subgroups' target sums.
+template <int T, bool SYM, bool POLY, int S = 1>
 __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T], const float (&ty)[T],
                                          const float (&tz)[T], const float (&qri)[T], const float (&qii)[T],
                                          const bool (&act)[T], const float4* s4, const float* sqi,
                                          const int* sidx, float rns2, float eps2, double kap2,
                                          const PassArgs& a, float (&accr)[T], float (&acci)[T], float* psw,
                                          float* dps, const NearPoly& np) {
+  static_assert(S == 1 || (T == 1 && (S == 2 || S == 4)), "source subgroups need one target per lane");
+  constexpr int NS = 8 / S;  // sources per lane and step
   const int lane = threadIdx.x & 63;
+  const int sb = S == 1 ? t : t + NS * (lane / (64 / S));  // this lane's first source
   // a vector value, not an array: the butterfly's selects stay selects of values
-  typedef float f16v __attribute__((ext_vector_type(16)));
+  typedef float f16v __attribute__((ext_vector_type(2 * NS)));
   f16v c;
   // the squared distance a pair is tested with: SYM, the one used; the own pass, the
   // plain one (the clamp only ever raises it to the threshold itself), with the pair
@@ -1300,12 +1307,12 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
   };
   float mn = 3.0e38f;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {  // two sources at a time
+  for (int v = 0; v < NS / 2; ++v) {  // two sources at a time
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const float4 sp = s4[t + 2 * v + u];
-      const float qr = sp.w, qi = sqi[t + 2 * v + u];
-      const int sj = SYM ? 0 : sidx[t + 2 * v + u];
+      const float4 sp = s4[sb + 2 * v + u];
+      const float qr = sp.w, qi = sqi[sb + 2 * v + u];
+      const int sj = SYM ? 0 : sidx[sb + 2 * v + u];
       float cr = 0.0f, ci = 0.0f;
 #pragma unroll
       for (int k = 0; k < T; ++k) {
@@ -1343,15 +1350,22 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
     // partner's same half.  Masks 32 and 16 by the lane-swap instructions (value
     // k to the low half of the lanes, k + H to the high half), the rest through
     // the DPP crossbar; lane l ends with value (l >> 2) summed over the 64 lanes.
+    // With S subgroups the first log2 S stages are left out: each subgroup's lanes
+    // form whole halves (S = 2) or rows (S = 4), and lane l still ends with value
+    // (l >> 2) of the step's 16, source t + (l >> 3), summed over its subgroup.
+    if constexpr (S == 1) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[k]), __float_as_uint(c[k + 8]), false, false);
-      c[k] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+      for (int k = 0; k < 8; ++k) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[k]), __float_as_uint(c[k + 8]), false, false);
+        c[k] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+      }
     }
+    if constexpr (S <= 2) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(c[k]), __float_as_uint(c[k + 4]), false, false);
-      c[k] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+      for (int k = 0; k < 4; ++k) {
+        const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(c[k]), __float_as_uint(c[k + 4]), false, false);
+        c[k] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+      }
     }
     const float tot = butterfly_tail<float>(c[0], c[1], c[2], c[3], lane);
     if (!(lane & 3)) psw[2 * t + (lane >> 2)] = tot;
@@ -1363,7 +1377,9 @@ __device__ __forceinline__ void p2p_sym8(int t, int tbase, const float (&tx)[T],
   for (int uu = 0; uu < 8; ++uu)
 #pragma unroll
     for (int k = 0; k < T; ++k)
-      mine |= (act[k] && tested(k, s4[t + uu], SYM ? 0 : sidx[t + uu]) < rns2) ? 1u << (uu * T + k) : 0u;
+      mine |= (act[k] && t + uu >= sb && t + uu < sb + NS && tested(k, s4[t + uu], SYM ? 0 : sidx[t + uu]) < rns2)
+                  ? 1u << (uu * T + k)
+                  : 0u;
   unsigned long long bal = __ballot(mine != 0);
   while (bal) {
     const int l = __builtin_ctzll(bal);
@@ -1502,7 +1518,8 @@ struct SymShared {
 // staged source chunks of SC sources: chunk c of the pass, counted over the ranges,
 // goes to wave c mod NW).  Each wave stages, evaluates and writes its chunks'
 // source-side sums on its own (part[G slot + half]); at the end of a pass the waves'
-// target sums are added in wave order.  Charge vector r of nrhs.
+// target sums are added in wave order.  Charge vector r of nrhs.  In FP32 a last pass
+// of at most 32 or 16 targets has 2 or 4 lanes per target sharing out the sources.
 template <typename R, int T, int NW, bool POLY, typename SH>
 __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r, int G,
                                              typename SymTypes<R>::R2* part, const NearPoly& np, int wi, SH& sh) {
@@ -1535,15 +1552,18 @@ __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r,
     const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
     const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
     if (half * TP >= cnt) return;
-    // one pass over the neighbourhood for 64 TT targets from c0 on
-    auto pass = [&](auto tt, int c0) {
+    // one pass over the neighbourhood for 64 TT targets from c0 on; SS = 2, 4 (FP32,
+    // TT = 1): 64 / SS targets, each on SS lanes that share out the sources
+    auto pass = [&](auto tt, auto ss, int c0) {
       constexpr int TT = decltype(tt)::value;
+      constexpr int SS = decltype(ss)::value;
       R tx[TT], ty[TT], tz[TT], qri[TT], qii[TT], accr[TT], acci[TT];
       bool act[TT];
-      const int tbase = start + c0 + lane;  // target index of slot k: tbase + 64 k
+      const int tl = SS == 1 ? lane : lane % (64 / SS);
+      const int tbase = start + c0 + tl;  // target index of slot k: tbase + 64 k
 #pragma unroll
       for (int k = 0; k < TT; ++k) {
-        const int c = c0 + 64 * k + lane;
+        const int c = c0 + 64 * k + tl;
         act[k] = c < cnt;
         const int64_t i = start + (act[k] ? c : 0);
         tx[k] = (R)((a.xs[i] - a.lo[0]) * kap);
@@ -1597,13 +1617,13 @@ __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r,
           if constexpr (F32) {
             if (rg == 0) {
               for (int t = 0; t < mu; t += 8)
-                p2p_sym8<TT, false, POLY>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2,
-                                          eps2, kap * kap, a, accr, acci, psw[w], dps[w], npv);
+                p2p_sym8<TT, false, POLY, SS>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2,
+                                              eps2, kap * kap, a, accr, acci, psw[w], dps[w], npv);
               continue;
             }
             for (int t = 0; t < mu; t += 8)
-              p2p_sym8<TT, true, POLY>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2,
-                                       kap * kap, a, accr, acci, psw[w], dps[w], npv);
+              p2p_sym8<TT, true, POLY, SS>(t, tbase, tx, ty, tz, qri, qii, act, s4[w], sqi[w], sidx[w], rns2, eps2,
+                                           kap * kap, a, accr, acci, psw[w], dps[w], npv);
           } else {
             if (rg == 0) {
               for (int t = 0; t < mu; t += 8) {
@@ -1641,6 +1661,22 @@ __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r,
           }
         }
       }
+      if constexpr (SS > 1) {
+        // the subgroups' target sums: halves, then (SS = 4) rows, added alike in every lane
+#pragma unroll
+        for (int k = 0; k < TT; ++k) {
+          auto sr = __builtin_amdgcn_permlane32_swap(__float_as_uint(accr[k]), __float_as_uint(accr[k]), false, false);
+          auto si = __builtin_amdgcn_permlane32_swap(__float_as_uint(acci[k]), __float_as_uint(acci[k]), false, false);
+          accr[k] = __uint_as_float(sr[0]) + __uint_as_float(sr[1]);
+          acci[k] = __uint_as_float(si[0]) + __uint_as_float(si[1]);
+          if constexpr (SS == 4) {
+            sr = __builtin_amdgcn_permlane16_swap(__float_as_uint(accr[k]), __float_as_uint(accr[k]), false, false);
+            si = __builtin_amdgcn_permlane16_swap(__float_as_uint(acci[k]), __float_as_uint(acci[k]), false, false);
+            accr[k] = __uint_as_float(sr[0]) + __uint_as_float(sr[1]);
+            acci[k] = __uint_as_float(si[0]) + __uint_as_float(si[1]);
+          }
+        }
+      }
       if (NW > 1) {
         // the waves' target sums, added in wave order
 #pragma unroll
@@ -1655,19 +1691,24 @@ __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r,
         }
         __syncthreads();
       }
-      if (w == 0)
+      if (w == 0 && tl == lane)
 #pragma unroll
         for (int k = 0; k < TT; ++k)
           if (act[k])
             a.phi[(int64_t)r * a.n + tbase + 64 * k] = make_double2((double)accr[k] * kap, (double)acci[k] * kap);
     };
     // passes of 64 T targets (this workgroup's: every G-th one); a last one of at most 64
-    // with one target per lane
+    // with one target per lane, and in FP32 of at most 32 or 16 on 2 or 4 lanes each
     for (int c0 = half * TP; c0 < cnt; c0 += G * TP) {
-      if (T > 1 && cnt - c0 <= 64)
-        pass(std::integral_constant<int, 1>(), c0);
+      const int left = cnt - c0;
+      if (F32 && left <= 16)
+        pass(std::integral_constant<int, 1>(), std::integral_constant<int, F32 ? 4 : 1>(), c0);
+      else if (F32 && left <= 32)
+        pass(std::integral_constant<int, 1>(), std::integral_constant<int, F32 ? 2 : 1>(), c0);
+      else if (T > 1 && left <= 64)
+        pass(std::integral_constant<int, 1>(), std::integral_constant<int, 1>(), c0);
       else
-        pass(std::integral_constant<int, T>(), c0);
+        pass(std::integral_constant<int, T>(), std::integral_constant<int, 1>(), c0);
     }
   }
 }
