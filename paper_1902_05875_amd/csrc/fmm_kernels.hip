@@ -1435,18 +1435,22 @@ __device__ __forceinline__ void swap16_f64(double& x, double& y) {
   y = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
 }
 
-template <int T, bool SYM, bool SMALL>
+// S = 2, 4 (T = 1): source subgroups as in p2p_sym8.
+template <int T, bool SYM, bool SMALL, int S = 1>
 __device__ __forceinline__ void p2p_sym8_f64(int t, const double (&tx)[T], const double (&ty)[T],
                                              const double (&tz)[T], const double (&qri)[T], const double (&qii)[T],
                                              const double4* s4, const double* sqi, double k, double (&accr)[T],
                                              double (&acci)[T], double* psw) {
+  static_assert(S == 1 || (T == 1 && (S == 2 || S == 4)), "source subgroups need one target per lane");
+  constexpr int NS = 8 / S;
   const int lane = threadIdx.x & 63;
-  typedef double d16v __attribute__((ext_vector_type(16)));
+  const int sb = S == 1 ? t : t + NS * (lane / (64 / S));
+  typedef double d16v __attribute__((ext_vector_type(2 * NS)));
   d16v c;
 #pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    const double4 sp = s4[t + v];
-    const double qr = sp.w, qi = sqi[t + v];
+  for (int v = 0; v < NS; ++v) {
+    const double4 sp = s4[sb + v];
+    const double qr = sp.w, qi = sqi[sb + v];
     double cr = 0.0, ci = 0.0;
 #pragma unroll
     for (int kk = 0; kk < T; ++kk) {
@@ -1478,18 +1482,23 @@ __device__ __forceinline__ void p2p_sym8_f64(int t, const double (&tx)[T], const
     for (int kk = 0; kk < T; ++kk) asm volatile("" : "+v"(accr[kk]), "+v"(acci[kk]));
   }
   if (SYM) {
-    // the transposing butterfly of p2p_sym8: lane 4 u ends with the wave's sum of value u
+    // the transposing butterfly of p2p_sym8: lane 4 u ends with the wave's (subgroup's)
+    // sum of value u
+    if constexpr (S == 1) {
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      double x = c[kk], y = c[kk + 8];
-      swap32_f64(x, y);
-      c[kk] = x + y;
+      for (int kk = 0; kk < 8; ++kk) {
+        double x = c[kk], y = c[kk + 8];
+        swap32_f64(x, y);
+        c[kk] = x + y;
+      }
     }
+    if constexpr (S <= 2) {
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      double x = c[kk], y = c[kk + 4];
-      swap16_f64(x, y);
-      c[kk] = x + y;
+      for (int kk = 0; kk < 4; ++kk) {
+        double x = c[kk], y = c[kk + 4];
+        swap16_f64(x, y);
+        c[kk] = x + y;
+      }
     }
     const double tot = butterfly_tail<double>(c[0], c[1], c[2], c[3], lane);
     if (!(lane & 3)) psw[2 * t + (lane >> 2)] = tot;
@@ -1518,8 +1527,8 @@ struct SymShared {
 // staged source chunks of SC sources: chunk c of the pass, counted over the ranges,
 // goes to wave c mod NW).  Each wave stages, evaluates and writes its chunks'
 // source-side sums on its own (part[G slot + half]); at the end of a pass the waves'
-// target sums are added in wave order.  Charge vector r of nrhs.  In FP32 a last pass
-// of at most 32 or 16 targets has 2 or 4 lanes per target sharing out the sources.
+// target sums are added in wave order.  Charge vector r of nrhs.  A last pass of at most
+// 32 or 16 targets has 2 or 4 lanes per target sharing out the sources.
 template <typename R, int T, int NW, bool POLY, typename SH>
 __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r, int G,
                                              typename SymTypes<R>::R2* part, const NearPoly& np, int wi, SH& sh) {
@@ -1552,8 +1561,8 @@ __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r,
     const int ix = leaf / (nb * nb), iy = (leaf / nb) % nb, iz = leaf % nb;
     const int start = a.leaf_start[a.leaf_base + leaf], cnt = a.leaf_count[a.leaf_base + leaf];
     if (half * TP >= cnt) return;
-    // one pass over the neighbourhood for 64 TT targets from c0 on; SS = 2, 4 (FP32,
-    // TT = 1): 64 / SS targets, each on SS lanes that share out the sources
+    // one pass over the neighbourhood for 64 TT targets from c0 on; SS = 2, 4 (TT = 1):
+    // 64 / SS targets, each on SS lanes that share out the sources
     auto pass = [&](auto tt, auto ss, int c0) {
       constexpr int TT = decltype(tt)::value;
       constexpr int SS = decltype(ss)::value;
@@ -1628,17 +1637,17 @@ __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r,
             if (rg == 0) {
               for (int t = 0; t < mu; t += 8) {
                 if (small)
-                  p2p_sym8_f64<TT, false, true>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
+                  p2p_sym8_f64<TT, false, true, SS>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
                 else
-                  p2p_sym8_f64<TT, false, false>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
+                  p2p_sym8_f64<TT, false, false, SS>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
               }
               continue;
             }
             for (int t = 0; t < mu; t += 8) {
               if (small)
-                p2p_sym8_f64<TT, true, true>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
+                p2p_sym8_f64<TT, true, true, SS>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
               else
-                p2p_sym8_f64<TT, true, false>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
+                p2p_sym8_f64<TT, true, false, SS>(t, tx, ty, tz, qri, qii, s4[w], sqi[w], a.k, accr, acci, psw[w]);
             }
           }
           wave_lds_sync();
@@ -1665,15 +1674,26 @@ __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r,
         // the subgroups' target sums: halves, then (SS = 4) rows, added alike in every lane
 #pragma unroll
         for (int k = 0; k < TT; ++k) {
-          auto sr = __builtin_amdgcn_permlane32_swap(__float_as_uint(accr[k]), __float_as_uint(accr[k]), false, false);
-          auto si = __builtin_amdgcn_permlane32_swap(__float_as_uint(acci[k]), __float_as_uint(acci[k]), false, false);
-          accr[k] = __uint_as_float(sr[0]) + __uint_as_float(sr[1]);
-          acci[k] = __uint_as_float(si[0]) + __uint_as_float(si[1]);
-          if constexpr (SS == 4) {
-            sr = __builtin_amdgcn_permlane16_swap(__float_as_uint(accr[k]), __float_as_uint(accr[k]), false, false);
-            si = __builtin_amdgcn_permlane16_swap(__float_as_uint(acci[k]), __float_as_uint(acci[k]), false, false);
+          if constexpr (F32) {
+            auto sr = __builtin_amdgcn_permlane32_swap(__float_as_uint(accr[k]), __float_as_uint(accr[k]), false, false);
+            auto si = __builtin_amdgcn_permlane32_swap(__float_as_uint(acci[k]), __float_as_uint(acci[k]), false, false);
             accr[k] = __uint_as_float(sr[0]) + __uint_as_float(sr[1]);
             acci[k] = __uint_as_float(si[0]) + __uint_as_float(si[1]);
+            if constexpr (SS == 4) {
+              sr = __builtin_amdgcn_permlane16_swap(__float_as_uint(accr[k]), __float_as_uint(accr[k]), false, false);
+              si = __builtin_amdgcn_permlane16_swap(__float_as_uint(acci[k]), __float_as_uint(acci[k]), false, false);
+              accr[k] = __uint_as_float(sr[0]) + __uint_as_float(sr[1]);
+              acci[k] = __uint_as_float(si[0]) + __uint_as_float(si[1]);
+            }
+          } else {
+            double xr = accr[k], yr = accr[k], xi = acci[k], yi = acci[k];
+            swap32_f64(xr, yr), swap32_f64(xi, yi);
+            accr[k] = xr + yr, acci[k] = xi + yi;
+            if constexpr (SS == 4) {
+              xr = yr = accr[k], xi = yi = acci[k];
+              swap16_f64(xr, yr), swap16_f64(xi, yi);
+              accr[k] = xr + yr, acci[k] = xi + yi;
+            }
           }
         }
       }
@@ -1698,13 +1718,13 @@ __device__ __forceinline__ void p2p_sym_item(const PassArgs& a, int nrhs, int r,
             a.phi[(int64_t)r * a.n + tbase + 64 * k] = make_double2((double)accr[k] * kap, (double)acci[k] * kap);
     };
     // passes of 64 T targets (this workgroup's: every G-th one); a last one of at most 64
-    // with one target per lane, and in FP32 of at most 32 or 16 on 2 or 4 lanes each
+    // with one target per lane, and of at most 32 or 16 on 2 or 4 lanes each
     for (int c0 = half * TP; c0 < cnt; c0 += G * TP) {
       const int left = cnt - c0;
-      if (F32 && left <= 16)
-        pass(std::integral_constant<int, 1>(), std::integral_constant<int, F32 ? 4 : 1>(), c0);
-      else if (F32 && left <= 32)
-        pass(std::integral_constant<int, 1>(), std::integral_constant<int, F32 ? 2 : 1>(), c0);
+      if (left <= 16)
+        pass(std::integral_constant<int, 1>(), std::integral_constant<int, 4>(), c0);
+      else if (left <= 32)
+        pass(std::integral_constant<int, 1>(), std::integral_constant<int, 2>(), c0);
       else if (T > 1 && left <= 64)
         pass(std::integral_constant<int, 1>(), std::integral_constant<int, 1>(), c0);
       else
