@@ -10,12 +10,12 @@ complex-image fits, tables) is reported separately.
 Default workload: N = 1,000,000 particles uniform in the unit cube centred at
 (0, 0, -0.6) inside the three-layer medium (interfaces 0 and -1.2, k = 0.8,
 1.5, 2.0), one complex charge vector; seeded synthetic data.  Three modes are
-timed: the plain FP64 FMM (p = 13, relative error <= 1e-6 at this size), the mixed
-FP32 FMM (complex FP32 M2L and P2P, FP64 tables and accumulation) at p = 7, and the
-mixed FMM at p = 8 with the Sigma-table surrogate attached (its validated cells answer
-table rows, the rest fall back to the complex images); `value` is the mode named by
---headline (the fastest form within 1e-4: mixed FP32 at p = 7; the surrogate changes
-the set-up, not the evaluation).
+timed: the plain FP64 FMM (p = 13, relative error <= 1e-6 at this size), and the mixed
+FP32 FMM (complex FP32 M2L and P2P, FP64 tables and accumulation) at p = 7 and at
+p = 8, each with a Sigma-table surrogate of its order attached (its validated cells
+answer table rows, the rest fall back to the complex images); `value` is the mode
+named by --headline (the fastest form within 1e-4: surrogate + mixed FP32 at p = 7;
+the surrogate changes the set-up, not the evaluation).
 
 Prints one JSON line.
 """
@@ -410,7 +410,7 @@ def main():
         p = int(po) if po else (args.p64 if prec == "fp64" else args.p32)
         print(f"[bench] mode {m} p={p} N={N} n_rhs={qm.shape[0]}", file=sys.stderr, flush=True)
         modes[m] = run_mode(xyz, qm, p, prec, args.max_leaf, args.steps, args.warmup, args.workload,
-                            surrogate=(m == "fp32_p8" and not args.no_surrogate and args.workload != "c3"),
+                            surrogate=(prec == "fp32" and not args.no_surrogate and args.workload != "c3"),
                             autotune=not args.no_autotune)
         print(f"[bench] {m}: {modes[m]['ms_per_step']:.2f} ms/step, err {modes[m]['rel_err_sampled']}",
               file=sys.stderr, flush=True)

@@ -465,6 +465,12 @@ const char* tefmm_mlp_last_error(tefmm_mlp_t m);
 /* Host parameter vectors (num_params floats); set also clears the Adam state. */
 int tefmm_mlp_set_params(tefmm_mlp_t m, const float* theta_host);
 int tefmm_mlp_get_params(tefmm_mlp_t m, float* theta_host);
+/* split = 1: the hidden products carry each FP32 operand as two BF16 values
+ * (hi = bf16(x), lo = bf16(x - hi)) and take three BF16 MFMAs with FP32
+ * accumulation (lo hi + hi lo + hi hi), ~16 mantissa bits per operand instead of
+ * 8; split = 0 (the default): one MFMA on the rounded operands.  Applies to the
+ * forward pass, the loss gradient and training.  Anything else: INVALID_ARG. */
+int tefmm_mlp_set_split(tefmm_mlp_t m, int split);
 /* y[n x n_out] = network(x[n x n_in]) (device arrays). */
 int tefmm_mlp_forward(tefmm_mlp_t m, const float* x, int64_t n, float* y, void* stream);
 /* Forward pass that allocates nothing, for callers that cannot allocate device
@@ -511,8 +517,10 @@ int tefmm_mlp_train(tefmm_mlp_t m, const float* x, const float* t, int64_t n, in
  * points of the box (GPU FP64); training is minibatch Adam on the GPU
  * (tefmm_mlp kernels).  A validation map over cells_rho x cells_s cells keeps a
  * cell when the largest |W_network - W_images| over n_valid fresh points in it
- * is <= budget.  Attached to a handle, the surrogate produces the Sigma table
- * rows whose keys fall in kept cells; every other row (outside the box,
+ * is <= budget, taking cells in order of increasing error until their errors
+ * sum to err_total (each served row moves the potential).  Attached to a
+ * handle, the surrogate produces the Sigma table rows whose keys fall in kept
+ * cells; every other row (outside the box,
  * rejected cells, other layers) comes from the complex images as before.
  * ------------------------------------------------------------------------ */
 typedef struct tefmm_surrogate* tefmm_surrogate_t;
@@ -533,6 +541,10 @@ typedef struct {
   int envelope;        /* 1: outputs also divided by the envelope of the two mirror distances */
   int leaf_level;      /* 1: keys of the leaf level are answered too (0: only the levels above it,
                           whose translations carry less of the potential per row) */
+  int split_bf16;      /* 1: the network's hidden products as BF16 hi + lo pairs (see
+                          tefmm_mlp_set_split); 0: plain BF16 operands */
+  double err_total;    /* cells are kept in order of increasing error while the kept cells'
+                          errors sum to at most err_total (<= 0: no such limit) */
 } tefmm_surrogate_options;
 
 typedef struct {
@@ -550,7 +562,7 @@ typedef struct {
  * half-space), n_train 262144, 300 epochs of 1024, lr 2e-3, width 128,
  * 4 hidden layers, 8 x 16 cells with 16 points, budget 4e-4 (the error of W
  * in envelope units, entry (m, c) weighted by 2^-(m+c)), envelope on, leaf
- * level off. */
+ * level off, split BF16 products on, err_total 1.2e-3. */
 void tefmm_surrogate_default_options(const tefmm_medium* medium, int layer, tefmm_surrogate_options* o);
 /* Fit the images of the box, generate the training and validation targets,
  * train, build the validation map.  opt gives p and the image parameters

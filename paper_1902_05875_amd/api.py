@@ -28,7 +28,7 @@ EXPORTS = ["tefmm_default_options", "tefmm_create", "tefmm_set_particles", "tefm
            "tefmm_dcim_family", "tefmm_taylor_coefficients", "tefmm_get_moments", "tefmm_get_tree",
            "tefmm_selftest_mfma", "tefmm_evaluate_batch", "tefmm_autotune", "tefmm_dcim_cross",
            "tefmm_mlp_create", "tefmm_mlp_destroy", "tefmm_mlp_num_params", "tefmm_mlp_last_error",
-           "tefmm_mlp_set_params", "tefmm_mlp_get_params", "tefmm_mlp_forward", "tefmm_mlp_forward_noalloc",
+           "tefmm_mlp_set_params", "tefmm_mlp_get_params", "tefmm_mlp_set_split", "tefmm_mlp_forward", "tefmm_mlp_forward_noalloc",
            "tefmm_mlp_loss_grad",
            "tefmm_mlp_adam_step", "tefmm_mlp_train", "tefmm_surrogate_default_options", "tefmm_surrogate_train",
            "tefmm_surrogate_destroy", "tefmm_surrogate_cell_ok", "tefmm_set_surrogate", "tefmm_surrogate_cell_errors",
@@ -110,7 +110,8 @@ class SurOptionsC(ctypes.Structure):
                 ("batch", ctypes.c_int), ("lr", ctypes.c_float), ("width", ctypes.c_int), ("n_hidden", ctypes.c_int),
                 ("cells_rho", ctypes.c_int), ("cells_s", ctypes.c_int), ("n_valid", ctypes.c_int),
                 ("budget", ctypes.c_double), ("seed", ctypes.c_uint64), ("h_from_images", ctypes.c_int),
-                ("envelope", ctypes.c_int), ("leaf_level", ctypes.c_int)]
+                ("envelope", ctypes.c_int), ("leaf_level", ctypes.c_int), ("split_bf16", ctypes.c_int),
+                ("err_total", ctypes.c_double)]
 
 
 class SurReportC(ctypes.Structure):
@@ -170,6 +171,7 @@ def lib():
         L.tefmm_mlp_last_error.restype = ctypes.c_char_p
         L.tefmm_mlp_set_params.argtypes = [vp, vp]
         L.tefmm_mlp_get_params.argtypes = [vp, vp]
+        L.tefmm_mlp_set_split.argtypes = [vp, i32]
         L.tefmm_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
         L.tefmm_mlp_forward_noalloc.argtypes = [vp, vp, i64, vp, vp]
         L.tefmm_mlp_loss_grad.argtypes = [vp, vp, vp, i64, ctypes.POINTER(dbl), vp, vp]
@@ -549,6 +551,10 @@ class MLP:
         th = np.ascontiguousarray(theta, np.float32)
         assert th.size == self.num_params
         self._chk(lib().tefmm_mlp_set_params(self.h, th.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_split(self, split):
+        """Hidden products with BF16 hi + lo operand pairs (tefmm_mlp_set_split)."""
+        self._chk(lib().tefmm_mlp_set_split(self.h, int(split)))
 
     def get_params(self):
         th = np.empty(self.num_params, np.float32)

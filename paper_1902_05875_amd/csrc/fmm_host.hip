@@ -3237,6 +3237,8 @@ extern "C" void tefmm_surrogate_default_options(const tefmm_medium* medium, int 
   o->h_from_images = 0;
   o->envelope = 1;
   o->leaf_level = 0;
+  o->split_bf16 = 1;
+  o->err_total = 1.2e-3;
 }
 
 #define SURCHK(x)                                                \
@@ -3258,7 +3260,8 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
   if (rep) std::memset(rep, 0, sizeof(*rep));
   const tefmm_surrogate_options& o = *so;
   if (!(o.rho_max > 0) || !(o.s_hi > o.s_lo) || o.n_train < 64 || o.epochs < 0 || o.batch < 1 || !(o.lr > 0) ||
-      o.width < 16 || o.n_hidden < 1 || o.cells_rho < 1 || o.cells_s < 1 || o.n_valid < 1 || !(o.budget > 0))
+      o.width < 16 || o.n_hidden < 1 || o.cells_rho < 1 || o.cells_s < 1 || o.n_valid < 1 || !(o.budget > 0) ||
+      std::isnan(o.err_total))
     return TEFMM_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   tefmm_surrogate* su = new tefmm_surrogate();
@@ -3386,6 +3389,7 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
   auto t1 = std::chrono::steady_clock::now();
   // training on the matrix cores
   SURHIP(su->net.init(2, o.width, o.n_hidden, 2 * nH, o.seed ^ 0x5bd1e995ull));
+  su->net.split = o.split_bf16 ? 1 : 0;
   std::vector<double> losses;
   SURHIP(su->net.train(d_X, d_T, n, o.epochs, o.batch, o.lr, o.seed + 17, losses, s));
   if (epoch_loss)
@@ -3431,7 +3435,6 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
   su->cell_ok.assign(ncell, 0);
   su->cell_err.assign(ncell, 0.0);
   double emax = 0;
-  int ok = 0;
   for (int c = 0; c < ncell; ++c) {
     double e = 0;
     for (int j = 0; j < o.n_valid; ++j) {
@@ -3449,9 +3452,25 @@ extern "C" int tefmm_surrogate_train(tefmm_surrogate_t* out, const tefmm_medium*
       }
     }
     su->cell_err[c] = e;
-    su->cell_ok[c] = e <= o.budget;
-    ok += su->cell_ok[c];
     emax = std::max(emax, e);
+  }
+  // cells kept in order of increasing error while each is within the budget and the
+  // errors of the kept cells sum to at most err_total: every served row moves the
+  // potential, so the number of rows, not only their accuracy, has to stay bounded
+  int ok = 0;
+  {
+    std::vector<int> order(ncell);
+    for (int c = 0; c < ncell; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return su->cell_err[a] < su->cell_err[b]; });
+    double sum = 0;
+    for (int c : order) {
+      const double e = su->cell_err[c];
+      if (!(e <= o.budget) || (o.err_total > 0 && sum + e > o.err_total)) break;
+      sum += e;
+      su->cell_ok[c] = 1;
+      ++ok;
+    }
   }
   auto t3 = std::chrono::steady_clock::now();
   if (rep) {

@@ -5,7 +5,11 @@
 //   L = mean over samples and outputs of (y - t)^2,  Adam updates.
 //
 // The hidden products run as a BF16 MFMA GEMM (v_mfma_f32_16x16x16_bf16: operands
-// rounded to BF16 when staged into LDS, FP32 accumulation); the first layer
+// rounded to BF16 when staged into LDS, FP32 accumulation).  With `split` set, each
+// FP32 operand is carried as two BF16 values, x = hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi), and a product takes three MFMAs (lo hi + hi lo + hi hi, the
+// small terms first; lo lo is below FP32 rounding of the sum), which keeps about
+// 16 mantissa bits of each operand instead of 8.  The first layer
 // (a few inputs) and its weight gradient stay in FP32 on the vector units, since
 // rounding the coordinates themselves to 8 mantissa bits would cost more
 // accuracy than all later layers, and so does the output layer (forward and its
@@ -50,15 +54,19 @@ struct GemmArgs {
   int act;     // 0: none, 1: tanh
   int atomic;  // 1: accumulate atomically
   int kps;     // K per blockIdx.z
+  int split;   // 1: operands as BF16 hi + lo pairs, three MFMAs per product
 };
 
 // 64 x 64 output tile per workgroup, four waves of 32 x 32 (2 x 2 MFMA tiles).
 // MFMA 16x16x16 BF16 operand layout: lane l holds A[l & 15][4 (l >> 4) + 0..3]
 // and B[4 (l >> 4) + 0..3][l & 15]; result register r of lane l is
 // C[4 (l >> 4) + r][l & 15].
+template <bool SPLIT>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   __shared__ __align__(16) unsigned short sA[64][36];  // [row][k]
   __shared__ __align__(16) unsigned short sB[64][36];  // [col][k]
+  __shared__ __align__(16) unsigned short sAl[SPLIT ? 64 : 1][36];  // low parts (SPLIT)
+  __shared__ __align__(16) unsigned short sBl[SPLIT ? 64 : 1][36];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int kbeg = blockIdx.z * g.kps;
@@ -81,7 +89,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       }
       const int i = i0 + row, k = k0 + kk;
       const float v = (i < g.M && k < kend) ? g.A[(int64_t)i * g.sai + (int64_t)k * g.sak] : 0.f;
-      sA[row][kk] = f2bf(v);
+      const unsigned short hi = f2bf(v);
+      sA[row][kk] = hi;
+      if (SPLIT) sAl[row][kk] = f2bf(v - __uint_as_float((unsigned)hi << 16));
     }
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -94,7 +104,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       }
       const int j = j0 + col, k = k0 + kk;
       const float v = (j < g.N && k < kend) ? g.B[(int64_t)k * g.sbk + (int64_t)j * g.sbj] : 0.f;
-      sB[col][kk] = f2bf(v);
+      const unsigned short hi = f2bf(v);
+      sB[col][kk] = hi;
+      if (SPLIT) sBl[col][kk] = f2bf(v - __uint_as_float((unsigned)hi << 16));
     }
     __syncthreads();
 #pragma unroll
@@ -104,6 +116,21 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       for (int t = 0; t < 2; ++t) {
         av[t] = *(const bf16x4*)&sA[wr + 16 * t + (lane & 15)][ks + 4 * (lane >> 4)];
         bv[t] = *(const bf16x4*)&sB[wc + 16 * t + (lane & 15)][ks + 4 * (lane >> 4)];
+      }
+      if (SPLIT) {
+        bf16x4 al[2], bl[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          al[t] = *(const bf16x4*)&sAl[wr + 16 * t + (lane & 15)][ks + 4 * (lane >> 4)];
+          bl[t] = *(const bf16x4*)&sBl[wc + 16 * t + (lane & 15)][ks + 4 * (lane >> 4)];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[a], bv[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bl[b], acc[a][b], 0, 0, 0);
+          }
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -279,8 +306,10 @@ static hipError_t gemm(const GemmArgs& g0, hipStream_t s, bool f32 = false) {
   dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
   if (f32)
     hipLaunchKernelGGL(k_gemm_f32, grid, dim3(256), 0, s, g);
+  else if (g.split)
+    hipLaunchKernelGGL(k_gemm_bf16<true>, grid, dim3(256), 0, s, g);
   else
-    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_gemm_bf16<false>, grid, dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
@@ -343,6 +372,7 @@ hipError_t Mlp::forward_in(const float* x, int64_t n, float* out, hipStream_t s,
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.M = (int)n, g.N = rows[l], g.K = cols[l];
+    g.split = split;
     g.A = ain, g.sai = width, g.sak = 1;
     g.B = theta + off_W[l], g.sbk = 1, g.sbj = cols[l];  // B(k, j) = W[j][k]
     g.bias = theta + off_b[l];
@@ -375,6 +405,7 @@ hipError_t Mlp::loss_grad(const float* x, const float* t, int64_t n, hipStream_t
     std::memset(&g, 0, sizeof(g));
     // dW_l += d^T a_l : (rows x n)(n x cols)
     g.M = rows[l], g.N = cols[l], g.K = (int)n;
+    g.split = split;
     g.A = d, g.sai = 1, g.sak = ld;
     g.B = ain, g.sbk = width, g.sbj = 1;
     g.C = grad + off_W[l], g.ldc = cols[l], g.atomic = 1;
@@ -385,6 +416,7 @@ hipError_t Mlp::loss_grad(const float* x, const float* t, int64_t n, hipStream_t
     // d_prev = (d W_l) * (1 - a_l^2)
     std::memset(&g, 0, sizeof(g));
     g.M = (int)n, g.N = cols[l], g.K = rows[l];
+    g.split = split;
     g.A = d, g.sai = ld, g.sak = 1;
     g.B = theta + off_W[l], g.sbk = cols[l], g.sbj = 1;
     g.C = dn, g.ldc = width;
@@ -532,6 +564,12 @@ extern "C" int tefmm_mlp_set_params(tefmm_mlp_t m, const float* theta) {
 extern "C" int tefmm_mlp_get_params(tefmm_mlp_t m, float* theta) {
   if (!m || !theta) return TEFMM_ERR_INVALID_ARG;
   MLPCHK(hipMemcpy(theta, m->net.theta, sizeof(float) * m->net.P, hipMemcpyDeviceToHost));
+  return TEFMM_OK;
+}
+
+extern "C" int tefmm_mlp_set_split(tefmm_mlp_t m, int split) {
+  if (!m || (split != 0 && split != 1)) return TEFMM_ERR_INVALID_ARG;
+  m->net.split = split;
   return TEFMM_OK;
 }
 

@@ -15,6 +15,7 @@ struct Mlp {
   std::vector<int> rows, cols;                   // shape of W_l
   float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
   int64_t step = 0;
+  int split = 0;  // hidden products with operands as BF16 hi + lo pairs (three MFMAs each)
   // workspace for up to cap rows
   int64_t cap = 0;
   float *acts = nullptr, *y = nullptr, *d0 = nullptr, *d1 = nullptr, *xb = nullptr, *tb = nullptr;

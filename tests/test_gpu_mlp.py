@@ -81,3 +81,24 @@ def test_training_fits_smooth_function():
     losses = net.train(x, t, epochs=40, batch=512, lr=2e-3, seed=5)
     print("training losses", losses[0], losses[-1])
     assert losses[-1] < losses[0] / 30
+
+
+def test_split_products_vs_oracle():
+    """Hidden products with each operand as a BF16 hi + lo pair (three MFMAs, FP32
+    accumulation): forward and gradient close to the FP64 oracle at the level of ~16
+    mantissa bits per operand, and much closer than one BF16 product per pair."""
+    from oracle import mlp as om
+    net, th, X, T, x, t = _setup(5)
+    y1 = net.forward(x).cpu().numpy()
+    net.set_split(1)
+    y3 = net.forward(x).cpu().numpy()
+    ref, _ = om.forward(th, X, DIMS)
+    e1, e3 = _rel(y1, ref), _rel(y3, ref)
+    L, g = net.loss_grad(x, t)
+    Lr, gr = om.loss_and_grad(th, X, T, DIMS)
+    eg = _rel(g, gr)
+    print(f"mlp forward rel err: one BF16 product {e1:.2e}, split {e3:.2e}; split gradient {eg:.2e}")
+    assert e3 < 1e-4 and e3 < 0.1 * e1
+    assert abs(L - Lr) < 1e-4 * Lr and eg < 1e-3
+    with pytest.raises(Exception):
+        net.set_split(2)

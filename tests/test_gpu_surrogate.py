@@ -72,7 +72,14 @@ def test_training_and_validation_map(sur):
     assert r["status"] == 0 and r["n_out"] == 2 * (17 * 18 // 2)  # (m, c), m + c <= 2p = 16
     assert sur.losses[-1] < 0.01 * sur.losses[0]
     err = sur.cell_errors()
-    assert r["cells_ok"] == int(np.sum(err <= sur.options["budget"]))
+    # kept: cells in order of increasing error, each within the budget, while the kept
+    # errors sum to at most err_total
+    e = np.sort(err.ravel())
+    tot = sur.options["err_total"]
+    keep = (e <= sur.options["budget"]) & ((np.cumsum(e) <= tot) | (tot <= 0))
+    n_keep = keep.size if keep.all() else int(np.argmin(keep))
+    assert r["cells_ok"] == n_keep
+    assert r["cells_ok"] >= 1
     assert np.isclose(r["max_cell_err"], err.max())
     o = sur.options
     pts = np.array([[0.0, 0.0, 0.5 * (o["s_lo"] + o["s_hi"])], [0.0, 0.0, o["s_hi"] + 0.1],
@@ -83,8 +90,9 @@ def test_training_and_validation_map(sur):
 
 def test_served_rows_keep_the_budget(sur):
     """The rows of validated cells (levels above the leaves) come from the network, the rest
-    from the complex images: the mixed mode at p = 8 stays within 1e-4 of the oracle, and it
-    moves by no more than the served rows' share of the budget (identical if none)."""
+    from the complex images: some cells pass validation and serve rows, the mixed mode at
+    p = 8 stays within 1e-4 of the oracle, and it moves by no more than the served rows'
+    share of the budget."""
     idx, gold = _gold()
     ref, st0 = _c2(None, "fp32")
     phi, st = _c2(sur, "fp32")
@@ -92,12 +100,9 @@ def test_served_rows_keep_the_budget(sur):
     print(f"cells ok {sur.report['cells_ok']}/{sur.report['cells_total']}; rows from the network "
           f"{st['surrogate_keys']} of {st['sigma_keys']}; potential moves by {d:.2e}")
     assert st["sigma_keys"] == st0["sigma_keys"] > 0
-    if sur.report["cells_ok"] == 0:
-        assert st["surrogate_keys"] == 0
-    if st["surrogate_keys"] == 0:
-        assert np.array_equal(phi, ref)
+    assert sur.report["cells_ok"] >= 1 and st["surrogate_keys"] > 0
     check("C2 N=200k fp32 p=8 with the surrogate", phi[idx], gold, 1e-4)
-    assert d < 1e-4
+    assert d < 8e-5  # the mixed mode at p = 8 leaves 8.7e-5 of the 1e-4 budget
 
 
 def test_all_rows_from_the_network(sur):
@@ -105,7 +110,7 @@ def test_all_rows_from_the_network(sur):
     the network's accuracy costs in the potential (measured, reported; bounded only loosely:
     it is the reason the validation map keeps the cells it keeps)."""
     from paper_1902_05875_amd import api
-    all_in = api.Surrogate(K3, D3, 1, p=8, budget=1e30)
+    all_in = api.Surrogate(K3, D3, 1, p=8, budget=1e30, err_total=0.0)
     ref, _ = _c2(None, "fp32")
     phi, st = _c2(all_in, "fp32")
     d = float(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
@@ -117,9 +122,10 @@ def test_all_rows_from_the_network(sur):
 def test_gain_is_measured(sur):
     """What the network gains: the set-up of the same geometry with and without it (table
     generation with the rows it serves, whole set-up), and its training cost once per medium.
-    Measured and reported; the assertion is only that the served rows leave the result
-    within the budget (the gain itself is near zero in this design: the rows are produced by
-    the network and rebuilt, the images are still fitted for the rest)."""
+    Measured and reported: rows are served, the result stays within the budget, and the
+    table generation with the served rows takes no longer than without them (beyond timing
+    noise).  The gain is bounded by the served rows' share of the table time: the images are
+    still fitted for the other rows, and the evaluation itself is unchanged."""
     idx, gold = _gold()
     runs = {}
     for name, s in (("images", None), ("surrogate", sur)):
@@ -131,3 +137,5 @@ def test_gain_is_measured(sur):
           f"{1e3 * s0['setup_s']:.1f} -> {1e3 * s1['setup_s']:.1f} ms with {s1['surrogate_keys']} of "
           f"{s1['sigma_keys']} Sigma rows from the network; training {sur.wall:.1f} s once per medium")
     check("with the surrogate vs oracle", p1[idx], gold, 1e-4)
+    assert s1["surrogate_keys"] > 0
+    assert s1["t_setup_tables_ms"] < 1.25 * s0["t_setup_tables_ms"] + 1.0
