@@ -128,12 +128,15 @@ def test_gain_is_measured(sur):
     still fitted for the other rows, and the evaluation itself is unchanged."""
     idx, gold = _gold()
     runs = {}
-    for name, s in (("images", None), ("surrogate", sur)):
-        for _ in range(2):  # the second of two set-ups (the first also pays the launches' loading)
+    _c2(sur, "fp32")  # the first set-up also pays the launches' loading
+    for _ in range(3):  # alternating, the fastest set-up of each kept
+        for name, s in (("images", None), ("surrogate", sur)):
             phi, st = _c2(s, "fp32")
-        runs[name] = (phi, st)
+            if name not in runs or st["setup_s"] < runs[name][1]["setup_s"]:
+                runs[name] = (phi, st)
     (p0, s0), (p1, s1) = runs["images"], runs["surrogate"]
-    print(f"tables {s0['t_setup_tables_ms']:.2f} -> {s1['t_setup_tables_ms']:.2f} ms, set-up "
+    print(f"image fits {s0['t_setup_dcim_ms']:.2f} -> {s1['t_setup_dcim_ms']:.2f} ms (host threads), "
+          f"tables {s0['t_setup_tables_ms']:.2f} -> {s1['t_setup_tables_ms']:.2f} ms, set-up "
           f"{1e3 * s0['setup_s']:.1f} -> {1e3 * s1['setup_s']:.1f} ms with {s1['surrogate_keys']} of "
           f"{s1['sigma_keys']} Sigma rows from the network; training {sur.wall:.1f} s once per medium")
     check("with the surrogate vs oracle", p1[idx], gold, 1e-4)
