@@ -142,3 +142,26 @@ def test_gain_is_measured(sur):
     check("with the surrogate vs oracle", p1[idx], gold, 1e-4)
     assert s1["surrogate_keys"] > 0
     assert s1["t_setup_tables_ms"] < 1.25 * s0["t_setup_tables_ms"] + 1.0
+
+
+def test_headline_configuration_with_the_surrogate():
+    """The bench's headline form, surrogate + mixed FP32 at p = 7 on the N = 1,000,000
+    mid-layer cube (depth 4), against the 64 oracle targets stored for it (48 uniform, 16
+    closest to an interface): rows are served and the result stays within the 1e-4 bar."""
+    import torch
+    from paper_1902_05875_amd import api, inputs
+    xyz, q = inputs.workload("c4")
+    a = np.loadtxt(os.path.join(GOLD, "expected_c4m.txt"))
+    idx, ref = a[:, 0].astype(int), a[:, 1] + 1j * a[:, 2]
+    s7 = api.Surrogate(K3, D3, 1, p=7)
+    f = api.TEFMM(K3, D3, p=7, precision="fp32", depth=4)
+    f.set_surrogate(s7)
+    f.set_particles(xyz)
+    phi = f.evaluate(torch.from_numpy(q).cuda()).cpu().numpy()
+    st = f.stats()
+    f.close()
+    print(f"p = 7 network: cells ok {s7.report['cells_ok']}, {st['surrogate_keys']} of {st['sigma_keys']} "
+          f"Sigma rows served")
+    s7.close()
+    assert st["surrogate_keys"] > 0
+    check("C4 N=1M 64 targets, surrogate + fp32 p=7", phi[idx], ref, 1e-4)
