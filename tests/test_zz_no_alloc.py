@@ -19,10 +19,13 @@ def _net(seed):
     return net
 
 
-def test_noalloc_forward_matches_forward():
+@pytest.mark.parametrize("split", [0, 1])
+def test_noalloc_forward_matches_forward(split):
+    """Both product forms: one BF16 MFMA per product, and BF16 hi + lo operand pairs."""
     import torch
     from paper_1902_05875_amd import api
     net = _net(3)
+    net.set_split(split)
     rng = np.random.default_rng(7)
     limit = api.lib().tefmm_mlp_forward_noalloc  # exported
     assert limit is not None
